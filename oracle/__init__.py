@@ -1,0 +1,257 @@
+"""CPU oracle for the exact integer time-difference estimator.
+
+TEST INFRASTRUCTURE ONLY. Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package. It shares no code
+with the HIP library (``paper_2509_19974_amd``) and never imports it.
+
+What it computes is the plain definition of each step, written out:
+
+* ``sumsq_tree`` / ``inv_step`` -- the per-signal scale of the uniform
+  quantizer (the paper leaves the quantizer free, Section 3.2; this build fixes
+  a symmetric mid-tread quantizer on [-3 sigma, 3 sigma] and a fixed-order
+  float64 sum of squares so that two implementations agree bit for bit).
+* ``quantize`` -- Algorithm 1, line 2: monotone integer maps with phi(0) = 0;
+  sign with sign(0) = 0 (Section 4.2) for bits = 1.
+* ``xcorr`` / ``xcorr_at`` -- Algorithm 1, line 3: Eq. (1) on the integer
+  sequences, int64 direct sums.
+* ``argmax`` -- Algorithm 1, line 4: maximum, smallest maximising lag and the
+  number of maximisers (Remark 1).
+* ``xcorr_f64_at`` -- Eq. (1) on the unquantized signals in float64.
+* ``estimate`` / ``estimate_refined`` -- Algorithm 1 lines 1-4, and 1-6.
+* ``xcorr_long_certified`` -- for signals too long for the direct sum over all
+  lags: a float64 FFT correlation of the integer sequences, rounded to the
+  nearest integer, accepted only under an a-priori rounding-error bound below
+  one half (so the rounding is provably exact), and cross-checked by direct
+  sums on a lag subset.
+
+Everything heavy runs in ``tde_oracle.c`` (plain loops, int64/float64),
+compiled with gcc and loaded through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tde_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libtde_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (no fast-math, OpenMP for the lag loop)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+               "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build(force=False)
+    lib = ctypes.CDLL(_LIB_PATH)
+    i64, f32, f64, vp = ctypes.c_int64, ctypes.c_float, ctypes.c_double, ctypes.c_void_p
+    lib.oracle_sumsq_tree.argtypes = [vp, i64, vp]
+    lib.oracle_sumsq_tree.restype = f64
+    lib.oracle_kmax.argtypes = [ctypes.c_int]
+    lib.oracle_kmax.restype = ctypes.c_int
+    lib.oracle_inv_step_from_sumsq.argtypes = [f64, i64, ctypes.c_int]
+    lib.oracle_inv_step_from_sumsq.restype = f32
+    lib.oracle_quantize.argtypes = [vp, i64, ctypes.c_int, f32, vp]
+    lib.oracle_quantize.restype = i64
+    lib.oracle_xcorr_i64.argtypes = [vp, i64, vp, i64, i64, i64, vp]
+    lib.oracle_xcorr_i64.restype = None
+    lib.oracle_xcorr_i64_at.argtypes = [vp, i64, vp, i64, vp, i64, vp]
+    lib.oracle_xcorr_i64_at.restype = None
+    lib.oracle_argmax_i64.argtypes = [vp, i64, i64, vp, vp, vp]
+    lib.oracle_argmax_i64.restype = None
+    lib.oracle_xcorr_f64_at.argtypes = [vp, i64, vp, i64, vp, i64, vp]
+    lib.oracle_xcorr_f64_at.restype = None
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f32(x) -> np.ndarray:
+    return np.ascontiguousarray(x, dtype=np.float32)
+
+
+def _i8(x) -> np.ndarray:
+    return np.ascontiguousarray(x, dtype=np.int8)
+
+
+# ---------------------------------------------------------------- scale ----
+
+def kmax(bits: int) -> int:
+    """Largest code magnitude: 1 for sign (ternary), 2^(b-1)-1 otherwise."""
+    if bits not in (1, 2, 4, 8):
+        raise ValueError("bits must be 1, 2, 4 or 8")
+    return int(_load().oracle_kmax(bits))
+
+
+def sumsq_tree(x) -> float:
+    """Fixed-order float64 sum of squares over the finite samples (fan-in 256)."""
+    x = _f32(x)
+    n = x.size
+    scratch = np.zeros(max(1, (n + 255) // 256), dtype=np.float64)
+    return float(_load().oracle_sumsq_tree(_ptr(x), n, _ptr(scratch)))
+
+
+def inv_step(x, bits: int) -> float:
+    """fl32((2K+1) / (6 sigma)), sigma = sqrt(S/n); 0.0 when S == 0."""
+    x = _f32(x)
+    S = sumsq_tree(x)
+    return float(np.float32(_load().oracle_inv_step_from_sumsq(S, x.size, bits)))
+
+
+# ------------------------------------------------------------- quantize ----
+
+def quantize(x, bits: int, inv_step_value: float | None = None):
+    """Algorithm 1, line 2. Returns (q int8, n_nonfinite, inv_step used)."""
+    x = _f32(x)
+    if bits not in (1, 2, 4, 8):
+        raise ValueError("bits must be 1, 2, 4 or 8")
+    if bits == 1:
+        s = 0.0
+    elif inv_step_value is None or inv_step_value <= 0:
+        s = inv_step(x, bits)
+    else:
+        s = float(np.float32(inv_step_value))
+    q = np.empty(x.size, dtype=np.int8)
+    nf = _load().oracle_quantize(_ptr(x), x.size, bits, s, _ptr(q))
+    return q, int(nf), s
+
+
+# ---------------------------------------------------------- correlation ----
+
+def xcorr(u, v, lag_lo: int, lag_hi: int) -> np.ndarray:
+    """Eq. (1) on integer sequences: r[i] = sum_m u[m] v[m + lag_lo + i], int64."""
+    u, v = _i8(u), _i8(v)
+    if lag_hi < lag_lo:
+        raise ValueError("lag_hi < lag_lo")
+    r = np.empty(lag_hi - lag_lo + 1, dtype=np.int64)
+    _load().oracle_xcorr_i64(_ptr(u), u.size, _ptr(v), v.size, lag_lo, lag_hi, _ptr(r))
+    return r
+
+
+def xcorr_at(u, v, lags) -> np.ndarray:
+    """Eq. (1) at a list of lags, int64 direct sums."""
+    u, v = _i8(u), _i8(v)
+    lags = np.ascontiguousarray(lags, dtype=np.int64)
+    r = np.empty(lags.size, dtype=np.int64)
+    _load().oracle_xcorr_i64_at(_ptr(u), u.size, _ptr(v), v.size, _ptr(lags), lags.size, _ptr(r))
+    return r
+
+
+def argmax(r, lag_lo: int):
+    """Algorithm 1, line 4: (smallest maximising lag, max value, #maximisers)."""
+    r = np.ascontiguousarray(r, dtype=np.int64)
+    if r.size == 0:
+        raise ValueError("empty lag range")
+    lag, rmax, nt = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _load().oracle_argmax_i64(_ptr(r), r.size, lag_lo, ctypes.byref(lag),
+                              ctypes.byref(rmax), ctypes.byref(nt))
+    return int(lag.value), int(rmax.value), int(nt.value)
+
+
+def xcorr_f64_at(x, y, lags) -> np.ndarray:
+    """Eq. (1) on the float signals in float64, ascending-m summation."""
+    x, y = _f32(x), _f32(y)
+    lags = np.ascontiguousarray(lags, dtype=np.int64)
+    r = np.empty(lags.size, dtype=np.float64)
+    _load().oracle_xcorr_f64_at(_ptr(x), x.size, _ptr(y), y.size, _ptr(lags), lags.size, _ptr(r))
+    return r
+
+
+def overlap_count(nu: int, nv: int, tau: int) -> int:
+    """#{m : 0 <= m < nu, 0 <= m + tau < nv}."""
+    return max(0, min(nu, nv - tau) - max(0, -tau))
+
+
+# ------------------------------------------------------------- Alg. 1 -----
+
+def estimate(x, y, bits: int, lag_lo: int, lag_hi: int,
+             inv_step_x: float | None = None, inv_step_y: float | None = None):
+    """Algorithm 1, lines 1-4. Returns a dict with lag, rmax, n_ties, r, q's."""
+    u, nfx, sx = quantize(x, bits, inv_step_x)
+    v, nfy, sy = quantize(y, bits, inv_step_y)
+    r = xcorr(u, v, lag_lo, lag_hi)
+    lag, rmax, nt = argmax(r, lag_lo)
+    return {"lag": lag, "rmax": rmax, "n_ties": nt, "r": r, "u": u, "v": v,
+            "inv_step_x": sx, "inv_step_y": sy, "nonfinite_x": nfx, "nonfinite_y": nfy}
+
+
+def estimate_refined(x, y, bits: int, lag_lo: int, lag_hi: int,
+                     inv_step_x: float | None = None, inv_step_y: float | None = None):
+    """Algorithm 1, lines 1-6: ties of the integer correlation are resolved by
+    the float64 correlation of the unquantized signals, evaluated only at the
+    tied lags. Returns the refined argmax set (sorted) and the line-4 result."""
+    res = estimate(x, y, bits, lag_lo, lag_hi, inv_step_x, inv_step_y)
+    r = res["r"]
+    tied = np.nonzero(r == res["rmax"])[0].astype(np.int64) + lag_lo
+    if tied.size > 1:
+        rf = xcorr_f64_at(x, y, tied)
+        best = rf.max()
+        tied = tied[rf == best]
+    res["lag_set"] = [int(t) for t in tied]
+    return res
+
+
+# ------------------------------------------------- long-signal route ------
+
+def fft_rounding_bound(u, v, n_fft: int) -> float:
+    """A-priori bound on the max-norm error of a float64 FFT convolution of the
+    integer sequences u and v with transform length n_fft:
+    ||err||_inf <= ||u||_2 ||v||_2 * 3 log2(n) * 8 eps (a generous multiple of
+    the standard forward-error estimate for radix-2 FFT convolution)."""
+    nu2 = math.sqrt(float(np.dot(u.astype(np.float64), u.astype(np.float64))))
+    nv2 = math.sqrt(float(np.dot(v.astype(np.float64), v.astype(np.float64))))
+    eps = np.finfo(np.float64).eps
+    return nu2 * nv2 * 3.0 * math.log2(n_fft) * 8.0 * eps
+
+
+def xcorr_long_certified(u, v, lag_lo: int, lag_hi: int, check_lags=None):
+    """Exact int64 r over [lag_lo, lag_hi] for long sequences.
+
+    The float64 FFT correlation of the integer sequences is rounded to the
+    nearest integer; the result is exact when the rounding-error bound is
+    below 1/2, which is asserted. The lags in ``check_lags`` are additionally
+    recomputed by direct int64 sums and must agree."""
+    u, v = _i8(u), _i8(v)
+    nu, nv = u.size, v.size
+    n = 1
+    while n < nu + nv - 1:
+        n *= 2
+    bound = fft_rounding_bound(u, v, n)
+    if not bound < 0.5:
+        raise ArithmeticError(f"FFT rounding bound {bound} not below 1/2")
+    # r[tau] = sum_m u[m] v[m+tau]; with ur = reversed u, (ur conv v)[j] = r[j - (nu-1)]
+    ur = u[::-1].astype(np.float64)
+    full = np.fft.irfft(np.fft.rfft(ur, n) * np.fft.rfft(v.astype(np.float64), n), n)
+    full = full[: nu + nv - 1]
+    rounded = np.rint(full)
+    taus = np.arange(lag_lo, lag_hi + 1, dtype=np.int64)
+    idx = taus + (nu - 1)
+    r = np.zeros(taus.size, dtype=np.int64)
+    ok = (idx >= 0) & (idx < nu + nv - 1)
+    r[ok] = rounded[idx[ok]].astype(np.int64)
+    if check_lags is not None:
+        check_lags = np.ascontiguousarray(check_lags, dtype=np.int64)
+        direct = xcorr_at(u, v, check_lags)
+        got = r[check_lags - lag_lo]
+        if not np.array_equal(direct, got):
+            raise ArithmeticError("certified FFT route disagrees with direct sums")
+    return r

@@ -1,0 +1,183 @@
+/*
+ * CPU oracle for the exact integer time-difference estimator.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product path links, loads or calls
+ * this file; only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark do. It shares no code, header or table with the HIP library.
+ *
+ * Everything here is the plain definition written out, in the order the paper
+ * states it, with no blocking or reordering:
+ *   - the cross-correlation (x * y)[n] = sum_m x[m] y[m+n] of two finite-length
+ *     sequences (Section 2.2, Eq. (1));
+ *   - Algorithm 1, line 2: integer-valued monotone maps phi, psi with
+ *     phi(0) = psi(0) = 0 (sign with sign(0) = 0 as in Section 4.2, or a
+ *     symmetric mid-tread uniform quantizer on [-3 sigma, 3 sigma]);
+ *   - Algorithm 1, line 3: w = u * v, accumulated in int64;
+ *   - Algorithm 1, line 4: the argmax set, reported as its smallest element,
+ *     the maximum and the size of the set (Remark 1: ties are legitimate).
+ *   - the real-valued correlation of the unquantized signals in float64,
+ *     summed in ascending m (used by Algorithm 1, lines 5-6).
+ *
+ * Plain C, compiled without fast-math: every float operation below is one
+ * correctly rounded IEEE-754 operation.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- scale -- */
+
+/* Sum of squares used for the per-signal scale sigma. The paper does not fix
+ * how sigma is computed; this oracle fixes it so that two implementations can
+ * agree bit for bit:
+ *   s_m = (double)x_m * (double)x_m for finite x_m (exact in float64), 0 else;
+ *   repeatedly replace the list by the sums of consecutive groups of 256
+ *   entries (last group zero-padded), each group summed left to right in
+ *   float64, until one value remains. */
+#define ORACLE_FANIN 256
+
+static double group_sum(const double* a, int64_t len) {
+    double acc = 0.0;
+    for (int64_t i = 0; i < len; ++i) acc += a[i];
+    return acc;
+}
+
+/* scratch must hold ceil(n/256) doubles. */
+double oracle_sumsq_tree(const float* x, int64_t n, double* scratch) {
+    if (n <= 0) return 0.0;
+    int64_t ng = (n + ORACLE_FANIN - 1) / ORACLE_FANIN;
+    for (int64_t g = 0; g < ng; ++g) {
+        double acc = 0.0;
+        int64_t lo = g * ORACLE_FANIN, hi = lo + ORACLE_FANIN;
+        if (hi > n) hi = n;
+        for (int64_t m = lo; m < hi; ++m) {
+            double xm = (double)x[m];
+            double s = isfinite(xm) ? xm * xm : 0.0;
+            acc += s;
+        }
+        scratch[g] = acc;
+    }
+    int64_t len = ng;
+    while (len > 1) {
+        int64_t nn = (len + ORACLE_FANIN - 1) / ORACLE_FANIN;
+        for (int64_t g = 0; g < nn; ++g) {
+            int64_t lo = g * ORACLE_FANIN, hi = lo + ORACLE_FANIN;
+            if (hi > len) hi = len;
+            scratch[g] = group_sum(scratch + lo, hi - lo);
+        }
+        len = nn;
+    }
+    return scratch[0];
+}
+
+/* Largest code magnitude K of a b-bit symmetric quantizer; sign (b = 1) is
+ * ternary with K = 1 (Section 4.2 uses sign with sign(0) = 0, i.e. K = 1). */
+int oracle_kmax(int bits) {
+    if (bits == 1) return 1;
+    return (1 << (bits - 1)) - 1;
+}
+
+/* inv_step of the uniform quantizer on [-3 sigma, 3 sigma] with 2K+1 cells:
+ * step = 6 sigma / (2K+1), sigma = sqrt(S / n). Zero when S is zero. */
+float oracle_inv_step_from_sumsq(double S, int64_t n, int bits) {
+    if (!(S > 0.0)) return 0.0f;
+    int K = oracle_kmax(bits);
+    double var = S / (double)n;
+    double sigma = sqrt(var);
+    double inv = (double)(2 * K + 1) / (6.0 * sigma);
+    return (float)inv;
+}
+
+/* ------------------------------------------------------------- quantize -- */
+
+static uint32_t f32_bits(float f) { uint32_t b; memcpy(&b, &f, 4); return b; }
+
+/* Algorithm 1, line 2. Returns the number of non-finite samples.
+ * bits == 1: sign from the IEEE bits: +1 for positive non-zero (including
+ *   +Inf), -1 for negative non-zero (including -Inf), 0 for +-0 and NaN.
+ * bits in {2,4,8}: K = 2^(b-1)-1, t = fl32(x * inv_step), q = clamp(rne(t),
+ *   -K, K); NaN maps to 0; inv_step == 0 maps everything to 0. */
+int64_t oracle_quantize(const float* x, int64_t n, int bits, float inv_step, int8_t* q) {
+    int64_t nonfinite = 0;
+    int K = oracle_kmax(bits);
+    for (int64_t m = 0; m < n; ++m) {
+        uint32_t b = f32_bits(x[m]);
+        uint32_t mag = b & 0x7fffffffu;
+        int is_nan = mag > 0x7f800000u;
+        int is_inf = mag == 0x7f800000u;
+        if (is_nan || is_inf) nonfinite++;
+        int8_t out;
+        if (bits == 1) {
+            if (is_nan || mag == 0) out = 0;
+            else out = (b >> 31) ? -1 : 1;
+        } else {
+            if (is_nan || inv_step == 0.0f) {
+                out = 0;
+            } else {
+                float t = x[m] * inv_step;     /* one rounded fp32 multiply */
+                float rq = rintf(t);           /* ties to even (default mode) */
+                if (rq > (float)K) rq = (float)K;
+                if (rq < -(float)K) rq = -(float)K;
+                out = (int8_t)(int)rq;
+            }
+        }
+        q[m] = out;
+    }
+    return nonfinite;
+}
+
+/* ---------------------------------------------------------- correlation -- */
+
+/* Eq. (1) on integer sequences u on [0, nu), v on [0, nv), zero elsewhere:
+ * r[i] = sum_m u[m] v[m + tau], tau = lag_lo + i, int64 accumulation. */
+static int64_t xcorr_one(const int8_t* u, int64_t nu, const int8_t* v, int64_t nv, int64_t tau) {
+    int64_t m0 = tau < 0 ? -tau : 0;
+    int64_t m1 = nu < nv - tau ? nu : nv - tau;
+    int64_t acc = 0;
+    for (int64_t m = m0; m < m1; ++m) acc += (int64_t)u[m] * (int64_t)v[m + tau];
+    return acc;
+}
+
+void oracle_xcorr_i64(const int8_t* u, int64_t nu, const int8_t* v, int64_t nv,
+                      int64_t lag_lo, int64_t lag_hi, int64_t* r) {
+    int64_t L = lag_hi - lag_lo + 1;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < L; ++i) r[i] = xcorr_one(u, nu, v, nv, lag_lo + i);
+}
+
+/* The same sum at an arbitrary list of lags. */
+void oracle_xcorr_i64_at(const int8_t* u, int64_t nu, const int8_t* v, int64_t nv,
+                         const int64_t* lags, int64_t nlags, int64_t* r) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < nlags; ++i) r[i] = xcorr_one(u, nu, v, nv, lags[i]);
+}
+
+/* Algorithm 1, line 4 over r[0..L): the maximum, the smallest maximising lag
+ * and the number of maximisers. */
+void oracle_argmax_i64(const int64_t* r, int64_t L, int64_t lag_lo,
+                       int64_t* lag, int64_t* rmax, int64_t* nties) {
+    int64_t best = r[0], at = 0, cnt = 1;
+    for (int64_t i = 1; i < L; ++i) {
+        if (r[i] > best) { best = r[i]; at = i; cnt = 1; }
+        else if (r[i] == best) cnt++;
+    }
+    *lag = lag_lo + at;
+    *rmax = best;
+    *nties = cnt;
+}
+
+/* Eq. (1) on the unquantized float signals, in float64, summed in ascending
+ * m. Used for the refinement of tied lags (Algorithm 1, lines 5-6) and for the
+ * accuracy of the plain real correlation. */
+void oracle_xcorr_f64_at(const float* x, int64_t nx, const float* y, int64_t ny,
+                         const int64_t* lags, int64_t nlags, double* r) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < nlags; ++i) {
+        int64_t tau = lags[i];
+        int64_t m0 = tau < 0 ? -tau : 0;
+        int64_t m1 = nx < ny - tau ? nx : ny - tau;
+        double acc = 0.0;
+        for (int64_t m = m0; m < m1; ++m) acc += (double)x[m] * (double)y[m + tau];
+        r[i] = acc;
+    }
+}

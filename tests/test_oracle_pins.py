@@ -1,0 +1,367 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a library
+routine that computes the same quantity, the paper's own Kronecker-substitution
+route (Section 3.2), closed-form identities, the invariance theorem
+(Theorem 1) on exact shifts, or hand-derived tiny cases.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+import oracle
+import synth
+
+
+def rand_q(rng, n, k, p_zero=0.1):
+    return synth.random_int_seq(rng, n, k, p_zero)
+
+
+# ------------------------------------------------------------ correlation --
+
+@pytest.mark.parametrize("nu,nv", [(1, 1), (1, 7), (7, 1), (5, 9), (33, 17), (300, 301), (1000, 64)])
+@pytest.mark.parametrize("k", [1, 7, 127])
+def test_xcorr_full_equals_numpy_correlate(nu, nv, k):
+    """numpy.correlate(v, u, 'full')[j] = sum_n v[n + j - (nu-1)] u[n] (exact int64)."""
+    rng = np.random.default_rng(nu * 1000 + nv + k)
+    u, v = rand_q(rng, nu, k), rand_q(rng, nv, k)
+    r = oracle.xcorr(u, v, -(nu - 1), nv - 1)
+    ref = np.correlate(v.astype(np.int64), u.astype(np.int64), "full")
+    assert r.dtype == np.int64
+    np.testing.assert_array_equal(r, ref)
+
+
+def test_xcorr_is_convolution_with_reversal():
+    """Section 3.2: correlation = convolution with one signal reversed."""
+    rng = np.random.default_rng(3)
+    u, v = rand_q(rng, 211, 127), rand_q(rng, 97, 127)
+    r = oracle.xcorr(u, v, -(u.size - 1), v.size - 1)
+    conv = np.convolve(u[::-1].astype(np.int64), v.astype(np.int64))
+    np.testing.assert_array_equal(r, conv)
+
+
+def _kronecker_product(a, b, k):
+    """Section 3.2: evaluate both polynomials at 2^L with 2^L > 2 N K^2, one
+    big-integer product, then read off the signed coefficients."""
+    n = max(len(a), len(b))
+    L = int(math.floor(math.log2(n * k * k))) + 2
+    assert 2 ** L > 2 * n * k * k
+    A = sum(int(c) << (L * i) for i, c in enumerate(a))
+    B = sum(int(c) << (L * i) for i, c in enumerate(b))
+    W = A * B
+    out = []
+    half, full = 1 << (L - 1), 1 << L
+    for _ in range(len(a) + len(b) - 1):
+        c = W & (full - 1)
+        if c >= half:
+            c -= full
+        out.append(c)
+        W = (W - c) >> L
+    assert W == 0
+    return np.array(out, dtype=np.int64)
+
+
+@pytest.mark.parametrize("n,k", [(8, 1), (64, 7), (500, 127), (4096, 1), (2048, 7)])
+def test_xcorr_equals_kronecker_substitution(n, k):
+    rng = np.random.default_rng(n + k)
+    u, v = rand_q(rng, n, k), rand_q(rng, n + 3, k)
+    r = oracle.xcorr(u, v, -(u.size - 1), v.size - 1)
+    ks = _kronecker_product(u[::-1], v, k)
+    np.testing.assert_array_equal(r, ks)
+
+
+@pytest.mark.parametrize("nu,nv,k", [(1, 1, 1), (17, 40, 7), (1000, 999, 127), (4099, 4096, 127)])
+def test_xcorr_sum_and_moment_identities(nu, nv, k):
+    """sum_tau r = (sum u)(sum v); sum_tau tau r = (sum u)(sum k v_k) - (sum m u_m)(sum v)."""
+    rng = np.random.default_rng(nu + 7 * nv)
+    u, v = rand_q(rng, nu, k), rand_q(rng, nv, k)
+    r = oracle.xcorr(u, v, -(nu - 1), nv - 1)
+    taus = np.arange(-(nu - 1), nv, dtype=object)
+    su, sv = int(u.astype(np.int64).sum()), int(v.astype(np.int64).sum())
+    mu = int((np.arange(nu) * u.astype(np.int64)).sum())
+    mv = int((np.arange(nv) * v.astype(np.int64)).sum())
+    assert int(r.sum()) == su * sv
+    assert int((taus * r.astype(object)).sum()) == su * mv - mu * sv
+
+
+def test_xcorr_partial_lag_range_and_outside_support():
+    rng = np.random.default_rng(11)
+    u, v = rand_q(rng, 50, 7), rand_q(rng, 70, 7)
+    full = oracle.xcorr(u, v, -200, 200)
+    # outside the support the correlation is zero
+    taus = np.arange(-200, 201)
+    outside = (taus < -(u.size - 1)) | (taus > v.size - 1)
+    assert np.all(full[outside] == 0)
+    sub = oracle.xcorr(u, v, -13, 29)
+    np.testing.assert_array_equal(sub, full[200 - 13:200 + 30])
+    at = oracle.xcorr_at(u, v, [-200, -49, 0, 69, 5])
+    np.testing.assert_array_equal(at, full[np.array([-200, -49, 0, 69, 5]) + 200])
+
+
+def test_xcorr_symmetry_bound_and_parity():
+    rng = np.random.default_rng(12)
+    for k in (1, 7, 127):
+        u, v = rand_q(rng, 123, k, 0.3), rand_q(rng, 77, k, 0.3)
+        r_uv = oracle.xcorr(u, v, -130, 130)
+        r_vu = oracle.xcorr(v, u, -130, 130)
+        np.testing.assert_array_equal(r_uv, r_vu[::-1])
+        for i, tau in enumerate(range(-130, 131)):
+            assert abs(int(r_uv[i])) <= oracle.overlap_count(u.size, v.size, tau) * k * k
+    # ternary: every non-zero product is +-1, so r has the parity of their count
+    u, v = rand_q(rng, 200, 1, 0.4), rand_q(rng, 180, 1, 0.4)
+    r = oracle.xcorr(u, v, -199, 179)
+    nzu, nzv = (u != 0).astype(np.int64), (v != 0).astype(np.int64)
+    cnt = np.correlate(nzv, nzu, "full")
+    assert np.all((r - cnt) % 2 == 0)
+
+
+def test_xcorr_tiny_hand_derived():
+    # u = [1, -1, 1], v = [1, 1]; lags -2..1:
+    #  tau=-2: u2 v0 = 1; tau=-1: u1 v0 + u2 v1 = -1 + 1 = 0;
+    #  tau= 0: u0 v0 + u1 v1 = 1 - 1 = 0; tau=1: u0 v1 = 1.
+    r = oracle.xcorr([1, -1, 1], [1, 1], -2, 1)
+    assert r.tolist() == [1, 0, 0, 1]
+    assert oracle.argmax(r, -2) == (-2, 1, 2)
+    # all-positive x of length 5 delayed by 2 with zero fill, sign-quantized:
+    # u = [1,1,1,1,1], v = [0,0,1,1,1]; for 0 <= tau <= 2 the overlap with v's
+    # support is 3, so r plateaus at 3 there (a tie, Remark 1); r[-2] = v0 = 0 ... etc.
+    r = oracle.xcorr([1] * 5, [0, 0, 1, 1, 1], -4, 4)
+    assert r.tolist() == [0, 0, 1, 2, 3, 3, 3, 2, 1]
+    assert oracle.argmax(r, -4) == (0, 3, 3)
+
+
+def test_xcorr_exhaustive_ternary_n3():
+    """All 3^3 x 3^3 ternary pairs of length 3 against numpy.correlate."""
+    vals = np.array(np.meshgrid(*[[-1, 0, 1]] * 3, indexing="ij")).reshape(3, -1).T
+    for u in vals:
+        for v in vals[::3]:
+            r = oracle.xcorr(u, v, -2, 2)
+            np.testing.assert_array_equal(r, np.correlate(v, u, "full"))
+
+
+# ----------------------------------------------------------------- argmax --
+
+@pytest.mark.parametrize("seed", range(5))
+def test_argmax_matches_numpy(seed):
+    rng = np.random.default_rng(seed)
+    r = rng.integers(-5, 6, size=1000).astype(np.int64)
+    lag, rmax, nt = oracle.argmax(r, -500)
+    assert rmax == r.max()
+    assert lag == -500 + int(np.argmax(r))          # numpy: first occurrence
+    assert nt == int(np.count_nonzero(r == r.max()))
+
+
+def test_argmax_single_and_constant():
+    assert oracle.argmax(np.array([7]), 3) == (3, 7, 1)
+    assert oracle.argmax(np.zeros(11, dtype=np.int64), -5) == (-5, 0, 11)
+    big = np.array([-(2 ** 40), 2 ** 40, 2 ** 40 - 1, 2 ** 40], dtype=np.int64)
+    assert oracle.argmax(big, 0) == (1, 2 ** 40, 2)
+
+
+# -------------------------------------------------------------- quantizer --
+
+@pytest.mark.parametrize("bits", [2, 4, 8])
+def test_quantize_uniform_equals_numpy_rint(bits):
+    rng = np.random.default_rng(bits)
+    x = (rng.standard_normal(20000) * 3).astype(np.float32)
+    s = np.float32(1.37)
+    q, nf, used = oracle.quantize(x, bits, float(s))
+    K = oracle.kmax(bits)
+    ref = np.clip(np.rint(x * s), -K, K).astype(np.int8)   # float32 * float32 -> float32
+    np.testing.assert_array_equal(q, ref)
+    assert nf == 0 and used == float(s)
+
+
+def test_quantize_sign_equals_numpy_sign():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(5000).astype(np.float32)
+    x[::7] = 0.0
+    x[1::11] = -0.0
+    x[2::13] = np.float32(1e-45)      # smallest subnormal
+    x[3::13] = np.float32(-1e-45)
+    q, _, _ = oracle.quantize(x, 1)
+    np.testing.assert_array_equal(q, np.sign(x).astype(np.int8))
+
+
+def test_quantize_special_values():
+    x = np.array([0.0, -0.0, np.inf, -np.inf, np.nan, -np.nan, 1e-45, -1e-45], dtype=np.float32)
+    q1, nf1, _ = oracle.quantize(x, 1)
+    assert q1.tolist() == [0, 0, 1, -1, 0, 0, 1, -1] and nf1 == 4
+    q8, nf8, _ = oracle.quantize(x, 8, 2.0)
+    assert q8.tolist() == [0, 0, 127, -127, 0, 0, 0, 0] and nf8 == 4
+    qz, _, _ = oracle.quantize(np.array([1.0, -3.0], np.float32), 4, None)
+    assert qz.tolist() != [0, 0]
+
+
+@pytest.mark.parametrize("bits", [2, 4, 8])
+def test_quantize_thresholds_monotone_odd(bits):
+    """phi(0)=0, odd symmetry, monotone, and the exact cell edges at (k+1/2)/s.
+    With s = 1/2 the product x*s is exact, so the edge of cell k is x = 2k+1:
+    the float just below maps to k, just above to k+1, the edge itself rounds
+    half to even."""
+    K = oracle.kmax(bits)
+    s = 0.5
+    xs = []
+    for k in range(K):
+        e = np.float32(2 * k + 1)
+        xs += [np.nextafter(e, np.float32(-np.inf)), e, np.nextafter(e, np.float32(np.inf))]
+    xs = np.array(xs, dtype=np.float32)
+    q, _, _ = oracle.quantize(xs, bits, s)
+    for k in range(K):
+        lo, at, hi = q[3 * k:3 * k + 3]
+        assert lo == k and hi == k + 1
+        assert at == (k if k % 2 == 0 else k + 1)       # ties to even
+    big = np.array([2 * K + 1, 1e30, np.float32(3.4e38)], dtype=np.float32)
+    assert oracle.quantize(big, bits, s)[0].tolist() == [K, K, K]
+    rng = np.random.default_rng(5)
+    x = np.sort((rng.standard_normal(4000) * 4).astype(np.float32))
+    qs, _, _ = oracle.quantize(x, bits, 0.8125)
+    assert np.all(np.diff(qs.astype(np.int64)) >= 0)
+    qn, _, _ = oracle.quantize(-x, bits, 0.8125)
+    np.testing.assert_array_equal(qn, -qs)
+    assert oracle.quantize(np.zeros(3, np.float32), bits, 0.8125)[0].tolist() == [0, 0, 0]
+
+
+# ------------------------------------------------------------------ scale --
+
+def test_sumsq_tree_small_is_sequential_sum():
+    rng = np.random.default_rng(2)
+    for n in (1, 5, 255, 256):
+        x = rng.standard_normal(n).astype(np.float32)
+        seq = np.cumsum(x.astype(np.float64) ** 2)[-1]        # left-to-right sum
+        assert oracle.sumsq_tree(x) == seq
+
+
+def test_sumsq_tree_two_levels_and_fsum():
+    rng = np.random.default_rng(4)
+    n = 256 * 37 + 11
+    x = (rng.standard_normal(n) * 10).astype(np.float32)
+    x2 = x.astype(np.float64) ** 2
+    groups = [np.cumsum(x2[i:i + 256])[-1] for i in range(0, n, 256)]
+    assert oracle.sumsq_tree(x) == np.cumsum(np.array(groups))[-1]
+    exact = math.fsum(x2)
+    assert abs(oracle.sumsq_tree(x) - exact) <= 300 * np.finfo(np.float64).eps * exact
+    x[5] = np.nan
+    x[6] = np.inf
+    S = oracle.sumsq_tree(x)
+    assert math.isfinite(S)
+
+
+@pytest.mark.parametrize("bits", [2, 4, 8])
+@pytest.mark.parametrize("c", [0.25, 1.0, 8.0])
+def test_inv_step_closed_form(bits, c):
+    """x = +-c: S = n c^2 exactly, sigma = c, inv_step = fl32((2K+1)/(6c))."""
+    n = 1000
+    x = np.full(n, c, np.float32)
+    x[::2] = -c
+    K = oracle.kmax(bits)
+    expect = np.float32(float(Fraction(2 * K + 1) / (6 * Fraction(c))))
+    assert oracle.inv_step(x, bits) == expect
+    assert oracle.inv_step(np.zeros(7, np.float32), bits) == 0.0
+
+
+def test_uniform_quantizer_cells_tile_three_sigma():
+    """With inv_step = (2K+1)/(6 sigma), the cell of code K starts at
+    (K - 1/2) step and the outer edge (K + 1/2) step equals 3 sigma."""
+    for bits in (2, 4, 8):
+        K = oracle.kmax(bits)
+        step = Fraction(6, 2 * K + 1)          # sigma = 1
+        assert (K + Fraction(1, 2)) * step == 3
+
+
+# --------------------------------------------------------------- Theorem 1 --
+
+def _exact_shift_pair(rng, n, d, a):
+    """Untruncated support: x has its non-zeros inside a window that stays in
+    [0, n) after the shift, so x[m] = a y[m + d] holds for every m (Eq. (2))."""
+    L = n - abs(d)
+    s = rng.standard_normal(L)
+    x = np.zeros(n)
+    y = np.zeros(n)
+    x0 = max(0, -d)
+    x[x0:x0 + L] = s
+    y[x0 + d:x0 + d + L] = s / a
+    return x.astype(np.float32), y.astype(np.float32)
+
+
+def _monotone_map(rng, kind, k):
+    if kind == "sign":
+        return lambda z: np.sign(z).astype(np.int64)
+    if kind == "thresholds":
+        pos = np.sort(rng.exponential(1.0, size=k))
+        neg = np.sort(rng.exponential(1.0, size=k))
+        return lambda z: (np.searchsorted(pos, np.maximum(z, 0), side="right")
+                          - np.searchsorted(neg, np.maximum(-z, 0), side="right")).astype(np.int64)
+    if kind == "cubic":
+        return lambda z: np.trunc(np.clip(z, -3, 3) ** 3 * k / 27).astype(np.int64)
+    raise ValueError(kind)
+
+
+@settings(max_examples=60, deadline=None)
+@given(seed=st.integers(0, 10 ** 6), n=st.integers(8, 300), kind=st.sampled_from(["sign", "thresholds", "cubic"]),
+       k=st.integers(1, 20))
+def test_theorem1_peak_invariance(seed, n, kind, k):
+    """Theorem 1: for monotone phi, psi with phi(0)=psi(0)=0 the integer
+    correlation attains its maximum at the true shift nu."""
+    rng = np.random.default_rng(seed)
+    d = int(rng.integers(-(n // 2), n // 2 + 1))
+    a = float(rng.uniform(0.2, 5.0))
+    x, y = _exact_shift_pair(rng, n, d, a)
+    phi, psi = _monotone_map(rng, kind, k), _monotone_map(rng, kind, k)
+    u, v = phi(x.astype(np.float64)), psi(y.astype(np.float64))
+    assert phi(np.zeros(1))[0] == 0 and psi(np.zeros(1))[0] == 0
+    r = oracle.xcorr(u.astype(np.int8), v.astype(np.int8), -(n - 1), n - 1)
+    lag, rmax, nt = oracle.argmax(r, -(n - 1))
+    assert r[d + n - 1] == rmax
+    assert lag <= d
+    if nt == 1:
+        assert lag == d
+
+
+@pytest.mark.parametrize("bits", [1, 2, 4, 8])
+def test_algorithm1_refined_returns_true_shift(bits):
+    """Algorithm 1 with lines 5-6: ties are resolved by x * y, which is strictly
+    maximal at nu on exact shifts (Cauchy-Schwarz), so the set is {nu}."""
+    rng = np.random.default_rng(100 + bits)
+    for _ in range(20):
+        n = int(rng.integers(16, 400))
+        d = int(rng.integers(-(n // 2), n // 2 + 1))
+        x, y = _exact_shift_pair(rng, n, d, float(rng.uniform(0.5, 2.0)))
+        res = oracle.estimate_refined(x, y, bits, -(n - 1), n - 1)
+        assert res["lag_set"] == [d]
+        assert res["r"][d + n - 1] == res["rmax"]
+
+
+# ---------------------------------------------------------- float64 xcorr --
+
+def test_xcorr_f64_matches_numpy_within_rounding():
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(700).astype(np.float32)
+    y = rng.standard_normal(500).astype(np.float32)
+    lags = np.arange(-699, 500)
+    r = oracle.xcorr_f64_at(x, y, lags)
+    ref = np.correlate(y.astype(np.float64), x.astype(np.float64), "full")
+    scale = np.correlate(np.abs(y).astype(np.float64), np.abs(x).astype(np.float64), "full")
+    assert np.all(np.abs(r - ref) <= 700 * np.finfo(np.float64).eps * scale + 1e-300)
+
+
+def test_xcorr_f64_peak_at_exact_shift():
+    rng = np.random.default_rng(10)
+    x, y = _exact_shift_pair(rng, 300, 37, 1.5)
+    lags = np.arange(-299, 300)
+    r = oracle.xcorr_f64_at(x, y, lags)
+    assert lags[int(np.argmax(r))] == 37
+
+
+# ------------------------------------------------------ long-signal route --
+
+@pytest.mark.parametrize("n,k", [(4096, 127), (20000, 7)])
+def test_certified_fft_route_equals_direct(n, k):
+    rng = np.random.default_rng(n)
+    u, v = rand_q(rng, n, k), rand_q(rng, n - 5, k)
+    direct = oracle.xcorr(u, v, -(n - 1), n - 6)
+    got = oracle.xcorr_long_certified(u, v, -(n - 1), n - 6, check_lags=[-(n - 1), 0, 17])
+    np.testing.assert_array_equal(got, direct)
