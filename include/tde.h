@@ -1,0 +1,202 @@
+/*
+ * tde.h -- exact integer time-difference estimation on AMD Instinct MI355X
+ * (gfx950). C ABI of libtde.so.
+ *
+ * The method (Ueno, Sato, Ono, "On the Invariance of Cross-Correlation Peak
+ * Positions Under Monotonic Signal Transformations, with Application to Fast
+ * Time Difference Estimation"):
+ *
+ *   Section 2.2, Eq. (1):  (x * y)[tau] = sum_m x[m] y[m + tau]
+ *   Theorem 1:             for monotone non-decreasing phi, psi with
+ *                          phi(0) = psi(0) = 0, the correlation of phi(x) and
+ *                          psi(y) peaks at the same tau as that of x and y when
+ *                          x[m] = a y[m + nu] (Eq. (2)).
+ *   Algorithm 1:           quantize both signals to integers (line 2), compute
+ *                          the integer correlation exactly (line 3), take its
+ *                          argmax (line 4).
+ *
+ * Lag convention (Eqs. (1)-(2)): if y is x delayed by d samples,
+ * y[n] = x[n - d], the correlation peaks at tau = +d. Output arrays hold
+ * r[i] <-> tau = lag_lo + i.
+ *
+ * Conventions of every call:
+ *  - Every call returns an int status: TDE_OK (0) or a negative TDE_ERR_*.
+ *    Nothing throws, exits or aborts. tde_last_error() gives a thread-local
+ *    message for the last failing call of this thread.
+ *  - Array arguments are caller-owned DEVICE pointers (allocated on the
+ *    context's device), unless a parameter says "host". The library never
+ *    frees them and keeps none of them after the queued work has run; the
+ *    caller keeps them alive until its stream passes that point.
+ *  - Work is queued asynchronously on the caller's stream (a hipStream_t
+ *    passed as void*; NULL is the default stream) and is deterministic:
+ *    identical inputs give bit-identical outputs.
+ *  - Argument validation is synchronous and happens before anything is
+ *    queued. Data-dependent conditions (non-finite samples, all-zero
+ *    signals) are reported through per-result flags, not the status.
+ *  - Calls that need scratch memory take a caller-allocated device workspace
+ *    (ws, ws_bytes) whose minimum size the matching *_workspace_size call
+ *    returns; TDE_ERR_WS if it is too small. The hot calls allocate nothing.
+ */
+#ifndef TDE_H
+#define TDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------- status -- */
+#define TDE_OK               0
+#define TDE_ERR_ARG         -1   /* invalid argument (null, size, bits, range) */
+#define TDE_ERR_RANGE       -2   /* int32 result cannot hold the exact value */
+#define TDE_ERR_WS          -3   /* workspace missing or too small */
+#define TDE_ERR_HIP         -4   /* a HIP runtime call failed */
+#define TDE_ERR_UNSUPPORTED -5   /* valid request this build does not handle */
+#define TDE_ERR_IO          -6   /* file read/write failed (models) */
+
+/* r_dtype values */
+#define TDE_I32 0
+#define TDE_I64 1
+
+/* correlation engines (the autotuner picks one for TDE_PATH_AUTO) */
+#define TDE_PATH_AUTO 0
+#define TDE_PATH_MFMA 1          /* direct sums, int8 matrix cores */
+#define TDE_PATH_POPC 2          /* direct sums, bit planes (ternary codes only) */
+#define TDE_PATH_NTT  3          /* number-theoretic transform, CRT to int64 */
+
+/* result flags */
+#define TDE_FLAG_NONFINITE_X 1   /* x held NaN or Inf samples */
+#define TDE_FLAG_NONFINITE_Y 2
+#define TDE_FLAG_ZERO_X      4   /* every code of x is 0 (so r is 0 everywhere) */
+#define TDE_FLAG_ZERO_Y      8
+#define TDE_FLAG_FALLBACK   16   /* learned mode: proposal margin too low, full search used */
+
+typedef struct tde_ctx tde_ctx;
+
+/* Algorithm 1, line 4, reported for one pair: the smallest maximising lag,
+ * the maximum, and the size of the argmax set (Remark 1: the quantized
+ * correlation can have several peaks, the true shift always among them). */
+typedef struct {
+    int64_t lag;
+    int64_t rmax;
+    int32_t n_ties;
+    int32_t flags;
+} tde_peak;
+
+/* Per-signal statistics written by tde_quantize (device memory). */
+typedef struct {
+    float   inv_step;      /* scale used (0 for bits = 1 or an all-zero signal) */
+    int32_t flags;         /* TDE_FLAG_NONFINITE_X / TDE_FLAG_ZERO_X */
+    int64_t n_nonfinite;   /* NaN or Inf samples */
+    int64_t n_zero;        /* samples with code 0 */
+    int64_t sum_q;         /* sum of codes */
+    int64_t sum_q2;        /* sum of squared codes */
+} tde_qstat;
+
+/* ------------------------------------------------------------ context -- */
+
+/* Create a context bound to HIP device `device` (it becomes current while
+ * the library works). Owns the tuning table and internal caches. */
+int  tde_create(tde_ctx** ctx, int device);
+void tde_destroy(tde_ctx* ctx);
+const char* tde_status_string(int status);
+const char* tde_last_error(void);
+
+/* --------------------------------------------------------- quantize -- */
+
+/* Algorithm 1, lines 1-2: monotone integer maps phi with phi(0) = 0.
+ *
+ * x[n] (device, float32) -> q[n] (device, int8).
+ *  bits = 1: sign with sign(0) = 0 (Section 4.2), decided from the IEEE bits:
+ *            +1 for positive non-zero (incl. +Inf), -1 for negative non-zero
+ *            (incl. -Inf), 0 for +-0 and NaN. inv_step is ignored.
+ *  bits = 2, 4, 8: K = 2^(bits-1) - 1; t = fl32(x * inv_step) (one rounded
+ *            float32 multiply); q = clamp(round_half_even(t), -K, K); NaN -> 0.
+ *            The 2K+1 cells tile [-3 sigma, 3 sigma] when
+ *            inv_step = (2K+1) / (6 sigma).
+ *  inv_step <= 0 selects the automatic scale: sigma = sqrt(S / n) with S the
+ *            sum of x^2 over the finite samples, each square exact in float64,
+ *            summed in float64 in a fixed order (consecutive groups of 256
+ *            summed left to right, the group sums grouped the same way until
+ *            one value remains); inv_step = fl32((2K+1) / (6 sigma)), or 0 when
+ *            S = 0 (then every code is 0). The scale used is written to
+ *            stat->inv_step.
+ *  stat (device, may be NULL) receives the tde_qstat of the signal.
+ * Errors: TDE_ERR_ARG for n < 1, a null x/q, bits not in {1,2,4,8}, or a
+ * non-finite inv_step. ws: tde_quantize_workspace_size(n) bytes (may be 0
+ * when inv_step > 0 and stat is NULL). */
+size_t tde_quantize_workspace_size(int64_t n);
+int tde_quantize(tde_ctx* ctx, const float* x, int64_t n, int bits, float inv_step,
+                 int8_t* q, tde_qstat* stat, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------ correlation -- */
+
+/* Algorithm 1, line 3 (Eq. (1) on integer sequences), exact:
+ *   r[i] = sum_m u[m] v[m + tau],  tau = lag_lo + i,  i in [0, lag_hi - lag_lo],
+ * with u on [0, nu) and v on [0, nv), zero elsewhere (finite-length signals,
+ * Section 2.2). u and v (device, int8) hold codes with |u| <= kmax_u and
+ * |v| <= kmax_v (1..127); kmax only sizes the overflow bound and selects
+ * engines, values beyond it give undefined r. r (device) has lag_hi-lag_lo+1
+ * elements of r_dtype.
+ *  r_dtype = TDE_I32 requires max_tau overlap(tau) * kmax_u * kmax_v < 2^31
+ *  (the coefficient bound of Section 3.2), else TDE_ERR_RANGE; TDE_I64 is
+ *  always exact.
+ *  path = TDE_PATH_POPC needs kmax_u = kmax_v = 1. TDE_PATH_AUTO lets the
+ *  tuning table choose.
+ * Errors: TDE_ERR_ARG (nu, nv < 1, lag_lo > lag_hi, null pointers, kmax out
+ * of range), TDE_ERR_RANGE, TDE_ERR_WS. */
+size_t tde_xcorr_workspace_size(int64_t nu, int64_t nv, int kmax_u, int kmax_v,
+                                int64_t lag_lo, int64_t lag_hi, int path);
+int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, int64_t nv,
+                  int kmax_u, int kmax_v, int64_t lag_lo, int64_t lag_hi,
+                  void* r, int r_dtype, int path, void* ws, size_t ws_bytes, void* stream);
+
+/* Algorithm 1, line 4: over r[0 .. lag_hi-lag_lo] (device, r_dtype), writes
+ * *out (device) = {smallest tau with r = max, max, number of maximisers, 0}.
+ * Errors: TDE_ERR_ARG. ws: tde_argmax_workspace_size(lag_hi-lag_lo+1). */
+size_t tde_argmax_workspace_size(int64_t nlags);
+int tde_argmax_lag(tde_ctx* ctx, const void* r, int r_dtype, int64_t lag_lo, int64_t lag_hi,
+                   tde_peak* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------ batch -- */
+
+/* One pair of the batch. x, y: device float32 signals of nx, ny samples.
+ * Lags [lag_lo, lag_hi]; bits in {1,2,4,8}; inv_step_* <= 0 selects the
+ * automatic scale of tde_quantize. r_out (device, may be NULL): when set,
+ * receives r over the lag range in r_dtype. */
+typedef struct {
+    const float* x;
+    const float* y;
+    int64_t nx, ny;
+    int64_t lag_lo, lag_hi;
+    int32_t bits;
+    float   inv_step_x, inv_step_y;
+    int32_t r_dtype;
+    void*   r_out;
+} tde_pair;
+
+#define TDE_MODE_FULL    0
+#define TDE_MODE_LEARNED 1
+
+typedef struct {
+    int32_t mode;        /* TDE_MODE_FULL */
+    int32_t path;        /* TDE_PATH_* forced for every pair, or AUTO */
+    int32_t use_graph;   /* replay a captured HIP graph when the batch layout repeats */
+    int32_t reserved;
+} tde_opts;
+
+/* Algorithm 1, lines 1-4 for every pair of pairs_host[0..npairs) (host array):
+ * quantize x and y, correlate exactly, and write out[i] (device) for pair i.
+ * Pairs may differ in length, lag range and bits. Errors: TDE_ERR_ARG for an
+ * invalid pair (the message names it), TDE_ERR_RANGE if a requested int32 r
+ * cannot hold the exact values, TDE_ERR_WS. */
+size_t tde_estimate_workspace_size(const tde_pair* pairs_host, int64_t npairs, const tde_opts* opts);
+int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs_host, int64_t npairs,
+                       const tde_opts* opts, tde_peak* out, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDE_H */

@@ -1,0 +1,128 @@
+// Internal declarations shared by the HIP kernels and the C-ABI layer of
+// libtde.so. Nothing here is part of the public interface (include/tde.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/tde.h"
+
+namespace tde {
+
+// ------------------------------------------------------------- errors --
+int set_error(int status, const char* fmt, ...);
+#define TDE_HIP_CHECK(expr)                                                          \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            return ::tde::set_error(TDE_ERR_HIP, "%s failed: %s (%s:%d)", #expr,     \
+                                    hipGetErrorString(e_), __FILE__, __LINE__);      \
+    } while (0)
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+// floor division for possibly negative a (b > 0)
+__host__ __device__ inline int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+inline size_t align_bytes(size_t a) { return (a + 255) & ~size_t(255); }
+
+// Largest code magnitude of a b-bit quantizer (sign: ternary, K = 1).
+inline int kmax_of_bits(int bits) { return bits == 1 ? 1 : (1 << (bits - 1)) - 1; }
+
+// ------------------------------------------------------------ quantize --
+// One signal to quantize (Algorithm 1, line 2).
+struct QSig {
+    const float* x;
+    int64_t n;
+    int8_t* q;
+    tde_qstat* stat;      // may be null
+    double* gsum;         // ceil(n/256) doubles of scratch (auto scale only)
+    float* inv_out;       // where the scale in use is written (device)
+    int64_t grp_base;     // prefix of ceil(n/256) over the signals before it
+    int64_t blk_base;     // prefix of ceil(n/1024) over the signals before it
+    float inv_fixed;      // > 0: caller-supplied scale
+    int32_t bits;
+};
+
+int64_t quantize_gsum_doubles(int64_t n);
+// Queue scale (if needed) + quantization of nsig signals. `sigs_dev` holds the
+// descriptors in device memory when nsig > 1; for nsig == 1 `one` is used.
+int launch_quantize(const QSig* sigs_dev, const QSig& one, int nsig, int64_t total_groups,
+                    int64_t total_blocks, bool need_scale, hipStream_t s);
+
+// -------------------------------------------------------------- argmax --
+struct ArgPart {          // (max, smallest index, count) of a run of r
+    int64_t vmax;
+    int64_t idx;
+    int64_t cnt;
+};
+
+struct ArgSeg {           // one r array to reduce
+    const void* r;
+    int64_t L;
+    int64_t lag_lo;
+    int64_t part_base;    // first ArgPart slot of this segment
+    int32_t nparts;
+    int32_t dtype;
+    tde_peak* out;
+    const tde_qstat* stat_x;   // flags source (may be null)
+    const tde_qstat* stat_y;
+};
+
+constexpr int kArgChunk = 8192;   // r elements per partial block
+int launch_argmax(const ArgSeg* segs_dev, const ArgSeg& one, int nseg, int64_t total_parts,
+                  ArgPart* parts, hipStream_t s);
+
+// ---------------------------------------------------------------- xcorr --
+// One exact integer correlation r = u * v over [lag_lo, lag_hi].
+struct XPair {
+    const int8_t* u;
+    const int8_t* v;
+    int64_t nu, nv;
+    int64_t lag_lo, lag_hi;
+    void* r;              // lag_hi - lag_lo + 1 elements
+    int32_t r_dtype;
+    int32_t kuv;          // kmax_u * kmax_v
+};
+
+// fill r with zeros (a kernel, never a memset node)
+int launch_zero(void* p, size_t bytes, hipStream_t s);
+
+// One correlation job for a batched engine launch: the pair plus its plan.
+struct XItem {
+    XPair p;
+    int32_t engine;       // TDE_PATH_MFMA or TDE_PATH_POPC: kernels skip other items
+    int64_t T_start;      // first lag of tile 0
+    int64_t item_m;       // m values per work item (split of the m loop)
+    int64_t ntiles;       // lag tiles of this pair
+    int64_t nsplit;       // work items per tile (upper bound)
+    // bit-plane engine only
+    const uint32_t* usg;
+    const uint32_t* unz;
+    const uint32_t* vsg;  // word of sample 0 (zero padding before and after)
+    const uint32_t* vnz;
+    int64_t nuw;          // u words
+    int64_t nvw;          // v words
+};
+
+// zero the r arrays of a batch
+int launch_zero_r(const XItem* items_dev, const XItem& one, int nitems, int64_t max_rbytes, hipStream_t s);
+
+// direct int8-MFMA engine
+void mfma_plan(XItem& it, int64_t total_q_hint);
+int64_t mfma_total_q(const XPair& p);
+int launch_xcorr_mfma(const XItem* items_dev, const XItem& one, int nitems, int64_t max_split,
+                      int64_t max_tiles, hipStream_t s);
+
+// bit-plane engine for ternary codes
+size_t popc_ws_bytes(const XPair& p);
+// fills the plane pointers of `it` (inside ws) and its plan
+void popc_plan(XItem& it, void* ws);
+int launch_popc_pack(const XItem* items_dev, const XItem& one, int nitems, int64_t max_words, hipStream_t s);
+int launch_xcorr_popc(const XItem* items_dev, const XItem& one, int nitems, int64_t max_split,
+                      int64_t max_tiles, hipStream_t s);
+
+// int8 copy helper
+int launch_copy_bytes(void* dst, const void* src, size_t n, hipStream_t s);
+
+}  // namespace tde

@@ -1,0 +1,131 @@
+"""Host-side checks of libtde.so that need no GPU: the library loads, exports
+every entry point declared in include/tde.h, sizes workspaces, and rejects
+invalid arguments before queueing any work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2509_19974_amd import tde
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(tde_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = tde.load_library()
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings():
+    assert tde.tde_status_string(0) == "ok"
+    assert "int32" in tde.tde_status_string(tde.TDE_ERR_RANGE)
+    assert tde.tde_status_string(-99) == "unknown status"
+
+
+def test_struct_sizes_match_header():
+    assert tde.PEAK_DTYPE.itemsize == 24
+    assert tde.QSTAT_DTYPE.itemsize == 40
+    assert ctypes.sizeof(tde.tde_pair) == 8 * 6 + 4 * 4 + 8
+    assert ctypes.sizeof(tde.tde_opts) == 16
+
+
+def test_workspace_sizes():
+    assert tde.tde_quantize_workspace_size(0) == 0
+    assert tde.tde_quantize_workspace_size(1) > 0
+    assert tde.tde_quantize_workspace_size(1 << 22) >= 8 * (1 << 14)
+    assert tde.tde_argmax_workspace_size(131071) >= 16 * 24
+    assert tde.tde_xcorr_workspace_size(4096, 4096, 1, 1, -1024, 1024, tde.TDE_PATH_POPC) > 0
+    assert tde.tde_xcorr_workspace_size(4096, 4096, 7, 7, -1024, 1024, tde.TDE_PATH_MFMA) == 0
+
+
+FAKE = 0x10000   # never dereferenced: validation returns first
+
+
+def _xcorr_status(**kw):
+    a = dict(ctx=None, u=FAKE, nu=100, v=FAKE, nv=100, ku=1, kv=1, lo=-10, hi=10, r=FAKE, dt=tde.TDE_I64,
+             path=tde.TDE_PATH_AUTO)
+    a.update(kw)
+    lib = tde.load_library()
+    return lib.tde_xcorr_int(a["ctx"], a["u"], a["nu"], a["v"], a["nv"], a["ku"], a["kv"], a["lo"], a["hi"],
+                             a["r"], a["dt"], a["path"], None, 0, None)
+
+
+def test_xcorr_argument_validation():
+    assert _xcorr_status(lo=5, hi=4) == tde.TDE_ERR_ARG
+    assert _xcorr_status(nu=0) == tde.TDE_ERR_ARG
+    assert _xcorr_status(u=None) == tde.TDE_ERR_ARG
+    assert _xcorr_status(ku=0) == tde.TDE_ERR_ARG
+    assert _xcorr_status(ku=128) == tde.TDE_ERR_ARG
+    assert _xcorr_status(dt=7) == tde.TDE_ERR_ARG
+    assert _xcorr_status(r=FAKE + 2, dt=tde.TDE_I32) == tde.TDE_ERR_ARG
+    assert _xcorr_status(path=tde.TDE_PATH_POPC, ku=2) == tde.TDE_ERR_ARG
+    # int32 bound of Section 3.2: overlap * Ku * Kv must stay below 2^31
+    assert _xcorr_status(nu=200000, nv=200000, ku=127, kv=127, dt=tde.TDE_I32) == tde.TDE_ERR_RANGE
+    # 133145 * 127^2 = 2147495705 >= 2^31; 133144 * 127^2 = 2147479576 < 2^31
+    assert _xcorr_status(nu=133145, nv=133145, ku=127, kv=127, dt=tde.TDE_I32, lo=0, hi=0) == tde.TDE_ERR_RANGE
+    assert _xcorr_status(nu=133144, nv=133144, ku=127, kv=127, dt=tde.TDE_I32, lo=0, hi=0) == tde.TDE_ERR_ARG
+    assert "null context" in tde.tde_last_error()
+    # far lags have a small overlap, so int32 is fine there
+    assert _xcorr_status(nu=200000, nv=200000, ku=127, kv=127, dt=tde.TDE_I32, lo=199990, hi=199999) \
+        == tde.TDE_ERR_ARG and "null context" in tde.tde_last_error()
+
+
+def test_quantize_argument_validation():
+    lib = tde.load_library()
+    q = lambda **k: lib.tde_quantize(None, k.get("x", FAKE), k.get("n", 10), k.get("bits", 4),
+                                     k.get("inv", 1.0), k.get("q", FAKE), None, None, 0, None)
+    assert q(n=0) == tde.TDE_ERR_ARG
+    assert q(bits=3) == tde.TDE_ERR_ARG
+    assert q(inv=float("nan")) == tde.TDE_ERR_ARG
+    assert q(inv=float("inf")) == tde.TDE_ERR_ARG
+    assert q(x=None) == tde.TDE_ERR_ARG
+    assert q() == tde.TDE_ERR_ARG and "null context" in tde.tde_last_error()
+
+
+def test_batch_argument_validation():
+    def pair(**k):
+        p = tde.tde_pair()
+        p.x, p.y = FAKE, FAKE
+        p.nx, p.ny = k.get("nx", 100), k.get("ny", 100)
+        p.lag_lo, p.lag_hi = k.get("lo", -5), k.get("hi", 5)
+        p.bits = k.get("bits", 4)
+        p.inv_step_x = k.get("sx", 0.0)
+        p.inv_step_y = 0.0
+        p.r_dtype = k.get("dt", tde.TDE_I64)
+        p.r_out = k.get("r", None)
+        return p
+    opts = tde.tde_opts(tde.TDE_MODE_FULL, tde.TDE_PATH_AUTO, 0, 0)
+    good = tde.make_pairs([pair(), pair(nx=7, ny=300, bits=1)])
+    assert tde.tde_estimate_workspace_size(good, 2, opts) > 0
+    for bad in (pair(bits=5), pair(lo=3, hi=2), pair(nx=0), pair(sx=float("nan"))):
+        arr = tde.make_pairs([pair(), bad])
+        assert tde.tde_estimate_workspace_size(arr, 2, opts) == 0
+        assert "pair 1" in tde.tde_last_error()
+    arr = tde.make_pairs([pair(nx=300000, ny=300000, bits=8, lo=-10, hi=10, dt=tde.TDE_I32, r=FAKE)])
+    lib = tde.load_library()
+    st = lib.tde_estimate_batch(None, arr, 1, ctypes.byref(opts), FAKE, FAKE, 1 << 30, None)
+    assert st == tde.TDE_ERR_RANGE
+    st = lib.tde_estimate_batch(None, good, 2, ctypes.byref(opts), FAKE, FAKE, 16, None)
+    assert st == tde.TDE_ERR_WS
+
+
+def test_no_gpu_means_no_context():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(tde.TDEError):
+        tde.tde_create(0)

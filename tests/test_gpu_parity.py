@@ -1,0 +1,279 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Integer results (codes, r, lags, maxima, tie counts) must be bit-exact. The
+scale of the uniform quantizer is a float computation with a fixed order, so
+the automatic scale must also match the oracle's bit for bit."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    from paper_2509_19974_amd import tde
+    c = tde.Context(0)
+    yield c
+    T.cuda.synchronize()
+    c.close()
+
+
+def dev(T, a):
+    return T.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+# ---------------------------------------------------------------- quantize --
+
+@pytest.mark.parametrize("n", [1, 5, 1023, 1024, 1025, 65543, 300000])
+@pytest.mark.parametrize("bits", [1, 2, 4, 8])
+def test_quantize_auto_scale_parity(T, ctx, n, bits):
+    from paper_2509_19974_amd import tde
+    say(f"quantize auto n={n} bits={bits}")
+    rng = np.random.default_rng(n * 10 + bits)
+    x = (rng.standard_normal(n) * rng.uniform(0.1, 10)).astype(np.float32)
+    if n > 20:
+        x[3] = 0.0
+        x[7] = -0.0
+        x[11] = np.float32(1e-42)
+    q, stat = ctx.quantize(dev(T, x), bits, 0.0)
+    T.cuda.synchronize()
+    qo, nf, so = oracle.quantize(x, bits)
+    np.testing.assert_array_equal(q.cpu().numpy(), qo)
+    st = tde.decode_qstat(stat)[0]
+    assert st["inv_step"] == np.float32(so)
+    assert st["n_nonfinite"] == nf
+    assert st["n_zero"] == int(np.count_nonzero(qo == 0))
+    assert st["sum_q"] == int(qo.astype(np.int64).sum())
+    assert st["sum_q2"] == int((qo.astype(np.int64) ** 2).sum())
+
+
+@pytest.mark.parametrize("bits", [2, 4, 8])
+def test_quantize_fixed_scale_and_specials(T, ctx, bits):
+    from paper_2509_19974_amd import tde
+    say(f"quantize fixed bits={bits}")
+    rng = np.random.default_rng(bits)
+    x = (rng.standard_normal(10000) * 3).astype(np.float32)
+    x[:8] = [np.nan, np.inf, -np.inf, 0.0, -0.0, 1e-45, -1e-45, 3.4e38]
+    x[8:8 + 2 * 127] = np.repeat(np.arange(-127, 127) + 0.5, 1)[:254].astype(np.float32) * 2   # ties at s=0.5
+    for s in (0.5, 1.37, 123.25):
+        q, stat = ctx.quantize(dev(T, x), bits, s)
+        qo, nf, _ = oracle.quantize(x, bits, s)
+        np.testing.assert_array_equal(q.cpu().numpy(), qo)
+        st = tde.decode_qstat(stat)[0]
+        assert st["n_nonfinite"] == nf == 3
+        assert st["flags"] & tde.TDE_FLAG_NONFINITE_X
+
+
+def test_quantize_all_zero_and_sign_specials(T, ctx):
+    from paper_2509_19974_amd import tde
+    q, stat = ctx.quantize(dev(T, np.zeros(777, np.float32)), 8, 0.0)
+    st = tde.decode_qstat(stat)[0]
+    assert st["inv_step"] == 0.0 and st["flags"] & tde.TDE_FLAG_ZERO_X
+    assert not q.cpu().numpy().any()
+    x = np.array([0.0, -0.0, np.inf, -np.inf, np.nan, 1e-45, -1e-45, 2.0], np.float32)
+    q, _ = ctx.quantize(dev(T, x), 1, 0.0)
+    assert q.cpu().numpy().tolist() == [0, 0, 1, -1, 0, 1, -1, 1]
+
+
+def test_quantize_unaligned_views(T, ctx):
+    say("quantize unaligned")
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(5003).astype(np.float32)
+    xd = dev(T, x)
+    for off in (1, 2, 3):
+        q, _ = ctx.quantize(xd[off:], 4, 0.0)
+        qo, _, _ = oracle.quantize(x[off:], 4)
+        np.testing.assert_array_equal(q.cpu().numpy(), qo)
+
+
+# ------------------------------------------------------------- correlation --
+
+XCASES = [
+    # nu, nv, lag_lo, lag_hi, k
+    (1, 1, 0, 0, 1),
+    (1, 1, -3, 3, 127),
+    (5, 9, -4, 8, 7),
+    (37, 1000, -40, 1010, 127),
+    (1000, 37, -1010, 40, 1),
+    (4096, 4096, -1024, 1024, 1),
+    (4096, 4100, -4095, 4099, 127),
+    (20000, 17000, -19999, 16999, 127),
+    (70001, 65536, -3000, 2500, 7),
+    (3000, 3000, 5000, 9000, 7),          # entirely outside the support
+    (3000, 3000, -9000, -2990, 7),        # crossing the lower support edge
+    (33333, 33000, 16001, 32999, 1),
+    (9000, 150000, 100000, 100300, 127),
+]
+
+
+def _run_xcorr(T, ctx, path, nu, nv, lo, hi, k, dtype):
+    from paper_2509_19974_amd import tde
+    rng = np.random.default_rng(nu * 7 + nv + k + (hi - lo))
+    u = synth.random_int_seq(rng, nu, k, 0.2)
+    v = synth.random_int_seq(rng, nv, k, 0.2)
+    say(f"xcorr path={path} nu={nu} nv={nv} lags=[{lo},{hi}] k={k} dtype={dtype}")
+    r = ctx.xcorr(dev(T, u), dev(T, v), k, k, lo, hi, dtype, path)
+    T.cuda.synchronize()
+    ro = oracle.xcorr(u, v, lo, hi)
+    np.testing.assert_array_equal(r.cpu().numpy().astype(np.int64), ro)
+    return r, ro
+
+
+@pytest.mark.parametrize("case", XCASES)
+def test_xcorr_mfma_parity(T, ctx, case):
+    from paper_2509_19974_amd import tde
+    nu, nv, lo, hi, k = case
+    _run_xcorr(T, ctx, tde.TDE_PATH_MFMA, nu, nv, lo, hi, k, tde.TDE_I64)
+
+
+@pytest.mark.parametrize("case", [c for c in XCASES if c[4] * c[4] * min(c[0], c[1]) < 2 ** 31])
+def test_xcorr_mfma_parity_i32(T, ctx, case):
+    from paper_2509_19974_amd import tde
+    nu, nv, lo, hi, k = case
+    _run_xcorr(T, ctx, tde.TDE_PATH_MFMA, nu, nv, lo, hi, k, tde.TDE_I32)
+
+
+@pytest.mark.parametrize("case", [c[:4] + (1,) for c in XCASES])
+def test_xcorr_popc_parity(T, ctx, case):
+    from paper_2509_19974_amd import tde
+    nu, nv, lo, hi, k = case
+    _run_xcorr(T, ctx, tde.TDE_PATH_POPC, nu, nv, lo, hi, 1, tde.TDE_I32)
+
+
+def test_xcorr_unaligned_inputs(T, ctx):
+    from paper_2509_19974_amd import tde
+    rng = np.random.default_rng(77)
+    u = synth.random_int_seq(rng, 9000, 127)
+    v = synth.random_int_seq(rng, 8000, 127)
+    ud, vd = dev(T, u), dev(T, v)
+    for off in (1, 5, 15):
+        say(f"xcorr unaligned off={off}")
+        r = ctx.xcorr(ud[off:], vd[off + 1:], 127, 127, -2000, 3000, tde.TDE_I64, tde.TDE_PATH_MFMA)
+        np.testing.assert_array_equal(r.cpu().numpy(), oracle.xcorr(u[off:], v[off + 1:], -2000, 3000))
+
+
+def test_xcorr_near_int32_bound(T, ctx):
+    """Longest int32-safe overlap with extreme codes: every product is 127^2."""
+    from paper_2509_19974_amd import tde
+    n = 133144
+    u = np.full(n, 127, np.int8)
+    v = np.full(n, -127, np.int8)
+    say("xcorr int32 bound")
+    r = ctx.xcorr(dev(T, u), dev(T, v), 127, 127, -5, 5, tde.TDE_I32, tde.TDE_PATH_MFMA)
+    ro = oracle.xcorr(u, v, -5, 5)
+    assert ro.min() == -n * 127 * 127
+    np.testing.assert_array_equal(r.cpu().numpy().astype(np.int64), ro)
+    r64 = ctx.xcorr(dev(T, np.full(300000, 127, np.int8)), dev(T, np.full(300000, 127, np.int8)), 127, 127,
+                    -3, 3, tde.TDE_I64, tde.TDE_PATH_MFMA)
+    np.testing.assert_array_equal(r64.cpu().numpy(), oracle.xcorr(np.full(300000, 127, np.int8),
+                                                                   np.full(300000, 127, np.int8), -3, 3))
+
+
+# ------------------------------------------------------------------ argmax --
+
+@pytest.mark.parametrize("L,dt", [(1, 0), (7, 1), (8192, 0), (8193, 1), (100003, 0)])
+def test_argmax_parity(T, ctx, L, dt):
+    from paper_2509_19974_amd import tde
+    rng = np.random.default_rng(L)
+    r = rng.integers(-50, 50, size=L).astype(np.int32 if dt == 0 else np.int64)
+    if L > 10:
+        r[rng.integers(0, L, 5)] = 50          # several ties at the maximum
+    if dt == 1:
+        r = r * (1 << 33)
+    out = ctx.argmax(dev(T, r), -12345, -12345 + L - 1)
+    pk = tde.decode_peaks(out)[0]
+    lag, rmax, nt = oracle.argmax(r.astype(np.int64), -12345)
+    assert (pk["lag"], pk["rmax"], pk["n_ties"]) == (lag, rmax, nt)
+
+
+# ------------------------------------------------------------------- batch --
+
+def _batch(T, ctx, pairs, path=0, want_r=False):
+    from paper_2509_19974_amd import tde
+    specs = []
+    for p in pairs:
+        s = dict(x=dev(T, p["x"]), y=dev(T, p["y"]), lag_lo=p["lag_lo"], lag_hi=p["lag_hi"], bits=p["bits"])
+        if want_r:
+            s["r_out"] = T.empty(p["lag_hi"] - p["lag_lo"] + 1, dtype=T.int64, device="cuda")
+            s["r_dtype"] = tde.TDE_I64
+        specs.append(s)
+    out = ctx.estimate_batch(specs, path)
+    T.cuda.synchronize()
+    return tde.decode_peaks(out), specs
+
+
+def _check_pair(pk, p, r_gpu=None):
+    res = oracle.estimate(p["x"], p["y"], p["bits"], p["lag_lo"], p["lag_hi"])
+    assert (pk["lag"], pk["rmax"], pk["n_ties"]) == (res["lag"], res["rmax"], res["n_ties"])
+    if r_gpu is not None:
+        np.testing.assert_array_equal(r_gpu, res["r"])
+    return res
+
+
+@pytest.mark.parametrize("path", [0, 1, 2])
+def test_batch_config1_single_pair(T, ctx, path):
+    say(f"batch c1 path={path}")
+    pairs = synth.config1_single(npairs=4)
+    pk, specs = _batch(T, ctx, pairs, path, want_r=True)
+    for i, p in enumerate(pairs):
+        res = _check_pair(pk[i], p, specs[i]["r_out"].cpu().numpy())
+        assert res["lag"] == p["d"]          # 20 dB, sign quantization: the true delay
+
+
+@pytest.mark.parametrize("bits", [2, 4, 8])
+def test_batch_config2_small(T, ctx, bits):
+    say(f"batch c2-small bits={bits}")
+    pairs = synth.config2_batch(bits, npairs=6, n=4096)
+    pk, specs = _batch(T, ctx, pairs, 0, want_r=True)
+    for i, p in enumerate(pairs):
+        _check_pair(pk[i], p, specs[i]["r_out"].cpu().numpy())
+
+
+def test_batch_mixed_lengths_bits_and_ranges(T, ctx):
+    say("batch mixed")
+    pairs = synth.config4_uneven(npairs=24, nmin_log2=6, nmax_log2=13)
+    pk, specs = _batch(T, ctx, pairs, 0, want_r=True)
+    for i, p in enumerate(pairs):
+        _check_pair(pk[i], p, specs[i]["r_out"].cpu().numpy())
+
+
+def test_batch_deterministic(T, ctx):
+    pairs = synth.config2_batch(4, npairs=4, n=8192)
+    a, _ = _batch(T, ctx, pairs)
+    b, _ = _batch(T, ctx, pairs)
+    assert a.tobytes() == b.tobytes()
+
+
+def test_batch_config2_full_size_sampled(T, ctx):
+    """The 64-pair, N = 65536, b = 8 batch at full size in the benchmark's
+    launch configuration: the GPU's rmax must equal the oracle's direct sum at
+    the GPU's lag, and on 3 pairs the whole oracle argmax must agree."""
+    from paper_2509_19974_amd import tde
+    say("batch c2 full size")
+    pairs = synth.config2_batch(8, npairs=64, n=65536)
+    pk, _ = _batch(T, ctx, pairs)
+    for i, p in enumerate(pairs):
+        u, _, _ = oracle.quantize(p["x"], 8)
+        v, _, _ = oracle.quantize(p["y"], 8)
+        at = oracle.xcorr_at(u, v, [int(pk[i]["lag"]), p["d"]])
+        assert at[0] == pk[i]["rmax"]
+        assert at[1] <= pk[i]["rmax"]
+    for i in (0, 31, 63):
+        _check_pair(pk[i], pairs[i])
