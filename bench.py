@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Throughput of the exact integer time-difference estimator on one MI355X.
+
+One step = one call of tde_estimate_batch over the whole batch (Algorithm 1,
+lines 1-4 for every pair: scale + quantize, exact integer correlation over the
+full lag range, argmax), with the float32 inputs already resident in HBM.
+
+Default workload: 64 pairs of N = 65536 float32 AR(2) coloured noise (poles
+0.95, 0.6), delays uniform in [-N/4, N/4], SNR uniform in [0, 30] dB, uniform
+quantizer on [-3 sigma, 3 sigma] with b in {2, 4, 8} (pair i takes b =
+(2, 4, 8)[i % 3]), full lag range [-(N-1), N-1].
+
+Prints ONE JSON line (rank 0) with pairs/s, the algorithmic integer MAC rate,
+the roofline of the dominant kernel (the int8 matrix-core correlation, timed
+with HIP events on the stream it runs on), an FP32 FFT cross-correlation of
+the same pairs on the same GPU, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 matrix peak, 5.0 POP/s
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def alg_macs(nx: int, ny: int, lo: int, hi: int) -> int:
+    """sum over tau in [lo, hi] of #{m : 0 <= m < nx, 0 <= m + tau < ny}."""
+    import numpy as np
+    t = np.arange(lo, hi + 1, dtype=np.int64)
+    ov = np.minimum(nx, ny - t) - np.maximum(0, -t)
+    return int(np.clip(ov, 0, None).sum())
+
+
+def make_workload(name: str):
+    import synth
+    if name == "c2":
+        pairs = synth.config2_batch(8, npairs=64, n=65536)
+        for i, p in enumerate(pairs):
+            p["bits"] = (2, 4, 8)[i % 3]
+        desc = {"workload": "batch of 64 pairs, N=65536, AR(2) noise, b in {2,4,8}, full lag range",
+                "pairs": 64, "n": 65536, "bits": [2, 4, 8], "lags": "[-(N-1), N-1]"}
+        return pairs, desc
+    if name == "c1":
+        pairs = synth.config1_single(npairs=1)
+        desc = {"workload": "single pair, N=4096 white noise, sign quantization, lags [-1024, 1024]",
+                "pairs": 1, "n": 4096, "bits": [1], "lags": "[-1024, 1024]"}
+        return pairs, desc
+    if name == "c1x":
+        pairs = synth.config1_single(npairs=16384)
+        desc = {"workload": "16384 pairs shaped like the single-pair case (N=4096, sign, lags +-1024)",
+                "pairs": 16384, "n": 4096, "bits": [1], "lags": "[-1024, 1024]"}
+        return pairs, desc
+    raise SystemExit(f"unknown workload {name}")
+
+
+def traffic_from_profile(kernel_src: str):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "xcorr_mfma_c2_pmc.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != h:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def fft_baseline(torch, xs, ys, lo, hi, steps, warmup):
+    """FP32 FFT cross-correlation r = irfft(conj(X) Y) of the float signals,
+    argmax over [lo, hi] (first maximum = smallest lag)."""
+    B, N = xs.shape
+    nfft = 1
+    while nfft < 2 * N - 1:
+        nfft *= 2
+
+    def step():
+        X = torch.fft.rfft(xs, n=nfft)
+        Y = torch.fft.rfft(ys, n=nfft)
+        c = torch.fft.irfft(torch.conj(X) * Y, n=nfft)
+        neg = c[:, nfft + lo:] if lo < 0 else c[:, :0]
+        pos = c[:, max(lo, 0):hi + 1]
+        full = torch.cat([neg, pos], dim=1)
+        return torch.argmax(full, dim=1) + lo
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        lag = step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return ms, lag.cpu().numpy()
+
+
+def cpu_baseline(pairs, budget_s: float = 12.0, max_pairs: int = 16):
+    import oracle
+    t0 = time.perf_counter()
+    done = 0
+    macs = 0
+    for p in pairs[:max_pairs]:
+        oracle.estimate(p["x"], p["y"], p["bits"], p["lag_lo"], p["lag_hi"])
+        done += 1
+        macs += alg_macs(p["x"].size, p["y"].size, p["lag_lo"], p["lag_hi"])
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "pairs/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{done} of {len(pairs)} pairs, full Algorithm 1 lines 1-4 (scale, quantize, int64 direct "
+                      f"sums over every lag, argmax), {el:.1f} s",
+            "int_mac_per_s": macs / el}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fft", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "the pairs of a batch are independent, see the sharding note in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2509_19974_amd import tde
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log(f"[bench] generating workload {args.workload}")
+    pairs, desc = make_workload(args.workload)
+    ctx = tde.Context(0)
+    specs = [dict(x=torch.from_numpy(p["x"]).cuda(), y=torch.from_numpy(p["y"]).cuda(), lag_lo=p["lag_lo"],
+                  lag_hi=p["lag_hi"], bits=p["bits"]) for p in pairs]
+    plan = ctx.batch_plan(specs)
+    ws = torch.empty(plan[2], dtype=torch.uint8, device="cuda")
+    out = torch.empty(len(pairs) * tde.PEAK_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    macs = sum(alg_macs(p["x"].size, p["y"].size, p["lag_lo"], p["lag_hi"]) for p in pairs)
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        ctx.estimate_batch(specs, ws=ws, out=out, plan=plan)
+    torch.cuda.synchronize()
+    tde.tde_timing_read(ctx.handle)
+    tde.tde_timing_enable(ctx.handle, True)
+    log(f"[bench] timing {args.steps} steps")
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        ctx.estimate_batch(specs, ws=ws, out=out, plan=plan, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    stage_ms, stage_n = tde.tde_timing_read(ctx.handle)
+    tde.tde_timing_enable(ctx.handle, False)
+    ms_step = total_ms / args.steps
+    pk = tde.decode_peaks(out)
+    d = np.array([p["d"] for p in pairs])
+    int_correct = float(np.mean((pk["lag"] == d) & (pk["n_ties"] == 1)))
+    engine_ms = stage_ms[1] / max(stage_n[1], 1)
+    log(f"[bench] {ms_step:.3f} ms/step, engine {engine_ms:.3f} ms, stages {stage_ms} {stage_n}")
+
+    achieved = 2.0 * macs / (engine_ms * 1e-3) / 1e12
+    src = os.path.join(ROOT, "paper_2509_19974_amd", "csrc", "k_xcorr_mfma.hip")
+    roof = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
+            "frac": achieved / INT8_PEAK_TOPS, "traffic": traffic_from_profile(src),
+            "kernel": "k_xcorr_mfma (int8 MFMA 32x32x32, int32 accumulation)",
+            "kernel_ms": engine_ms, "alg_macs_per_launch": macs}
+
+    result = {
+        "metric": "pairs/s and int-MAC/s vs FP32-FFT xcorr on MI355X at oracle-exact lags",
+        "value": len(pairs) * 1e3 / ms_step,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8",
+        "data": "synthetic",
+        "config": desc,
+        "int_mac_per_s": macs * 1e3 / ms_step,
+        "stage_ms": {"quantize": stage_ms[0] / max(stage_n[0], 1), "engine": engine_ms,
+                     "argmax": stage_ms[2] / max(stage_n[2], 1), "call": stage_ms[3] / max(stage_n[3], 1)},
+        "lag_accuracy": {"int": int_correct},
+        "roofline": roof,
+    }
+    if not args.no_fft:
+        log("[bench] FP32 FFT baseline")
+        N = pairs[0]["x"].size
+        if all(p["x"].size == N and p["y"].size == N and p["lag_lo"] == pairs[0]["lag_lo"]
+               and p["lag_hi"] == pairs[0]["lag_hi"] for p in pairs):
+            xs = torch.stack([s["x"] for s in specs])
+            ys = torch.stack([s["y"] for s in specs])
+            fms, flag = fft_baseline(torch, xs, ys, pairs[0]["lag_lo"], pairs[0]["lag_hi"], args.steps, args.warmup)
+            result["fft_fp32"] = {"pairs_per_s": len(pairs) * 1e3 / fms, "ms_per_step": fms,
+                                  "lag_accuracy": float(np.mean(flag == d)),
+                                  "speedup_int_over_fft": fms / ms_step}
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        result["cpu_baseline"] = cpu_baseline(pairs)
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

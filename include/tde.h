@@ -196,6 +196,18 @@ size_t tde_estimate_workspace_size(const tde_pair* pairs_host, int64_t npairs, c
 int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs_host, int64_t npairs,
                        const tde_opts* opts, tde_peak* out, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------ measurement -- */
+
+/* Stage timing of tde_estimate_batch, for benchmarks. While enabled, each
+ * call records HIP events on the caller's stream around its stages:
+ *   0 quantize (scale + codes), 1 correlation engine, 2 argmax, 3 whole call.
+ * tde_timing_read waits for the recorded events, writes the summed
+ * milliseconds and the number of timed calls per stage to ms[4] and
+ * count[4] (host arrays), and clears the record. Enabling allocates events;
+ * the estimate call itself still allocates no device memory. */
+int tde_timing_enable(tde_ctx* ctx, int on);
+int tde_timing_read(tde_ctx* ctx, double* ms, int64_t* count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,8 +77,15 @@ def _load():
     lib.oracle_argmax_i64.restype = None
     lib.oracle_xcorr_f64_at.argtypes = [vp, i64, vp, i64, vp, i64, vp]
     lib.oracle_xcorr_f64_at.restype = None
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def threads() -> int:
+    """OpenMP threads used by the direct sums."""
+    return int(_load().oracle_threads())
 
 
 def _ptr(a: np.ndarray):

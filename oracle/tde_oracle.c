@@ -181,3 +181,7 @@ void oracle_xcorr_f64_at(const float* x, int64_t nx, const float* y, int64_t ny,
         r[i] = acc;
     }
 }
+
+/* Number of OpenMP threads the direct sums use. */
+#include <omp.h>
+int oracle_threads(void) { return omp_get_max_threads(); }

@@ -21,6 +21,15 @@ struct tde_ctx {
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
     std::mutex mu;
+    // stage timing (measurement only)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    struct Mark {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
 };
 
 namespace tde {
@@ -97,6 +106,27 @@ int upload(tde_ctx* ctx, void* dst_dev, const void* src_host, size_t bytes, hipS
     return TDE_OK;
 }
 
+hipEvent_t timing_event(tde_ctx* c) {
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[c->ev_used++];
+}
+
+// Records an event on s when timing is on; returns it (or null).
+hipEvent_t mark(tde_ctx* c, hipStream_t s) {
+    if (!c->timing) return nullptr;
+    hipEvent_t e = timing_event(c);
+    if (e) (void)hipEventRecord(e, s);
+    return e;
+}
+
+void mark_stage(tde_ctx* c, int stage, hipEvent_t a, hipEvent_t b) {
+    if (c->timing && a && b) c->marks.push_back({stage, a, b});
+}
+
 // Engine choice for one correlation. The direct engines are exact for every
 // size; the bit-plane engine only takes ternary codes.
 int choose_path(int path, int kuv) {
@@ -153,9 +183,37 @@ int tde_create(tde_ctx** out, int device) {
     return TDE_OK;
 }
 
+int tde_timing_enable(tde_ctx* c, int on) {
+    if (!c) return set_error(TDE_ERR_ARG, "tde_timing_enable: null context");
+    std::lock_guard<std::mutex> lock(c->mu);
+    c->timing = on != 0;
+    return TDE_OK;
+}
+
+int tde_timing_read(tde_ctx* c, double* ms, int64_t* count) {
+    if (!c || !ms || !count) return set_error(TDE_ERR_ARG, "tde_timing_read: null pointer");
+    std::lock_guard<std::mutex> lock(c->mu);
+    DeviceGuard g(c->device);
+    for (int k = 0; k < 4; ++k) {
+        ms[k] = 0.0;
+        count[k] = 0;
+    }
+    for (auto& m : c->marks) {
+        TDE_HIP_CHECK(hipEventSynchronize(m.b));
+        float t = 0.f;
+        TDE_HIP_CHECK(hipEventElapsedTime(&t, m.a, m.b));
+        ms[m.stage] += t;
+        count[m.stage] += 1;
+    }
+    c->marks.clear();
+    c->ev_used = 0;
+    return TDE_OK;
+}
+
 void tde_destroy(tde_ctx* c) {
     if (!c) return;
     DeviceGuard g(c->device);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->upload_pending) (void)hipEventSynchronize(c->upload_done);
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);
     if (c->pinned) (void)hipHostFree(c->pinned);
@@ -433,6 +491,7 @@ int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs, int64_t np, const td
     if (!g.ok) return set_error(TDE_ERR_HIP, "tde_estimate_batch: hipSetDevice failed");
     hipStream_t s = static_cast<hipStream_t>(stream);
     uint8_t* W = static_cast<uint8_t*>(ws);
+    hipEvent_t t_begin = mark(ctx, s);
 
     // ---- descriptors (host side)
     std::vector<QSig> sigs(2 * np);
@@ -521,10 +580,14 @@ int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs, int64_t np, const td
     ArgSeg noseg{};
     QSig nosig{};
 
+    hipEvent_t t_q0 = mark(ctx, s);
     rc = launch_quantize(sigs_dev, nosig, (int)(2 * np), gbase, bbase, need_scale, s);
     if (rc) return rc;
+    hipEvent_t t_q1 = mark(ctx, s);
+    mark_stage(ctx, 0, t_q0, t_q1);
     rc = launch_zero_r(items_dev, none, (int)np, max_rbytes, s);
     if (rc) return rc;
+    hipEvent_t t_e0 = mark(ctx, s);
     if (any_popc) {
         // zero the plane buffers (padding must read as 0), then pack
         for (int64_t i = 0; i < np; ++i)
@@ -542,7 +605,14 @@ int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs, int64_t np, const td
         rc = launch_xcorr_mfma(items_dev, none, (int)np, max_split, max_tiles, s);
         if (rc) return rc;
     }
-    return launch_argmax(segs_dev, noseg, (int)np, pbase, reinterpret_cast<ArgPart*>(W + B.off_parts), s);
+    hipEvent_t t_e1 = mark(ctx, s);
+    mark_stage(ctx, 1, t_e0, t_e1);
+    rc = launch_argmax(segs_dev, noseg, (int)np, pbase, reinterpret_cast<ArgPart*>(W + B.off_parts), s);
+    if (rc) return rc;
+    hipEvent_t t_end = mark(ctx, s);
+    mark_stage(ctx, 2, t_e1, t_end);
+    mark_stage(ctx, 3, t_begin, t_end);
+    return TDE_OK;
 }
 
 }  // extern "C"

@@ -84,6 +84,8 @@ def load_library(path: str = LIB_PATH):
         "tde_argmax_lag": (i32, [vp, vp, i32, i64, i64, vp, vp, sz, vp]),
         "tde_estimate_workspace_size": (sz, [ctypes.POINTER(tde_pair), i64, ctypes.POINTER(tde_opts)]),
         "tde_estimate_batch": (i32, [vp, ctypes.POINTER(tde_pair), i64, ctypes.POINTER(tde_opts), vp, vp, sz, vp]),
+        "tde_timing_enable": (i32, [vp, i32]),
+        "tde_timing_read": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -178,6 +180,18 @@ def tde_estimate_workspace_size(pairs_arr, npairs, opts: tde_opts) -> int:
 def tde_estimate_batch(ctx, pairs_arr, npairs, opts: tde_opts, out, ws, ws_bytes, stream=None):
     _check(load_library().tde_estimate_batch(ctx, pairs_arr, npairs, ctypes.byref(opts), _ptr(out), _ptr(ws),
                                              ws_bytes, _stream(stream)))
+
+
+def tde_timing_enable(ctx, on: bool) -> None:
+    _check(load_library().tde_timing_enable(ctx, 1 if on else 0))
+
+
+def tde_timing_read(ctx):
+    """Returns (ms[4], count[4]) for stages quantize, engine, argmax, whole call."""
+    ms = (ctypes.c_double * 4)()
+    cnt = (ctypes.c_int64 * 4)()
+    _check(load_library().tde_timing_read(ctx, ms, cnt))
+    return list(ms), list(cnt)
 
 
 # ------------------------------------------------------------ conveniences --
