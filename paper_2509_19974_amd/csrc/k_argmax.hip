@@ -181,6 +181,7 @@ namespace tde {
 // Zero the r arrays of a batch: blockIdx.y selects the item.
 __global__ void k_zero_r(const XItem* items, XItem one) {
     const XItem& it = items ? items[blockIdx.y] : one;
+    if (!it.p.r) return;
     const int64_t words = (it.p.lag_hi - it.p.lag_lo + 1) * (it.p.r_dtype == TDE_I32 ? 1 : 2);
     uint32_t* r = static_cast<uint32_t*>(it.p.r);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;

@@ -16,7 +16,6 @@
 namespace tde {
 
 constexpr int kFanIn = 256;       // sum-tree fan-in (part of the scale's definition)
-constexpr int kQBlock = 1024;     // samples per quantize block (256 threads x 4)
 
 __device__ __forceinline__ const QSig& pick_sig(const QSig* sigs, int nsig, const QSig& one,
                                                 int64_t unit, bool by_group, int64_t& local) {
@@ -49,13 +48,19 @@ __global__ void __launch_bounds__(256) k_sumsq_groups(const QSig* sigs, int nsig
     double acc = 0.0;
     int64_t m = lo;
     if ((((uintptr_t)(x + m)) & 15) == 0) {
-        for (; m + 4 <= hi; m += 4) {
-            float4 f = *reinterpret_cast<const float4*>(x + m);
-            double a0 = f.x, a1 = f.y, a2 = f.z, a3 = f.w;
-            acc += __builtin_isfinite(a0) ? a0 * a0 : 0.0;
-            acc += __builtin_isfinite(a1) ? a1 * a1 : 0.0;
-            acc += __builtin_isfinite(a2) ? a2 * a2 : 0.0;
-            acc += __builtin_isfinite(a3) ? a3 * a3 : 0.0;
+        // 16 independent loads in flight, then the left-to-right additions
+        for (; m + 64 <= hi; m += 64) {
+            float4 f[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) f[k] = *reinterpret_cast<const float4*>(x + m + 4 * k);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                double a0 = f[k].x, a1 = f[k].y, a2 = f[k].z, a3 = f[k].w;
+                acc += __builtin_isfinite(a0) ? a0 * a0 : 0.0;
+                acc += __builtin_isfinite(a1) ? a1 * a1 : 0.0;
+                acc += __builtin_isfinite(a2) ? a2 * a2 : 0.0;
+                acc += __builtin_isfinite(a3) ? a3 * a3 : 0.0;
+            }
         }
     }
     for (; m < hi; ++m) {
@@ -88,7 +93,15 @@ __global__ void __launch_bounds__(256) k_scale_finalize(const QSig* sigs, int ns
                 int64_t lo = g * kFanIn;
                 int64_t hi = lo + kFanIn < len ? lo + kFanIn : len;
                 double acc = 0.0;
-                for (int64_t i = lo; i < hi; ++i) acc += a[i];
+                int64_t i = lo;
+                for (; i + 16 <= hi; i += 16) {
+                    double v[16];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) v[k] = a[i + k];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) acc += v[k];
+                }
+                for (; i < hi; ++i) acc += a[i];
                 out[g] = acc;
             }
             __syncthreads();
@@ -144,7 +157,7 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-// 256 threads x 4 samples per block.
+// 256 threads x 16 samples per block; one set of statistic atomics per block.
 __global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QSig one,
                                                   int64_t total_blocks) {
     int64_t blk = blockIdx.x;
@@ -152,49 +165,58 @@ __global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QS
     const QSig& s = pick_sig(sigs, nsig, one, blk, false, lb);
     const float inv = (s.bits == 1) ? 0.f : (s.inv_fixed > 0.f ? s.inv_fixed : *s.inv_out);
     const int K = s.bits == 1 ? 1 : (1 << (s.bits - 1)) - 1;
-    const int64_t m0 = lb * kQBlock + 4 * (int64_t)threadIdx.x;
+    const int64_t m0 = lb * kQuantBlock + 16 * (int64_t)threadIdx.x;
     int nonfinite = 0, nzero = 0;
     int sq = 0, sq2 = 0;
     if (m0 < s.n) {
-        float xs[4];
-        bool full = m0 + 4 <= s.n;
+        float xs[16];
+        const bool full = m0 + 16 <= s.n;
         if (full && ((((uintptr_t)(s.x + m0)) & 15) == 0)) {
-            float4 f = *reinterpret_cast<const float4*>(s.x + m0);
-            xs[0] = f.x; xs[1] = f.y; xs[2] = f.z; xs[3] = f.w;
-        } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) xs[e] = (m0 + e < s.n) ? s.x[m0 + e] : 0.f;
-        }
-        int c[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            c[e] = quant1(xs[e], s.bits, inv, K, nonfinite);
-            if (m0 + e < s.n) {
-                nzero += c[e] == 0;
-                sq += c[e];
-                sq2 += c[e] * c[e];
+            for (int k = 0; k < 4; ++k) {
+                float4 f = *reinterpret_cast<const float4*>(s.x + m0 + 4 * k);
+                xs[4 * k] = f.x; xs[4 * k + 1] = f.y; xs[4 * k + 2] = f.z; xs[4 * k + 3] = f.w;
             }
-        }
-        if (full && ((((uintptr_t)(s.q + m0)) & 3) == 0)) {
-            uint32_t w = (uint32_t)(uint8_t)c[0] | ((uint32_t)(uint8_t)c[1] << 8) |
-                         ((uint32_t)(uint8_t)c[2] << 16) | ((uint32_t)(uint8_t)c[3] << 24);
-            *reinterpret_cast<uint32_t*>(s.q + m0) = w;
         } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (m0 + e < s.n) s.q[m0 + e] = (int8_t)c[e];
+            for (int e = 0; e < 16; ++e) xs[e] = (m0 + e < s.n) ? s.x[m0 + e] : 0.f;
+        }
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            int c = quant1(xs[e], s.bits, inv, K, nonfinite);
+            if (m0 + e < s.n) {
+                nzero += c == 0;
+                sq += c;
+                sq2 += c * c;
+            }
+            w[e >> 2] |= (uint32_t)(uint8_t)c << (8 * (e & 3));
+        }
+        if (full && ((((uintptr_t)(s.q + m0)) & 15) == 0)) {
+            *reinterpret_cast<uint4*>(s.q + m0) = make_uint4(w[0], w[1], w[2], w[3]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                if (m0 + e < s.n) s.q[m0 + e] = (int8_t)(w[e >> 2] >> (8 * (e & 3)));
         }
     }
     if (s.stat) {
+        __shared__ long long red[4][4];
         long long a = wave_sum<long long>(nonfinite);
         long long z = wave_sum<long long>(nzero);
         long long q1 = wave_sum<long long>(sq);
         long long q2 = wave_sum<long long>(sq2);
+        const int wv = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
-            if (a) atomicAdd((unsigned long long*)&s.stat->n_nonfinite, (unsigned long long)a);
-            if (z) atomicAdd((unsigned long long*)&s.stat->n_zero, (unsigned long long)z);
-            if (q1) atomicAdd((unsigned long long*)&s.stat->sum_q, (unsigned long long)q1);
-            if (q2) atomicAdd((unsigned long long*)&s.stat->sum_q2, (unsigned long long)q2);
+            red[wv][0] = a; red[wv][1] = z; red[wv][2] = q1; red[wv][3] = q2;
+        }
+        __syncthreads();
+        if (threadIdx.x < 4) {
+            long long v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+            int64_t* dst = threadIdx.x == 0 ? &s.stat->n_nonfinite
+                           : threadIdx.x == 1 ? &s.stat->n_zero
+                           : threadIdx.x == 2 ? &s.stat->sum_q : &s.stat->sum_q2;
+            if (v) atomicAdd((unsigned long long*)dst, (unsigned long long)v);
         }
     }
 }

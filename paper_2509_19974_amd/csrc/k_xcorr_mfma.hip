@@ -1,32 +1,47 @@
 // Algorithm 1, line 3 (Eq. (1) on integer codes), exact, on the int8 matrix
-// cores of gfx950 (v_mfma_i32_32x32x32_i8, int32 accumulation).
+// cores of gfx950 (v_mfma_i32_32x32x32_i8, int32 accumulation), with the
+// argmax of line 4 taken on chip.
 //
 // The correlation r[tau] = sum_m u[m] v[m + tau] is a product of a Hankel
-// and a Toeplitz matrix. One wave owns 1024*MB consecutive lags
-//     tau = Tw + c + S*i,   c = j + 32 b in [0, S),  S = 32 MB,  i, j in [0, 32)
-// held in MB accumulator tiles C_b[i][j] (rows i: coarse lag, columns j: fine
-// lag, so the 32 lanes of a tile row hold 32 consecutive lags). The k loop
-// walks m in steps of 32:
-//     A[i][k]   = v[q + Tw + S i + k]        (rows S bytes apart, 16-byte aligned)
+// and a Toeplitz matrix. A lag tile is 1024*MB consecutive lags
+//     tau = T0 + c + S*i,   c = j + 32 b in [0, S),  S = 32 MB,  i, j in [0, 32)
+// held in MB accumulator tiles C_b[i][j] per wave (rows i: coarse lag,
+// columns j: fine lag, so the 32 lanes of a tile row hold 32 consecutive
+// lags). The k loop walks m in steps of 32:
+//     A[i][k]   = v[q + T0 + S i + k]        (rows S bytes apart, 16-byte aligned)
 //     B_b[k][j] = u[q + k - j - 32 b]        (Hankel in (k, j))
 //     C_b      += A x B_b
 // so C_b[i][j] collects u[m] v[m + tau] for m = q + k - j - 32 b. The Hankel
-// structure gives B_b(q) = B_0(q - 32 b): each step loads one new B fragment
-// and one A fragment for MB matrix instructions; the other MB-1 B fragments
-// are the previous steps' B_0, kept in registers.
+// structure gives B_b(q) = B_0(q - 32 b): each step reads one A and one new B
+// fragment for MB matrix instructions; the other MB-1 B fragments are the
+// previous steps' B_0, kept in registers.
 //
-// Windows of v and u for a chunk of 64 steps are staged in LDS (double
-// buffered) by the whole workgroup; out-of-range samples are staged as 0,
-// which is the finite-length (zero outside the support) convention of
-// Section 2.2. A rows are read with 16-byte LDS reads through an XOR swizzle
-// (rows S bytes apart would otherwise fall into one bank group); B rows start
-// at arbitrary byte offsets and are assembled from 5 aligned dwords with
-// v_alignbyte.
+// Work decomposition: a work item is one lag tile of one pair and the whole
+// m range that tile needs (or, for very long signals, one segment of it).
+// The 4 waves of a workgroup take one quarter of the m range each and run
+// independently: each wave stages its own v and u windows in a private LDS
+// region, so the main loop has no workgroup barrier. The v window of a
+// 64-step chunk (TLW + 2048 bytes) moves by 2048 bytes per chunk and lives in
+// a power-of-two ring; every S bytes carry 16 bytes of padding so the 32 rows
+// of an A fragment fall into distinct banks. B rows start at arbitrary byte
+// offsets and are assembled from 5 dwords with v_alignbyte. Out-of-range
+// samples are staged as 0: the finite-length convention of Section 2.2.
 //
-// Partial sums per work item cover at most floor((2^31-1)/(Ku Kv)) values of
-// m, so no int32 accumulator can overflow (coefficient bound of Section 3.2);
-// items add their partials to r with integer atomics, which are exact and
-// order-independent.
+// At the end of an item the four partial sums meet in LDS (ds_add). The tile
+// then writes r with plain coalesced stores when r is requested, and its
+// (max, smallest lag, count) triple, so no r array is needed for the argmax.
+// Each wave's partial covers at most floor((2^31-1)/(Ku Kv)) values of m, so
+// no int32 accumulator overflows (coefficient bound of Section 3.2); tiles
+// whose total may exceed int32 are summed in int64. Segmented tiles add into
+// r with integer atomics (exact, order-independent).
+//
+// The kernel is persistent: workgroups take items from an atomic counter over
+// a list sorted longest-first.
+#include <stdlib.h>
+
+#include <algorithm>
+#include <vector>
+
 #include "tde_internal.h"
 
 namespace tde {
@@ -37,26 +52,34 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 template <int MB>
 struct MCfg {
     static constexpr int S = 32 * MB;          // coarse lag stride, A row stride
-    static constexpr int LS = MB == 1 ? 5 : MB == 2 ? 6 : MB == 4 ? 7 : 8;
-    static constexpr int WAVES = 4;
-    static constexpr int TLW = 32 * S;         // lags per wave
-    static constexpr int TL = WAVES * TLW;     // lags per workgroup
+    static constexpr int LS = MB == 4 ? 7 : 8; // log2(S)
+    static constexpr int TLW = 32 * S;         // lags per tile
     static constexpr int CQ = 64;              // k steps per staged chunk
     static constexpr int CM = 32 * CQ;         // m per chunk
-    static constexpr int VW = TL + CM;         // staged v bytes
-    static constexpr int UOFF = 32 * MB;       // u window starts UOFF before the chunk
-    static constexpr int UW = CM + UOFF + 64;  // staged u bytes (multiple of 16)
-    static constexpr int BUF = VW + UW;
-    static constexpr int LDS = 2 * BUF;
-    static constexpr int VUNITS = VW / 16;
-    static constexpr int UUNITS = UW / 16;
-    static constexpr int PER_THREAD = (VUNITS + UUNITS + 255) / 256;
+    // per-wave v window of a chunk: [0, VW); the last A read (one step ahead)
+    // ends at TLW + CM - S + 32 <= VW
+    static constexpr int VW = TLW + CM;
+    static constexpr int R = MB == 4 ? 8192 : 16384;   // ring, >= VW + CM, power of two
+    static_assert(R >= VW + CM, "ring too small");
+    static constexpr int VPH = R + 16 * (R / S);       // padded ring bytes
+    static constexpr int UOFF = 32 * MB;               // u window starts UOFF before the chunk
+    // u window (double buffered); the last B read (one step ahead) ends at
+    // UOFF + CM + 36 <= UW
+    static constexpr int UW = CM + UOFF + 64;
+    static constexpr int WAVE_LDS = VPH + 2 * UW;
+    static constexpr int LDS = 4 * WAVE_LDS;
+    static_assert(LDS >= TLW * 8, "reduction area must fit");
+    static constexpr int FILL_V = VW / 16;             // 16-byte units
+    static constexpr int NEW_V = CM / 16;
+    static constexpr int U_UNITS = UW / 16;
+    static constexpr int FILL_PER_LANE = (FILL_V + U_UNITS + 63) / 64;
+    static constexpr int NEXT_PER_LANE = (NEW_V + U_UNITS + 63) / 64;
 };
 
-// XOR swizzle of 16-byte chunks inside 128-byte rows, keyed by the A row.
-template <int LS>
-__device__ __forceinline__ int swz(int t) {
-    return t ^ (((t >> LS) & 7) << 4);
+// ring position -> LDS byte (16 bytes of padding after every S bytes)
+template <int MB>
+__device__ __forceinline__ int vphys(int p) {
+    return p + 16 * (p >> MCfg<MB>::LS);
 }
 
 __device__ __forceinline__ uint4 load16_guarded(const int8_t* base, int64_t n, int64_t gi) {
@@ -66,7 +89,6 @@ __device__ __forceinline__ uint4 load16_guarded(const int8_t* base, int64_t n, i
     }
     uint32_t w[4] = {0u, 0u, 0u, 0u};
     if (gi + 16 > 0 && gi < n) {
-#pragma unroll
         for (int e = 0; e < 16; ++e) {
             int64_t idx = gi + e;
             uint32_t byte = (idx >= 0 && idx < n) ? (uint32_t)(uint8_t)base[idx] : 0u;
@@ -76,221 +98,449 @@ __device__ __forceinline__ uint4 load16_guarded(const int8_t* base, int64_t n, i
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// Per-wave staging. Chunk c of a wave covers m steps [qw + c CM, qw + (c+1) CM);
+// its v window starts at global v index qw + c CM + T0, at ring byte
+// (c CM) mod R. Only the wave itself touches its region.
 template <int MB>
-struct Stager {
+struct WaveStager {
     using C = MCfg<MB>;
-    uint4 reg[C::PER_THREAD];
+    uint4 reg[C::NEXT_PER_LANE];
 
-    __device__ __forceinline__ void load(const XPair& p, int64_t T0, int64_t qc) {
-        const int64_t gv0 = qc + T0;
-        const int64_t gu0 = qc - C::UOFF;
+    __device__ __forceinline__ void fill(const XPair& p, int64_t T0, int64_t qw, uint8_t* vb, uint8_t* ub,
+                                         int lane) {
+        const int64_t gv0 = qw + T0;
+        const int64_t gu0 = qw - C::UOFF;
+        uint4 x[C::FILL_PER_LANE];
 #pragma unroll
-        for (int k = 0; k < C::PER_THREAD; ++k) {
-            int unit = threadIdx.x + 256 * k;
-            if (unit < C::VUNITS) {
-                reg[k] = load16_guarded(p.v, p.nv, gv0 + 16 * (int64_t)unit);
-            } else if (unit < C::VUNITS + C::UUNITS) {
-                reg[k] = load16_guarded(p.u, p.nu, gu0 + 16 * (int64_t)(unit - C::VUNITS));
-            }
+        for (int k = 0; k < C::FILL_PER_LANE; ++k) {
+            const int unit = lane + 64 * k;
+            if (unit < C::FILL_V)
+                x[k] = load16_guarded(p.v, p.nv, gv0 + 16 * (int64_t)unit);
+            else if (unit < C::FILL_V + C::U_UNITS)
+                x[k] = load16_guarded(p.u, p.nu, gu0 + 16 * (int64_t)(unit - C::FILL_V));
+        }
+#pragma unroll
+        for (int k = 0; k < C::FILL_PER_LANE; ++k) {
+            const int unit = lane + 64 * k;
+            if (unit < C::FILL_V)
+                *reinterpret_cast<uint4*>(vb + vphys<MB>(16 * unit)) = x[k];
+            else if (unit < C::FILL_V + C::U_UNITS)
+                *reinterpret_cast<uint4*>(ub + 16 * (unit - C::FILL_V)) = x[k];
         }
     }
-    __device__ __forceinline__ void store(uint8_t* buf) {
+    __device__ __forceinline__ void load_next(const XPair& p, int64_t T0, int64_t qw, int c, int lane) {
+        const int64_t rel0 = (int64_t)(c - 1) * C::CM + C::VW;    // first new window byte
+        const int64_t gv0 = qw + T0 + rel0;
+        const int64_t gu0 = qw + (int64_t)c * C::CM - C::UOFF;
 #pragma unroll
-        for (int k = 0; k < C::PER_THREAD; ++k) {
-            int unit = threadIdx.x + 256 * k;
-            if (unit < C::VUNITS) {
-                *reinterpret_cast<uint4*>(buf + swz<C::LS>(16 * unit)) = reg[k];
-            } else if (unit < C::VUNITS + C::UUNITS) {
-                *reinterpret_cast<uint4*>(buf + C::VW + 16 * (unit - C::VUNITS)) = reg[k];
-            }
+        for (int k = 0; k < C::NEXT_PER_LANE; ++k) {
+            const int unit = lane + 64 * k;
+            if (unit < C::NEW_V)
+                reg[k] = load16_guarded(p.v, p.nv, gv0 + 16 * (int64_t)unit);
+            else if (unit < C::NEW_V + C::U_UNITS)
+                reg[k] = load16_guarded(p.u, p.nu, gu0 + 16 * (int64_t)(unit - C::NEW_V));
+        }
+    }
+    __device__ __forceinline__ void store_next(int c, uint8_t* vb, uint8_t* ub, int lane) {
+        const int rel0 = (int)(((int64_t)(c - 1) * C::CM + C::VW) & (C::R - 1));
+#pragma unroll
+        for (int k = 0; k < C::NEXT_PER_LANE; ++k) {
+            const int unit = lane + 64 * k;
+            if (unit < C::NEW_V)
+                *reinterpret_cast<uint4*>(vb + vphys<MB>((rel0 + 16 * unit) & (C::R - 1))) = reg[k];
+            else if (unit < C::NEW_V + C::U_UNITS)
+                *reinterpret_cast<uint4*>(ub + 16 * (unit - C::NEW_V)) = reg[k];
         }
     }
 };
 
-// 16 bytes of the staged u window starting at byte t (any alignment).
-__device__ __forceinline__ v4i read_b(const uint8_t* ub, int t) {
-    const uint32_t* d = reinterpret_cast<const uint32_t*>(ub) + (t >> 2);
-    const uint32_t sh = (uint32_t)(t & 3);
-    uint32_t d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
-    v4i r;
-    r[0] = (int)__builtin_amdgcn_alignbyte(d1, d0, sh);
-    r[1] = (int)__builtin_amdgcn_alignbyte(d2, d1, sh);
-    r[2] = (int)__builtin_amdgcn_alignbyte(d3, d2, sh);
-    r[3] = (int)__builtin_amdgcn_alignbyte(d4, d3, sh);
+// 16 bytes of the u window at a byte offset, read as 5 dwords (issued early)
+// and assembled with v_alignbyte (later).
+struct BRaw {
+    uint32_t d[5];
+};
+
+__device__ __forceinline__ BRaw read_b_raw(const uint32_t* dw) {
+    BRaw r;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) r.d[k] = dw[k];
     return r;
 }
 
-template <int MB>
-__device__ __forceinline__ v4i read_a(const uint8_t* vb, int t) {
-    uint4 x = *reinterpret_cast<const uint4*>(vb + swz<MCfg<MB>::LS>(t));
+__device__ __forceinline__ v4i assemble_b(const BRaw& r, uint32_t sh) {
+    v4i o;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = (int)__builtin_amdgcn_alignbyte(r.d[k + 1], r.d[k], sh);
+    return o;
+}
+
+__device__ __forceinline__ v4i read_a(const uint8_t* p) {
+    uint4 x = *reinterpret_cast<const uint4*>(p);
     v4i r;
     r[0] = (int)x.x; r[1] = (int)x.y; r[2] = (int)x.z; r[3] = (int)x.w;
     return r;
 }
 
+// (max, smallest index, count) over a run of lags.
+struct Tri64 {
+    int64_t v, i, c;
+};
+
+__device__ __forceinline__ Tri64 tri_join(Tri64 a, Tri64 b) {
+    if (b.v > a.v) return b;
+    if (a.v > b.v) return a;
+    return Tri64{a.v, a.i < b.i ? a.i : b.i, a.c + b.c};
+}
+
+// The m loop of one wave over [qw_a, qw_b) for the tile at T0.
 template <int MB>
-__global__ void __launch_bounds__(256, 2) k_xcorr_mfma(const XItem* items, XItem one) {
+__device__ __forceinline__ void wave_loop(const XPair& p, int64_t T0, int64_t qw_a, int64_t qw_b, uint8_t* wl,
+                                          int lane, v16i* acc) {
     using C = MCfg<MB>;
-    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-
-    const XItem& it = items ? items[blockIdx.z] : one;
-    const XPair& p = it.p;
-    const int64_t T_start = it.T_start;
-    const int64_t item_m = it.item_m;
-    const int64_t tile = blockIdx.y;
-    if (it.engine != TDE_PATH_MFMA || tile >= it.ntiles) return;
-    const int64_t T0 = T_start + tile * C::TL;
-    const int64_t T1 = T0 + C::TL - 1;
-    // m range where some lag of the tile has both u[m] and v[m + tau] in range
-    const int64_t m_lo = T1 < 0 ? -T1 : 0;
-    const int64_t m_hi = p.nu < p.nv - T0 ? p.nu : p.nv - T0;
-    if (m_hi <= m_lo) return;
-    const int64_t Q_lo = (m_lo / 32) * 32;
-    const int64_t Q_hi = Q_lo + round_up(m_hi + C::S - Q_lo, 32 * MB);
-    const int64_t qa = Q_lo + (int64_t)blockIdx.x * item_m;
-    if (qa >= Q_hi) return;
-    const int64_t qb = qa + item_m < Q_hi ? qa + item_m : Q_hi;
-
-    const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
     const int lc = lane & 31;
     const int g = lane >> 5;
+    uint8_t* vb = wl;
+    uint8_t* ubufs = wl + C::VPH;
+    WaveStager<MB> st;
+    const int nch = (int)((qw_b - qw_a + C::CM - 1) / C::CM);
+    st.fill(p, T0, qw_a, vb, ubufs, lane);
+
+    const int a_off = C::S * lc + 16 * g;             // A read offset at step 0
+    const int b_off = C::UOFF + 16 * g - lc;          // B_0 read offset at step 0 (> 0)
+    const uint32_t bsh = (uint32_t)(b_off & 3);
+
+    for (int c = 0; c < nch; ++c) {
+        if (c + 1 < nch) st.load_next(p, T0, qw_a, c + 1, lane);
+        const int base = (int)(((int64_t)c * C::CM) & (C::R - 1));
+        const uint32_t* ubw = reinterpret_cast<const uint32_t*>(ubufs + (c & 1) * C::UW) + (b_off >> 2);
+        const int64_t rem = (qw_b - qw_a - (int64_t)c * C::CM) / 32;
+        const int nsteps = rem < C::CQ ? (int)rem : C::CQ;
+
+        v4i breg[MB];
+#pragma unroll
+        for (int b = 1; b < MB; ++b) breg[MB - b] = assemble_b(read_b_raw(ubw - 8 * b), bsh);
+        // Software pipeline: fragments of step s+1 are read while the matrix
+        // instructions of step s run; reading one step past the chunk stays
+        // inside the staged windows. Inside a group of MB steps the A rows
+        // stay in one padded S-byte block (the ring end is S-aligned), so
+        // their LDS offsets are constants.
+        int p0 = (base + a_off) & (C::R - 1);
+        const uint8_t* arow = vb + vphys<MB>(p0);
+        v4i a_cur = read_a(arow);
+        v4i b_cur = assemble_b(read_b_raw(ubw), bsh);
+        for (int s0 = 0; s0 < nsteps; s0 += MB) {
+            const int pn = (p0 + C::S) & (C::R - 1);
+            const uint8_t* arow_next = vb + vphys<MB>(pn);
+#pragma unroll
+            for (int t = 0; t < MB; ++t) {
+                const int s = s0 + t;
+                const v4i a_nxt = read_a(t + 1 < MB ? arow + 32 * (t + 1) : arow_next);
+                const BRaw b_raw = read_b_raw(ubw + 8 * (s + 1));
+                __builtin_amdgcn_sched_barrier(0);
+                breg[t] = b_cur;
+#pragma unroll
+                for (int b = 0; b < MB; ++b)
+                    acc[b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_cur, breg[(t - b + MB) % MB], acc[b], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                a_cur = a_nxt;
+                b_cur = assemble_b(b_raw, bsh);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            p0 = pn;
+            arow = arow_next;
+        }
+        // the wave's own region: its LDS operations complete in order
+        if (c + 1 < nch) st.store_next(c + 1, vb, ubufs + ((c + 1) & 1) * C::UW, lane);
+    }
+}
+
+template <int MB>
+__device__ __forceinline__ void mfma_item(const XItem& it, const MWork& wk, uint8_t* lds, ArgPart* tile_parts) {
+    using C = MCfg<MB>;
+    const XPair& p = it.p;
+    const int64_t T0 = it.T_start + (int64_t)wk.tile * C::TLW;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+
+    // quarter of the m range of this item for this wave
+    const int64_t part = round_up(ceil_div(wk.qb - wk.qa, 4), 32 * MB);
+    const int64_t qw_a = wk.qa + (int64_t)w * part;
+    const int64_t qw_b = qw_a + part < wk.qb ? qw_a + part : wk.qb;
 
     v16i acc[MB];
 #pragma unroll
     for (int b = 0; b < MB; ++b)
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[b][e] = 0;
+    if (qw_a < qw_b) wave_loop<MB>(p, T0, qw_a, qw_b, lds + w * C::WAVE_LDS, lane, acc);
 
-    Stager<MB> st;
-    const int nch = (int)((qb - qa + C::CM - 1) / C::CM);
-    st.load(p, T0, qa);
-    st.store(lds);
+    // ---- the four partial sums meet in LDS (index = lag - T0)
+    __syncthreads();
+    const bool wide = it.wide != 0;
+    if (wide) {
+        unsigned long long* red = reinterpret_cast<unsigned long long*>(lds);
+        for (int k = threadIdx.x; k < C::TLW; k += 256) red[k] = 0ull;
+    } else {
+        uint32_t* red = reinterpret_cast<uint32_t*>(lds);
+        for (int k = threadIdx.x; k < C::TLW; k += 256) red[k] = 0u;
+    }
+    __syncthreads();
+    {
+        const int lc = lane & 31, g = lane >> 5;
+#pragma unroll
+        for (int b = 0; b < MB; ++b) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                // accumulator layout: lane (j = lc, g), register e -> row 8(e/4) + 4g + e%4
+                const int i = 8 * (e >> 2) + 4 * g + (e & 3);
+                const int idx = lc + 32 * b + C::S * i;
+                const int val = acc[b][e];
+                if (val != 0) {
+                    if (wide)
+                        atomicAdd(reinterpret_cast<unsigned long long*>(lds) + idx,
+                                  (unsigned long long)(long long)val);
+                    else
+                        atomicAdd(reinterpret_cast<unsigned int*>(lds) + idx, (unsigned int)val);
+                }
+            }
+        }
+    }
     __syncthreads();
 
-    const int a_off = w * C::TLW + C::S * lc + 16 * g;   // A read offset at step 0
-    const int b_off = C::UOFF + 16 * g - lc;             // B_0 read offset at step 0
-
-    for (int c = 0; c < nch; ++c) {
-        const int64_t qc = qa + (int64_t)c * C::CM;
-        if (c + 1 < nch) st.load(p, T0, qc + C::CM);
-        const uint8_t* vb = lds + (c & 1) * C::BUF;
-        const uint8_t* ub = vb + C::VW;
-        const int64_t rem = (qb - qc) / 32;
-        const int nsteps = rem < C::CQ ? (int)rem : C::CQ;
-
-        v4i breg[MB];
-#pragma unroll
-        for (int b = 1; b < MB; ++b) breg[MB - b] = read_b(ub, b_off - 32 * b);
-
-        for (int s0 = 0; s0 < nsteps; s0 += MB) {
-#pragma unroll
-            for (int t = 0; t < MB; ++t) {
-                const int s = s0 + t;
-                v4i a = read_a<MB>(vb, a_off + 32 * s);
-                breg[t] = read_b(ub, b_off + 32 * s);
-#pragma unroll
-                for (int b = 0; b < MB; ++b)
-                    acc[b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, breg[(t - b + MB) % MB], acc[b], 0, 0, 0);
+    // ---- outputs: r (plain stores or, for segments, atomics) and the triple
+    const int64_t L = p.lag_hi - p.lag_lo + 1;
+    Tri64 t{INT64_MIN, INT64_MAX, 0};
+    for (int k = threadIdx.x; k < C::TLW; k += 256) {
+        const int64_t tau = T0 + k;
+        const int64_t idx = tau - p.lag_lo;
+        if (idx < 0 || idx >= L) continue;
+        const int64_t val = wide ? (int64_t)reinterpret_cast<const unsigned long long*>(lds)[k]
+                                 : (int64_t)(int32_t)reinterpret_cast<const uint32_t*>(lds)[k];
+        if (p.r) {
+            if (wk.segmented) {
+                if (val != 0) {
+                    if (p.r_dtype == TDE_I32)
+                        atomicAdd(static_cast<int*>(p.r) + idx, (int)val);
+                    else
+                        atomicAdd(static_cast<unsigned long long*>(p.r) + idx, (unsigned long long)val);
+                }
+            } else if (p.r_dtype == TDE_I32) {
+                static_cast<int32_t*>(p.r)[idx] = (int32_t)val;
+            } else {
+                static_cast<int64_t*>(p.r)[idx] = val;
             }
         }
-        if (c + 1 < nch) st.store(lds + ((c + 1) & 1) * C::BUF);
+        t = tri_join(t, Tri64{val, idx, 1});
+    }
+    if (tile_parts && !wk.segmented) {
+        // workgroup reduction of the triple
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            Tri64 u{__shfl_xor(t.v, o, 64), __shfl_xor(t.i, o, 64), __shfl_xor(t.c, o, 64)};
+            t = tri_join(t, u);
+        }
+        __shared__ Tri64 sh[4];
+        if (lane == 0) sh[w] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            Tri64 a = tri_join(tri_join(sh[0], sh[1]), tri_join(sh[2], sh[3]));
+            tile_parts[it.part_base + wk.tile] = ArgPart{a.v, a.i, a.c};
+        }
+    }
+}
+
+// Persistent: each workgroup takes items until the list is exhausted; every
+// wave of the grid reaches the exit once the counter passes nwork.
+template <int MB>
+__global__ void __launch_bounds__(256, 2) k_xcorr_mfma(const XItem* items, XItem one, const MWork* work,
+                                                       int nwork, int* counter, ArgPart* tile_parts) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int wi = s_item;
+        __syncthreads();
+        if (wi >= nwork) break;
+        const MWork wk = work[wi];
+        const XItem& it = items ? items[wk.pair] : one;
+        mfma_item<MB>(it, wk, lds, tile_parts);
         __syncthreads();
     }
+}
 
-    // accumulator layout: lane (j = lc, g), register e -> row i = 8(e/4) + 4g + e%4
-    const int64_t Tw = T0 + (int64_t)w * C::TLW;
-    const int64_t L = p.lag_hi - p.lag_lo + 1;
+__global__ void k_zero_counters(int* c, int n) {
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
+}
+
+// Per pair: join the tile triples with the triple of the lags no tile covers
+// (their correlation is 0) and write the peak.
+__global__ void __launch_bounds__(64) k_tiles_final(const XItem* items, XItem one, int npairs,
+                                                    const ArgPart* tile_parts) {
+    const int pi = blockIdx.x;
+    const XItem& it = items ? items[pi] : one;
+    if (!it.fused) return;
+    Tri64 t{it.out_v, it.out_i, it.out_c};
+    for (int64_t k = threadIdx.x; k < it.ntiles; k += 64) {
+        ArgPart a = tile_parts[it.part_base + k];
+        t = tri_join(t, Tri64{a.vmax, a.idx, a.cnt});
+    }
 #pragma unroll
-    for (int b = 0; b < MB; ++b) {
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int i = 8 * (e >> 2) + 4 * g + (e & 3);
-            const int64_t tau = Tw + lc + 32 * b + (int64_t)C::S * i;
-            const int64_t idx = tau - p.lag_lo;
-            const int val = acc[b][e];
-            if (idx >= 0 && idx < L && val != 0) {
-                if (p.r_dtype == TDE_I32)
-                    atomicAdd(static_cast<int*>(p.r) + idx, val);
-                else
-                    atomicAdd(static_cast<unsigned long long*>(p.r) + idx, (unsigned long long)(long long)val);
-            }
-        }
+    for (int o = 32; o > 0; o >>= 1) {
+        Tri64 u{__shfl_xor(t.v, o, 64), __shfl_xor(t.i, o, 64), __shfl_xor(t.c, o, 64)};
+        t = tri_join(t, u);
+    }
+    if (threadIdx.x == 0) {
+        int flags = 0;
+        if (it.stat_x) flags |= it.stat_x->flags & (TDE_FLAG_NONFINITE_X | TDE_FLAG_ZERO_X);
+        if (it.stat_y) flags |= (it.stat_y->flags & (TDE_FLAG_NONFINITE_X | TDE_FLAG_ZERO_X)) << 1;
+        tde_peak pk;
+        pk.lag = it.p.lag_lo + t.i;
+        pk.rmax = t.v;
+        pk.n_ties = (int32_t)t.c;
+        pk.flags = flags;
+        *it.peak = pk;
     }
 }
 
 // ----------------------------------------------------------------- host --
 
-namespace {
-constexpr int kMB = 4;
+static void clamp_support(const XPair& p, int64_t& lo, int64_t& hi) {
+    lo = p.lag_lo > -(p.nu - 1) ? p.lag_lo : -(p.nu - 1);
+    hi = p.lag_hi < p.nv - 1 ? p.lag_hi : p.nv - 1;
 }
 
-// Sum over the lag tiles of a pair of the m range each tile walks.
-int64_t mfma_total_q(const XPair& p) {
-    using C = MCfg<kMB>;
-    int64_t lo = p.lag_lo > -(p.nu - 1) ? p.lag_lo : -(p.nu - 1);
-    int64_t hi = p.lag_hi < p.nv - 1 ? p.lag_hi : p.nv - 1;
-    if (lo > hi) return 0;
-    int64_t T_start = floor_div(lo, 16) * 16;
-    int64_t ntiles = ceil_div(hi - T_start + 1, C::TL);
+// m range [Q_lo, Q_lo + len) of the tile starting at T0 (len a multiple of
+// 4 waves x 4 steps x 32).
+static void tile_range(const XPair& p, int64_t T0, int64_t& Q_lo, int64_t& len) {
+    using C = MCfg<4>;
+    const int64_t T1 = T0 + C::TLW - 1;
+    const int64_t m_lo = T1 < 0 ? -T1 : 0;
+    const int64_t m_hi = p.nu < p.nv - T0 ? p.nu : p.nv - T0;
+    if (m_hi <= m_lo) {
+        Q_lo = 0;
+        len = 0;
+        return;
+    }
+    Q_lo = (m_lo / 32) * 32;
+    len = round_up(m_hi + C::S - Q_lo, 4 * 32 * 4);
+}
+
+// Longest m range one item may cover: each wave's quarter stays int32-safe.
+static int64_t seg_cap(const XPair& p) {
+    const int64_t per_wave = ((int64_t)0x7fffffff / p.kuv) / 128 * 128;
+    return 4 * per_wave;
+}
+
+void mfma_plan_pair(XItem& it) {
+    using C = MCfg<4>;
+    it.mb = 4;
+    int64_t lo, hi;
+    clamp_support(it.p, lo, hi);
+    it.ntiles = 0;
+    it.T_start = 0;
+    it.segmented = 0;
+    it.wide = 0;
+    if (lo <= hi) {
+        it.T_start = floor_div(lo, 16) * 16;
+        it.ntiles = ceil_div(hi - it.T_start + 1, C::TLW);
+    }
+    int64_t maxlen = 0;
+    for (int64_t t = 0; t < it.ntiles; ++t) {
+        int64_t Q_lo, len;
+        tile_range(it.p, it.T_start + t * C::TLW, Q_lo, len);
+        if (len > maxlen) maxlen = len;
+    }
+    if (maxlen > seg_cap(it.p)) it.segmented = 1;
+    // a tile sum can exceed int32 only if its m range times Ku Kv does
+    if ((__int128)maxlen * it.p.kuv >= ((__int128)1 << 31)) it.wide = 1;
+    // lags of [lag_lo, lag_hi] outside every tile: r = 0 there
+    const int64_t L = it.p.lag_hi - it.p.lag_lo + 1;
+    int64_t c_lo = it.T_start, c_hi = it.T_start + it.ntiles * C::TLW - 1;   // covered lags
+    if (it.ntiles == 0) {
+        c_lo = 1;
+        c_hi = 0;
+    }
+    c_lo = c_lo > it.p.lag_lo ? c_lo : it.p.lag_lo;
+    c_hi = c_hi < it.p.lag_hi ? c_hi : it.p.lag_hi;
+    const int64_t covered = c_hi >= c_lo ? c_hi - c_lo + 1 : 0;
+    it.out_c = L - covered;
+    if (it.out_c == 0) {
+        it.out_v = INT64_MIN;
+        it.out_i = INT64_MAX;
+    } else {
+        it.out_v = 0;
+        it.out_i = (covered == 0 || c_lo > it.p.lag_lo) ? 0 : (c_hi + 1 - it.p.lag_lo);
+    }
+}
+
+int64_t mfma_total_q(const XItem& it) {
     int64_t tot = 0;
-    for (int64_t t = 0; t < ntiles; ++t) {
-        int64_t T0 = T_start + t * C::TL, T1 = T0 + C::TL - 1;
-        int64_t m_lo = T1 < 0 ? -T1 : 0;
-        int64_t m_hi = p.nu < p.nv - T0 ? p.nu : p.nv - T0;
-        if (m_hi <= m_lo) continue;
-        int64_t Q_lo = (m_lo / 32) * 32;
-        tot += round_up(m_hi + C::S - Q_lo, 32 * kMB);
+    for (int64_t t = 0; t < it.ntiles; ++t) {
+        int64_t Q_lo, len;
+        tile_range(it.p, it.T_start + t * MCfg<4>::TLW, Q_lo, len);
+        tot += len;
     }
     return tot;
 }
 
-// Tiles of the lag range and the split of each tile's m loop. total_q_hint is
-// the summed m range of every pair launched together (to size the split).
-void mfma_plan(XItem& it, int64_t total_q_hint) {
-    using C = MCfg<kMB>;
-    const XPair& p = it.p;
-    int64_t lo = p.lag_lo > -(p.nu - 1) ? p.lag_lo : -(p.nu - 1);
-    int64_t hi = p.lag_hi < p.nv - 1 ? p.lag_hi : p.nv - 1;
-    it.ntiles = 0;
-    it.nsplit = 0;
-    it.item_m = C::CM;
-    it.T_start = 0;
-    if (lo > hi) return;
-    it.T_start = floor_div(lo, 16) * 16;
-    it.ntiles = ceil_div(hi - it.T_start + 1, C::TL);
-    int64_t maxq = 0;
+int64_t mfma_count_items(const XItem& it) {
+    const int64_t cap = seg_cap(it.p);
+    int64_t n = 0;
     for (int64_t t = 0; t < it.ntiles; ++t) {
-        int64_t T0 = it.T_start + t * C::TL, T1 = T0 + C::TL - 1;
-        int64_t m_lo = T1 < 0 ? -T1 : 0;
-        int64_t m_hi = p.nu < p.nv - T0 ? p.nu : p.nv - T0;
-        if (m_hi <= m_lo) continue;
-        int64_t Q_lo = (m_lo / 32) * 32;
-        int64_t len = round_up(m_hi + C::S - Q_lo, 32 * kMB);
-        if (len > maxq) maxq = len;
+        int64_t Q_lo, len;
+        tile_range(it.p, it.T_start + t * MCfg<4>::TLW, Q_lo, len);
+        n += len == 0 ? 1 : ceil_div(len, cap);
     }
-    // int32 partials: item_m * Ku * Kv < 2^31 (kuv <= 127*127 keeps this >= 131072)
-    int64_t cap = ((int64_t)0x7fffffff / p.kuv) / C::CM * C::CM;
-    if (cap < C::CM) cap = C::CM;
-    // aim for ~2048 work items over the whole launch (256 CUs x 2 groups, 4 deep)
-    int64_t want = round_up(ceil_div(total_q_hint, 2048), C::CM);
-    if (want < C::CM) want = C::CM;
-    it.item_m = want < cap ? want : cap;
-    it.nsplit = ceil_div(maxq, it.item_m);
+    return n;
 }
 
-int launch_xcorr_mfma(const XItem* items_dev, const XItem& one, int nitems, int64_t max_split,
-                      int64_t max_tiles, hipStream_t s) {
-    using C = MCfg<kMB>;
-    if (max_split == 0 || max_tiles == 0) return TDE_OK;
-    static bool attr_set = false;
-    if (!attr_set) {
-        TDE_HIP_CHECK(hipFuncSetAttribute((const void*)k_xcorr_mfma<kMB>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS));
-        attr_set = true;
+void mfma_items(const XItem& it, int pair, std::vector<MWork>& out) {
+    const int64_t cap = seg_cap(it.p);
+    for (int64_t t = 0; t < it.ntiles; ++t) {
+        int64_t Q_lo, len;
+        tile_range(it.p, it.T_start + t * MCfg<4>::TLW, Q_lo, len);
+        if (len == 0) {
+            // no overlap anywhere in the tile: an empty item writes its zeros
+            out.push_back(MWork{pair, (int32_t)t, 0, 0, it.segmented, 0});
+            continue;
+        }
+        for (int64_t o = 0; o < len; o += cap)
+            out.push_back(MWork{pair, (int32_t)t, Q_lo + o, Q_lo + (o + cap < len ? o + cap : len), it.segmented, 0});
     }
-    hipLaunchKernelGGL(k_xcorr_mfma<kMB>, dim3((unsigned)max_split, (unsigned)max_tiles, (unsigned)nitems),
-                       dim3(256), C::LDS, s, items_dev, one);
+}
+
+void mfma_sort_items(std::vector<MWork>& w) {
+    std::stable_sort(w.begin(), w.end(), [](const MWork& a, const MWork& b) {
+        return (a.qb - a.qa) > (b.qb - b.qa);
+    });
+}
+
+int launch_xcorr_mfma(const XItem* items_dev, const XItem& one, const MWork* work_dev, int nwork,
+                      int* counters_dev, ArgPart* tile_parts, int num_cu, hipStream_t s) {
+    using C = MCfg<4>;
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, counters_dev, 2);
+    TDE_HIP_CHECK(hipGetLastError());
+    if (nwork == 0) return TDE_OK;
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        TDE_HIP_CHECK(hipFuncSetAttribute((const void*)k_xcorr_mfma<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          C::LDS));
+        int nb = 0;
+        TDE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_xcorr_mfma<4>, 256, C::LDS));
+        per_cu = nb > 0 ? nb : 1;
+    }
+    int grid = per_cu * num_cu;
+    if (grid > nwork) grid = nwork;
+    hipLaunchKernelGGL(k_xcorr_mfma<4>, dim3(grid), dim3(256), C::LDS, s, items_dev, one, work_dev, nwork,
+                       counters_dev, tile_parts);
+    TDE_HIP_CHECK(hipGetLastError());
+    return TDE_OK;
+}
+
+int launch_tiles_final(const XItem* items_dev, const XItem& one, int npairs, const ArgPart* tile_parts,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_tiles_final, dim3(npairs), dim3(64), 0, s, items_dev, one, npairs, tile_parts);
     TDE_HIP_CHECK(hipGetLastError());
     return TDE_OK;
 }

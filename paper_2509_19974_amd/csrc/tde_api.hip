@@ -252,7 +252,7 @@ int tde_quantize(tde_ctx* ctx, const float* x, int64_t n, int bits, float inv_st
     }
     DeviceGuard g(ctx->device);
     if (!g.ok) return set_error(TDE_ERR_HIP, "tde_quantize: hipSetDevice failed");
-    return launch_quantize(nullptr, one, 1, ceil_div(n, 256), ceil_div(n, 1024), need_scale,
+    return launch_quantize(nullptr, one, 1, ceil_div(n, 256), ceil_div(n, kQuantBlock), need_scale,
                            static_cast<hipStream_t>(stream));
 }
 
@@ -284,16 +284,17 @@ static int check_xcorr(const int8_t* u, int64_t nu, const int8_t* v, int64_t nv,
 
 size_t tde_xcorr_workspace_size(int64_t nu, int64_t nv, int kmax_u, int kmax_v, int64_t lag_lo, int64_t lag_hi,
                                 int path) {
-    if (nu < 1 || nv < 1 || lag_lo > lag_hi) return 0;
-    XPair p{};
-    p.nu = nu;
-    p.nv = nv;
-    p.lag_lo = lag_lo;
-    p.lag_hi = lag_hi;
-    p.kuv = kmax_u * kmax_v;
-    int eng = choose_path(path, p.kuv);
-    if (eng == TDE_PATH_POPC) return popc_ws_bytes(p);
-    return 0;
+    if (nu < 1 || nv < 1 || lag_lo > lag_hi || kmax_u < 1 || kmax_v < 1) return 0;
+    XItem it{};
+    it.p.nu = nu;
+    it.p.nv = nv;
+    it.p.lag_lo = lag_lo;
+    it.p.lag_hi = lag_hi;
+    it.p.kuv = kmax_u * kmax_v;
+    int eng = choose_path(path, it.p.kuv);
+    if (eng == TDE_PATH_POPC) return popc_ws_bytes(it.p);
+    mfma_plan_pair(it);
+    return align_bytes((size_t)mfma_count_items(it) * sizeof(MWork)) + align_bytes(2 * sizeof(int));
 }
 
 int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, int64_t nv, int kmax_u, int kmax_v,
@@ -331,8 +332,19 @@ int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, in
         if (rc) return rc;
         return launch_xcorr_popc(nullptr, it, 1, it.nsplit, it.ntiles, s);
     }
-    mfma_plan(it, mfma_total_q(it.p));
-    return launch_xcorr_mfma(nullptr, it, 1, it.nsplit, it.ntiles, s);
+    mfma_plan_pair(it);
+    std::vector<MWork> work;
+    mfma_items(it, 0, work);
+    mfma_sort_items(work);
+    MWork* work_dev = static_cast<MWork*>(ws);
+    int* counters = reinterpret_cast<int*>(static_cast<uint8_t*>(ws) +
+                                           align_bytes((size_t)mfma_count_items(it) * sizeof(MWork)));
+    {
+        std::lock_guard<std::mutex> lock(ctx->mu);
+        rc = upload(ctx, work_dev, work.data(), work.size() * sizeof(MWork), s);
+    }
+    if (rc) return rc;
+    return launch_xcorr_mfma(nullptr, it, work_dev, (int)work.size(), counters, nullptr, ctx->num_cu, s);
 }
 
 // -------------------------------------------------------------- argmax --
@@ -370,19 +382,6 @@ int tde_argmax_lag(tde_ctx* ctx, const void* r, int r_dtype, int64_t lag_lo, int
 
 namespace {
 
-struct BatchPlan {
-    size_t total = 0;
-    // offsets inside the workspace
-    size_t off_qsig, off_items, off_segs, off_stats, off_inv, off_parts;
-    std::vector<size_t> off_q;      // per signal (2 per pair)
-    std::vector<size_t> off_gsum;   // per signal
-    std::vector<size_t> off_r;      // per pair (when r_out is NULL)
-    std::vector<size_t> off_planes; // per pair (bit-plane engine)
-    std::vector<int> rdt;           // r dtype per pair
-    std::vector<int> eng;           // engine per pair
-    int64_t total_parts = 0;
-};
-
 int validate_pairs(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
     if (!pairs || np < 1) return set_error(TDE_ERR_ARG, "tde_estimate_batch: no pairs");
     if (np > 65535) return set_error(TDE_ERR_ARG, "tde_estimate_batch: at most 65535 pairs per call");
@@ -417,6 +416,49 @@ int validate_pairs(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
     return TDE_OK;
 }
 
+// Per-pair decisions shared by the workspace size and the launch.
+struct PairPlan {
+    int eng;            // engine
+    int rdt;            // r dtype
+    bool fused;         // argmax from tile triples, no r array
+    bool need_r;        // r materialized (requested or needed by the argmax kernel)
+    XItem probe;        // MFMA plan of the pair (sizes only)
+};
+
+PairPlan plan_pair(const tde_pair& q, int path) {
+    PairPlan pp{};
+    const int K = kmax_of_bits(q.bits);
+    pp.eng = choose_path(path, K * K);
+    pp.rdt = q.r_out ? q.r_dtype
+                     : ((__int128)max_overlap(q.nx, q.ny, q.lag_lo, q.lag_hi) * K * K < ((__int128)1 << 31) ? TDE_I32
+                                                                                                          : TDE_I64);
+    pp.probe.p.nu = q.nx;
+    pp.probe.p.nv = q.ny;
+    pp.probe.p.lag_lo = q.lag_lo;
+    pp.probe.p.lag_hi = q.lag_hi;
+    pp.probe.p.kuv = K * K;
+    if (pp.eng == TDE_PATH_MFMA) {
+        mfma_plan_pair(pp.probe);
+        pp.fused = !pp.probe.segmented;
+    } else {
+        pp.fused = false;
+    }
+    pp.need_r = q.r_out != nullptr || !pp.fused;
+    return pp;
+}
+
+struct BatchPlan {
+    size_t total = 0;
+    // offsets inside the workspace; [0, off_stats) is uploaded from the host
+    size_t off_qsig, off_items, off_segs, off_work, off_counters, off_tparts, off_stats, off_inv, off_parts;
+    int64_t nwork = 0, ntparts = 0, nsegs = 0, total_parts = 0;
+    std::vector<PairPlan> pp;
+    std::vector<size_t> off_q;      // per signal (2 per pair)
+    std::vector<size_t> off_gsum;   // per signal
+    std::vector<size_t> off_r;      // per pair (r materialized in the workspace)
+    std::vector<size_t> off_planes; // per pair (bit-plane engine)
+};
+
 BatchPlan plan_batch(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
     BatchPlan B;
     size_t off = 0;
@@ -426,44 +468,43 @@ BatchPlan plan_batch(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
         return o;
     };
     const int path = opts ? opts->path : TDE_PATH_AUTO;
+    B.pp.resize(np);
+    for (int64_t i = 0; i < np; ++i) {
+        B.pp[i] = plan_pair(pairs[i], path);
+        const PairPlan& pp = B.pp[i];
+        if (pp.eng == TDE_PATH_MFMA) {
+            B.nwork += mfma_count_items(pp.probe);
+            if (pp.fused) B.ntparts += pp.probe.ntiles;
+        }
+        if (!pp.fused) {
+            B.nsegs += 1;
+            B.total_parts += ceil_div(pairs[i].lag_hi - pairs[i].lag_lo + 1, kArgChunk);
+        }
+    }
     B.off_qsig = take(sizeof(QSig) * 2 * np);
     B.off_items = take(sizeof(XItem) * np);
-    B.off_segs = take(sizeof(ArgSeg) * np);
+    B.off_segs = take(sizeof(ArgSeg) * (B.nsegs ? B.nsegs : 1));
+    B.off_work = take(sizeof(MWork) * (B.nwork ? B.nwork : 1));
+    B.off_counters = take(2 * sizeof(int));
+    B.off_tparts = take(sizeof(ArgPart) * (B.ntparts ? B.ntparts : 1));
     B.off_stats = take(sizeof(tde_qstat) * 2 * np);
     B.off_inv = take(sizeof(float) * 2 * np);
+    B.off_parts = take(sizeof(ArgPart) * (B.total_parts ? B.total_parts : 1));
     B.off_q.resize(2 * np);
     B.off_gsum.resize(2 * np);
-    B.off_r.resize(np);
-    B.off_planes.resize(np);
-    B.rdt.resize(np);
-    B.eng.resize(np);
+    B.off_r.assign(np, 0);
+    B.off_planes.assign(np, 0);
     for (int64_t i = 0; i < np; ++i) {
         const tde_pair& q = pairs[i];
+        const PairPlan& pp = B.pp[i];
         B.off_q[2 * i] = take(q.nx);
         B.off_q[2 * i + 1] = take(q.ny);
         B.off_gsum[2 * i] = take((size_t)quantize_gsum_doubles(q.nx) * 8);
         B.off_gsum[2 * i + 1] = take((size_t)quantize_gsum_doubles(q.ny) * 8);
-        const int K = kmax_of_bits(q.bits);
-        int dt = q.r_out ? q.r_dtype
-                         : ((__int128)max_overlap(q.nx, q.ny, q.lag_lo, q.lag_hi) * K * K < ((__int128)1 << 31)
-                                ? TDE_I32
-                                : TDE_I64);
-        B.rdt[i] = dt;
         const int64_t L = q.lag_hi - q.lag_lo + 1;
-        B.off_r[i] = q.r_out ? 0 : take((size_t)L * (dt == TDE_I32 ? 4 : 8));
-        int eng = choose_path(path, K * K);
-        B.eng[i] = eng;
-        if (eng == TDE_PATH_POPC) {
-            XPair p{};
-            p.nu = q.nx;
-            p.nv = q.ny;
-            p.lag_lo = q.lag_lo;
-            p.lag_hi = q.lag_hi;
-            B.off_planes[i] = take(popc_ws_bytes(p));
-        }
-        B.total_parts += ceil_div(L, kArgChunk);
+        if (pp.need_r && !q.r_out) B.off_r[i] = take((size_t)L * (pp.rdt == TDE_I32 ? 4 : 8));
+        if (pp.eng == TDE_PATH_POPC) B.off_planes[i] = take(popc_ws_bytes(pp.probe.p));
     }
-    B.off_parts = take(sizeof(ArgPart) * B.total_parts);
     B.total = off;
     return B;
 }
@@ -496,14 +537,17 @@ int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs, int64_t np, const td
     // ---- descriptors (host side)
     std::vector<QSig> sigs(2 * np);
     std::vector<XItem> items(np);
-    std::vector<ArgSeg> segs(np);
-    int64_t gbase = 0, bbase = 0, pbase = 0;
-    int64_t total_q = 0;
+    std::vector<ArgSeg> segs;
+    std::vector<MWork> work;
+    int64_t gbase = 0, bbase = 0, pbase = 0, tbase = 0;
     tde_qstat* stats = reinterpret_cast<tde_qstat*>(W + B.off_stats);
     float* invs = reinterpret_cast<float*>(W + B.off_inv);
-    bool need_scale = false;
+    ArgPart* tparts = reinterpret_cast<ArgPart*>(W + B.off_tparts);
+    bool need_scale = false, any_popc = false, any_mfma = false, any_fused = false, any_r = false;
+    int64_t max_rbytes = 0, p_split = 0, p_tiles = 0, p_words = 0;
     for (int64_t i = 0; i < np; ++i) {
         const tde_pair& q = pairs[i];
+        const PairPlan& pp = B.pp[i];
         for (int side = 0; side < 2; ++side) {
             QSig& S = sigs[2 * i + side];
             S.x = side ? q.y : q.x;
@@ -519,58 +563,61 @@ int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs, int64_t np, const td
             S.bits = q.bits;
             if (q.bits != 1 && !(fixed > 0.f)) need_scale = true;
             gbase += ceil_div(S.n, 256);
-            bbase += ceil_div(S.n, 1024);
+            bbase += ceil_div(S.n, kQuantBlock);
         }
         XItem& it = items[i];
-        it.engine = B.eng[i];
+        it = pp.probe;                     // plan (tiles, flags, outside triple)
+        it.engine = pp.eng;
         it.p.u = sigs[2 * i].q;
         it.p.v = sigs[2 * i + 1].q;
-        it.p.nu = q.nx;
-        it.p.nv = q.ny;
-        it.p.lag_lo = q.lag_lo;
-        it.p.lag_hi = q.lag_hi;
-        it.p.r = q.r_out ? q.r_out : (void*)(W + B.off_r[i]);
-        it.p.r_dtype = B.rdt[i];
-        const int K = kmax_of_bits(q.bits);
-        it.p.kuv = K * K;
-        if (B.eng[i] == TDE_PATH_MFMA) total_q += mfma_total_q(it.p);
-        ArgSeg& sg = segs[i];
-        sg.r = it.p.r;
-        sg.L = q.lag_hi - q.lag_lo + 1;
-        sg.lag_lo = q.lag_lo;
-        sg.part_base = pbase;
-        sg.nparts = (int32_t)ceil_div(sg.L, kArgChunk);
-        sg.dtype = B.rdt[i];
-        sg.out = out + i;
-        sg.stat_x = stats + 2 * i;
-        sg.stat_y = stats + 2 * i + 1;
-        pbase += sg.nparts;
-    }
-    int64_t max_split = 0, max_tiles = 0, max_rbytes = 0;
-    int64_t p_split = 0, p_tiles = 0, p_words = 0;
-    bool any_popc = false, any_mfma = false;
-    for (int64_t i = 0; i < np; ++i) {
-        XItem& it = items[i];
-        max_rbytes = std::max<int64_t>(max_rbytes, (it.p.lag_hi - it.p.lag_lo + 1) * (it.p.r_dtype == TDE_I32 ? 4 : 8));
-        if (B.eng[i] == TDE_PATH_POPC) {
+        it.p.r = pp.need_r ? (q.r_out ? q.r_out : (void*)(W + B.off_r[i])) : nullptr;
+        it.p.r_dtype = pp.rdt;
+        it.stat_x = stats + 2 * i;
+        it.stat_y = stats + 2 * i + 1;
+        it.peak = out + i;
+        it.fused = pp.fused ? 1 : 0;
+        if (it.p.r) {
+            any_r = true;
+            max_rbytes = std::max<int64_t>(max_rbytes, (q.lag_hi - q.lag_lo + 1) * (pp.rdt == TDE_I32 ? 4 : 8));
+        }
+        if (pp.eng == TDE_PATH_MFMA) {
+            any_mfma = true;
+            if (pp.fused) {
+                it.part_base = tbase;
+                tbase += it.ntiles;
+                any_fused = true;
+            }
+            mfma_items(it, (int)i, work);
+        } else {
             popc_plan(it, W + B.off_planes[i]);
             p_split = std::max(p_split, it.nsplit);
             p_tiles = std::max(p_tiles, it.ntiles);
             p_words = std::max(p_words, std::max(it.nuw, it.nvw));
             any_popc = true;
-        } else {
-            mfma_plan(it, total_q);
-            max_split = std::max(max_split, it.nsplit);
-            max_tiles = std::max(max_tiles, it.ntiles);
-            any_mfma = true;
+        }
+        if (!pp.fused) {
+            ArgSeg sg{};
+            sg.r = it.p.r;
+            sg.L = q.lag_hi - q.lag_lo + 1;
+            sg.lag_lo = q.lag_lo;
+            sg.part_base = pbase;
+            sg.nparts = (int32_t)ceil_div(sg.L, kArgChunk);
+            sg.dtype = pp.rdt;
+            sg.out = out + i;
+            sg.stat_x = it.stat_x;
+            sg.stat_y = it.stat_y;
+            pbase += sg.nparts;
+            segs.push_back(sg);
         }
     }
+    mfma_sort_items(work);
 
     // ---- upload descriptors (one copy) and queue the kernels
-    std::vector<uint8_t> blob(B.off_stats);
+    std::vector<uint8_t> blob(B.off_work + work.size() * sizeof(MWork));
     memcpy(blob.data() + B.off_qsig, sigs.data(), sizeof(QSig) * 2 * np);
     memcpy(blob.data() + B.off_items, items.data(), sizeof(XItem) * np);
-    memcpy(blob.data() + B.off_segs, segs.data(), sizeof(ArgSeg) * np);
+    if (!segs.empty()) memcpy(blob.data() + B.off_segs, segs.data(), sizeof(ArgSeg) * segs.size());
+    if (!work.empty()) memcpy(blob.data() + B.off_work, work.data(), work.size() * sizeof(MWork));
     rc = upload(ctx, W, blob.data(), blob.size(), s);
     if (rc) return rc;
     const QSig* sigs_dev = reinterpret_cast<const QSig*>(W + B.off_qsig);
@@ -585,15 +632,16 @@ int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs, int64_t np, const td
     if (rc) return rc;
     hipEvent_t t_q1 = mark(ctx, s);
     mark_stage(ctx, 0, t_q0, t_q1);
-    rc = launch_zero_r(items_dev, none, (int)np, max_rbytes, s);
-    if (rc) return rc;
+    if (any_r) {
+        rc = launch_zero_r(items_dev, none, (int)np, max_rbytes, s);
+        if (rc) return rc;
+    }
     hipEvent_t t_e0 = mark(ctx, s);
     if (any_popc) {
         // zero the plane buffers (padding must read as 0), then pack
         for (int64_t i = 0; i < np; ++i)
-            if (B.eng[i] == TDE_PATH_POPC) {
-                XPair p = items[i].p;
-                rc = launch_zero(W + B.off_planes[i], popc_ws_bytes(p), s);
+            if (B.pp[i].eng == TDE_PATH_POPC) {
+                rc = launch_zero(W + B.off_planes[i], popc_ws_bytes(items[i].p), s);
                 if (rc) return rc;
             }
         rc = launch_popc_pack(items_dev, none, (int)np, p_words, s);
@@ -602,13 +650,20 @@ int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs, int64_t np, const td
         if (rc) return rc;
     }
     if (any_mfma) {
-        rc = launch_xcorr_mfma(items_dev, none, (int)np, max_split, max_tiles, s);
+        rc = launch_xcorr_mfma(items_dev, none, reinterpret_cast<const MWork*>(W + B.off_work), (int)work.size(),
+                               reinterpret_cast<int*>(W + B.off_counters), tparts, ctx->num_cu, s);
         if (rc) return rc;
     }
     hipEvent_t t_e1 = mark(ctx, s);
     mark_stage(ctx, 1, t_e0, t_e1);
-    rc = launch_argmax(segs_dev, noseg, (int)np, pbase, reinterpret_cast<ArgPart*>(W + B.off_parts), s);
-    if (rc) return rc;
+    if (any_fused) {
+        rc = launch_tiles_final(items_dev, none, (int)np, tparts, s);
+        if (rc) return rc;
+    }
+    if (!segs.empty()) {
+        rc = launch_argmax(segs_dev, noseg, (int)segs.size(), pbase, reinterpret_cast<ArgPart*>(W + B.off_parts), s);
+        if (rc) return rc;
+    }
     hipEvent_t t_end = mark(ctx, s);
     mark_stage(ctx, 2, t_e1, t_end);
     mark_stage(ctx, 3, t_begin, t_end);

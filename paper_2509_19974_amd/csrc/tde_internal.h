@@ -6,6 +6,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <vector>
+
 #include "../../include/tde.h"
 
 namespace tde {
@@ -39,11 +41,12 @@ struct QSig {
     double* gsum;         // ceil(n/256) doubles of scratch (auto scale only)
     float* inv_out;       // where the scale in use is written (device)
     int64_t grp_base;     // prefix of ceil(n/256) over the signals before it
-    int64_t blk_base;     // prefix of ceil(n/1024) over the signals before it
+    int64_t blk_base;     // prefix of ceil(n/kQuantBlock) over the signals before it
     float inv_fixed;      // > 0: caller-supplied scale
     int32_t bits;
 };
 
+constexpr int kQuantBlock = 4096;   // samples per quantize workgroup (256 threads x 16)
 int64_t quantize_gsum_doubles(int64_t n);
 // Queue scale (if needed) + quantization of nsig signals. `sigs_dev` holds the
 // descriptors in device memory when nsig > 1; for nsig == 1 `one` is used.
@@ -92,10 +95,21 @@ int launch_zero(void* p, size_t bytes, hipStream_t s);
 struct XItem {
     XPair p;
     int32_t engine;       // TDE_PATH_MFMA or TDE_PATH_POPC: kernels skip other items
+    int32_t mb;           // MFMA engine: accumulator tiles per wave
     int64_t T_start;      // first lag of tile 0
-    int64_t item_m;       // m values per work item (split of the m loop)
+    int64_t item_m;       // bit-plane engine: u words per split item
     int64_t ntiles;       // lag tiles of this pair
-    int64_t nsplit;       // work items per tile (upper bound)
+    int64_t nsplit;       // bit-plane engine: split items per tile
+    // MFMA engine
+    int32_t wide;         // tile sums may exceed int32: reduce in int64
+    int32_t segmented;    // tiles cut into several items: r by atomics, no triples
+    int32_t fused;        // argmax from tile triples (no r array needed)
+    int32_t pad0;
+    int64_t part_base;    // first tile-triple slot of this pair
+    int64_t out_v, out_i, out_c;   // triple of the lags no tile covers (r = 0)
+    const tde_qstat* stat_x;
+    const tde_qstat* stat_y;
+    tde_peak* peak;
     // bit-plane engine only
     const uint32_t* usg;
     const uint32_t* unz;
@@ -108,11 +122,27 @@ struct XItem {
 // zero the r arrays of a batch
 int launch_zero_r(const XItem* items_dev, const XItem& one, int nitems, int64_t max_rbytes, hipStream_t s);
 
-// direct int8-MFMA engine
-void mfma_plan(XItem& it, int64_t total_q_hint);
-int64_t mfma_total_q(const XPair& p);
-int launch_xcorr_mfma(const XItem* items_dev, const XItem& one, int nitems, int64_t max_split,
-                      int64_t max_tiles, hipStream_t s);
+// direct int8-MFMA engine: pairs are cut into lag tiles, each one work item
+// (or several segments for very long signals) that a persistent kernel takes
+// longest-first.
+struct MWork {
+    int32_t pair;         // index into the XItem array
+    int32_t tile;         // lag tile of the pair
+    int64_t qa, qb;       // m range [qa, qb), multiples of 32
+    int32_t segmented;
+    int32_t pad;
+};
+void mfma_plan_pair(XItem& it);                 // sets mb, T_start, ntiles, wide, segmented, outside triple
+int64_t mfma_total_q(const XItem& it);          // summed m range of its tiles
+int64_t mfma_count_items(const XItem& it);
+void mfma_items(const XItem& it, int pair, std::vector<MWork>& out);
+void mfma_sort_items(std::vector<MWork>& w);
+// tile_parts may be null (no triples written); counters_dev: 2 ints of scratch
+int launch_xcorr_mfma(const XItem* items_dev, const XItem& one, const MWork* work_dev, int nwork,
+                      int* counters_dev, ArgPart* tile_parts, int num_cu, hipStream_t s);
+// peaks of the fused pairs from their tile triples
+int launch_tiles_final(const XItem* items_dev, const XItem& one, int npairs, const ArgPart* tile_parts,
+                       hipStream_t s);
 
 // bit-plane engine for ternary codes
 size_t popc_ws_bytes(const XPair& p);

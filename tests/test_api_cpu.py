@@ -49,7 +49,10 @@ def test_workspace_sizes():
     assert tde.tde_quantize_workspace_size(1 << 22) >= 8 * (1 << 14)
     assert tde.tde_argmax_workspace_size(131071) >= 16 * 24
     assert tde.tde_xcorr_workspace_size(4096, 4096, 1, 1, -1024, 1024, tde.TDE_PATH_POPC) > 0
-    assert tde.tde_xcorr_workspace_size(4096, 4096, 7, 7, -1024, 1024, tde.TDE_PATH_MFMA) == 0
+    # the matrix-core engine keeps its work list in the workspace
+    assert tde.tde_xcorr_workspace_size(4096, 4096, 7, 7, -1024, 1024, tde.TDE_PATH_MFMA) > 0
+    assert tde.tde_xcorr_workspace_size(1 << 20, 1 << 20, 127, 127, -(1 << 20) + 1, (1 << 20) - 1,
+                                        tde.TDE_PATH_MFMA) >= 24 * ((1 << 21) // 2048)
 
 
 FAKE = 0x10000   # never dereferenced: validation returns first
