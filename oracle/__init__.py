@@ -6,10 +6,11 @@ with the HIP library (``paper_2509_19974_amd``) and never imports it.
 
 What it computes is the plain definition of each step, written out:
 
-* ``sumsq_tree`` / ``inv_step`` -- the per-signal scale of the uniform
+* ``sumsq_pairwise`` / ``inv_step`` -- the per-signal scale of the uniform
   quantizer (the paper leaves the quantizer free, Section 3.2; this build fixes
-  a symmetric mid-tread quantizer on [-3 sigma, 3 sigma] and a fixed-order
-  float64 sum of squares so that two implementations agree bit for bit).
+  a symmetric mid-tread quantizer on [-3 sigma, 3 sigma] and a pairwise
+  float64 sum of squares over a fixed binary tree so that two implementations
+  agree bit for bit).
 * ``quantize`` -- Algorithm 1, line 2: monotone integer maps with phi(0) = 0;
   sign with sign(0) = 0 (Section 4.2) for bits = 1.
 * ``xcorr`` / ``xcorr_at`` -- Algorithm 1, line 3: Eq. (1) on the integer
@@ -61,8 +62,8 @@ def _load():
         build(force=False)
     lib = ctypes.CDLL(_LIB_PATH)
     i64, f32, f64, vp = ctypes.c_int64, ctypes.c_float, ctypes.c_double, ctypes.c_void_p
-    lib.oracle_sumsq_tree.argtypes = [vp, i64, vp]
-    lib.oracle_sumsq_tree.restype = f64
+    lib.oracle_sumsq_pairwise.argtypes = [vp, i64, vp]
+    lib.oracle_sumsq_pairwise.restype = f64
     lib.oracle_kmax.argtypes = [ctypes.c_int]
     lib.oracle_kmax.restype = ctypes.c_int
     lib.oracle_inv_step_from_sumsq.argtypes = [f64, i64, ctypes.c_int]
@@ -109,18 +110,22 @@ def kmax(bits: int) -> int:
     return int(_load().oracle_kmax(bits))
 
 
-def sumsq_tree(x) -> float:
-    """Fixed-order float64 sum of squares over the finite samples (fan-in 256)."""
+def sumsq_pairwise(x) -> float:
+    """Pairwise (fixed binary tree) float64 sum of the exact squares of the
+    finite samples, zero-padded to a power-of-two length."""
     x = _f32(x)
     n = x.size
-    scratch = np.zeros(max(1, (n + 255) // 256), dtype=np.float64)
-    return float(_load().oracle_sumsq_tree(_ptr(x), n, _ptr(scratch)))
+    p2 = 1
+    while p2 < n:
+        p2 *= 2
+    scratch = np.zeros(p2, dtype=np.float64)
+    return float(_load().oracle_sumsq_pairwise(_ptr(x), n, _ptr(scratch)))
 
 
 def inv_step(x, bits: int) -> float:
     """fl32((2K+1) / (6 sigma)), sigma = sqrt(S/n); 0.0 when S == 0."""
     x = _f32(x)
-    S = sumsq_tree(x)
+    S = sumsq_pairwise(x)
     return float(np.float32(_load().oracle_inv_step_from_sumsq(S, x.size, bits)))
 
 

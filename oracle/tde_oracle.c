@@ -31,41 +31,25 @@
  * how sigma is computed; this oracle fixes it so that two implementations can
  * agree bit for bit:
  *   s_m = (double)x_m * (double)x_m for finite x_m (exact in float64), 0 else;
- *   repeatedly replace the list by the sums of consecutive groups of 256
- *   entries (last group zero-padded), each group summed left to right in
- *   float64, until one value remains. */
-#define ORACLE_FANIN 256
-
-static double group_sum(const double* a, int64_t len) {
-    double acc = 0.0;
-    for (int64_t i = 0; i < len; ++i) acc += a[i];
-    return acc;
-}
-
-/* scratch must hold ceil(n/256) doubles. */
-double oracle_sumsq_tree(const float* x, int64_t n, double* scratch) {
+ *   pad the list with zeros to a power-of-two length and repeatedly replace it
+ *   by the float64 sums of adjacent pairs (a[2k] + a[2k+1]) until one value
+ *   remains (a pairwise sum over a fixed binary tree).
+ * scratch must hold the padded length (the next power of two >= n) doubles. */
+double oracle_sumsq_pairwise(const float* x, int64_t n, double* scratch) {
     if (n <= 0) return 0.0;
-    int64_t ng = (n + ORACLE_FANIN - 1) / ORACLE_FANIN;
-    for (int64_t g = 0; g < ng; ++g) {
-        double acc = 0.0;
-        int64_t lo = g * ORACLE_FANIN, hi = lo + ORACLE_FANIN;
-        if (hi > n) hi = n;
-        for (int64_t m = lo; m < hi; ++m) {
+    int64_t len = 1;
+    while (len < n) len *= 2;
+    for (int64_t m = 0; m < len; ++m) {
+        double s = 0.0;
+        if (m < n) {
             double xm = (double)x[m];
-            double s = isfinite(xm) ? xm * xm : 0.0;
-            acc += s;
+            if (isfinite(xm)) s = xm * xm;
         }
-        scratch[g] = acc;
+        scratch[m] = s;
     }
-    int64_t len = ng;
     while (len > 1) {
-        int64_t nn = (len + ORACLE_FANIN - 1) / ORACLE_FANIN;
-        for (int64_t g = 0; g < nn; ++g) {
-            int64_t lo = g * ORACLE_FANIN, hi = lo + ORACLE_FANIN;
-            if (hi > len) hi = len;
-            scratch[g] = group_sum(scratch + lo, hi - lo);
-        }
-        len = nn;
+        len /= 2;
+        for (int64_t k = 0; k < len; ++k) scratch[k] = scratch[2 * k] + scratch[2 * k + 1];
     }
     return scratch[0];
 }

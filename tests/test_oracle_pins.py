@@ -227,27 +227,31 @@ def test_quantize_thresholds_monotone_odd(bits):
 
 # ------------------------------------------------------------------ scale --
 
-def test_sumsq_tree_small_is_sequential_sum():
+def test_sumsq_pairwise_hand_derived_rounding():
+    """Squares [2^54, 1 x 7]: ulp(2^54) = 4. Pairwise: (2^54+1) -> 2^54,
+    1+1 = 2 three times; (2^54+2) is a tie -> 2^54 (even), 2+2 = 4; then
+    2^54 + 4 is exact. A left-to-right sum would lose every +1 (2^54), the
+    exact value is 2^54 + 7."""
+    x = np.array([2.0 ** 27] + [1.0] * 7, dtype=np.float32)
+    assert oracle.sumsq_pairwise(x) == 2.0 ** 54 + 4
+    assert oracle.sumsq_pairwise(np.array([3.0], np.float32)) == 9.0
+    assert oracle.sumsq_pairwise(np.array([1.0, 2.0, 3.0], np.float32)) == 14.0
+
+
+def test_sumsq_pairwise_exact_on_integers_and_fsum_bound():
     rng = np.random.default_rng(2)
-    for n in (1, 5, 255, 256):
-        x = rng.standard_normal(n).astype(np.float32)
-        seq = np.cumsum(x.astype(np.float64) ** 2)[-1]        # left-to-right sum
-        assert oracle.sumsq_tree(x) == seq
-
-
-def test_sumsq_tree_two_levels_and_fsum():
-    rng = np.random.default_rng(4)
-    n = 256 * 37 + 11
-    x = (rng.standard_normal(n) * 10).astype(np.float32)
-    x2 = x.astype(np.float64) ** 2
-    groups = [np.cumsum(x2[i:i + 256])[-1] for i in range(0, n, 256)]
-    assert oracle.sumsq_tree(x) == np.cumsum(np.array(groups))[-1]
-    exact = math.fsum(x2)
-    assert abs(oracle.sumsq_tree(x) - exact) <= 300 * np.finfo(np.float64).eps * exact
+    for n in (1, 5, 255, 256, 1000, 65536 + 17):
+        xi = rng.integers(-1000, 1001, size=n)
+        x = xi.astype(np.float32)
+        # every partial sum is an integer below 2^53: the tree sum is exact
+        assert oracle.sumsq_pairwise(x) == float(int((xi.astype(np.int64) ** 2).sum()))
+    x = (rng.standard_normal(256 * 37 + 11) * 10).astype(np.float32)
+    exact = math.fsum(x.astype(np.float64) ** 2)
+    depth = math.ceil(math.log2(x.size))
+    assert abs(oracle.sumsq_pairwise(x) - exact) <= depth * np.finfo(np.float64).eps * exact
     x[5] = np.nan
     x[6] = np.inf
-    S = oracle.sumsq_tree(x)
-    assert math.isfinite(S)
+    assert math.isfinite(oracle.sumsq_pairwise(x))
 
 
 @pytest.mark.parametrize("bits", [2, 4, 8])
