@@ -118,10 +118,10 @@ const char* tde_last_error(void);
  *            inv_step = (2K+1) / (6 sigma).
  *  inv_step <= 0 selects the automatic scale: sigma = sqrt(S / n) with S the
  *            sum of x^2 over the finite samples, each square exact in float64,
- *            summed in float64 in a fixed order (consecutive groups of 256
- *            summed left to right, the group sums grouped the same way until
- *            one value remains); inv_step = fl32((2K+1) / (6 sigma)), or 0 when
- *            S = 0 (then every code is 0). The scale used is written to
+ *            summed in float64 over a fixed binary tree (the list of squares
+ *            zero-padded to a power-of-two length, adjacent pairs added level
+ *            by level); inv_step = fl32((2K+1) / (6 sigma)), or 0 when S = 0
+ *            (then every code is 0). The scale used is written to
  *            stat->inv_step.
  *  stat (device, may be NULL) receives the tde_qstat of the signal.
  * Errors: TDE_ERR_ARG for n < 1, a null x/q, bits not in {1,2,4,8}, or a
@@ -183,9 +183,19 @@ typedef struct {
 typedef struct {
     int32_t mode;        /* TDE_MODE_FULL */
     int32_t path;        /* TDE_PATH_* forced for every pair, or AUTO */
-    int32_t use_graph;   /* replay a captured HIP graph when the batch layout repeats */
+    int32_t use_graph;   /* see below */
     int32_t reserved;
 } tde_opts;
+
+/* use_graph = 1: the first call with a given signature (the bytes of the
+ * pairs array, opts, ws, ws_bytes and out) waits for the caller's stream,
+ * writes its descriptors into the workspace and captures its kernels into a
+ * HIP graph; later calls with the same signature only launch that graph on
+ * the caller's stream (new sample values in the same device buffers are
+ * picked up). The workspace then keeps state between calls: the caller must
+ * not write to it while such calls continue. Any other call of the same
+ * context whose workspace overlaps it drops the cached graph. Stage timing
+ * is not recorded for graph launches. */
 
 /* Algorithm 1, lines 1-4 for every pair of pairs_host[0..npairs) (host array):
  * quantize x and y, correlate exactly, and write out[i] (device) for pair i.

@@ -106,9 +106,7 @@ __global__ void __launch_bounds__(256) k_argmax_final(const ArgSeg* segs, int ns
     }
     t = block_tri(t);
     if (threadIdx.x == 0) {
-        int flags = 0;
-        if (s.stat_x) flags |= s.stat_x->flags & (TDE_FLAG_NONFINITE_X | TDE_FLAG_ZERO_X);
-        if (s.stat_y) flags |= (s.stat_y->flags & (TDE_FLAG_NONFINITE_X | TDE_FLAG_ZERO_X)) << 1;
+        const int flags = peak_flags(s.stat_x, s.nx, s.stat_y, s.ny);
         tde_peak pk;
         pk.lag = s.lag_lo + t.i;
         pk.rmax = t.v;

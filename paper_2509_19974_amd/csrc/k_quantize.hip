@@ -1,9 +1,13 @@
 // Algorithm 1, lines 1-2: per-signal scale and monotone integer quantization.
 //
 // Scale: S = sum of x^2 over finite samples, every square exact in float64,
-// summed in float64 in a fixed order (groups of 256 consecutive values summed
-// left to right; the group sums grouped the same way until one value is
-// left). sigma = sqrt(S / n), inv_step = fl32((2K+1) / (6 sigma)).
+// summed in float64 over a fixed binary tree (zero-padded to a power-of-two
+// length, adjacent pairs added level by level). sigma = sqrt(S / n),
+// inv_step = fl32((2K+1) / (6 sigma)). The tree maps onto the GPU directly:
+// pairs inside a lane, then wave shuffles (lane l with l ^ k, lower lane on
+// the left; float64 addition is commutative, so either order gives the same
+// bits), then LDS across waves and blocks; every subtree is aligned to its
+// own power-of-two boundary, so the split into kernels does not change it.
 //
 // Quantizer: bits = 1 is sign with sign(0) = 0 (Section 4.2), taken from the
 // IEEE bits; bits in {2,4,8} is clamp(round_half_even(fl32(x * inv_step)),
@@ -15,96 +19,114 @@
 
 namespace tde {
 
-constexpr int kFanIn = 256;       // sum-tree fan-in (part of the scale's definition)
+constexpr int kSumBlock = 1024;    // samples per block sum (a level-10 subtree)
+constexpr int kSumChunk = 4096;    // block sums reduced per LDS pass in the finalize
 
-__device__ __forceinline__ const QSig& pick_sig(const QSig* sigs, int nsig, const QSig& one,
-                                                int64_t unit, bool by_group, int64_t& local) {
+// Signal of a global block index: a 64-way search per round (one load per
+// lane, a ballot), so finding the signal takes ceil(log64(nsig)) rounds
+// instead of a chain of dependent loads. Every wave computes it by itself.
+__device__ __forceinline__ const QSig& pick_sig(const QSig* sigs, int nsig, const QSig& one, int64_t unit,
+                                                int64_t& local) {
     if (sigs == nullptr) {
         local = unit;
         return one;
     }
-    // binary search: last signal whose base <= unit
-    int lo = 0, hi = nsig - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        int64_t b = by_group ? sigs[mid].grp_base : sigs[mid].blk_base;
-        if (b <= unit) lo = mid; else hi = mid - 1;
+    const int lane = threadIdx.x & 63;
+    int lo = 0, n = nsig;                      // invariant: sigs[lo].blk_base <= unit
+    while (n > 1) {
+        const int step = (n + 63) / 64;
+        const int cand = lo + lane * step;
+        const bool ok = lane * step < n && sigs[cand].blk_base <= unit;
+        const unsigned long long m = __ballot(ok);
+        const int l = 63 - __builtin_clzll(m);
+        const int nlo = lo + l * step;
+        n = (lo + n - nlo) < step ? (lo + n - nlo) : step;
+        lo = nlo;
     }
-    local = unit - (by_group ? sigs[lo].grp_base : sigs[lo].blk_base);
+    local = unit - sigs[lo].blk_base;
     return sigs[lo];
 }
 
-// One thread per group of 256 samples: the group's left-to-right float64 sum.
-__global__ void __launch_bounds__(256) k_sumsq_groups(const QSig* sigs, int nsig, QSig one,
-                                                      int64_t total_groups) {
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total_groups) return;
-    int64_t lg;
-    const QSig& s = pick_sig(sigs, nsig, one, g, true, lg);
+__device__ __forceinline__ double sq_or_zero(float f) {
+    double a = f;
+    return __builtin_isfinite(a) ? a * a : 0.0;
+}
+
+// One block per 4096 samples of a signal: four level-10 nodes of the tree
+// (1024 samples each), thread t holding samples 1024 k + 4t .. 4t+3 of node k.
+__global__ void __launch_bounds__(256) k_sumsq_blocks(const QSig* sigs, int nsig, QSig one) {
+    const int64_t blk = blockIdx.x;
+    int64_t lb;
+    const QSig& s = pick_sig(sigs, nsig, one, blk, lb);
     if (s.inv_fixed > 0.f || s.bits == 1) return;
-    int64_t lo = lg * kFanIn;
-    int64_t hi = lo + kFanIn < s.n ? lo + kFanIn : s.n;
-    const float* x = s.x;
-    double acc = 0.0;
-    int64_t m = lo;
-    if ((((uintptr_t)(x + m)) & 15) == 0) {
-        // 16 independent loads in flight, then the left-to-right additions
-        for (; m + 64 <= hi; m += 64) {
-            float4 f[16];
+    const int64_t base = lb * kQuantBlock;
+    float4 xv[4];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) f[k] = *reinterpret_cast<const float4*>(x + m + 4 * k);
+    for (int k = 0; k < 4; ++k) {
+        const int64_t m = base + 1024 * k + 4 * (int64_t)threadIdx.x;
+        if (m + 4 <= s.n && ((((uintptr_t)(s.x + m)) & 15) == 0)) {
+            xv[k] = *reinterpret_cast<const float4*>(s.x + m);
+        } else {
+            float t4[4];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                double a0 = f[k].x, a1 = f[k].y, a2 = f[k].z, a3 = f[k].w;
-                acc += __builtin_isfinite(a0) ? a0 * a0 : 0.0;
-                acc += __builtin_isfinite(a1) ? a1 * a1 : 0.0;
-                acc += __builtin_isfinite(a2) ? a2 * a2 : 0.0;
-                acc += __builtin_isfinite(a3) ? a3 * a3 : 0.0;
-            }
+            for (int e = 0; e < 4; ++e) t4[e] = (m + e < s.n) ? s.x[m + e] : 0.f;
+            xv[k] = make_float4(t4[0], t4[1], t4[2], t4[3]);
         }
     }
-    for (; m < hi; ++m) {
-        double a = x[m];
-        acc += __builtin_isfinite(a) ? a * a : 0.0;
+    __shared__ double ws[4][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double a = (sq_or_zero(xv[k].x) + sq_or_zero(xv[k].y)) + (sq_or_zero(xv[k].z) + sq_or_zero(xv[k].w));
+#pragma unroll
+        for (int h = 1; h < 64; h <<= 1) {
+            double o = __shfl_xor(a, h, 64);
+            a = a + o;     // lanes l and l^h hold the two children; the sum is the same in both
+        }
+        if ((threadIdx.x & 63) == 0) ws[k][threadIdx.x >> 6] = a;
     }
-    s.gsum[lg] = acc;
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        const int64_t node = lb * 4 + k;
+        if (node * kSumBlock < s.n) s.gsum[node] = (ws[k][0] + ws[k][1]) + (ws[k][2] + ws[k][3]);
+    }
 }
 
 // One block per signal: remaining levels of the sum tree, then the scale.
 // Also zeroes the statistics that the quantize kernel accumulates.
-__global__ void __launch_bounds__(256) k_scale_finalize(const QSig* sigs, int nsig, QSig one) {
+__global__ void __launch_bounds__(256) k_scale_finalize(const QSig* sigs, int nsig, QSig one, int* zero_me,
+                                                        int nzero) {
     const QSig& s = sigs ? sigs[blockIdx.x] : one;
     const int t = threadIdx.x;
+    // scratch counters of a later kernel of the same call start at zero
+    if (blockIdx.x == 0 && zero_me && t < nzero) zero_me[t] = 0;
     float inv;
     if (s.bits == 1) {
         inv = 0.f;
     } else if (s.inv_fixed > 0.f) {
         inv = s.inv_fixed;
     } else {
-        // levels >= 1: each level's sums are written after the previous level
-        // in the same scratch (sized by quantize_gsum_doubles), so no thread
-        // overwrites values another thread still reads.
-        int64_t len = (s.n + kFanIn - 1) / kFanIn;
+        // levels above the 1024-sample blocks: chunks of 4096 values (each
+        // a complete aligned subtree) are reduced in LDS, until one is left
+        int64_t len = (s.n + kSumBlock - 1) / kSumBlock;
         double* a = s.gsum;
         double* out = a + len;
+        __shared__ double st[kSumChunk];
         while (len > 1) {
-            int64_t nn = (len + kFanIn - 1) / kFanIn;
-            for (int64_t g = t; g < nn; g += blockDim.x) {
-                int64_t lo = g * kFanIn;
-                int64_t hi = lo + kFanIn < len ? lo + kFanIn : len;
-                double acc = 0.0;
-                int64_t i = lo;
-                for (; i + 16 <= hi; i += 16) {
-                    double v[16];
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) v[k] = a[i + k];
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) acc += v[k];
+            const int64_t nn = (len + kSumChunk - 1) / kSumChunk;
+            for (int64_t c = 0; c < nn; ++c) {
+                const int64_t lo = c * kSumChunk;
+                int width = 1;
+                while (width < kSumChunk && width < len - lo) width *= 2;     // padded subtree width
+                for (int i = t; i < width; i += blockDim.x) st[i] = (lo + i < len) ? a[lo + i] : 0.0;
+                __syncthreads();
+                for (int h = width / 2; h >= 1; h /= 2) {
+                    for (int i = t; i < h; i += blockDim.x) st[i] = st[2 * i] + st[2 * i + 1];
+                    __syncthreads();
                 }
-                for (; i < hi; ++i) acc += a[i];
-                out[g] = acc;
+                if (t == 0) out[c] = st[0];
+                __syncthreads();
             }
-            __syncthreads();
             a = out;
             out = a + nn;
             len = nn;
@@ -160,44 +182,50 @@ __device__ __forceinline__ T wave_sum(T v) {
 // 256 threads x 16 samples per block; one set of statistic atomics per block.
 __global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QSig one,
                                                   int64_t total_blocks) {
-    int64_t blk = blockIdx.x;
+    const int64_t blk = blockIdx.x;
     int64_t lb;
-    const QSig& s = pick_sig(sigs, nsig, one, blk, false, lb);
+    const QSig& s = pick_sig(sigs, nsig, one, blk, lb);
     const float inv = (s.bits == 1) ? 0.f : (s.inv_fixed > 0.f ? s.inv_fixed : *s.inv_out);
     const int K = s.bits == 1 ? 1 : (1 << (s.bits - 1)) - 1;
-    const int64_t m0 = lb * kQuantBlock + 16 * (int64_t)threadIdx.x;
+    const int64_t base = lb * kQuantBlock;
     int nonfinite = 0, nzero = 0;
     int sq = 0, sq2 = 0;
-    if (m0 < s.n) {
-        float xs[16];
-        const bool full = m0 + 16 <= s.n;
-        if (full && ((((uintptr_t)(s.x + m0)) & 15) == 0)) {
+    // four coalesced passes: thread t takes samples base + 1024 k + 4t + e
+    float4 xv[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                float4 f = *reinterpret_cast<const float4*>(s.x + m0 + 4 * k);
-                xs[4 * k] = f.x; xs[4 * k + 1] = f.y; xs[4 * k + 2] = f.z; xs[4 * k + 3] = f.w;
-            }
+    for (int k = 0; k < 4; ++k) {
+        const int64_t m = base + 1024 * k + 4 * (int64_t)threadIdx.x;
+        if (m + 4 <= s.n && ((((uintptr_t)(s.x + m)) & 15) == 0)) {
+            xv[k] = *reinterpret_cast<const float4*>(s.x + m);
         } else {
+            float t4[4];
 #pragma unroll
-            for (int e = 0; e < 16; ++e) xs[e] = (m0 + e < s.n) ? s.x[m0 + e] : 0.f;
+            for (int e = 0; e < 4; ++e) t4[e] = (m + e < s.n) ? s.x[m + e] : 0.f;
+            xv[k] = make_float4(t4[0], t4[1], t4[2], t4[3]);
         }
-        uint32_t w[4] = {0u, 0u, 0u, 0u};
+    }
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
+    for (int k = 0; k < 4; ++k) {
+        const int64_t m = base + 1024 * k + 4 * (int64_t)threadIdx.x;
+        if (m >= s.n) continue;
+        const float xs[4] = {xv[k].x, xv[k].y, xv[k].z, xv[k].w};
+        uint32_t w = 0u;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
             int c = quant1(xs[e], s.bits, inv, K, nonfinite);
-            if (m0 + e < s.n) {
+            if (m + e < s.n) {
                 nzero += c == 0;
                 sq += c;
                 sq2 += c * c;
             }
-            w[e >> 2] |= (uint32_t)(uint8_t)c << (8 * (e & 3));
+            w |= (uint32_t)(uint8_t)c << (8 * e);
         }
-        if (full && ((((uintptr_t)(s.q + m0)) & 15) == 0)) {
-            *reinterpret_cast<uint4*>(s.q + m0) = make_uint4(w[0], w[1], w[2], w[3]);
+        if (m + 4 <= s.n && ((((uintptr_t)(s.q + m)) & 3) == 0)) {
+            *reinterpret_cast<uint32_t*>(s.q + m) = w;
         } else {
 #pragma unroll
-            for (int e = 0; e < 16; ++e)
-                if (m0 + e < s.n) s.q[m0 + e] = (int8_t)(w[e >> 2] >> (8 * (e & 3)));
+            for (int e = 0; e < 4; ++e)
+                if (m + e < s.n) s.q[m + e] = (int8_t)(w >> (8 * e));
         }
     }
     if (s.stat) {
@@ -221,7 +249,7 @@ __global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QS
     }
 }
 
-// Flags from the finished statistics (one thread per signal).
+// tde_qstat::flags from the finished counts (one thread per signal).
 __global__ void k_quantize_flags(const QSig* sigs, int nsig, QSig one) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nsig) return;
@@ -233,28 +261,29 @@ __global__ void k_quantize_flags(const QSig* sigs, int nsig, QSig one) {
     s.stat->flags = f;
 }
 
-// Doubles of scratch for the sum tree of an n-sample signal (all levels).
+// Doubles of scratch for the sum tree of an n-sample signal (block sums and
+// the chunk sums of every further pass).
 int64_t quantize_gsum_doubles(int64_t n) {
-    int64_t len = (n + kFanIn - 1) / kFanIn, tot = len;
+    int64_t len = (n + kSumBlock - 1) / kSumBlock, tot = len;
     while (len > 1) {
-        len = (len + kFanIn - 1) / kFanIn;
+        len = (len + kSumChunk - 1) / kSumChunk;
         tot += len;
     }
     return tot + 1;
 }
 
-int launch_quantize(const QSig* sigs_dev, const QSig& one, int nsig, int64_t total_groups,
-                    int64_t total_blocks, bool need_scale, hipStream_t s) {
+int launch_quantize(const QSig* sigs_dev, const QSig& one, int nsig, int64_t total_blocks, bool need_scale,
+                    bool write_flags, int* zero_me, int nzero, hipStream_t s) {
     if (need_scale) {
-        hipLaunchKernelGGL(k_sumsq_groups, dim3((unsigned)ceil_div(total_groups, 256)), dim3(256), 0, s,
-                           sigs_dev, nsig, one, total_groups);
+        hipLaunchKernelGGL(k_sumsq_blocks, dim3((unsigned)total_blocks), dim3(256), 0, s, sigs_dev, nsig, one);
     }
-    if (need_scale || sigs_dev != nullptr || one.stat != nullptr || one.inv_out != nullptr)
-        hipLaunchKernelGGL(k_scale_finalize, dim3(nsig), dim3(256), 0, s, sigs_dev, nsig, one);
+    if (need_scale || sigs_dev != nullptr || one.stat != nullptr || one.inv_out != nullptr || zero_me != nullptr)
+        hipLaunchKernelGGL(k_scale_finalize, dim3(nsig), dim3(256), 0, s, sigs_dev, nsig, one, zero_me, nzero);
     hipLaunchKernelGGL(k_quantize, dim3((unsigned)total_blocks), dim3(256), 0, s, sigs_dev, nsig, one,
                        total_blocks);
-    hipLaunchKernelGGL(k_quantize_flags, dim3((unsigned)ceil_div(nsig, 256)), dim3(256), 0, s, sigs_dev,
-                       nsig, one);
+    if (write_flags)
+        hipLaunchKernelGGL(k_quantize_flags, dim3((unsigned)ceil_div(nsig, 256)), dim3(256), 0, s, sigs_dev, nsig,
+                           one);
     TDE_HIP_CHECK(hipGetLastError());
     return TDE_OK;
 }

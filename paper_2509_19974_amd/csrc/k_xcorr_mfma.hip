@@ -391,9 +391,7 @@ __global__ void __launch_bounds__(64) k_tiles_final(const XItem* items, XItem on
         t = tri_join(t, u);
     }
     if (threadIdx.x == 0) {
-        int flags = 0;
-        if (it.stat_x) flags |= it.stat_x->flags & (TDE_FLAG_NONFINITE_X | TDE_FLAG_ZERO_X);
-        if (it.stat_y) flags |= (it.stat_y->flags & (TDE_FLAG_NONFINITE_X | TDE_FLAG_ZERO_X)) << 1;
+        const int flags = peak_flags(it.stat_x, it.p.nu, it.stat_y, it.p.nv);
         tde_peak pk;
         pk.lag = it.p.lag_lo + t.i;
         pk.rmax = t.v;
@@ -517,10 +515,12 @@ void mfma_sort_items(std::vector<MWork>& w) {
 }
 
 int launch_xcorr_mfma(const XItem* items_dev, const XItem& one, const MWork* work_dev, int nwork,
-                      int* counters_dev, ArgPart* tile_parts, int num_cu, hipStream_t s) {
+                      int* counters_dev, bool counters_zeroed, ArgPart* tile_parts, int num_cu, hipStream_t s) {
     using C = MCfg<4>;
-    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, counters_dev, 2);
-    TDE_HIP_CHECK(hipGetLastError());
+    if (!counters_zeroed) {
+        hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, counters_dev, 2);
+        TDE_HIP_CHECK(hipGetLastError());
+    }
     if (nwork == 0) return TDE_OK;
     static int per_cu = 0;
     if (per_cu == 0) {

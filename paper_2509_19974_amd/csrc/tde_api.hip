@@ -21,6 +21,15 @@ struct tde_ctx {
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
     std::mutex mu;
+    // captured batch graphs, keyed by the exact call signature
+    struct Graph {
+        std::vector<uint8_t> sig;
+        uintptr_t ws_lo, ws_hi;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
+    hipStream_t cap_stream = nullptr;
     // stage timing (measurement only)
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -127,6 +136,23 @@ void mark_stage(tde_ctx* c, int stage, hipEvent_t a, hipEvent_t b) {
     if (c->timing && a && b) c->marks.push_back({stage, a, b});
 }
 
+// A call that writes [ws, ws + bytes) clobbers the descriptors a cached graph
+// keeps there: drop such graphs.
+void drop_graphs_on(tde_ctx* c, const void* ws, size_t bytes) {
+    if (!ws || c->graphs.empty()) return;
+    const uintptr_t lo = (uintptr_t)ws, hi = lo + bytes;
+    for (size_t k = 0; k < c->graphs.size();) {
+        auto& gr = c->graphs[k];
+        if (gr.ws_lo < hi && lo < gr.ws_hi) {
+            (void)hipGraphExecDestroy(gr.exec);
+            (void)hipGraphDestroy(gr.graph);
+            c->graphs.erase(c->graphs.begin() + k);
+        } else {
+            ++k;
+        }
+    }
+}
+
 // Engine choice for one correlation. The direct engines are exact for every
 // size; the bit-plane engine only takes ternary codes.
 int choose_path(int path, int kuv) {
@@ -174,9 +200,10 @@ int tde_create(tde_ctx** out, int device) {
     c->num_cu = prop.multiProcessorCount;
     {
         DeviceGuard g(device);
-        if (hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) != hipSuccess) {
+        if (hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) != hipSuccess ||
+            hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
             delete c;
-            return set_error(TDE_ERR_HIP, "tde_create: event creation failed");
+            return set_error(TDE_ERR_HIP, "tde_create: event or stream creation failed");
         }
     }
     *out = c;
@@ -214,6 +241,11 @@ void tde_destroy(tde_ctx* c) {
     if (!c) return;
     DeviceGuard g(c->device);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    for (auto& gr : c->graphs) {
+        (void)hipGraphExecDestroy(gr.exec);
+        (void)hipGraphDestroy(gr.graph);
+    }
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->upload_pending) (void)hipEventSynchronize(c->upload_done);
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);
     if (c->pinned) (void)hipHostFree(c->pinned);
@@ -252,7 +284,11 @@ int tde_quantize(tde_ctx* ctx, const float* x, int64_t n, int bits, float inv_st
     }
     DeviceGuard g(ctx->device);
     if (!g.ok) return set_error(TDE_ERR_HIP, "tde_quantize: hipSetDevice failed");
-    return launch_quantize(nullptr, one, 1, ceil_div(n, 256), ceil_div(n, kQuantBlock), need_scale,
+    {
+        std::lock_guard<std::mutex> lock(ctx->mu);
+        drop_graphs_on(ctx, ws, ws_bytes);
+    }
+    return launch_quantize(nullptr, one, 1, ceil_div(n, kQuantBlock), need_scale, stat != nullptr, nullptr, 0,
                            static_cast<hipStream_t>(stream));
 }
 
@@ -325,6 +361,10 @@ int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, in
     rc = launch_zero_r(nullptr, it, 1, rbytes, s);
     if (rc) return rc;
     if (eng == TDE_PATH_POPC) {
+        {
+            std::lock_guard<std::mutex> lock(ctx->mu);
+            drop_graphs_on(ctx, ws, ws_bytes);
+        }
         popc_plan(it, ws);
         rc = launch_zero(ws, need, s);
         if (rc) return rc;
@@ -341,10 +381,11 @@ int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, in
                                            align_bytes((size_t)mfma_count_items(it) * sizeof(MWork)));
     {
         std::lock_guard<std::mutex> lock(ctx->mu);
+        drop_graphs_on(ctx, ws, ws_bytes);
         rc = upload(ctx, work_dev, work.data(), work.size() * sizeof(MWork), s);
     }
     if (rc) return rc;
-    return launch_xcorr_mfma(nullptr, it, work_dev, (int)work.size(), counters, nullptr, ctx->num_cu, s);
+    return launch_xcorr_mfma(nullptr, it, work_dev, (int)work.size(), counters, false, nullptr, ctx->num_cu, s);
 }
 
 // -------------------------------------------------------------- argmax --
@@ -373,6 +414,10 @@ int tde_argmax_lag(tde_ctx* ctx, const void* r, int r_dtype, int64_t lag_lo, int
     one.out = out;
     DeviceGuard g(ctx->device);
     if (!g.ok) return set_error(TDE_ERR_HIP, "tde_argmax_lag: hipSetDevice failed");
+    {
+        std::lock_guard<std::mutex> lock(ctx->mu);
+        drop_graphs_on(ctx, ws, ws_bytes);
+    }
     return launch_argmax(nullptr, one, 1, one.nparts, static_cast<ArgPart*>(ws), static_cast<hipStream_t>(stream));
 }
 
@@ -518,33 +563,31 @@ size_t tde_estimate_workspace_size(const tde_pair* pairs, int64_t np, const tde_
     return plan_batch(pairs, np, opts).total;
 }
 
-int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs, int64_t np, const tde_opts* opts, tde_peak* out,
-                       void* ws, size_t ws_bytes, void* stream) {
-    if (!out) return set_error(TDE_ERR_ARG, "tde_estimate_batch: null out");
-    int rc = validate_pairs(pairs, np, opts);
-    if (rc) return rc;
-    BatchPlan B = plan_batch(pairs, np, opts);
-    if (!ws || ws_bytes < B.total)
-        return set_error(TDE_ERR_WS, "tde_estimate_batch: workspace %zu < %zu bytes", ws_bytes, B.total);
-    if (!ctx) return set_error(TDE_ERR_ARG, "tde_estimate_batch: null context");
-    std::lock_guard<std::mutex> lock(ctx->mu);
-    DeviceGuard g(ctx->device);
-    if (!g.ok) return set_error(TDE_ERR_HIP, "tde_estimate_batch: hipSetDevice failed");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    uint8_t* W = static_cast<uint8_t*>(ws);
-    hipEvent_t t_begin = mark(ctx, s);
+}  // extern "C"
 
-    // ---- descriptors (host side)
+namespace {
+
+// Everything a batch call queues, prepared on the host.
+struct BatchLaunch {
+    std::vector<uint8_t> blob;       // descriptors for [0, blob.size()) of the workspace
+    int64_t np = 0, bbase = 0, pbase = 0;
+    bool need_scale = false, any_popc = false, any_mfma = false, any_fused = false, any_r = false;
+    int64_t max_rbytes = 0, p_split = 0, p_tiles = 0, p_words = 0;
+    int nwork = 0, nsegs = 0;
+    std::vector<std::pair<size_t, size_t>> plane_zero;   // (offset, bytes) of bit-plane buffers
+};
+
+void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* out, uint8_t* W, const BatchPlan& B,
+                   BatchLaunch& L) {
+    (void)ctx;
     std::vector<QSig> sigs(2 * np);
     std::vector<XItem> items(np);
     std::vector<ArgSeg> segs;
     std::vector<MWork> work;
-    int64_t gbase = 0, bbase = 0, pbase = 0, tbase = 0;
+    int64_t bbase = 0, pbase = 0, tbase = 0;
     tde_qstat* stats = reinterpret_cast<tde_qstat*>(W + B.off_stats);
     float* invs = reinterpret_cast<float*>(W + B.off_inv);
-    ArgPart* tparts = reinterpret_cast<ArgPart*>(W + B.off_tparts);
-    bool need_scale = false, any_popc = false, any_mfma = false, any_fused = false, any_r = false;
-    int64_t max_rbytes = 0, p_split = 0, p_tiles = 0, p_words = 0;
+    L.np = np;
     for (int64_t i = 0; i < np; ++i) {
         const tde_pair& q = pairs[i];
         const PairPlan& pp = B.pp[i];
@@ -556,13 +599,11 @@ int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs, int64_t np, const td
             S.stat = stats + 2 * i + side;
             S.gsum = reinterpret_cast<double*>(W + B.off_gsum[2 * i + side]);
             S.inv_out = invs + 2 * i + side;
-            S.grp_base = gbase;
             S.blk_base = bbase;
             const float fixed = side ? q.inv_step_y : q.inv_step_x;
             S.inv_fixed = (q.bits != 1 && fixed > 0.f) ? fixed : 0.f;
             S.bits = q.bits;
-            if (q.bits != 1 && !(fixed > 0.f)) need_scale = true;
-            gbase += ceil_div(S.n, 256);
+            if (q.bits != 1 && !(fixed > 0.f)) L.need_scale = true;
             bbase += ceil_div(S.n, kQuantBlock);
         }
         XItem& it = items[i];
@@ -577,23 +618,24 @@ int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs, int64_t np, const td
         it.peak = out + i;
         it.fused = pp.fused ? 1 : 0;
         if (it.p.r) {
-            any_r = true;
-            max_rbytes = std::max<int64_t>(max_rbytes, (q.lag_hi - q.lag_lo + 1) * (pp.rdt == TDE_I32 ? 4 : 8));
+            L.any_r = true;
+            L.max_rbytes = std::max<int64_t>(L.max_rbytes, (q.lag_hi - q.lag_lo + 1) * (pp.rdt == TDE_I32 ? 4 : 8));
         }
         if (pp.eng == TDE_PATH_MFMA) {
-            any_mfma = true;
+            L.any_mfma = true;
             if (pp.fused) {
                 it.part_base = tbase;
                 tbase += it.ntiles;
-                any_fused = true;
+                L.any_fused = true;
             }
             mfma_items(it, (int)i, work);
         } else {
             popc_plan(it, W + B.off_planes[i]);
-            p_split = std::max(p_split, it.nsplit);
-            p_tiles = std::max(p_tiles, it.ntiles);
-            p_words = std::max(p_words, std::max(it.nuw, it.nvw));
-            any_popc = true;
+            L.p_split = std::max(L.p_split, it.nsplit);
+            L.p_tiles = std::max(L.p_tiles, it.ntiles);
+            L.p_words = std::max(L.p_words, std::max(it.nuw, it.nvw));
+            L.any_popc = true;
+            L.plane_zero.push_back({B.off_planes[i], popc_ws_bytes(it.p)});
         }
         if (!pp.fused) {
             ArgSeg sg{};
@@ -606,67 +648,162 @@ int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs, int64_t np, const td
             sg.out = out + i;
             sg.stat_x = it.stat_x;
             sg.stat_y = it.stat_y;
+            sg.nx = q.nx;
+            sg.ny = q.ny;
             pbase += sg.nparts;
             segs.push_back(sg);
         }
     }
     mfma_sort_items(work);
+    L.bbase = bbase;
+    L.pbase = pbase;
+    L.nwork = (int)work.size();
+    L.nsegs = (int)segs.size();
+    L.blob.assign(B.off_work + work.size() * sizeof(MWork), 0);
+    memcpy(L.blob.data() + B.off_qsig, sigs.data(), sizeof(QSig) * 2 * np);
+    memcpy(L.blob.data() + B.off_items, items.data(), sizeof(XItem) * np);
+    if (!segs.empty()) memcpy(L.blob.data() + B.off_segs, segs.data(), sizeof(ArgSeg) * segs.size());
+    if (!work.empty()) memcpy(L.blob.data() + B.off_work, work.data(), work.size() * sizeof(MWork));
+}
 
-    // ---- upload descriptors (one copy) and queue the kernels
-    std::vector<uint8_t> blob(B.off_work + work.size() * sizeof(MWork));
-    memcpy(blob.data() + B.off_qsig, sigs.data(), sizeof(QSig) * 2 * np);
-    memcpy(blob.data() + B.off_items, items.data(), sizeof(XItem) * np);
-    if (!segs.empty()) memcpy(blob.data() + B.off_segs, segs.data(), sizeof(ArgSeg) * segs.size());
-    if (!work.empty()) memcpy(blob.data() + B.off_work, work.data(), work.size() * sizeof(MWork));
-    rc = upload(ctx, W, blob.data(), blob.size(), s);
-    if (rc) return rc;
+// Queues the kernels of a prepared batch on s (the descriptors are already in
+// the workspace). No memset or copy nodes: safe to capture in a graph.
+int batch_enqueue(tde_ctx* ctx, uint8_t* W, const BatchPlan& B, const BatchLaunch& L, hipStream_t s, bool timed) {
     const QSig* sigs_dev = reinterpret_cast<const QSig*>(W + B.off_qsig);
     const XItem* items_dev = reinterpret_cast<const XItem*>(W + B.off_items);
     const ArgSeg* segs_dev = reinterpret_cast<const ArgSeg*>(W + B.off_segs);
+    ArgPart* tparts = reinterpret_cast<ArgPart*>(W + B.off_tparts);
     XItem none{};
     ArgSeg noseg{};
     QSig nosig{};
-
-    hipEvent_t t_q0 = mark(ctx, s);
-    rc = launch_quantize(sigs_dev, nosig, (int)(2 * np), gbase, bbase, need_scale, s);
+    auto mk = [&](void) { return timed ? mark(ctx, s) : nullptr; };
+    hipEvent_t t_q0 = mk();
+    int rc = launch_quantize(sigs_dev, nosig, (int)(2 * L.np), L.bbase, L.need_scale, false,
+                             L.any_mfma ? reinterpret_cast<int*>(W + B.off_counters) : nullptr, 2, s);
     if (rc) return rc;
-    hipEvent_t t_q1 = mark(ctx, s);
-    mark_stage(ctx, 0, t_q0, t_q1);
-    if (any_r) {
-        rc = launch_zero_r(items_dev, none, (int)np, max_rbytes, s);
+    hipEvent_t t_q1 = mk();
+    if (timed) mark_stage(ctx, 0, t_q0, t_q1);
+    if (L.any_r) {
+        rc = launch_zero_r(items_dev, none, (int)L.np, L.max_rbytes, s);
         if (rc) return rc;
     }
-    hipEvent_t t_e0 = mark(ctx, s);
-    if (any_popc) {
+    hipEvent_t t_e0 = mk();
+    if (L.any_popc) {
         // zero the plane buffers (padding must read as 0), then pack
-        for (int64_t i = 0; i < np; ++i)
-            if (B.pp[i].eng == TDE_PATH_POPC) {
-                rc = launch_zero(W + B.off_planes[i], popc_ws_bytes(items[i].p), s);
-                if (rc) return rc;
+        for (const auto& z : L.plane_zero) {
+            rc = launch_zero(W + z.first, z.second, s);
+            if (rc) return rc;
+        }
+        rc = launch_popc_pack(items_dev, none, (int)L.np, L.p_words, s);
+        if (rc) return rc;
+        rc = launch_xcorr_popc(items_dev, none, (int)L.np, L.p_split, L.p_tiles, s);
+        if (rc) return rc;
+    }
+    if (L.any_mfma) {
+        rc = launch_xcorr_mfma(items_dev, none, reinterpret_cast<const MWork*>(W + B.off_work), L.nwork,
+                               reinterpret_cast<int*>(W + B.off_counters), true, tparts, ctx->num_cu, s);
+        if (rc) return rc;
+    }
+    hipEvent_t t_e1 = mk();
+    if (timed) mark_stage(ctx, 1, t_e0, t_e1);
+    if (L.any_fused) {
+        rc = launch_tiles_final(items_dev, none, (int)L.np, tparts, s);
+        if (rc) return rc;
+    }
+    if (L.nsegs) {
+        rc = launch_argmax(segs_dev, noseg, L.nsegs, L.pbase, reinterpret_cast<ArgPart*>(W + B.off_parts), s);
+        if (rc) return rc;
+    }
+    hipEvent_t t_end = mk();
+    if (timed) mark_stage(ctx, 2, t_e1, t_end);
+    return TDE_OK;
+}
+
+std::vector<uint8_t> batch_signature(const tde_pair* pairs, int64_t np, const tde_opts* opts, const void* ws,
+                                     size_t ws_bytes, const tde_peak* out) {
+    std::vector<uint8_t> sig(sizeof(tde_pair) * np + sizeof(tde_opts) + 3 * sizeof(uint64_t));
+    uint8_t* d = sig.data();
+    memcpy(d, pairs, sizeof(tde_pair) * np);
+    d += sizeof(tde_pair) * np;
+    memcpy(d, opts, sizeof(tde_opts));
+    d += sizeof(tde_opts);
+    uint64_t extra[3] = {(uint64_t)(uintptr_t)ws, (uint64_t)ws_bytes, (uint64_t)(uintptr_t)out};
+    memcpy(d, extra, sizeof(extra));
+    return sig;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs, int64_t np, const tde_opts* opts, tde_peak* out,
+                       void* ws, size_t ws_bytes, void* stream) {
+    if (!out) return set_error(TDE_ERR_ARG, "tde_estimate_batch: null out");
+    int rc = validate_pairs(pairs, np, opts);
+    if (rc) return rc;
+    const bool use_graph = opts && opts->use_graph;
+    if (!ctx) {
+        BatchPlan B = plan_batch(pairs, np, opts);
+        if (!ws || ws_bytes < B.total)
+            return set_error(TDE_ERR_WS, "tde_estimate_batch: workspace %zu < %zu bytes", ws_bytes, B.total);
+        return set_error(TDE_ERR_ARG, "tde_estimate_batch: null context");
+    }
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return set_error(TDE_ERR_HIP, "tde_estimate_batch: hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<uint8_t> sig;
+    if (use_graph) {
+        sig = batch_signature(pairs, np, opts, ws, ws_bytes, out);
+        for (auto& gr : ctx->graphs)
+            if (gr.sig == sig) {
+                TDE_HIP_CHECK(hipGraphLaunch(gr.exec, s));
+                return TDE_OK;
             }
-        rc = launch_popc_pack(items_dev, none, (int)np, p_words, s);
-        if (rc) return rc;
-        rc = launch_xcorr_popc(items_dev, none, (int)np, p_split, p_tiles, s);
-        if (rc) return rc;
     }
-    if (any_mfma) {
-        rc = launch_xcorr_mfma(items_dev, none, reinterpret_cast<const MWork*>(W + B.off_work), (int)work.size(),
-                               reinterpret_cast<int*>(W + B.off_counters), tparts, ctx->num_cu, s);
+    BatchPlan B = plan_batch(pairs, np, opts);
+    if (!ws || ws_bytes < B.total)
+        return set_error(TDE_ERR_WS, "tde_estimate_batch: workspace %zu < %zu bytes", ws_bytes, B.total);
+    uint8_t* W = static_cast<uint8_t*>(ws);
+    BatchLaunch L;
+    batch_prepare(ctx, pairs, np, out, W, B, L);
+    drop_graphs_on(ctx, ws, B.total);
+    if (!use_graph) {
+        hipEvent_t t_begin = mark(ctx, s);
+        rc = upload(ctx, W, L.blob.data(), L.blob.size(), s);
         if (rc) return rc;
-    }
-    hipEvent_t t_e1 = mark(ctx, s);
-    mark_stage(ctx, 1, t_e0, t_e1);
-    if (any_fused) {
-        rc = launch_tiles_final(items_dev, none, (int)np, tparts, s);
+        rc = batch_enqueue(ctx, W, B, L, s, true);
         if (rc) return rc;
+        hipEvent_t t_end = mark(ctx, s);
+        mark_stage(ctx, 3, t_begin, t_end);
+        return TDE_OK;
     }
-    if (!segs.empty()) {
-        rc = launch_argmax(segs_dev, noseg, (int)segs.size(), pbase, reinterpret_cast<ArgPart*>(W + B.off_parts), s);
-        if (rc) return rc;
+    // graph: descriptors go in once, synchronously, then the kernels are
+    // captured on the context's stream and replayed on the caller's.
+    TDE_HIP_CHECK(hipStreamSynchronize(s));
+    TDE_HIP_CHECK(hipMemcpy(W, L.blob.data(), L.blob.size(), hipMemcpyHostToDevice));
+    TDE_HIP_CHECK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    rc = batch_enqueue(ctx, W, B, L, ctx->cap_stream, false);
+    hipGraph_t graph = nullptr;
+    hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
     }
-    hipEvent_t t_end = mark(ctx, s);
-    mark_stage(ctx, 2, t_e1, t_end);
-    mark_stage(ctx, 3, t_begin, t_end);
+    if (ec != hipSuccess) return set_error(TDE_ERR_HIP, "graph capture failed: %s", hipGetErrorString(ec));
+    hipGraphExec_t exec = nullptr;
+    ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ec != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return set_error(TDE_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(ec));
+    }
+    if (ctx->graphs.size() >= 16) {
+        (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+        (void)hipGraphDestroy(ctx->graphs.front().graph);
+        ctx->graphs.erase(ctx->graphs.begin());
+    }
+    ctx->graphs.push_back({std::move(sig), (uintptr_t)ws, (uintptr_t)ws + B.total, graph, exec});
+    TDE_HIP_CHECK(hipGraphLaunch(exec, s));
     return TDE_OK;
 }
 

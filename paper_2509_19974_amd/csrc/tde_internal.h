@@ -38,9 +38,8 @@ struct QSig {
     int64_t n;
     int8_t* q;
     tde_qstat* stat;      // may be null
-    double* gsum;         // ceil(n/256) doubles of scratch (auto scale only)
+    double* gsum;         // quantize_gsum_doubles(n) doubles of scratch (auto scale only)
     float* inv_out;       // where the scale in use is written (device)
-    int64_t grp_base;     // prefix of ceil(n/256) over the signals before it
     int64_t blk_base;     // prefix of ceil(n/kQuantBlock) over the signals before it
     float inv_fixed;      // > 0: caller-supplied scale
     int32_t bits;
@@ -50,8 +49,25 @@ constexpr int kQuantBlock = 4096;   // samples per quantize workgroup (256 threa
 int64_t quantize_gsum_doubles(int64_t n);
 // Queue scale (if needed) + quantization of nsig signals. `sigs_dev` holds the
 // descriptors in device memory when nsig > 1; for nsig == 1 `one` is used.
-int launch_quantize(const QSig* sigs_dev, const QSig& one, int nsig, int64_t total_groups,
-                    int64_t total_blocks, bool need_scale, hipStream_t s);
+// write_flags: also fill tde_qstat::flags (a separate small launch; the batch
+// path derives the flags from the counts where it needs them).
+// zero_me (may be null): nzero ints that later kernels of the call expect at 0.
+int launch_quantize(const QSig* sigs_dev, const QSig& one, int nsig, int64_t total_blocks, bool need_scale,
+                    bool write_flags, int* zero_me, int nzero, hipStream_t s);
+
+// Result flags of a pair from the statistics of its two signals.
+__device__ inline int peak_flags(const tde_qstat* sx, int64_t nx, const tde_qstat* sy, int64_t ny) {
+    int f = 0;
+    if (sx) {
+        if (sx->n_nonfinite) f |= TDE_FLAG_NONFINITE_X;
+        if (sx->n_zero == nx) f |= TDE_FLAG_ZERO_X;
+    }
+    if (sy) {
+        if (sy->n_nonfinite) f |= TDE_FLAG_NONFINITE_Y;
+        if (sy->n_zero == ny) f |= TDE_FLAG_ZERO_Y;
+    }
+    return f;
+}
 
 // -------------------------------------------------------------- argmax --
 struct ArgPart {          // (max, smallest index, count) of a run of r
@@ -70,6 +86,7 @@ struct ArgSeg {           // one r array to reduce
     tde_peak* out;
     const tde_qstat* stat_x;   // flags source (may be null)
     const tde_qstat* stat_y;
+    int64_t nx, ny;            // signal lengths (for the all-zero flags)
 };
 
 constexpr int kArgChunk = 8192;   // r elements per partial block
@@ -137,9 +154,10 @@ int64_t mfma_total_q(const XItem& it);          // summed m range of its tiles
 int64_t mfma_count_items(const XItem& it);
 void mfma_items(const XItem& it, int pair, std::vector<MWork>& out);
 void mfma_sort_items(std::vector<MWork>& w);
-// tile_parts may be null (no triples written); counters_dev: 2 ints of scratch
+// tile_parts may be null (no triples written); counters_dev: 2 ints of
+// scratch, reset here unless an earlier kernel of the call already did
 int launch_xcorr_mfma(const XItem* items_dev, const XItem& one, const MWork* work_dev, int nwork,
-                      int* counters_dev, ArgPart* tile_parts, int num_cu, hipStream_t s);
+                      int* counters_dev, bool counters_zeroed, ArgPart* tile_parts, int num_cu, hipStream_t s);
 // peaks of the fused pairs from their tile triples
 int launch_tiles_final(const XItem* items_dev, const XItem& one, int npairs, const ArgPart* tile_parts,
                        hipStream_t s);

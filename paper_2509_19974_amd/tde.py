@@ -281,7 +281,7 @@ class Context:
             p.r_dtype = int(s.get("r_dtype", TDE_I64))
             pairs.append(p)
         arr = make_pairs(pairs)
-        opts = tde_opts(mode, path, use_graph, 0)
+        opts = tde_opts(mode, path, int(use_graph), 0)
         wsb = tde_estimate_workspace_size(arr, len(pairs), opts)
         if wsb == 0:
             raise TDEError(TDE_ERR_ARG, tde_last_error())

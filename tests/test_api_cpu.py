@@ -46,7 +46,7 @@ def test_struct_sizes_match_header():
 def test_workspace_sizes():
     assert tde.tde_quantize_workspace_size(0) == 0
     assert tde.tde_quantize_workspace_size(1) > 0
-    assert tde.tde_quantize_workspace_size(1 << 22) >= 8 * (1 << 14)
+    assert tde.tde_quantize_workspace_size(1 << 22) >= 8 * (1 << 12)    # one double per 1024 samples
     assert tde.tde_argmax_workspace_size(131071) >= 16 * 24
     assert tde.tde_xcorr_workspace_size(4096, 4096, 1, 1, -1024, 1024, tde.TDE_PATH_POPC) > 0
     # the matrix-core engine keeps its work list in the workspace

@@ -277,3 +277,78 @@ def test_batch_config2_full_size_sampled(T, ctx):
         assert at[1] <= pk[i]["rmax"]
     for i in (0, 31, 63):
         _check_pair(pk[i], pairs[i])
+
+
+# ------------------------------------------------------------------- graphs --
+
+def test_batch_graph_replay_matches_eager(T, ctx):
+    """use_graph: several replays, with eager work and new input values in the
+    same buffers between them; every replay must equal the eager result."""
+    from paper_2509_19974_amd import tde
+    say("batch graph replay")
+    pairs_a = synth.config2_batch(4, npairs=8, n=8192)
+    pairs_b = synth.config2_batch(8, npairs=8, n=8192, salt=7)
+    specs = [dict(x=dev(T, p["x"]), y=dev(T, p["y"]), lag_lo=p["lag_lo"], lag_hi=p["lag_hi"], bits=p["bits"])
+             for p in pairs_a]
+    plan_g = ctx.batch_plan(specs, mode=tde.TDE_MODE_FULL, use_graph=1)
+    plan_e = ctx.batch_plan(specs)
+    ws_g = T.empty(plan_g[2], dtype=T.uint8, device="cuda")
+    out_g = T.empty(len(specs) * 24, dtype=T.uint8, device="cuda")
+    for rep in range(4):
+        src = pairs_a if rep % 2 == 0 else pairs_b
+        for s, p in zip(specs, src):
+            s["x"].copy_(T.from_numpy(p["x"]))
+            s["y"].copy_(T.from_numpy(p["y"]))
+        ctx.estimate_batch(specs, ws=ws_g, out=out_g, plan=plan_g)            # graph (captured on rep 0)
+        eager = ctx.estimate_batch(specs, plan=plan_e)                         # separate workspace
+        T.cuda.synchronize()
+        g = tde.decode_peaks(out_g)
+        e = tde.decode_peaks(eager)
+        assert g.tobytes() == e.tobytes(), rep
+        for i, p in enumerate(src[:2]):
+            _check_pair(g[i], dict(p, bits=specs[i]["bits"]))     # the plan's bits
+
+
+def test_batch_maximum_outside_the_support(T, ctx):
+    """y = -x: inside the support the correlation is mostly negative, so the
+    maximum can be the 0 of a lag where the signals do not overlap."""
+    from paper_2509_19974_amd import tde
+    say("batch outside-support maximum")
+    rng = np.random.default_rng(5)
+    pairs = []
+    for n, lo, hi in ((3000, -5000, 5000), (3000, -2999, 2999), (1000, -1500, -100), (1000, 200, 4000)):
+        x = rng.standard_normal(n).astype(np.float32)
+        pairs.append(dict(x=x, y=(-x).copy(), lag_lo=lo, lag_hi=hi, bits=8))
+    pk, specs = _batch(T, ctx, pairs, 0, want_r=True)
+    for i, p in enumerate(pairs):
+        _check_pair(pk[i], p, specs[i]["r_out"].cpu().numpy())
+    pk2, _ = _batch(T, ctx, pairs, 0, want_r=False)          # fused path, no r array
+    assert pk2.tobytes() == pk.tobytes()
+
+
+def test_xcorr_segmented_long_int64(T, ctx):
+    """m ranges longer than four int32-safe quarters: the tile is cut into
+    segments that add into r."""
+    from paper_2509_19974_amd import tde
+    n = 600000
+    rng = np.random.default_rng(600)
+    u = synth.random_int_seq(rng, n, 127, 0.0)
+    v = u.copy()
+    say("xcorr segmented")
+    r = ctx.xcorr(dev(T, u), dev(T, v), 127, 127, -1500, 1500, tde.TDE_I64, tde.TDE_PATH_MFMA)
+    np.testing.assert_array_equal(r.cpu().numpy(), oracle.xcorr(u, v, -1500, 1500))
+
+
+def test_batch_segmented_pair(T, ctx):
+    say("batch segmented")
+    rng = np.random.default_rng(601)
+    n = 560000
+    x = (rng.standard_normal(n) * 3).astype(np.float32)
+    y = np.zeros(n, np.float32)
+    y[700:] = x[:-700]
+    pairs = [dict(x=x, y=y, lag_lo=-1000, lag_hi=1000, bits=8),
+             dict(x=x[:5000].copy(), y=y[:5000].copy(), lag_lo=-4999, lag_hi=4999, bits=4)]
+    pk, _ = _batch(T, ctx, pairs, 0, want_r=False)
+    for i, p in enumerate(pairs):
+        res = _check_pair(pk[i], p)
+    assert pk[0]["lag"] == 700
