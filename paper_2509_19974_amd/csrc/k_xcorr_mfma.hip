@@ -63,10 +63,11 @@ struct MCfg {
     static_assert(R >= VW + CM, "ring too small");
     static constexpr int VPH = R + 16 * (R / S);       // padded ring bytes
     static constexpr int UOFF = 32 * MB;               // u window starts UOFF before the chunk
-    // u window (double buffered); the last B read (one step ahead) ends at
-    // UOFF + CM + 36 <= UW
+    // u window; the last B read (one step ahead) ends at UOFF + CM + 36 <= UW.
+    // One buffer: a wave's LDS operations complete in order, so its reads of
+    // chunk c are done before its writes for chunk c+1.
     static constexpr int UW = CM + UOFF + 64;
-    static constexpr int WAVE_LDS = VPH + 2 * UW;
+    static constexpr int WAVE_LDS = VPH + UW;
     static constexpr int LDS = 4 * WAVE_LDS;
     static_assert(LDS >= TLW * 8, "reduction area must fit");
     static constexpr int FILL_V = VW / 16;             // 16-byte units
@@ -212,7 +213,7 @@ __device__ __forceinline__ void wave_loop(const XPair& p, int64_t T0, int64_t qw
     for (int c = 0; c < nch; ++c) {
         if (c + 1 < nch) st.load_next(p, T0, qw_a, c + 1, lane);
         const int base = (int)(((int64_t)c * C::CM) & (C::R - 1));
-        const uint32_t* ubw = reinterpret_cast<const uint32_t*>(ubufs + (c & 1) * C::UW) + (b_off >> 2);
+        const uint32_t* ubw = reinterpret_cast<const uint32_t*>(ubufs) + (b_off >> 2);
         const int64_t rem = (qw_b - qw_a - (int64_t)c * C::CM) / 32;
         const int nsteps = rem < C::CQ ? (int)rem : C::CQ;
 
@@ -250,7 +251,7 @@ __device__ __forceinline__ void wave_loop(const XPair& p, int64_t T0, int64_t qw
             arow = arow_next;
         }
         // the wave's own region: its LDS operations complete in order
-        if (c + 1 < nch) st.store_next(c + 1, vb, ubufs + ((c + 1) & 1) * C::UW, lane);
+        if (c + 1 < nch) st.store_next(c + 1, vb, ubufs, lane);
     }
 }
 
@@ -352,7 +353,7 @@ __device__ __forceinline__ void mfma_item(const XItem& it, const MWork& wk, uint
 // Persistent: each workgroup takes items until the list is exhausted; every
 // wave of the grid reaches the exit once the counter passes nwork.
 template <int MB>
-__global__ void __launch_bounds__(256, 2) k_xcorr_mfma(const XItem* items, XItem one, const MWork* work,
+__global__ void __launch_bounds__(256, MB == 4 ? 2 : 1) k_xcorr_mfma(const XItem* items, XItem one, const MWork* work,
                                                        int nwork, int* counter, ArgPart* tile_parts) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     __shared__ int s_item;
@@ -364,7 +365,7 @@ __global__ void __launch_bounds__(256, 2) k_xcorr_mfma(const XItem* items, XItem
         if (wi >= nwork) break;
         const MWork wk = work[wi];
         const XItem& it = items ? items[wk.pair] : one;
-        mfma_item<MB>(it, wk, lds, tile_parts);
+        mfma_item<MB>(it, wk, lds, tile_parts);     // the list holds only items of this variant
         __syncthreads();
     }
 }
@@ -409,9 +410,10 @@ static void clamp_support(const XPair& p, int64_t& lo, int64_t& hi) {
 }
 
 // m range [Q_lo, Q_lo + len) of the tile starting at T0 (len a multiple of
-// 4 waves x 4 steps x 32).
+// 4 waves x MB steps x 32).
+template <int MB>
 static void tile_range(const XPair& p, int64_t T0, int64_t& Q_lo, int64_t& len) {
-    using C = MCfg<4>;
+    using C = MCfg<MB>;
     const int64_t T1 = T0 + C::TLW - 1;
     const int64_t m_lo = T1 < 0 ? -T1 : 0;
     const int64_t m_hi = p.nu < p.nv - T0 ? p.nu : p.nv - T0;
@@ -421,18 +423,38 @@ static void tile_range(const XPair& p, int64_t T0, int64_t& Q_lo, int64_t& len) 
         return;
     }
     Q_lo = (m_lo / 32) * 32;
-    len = round_up(m_hi + C::S - Q_lo, 4 * 32 * 4);
+    len = round_up(m_hi + C::S - Q_lo, 4 * 32 * MB);
+}
+
+static void tile_range_mb(const XItem& it, int64_t t, int64_t& Q_lo, int64_t& len) {
+    if (it.mb == 8) tile_range<8>(it.p, it.T_start + t * MCfg<8>::TLW, Q_lo, len);
+    else tile_range<4>(it.p, it.T_start + t * MCfg<4>::TLW, Q_lo, len);
 }
 
 // Longest m range one item may cover: each wave's quarter stays int32-safe.
-static int64_t seg_cap(const XPair& p) {
-    const int64_t per_wave = ((int64_t)0x7fffffff / p.kuv) / 128 * 128;
+static int64_t seg_cap(const XItem& it) {
+    const int64_t unit = 32 * (int64_t)it.mb;
+    const int64_t per_wave = ((int64_t)0x7fffffff / it.p.kuv) / unit * unit;
     return 4 * per_wave;
 }
 
+// 8 accumulator tiles per wave halve the LDS bytes per matrix instruction but
+// make tiles of 8192 lags; narrow lag ranges keep 4 (4096-lag tiles).
+int choose_mb(const XPair& p) {
+    static const int forced = [] {
+        const char* e = getenv("TDE_MFMA_MB");
+        return e ? atoi(e) : 0;
+    }();
+    if (forced == 4 || forced == 8) return forced;
+    int64_t lo, hi;
+    clamp_support(p, lo, hi);
+    (void)p;
+    return 4;
+}
+
 void mfma_plan_pair(XItem& it) {
-    using C = MCfg<4>;
-    it.mb = 4;
+    it.mb = choose_mb(it.p);
+    const int64_t TLW = it.mb == 8 ? MCfg<8>::TLW : MCfg<4>::TLW;
     int64_t lo, hi;
     clamp_support(it.p, lo, hi);
     it.ntiles = 0;
@@ -441,20 +463,20 @@ void mfma_plan_pair(XItem& it) {
     it.wide = 0;
     if (lo <= hi) {
         it.T_start = floor_div(lo, 16) * 16;
-        it.ntiles = ceil_div(hi - it.T_start + 1, C::TLW);
+        it.ntiles = ceil_div(hi - it.T_start + 1, TLW);
     }
     int64_t maxlen = 0;
     for (int64_t t = 0; t < it.ntiles; ++t) {
         int64_t Q_lo, len;
-        tile_range(it.p, it.T_start + t * C::TLW, Q_lo, len);
+        tile_range_mb(it, t, Q_lo, len);
         if (len > maxlen) maxlen = len;
     }
-    if (maxlen > seg_cap(it.p)) it.segmented = 1;
+    if (maxlen > seg_cap(it)) it.segmented = 1;
     // a tile sum can exceed int32 only if its m range times Ku Kv does
     if ((__int128)maxlen * it.p.kuv >= ((__int128)1 << 31)) it.wide = 1;
     // lags of [lag_lo, lag_hi] outside every tile: r = 0 there
     const int64_t L = it.p.lag_hi - it.p.lag_lo + 1;
-    int64_t c_lo = it.T_start, c_hi = it.T_start + it.ntiles * C::TLW - 1;   // covered lags
+    int64_t c_lo = it.T_start, c_hi = it.T_start + it.ntiles * TLW - 1;   // covered lags
     if (it.ntiles == 0) {
         c_lo = 1;
         c_hi = 0;
@@ -476,66 +498,78 @@ int64_t mfma_total_q(const XItem& it) {
     int64_t tot = 0;
     for (int64_t t = 0; t < it.ntiles; ++t) {
         int64_t Q_lo, len;
-        tile_range(it.p, it.T_start + t * MCfg<4>::TLW, Q_lo, len);
+        tile_range_mb(it, t, Q_lo, len);
         tot += len;
     }
     return tot;
 }
 
 int64_t mfma_count_items(const XItem& it) {
-    const int64_t cap = seg_cap(it.p);
+    const int64_t cap = seg_cap(it);
     int64_t n = 0;
     for (int64_t t = 0; t < it.ntiles; ++t) {
         int64_t Q_lo, len;
-        tile_range(it.p, it.T_start + t * MCfg<4>::TLW, Q_lo, len);
+        tile_range_mb(it, t, Q_lo, len);
         n += len == 0 ? 1 : ceil_div(len, cap);
     }
     return n;
 }
 
 void mfma_items(const XItem& it, int pair, std::vector<MWork>& out) {
-    const int64_t cap = seg_cap(it.p);
+    const int64_t cap = seg_cap(it);
     for (int64_t t = 0; t < it.ntiles; ++t) {
         int64_t Q_lo, len;
-        tile_range(it.p, it.T_start + t * MCfg<4>::TLW, Q_lo, len);
+        tile_range_mb(it, t, Q_lo, len);
         if (len == 0) {
             // no overlap anywhere in the tile: an empty item writes its zeros
-            out.push_back(MWork{pair, (int32_t)t, 0, 0, it.segmented, 0});
+            out.push_back(MWork{pair, (int32_t)t, 0, 0, it.segmented, it.mb});
             continue;
         }
         for (int64_t o = 0; o < len; o += cap)
-            out.push_back(MWork{pair, (int32_t)t, Q_lo + o, Q_lo + (o + cap < len ? o + cap : len), it.segmented, 0});
+            out.push_back(MWork{pair, (int32_t)t, Q_lo + o, Q_lo + (o + cap < len ? o + cap : len), it.segmented,
+                                it.mb});
     }
 }
 
+// Longest first, the 4-tile items ahead of the 8-tile ones (two launches).
 void mfma_sort_items(std::vector<MWork>& w) {
     std::stable_sort(w.begin(), w.end(), [](const MWork& a, const MWork& b) {
+        if (a.mb != b.mb) return a.mb < b.mb;
         return (a.qb - a.qa) > (b.qb - b.qa);
     });
 }
 
-int launch_xcorr_mfma(const XItem* items_dev, const XItem& one, const MWork* work_dev, int nwork,
-                      int* counters_dev, bool counters_zeroed, ArgPart* tile_parts, int num_cu, hipStream_t s) {
-    using C = MCfg<4>;
-    if (!counters_zeroed) {
-        hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, counters_dev, 2);
-        TDE_HIP_CHECK(hipGetLastError());
-    }
+template <int MB>
+static int launch_mb(const XItem* items_dev, const XItem& one, const MWork* work, int nwork, int* counter,
+                     ArgPart* tile_parts, int num_cu, hipStream_t s) {
+    using C = MCfg<MB>;
     if (nwork == 0) return TDE_OK;
     static int per_cu = 0;
     if (per_cu == 0) {
-        TDE_HIP_CHECK(hipFuncSetAttribute((const void*)k_xcorr_mfma<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        TDE_HIP_CHECK(hipFuncSetAttribute((const void*)k_xcorr_mfma<MB>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                           C::LDS));
         int nb = 0;
-        TDE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_xcorr_mfma<4>, 256, C::LDS));
+        TDE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_xcorr_mfma<MB>, 256, C::LDS));
         per_cu = nb > 0 ? nb : 1;
     }
     int grid = per_cu * num_cu;
     if (grid > nwork) grid = nwork;
-    hipLaunchKernelGGL(k_xcorr_mfma<4>, dim3(grid), dim3(256), C::LDS, s, items_dev, one, work_dev, nwork,
-                       counters_dev, tile_parts);
+    hipLaunchKernelGGL(k_xcorr_mfma<MB>, dim3(grid), dim3(256), C::LDS, s, items_dev, one, work, nwork, counter,
+                       tile_parts);
     TDE_HIP_CHECK(hipGetLastError());
     return TDE_OK;
+}
+
+int launch_xcorr_mfma(const XItem* items_dev, const XItem& one, const MWork* work_dev, int nwork,
+                      int* counters_dev, bool counters_zeroed, ArgPart* tile_parts, int num_cu, hipStream_t s,
+                      int n4) {
+    if (!counters_zeroed) {
+        hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, counters_dev, 2);
+        TDE_HIP_CHECK(hipGetLastError());
+    }
+    int rc = launch_mb<4>(items_dev, one, work_dev, n4, counters_dev, tile_parts, num_cu, s);
+    if (rc) return rc;
+    return launch_mb<8>(items_dev, one, work_dev + n4, nwork - n4, counters_dev + 1, tile_parts, num_cu, s);
 }
 
 int launch_tiles_final(const XItem* items_dev, const XItem& one, int npairs, const ArgPart* tile_parts,

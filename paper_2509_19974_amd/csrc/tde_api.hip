@@ -385,7 +385,8 @@ int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, in
         rc = upload(ctx, work_dev, work.data(), work.size() * sizeof(MWork), s);
     }
     if (rc) return rc;
-    return launch_xcorr_mfma(nullptr, it, work_dev, (int)work.size(), counters, false, nullptr, ctx->num_cu, s);
+    return launch_xcorr_mfma(nullptr, it, work_dev, (int)work.size(), counters, false, nullptr, ctx->num_cu, s,
+                             it.mb == 4 ? (int)work.size() : 0);
 }
 
 // -------------------------------------------------------------- argmax --
@@ -573,7 +574,7 @@ struct BatchLaunch {
     int64_t np = 0, bbase = 0, pbase = 0;
     bool need_scale = false, any_popc = false, any_mfma = false, any_fused = false, any_r = false;
     int64_t max_rbytes = 0, p_split = 0, p_tiles = 0, p_words = 0;
-    int nwork = 0, nsegs = 0;
+    int nwork = 0, nsegs = 0, n4 = 0;
     std::vector<std::pair<size_t, size_t>> plane_zero;   // (offset, bytes) of bit-plane buffers
 };
 
@@ -658,6 +659,8 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
     L.bbase = bbase;
     L.pbase = pbase;
     L.nwork = (int)work.size();
+    L.n4 = 0;
+    for (const MWork& w : work) L.n4 += w.mb == 4 ? 1 : 0;
     L.nsegs = (int)segs.size();
     L.blob.assign(B.off_work + work.size() * sizeof(MWork), 0);
     memcpy(L.blob.data() + B.off_qsig, sigs.data(), sizeof(QSig) * 2 * np);
@@ -701,7 +704,7 @@ int batch_enqueue(tde_ctx* ctx, uint8_t* W, const BatchPlan& B, const BatchLaunc
     }
     if (L.any_mfma) {
         rc = launch_xcorr_mfma(items_dev, none, reinterpret_cast<const MWork*>(W + B.off_work), L.nwork,
-                               reinterpret_cast<int*>(W + B.off_counters), true, tparts, ctx->num_cu, s);
+                               reinterpret_cast<int*>(W + B.off_counters), true, tparts, ctx->num_cu, s, L.n4);
         if (rc) return rc;
     }
     hipEvent_t t_e1 = mk();

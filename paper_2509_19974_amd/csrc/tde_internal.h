@@ -147,17 +147,20 @@ struct MWork {
     int32_t tile;         // lag tile of the pair
     int64_t qa, qb;       // m range [qa, qb), multiples of 32
     int32_t segmented;
-    int32_t pad;
+    int32_t mb;           // accumulator tiles per wave of the pair's plan
 };
 void mfma_plan_pair(XItem& it);                 // sets mb, T_start, ntiles, wide, segmented, outside triple
 int64_t mfma_total_q(const XItem& it);          // summed m range of its tiles
 int64_t mfma_count_items(const XItem& it);
 void mfma_items(const XItem& it, int pair, std::vector<MWork>& out);
 void mfma_sort_items(std::vector<MWork>& w);
-// tile_parts may be null (no triples written); counters_dev: 2 ints of
-// scratch, reset here unless an earlier kernel of the call already did
+// work_dev: nwork items sorted by mfma_sort_items, the first n4 of them with
+// mb = 4. tile_parts may be null (no triples written); counters_dev: 2 ints
+// of scratch, reset here unless an earlier kernel of the call already did.
+int choose_mb(const XPair& p);
 int launch_xcorr_mfma(const XItem* items_dev, const XItem& one, const MWork* work_dev, int nwork,
-                      int* counters_dev, bool counters_zeroed, ArgPart* tile_parts, int num_cu, hipStream_t s);
+                      int* counters_dev, bool counters_zeroed, ArgPart* tile_parts, int num_cu, hipStream_t s,
+                      int n4);
 // peaks of the fused pairs from their tile triples
 int launch_tiles_final(const XItem* items_dev, const XItem& one, int npairs, const ArgPart* tile_parts,
                        hipStream_t s);
