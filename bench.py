@@ -57,6 +57,13 @@ def make_workload(name: str):
         desc = {"workload": "single pair, N=4096 white noise, sign quantization, lags [-1024, 1024]",
                 "pairs": 1, "n": 4096, "bits": [1], "lags": "[-1024, 1024]"}
         return pairs, desc
+    if name.startswith("c3_"):
+        lg = int(name[3:])
+        n = 1 << lg
+        pairs = synth.config3_long(n, npairs=8)
+        desc = {"workload": f"8 long pairs, N=2^{lg}, filtered noise, b=8, full lag range", "pairs": 8, "n": n,
+                "bits": [8], "lags": "[-(N-1), N-1]"}
+        return pairs, desc
     if name == "c1x":
         pairs = synth.config1_single(npairs=16384)
         desc = {"workload": "16384 pairs shaped like the single-pair case (N=4096, sign, lags +-1024)",
@@ -138,6 +145,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2")
+    ap.add_argument("--path", default="auto", choices=["auto", "mfma", "popc", "ntt"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fft", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -168,14 +176,16 @@ def main():
     ctx = tde.Context(0)
     specs = [dict(x=torch.from_numpy(p["x"]).cuda(), y=torch.from_numpy(p["y"]).cuda(), lag_lo=p["lag_lo"],
                   lag_hi=p["lag_hi"], bits=p["bits"]) for p in pairs]
-    plan = ctx.batch_plan(specs)
+    path = {"auto": tde.TDE_PATH_AUTO, "mfma": tde.TDE_PATH_MFMA, "popc": tde.TDE_PATH_POPC,
+            "ntt": tde.TDE_PATH_NTT}[args.path]
+    plan = ctx.batch_plan(specs, path=path)
     ws = torch.empty(plan[2], dtype=torch.uint8, device="cuda")
     out = torch.empty(len(pairs) * tde.PEAK_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
     macs = sum(alg_macs(p["x"].size, p["y"].size, p["lag_lo"], p["lag_hi"]) for p in pairs)
 
     log(f"[bench] warmup {args.warmup}")
     for _ in range(args.warmup):
-        ctx.estimate_batch(specs, ws=ws, out=out, plan=plan)
+        ctx.estimate_batch(specs, path, ws=ws, out=out, plan=plan)
     torch.cuda.synchronize()
     tde.tde_timing_read(ctx.handle)
     tde.tde_timing_enable(ctx.handle, True)
@@ -185,7 +195,7 @@ def main():
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(args.steps):
-        ctx.estimate_batch(specs, ws=ws, out=out, plan=plan, stream=stream)
+        ctx.estimate_batch(specs, path, ws=ws, out=out, plan=plan, stream=stream)
     e1.record(stream)
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)

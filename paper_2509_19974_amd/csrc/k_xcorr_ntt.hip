@@ -1,0 +1,425 @@
+// Algorithm 1, line 3 for long signals: the exact integer correlation as a
+// cyclic convolution computed with number-theoretic transforms modulo one or
+// two primes, combined by the Chinese remainder theorem (the multimodular
+// route among the exact multiplication methods of Section 3.2).
+//
+// With ur = u reversed, (ur conv v)[j] = r[j - (nu - 1)]. A cyclic
+// convolution of length n = 2^L equals the linear one at every position
+// j in [jlo, jhi] when no other position aliases onto it; the host picks
+// n > max(jhi, nu + nv - 2 - jlo). |r| <= overlap * Ku * Kv (the coefficient
+// bound of Section 3.2): one prime suffices below p1 / 2, two primes
+// (product ~ 2^61.7) cover every int8 case this library accepts.
+//
+// Transform (four-step, n = n1 x 4096, element j = b + 4096 i):
+//   K1 columns:  for each column b, a length-n1 decimation-in-frequency
+//                transform over i (output in bit-reversed order of k1),
+//                then the factor w_n^(b k1);
+//   K2 rows:     for each row (fixed k1), a length-4096 DIF transform over b
+//                of both signals, the pointwise product, and the inverse
+//                (decimation-in-time) row transform, all on chip;
+//   K3 columns:  the factor w_n^(-b k1), the inverse length-n1 transform,
+//                scaling by 1/n, CRT to a signed 64-bit value, the output r
+//                and the (max, smallest index, count) triple of the tile.
+// Arithmetic: Montgomery multiplication with R = 2^32 on residues in [0, p);
+// twiddle tables hold w^k R mod p.
+#include <algorithm>
+#include <vector>
+
+#include "tde_internal.h"
+
+namespace tde {
+
+namespace {
+
+constexpr uint32_t kP[2] = {2013265921u, 1811939329u};   // 15*2^27+1, 27*2^26+1
+constexpr uint32_t kG[2] = {31u, 13u};                    // primitive roots
+
+__device__ __forceinline__ uint32_t mont(uint32_t a, uint32_t b, uint32_t p, uint32_t pinv) {
+    const uint64_t t = (uint64_t)a * b;
+    const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
+    const uint32_t m = tlo * pinv;                 // t p^-1 mod 2^32
+    const uint32_t mh = __umulhi(m, p);            // (t - m p) / 2^32 = thi - mh exactly
+    const uint32_t r = thi - mh;
+    return thi < mh ? r + p : r;
+}
+
+__device__ __forceinline__ uint32_t addm(uint32_t a, uint32_t b, uint32_t p) {
+    const uint32_t s = a + b;
+    return s >= p ? s - p : s;
+}
+
+__device__ __forceinline__ uint32_t subm(uint32_t a, uint32_t b, uint32_t p) {
+    return a >= b ? a - b : a + p - b;
+}
+
+__device__ __forceinline__ uint32_t residue(int8_t x, uint32_t p) {
+    return x < 0 ? (uint32_t)((int32_t)p + x) : (uint32_t)x;
+}
+
+__device__ __forceinline__ uint32_t brev(uint32_t x, int bits) {
+    return bits ? __builtin_bitreverse32(x) >> (32 - bits) : 0u;
+}
+
+// table layout per prime: TC[n1] (w_n1^k), TL[4096] (w_n^k), TR[4096] (w_4096^k)
+__device__ __forceinline__ const uint32_t* tab_of(const NttGroup& g, int pr) {
+    return g.tab + (size_t)pr * (g.n1 + 2 * kNttRow);
+}
+
+// w_n^e R for e in [0, n), from the two small tables: w_n^(4096 eh) = w_n1^eh.
+__device__ __forceinline__ uint32_t twiddle_n(const uint32_t* T, int n1, uint32_t e, uint32_t p, uint32_t pinv) {
+    return mont(T[e >> 12], T[n1 + (e & 4095u)], p, pinv);
+}
+
+// ------------------------------------------------------------- tables --
+
+__global__ void k_ntt_tables(NttGroup g) {
+    const int per = g.n1 + 2 * kNttRow;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)per * g.nprimes) return;
+    const int pr = (int)(k / per);
+    const int o = (int)(k % per);
+    const uint32_t p = g.p[pr], pinv = g.pinv[pr];
+    uint64_t e;                                    // exponent of w_n
+    if (o < g.n1) e = (uint64_t)o << 12;
+    else if (o < g.n1 + kNttRow) e = (uint64_t)(o - g.n1);
+    else e = (uint64_t)(o - g.n1 - kNttRow) * (uint64_t)g.n1;
+    uint32_t acc = g.one_m[pr], base = g.root_m[pr];
+    while (e) {
+        if (e & 1) acc = mont(acc, base, p, pinv);
+        base = mont(base, base, p, pinv);
+        e >>= 1;
+    }
+    g.tab[k] = acc;
+}
+
+// ------------------------------------------------- K1: forward columns --
+// grid (4096 / kNttC1, 2 * nprimes, njobs); LDS: kNttC1 x n1 residues,
+// row-major (16 consecutive columns of a row side by side).
+
+__global__ void __launch_bounds__(1024) k_ntt_cols_fwd(NttGroup g, const NttJob* jobs) {
+    extern __shared__ uint32_t L[];
+    const NttJob& J = jobs[blockIdx.z];
+    const int side = blockIdx.y / g.nprimes;       // 0: reversed u, 1: v
+    const int pr = blockIdx.y % g.nprimes;
+    const uint32_t p = g.p[pr], pinv = g.pinv[pr];
+    const uint32_t* T = tab_of(g, pr);
+    const int n1 = g.n1, ln1 = g.log_n1;
+    const int b0 = blockIdx.x * kNttC1;
+    const int tot = kNttC1 * n1;
+    const int8_t* src = side ? J.v : J.u;
+    const int64_t nsrc = side ? J.nv : J.nu;
+    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+        const int c = idx % kNttC1, i = idx / kNttC1;
+        const int64_t j = b0 + c + ((int64_t)i << 12);
+        uint32_t val = 0;
+        if (j < nsrc) val = residue(side ? src[j] : src[nsrc - 1 - j], p);
+        L[idx] = val;
+    }
+    __syncthreads();
+    // decimation in frequency over i: half-distance h = n1/2 .. 1
+    for (int lh = ln1 - 1; lh >= 0; --lh) {
+        const int h = 1 << lh;
+        for (int bi = threadIdx.x; bi < tot / 2; bi += blockDim.x) {
+            const int c = bi % kNttC1, q = bi / kNttC1;
+            const int pos = q & (h - 1);
+            const int e = ((q >> lh) << (lh + 1)) + pos;
+            const uint32_t a = L[e * kNttC1 + c], b = L[(e + h) * kNttC1 + c];
+            L[e * kNttC1 + c] = addm(a, b, p);
+            L[(e + h) * kNttC1 + c] = mont(subm(a, b, p), T[pos << (ln1 - 1 - lh)], p, pinv);
+        }
+        __syncthreads();
+    }
+    // factor w_n^(b k1), k1 = bit-reversed row index; store the residues
+    uint32_t* out = J.res + ((size_t)side * g.nprimes + pr) * ((size_t)n1 << 12);
+    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+        const int c = idx % kNttC1, i = idx / kNttC1;
+        const uint32_t k1 = brev((uint32_t)i, ln1);
+        const uint32_t e = (uint32_t)(b0 + c) * k1;          // < 4096 n1 = n <= 2^23
+        const uint32_t w = twiddle_n(T, n1, e, p, pinv);
+        out[(size_t)b0 + c + ((size_t)i << 12)] = mont(L[idx], w, p, pinv);
+    }
+}
+
+// ---------------------------------------------------- K2: fused rows --
+// grid (n1, nprimes, njobs), 256 threads, 16 residues per thread.
+// Rounds of 4 radix-2 stages in registers with LDS exchanges between them:
+//   round A: elements t + 256 k   (h = 2048 .. 256)
+//   round B: elements 256 (t/16) + t%16 + 16 k   (h = 128 .. 16)
+//   round C: elements 16 t + k    (h = 8 .. 1)
+// LDS index b + b/16 keeps the exchanges free of bank conflicts.
+
+__device__ __forceinline__ int rpos(int round, int t, int k) {
+    if (round == 0) return t + 256 * k;
+    if (round == 1) return ((t >> 4) << 8) + (t & 15) + 16 * k;
+    return 16 * t + k;
+}
+
+__device__ __forceinline__ int lds_ix(int b) { return b + (b >> 4); }
+
+// forward DIF stages of one round; the stage's register distance is d and
+// its half-distance in the row is h = d * stride(round)
+__device__ __forceinline__ void dif_round(uint32_t* x, int round, int t, const uint32_t* TR, uint32_t p,
+                                          uint32_t pinv) {
+    const int lstride = round == 0 ? 8 : (round == 1 ? 4 : 0);
+#pragma unroll
+    for (int ld = 3; ld >= 0; --ld) {
+        const int d = 1 << ld;
+        const int lh = ld + lstride;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (k & d) continue;
+            const int pos = rpos(round, t, k) & ((2 << lh) - 1);
+            const uint32_t a = x[k], b = x[k + d];
+            x[k] = addm(a, b, p);
+            x[k + d] = mont(subm(a, b, p), TR[pos << (11 - lh)], p, pinv);
+        }
+    }
+}
+
+// inverse DIT stages of one round (h increasing), twiddles w^-pos
+__device__ __forceinline__ void dit_round(uint32_t* x, int round, int t, const uint32_t* TR, uint32_t p,
+                                          uint32_t pinv) {
+    const int lstride = round == 0 ? 8 : (round == 1 ? 4 : 0);
+#pragma unroll
+    for (int ld = 0; ld <= 3; ++ld) {
+        const int d = 1 << ld;
+        const int lh = ld + lstride;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (k & d) continue;
+            const int pos = rpos(round, t, k) & ((2 << lh) - 1);
+            const uint32_t w = TR[(kNttRow - (pos << (11 - lh))) & (kNttRow - 1)];
+            const uint32_t a = x[k], b = mont(x[k + d], w, p, pinv);
+            x[k] = addm(a, b, p);
+            x[k + d] = subm(a, b, p);
+        }
+    }
+}
+
+__device__ __forceinline__ void exchange(uint32_t* x, uint32_t* S, int from, int to, int t) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) S[lds_ix(rpos(from, t, k))] = x[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = S[lds_ix(rpos(to, t, k))];
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_ntt_rows(NttGroup g, const NttJob* jobs) {
+    __shared__ uint32_t S[kNttRow + kNttRow / 16];
+    const NttJob& J = jobs[blockIdx.z];
+    const int pr = blockIdx.y;
+    const uint32_t p = g.p[pr], pinv = g.pinv[pr];
+    const uint32_t* TR = tab_of(g, pr) + g.n1 + kNttRow;
+    const size_t n = (size_t)g.n1 << 12;
+    uint32_t* U = J.res + (size_t)pr * n + ((size_t)blockIdx.x << 12);
+    const uint32_t* V = J.res + ((size_t)g.nprimes + pr) * n + ((size_t)blockIdx.x << 12);
+    const int t = threadIdx.x;
+    uint32_t xu[16], xv[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) xu[k] = U[t + 256 * k];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) xv[k] = V[t + 256 * k];
+    dif_round(xu, 0, t, TR, p, pinv);
+    exchange(xu, S, 0, 1, t);
+    dif_round(xu, 1, t, TR, p, pinv);
+    exchange(xu, S, 1, 2, t);
+    dif_round(xu, 2, t, TR, p, pinv);
+    dif_round(xv, 0, t, TR, p, pinv);
+    exchange(xv, S, 0, 1, t);
+    dif_round(xv, 1, t, TR, p, pinv);
+    exchange(xv, S, 1, 2, t);
+    dif_round(xv, 2, t, TR, p, pinv);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) xu[k] = mont(xu[k], xv[k], p, pinv);   // carries R^-1, removed in K3
+    dit_round(xu, 2, t, TR, p, pinv);
+    exchange(xu, S, 2, 1, t);
+    dit_round(xu, 1, t, TR, p, pinv);
+    exchange(xu, S, 1, 0, t);
+    dit_round(xu, 0, t, TR, p, pinv);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) U[t + 256 * k] = xu[k];
+}
+
+// ------------------------------------------------- K3: inverse columns --
+// grid (4096 / wc3, 1, njobs); LDS: nprimes x wc3 x n1 residues.
+
+struct Tri {
+    int64_t v, i, c;
+};
+
+__device__ __forceinline__ Tri tjoin(Tri a, Tri b) {
+    if (b.v > a.v) return b;
+    if (a.v > b.v) return a;
+    return Tri{a.v, a.i < b.i ? a.i : b.i, a.c + b.c};
+}
+
+__global__ void __launch_bounds__(1024) k_ntt_cols_inv(NttGroup g, const NttJob* jobs) {
+    extern __shared__ uint32_t L[];
+    const NttJob& J = jobs[blockIdx.z];
+    const int n1 = g.n1, ln1 = g.log_n1, wc = g.wc3;
+    const int b0 = blockIdx.x * wc;
+    const int tot = wc * n1;
+    const uint32_t nmask = ((uint32_t)n1 << 12) - 1u;
+    for (int pr = 0; pr < g.nprimes; ++pr) {
+        const uint32_t p = g.p[pr], pinv = g.pinv[pr];
+        const uint32_t* T = tab_of(g, pr);
+        const uint32_t* W = J.res + (size_t)pr * ((size_t)n1 << 12);
+        uint32_t* Lp = L + pr * tot;
+        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+            const int c = idx % wc, i = idx / wc;
+            const uint32_t k1 = brev((uint32_t)i, ln1);
+            const uint32_t e = ((uint32_t)(b0 + c) * k1) & nmask;
+            const uint32_t w = twiddle_n(T, n1, (0u - e) & nmask, p, pinv);
+            Lp[idx] = mont(W[(size_t)b0 + c + ((size_t)i << 12)], w, p, pinv);
+        }
+        __syncthreads();
+        for (int lh = 0; lh < ln1; ++lh) {
+            const int h = 1 << lh;
+            for (int bi = threadIdx.x; bi < tot / 2; bi += blockDim.x) {
+                const int c = bi % wc, q = bi / wc;
+                const int pos = q & (h - 1);
+                const int e = ((q >> lh) << (lh + 1)) + pos;
+                const uint32_t w = T[(n1 - (pos << (ln1 - 1 - lh))) & (n1 - 1)];
+                const uint32_t a = Lp[e * wc + c], b = mont(Lp[(e + h) * wc + c], w, p, pinv);
+                Lp[e * wc + c] = addm(a, b, p);
+                Lp[(e + h) * wc + c] = subm(a, b, p);
+            }
+            __syncthreads();
+        }
+    }
+    // scale, CRT, outputs
+    Tri tr{INT64_MIN, INT64_MAX, 0};
+    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+        const int c = idx % wc, i = idx / wc;
+        const int64_t j = b0 + c + ((int64_t)i << 12);
+        if (j < J.jlo || j > J.jhi) continue;
+        const uint32_t a1 = mont(L[idx], g.scale_m[0], g.p[0], g.pinv[0]);
+        int64_t val;
+        if (g.nprimes == 1) {
+            val = a1 > (g.p[0] - 1) / 2 ? (int64_t)a1 - (int64_t)g.p[0] : (int64_t)a1;
+        } else {
+            const uint32_t a2 = mont(L[tot + idx], g.scale_m[1], g.p[1], g.pinv[1]);
+            const uint32_t a1r = a1 >= g.p[1] ? a1 - g.p[1] : a1;
+            const uint32_t d = subm(a2, a1r, g.p[1]);
+            const uint32_t tq = mont(d, g.crt_m, g.p[1], g.pinv[1]);       // (a2 - a1) p1^-1 mod p2
+            const uint64_t x = (uint64_t)a1 + (uint64_t)g.p[0] * tq;        // in [0, p1 p2)
+            const uint64_t M = (uint64_t)g.p[0] * g.p[1];
+            val = x > (M - 1) / 2 ? (int64_t)(x - M) : (int64_t)x;
+        }
+        const int64_t ri = j - (J.nu - 1) - J.lag_lo;
+        if (J.r) {
+            if (J.r_dtype == TDE_I32) static_cast<int32_t*>(J.r)[ri] = (int32_t)val;
+            else static_cast<int64_t*>(J.r)[ri] = val;
+        }
+        tr = tjoin(tr, Tri{val, ri, 1});
+    }
+    if (!J.parts) return;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        Tri u{__shfl_xor(tr.v, o, 64), __shfl_xor(tr.i, o, 64), __shfl_xor(tr.c, o, 64)};
+        tr = tjoin(tr, u);
+    }
+    __shared__ Tri sh[16];
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = tr;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Tri a = sh[0];
+        for (int k = 1; k < nw; ++k) a = tjoin(a, sh[k]);
+        J.parts[blockIdx.x] = ArgPart{a.v, a.i, a.c};
+    }
+}
+
+uint64_t powmod(uint64_t a, uint64_t e, uint64_t p) {
+    uint64_t r = 1 % p;
+    a %= p;
+    while (e) {
+        if (e & 1) r = (unsigned __int128)r * a % p;
+        a = (unsigned __int128)a * a % p;
+        e >>= 1;
+    }
+    return r;
+}
+
+uint32_t to_mont(uint64_t x, uint32_t p) { return (uint32_t)(((unsigned __int128)(x % p) << 32) % p); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- host --
+
+bool ntt_plan(int64_t nu, int64_t nv, int kuv, int64_t lag_lo, int64_t lag_hi, NttPlan& P) {
+    // positions j = tau + nu - 1 of the lags inside the support
+    const int64_t lo = std::max<int64_t>(lag_lo, -(nu - 1));
+    const int64_t hi = std::min<int64_t>(lag_hi, nv - 1);
+    P.jlo = lo + nu - 1;
+    P.jhi = hi + nu - 1;
+    int64_t need = 1;
+    if (P.jlo <= P.jhi) need = std::max<int64_t>(P.jhi + 1, nu + nv - 1 - P.jlo);
+    int L = kNttMinLog;
+    while (L < kNttMaxLog && ((int64_t)1 << L) < need) ++L;
+    if (((int64_t)1 << L) < need) return false;
+    P.log_n = L;
+    // one prime while every |r| < p1 / 2
+    const int64_t ov = std::min(nu, nv);
+    P.nprimes = ((__int128)ov * kuv < (__int128)(kP[0] / 2)) ? 1 : 2;
+    const int n1 = 1 << (L - 12);
+    P.wc3 = std::min(kNttC1, (int)(32768 / (P.nprimes * n1)));
+    P.ntiles = kNttRow / P.wc3;
+    return true;
+}
+
+size_t ntt_tab_words(const NttPlan& P) { return (size_t)P.nprimes * ((1u << (P.log_n - 12)) + 2 * kNttRow); }
+
+size_t ntt_res_bytes(const NttPlan& P) { return (size_t)2 * P.nprimes * ((size_t)4 << P.log_n); }
+
+NttGroup ntt_group(const NttPlan& P, uint32_t* tab) {
+    NttGroup g{};
+    g.tab = tab;
+    g.log_n = P.log_n;
+    g.log_n1 = P.log_n - 12;
+    g.n1 = 1 << g.log_n1;
+    g.nprimes = P.nprimes;
+    g.wc3 = P.wc3;
+    const uint64_t n = (uint64_t)1 << P.log_n;
+    for (int pr = 0; pr < 2; ++pr) {
+        const uint32_t p = kP[pr];
+        uint32_t inv = 1;                                  // p^-1 mod 2^32 by Newton steps
+        for (int k = 0; k < 5; ++k) inv *= 2u - p * inv;
+        g.p[pr] = p;
+        g.pinv[pr] = inv;
+        g.one_m[pr] = to_mont(1, p);
+        g.root_m[pr] = to_mont(powmod(kG[pr], (p - 1) / n, p), p);
+        // n^-1 R, in Montgomery form: removes the R^-1 of the pointwise product
+        const uint64_t ninv = powmod(n, p - 2, p);
+        g.scale_m[pr] = to_mont((unsigned __int128)ninv * (((uint64_t)1 << 32) % p) % p, p);
+    }
+    g.crt_m = to_mont(powmod(kP[0] % kP[1], kP[1] - 2, kP[1]), kP[1]);
+    return g;
+}
+
+int launch_ntt(const NttGroup& g, const NttJob* jobs_dev, int njobs, hipStream_t s) {
+    if (njobs == 0) return TDE_OK;
+    const int per = (g.n1 + 2 * kNttRow) * g.nprimes;
+    hipLaunchKernelGGL(k_ntt_tables, dim3(ceil_div(per, 256)), dim3(256), 0, s, g);
+    TDE_HIP_CHECK(hipGetLastError());
+    static bool attr = false;
+    if (!attr) {
+        TDE_HIP_CHECK(hipFuncSetAttribute((const void*)k_ntt_cols_fwd, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          kNttC1 * 2048 * 4));
+        TDE_HIP_CHECK(hipFuncSetAttribute((const void*)k_ntt_cols_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          32768 * 4));
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_ntt_cols_fwd, dim3(kNttRow / kNttC1, 2 * g.nprimes, njobs), dim3(1024),
+                       kNttC1 * g.n1 * 4, s, g, jobs_dev);
+    TDE_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_ntt_rows, dim3(g.n1, g.nprimes, njobs), dim3(256), 0, s, g, jobs_dev);
+    TDE_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_ntt_cols_inv, dim3(kNttRow / g.wc3, 1, njobs), dim3(1024), g.nprimes * g.wc3 * g.n1 * 4, s,
+                       g, jobs_dev);
+    TDE_HIP_CHECK(hipGetLastError());
+    return TDE_OK;
+}
+
+}  // namespace tde

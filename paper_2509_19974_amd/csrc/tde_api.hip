@@ -308,7 +308,11 @@ static int check_xcorr(const int8_t* u, int64_t nu, const int8_t* v, int64_t nv,
     if (path < TDE_PATH_AUTO || path > TDE_PATH_NTT) return set_error(TDE_ERR_ARG, "%s: bad path", who);
     if (path == TDE_PATH_POPC && (kmax_u != 1 || kmax_v != 1))
         return set_error(TDE_ERR_ARG, "%s: the bit-plane engine needs ternary codes (kmax 1)", who);
-    if (path == TDE_PATH_NTT) return set_error(TDE_ERR_UNSUPPORTED, "%s: NTT engine not available", who);
+    if (path == TDE_PATH_NTT) {
+        NttPlan P;
+        if (!ntt_plan(nu, nv, kmax_u * kmax_v, lag_lo, lag_hi, P))
+            return set_error(TDE_ERR_UNSUPPORTED, "%s: transform longer than 2^%d", who, kNttMaxLog);
+    }
     if (r_dtype == TDE_I32) {
         const int64_t ov = max_overlap(nu, nv, lag_lo, lag_hi);
         if ((__int128)ov * kmax_u * kmax_v >= ((__int128)1 << 31))
@@ -329,6 +333,11 @@ size_t tde_xcorr_workspace_size(int64_t nu, int64_t nv, int kmax_u, int kmax_v, 
     it.p.kuv = kmax_u * kmax_v;
     int eng = choose_path(path, it.p.kuv);
     if (eng == TDE_PATH_POPC) return popc_ws_bytes(it.p);
+    if (eng == TDE_PATH_NTT) {
+        NttPlan P;
+        if (!ntt_plan(nu, nv, it.p.kuv, lag_lo, lag_hi, P)) return 0;
+        return align_bytes(sizeof(NttJob)) + align_bytes(ntt_tab_words(P) * 4) + align_bytes(ntt_res_bytes(P));
+    }
     mfma_plan_pair(it);
     return align_bytes((size_t)mfma_count_items(it) * sizeof(MWork)) + align_bytes(2 * sizeof(int));
 }
@@ -371,6 +380,33 @@ int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, in
         rc = launch_popc_pack(nullptr, it, 1, std::max(it.nuw, it.nvw), s);
         if (rc) return rc;
         return launch_xcorr_popc(nullptr, it, 1, it.nsplit, it.ntiles, s);
+    }
+    if (eng == TDE_PATH_NTT) {
+        NttPlan P;
+        ntt_plan(nu, nv, it.p.kuv, lag_lo, lag_hi, P);
+        Carve cv(ws);
+        NttJob* job_dev = static_cast<NttJob*>(cv.take(sizeof(NttJob)));
+        uint32_t* tab = static_cast<uint32_t*>(cv.take(ntt_tab_words(P) * 4));
+        NttJob job{};
+        job.u = u;
+        job.v = v;
+        job.nu = nu;
+        job.nv = nv;
+        job.lag_lo = lag_lo;
+        job.jlo = P.jlo;
+        job.jhi = P.jhi;
+        job.r = r;
+        job.r_dtype = r_dtype;
+        job.res = static_cast<uint32_t*>(cv.take(ntt_res_bytes(P)));
+        job.parts = nullptr;
+        {
+            std::lock_guard<std::mutex> lock(ctx->mu);
+            drop_graphs_on(ctx, ws, ws_bytes);
+            rc = upload(ctx, job_dev, &job, sizeof(job), s);
+        }
+        if (rc) return rc;
+        if (P.jlo > P.jhi) return TDE_OK;          // every requested lag is outside the support
+        return launch_ntt(ntt_group(P, tab), job_dev, 1, s);
     }
     mfma_plan_pair(it);
     std::vector<MWork> work;
@@ -456,8 +492,13 @@ int validate_pairs(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
         }
         if (path == TDE_PATH_POPC && q.bits > 2)
             return set_error(TDE_ERR_ARG, "pair %lld: the bit-plane engine needs ternary codes", (long long)i);
-        if (path == TDE_PATH_NTT)
-            return set_error(TDE_ERR_UNSUPPORTED, "tde_estimate_batch: NTT engine not available");
+        if (path == TDE_PATH_NTT) {
+            const int K = kmax_of_bits(q.bits);
+            NttPlan P;
+            if (!ntt_plan(q.nx, q.ny, K * K, q.lag_lo, q.lag_hi, P))
+                return set_error(TDE_ERR_UNSUPPORTED, "pair %lld: transform longer than 2^%d", (long long)i,
+                                 kNttMaxLog);
+        }
     }
     return TDE_OK;
 }
@@ -469,7 +510,24 @@ struct PairPlan {
     bool fused;         // argmax from tile triples, no r array
     bool need_r;        // r materialized (requested or needed by the argmax kernel)
     XItem probe;        // MFMA plan of the pair (sizes only)
+    NttPlan ntt;        // NTT plan (engine NTT)
 };
+
+// Triple (value 0) of the lags of [lo, hi] outside the covered run [c_lo, c_hi].
+void outside_triple(int64_t lo, int64_t hi, int64_t c_lo, int64_t c_hi, XItem& it) {
+    const int64_t L = hi - lo + 1;
+    c_lo = std::max(c_lo, lo);
+    c_hi = std::min(c_hi, hi);
+    const int64_t covered = c_hi >= c_lo ? c_hi - c_lo + 1 : 0;
+    it.out_c = L - covered;
+    if (it.out_c == 0) {
+        it.out_v = INT64_MIN;
+        it.out_i = INT64_MAX;
+    } else {
+        it.out_v = 0;
+        it.out_i = (covered == 0 || c_lo > lo) ? 0 : (c_hi + 1 - lo);
+    }
+}
 
 PairPlan plan_pair(const tde_pair& q, int path) {
     PairPlan pp{};
@@ -486,6 +544,11 @@ PairPlan plan_pair(const tde_pair& q, int path) {
     if (pp.eng == TDE_PATH_MFMA) {
         mfma_plan_pair(pp.probe);
         pp.fused = !pp.probe.segmented;
+    } else if (pp.eng == TDE_PATH_NTT) {
+        ntt_plan(q.nx, q.ny, K * K, q.lag_lo, q.lag_hi, pp.ntt);
+        pp.fused = true;
+        pp.probe.ntiles = pp.ntt.jlo <= pp.ntt.jhi ? pp.ntt.ntiles : 0;
+        outside_triple(q.lag_lo, q.lag_hi, pp.ntt.jlo - (q.nx - 1), pp.ntt.jhi - (q.nx - 1), pp.probe);
     } else {
         pp.fused = false;
     }
@@ -496,8 +559,17 @@ PairPlan plan_pair(const tde_pair& q, int path) {
 struct BatchPlan {
     size_t total = 0;
     // offsets inside the workspace; [0, off_stats) is uploaded from the host
-    size_t off_qsig, off_items, off_segs, off_work, off_counters, off_tparts, off_stats, off_inv, off_parts;
-    int64_t nwork = 0, ntparts = 0, nsegs = 0, total_parts = 0;
+    size_t off_qsig, off_items, off_segs, off_jobs, off_work, off_counters, off_tparts, off_stats, off_inv,
+        off_parts;
+    int64_t nwork = 0, ntparts = 0, nsegs = 0, total_parts = 0, njobs = 0;
+    // NTT launch groups: pairs with the same transform length and prime count
+    struct NGroup {
+        int log_n, nprimes;
+        std::vector<int64_t> pairs;
+        size_t off_tab;
+    };
+    std::vector<NGroup> ngroups;
+    std::vector<size_t> off_res;    // per pair (NTT residues)
     std::vector<PairPlan> pp;
     std::vector<size_t> off_q;      // per signal (2 per pair)
     std::vector<size_t> off_gsum;   // per signal
@@ -522,6 +594,18 @@ BatchPlan plan_batch(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
             B.nwork += mfma_count_items(pp.probe);
             if (pp.fused) B.ntparts += pp.probe.ntiles;
         }
+        if (pp.eng == TDE_PATH_NTT && pp.probe.ntiles > 0) {
+            B.ntparts += pp.probe.ntiles;
+            B.njobs += 1;
+            auto g = std::find_if(B.ngroups.begin(), B.ngroups.end(), [&](const BatchPlan::NGroup& x) {
+                return x.log_n == pp.ntt.log_n && x.nprimes == pp.ntt.nprimes;
+            });
+            if (g == B.ngroups.end()) {
+                B.ngroups.push_back({pp.ntt.log_n, pp.ntt.nprimes, {}, 0});
+                g = B.ngroups.end() - 1;
+            }
+            g->pairs.push_back(i);
+        }
         if (!pp.fused) {
             B.nsegs += 1;
             B.total_parts += ceil_div(pairs[i].lag_hi - pairs[i].lag_lo + 1, kArgChunk);
@@ -530,6 +614,7 @@ BatchPlan plan_batch(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
     B.off_qsig = take(sizeof(QSig) * 2 * np);
     B.off_items = take(sizeof(XItem) * np);
     B.off_segs = take(sizeof(ArgSeg) * (B.nsegs ? B.nsegs : 1));
+    B.off_jobs = take(sizeof(NttJob) * (B.njobs ? B.njobs : 1));
     B.off_work = take(sizeof(MWork) * (B.nwork ? B.nwork : 1));
     B.off_counters = take(2 * sizeof(int));
     B.off_tparts = take(sizeof(ArgPart) * (B.ntparts ? B.ntparts : 1));
@@ -540,6 +625,13 @@ BatchPlan plan_batch(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
     B.off_gsum.resize(2 * np);
     B.off_r.assign(np, 0);
     B.off_planes.assign(np, 0);
+    B.off_res.assign(np, 0);
+    for (auto& g : B.ngroups) {
+        NttPlan P{};
+        P.log_n = g.log_n;
+        P.nprimes = g.nprimes;
+        g.off_tab = take(ntt_tab_words(P) * 4);
+    }
     for (int64_t i = 0; i < np; ++i) {
         const tde_pair& q = pairs[i];
         const PairPlan& pp = B.pp[i];
@@ -550,6 +642,7 @@ BatchPlan plan_batch(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
         const int64_t L = q.lag_hi - q.lag_lo + 1;
         if (pp.need_r && !q.r_out) B.off_r[i] = take((size_t)L * (pp.rdt == TDE_I32 ? 4 : 8));
         if (pp.eng == TDE_PATH_POPC) B.off_planes[i] = take(popc_ws_bytes(pp.probe.p));
+        if (pp.eng == TDE_PATH_NTT && pp.probe.ntiles > 0) B.off_res[i] = take(ntt_res_bytes(pp.ntt));
     }
     B.total = off;
     return B;
@@ -575,6 +668,8 @@ struct BatchLaunch {
     bool need_scale = false, any_popc = false, any_mfma = false, any_fused = false, any_r = false;
     int64_t max_rbytes = 0, p_split = 0, p_tiles = 0, p_words = 0;
     int nwork = 0, nsegs = 0, n4 = 0;
+    std::vector<std::pair<NttGroup, int64_t>> ngroups;   // (group, first job index)
+    std::vector<int> ngroup_jobs;
     std::vector<std::pair<size_t, size_t>> plane_zero;   // (offset, bytes) of bit-plane buffers
 };
 
@@ -630,6 +725,10 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
                 L.any_fused = true;
             }
             mfma_items(it, (int)i, work);
+        } else if (pp.eng == TDE_PATH_NTT) {
+            it.part_base = tbase;
+            tbase += it.ntiles;
+            L.any_fused = true;
         } else {
             popc_plan(it, W + B.off_planes[i]);
             L.p_split = std::max(L.p_split, it.nsplit);
@@ -655,6 +754,34 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
             segs.push_back(sg);
         }
     }
+    // NTT jobs, grouped by transform length and prime count
+    std::vector<NttJob> jobs;
+    for (const auto& g : B.ngroups) {
+        NttPlan P{};
+        P.log_n = g.log_n;
+        P.nprimes = g.nprimes;
+        P.wc3 = B.pp[g.pairs[0]].ntt.wc3;
+        L.ngroups.push_back({ntt_group(P, reinterpret_cast<uint32_t*>(W + g.off_tab)), (int64_t)jobs.size()});
+        L.ngroup_jobs.push_back((int)g.pairs.size());
+        for (int64_t i : g.pairs) {
+            const tde_pair& q = pairs[i];
+            const PairPlan& pp = B.pp[i];
+            const XItem& it = items[i];
+            NttJob J{};
+            J.u = it.p.u;
+            J.v = it.p.v;
+            J.nu = q.nx;
+            J.nv = q.ny;
+            J.lag_lo = q.lag_lo;
+            J.jlo = pp.ntt.jlo;
+            J.jhi = pp.ntt.jhi;
+            J.r = it.p.r;
+            J.r_dtype = it.p.r_dtype;
+            J.res = reinterpret_cast<uint32_t*>(W + B.off_res[i]);
+            J.parts = reinterpret_cast<ArgPart*>(W + B.off_tparts) + it.part_base;
+            jobs.push_back(J);
+        }
+    }
     mfma_sort_items(work);
     L.bbase = bbase;
     L.pbase = pbase;
@@ -667,6 +794,7 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
     memcpy(L.blob.data() + B.off_items, items.data(), sizeof(XItem) * np);
     if (!segs.empty()) memcpy(L.blob.data() + B.off_segs, segs.data(), sizeof(ArgSeg) * segs.size());
     if (!work.empty()) memcpy(L.blob.data() + B.off_work, work.data(), work.size() * sizeof(MWork));
+    if (!jobs.empty()) memcpy(L.blob.data() + B.off_jobs, jobs.data(), jobs.size() * sizeof(NttJob));
 }
 
 // Queues the kernels of a prepared batch on s (the descriptors are already in
@@ -700,6 +828,11 @@ int batch_enqueue(tde_ctx* ctx, uint8_t* W, const BatchPlan& B, const BatchLaunc
         rc = launch_popc_pack(items_dev, none, (int)L.np, L.p_words, s);
         if (rc) return rc;
         rc = launch_xcorr_popc(items_dev, none, (int)L.np, L.p_split, L.p_tiles, s);
+        if (rc) return rc;
+    }
+    for (size_t k = 0; k < L.ngroups.size(); ++k) {
+        rc = launch_ntt(L.ngroups[k].first, reinterpret_cast<const NttJob*>(W + B.off_jobs) + L.ngroups[k].second,
+                        L.ngroup_jobs[k], s);
         if (rc) return rc;
     }
     if (L.any_mfma) {

@@ -176,4 +176,44 @@ int launch_xcorr_popc(const XItem* items_dev, const XItem& one, int nitems, int6
 // int8 copy helper
 int launch_copy_bytes(void* dst, const void* src, size_t n, hipStream_t s);
 
+// ----------------------------------------------------------------- NTT --
+// Number-theoretic-transform engine (two primes + CRT), for long signals.
+constexpr int kNttRow = 4096;      // row length of the four-step split
+constexpr int kNttC1 = 16;         // columns per forward-column workgroup
+constexpr int kNttMinLog = 13, kNttMaxLog = 23;
+
+struct NttPlan {
+    int log_n;            // transform length n = 2^log_n
+    int nprimes;          // 1 or 2
+    int64_t jlo, jhi;     // positions j = tau + nu - 1 computed (empty if jlo > jhi)
+    int wc3;              // columns per inverse-column workgroup
+    int ntiles;           // inverse-column workgroups = argmax triples
+};
+
+struct NttGroup {         // passed by value: everything shared by a launch
+    uint32_t* tab;        // twiddle tables (device), nprimes x (n1 + 8192) words
+    int log_n, log_n1, n1, nprimes, wc3;
+    uint32_t p[2], pinv[2], one_m[2], root_m[2], scale_m[2], crt_m;
+};
+
+struct NttJob {           // one pair (device descriptor)
+    const int8_t* u;
+    const int8_t* v;
+    int64_t nu, nv, lag_lo;
+    int64_t jlo, jhi;
+    void* r;              // may be null
+    int32_t r_dtype;
+    int32_t pad;
+    uint32_t* res;        // 2 x nprimes x n residues
+    ArgPart* parts;       // ntiles triples, or null
+};
+
+// false when the transform would exceed 2^kNttMaxLog
+bool ntt_plan(int64_t nu, int64_t nv, int kuv, int64_t lag_lo, int64_t lag_hi, NttPlan& P);
+size_t ntt_tab_words(const NttPlan& P);
+size_t ntt_res_bytes(const NttPlan& P);
+NttGroup ntt_group(const NttPlan& P, uint32_t* tab);
+// All jobs share the group's n and prime count.
+int launch_ntt(const NttGroup& g, const NttJob* jobs_dev, int njobs, hipStream_t s);
+
 }  // namespace tde

@@ -53,6 +53,11 @@ def test_workspace_sizes():
     assert tde.tde_xcorr_workspace_size(4096, 4096, 7, 7, -1024, 1024, tde.TDE_PATH_MFMA) > 0
     assert tde.tde_xcorr_workspace_size(1 << 20, 1 << 20, 127, 127, -(1 << 20) + 1, (1 << 20) - 1,
                                         tde.TDE_PATH_MFMA) >= 24 * ((1 << 21) // 2048)
+    # transform engine: two primes x two signals x n residues (n = 2^22 for N = 2^21 full range)
+    n21 = 1 << 21
+    assert tde.tde_xcorr_workspace_size(n21, n21, 127, 127, -(n21 - 1), n21 - 1, tde.TDE_PATH_NTT) >= 16 * (1 << 22)
+    # b <= 4 codes fit one prime: half the residues
+    assert tde.tde_xcorr_workspace_size(n21, n21, 7, 7, -(n21 - 1), n21 - 1, tde.TDE_PATH_NTT) < 16 * (1 << 22)
 
 
 FAKE = 0x10000   # never dereferenced: validation returns first
@@ -76,6 +81,10 @@ def test_xcorr_argument_validation():
     assert _xcorr_status(dt=7) == tde.TDE_ERR_ARG
     assert _xcorr_status(r=FAKE + 2, dt=tde.TDE_I32) == tde.TDE_ERR_ARG
     assert _xcorr_status(path=tde.TDE_PATH_POPC, ku=2) == tde.TDE_ERR_ARG
+    # the transform engine stops at n = 2^23: nu + nv - 1 = 2^23 fits, 2^23 + 1 does not
+    n22 = 1 << 22
+    assert _xcorr_status(path=tde.TDE_PATH_NTT, nu=n22, nv=n22, lo=-(n22 - 1), hi=n22 - 1) == tde.TDE_ERR_ARG
+    assert _xcorr_status(path=tde.TDE_PATH_NTT, nu=n22 + 2, nv=n22, lo=-(n22 + 1), hi=n22 - 1) == tde.TDE_ERR_UNSUPPORTED
     # int32 bound of Section 3.2: overlap * Ku * Kv must stay below 2^31
     assert _xcorr_status(nu=200000, nv=200000, ku=127, kv=127, dt=tde.TDE_I32) == tde.TDE_ERR_RANGE
     # 133145 * 127^2 = 2147495705 >= 2^31; 133144 * 127^2 = 2147479576 < 2^31

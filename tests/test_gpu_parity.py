@@ -157,6 +157,38 @@ def test_xcorr_popc_parity(T, ctx, case):
     _run_xcorr(T, ctx, tde.TDE_PATH_POPC, nu, nv, lo, hi, 1, tde.TDE_I32)
 
 
+@pytest.mark.parametrize("case", XCASES)
+def test_xcorr_ntt_parity(T, ctx, case):
+    from paper_2509_19974_amd import tde
+    nu, nv, lo, hi, k = case
+    _run_xcorr(T, ctx, tde.TDE_PATH_NTT, nu, nv, lo, hi, k, tde.TDE_I64)
+
+
+@pytest.mark.parametrize("case", [c for c in XCASES if c[4] * c[4] * min(c[0], c[1]) < 2 ** 31][::2])
+def test_xcorr_ntt_parity_i32(T, ctx, case):
+    from paper_2509_19974_amd import tde
+    nu, nv, lo, hi, k = case
+    _run_xcorr(T, ctx, tde.TDE_PATH_NTT, nu, nv, lo, hi, k, tde.TDE_I32)
+
+
+@pytest.mark.parametrize("n", [4095, 4096, 8193, 131072])
+def test_xcorr_ntt_transform_lengths(T, ctx, n):
+    """Full range at lengths around the transform sizes (the plan takes the
+    smallest power of two that leaves no alias), extreme codes (two primes)
+    and small codes (one prime)."""
+    from paper_2509_19974_amd import tde
+    rng = np.random.default_rng(n)
+    for k in (127, 3):
+        u = synth.random_int_seq(rng, n, k, 0.1)
+        v = synth.random_int_seq(rng, n + 17, k, 0.1)
+        if k == 127:
+            u[: n // 3] = 127
+            v[: n // 3] = 127
+        say(f"xcorr ntt n={n} k={k}")
+        r = ctx.xcorr(dev(T, u), dev(T, v), k, k, -(n - 1), n + 16, tde.TDE_I64, tde.TDE_PATH_NTT)
+        np.testing.assert_array_equal(r.cpu().numpy(), oracle.xcorr(u, v, -(n - 1), n + 16))
+
+
 def test_xcorr_unaligned_inputs(T, ctx):
     from paper_2509_19974_amd import tde
     rng = np.random.default_rng(77)
@@ -227,7 +259,7 @@ def _check_pair(pk, p, r_gpu=None):
     return res
 
 
-@pytest.mark.parametrize("path", [0, 1, 2])
+@pytest.mark.parametrize("path", [0, 1, 2, 3])
 def test_batch_config1_single_pair(T, ctx, path):
     say(f"batch c1 path={path}")
     pairs = synth.config1_single(npairs=4)
@@ -246,10 +278,23 @@ def test_batch_config2_small(T, ctx, bits):
         _check_pair(pk[i], p, specs[i]["r_out"].cpu().numpy())
 
 
-def test_batch_mixed_lengths_bits_and_ranges(T, ctx):
-    say("batch mixed")
+@pytest.mark.parametrize("path", [0, 3])
+def test_batch_mixed_lengths_bits_and_ranges(T, ctx, path):
+    say(f"batch mixed path={path}")
     pairs = synth.config4_uneven(npairs=24, nmin_log2=6, nmax_log2=13)
-    pk, specs = _batch(T, ctx, pairs, 0, want_r=True)
+    pk, specs = _batch(T, ctx, pairs, path, want_r=True)
+    for i, p in enumerate(pairs):
+        _check_pair(pk[i], p, specs[i]["r_out"].cpu().numpy())
+    pk2, _ = _batch(T, ctx, pairs, path, want_r=False)        # fused argmax, no r array
+    assert pk2.tobytes() == pk.tobytes()
+
+
+@pytest.mark.parametrize("bits", [4, 8])
+def test_batch_ntt_config2_small(T, ctx, bits):
+    """One prime (b = 4) and two primes with CRT (b = 8)."""
+    say(f"batch ntt c2-small bits={bits}")
+    pairs = synth.config2_batch(bits, npairs=5, n=40000)
+    pk, specs = _batch(T, ctx, pairs, 3, want_r=True)
     for i, p in enumerate(pairs):
         _check_pair(pk[i], p, specs[i]["r_out"].cpu().numpy())
 
@@ -352,3 +397,41 @@ def test_batch_segmented_pair(T, ctx):
     for i, p in enumerate(pairs):
         res = _check_pair(pk[i], p)
     assert pk[0]["lag"] == 700
+
+
+# ---------------------------------------------------------- long signals --
+
+@pytest.mark.parametrize("log_n,npairs", [(20, 2), (22, 1)])
+def test_batch_ntt_long_signals(T, ctx, log_n, npairs):
+    """Long-signal workload (N = 2^20 and 2^22, b = 8, full lag range of
+    2N - 1 lags, the two-prime transform with CRT to int64) in the batch
+    call's launch configuration. The oracle cannot sum 2^44 products per
+    pair directly, so r is checked over every lag against the certified
+    float64 FFT route (exact after rounding, its error bound asserted below
+    1/2), and at sampled lags (every 4099th, the ends, and +-64 around both
+    the GPU's argmax and the true delay) against direct int64 sums; the peak
+    must be the oracle argmax of that r."""
+    from paper_2509_19974_amd import tde
+    n = 1 << log_n
+    pairs = synth.config3_long(n, npairs=npairs)
+    say(f"batch ntt long N=2^{log_n} pairs={npairs}")
+    pk, specs = _batch(T, ctx, pairs, tde.TDE_PATH_NTT, want_r=True)
+    for i, p in enumerate(pairs):
+        r_gpu = specs[i]["r_out"].cpu().numpy()
+        u, _, _ = oracle.quantize(p["x"], 8)
+        v, _, _ = oracle.quantize(p["y"], 8)
+        lo, hi = p["lag_lo"], p["lag_hi"]
+        lag = int(pk[i]["lag"])
+        sample = np.unique(np.concatenate([
+            np.arange(lo, hi + 1, 4099), [lo, hi],
+            np.clip(np.arange(lag - 64, lag + 65), lo, hi),
+            np.clip(np.arange(p["d"] - 64, p["d"] + 65), lo, hi)])).astype(np.int64)
+        r_ref = oracle.xcorr_long_certified(u, v, lo, hi, check_lags=sample)
+        np.testing.assert_array_equal(r_gpu[sample - lo], oracle.xcorr_at(u, v, sample))
+        np.testing.assert_array_equal(r_gpu, r_ref)
+        assert int(r_gpu.sum()) == int(u.astype(np.int64).sum()) * int(v.astype(np.int64).sum())
+        olag, ormax, ont = oracle.argmax(r_ref, lo)
+        assert (pk[i]["lag"], pk[i]["rmax"], pk[i]["n_ties"]) == (olag, ormax, ont)
+        assert olag == p["d"]                      # noiseless shift: the true delay
+    pk2, _ = _batch(T, ctx, pairs, tde.TDE_PATH_NTT, want_r=False)
+    assert pk2.tobytes() == pk.tobytes()
