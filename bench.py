@@ -3,7 +3,12 @@
 
 One step = one call of tde_estimate_batch over the whole batch (Algorithm 1,
 lines 1-4 for every pair: scale + quantize, exact integer correlation over the
-full lag range, argmax), with the float32 inputs already resident in HBM.
+full lag range, argmax), with the float32 inputs already resident in HBM. By
+default the call is replayed from its captured HIP graph (use_graph = 1: the
+descriptors stay in the workspace, so a step is only kernel launches);
+--eager times plain calls (descriptor upload + launches). Stage times (and the
+roofline's kernel time) come from an eager pass with the library's stage
+events, recorded on the stream the kernels run on.
 
 Default workload: 64 pairs of N = 65536 float32 AR(2) coloured noise (poles
 0.95, 0.6), delays uniform in [-N/4, N/4], SNR uniform in [0, 30] dB, uniform
@@ -29,6 +34,10 @@ sys.path.insert(0, ROOT)
 
 INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 matrix peak, 5.0 POP/s
 HBM_PEAK_GBS = 8000.0
+# 256 CUs x 16 lanes/clock of 32-bit integer multiply (a quarter of the 64
+# lanes/clock of simple VALU ops) x 2.4 GHz, 4 multiplies per Montgomery
+# butterfly: 2.46e12 butterflies/s
+MODMUL_PEAK_T = 256 * 16 * 2.4e9 / 4 / 1e12
 
 
 def log(*a):
@@ -64,6 +73,11 @@ def make_workload(name: str):
         desc = {"workload": f"8 long pairs, N=2^{lg}, filtered noise, b=8, full lag range", "pairs": 8, "n": n,
                 "bits": [8], "lags": "[-(N-1), N-1]"}
         return pairs, desc
+    if name == "c4":
+        pairs = synth.config4_uneven(4096)
+        desc = {"workload": "4096 uneven pairs, N log-uniform in [2^10, 2^18], b in {1,2,4}, lags +-N/4",
+                "pairs": 4096, "n": "2^U[10,18]", "bits": [1, 2, 4], "lags": "+-floor(N/4)"}
+        return pairs, desc
     if name == "c1x":
         pairs = synth.config1_single(npairs=16384)
         desc = {"workload": "16384 pairs shaped like the single-pair case (N=4096, sign, lags +-1024)",
@@ -88,22 +102,43 @@ def traffic_from_profile(kernel_src: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def fft_baseline(torch, xs, ys, lo, hi, steps, warmup):
+def fft_baseline(torch, pairs, specs, steps, warmup):
     """FP32 FFT cross-correlation r = irfft(conj(X) Y) of the float signals,
-    argmax over [lo, hi] (first maximum = smallest lag)."""
-    B, N = xs.shape
-    nfft = 1
-    while nfft < 2 * N - 1:
-        nfft *= 2
+    argmax over each pair's lags (first maximum = smallest lag). Pairs are
+    batched by transform length (a power of two covering the pair's lags
+    without wrap-around), zero-padded to the longest signal of their batch."""
+    groups = {}
+    for i, p in enumerate(pairs):
+        nx, ny = p["x"].size, p["y"].size
+        need = max(p["lag_hi"] + nx, ny - p["lag_lo"])
+        nfft = 1
+        while nfft < need:
+            nfft *= 2
+        groups.setdefault(nfft, []).append(i)
+    plans = []
+    for nfft, idx in groups.items():
+        nmax = max(max(pairs[i]["x"].size, pairs[i]["y"].size) for i in idx)
+        xs = torch.zeros(len(idx), nmax, device="cuda")
+        ys = torch.zeros(len(idx), nmax, device="cuda")
+        for k, i in enumerate(idx):
+            xs[k, :pairs[i]["x"].size] = specs[i]["x"]
+            ys[k, :pairs[i]["y"].size] = specs[i]["y"]
+        lo = torch.tensor([pairs[i]["lag_lo"] for i in idx], device="cuda")
+        L = max(pairs[i]["lag_hi"] - pairs[i]["lag_lo"] + 1 for i in idx)
+        off = torch.arange(L, device="cuda")[None, :]
+        valid = off <= torch.tensor([pairs[i]["lag_hi"] - pairs[i]["lag_lo"] for i in idx], device="cuda")[:, None]
+        pos = (lo[:, None] + off) % nfft              # circular index of lag tau
+        plans.append((nfft, idx, xs, ys, lo, pos, valid))
 
     def step():
-        X = torch.fft.rfft(xs, n=nfft)
-        Y = torch.fft.rfft(ys, n=nfft)
-        c = torch.fft.irfft(torch.conj(X) * Y, n=nfft)
-        neg = c[:, nfft + lo:] if lo < 0 else c[:, :0]
-        pos = c[:, max(lo, 0):hi + 1]
-        full = torch.cat([neg, pos], dim=1)
-        return torch.argmax(full, dim=1) + lo
+        outs = []
+        for nfft, idx, xs, ys, lo, pos, valid in plans:
+            X = torch.fft.rfft(xs, n=nfft)
+            Y = torch.fft.rfft(ys, n=nfft)
+            c = torch.fft.irfft(torch.conj(X) * Y, n=nfft)
+            g = torch.gather(c, 1, pos).masked_fill(~valid, float("-inf"))
+            outs.append((idx, torch.argmax(g, dim=1) + lo))
+        return outs
 
     for _ in range(warmup):
         step()
@@ -111,11 +146,15 @@ def fft_baseline(torch, xs, ys, lo, hi, steps, warmup):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
-        lag = step()
+        outs = step()
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    return ms, lag.cpu().numpy()
+    lag = [0] * len(pairs)
+    for idx, l in outs:
+        for k, v in zip(idx, l.cpu().numpy().tolist()):
+            lag[k] = v
+    return ms, lag
 
 
 def cpu_baseline(pairs, budget_s: float = 12.0):
@@ -146,6 +185,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--path", default="auto", choices=["auto", "mfma", "popc", "ntt"])
+    ap.add_argument("--eager", action="store_true",
+                    help="time eager calls instead of HIP-graph replays of the whole call")
+    ap.add_argument("--tune", action="store_true", help="run the engine autotuner before planning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fft", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -178,6 +220,11 @@ def main():
                   lag_hi=p["lag_hi"], bits=p["bits"]) for p in pairs]
     path = {"auto": tde.TDE_PATH_AUTO, "mfma": tde.TDE_PATH_MFMA, "popc": tde.TDE_PATH_POPC,
             "ntt": tde.TDE_PATH_NTT}[args.path]
+    if args.tune:
+        log("[bench] autotuning engines")
+        tde.tde_tune(ctx.handle, 20)
+    engines = [tde.tde_tune_query(p["x"].size, p["y"].size, tde.kmax_of_bits(p["bits"]), tde.kmax_of_bits(p["bits"]),
+                                  p["lag_lo"], p["lag_hi"]) if path == tde.TDE_PATH_AUTO else path for p in pairs]
     plan = ctx.batch_plan(specs, path=path)
     ws = torch.empty(plan[2], dtype=torch.uint8, device="cuda")
     out = torch.empty(len(pairs) * tde.PEAK_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
@@ -202,18 +249,54 @@ def main():
     stage_ms, stage_n = tde.tde_timing_read(ctx.handle)
     tde.tde_timing_enable(ctx.handle, False)
     ms_step = total_ms / args.steps
+    eager_ms = ms_step
+    if not args.eager:
+        # the same call replayed from a captured HIP graph (descriptors stay in
+        # the workspace); stage timing is not recorded in this mode
+        gplan = ctx.batch_plan(specs, path=path, use_graph=1)
+        gws = torch.empty(gplan[2], dtype=torch.uint8, device="cuda")
+        for _ in range(max(args.warmup, 1)):
+            ctx.estimate_batch(specs, path, ws=gws, out=out, plan=gplan, stream=stream)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            ctx.estimate_batch(specs, path, ws=gws, out=out, plan=gplan, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_step = e0.elapsed_time(e1) / args.steps
     pk = tde.decode_peaks(out)
     d = np.array([p["d"] for p in pairs])
     int_correct = float(np.mean((pk["lag"] == d) & (pk["n_ties"] == 1)))
     engine_ms = stage_ms[1] / max(stage_n[1], 1)
     log(f"[bench] {ms_step:.3f} ms/step, engine {engine_ms:.3f} ms, stages {stage_ms} {stage_n}")
 
-    achieved = 2.0 * macs / (engine_ms * 1e-3) / 1e12
-    src = os.path.join(ROOT, "paper_2509_19974_amd", "csrc", "k_xcorr_mfma.hip")
-    roof = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
-            "frac": achieved / INT8_PEAK_TOPS, "traffic": traffic_from_profile(src),
-            "kernel": "k_xcorr_mfma (int8 MFMA 32x32x32, int32 accumulation)",
-            "kernel_ms": engine_ms, "alg_macs_per_launch": macs}
+    n_ntt = sum(1 for e in engines if e == tde.TDE_PATH_NTT)
+    if n_ntt * 2 < len(engines):
+        achieved = 2.0 * macs / (engine_ms * 1e-3) / 1e12
+        src = os.path.join(ROOT, "paper_2509_19974_amd", "csrc", "k_xcorr_mfma.hip")
+        roof = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
+                "frac": achieved / INT8_PEAK_TOPS, "traffic": traffic_from_profile(src),
+                "kernel": "k_xcorr_mfma (int8 MFMA 32x32x32, int32 accumulation)",
+                "kernel_ms": engine_ms, "alg_macs_per_launch": macs}
+    else:
+        # transform engine: modular butterflies (one Montgomery product each)
+        # of the three transforms per prime, against the 32-bit multiply rate
+        bf = 0
+        for p in pairs:
+            nx, ny = p["x"].size, p["y"].size
+            lo, hi = max(p["lag_lo"], -(nx - 1)), min(p["lag_hi"], ny - 1)
+            need = max(hi + nx, ny - lo)
+            lg = 13
+            while (1 << lg) < need:
+                lg += 1
+            k = tde.kmax_of_bits(p["bits"])
+            nprimes = 1 if min(nx, ny) * k * k < 2013265921 // 2 else 2
+            bf += nprimes * 3 * (1 << (lg - 1)) * lg
+        achieved = bf / (engine_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": MODMUL_PEAK_T, "unit": "Tbutterfly/s",
+                "frac": achieved / MODMUL_PEAK_T, "traffic": None,
+                "kernel": "k_ntt_cols_fwd + k_ntt_rows + k_ntt_cols_inv (two-prime NTT, Montgomery)",
+                "kernel_ms": engine_ms, "alg_butterflies_per_launch": bf}
 
     result = {
         "metric": "pairs/s and int-MAC/s vs FP32-FFT xcorr on MI355X at oracle-exact lags",
@@ -230,6 +313,10 @@ def main():
         "data": "synthetic",
         "config": desc,
         "int_mac_per_s": macs * 1e3 / ms_step,
+        "engines": {name: sum(1 for e in engines if e == code) for name, code in
+                    (("mfma", tde.TDE_PATH_MFMA), ("popc", tde.TDE_PATH_POPC), ("ntt", tde.TDE_PATH_NTT))},
+        "timing": "eager calls" if args.eager else "hip graph replay",
+        "eager_ms_per_step": eager_ms,
         "stage_ms": {"quantize": stage_ms[0] / max(stage_n[0], 1), "engine": engine_ms,
                      "argmax": stage_ms[2] / max(stage_n[2], 1), "call": stage_ms[3] / max(stage_n[3], 1)},
         "lag_accuracy": {"int": int_correct},
@@ -237,15 +324,10 @@ def main():
     }
     if not args.no_fft:
         log("[bench] FP32 FFT baseline")
-        N = pairs[0]["x"].size
-        if all(p["x"].size == N and p["y"].size == N and p["lag_lo"] == pairs[0]["lag_lo"]
-               and p["lag_hi"] == pairs[0]["lag_hi"] for p in pairs):
-            xs = torch.stack([s["x"] for s in specs])
-            ys = torch.stack([s["y"] for s in specs])
-            fms, flag = fft_baseline(torch, xs, ys, pairs[0]["lag_lo"], pairs[0]["lag_hi"], args.steps, args.warmup)
-            result["fft_fp32"] = {"pairs_per_s": len(pairs) * 1e3 / fms, "ms_per_step": fms,
-                                  "lag_accuracy": float(np.mean(flag == d)),
-                                  "speedup_int_over_fft": fms / ms_step}
+        fms, flag = fft_baseline(torch, pairs, specs, args.steps, args.warmup)
+        result["fft_fp32"] = {"pairs_per_s": len(pairs) * 1e3 / fms, "ms_per_step": fms,
+                              "lag_accuracy": float(np.mean(np.array(flag) == d)),
+                              "speedup_int_over_fft": fms / ms_step}
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         result["cpu_baseline"] = cpu_baseline(pairs)

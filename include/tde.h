@@ -98,7 +98,8 @@ typedef struct {
 /* ------------------------------------------------------------ context -- */
 
 /* Create a context bound to HIP device `device` (it becomes current while
- * the library works). Owns the tuning table and internal caches. */
+ * the library works). Owns pinned staging memory, captured graphs and timing
+ * events. Fails with TDE_ERR_UNSUPPORTED on a device that is not gfx950. */
 int  tde_create(tde_ctx** ctx, int device);
 void tde_destroy(tde_ctx* ctx);
 const char* tde_status_string(int status);
@@ -143,8 +144,12 @@ int tde_quantize(tde_ctx* ctx, const float* x, int64_t n, int bits, float inv_st
  *  r_dtype = TDE_I32 requires max_tau overlap(tau) * kmax_u * kmax_v < 2^31
  *  (the coefficient bound of Section 3.2), else TDE_ERR_RANGE; TDE_I64 is
  *  always exact.
- *  path = TDE_PATH_POPC needs kmax_u = kmax_v = 1. TDE_PATH_AUTO lets the
- *  tuning table choose.
+ *  path = TDE_PATH_POPC needs kmax_u = kmax_v = 1. TDE_PATH_NTT takes
+ *  transforms up to 2^23 points (TDE_ERR_UNSUPPORTED beyond): the smallest
+ *  power of two n with no alias on the requested lags inside the support,
+ *  n > max(hi + nu - 1, nv - 1 - lo) for the clamped range [lo, hi], so
+ *  nu + nv - 1 <= 2^23 for the full range. TDE_PATH_AUTO lets the tuning
+ *  table choose.
  * Errors: TDE_ERR_ARG (nu, nv < 1, lag_lo > lag_hi, null pointers, kmax out
  * of range), TDE_ERR_RANGE, TDE_ERR_WS. */
 size_t tde_xcorr_workspace_size(int64_t nu, int64_t nv, int kmax_u, int kmax_v,
@@ -205,6 +210,36 @@ typedef struct {
 size_t tde_estimate_workspace_size(const tde_pair* pairs_host, int64_t npairs, const tde_opts* opts);
 int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs_host, int64_t npairs,
                        const tde_opts* opts, tde_peak* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------ tuning -- */
+
+/* TDE_PATH_AUTO picks the engine of each correlation from a tuning table
+ * shared by every context of the process, keyed on the size bucket
+ * round(log2(max(nu, nv))) in [10, 23], the requested fraction of the full
+ * linear lag range (<= 1/16, <= 1/2, more) and the code class (Ku Kv = 1,
+ * <= 49, larger). Without a table a built-in cost model decides. All engines
+ * give identical results; only speed differs. Workspace sizes computed for
+ * TDE_PATH_AUTO assume the table in place at that moment: install or change
+ * the table before sizing workspaces (a call with a too-small workspace
+ * returns TDE_ERR_WS). */
+
+/* Measure every applicable engine for sizes 2^10 .. 2^max_log_n (max_log_n
+ * in [10, 22]) and all buckets, and install the fastest per bucket; larger
+ * sizes take the largest measured bucket. Each bucket is timed as the batch
+ * call runs it: a batch of identical synthetic pairs (b = 1, 4 or 8 for the
+ * three code classes) large enough to fill the device, scored per pair. Not
+ * a hot call: it allocates its own device buffers and synchronizes `stream`. */
+int tde_tune(tde_ctx* ctx, int max_log_n, void* stream);
+/* The engine (TDE_PATH_MFMA, _POPC or _NTT) that TDE_PATH_AUTO takes for this
+ * correlation, or TDE_ERR_ARG. */
+int tde_tune_query(int64_t nu, int64_t nv, int kmax_u, int kmax_v, int64_t lag_lo, int64_t lag_hi);
+/* Text file: a line "tde-tune 1", then lines "code_class lag_class log2n
+ * engine". Save fails with TDE_ERR_ARG when no table is installed; load
+ * replaces the table (TDE_ERR_IO for an unreadable or malformed file, which
+ * leaves the table unchanged); reset returns to the cost model. */
+int tde_tune_save(const char* path);
+int tde_tune_load(const char* path);
+int tde_tune_reset(void);
 
 /* ------------------------------------------------------ measurement -- */
 

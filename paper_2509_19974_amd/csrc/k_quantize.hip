@@ -118,10 +118,23 @@ __global__ void __launch_bounds__(256) k_scale_finalize(const QSig* sigs, int ns
                 const int64_t lo = c * kSumChunk;
                 int width = 1;
                 while (width < kSumChunk && width < len - lo) width *= 2;     // padded subtree width
-                for (int i = t; i < width; i += blockDim.x) st[i] = (lo + i < len) ? a[lo + i] : 0.0;
+                for (int i = t; i < width; i += 256) st[i] = (lo + i < len) ? a[lo + i] : 0.0;
                 __syncthreads();
+                // one level per step: every node of the level is read before
+                // any is overwritten (a level can span several waves)
                 for (int h = width / 2; h >= 1; h /= 2) {
-                    for (int i = t; i < h; i += blockDim.x) st[i] = st[2 * i] + st[2 * i + 1];
+                    double v[kSumChunk / 2 / 256];
+#pragma unroll
+                    for (int k = 0; k < kSumChunk / 2 / 256; ++k) {
+                        const int i = t + 256 * k;
+                        if (i < h) v[k] = st[2 * i] + st[2 * i + 1];
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int k = 0; k < kSumChunk / 2 / 256; ++k) {
+                        const int i = t + 256 * k;
+                        if (i < h) st[i] = v[k];
+                    }
                     __syncthreads();
                 }
                 if (t == 0) out[c] = st[0];

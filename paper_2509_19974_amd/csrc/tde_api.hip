@@ -43,6 +43,8 @@ struct tde_ctx {
 
 namespace tde {
 
+int ctx_device(const tde_ctx* ctx) { return ctx->device; }
+
 static thread_local char g_err[512] = "";
 
 int set_error(int status, const char* fmt, ...) {
@@ -153,12 +155,11 @@ void drop_graphs_on(tde_ctx* c, const void* ws, size_t bytes) {
     }
 }
 
-// Engine choice for one correlation. The direct engines are exact for every
-// size; the bit-plane engine only takes ternary codes.
-int choose_path(int path, int kuv) {
+// Engine choice for one correlation: the caller's, or the tuning table's
+// (every engine is exact; they differ in speed).
+int choose_path(int path, int64_t nu, int64_t nv, int kuv, int64_t lo, int64_t hi) {
     if (path != TDE_PATH_AUTO) return path;
-    (void)kuv;
-    return TDE_PATH_MFMA;
+    return auto_engine(nu, nv, kuv, lo, hi);
 }
 
 }  // namespace
@@ -331,7 +332,7 @@ size_t tde_xcorr_workspace_size(int64_t nu, int64_t nv, int kmax_u, int kmax_v, 
     it.p.lag_lo = lag_lo;
     it.p.lag_hi = lag_hi;
     it.p.kuv = kmax_u * kmax_v;
-    int eng = choose_path(path, it.p.kuv);
+    int eng = choose_path(path, nu, nv, it.p.kuv, lag_lo, lag_hi);
     if (eng == TDE_PATH_POPC) return popc_ws_bytes(it.p);
     if (eng == TDE_PATH_NTT) {
         NttPlan P;
@@ -349,7 +350,6 @@ int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, in
     if (rc) return rc;
     if (!ctx) return set_error(TDE_ERR_ARG, "tde_xcorr_int: null context");
     XItem it{};
-    it.engine = choose_path(path, kmax_u * kmax_v);
     it.p.u = u;
     it.p.v = v;
     it.p.nu = nu;
@@ -359,7 +359,8 @@ int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, in
     it.p.r = r;
     it.p.r_dtype = r_dtype;
     it.p.kuv = kmax_u * kmax_v;
-    const int eng = choose_path(path, it.p.kuv);
+    const int eng = choose_path(path, nu, nv, it.p.kuv, lag_lo, lag_hi);
+    it.engine = eng;
     size_t need = tde_xcorr_workspace_size(nu, nv, kmax_u, kmax_v, lag_lo, lag_hi, eng);
     if (need && (!ws || ws_bytes < need))
         return set_error(TDE_ERR_WS, "tde_xcorr_int: workspace %zu < %zu bytes", ws_bytes, need);
@@ -532,7 +533,7 @@ void outside_triple(int64_t lo, int64_t hi, int64_t c_lo, int64_t c_hi, XItem& i
 PairPlan plan_pair(const tde_pair& q, int path) {
     PairPlan pp{};
     const int K = kmax_of_bits(q.bits);
-    pp.eng = choose_path(path, K * K);
+    pp.eng = choose_path(path, q.nx, q.ny, K * K, q.lag_lo, q.lag_hi);
     pp.rdt = q.r_out ? q.r_dtype
                      : ((__int128)max_overlap(q.nx, q.ny, q.lag_lo, q.lag_hi) * K * K < ((__int128)1 << 31) ? TDE_I32
                                                                                                           : TDE_I64);

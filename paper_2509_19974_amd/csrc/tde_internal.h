@@ -176,6 +176,12 @@ int launch_xcorr_popc(const XItem* items_dev, const XItem& one, int nitems, int6
 // int8 copy helper
 int launch_copy_bytes(void* dst, const void* src, size_t n, hipStream_t s);
 
+// ---------------------------------------------------------- auto engine --
+// HIP device of a context.
+int ctx_device(const tde_ctx* ctx);
+// Engine for TDE_PATH_AUTO (tuning table, else the built-in cost model).
+int auto_engine(int64_t nu, int64_t nv, int kuv, int64_t lag_lo, int64_t lag_hi);
+
 // ----------------------------------------------------------------- NTT --
 // Number-theoretic-transform engine (two primes + CRT), for long signals.
 constexpr int kNttRow = 4096;      // row length of the four-step split

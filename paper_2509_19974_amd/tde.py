@@ -84,6 +84,11 @@ def load_library(path: str = LIB_PATH):
         "tde_argmax_lag": (i32, [vp, vp, i32, i64, i64, vp, vp, sz, vp]),
         "tde_estimate_workspace_size": (sz, [ctypes.POINTER(tde_pair), i64, ctypes.POINTER(tde_opts)]),
         "tde_estimate_batch": (i32, [vp, ctypes.POINTER(tde_pair), i64, ctypes.POINTER(tde_opts), vp, vp, sz, vp]),
+        "tde_tune": (i32, [vp, i32, vp]),
+        "tde_tune_query": (i32, [i64, i64, i32, i32, i64, i64]),
+        "tde_tune_save": (i32, [ctypes.c_char_p]),
+        "tde_tune_load": (i32, [ctypes.c_char_p]),
+        "tde_tune_reset": (i32, []),
         "tde_timing_enable": (i32, [vp, i32]),
         "tde_timing_read": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     }
@@ -180,6 +185,29 @@ def tde_estimate_workspace_size(pairs_arr, npairs, opts: tde_opts) -> int:
 def tde_estimate_batch(ctx, pairs_arr, npairs, opts: tde_opts, out, ws, ws_bytes, stream=None):
     _check(load_library().tde_estimate_batch(ctx, pairs_arr, npairs, ctypes.byref(opts), _ptr(out), _ptr(ws),
                                              ws_bytes, _stream(stream)))
+
+
+def tde_tune(ctx, max_log_n: int = 22, stream=None) -> None:
+    _check(load_library().tde_tune(ctx, max_log_n, _stream(stream)))
+
+
+def tde_tune_query(nu, nv, kmax_u, kmax_v, lag_lo, lag_hi) -> int:
+    st = load_library().tde_tune_query(nu, nv, kmax_u, kmax_v, lag_lo, lag_hi)
+    if st < 0:
+        _check(st)
+    return st
+
+
+def tde_tune_save(path: str) -> None:
+    _check(load_library().tde_tune_save(path.encode()))
+
+
+def tde_tune_load(path: str) -> None:
+    _check(load_library().tde_tune_load(path.encode()))
+
+
+def tde_tune_reset() -> None:
+    _check(load_library().tde_tune_reset())
 
 
 def tde_timing_enable(ctx, on: bool) -> None:

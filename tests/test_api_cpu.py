@@ -141,3 +141,41 @@ def test_no_gpu_means_no_context():
         pytest.skip("a GPU is present")
     with pytest.raises(tde.TDEError):
         tde.tde_create(0)
+
+
+def test_auto_engine_cost_model_and_tuning_file(tmp_path):
+    """Without a table the cost model decides: direct sums for short signals
+    and narrow lag ranges, the transform for long full-range correlations; a
+    loaded table overrides it where its engine applies."""
+    tde.tde_tune_reset()
+    n16, n22 = 1 << 16, 1 << 22
+    assert tde.tde_tune_query(n16, n16, 127, 127, -(n16 - 1), n16 - 1) == tde.TDE_PATH_MFMA
+    assert tde.tde_tune_query(n22, n22, 127, 127, -(n22 - 1), n22 - 1) == tde.TDE_PATH_NTT
+    assert tde.tde_tune_query(n22, n22, 127, 127, -1024, 1024) == tde.TDE_PATH_MFMA
+    with pytest.raises(tde.TDEError):
+        tde.tde_tune_query(0, 5, 1, 1, 0, 0)
+    with pytest.raises(tde.TDEError) as e:
+        tde.tde_tune_save(str(tmp_path / "none.txt"))
+    assert e.value.status == tde.TDE_ERR_ARG
+    f = tmp_path / "tune.txt"
+    # ternary, full range, 2^16: bit planes; int8 full range 2^16: transform;
+    # an entry that does not apply (bit planes for int8 codes) falls back
+    f.write_text("tde-tune 1\n0 2 16 2\n2 2 16 3\n2 0 16 2\n")
+    tde.tde_tune_load(str(f))
+    assert tde.tde_tune_query(n16, n16, 1, 1, -(n16 - 1), n16 - 1) == tde.TDE_PATH_POPC
+    assert tde.tde_tune_query(n16, n16, 127, 127, -(n16 - 1), n16 - 1) == tde.TDE_PATH_NTT
+    assert tde.tde_tune_query(n16, n16, 127, 127, -100, 100) == tde.TDE_PATH_MFMA
+    g = tmp_path / "back.txt"
+    tde.tde_tune_save(str(g))
+    assert g.read_text().split("\n")[0] == "tde-tune 1"
+    assert sorted(g.read_text().split("\n")[1:-1]) == sorted(["0 2 16 2", "2 2 16 3", "2 0 16 2"])
+    bad = tmp_path / "bad.txt"
+    for text in ("nope 1\n", "tde-tune 1\n0 2 16 9\n", "tde-tune 1\n0 2 16 2 x\n", "tde-tune 1\n5 0 12 1\n"):
+        bad.write_text(text)
+        with pytest.raises(tde.TDEError) as e:
+            tde.tde_tune_load(str(bad))
+        assert e.value.status == tde.TDE_ERR_IO
+    # a failed load leaves the table in place
+    assert tde.tde_tune_query(n16, n16, 1, 1, -(n16 - 1), n16 - 1) == tde.TDE_PATH_POPC
+    tde.tde_tune_reset()
+    assert tde.tde_tune_query(n16, n16, 1, 1, -(n16 - 1), n16 - 1) == tde.TDE_PATH_MFMA

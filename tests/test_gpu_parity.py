@@ -435,3 +435,61 @@ def test_batch_ntt_long_signals(T, ctx, log_n, npairs):
         assert olag == p["d"]                      # noiseless shift: the true delay
     pk2, _ = _batch(T, ctx, pairs, tde.TDE_PATH_NTT, want_r=False)
     assert pk2.tobytes() == pk.tobytes()
+
+
+# -------------------------------------------------------- autotuned batch --
+
+def test_tune_on_device_and_auto_batch(T, ctx, tmp_path):
+    """The tuner measures every applicable engine per bucket and installs the
+    fastest; a batch under TDE_PATH_AUTO then matches the oracle whatever it
+    picked, and the saved table reloads to the same choices."""
+    from paper_2509_19974_amd import tde
+    say("tune max_log_n=16")
+    tde.tde_tune(ctx.handle, 16)
+    f = str(tmp_path / "tune.txt")
+    tde.tde_tune_save(f)
+    lines = open(f).read().split("\n")
+    assert lines[0] == "tde-tune 1" and len(lines) > 3 * 3 * 7
+    n16 = 1 << 16
+    before = [tde.tde_tune_query(n, n, k, k, -(n // 4), n // 4) for n in (1000, 5000, n16) for k in (1, 7, 127)]
+    tde.tde_tune_reset()
+    tde.tde_tune_load(f)
+    after = [tde.tde_tune_query(n, n, k, k, -(n // 4), n // 4) for n in (1000, 5000, n16) for k in (1, 7, 127)]
+    assert before == after
+    pairs = synth.config4_uneven(npairs=32, nmin_log2=10, nmax_log2=15, salt=3)
+    pk, specs = _batch(T, ctx, pairs, tde.TDE_PATH_AUTO, want_r=True)
+    for i, p in enumerate(pairs):
+        _check_pair(pk[i], p, specs[i]["r_out"].cpu().numpy())
+    tde.tde_tune_reset()
+
+
+def test_batch_config4_full_size_graph_sampled(T, ctx):
+    """The 4096-pair uneven load (N log-uniform in [2^10, 2^18], b in
+    {1, 2, 4}, lags +-N/4) under TDE_PATH_AUTO, replayed from a HIP graph:
+    every pair's rmax equals the oracle's direct sum at the GPU's lag and is
+    at least the oracle's value at the true delay; on a sample of pairs the
+    whole oracle estimate must agree."""
+    from paper_2509_19974_amd import tde
+    say("batch c4 full size (graph)")
+    pairs = synth.config4_uneven(4096)
+    specs = [dict(x=dev(T, p["x"]), y=dev(T, p["y"]), lag_lo=p["lag_lo"], lag_hi=p["lag_hi"], bits=p["bits"])
+             for p in pairs]
+    plan = ctx.batch_plan(specs, use_graph=1)
+    ws = T.empty(plan[2], dtype=T.uint8, device="cuda")
+    out = T.empty(len(specs) * 24, dtype=T.uint8, device="cuda")
+    for _ in range(3):                                   # capture, then two replays
+        ctx.estimate_batch(specs, ws=ws, out=out, plan=plan)
+    T.cuda.synchronize()
+    pk = tde.decode_peaks(out)
+    eager = tde.decode_peaks(ctx.estimate_batch(specs))
+    T.cuda.synchronize()
+    assert pk.tobytes() == eager.tobytes()
+    for i, p in enumerate(pairs):
+        u, _, _ = oracle.quantize(p["x"], p["bits"])
+        v, _, _ = oracle.quantize(p["y"], p["bits"])
+        at = oracle.xcorr_at(u, v, [int(pk[i]["lag"]), p["d"]])
+        assert at[0] == pk[i]["rmax"], i
+        assert at[1] <= pk[i]["rmax"], i
+    sizes = np.array([p["x"].size for p in pairs])
+    for i in list(np.argsort(sizes)[:4]) + list(np.argsort(sizes)[2048:2052]) + [int(np.argmax(sizes))]:
+        _check_pair(pk[i], pairs[i])
