@@ -369,3 +369,113 @@ def test_certified_fft_route_equals_direct(n, k):
     direct = oracle.xcorr(u, v, -(n - 1), n - 6)
     got = oracle.xcorr_long_certified(u, v, -(n - 1), n - 6, check_lags=[-(n - 1), 0, 17])
     np.testing.assert_array_equal(got, direct)
+
+
+# ------------------------------------------------- learned proposer (CNN) --
+
+from oracle import cnn  # noqa: E402
+
+TINY = cnn.Shape(ld=64, c=3, layers=2, nbins=8)
+
+
+def _tiny_params(rng, s=TINY, scale=0.4):
+    p = {}
+    for name, sh in cnn.param_sizes(s):
+        p[name] = rng.standard_normal(sh) * scale if sh else 0.7
+    return p
+
+
+def test_cnn_gradients_match_central_differences():
+    """Every parameter's gradient of the softmax cross-entropy equals the
+    central finite difference of the loss (float64, h = 1e-6)."""
+    rng = np.random.default_rng(11)
+    p = _tiny_params(rng)
+    xd, yd = rng.standard_normal(TINY.ld), rng.standard_normal(TINY.ld)
+    label = 5
+    loss, g, _ = cnn.loss_and_grads(TINY, p, xd, yd, label)
+    flat = cnn.flatten(TINY, p)
+    gflat = cnn.flatten(TINY, g)
+    h = 1e-6
+    for i in range(flat.size):
+        a, b = flat.copy(), flat.copy()
+        a[i] += h
+        b[i] -= h
+        la, _, _ = cnn.loss_and_grads(TINY, cnn.unflatten(TINY, a), xd, yd, label)
+        lb, _, _ = cnn.loss_and_grads(TINY, cnn.unflatten(TINY, b), xd, yd, label)
+        fd = (la - lb) / (2 * h)
+        assert abs(fd - gflat[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, gflat[i])
+
+
+def test_cnn_input_gradients_match_central_differences():
+    """The gradient reaching the decimated inputs (encoder backward through
+    every layer) equals finite differences too."""
+    rng = np.random.default_rng(12)
+    p = _tiny_params(rng)
+    xd, yd = rng.standard_normal(TINY.ld), rng.standard_normal(TINY.ld)
+    logits, (Fx, Fy, cx, cy, raw) = cnn.forward(TINY, p, xd, yd)
+    loss, dlog = cnn.softmax_ce(logits, 2)
+    dFx, dFy, _ = cnn.head_bwd(TINY, p, Fx, Fy, raw, dlog)
+    gsink = {name: np.zeros(sh) if sh else 0.0 for name, sh in cnn.param_sizes(TINY)}
+    dx = cnn.encoder_bwd(TINY, p, cx, dFx, gsink)[0]
+    h = 1e-6
+    for i in range(0, TINY.ld, 7):
+        a, b = xd.copy(), xd.copy()
+        a[i] += h
+        b[i] -= h
+        la = cnn.softmax_ce(cnn.forward(TINY, p, a, yd)[0], 2)[0]
+        lb = cnn.softmax_ce(cnn.forward(TINY, p, b, yd)[0], 2)[0]
+        assert abs((la - lb) / (2 * h) - dx[i]) <= 1e-6 * max(1.0, abs(dx[i]))
+
+
+def test_cnn_zero_weights_give_uniform_logits():
+    s = cnn.Shape(ld=256, c=4, layers=3, nbins=16)
+    p = {name: np.zeros(sh) if sh else 1.0 for name, sh in cnn.param_sizes(s)}
+    rng = np.random.default_rng(0)
+    logits, _ = cnn.forward(s, p, rng.standard_normal(256), rng.standard_normal(256))
+    assert np.all(logits == 0.0)
+    loss, g = cnn.softmax_ce(logits, 3)
+    assert abs(loss - np.log(16)) < 1e-12 and abs(g.sum()) < 1e-12
+
+
+def test_cnn_single_channel_conv_is_numpy_correlate():
+    """One input and one output channel, no bias: the layer is the 'same'
+    correlation of numpy with the 9-tap kernel."""
+    rng = np.random.default_rng(1)
+    x, w = rng.standard_normal(50), rng.standard_normal(9)
+    z = cnn.conv_fwd(x[None, :], w[None, None, :], np.zeros(1))[0]
+    np.testing.assert_allclose(z, np.correlate(x, w, "same"), rtol=0, atol=1e-12)
+    a, pooled = cnn.relu_pool_fwd(np.array([[-1.0, 3.0, 2.0, 4.0, -5.0, -6.0]]))
+    assert pooled.tolist() == [[1.5, 3.0, 0.0]]
+
+
+def test_cnn_head_is_channel_sum_of_numpy_correlations():
+    rng = np.random.default_rng(2)
+    s = cnn.Shape(ld=160, c=5, layers=2, nbins=20)
+    Fx, Fy = rng.standard_normal((5, 40)), rng.standard_normal((5, 40))
+    raw = cnn.head_raw(s, Fx, Fy)
+    full = sum(np.correlate(Fy[c], Fx[c], "full") for c in range(5))   # index j <-> shift j - (F - 1)
+    for k in range(20):
+        assert abs(raw[k] - full[k - 10 + 39]) < 1e-10
+
+
+def test_cnn_adam_first_step_is_signed_lr():
+    """After one step, bias correction makes m_hat = g and v_hat = g^2, so the
+    update is lr * g / (|g| + eps)."""
+    g = np.array([0.3, -2.0, 1e-3, 0.0])
+    w = np.array([1.0, 1.0, 1.0, 1.0])
+    w1, m, v = cnn.adam_step(w, g, np.zeros(4), np.zeros(4), 1, lr=0.01)
+    np.testing.assert_allclose(w1, w - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def test_cnn_bins_and_bf16_rounding():
+    assert cnn.label_of_lag(-65536, 512, 256) == 0
+    assert cnn.label_of_lag(-65281, 512, 256) == 0
+    assert cnn.label_of_lag(-65280, 512, 256) == 1
+    assert cnn.label_of_lag(0, 512, 256) == 256
+    assert cnn.label_of_lag(65535, 512, 256) == 511
+    assert cnn.label_of_lag(10 ** 6, 512, 256) == 511
+    # bfloat16 keeps 8 significant bits; ties go to the even mantissa
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 2 ** -7 + 2 ** -9, -2.5])
+    assert cnn.bf16_round(vals).tolist() == [1.0, 1.0, 1.0 + 2 ** -6, 1.0 + 2 ** -7, -2.5]
+    top, margin = cnn.topk_margin(np.array([0.5, 2.0, 2.0, -1.0, 1.0]), 2)
+    assert top.tolist() == [1, 2] and margin == 1.0          # logit_(1) - logit_(3)
