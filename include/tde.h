@@ -211,6 +211,65 @@ size_t tde_estimate_workspace_size(const tde_pair* pairs_host, int64_t npairs, c
 int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs_host, int64_t npairs,
                        const tde_opts* opts, tde_peak* out, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------ learned model -- */
+
+/* Learned lag-window proposer. Not part of the paper: it only chooses where
+ * Algorithm 1's exact correlation (line 3) is evaluated, and the full lag
+ * range remains the fallback, so results stay exact. Architecture (fixed):
+ *   input   xd[t] = bf16(mean of x[16t .. 16t+15] / sigma), t < ld, with
+ *           sigma = sqrt(S/n) of the quantizer scale (Section on the scale in
+ *           tde_quantize); both signals of a pair go through the same encoder
+ *   encoder 4 x [conv1d kernel 9, zero padding 4, 32 channels, bias, ReLU,
+ *           average pooling of 2] -> 32 x F features, F = ld / 16
+ *   head    logits[k] = alpha sum_t sum_c Fx[c][t] Fy[c][t + k - nbins/2],
+ *           k < nbins: bin k covers the lags [(k - nbins/2) 256,
+ *           (k - nbins/2 + 1) 256) of the raw signals (one feature step is
+ *           256 samples)
+ * Parameters (float32, in this order): for each layer l, W_l[32][cin][9]
+ * (cin = 1 for l = 0, else 32) then b_l[32]; then alpha. Kernels use
+ * bf16-rounded copies of the weights and bf16 activations with float32
+ * accumulation (alpha stays float32). Training: softmax cross-entropy against a bin label, Adam
+ * (beta 0.9 / 0.999, eps 1e-8) on float32 masters.
+ *
+ * These are support calls, not hot calls: they may allocate device memory
+ * (model parameters, training buffers sized for the largest batch seen) and
+ * synchronize. xdec arrays hold bf16 bit patterns, [B][2][ld] (x then y). */
+typedef struct tde_model tde_model;
+
+/* ld: multiple of 256 in [256, 2^20]; nbins: multiple of 64, at most 2 ld/16
+ * and 4096. Weights start He-normal from `seed`, biases 0, alpha 1/(32 F). */
+int tde_model_create(tde_ctx* ctx, int ld, int nbins, uint64_t seed, tde_model** out);
+void tde_model_destroy(tde_model* model);
+int64_t tde_model_num_params(const tde_model* model);
+/* Host copies of the float32 parameters (n = tde_model_num_params). Setting
+ * them also resets the Adam state. */
+int tde_model_get_params(tde_model* model, float* host, int64_t n);
+int tde_model_set_params(tde_model* model, const float* host, int64_t n);
+/* Gradient of the mean loss from the last tde_train_step (host copy). */
+int tde_model_gradients(tde_model* model, float* host, int64_t n);
+/* Binary file: magic, ld, nbins, count, then the float32 parameters. */
+int tde_model_save(tde_model* model, const char* path);
+int tde_model_load(tde_model* model, const char* path);
+
+/* Decimated, normalised inputs of npairs pairs (pairs_host as for
+ * tde_estimate_batch; every pair has nx = ny = 16 ld and bits in {2,4,8},
+ * whose automatic scale gives sigma) into xdec [npairs][2][ld] (device). ws:
+ * tde_model_prepare_workspace_size bytes. */
+size_t tde_model_prepare_workspace_size(const tde_pair* pairs_host, int64_t npairs);
+int tde_model_prepare(tde_ctx* ctx, const tde_model* model, const tde_pair* pairs_host, int64_t npairs,
+                      uint16_t* xdec, void* ws, size_t ws_bytes, void* stream);
+
+/* logits [B][nbins] (device) of B input pairs; with top and margin (device,
+ * may both be NULL) also the topk best bins per pair (descending logit, ties
+ * to the smaller bin; 1 <= topk <= 16) and margin = logit_(1) - logit_(topk+1). */
+int tde_model_forward(tde_ctx* ctx, tde_model* model, const uint16_t* xdec, int64_t B, float* logits, int topk,
+                      int32_t* top, float* margin, void* stream);
+/* One Adam step on the mean softmax cross-entropy of B pairs against labels
+ * (device int32 bins). loss_out (host, may be NULL) receives the mean loss
+ * (the call then waits for the stream). */
+int tde_train_step(tde_ctx* ctx, tde_model* model, const uint16_t* xdec, const int32_t* labels, int64_t B, float lr,
+                   float* loss_out, void* stream);
+
 /* ------------------------------------------------------------ tuning -- */
 
 /* TDE_PATH_AUTO picks the engine of each correlation from a tuning table

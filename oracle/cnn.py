@@ -89,6 +89,11 @@ def decimate(x, inv_step: float, kmax: int, ld: int):
     return x.reshape(ld, 16).mean(axis=1) * scale
 
 
+def round_params(s: Shape, p, fn):
+    """Apply ``fn`` to every weight and bias (not alpha)."""
+    return {k: (fn(v) if k != "alpha" else v) for k, v in p.items()}
+
+
 def bf16_round(a):
     """Round float64 values to bfloat16 (round to nearest even), as float64."""
     f = np.asarray(a, dtype=np.float32)
@@ -116,15 +121,18 @@ def relu_pool_fwd(Z):
     return A, P
 
 
-def encoder_fwd(s: Shape, p, xd):
-    """Returns the features and the cache (input and pre-activation per layer)."""
+def encoder_fwd(s: Shape, p, xd, store=None):
+    """Returns the features and the cache (input and pre-activation per layer).
+    ``store`` (e.g. ``bf16_round``) is applied to every stored activation (the
+    layer outputs), modelling a device that keeps activations in a narrower
+    format; the arithmetic itself stays float64."""
     X = np.asarray(xd, dtype=np.float64)[None, :]
     cache = []
     for l in range(s.layers):
         Z = conv_fwd(X, p[f"W{l}"], p[f"b{l}"])
         A, P = relu_pool_fwd(Z)
         cache.append((X, Z))
-        X = P
+        X = store(P) if store is not None else P
     return X, cache
 
 
@@ -141,9 +149,9 @@ def head_raw(s: Shape, Fx, Fy):
     return raw
 
 
-def forward(s: Shape, p, xd, yd):
-    Fx, cx = encoder_fwd(s, p, xd)
-    Fy, cy = encoder_fwd(s, p, yd)
+def forward(s: Shape, p, xd, yd, store=None):
+    Fx, cx = encoder_fwd(s, p, xd, store)
+    Fy, cy = encoder_fwd(s, p, yd, store)
     raw = head_raw(s, Fx, Fy)
     return p["alpha"] * raw, (Fx, Fy, cx, cy, raw)
 
@@ -205,8 +213,8 @@ def encoder_bwd(s: Shape, p, cache, dF, grads):
     return d
 
 
-def loss_and_grads(s: Shape, p, xd, yd, label: int):
-    logits, (Fx, Fy, cx, cy, raw) = forward(s, p, xd, yd)
+def loss_and_grads(s: Shape, p, xd, yd, label: int, store=None):
+    logits, (Fx, Fy, cx, cy, raw) = forward(s, p, xd, yd, store)
     loss, dlog = softmax_ce(logits, label)
     grads = {name: np.zeros(sh) if sh else 0.0 for name, sh in param_sizes(s)}
     dFx, dFy, dalpha = head_bwd(s, p, Fx, Fy, raw, dlog)
@@ -216,14 +224,14 @@ def loss_and_grads(s: Shape, p, xd, yd, label: int):
     return loss, grads, logits
 
 
-def batch_loss_and_grads(s: Shape, p, xds, yds, labels):
+def batch_loss_and_grads(s: Shape, p, xds, yds, labels, store=None):
     """Mean loss and mean gradients over a batch."""
     B = len(labels)
     tot = {name: np.zeros(sh) if sh else 0.0 for name, sh in param_sizes(s)}
     L = 0.0
     logits = []
     for b in range(B):
-        loss, g, lg = loss_and_grads(s, p, xds[b], yds[b], int(labels[b]))
+        loss, g, lg = loss_and_grads(s, p, xds[b], yds[b], int(labels[b]), store)
         L += loss
         logits.append(lg)
         for k in tot:

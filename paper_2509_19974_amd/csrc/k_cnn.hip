@@ -1,0 +1,637 @@
+// Learned lag-window proposer (not part of the paper): a small 1-D CNN over
+// decimated signals whose feature cross-correlation scores coarse lag bins,
+// so that the exact integer correlation of Algorithm 1 (line 3) is evaluated
+// only inside the best bins.
+//
+//   input   xd[t] = bf16(mean of x[16t .. 16t+15] / sigma), t < Ld
+//   layer l (4 of them, C = 32 channels, kernel 9, zero padding 4):
+//           Z[t][o] = b[o] + sum_i sum_k W[o][i][k] X[t + k - 4][i]
+//           P[t][o] = (relu(Z[2t][o]) + relu(Z[2t+1][o])) / 2      (next X)
+//   head    raw[k] = sum_t sum_c Fx[t][c] Fy[t + k - nb/2][c],  logits = alpha raw
+//
+// Storage: activations bf16, position-major ([t][c], 64 bytes per position);
+// arithmetic fp32. The weights and biases used by the kernels are
+// bf16-rounded copies of fp32 master weights (kept as float); alpha stays
+// float32. Training: softmax cross-entropy,
+// backward through head, pooling, ReLU and convolutions, Adam on the masters.
+// Signals are indexed g = 2 * pair + side (side 0: x, 1: y).
+#include "tde_internal.h"
+
+namespace tde {
+
+namespace {
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);     // round to nearest even
+}
+
+}  // namespace
+
+__device__ __forceinline__ float bf16_round_dev(float f) { return bf2f(f2bf(f)); }
+
+// ------------------------------------------------------------- decimate --
+// out[g][t] = bf16(mean16(x_g) * scale_g); one thread per output sample.
+__global__ void __launch_bounds__(256) k_cnn_decimate(const CnnSig* sigs, int ld, uint16_t* out) {
+    const int g = blockIdx.y;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= ld) return;
+    const CnnSig s = sigs[g];
+    const float* x = s.x + (int64_t)16 * t;
+    float acc = 0.f;
+    if ((((uintptr_t)x) & 15) == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float4 v = reinterpret_cast<const float4*>(x)[k];
+            acc += (v.x + v.y) + (v.z + v.w);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc += x[k];
+    }
+    const float scale = s.inv ? (*s.inv) * s.scale_mul : s.scale_mul;
+    out[(int64_t)g * ld + t] = f2bf(acc * (1.f / 16.f) * scale);
+}
+
+// ---------------------------------------------------------- conv layer 0 --
+// One input channel. grid (ceil(L / 512), nsig); thread -> one pooled
+// position (two conv positions), all 32 channels.
+template <bool SAVE>
+__global__ void __launch_bounds__(256) k_conv1_fwd(const uint16_t* X, const float* W, const float* bias,
+                                                   uint16_t* Z, uint16_t* P, int L) {
+    __shared__ float ws[kCnnK][kCnnC];
+    __shared__ float bs[kCnnC];
+    for (int e = threadIdx.x; e < kCnnK * kCnnC; e += 256) ws[e % kCnnK][e / kCnnK] = W[e];
+    if (threadIdx.x < kCnnC) bs[threadIdx.x] = bias[threadIdx.x];
+    __syncthreads();
+    const int g = blockIdx.y;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (2 * p >= L) return;
+    const uint16_t* x = X + (int64_t)g * L;
+    float xv[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) {
+        const int t = 2 * p - 4 + j;
+        xv[j] = (t >= 0 && t < L) ? bf2f(x[t]) : 0.f;
+    }
+    uint16_t zo[2][kCnnC];
+    uint16_t po[kCnnC];
+#pragma unroll
+    for (int c = 0; c < kCnnC; ++c) {
+        float z0 = bs[c], z1 = bs[c];
+#pragma unroll
+        for (int k = 0; k < kCnnK; ++k) {
+            z0 += ws[k][c] * xv[k];
+            z1 += ws[k][c] * xv[k + 1];
+        }
+        zo[0][c] = f2bf(z0);
+        zo[1][c] = f2bf(z1);
+        po[c] = f2bf(0.5f * (fmaxf(z0, 0.f) + fmaxf(z1, 0.f)));
+    }
+    if (SAVE) {
+        uint4* zd = reinterpret_cast<uint4*>(Z + ((int64_t)g * L + 2 * p) * kCnnC);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) zd[q] = reinterpret_cast<const uint4*>(&zo[0][0])[q];
+    }
+    uint4* pd = reinterpret_cast<uint4*>(P + ((int64_t)g * (L / 2) + p) * kCnnC);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pd[q] = reinterpret_cast<const uint4*>(po)[q];
+}
+
+// -------------------------------------------------------- conv layers 1+ --
+// 32 -> 32 channels. grid (L / 128, nsig); a workgroup makes 128 conv
+// positions (64 pooled) x 32 channels; thread -> pooled position tp (0..63)
+// and channel group cg (0..3, 8 channels).
+constexpr int kTile = 128;
+constexpr int kXs = kTile + 8;       // input rows with halo
+
+template <bool SAVE>
+__global__ void __launch_bounds__(256) k_conv32_fwd(const uint16_t* X, const float* W, const float* bias,
+                                                    uint16_t* Z, uint16_t* P, int L) {
+    __shared__ float xs[kCnnC][kXs + 1];
+    __shared__ float ws[kCnnK][kCnnC][kCnnC];   // [k][ci][co]
+    const int g = blockIdx.y;
+    const int t0 = blockIdx.x * kTile;
+    const uint16_t* x = X + (int64_t)g * L * kCnnC;
+    for (int e = threadIdx.x; e < kXs * kCnnC; e += 256) {
+        const int r = e / kCnnC, c = e % kCnnC;
+        const int t = t0 - 4 + r;
+        xs[c][r] = (t >= 0 && t < L) ? bf2f(x[(int64_t)t * kCnnC + c]) : 0.f;
+    }
+    for (int e = threadIdx.x; e < kCnnC * kCnnC * kCnnK; e += 256) {
+        const int co = e / (kCnnC * kCnnK), rem = e % (kCnnC * kCnnK);
+        const int ci = rem / kCnnK, k = rem % kCnnK;
+        ws[k][ci][co] = W[e];
+    }
+    __syncthreads();
+    const int tp = threadIdx.x & 63, cg = threadIdx.x >> 6;
+    float acc[2][8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[0][c] = acc[1][c] = bias[cg * 8 + c];
+    for (int ci = 0; ci < kCnnC; ++ci) {
+        float xv[10];
+#pragma unroll
+        for (int j = 0; j < 10; ++j) xv[j] = xs[ci][2 * tp + j];
+#pragma unroll
+        for (int k = 0; k < kCnnK; ++k) {
+            const float4 wa = *reinterpret_cast<const float4*>(&ws[k][ci][cg * 8]);
+            const float4 wb = *reinterpret_cast<const float4*>(&ws[k][ci][cg * 8 + 4]);
+            const float w8[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                acc[0][c] += w8[c] * xv[k];
+                acc[1][c] += w8[c] * xv[k + 1];
+            }
+        }
+    }
+    const int tc = t0 + 2 * tp;
+    if (tc >= L) return;
+    uint16_t zo[2][8], po[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        zo[0][c] = f2bf(acc[0][c]);
+        zo[1][c] = f2bf(acc[1][c]);
+        po[c] = f2bf(0.5f * (fmaxf(acc[0][c], 0.f) + fmaxf(acc[1][c], 0.f)));
+    }
+    if (SAVE) {
+        *reinterpret_cast<uint4*>(Z + ((int64_t)g * L + tc) * kCnnC + cg * 8) = *reinterpret_cast<const uint4*>(zo[0]);
+        *reinterpret_cast<uint4*>(Z + ((int64_t)g * L + tc + 1) * kCnnC + cg * 8) =
+            *reinterpret_cast<const uint4*>(zo[1]);
+    }
+    *reinterpret_cast<uint4*>(P + ((int64_t)g * (L / 2) + tc / 2) * kCnnC + cg * 8) = *reinterpret_cast<const uint4*>(po);
+}
+
+// ----------------------------------------------------------------- head --
+// raw[b][k] = sum_t sum_c Fx[t][c] Fy[t + k - nb/2][c]; grid (nb / 64, B).
+// Thread -> lag kk (0..63) of the block and quarter q of the t range.
+__global__ void __launch_bounds__(256) k_head_fwd(const uint16_t* Fe, const float* params_alpha, float* raw,
+                                                  float* logits, int F, int nb) {
+    extern __shared__ uint16_t hs[];
+    const int b = blockIdx.y;
+    const int k0 = blockIdx.x * 64;
+    const int h = nb / 2;
+    const uint16_t* fx = Fe + (int64_t)(2 * b) * F * kCnnC;
+    const uint16_t* fy = Fe + (int64_t)(2 * b + 1) * F * kCnnC;
+    uint16_t* sx = hs;                          // [F][32]
+    uint16_t* sy = hs + F * kCnnC;              // window rows w = t + s, s = k0 - h + j
+    const int wlo = k0 - h;                     // fy row of window row 0
+    const int nw = F + 64;
+    for (int e = threadIdx.x; e < F * kCnnC / 8; e += 256)
+        reinterpret_cast<uint4*>(sx)[e] = reinterpret_cast<const uint4*>(fx)[e];
+    for (int e = threadIdx.x; e < nw * 4; e += 256) {
+        const int r = e >> 2, q = e & 3;
+        const int t = wlo + r;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (t >= 0 && t < F) v = reinterpret_cast<const uint4*>(fy + (int64_t)t * kCnnC)[q];
+        reinterpret_cast<uint4*>(sy)[e] = v;
+    }
+    __syncthreads();
+    const int kk = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int tq = F / 4;
+    float acc = 0.f;
+    for (int t = q * tq; t < (q + 1) * tq; ++t) {
+        const uint4* ax = reinterpret_cast<const uint4*>(sx + t * kCnnC);
+        const uint4* ay = reinterpret_cast<const uint4*>(sy + (t + kk) * kCnnC);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const uint4 a = ax[v], c = ay[v];
+            const uint32_t aw[4] = {a.x, a.y, a.z, a.w}, cw[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                acc += __uint_as_float(aw[e] << 16) * __uint_as_float(cw[e] << 16);
+                acc += __uint_as_float(aw[e] & 0xFFFF0000u) * __uint_as_float(cw[e] & 0xFFFF0000u);
+            }
+        }
+    }
+    __shared__ float red[4][64];
+    red[q][kk] = acc;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const float r = (red[0][kk] + red[1][kk]) + (red[2][kk] + red[3][kk]);
+        const int k = k0 + kk;
+        raw[(int64_t)b * nb + k] = r;
+        logits[(int64_t)b * nb + k] = (*params_alpha) * r;
+    }
+}
+
+// ------------------------------------------------ softmax, loss, top-k --
+// One workgroup per pair. Training (labels set): loss, dlog = (softmax -
+// onehot) / B and dalpha_b = sum dlog raw. Proposal (top set): the top-k
+// bins (ties to the smaller bin) and margin = logit_(1) - logit_(k+1).
+__global__ void __launch_bounds__(256) k_softmax_topk(const float* logits, const float* raw, const int32_t* labels,
+                                                      int nb, float inv_b, float* loss, float* dlog, float* dalpha,
+                                                      int topk, int32_t* top, float* margin) {
+    const int b = blockIdx.x;
+    const float* z = logits + (int64_t)b * nb;
+    __shared__ float sv[256];
+    __shared__ int si[256];
+    __shared__ float s_max, s_sum;
+    const int t = threadIdx.x;
+    // max
+    float m = -INFINITY;
+    for (int k = t; k < nb; k += 256) m = fmaxf(m, z[k]);
+    sv[t] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) sv[t] = fmaxf(sv[t], sv[t + o]);
+        __syncthreads();
+    }
+    if (t == 0) s_max = sv[0];
+    __syncthreads();
+    const float mx = s_max;
+    if (labels) {
+        float s = 0.f;
+        for (int k = t; k < nb; k += 256) s += __expf(z[k] - mx);
+        __syncthreads();
+        sv[t] = s;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (t < o) sv[t] += sv[t + o];
+            __syncthreads();
+        }
+        if (t == 0) s_sum = sv[0];
+        __syncthreads();
+        const float S = s_sum;
+        const int lab = labels[b];
+        float da = 0.f;
+        for (int k = t; k < nb; k += 256) {
+            const float pr = __expf(z[k] - mx) / S;
+            const float g = (pr - (k == lab ? 1.f : 0.f)) * inv_b;
+            dlog[(int64_t)b * nb + k] = g;
+            da += g * raw[(int64_t)b * nb + k];
+        }
+        __syncthreads();
+        sv[t] = da;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (t < o) sv[t] += sv[t + o];
+            __syncthreads();
+        }
+        if (t == 0) {
+            dalpha[b] = sv[0];
+            loss[b] = -(z[lab] - mx - __logf(S));
+        }
+    }
+    if (top) {
+        // k+1 rounds of (max, smallest index) over the bins not yet taken
+        __shared__ int taken[kCnnMaxTop + 1];
+        float first = 0.f;
+        for (int r = 0; r <= topk; ++r) {
+            float bv = -INFINITY;
+            int bi = INT32_MAX;
+            for (int k = t; k < nb; k += 256) {
+                bool used = false;
+                for (int j = 0; j < r; ++j) used |= taken[j] == k;
+                if (used) continue;
+                const float v = z[k];
+                if (v > bv || (v == bv && k < bi)) {
+                    bv = v;
+                    bi = k;
+                }
+            }
+            __syncthreads();
+            sv[t] = bv;
+            si[t] = bi;
+            __syncthreads();
+            for (int o = 128; o > 0; o >>= 1) {
+                if (t < o) {
+                    const float v2 = sv[t + o];
+                    const int i2 = si[t + o];
+                    if (v2 > sv[t] || (v2 == sv[t] && i2 < si[t])) {
+                        sv[t] = v2;
+                        si[t] = i2;
+                    }
+                }
+                __syncthreads();
+            }
+            if (t == 0) taken[r] = si[0];
+            if (r == 0) first = sv[0];
+            if (r == topk && t == 0) margin[b] = si[0] == INT32_MAX ? INFINITY : first - sv[0];
+            __syncthreads();
+        }
+        if (t < topk) top[(int64_t)b * topk + t] = taken[t];
+    }
+}
+
+// ------------------------------------------------------------ head bwd --
+// dFx[t][c] = alpha sum_k dlog[k] Fy[t + k - h][c]
+// dFy[t][c] = alpha sum_k dlog[k] Fx[t - k + h][c]
+// grid (F / 64, B, 2 sides); thread -> position (0..63) and 8 channels.
+__global__ void __launch_bounds__(256) k_head_bwd(const uint16_t* Fe, const float* dlog, const float* params_alpha,
+                                                  float* dFe, int F, int nb) {
+    extern __shared__ float hb[];
+    const int b = blockIdx.y, side = blockIdx.z;
+    const int t0 = blockIdx.x * 64;
+    const int h = nb / 2;
+    float* sd = hb;                                  // dlog [nb]
+    uint16_t* so = reinterpret_cast<uint16_t*>(hb + nb);   // other side's window
+    const uint16_t* other = Fe + (int64_t)(2 * b + (1 - side)) * F * kCnnC;
+    // side 0 needs Fy rows t + k - h, k in [0, nb): rows [t0 - h, t0 + 63 - h + nb - 1]
+    // side 1 needs Fx rows t - k + h: rows [t0 + h - nb + 1, t0 + 63 + h]
+    const int wlo = side == 0 ? t0 - h : t0 + h - nb + 1;
+    const int nw = 64 + nb - 1;
+    for (int k = threadIdx.x; k < nb; k += 256) sd[k] = dlog[(int64_t)b * nb + k];
+    for (int e = threadIdx.x; e < nw * 4; e += 256) {
+        const int r = e >> 2, q = e & 3;
+        const int t = wlo + r;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (t >= 0 && t < F) v = reinterpret_cast<const uint4*>(other + (int64_t)t * kCnnC)[q];
+        reinterpret_cast<uint4*>(so)[e] = v;
+    }
+    __syncthreads();
+    const int tp = threadIdx.x & 63, cg = threadIdx.x >> 6;
+    const int t = t0 + tp;
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < nb; ++k) {
+        // window row of the partner position
+        const int r = side == 0 ? (t + k - h) - wlo : (t - k + h) - wlo;
+        const uint4 v = reinterpret_cast<const uint4*>(so + r * kCnnC)[cg];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+        const float d = sd[k];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            acc[2 * e] += d * __uint_as_float(w[e] << 16);
+            acc[2 * e + 1] += d * __uint_as_float(w[e] & 0xFFFF0000u);
+        }
+    }
+    if (t >= F) return;
+    const float a = *params_alpha;
+    float* dst = dFe + ((int64_t)(2 * b + side) * F + t) * kCnnC + cg * 8;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) dst[c] = a * acc[c];
+}
+
+// ------------------------------------------------- conv backward (data) --
+// dZ[t][o] = dP[t/2][o] / 2 * (Z[t][o] > 0); dX[t][i] = sum_o sum_k
+// W[o][i][k] dZ[t + 4 - k][o]. grid (L / 128, nsig), thread -> 2 positions
+// and 8 input channels.
+__global__ void __launch_bounds__(256) k_conv32_bwd_data(const float* dP, const uint16_t* Z, const float* W,
+                                                         float* dX, int L) {
+    __shared__ float dz[kCnnC][kXs + 1];
+    __shared__ float ws[kCnnK][kCnnC][kCnnC];   // [k][co][ci]
+    const int g = blockIdx.y;
+    const int t0 = blockIdx.x * kTile;
+    for (int e = threadIdx.x; e < kXs * kCnnC; e += 256) {
+        const int r = e / kCnnC, c = e % kCnnC;
+        const int t = t0 - 4 + r;
+        float v = 0.f;
+        if (t >= 0 && t < L) {
+            const float z = bf2f(Z[((int64_t)g * L + t) * kCnnC + c]);
+            if (z > 0.f) v = 0.5f * dP[((int64_t)g * (L / 2) + t / 2) * kCnnC + c];
+        }
+        dz[c][r] = v;
+    }
+    for (int e = threadIdx.x; e < kCnnC * kCnnC * kCnnK; e += 256) {
+        const int co = e / (kCnnC * kCnnK), rem = e % (kCnnC * kCnnK);
+        const int ci = rem / kCnnK, k = rem % kCnnK;
+        ws[k][co][ci] = W[e];
+    }
+    __syncthreads();
+    const int tp = threadIdx.x & 63, cg = threadIdx.x >> 6;
+    float acc[2][8] = {};
+    for (int co = 0; co < kCnnC; ++co) {
+        float zv[10];
+        // dZ rows t + 4 - k for t = 2tp, 2tp+1 (tile coordinates: + 4)
+#pragma unroll
+        for (int j = 0; j < 10; ++j) zv[j] = dz[co][2 * tp + j];
+#pragma unroll
+        for (int k = 0; k < kCnnK; ++k) {
+            const float4 wa = *reinterpret_cast<const float4*>(&ws[k][co][cg * 8]);
+            const float4 wb = *reinterpret_cast<const float4*>(&ws[k][co][cg * 8 + 4]);
+            const float w8[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+            // tile row of dZ[t + 4 - k] is (t - t0) + 8 - k
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                acc[0][c] += w8[c] * zv[8 - k];
+                acc[1][c] += w8[c] * zv[9 - k];
+            }
+        }
+    }
+    const int tc = t0 + 2 * tp;
+    if (tc >= L) return;
+    float* d0 = dX + ((int64_t)g * L + tc) * kCnnC + cg * 8;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        d0[c] = acc[0][c];
+        d0[kCnnC + c] = acc[1][c];
+    }
+}
+
+// ----------------------------------------------- conv backward (weights) --
+// Per workgroup (signal g, chunk of kWChunk positions): partial dW[o][i][k]
+// = sum_t dZ[t][o] X[t + k - 4][i] and db[o] = sum_t dZ[t][o], written to
+// part[blk][n] with n = 32 cin 9 + 32. Thread -> o = t % 32 and a group of
+// cin/8 input channels (cin = 32) or one (o, k) slot pair (cin = 1).
+constexpr int kWChunk = 512;
+
+template <int CIN>
+__global__ void __launch_bounds__(256) k_conv_bwd_w(const float* dP, const uint16_t* Z, const uint16_t* X, int L,
+                                                    float* part) {
+    constexpr int NW = kCnnC * CIN * kCnnK;
+    __shared__ float dz[64][kCnnC + 1];
+    __shared__ float xs[64 + 8][CIN == 1 ? 1 : kCnnC + 1];
+    const int g = blockIdx.y;
+    const int nchunk = gridDim.x;
+    const int c0 = blockIdx.x * kWChunk;
+    const int o = threadIdx.x & 31;
+    const int grp = threadIdx.x >> 5;          // 0..7
+    constexpr int NI = CIN == 1 ? 1 : CIN / 8;
+    float acc[NI][kCnnK] = {};
+    float accb = 0.f;
+    // cin = 1: thread (o, grp) owns tap k = grp (and grp 0 also tap 8)
+    float acc8 = 0.f;
+    for (int tb = c0; tb < c0 + kWChunk && tb < L; tb += 64) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * kCnnC; e += 256) {
+            const int r = e / kCnnC, c = e % kCnnC;
+            const int t = tb + r;
+            float v = 0.f;
+            if (t < L) {
+                const float z = bf2f(Z[((int64_t)g * L + t) * kCnnC + c]);
+                if (z > 0.f) v = 0.5f * dP[((int64_t)g * (L / 2) + t / 2) * kCnnC + c];
+            }
+            dz[r][c] = v;
+        }
+        for (int e = threadIdx.x; e < 72 * CIN; e += 256) {
+            const int r = e / CIN, c = e % CIN;
+            const int t = tb - 4 + r;
+            float v = 0.f;
+            if (t >= 0 && t < L) v = bf2f(X[((int64_t)g * L + t) * CIN + c]);
+            xs[r][CIN == 1 ? 0 : c] = v;
+        }
+        __syncthreads();
+        for (int r = 0; r < 64; ++r) {
+            const float d = dz[r][o];
+            if (CIN == 1) {
+                acc[0][0] += d * xs[r + grp][0];
+                if (grp == 0) acc8 += d * xs[r + 8][0];
+            } else {
+#pragma unroll
+                for (int ii = 0; ii < NI; ++ii) {
+#pragma unroll
+                    for (int k = 0; k < kCnnK; ++k) acc[ii][k] += d * xs[r + k][grp * NI + ii];
+                }
+            }
+            if (grp == 0) accb += d;
+        }
+    }
+    float* dst = part + ((int64_t)g * nchunk + blockIdx.x) * (NW + kCnnC);
+    if (CIN == 1) {
+        dst[o * kCnnK + grp] = acc[0][0];
+        if (grp == 0) dst[o * kCnnK + 8] = acc8;
+    } else {
+#pragma unroll
+        for (int ii = 0; ii < NI; ++ii)
+#pragma unroll
+            for (int k = 0; k < kCnnK; ++k) dst[(o * CIN + grp * NI + ii) * kCnnK + k] = acc[ii][k];
+    }
+    if (grp == 0) dst[NW + o] = accb;
+}
+
+// grad[i] = sum_b part[b][i] (fixed order); one thread per element.
+__global__ void k_reduce_parts(const float* part, int nblk, int n, float* grad) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * n + i];
+    grad[i] = s;
+}
+
+// --------------------------------------------------------------- Adam --
+// Updates the fp32 masters and refreshes their bf16-rounded copies.
+__global__ void k_adam(float* p, const float* g, float* m, float* v, float* wc, int n, float lr, float b1, float b2,
+                       float eps, float bc1, float bc2) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    p[i] = pi;
+    wc[i] = i == n - 1 ? pi : bf16_round_dev(pi);     // alpha (last) stays float32
+}
+
+__global__ void k_round_copy(const float* p, float* wc, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) wc[i] = i == n - 1 ? p[i] : bf16_round_dev(p[i]);
+}
+
+// ---------------------------------------------------------------- host --
+
+int cnn_param_count(int layers) { return kCnnC * 1 * kCnnK + kCnnC + (layers - 1) * (kCnnC * kCnnC * kCnnK + kCnnC) + 1; }
+
+size_t cnn_param_offset(int layer) {
+    if (layer == 0) return 0;
+    return (size_t)(kCnnC * kCnnK + kCnnC) + (size_t)(layer - 1) * (kCnnC * kCnnC * kCnnK + kCnnC);
+}
+
+int launch_cnn_decimate(const CnnSig* sigs, int nsig, int ld, uint16_t* out, hipStream_t s) {
+    if (nsig == 0) return TDE_OK;
+    hipLaunchKernelGGL(k_cnn_decimate, dim3(ceil_div(ld, 256), nsig), dim3(256), 0, s, sigs, ld, out);
+    TDE_HIP_CHECK(hipGetLastError());
+    return TDE_OK;
+}
+
+// Forward through the encoder and head for nsig = 2 B signals. acts: Z_l
+// (may be null: inference) and X_l per layer; logits and raw [B][nb].
+int launch_cnn_forward(const CnnNet& net, const float* wc, const uint16_t* xdec, int B, CnnActs& A, float* raw,
+                       float* logits, hipStream_t s) {
+    const int nsig = 2 * B;
+    int L = net.ld;
+    const uint16_t* X = xdec;
+    for (int l = 0; l < kCnnLayers; ++l) {
+        const float* W = wc + cnn_param_offset(l);
+        const float* bias = W + (l == 0 ? kCnnC * kCnnK : kCnnC * kCnnC * kCnnK);
+        uint16_t* Z = A.z[l];
+        uint16_t* P = A.x[l + 1];
+        if (l == 0) {
+            if (Z) hipLaunchKernelGGL(k_conv1_fwd<true>, dim3(ceil_div(L / 2, 256), nsig), dim3(256), 0, s, X, W, bias, Z, P, L);
+            else hipLaunchKernelGGL(k_conv1_fwd<false>, dim3(ceil_div(L / 2, 256), nsig), dim3(256), 0, s, X, W, bias, Z, P, L);
+        } else {
+            if (Z) hipLaunchKernelGGL(k_conv32_fwd<true>, dim3(ceil_div(L, kTile), nsig), dim3(256), 0, s, X, W, bias, Z, P, L);
+            else hipLaunchKernelGGL(k_conv32_fwd<false>, dim3(ceil_div(L, kTile), nsig), dim3(256), 0, s, X, W, bias, Z, P, L);
+        }
+        TDE_HIP_CHECK(hipGetLastError());
+        X = P;
+        L /= 2;
+    }
+    const int F = L;
+    const size_t hl = (size_t)(F + F + 64) * kCnnC * 2;
+    static bool attr = false;
+    if (!attr) {
+        TDE_HIP_CHECK(hipFuncSetAttribute((const void*)k_head_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
+        TDE_HIP_CHECK(hipFuncSetAttribute((const void*)k_head_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_head_fwd, dim3(net.nb / 64, B), dim3(256), hl, s, X, wc + net.nparams - 1, raw, logits, F,
+                       net.nb);
+    TDE_HIP_CHECK(hipGetLastError());
+    return TDE_OK;
+}
+
+int launch_cnn_topk(const float* logits, int B, int nb, int topk, int32_t* top, float* margin, hipStream_t s) {
+    hipLaunchKernelGGL(k_softmax_topk, dim3(B), dim3(256), 0, s, logits, nullptr, nullptr, nb, 0.f, nullptr, nullptr,
+                       nullptr, topk, top, margin);
+    TDE_HIP_CHECK(hipGetLastError());
+    return TDE_OK;
+}
+
+// Loss, gradients (into grad, the flat parameter layout) of the mean loss.
+int launch_cnn_backward(const CnnNet& net, const float* wc, int B, const int32_t* labels, CnnActs& A,
+                        const float* raw, const float* logits, CnnGrad& G, hipStream_t s) {
+    const int nsig = 2 * B;
+    const int F = net.ld >> kCnnLayers;
+    hipLaunchKernelGGL(k_softmax_topk, dim3(B), dim3(256), 0, s, logits, raw, labels, net.nb, 1.f / B, G.loss,
+                       G.dlog, G.dalpha, 0, nullptr, nullptr);
+    TDE_HIP_CHECK(hipGetLastError());
+    const size_t hl = (size_t)net.nb * 4 + (size_t)(64 + net.nb) * kCnnC * 2;
+    hipLaunchKernelGGL(k_head_bwd, dim3(ceil_div(F, 64), B, 2), dim3(256), hl, s, A.x[kCnnLayers], G.dlog,
+                       wc + net.nparams - 1, G.dx[kCnnLayers], F, net.nb);
+    TDE_HIP_CHECK(hipGetLastError());
+    for (int l = kCnnLayers - 1; l >= 0; --l) {
+        const int L = net.ld >> l;
+        const float* W = wc + cnn_param_offset(l);
+        const float* dP = G.dx[l + 1];
+        const int nchunk = (int)ceil_div(L, kWChunk);
+        const int cin = l == 0 ? 1 : kCnnC;
+        const int n = kCnnC * cin * kCnnK + kCnnC;
+        if (l == 0)
+            hipLaunchKernelGGL(k_conv_bwd_w<1>, dim3(nchunk, nsig), dim3(256), 0, s, dP, A.z[l], A.x[l], L, G.part);
+        else
+            hipLaunchKernelGGL(k_conv_bwd_w<kCnnC>, dim3(nchunk, nsig), dim3(256), 0, s, dP, A.z[l], A.x[l], L, G.part);
+        TDE_HIP_CHECK(hipGetLastError());
+        hipLaunchKernelGGL(k_reduce_parts, dim3(ceil_div(n, 256)), dim3(256), 0, s, G.part, nchunk * nsig, n,
+                           G.grad + cnn_param_offset(l));
+        TDE_HIP_CHECK(hipGetLastError());
+        if (l > 0) {
+            hipLaunchKernelGGL(k_conv32_bwd_data, dim3(ceil_div(L, kTile), nsig), dim3(256), 0, s, dP, A.z[l], W,
+                               G.dx[l], L);
+            TDE_HIP_CHECK(hipGetLastError());
+        }
+    }
+    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, s, G.dalpha, B, 1, G.grad + net.nparams - 1);
+    TDE_HIP_CHECK(hipGetLastError());
+    return TDE_OK;
+}
+
+int launch_adam(float* p, const float* g, float* m, float* v, float* wc, int n, float lr, int step,
+                hipStream_t s) {
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float bc1 = 1.f - powf(b1, (float)step), bc2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(ceil_div(n, 256)), dim3(256), 0, s, p, g, m, v, wc, n, lr, b1, b2, 1e-8f, bc1,
+                       bc2);
+    TDE_HIP_CHECK(hipGetLastError());
+    return TDE_OK;
+}
+
+int launch_round_copy(const float* p, float* wc, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_round_copy, dim3(ceil_div(n, 256)), dim3(256), 0, s, p, wc, n);
+    TDE_HIP_CHECK(hipGetLastError());
+    return TDE_OK;
+}
+
+}  // namespace tde

@@ -945,3 +945,127 @@ int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs, int64_t np, const td
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------- model inputs --
+
+namespace {
+
+int check_model_pairs(const tde_model* M, const tde_pair* pairs, int64_t np, const char* who) {
+    if (!pairs || np < 1 || np > 65535) return set_error(TDE_ERR_ARG, "%s: 1..65535 pairs", who);
+    const int64_t n = M ? 16 * (int64_t)model_net(M).ld : -1;
+    for (int64_t i = 0; i < np; ++i) {
+        const tde_pair& q = pairs[i];
+        if (!q.x || !q.y) return set_error(TDE_ERR_ARG, "%s: pair %lld: null signal", who, (long long)i);
+        if (q.bits != 2 && q.bits != 4 && q.bits != 8)
+            return set_error(TDE_ERR_ARG, "%s: pair %lld: bits must be 2, 4 or 8", who, (long long)i);
+        if (M && (q.nx != n || q.ny != n))
+            return set_error(TDE_ERR_ARG, "%s: pair %lld: signals must have 16 ld = %lld samples", who, (long long)i,
+                             (long long)n);
+        if (q.nx < 1 || q.ny < 1 || (q.nx % 16) || (q.ny % 16))
+            return set_error(TDE_ERR_ARG, "%s: pair %lld: lengths must be multiples of 16", who, (long long)i);
+        if (!std::isfinite(q.inv_step_x) || !std::isfinite(q.inv_step_y))
+            return set_error(TDE_ERR_ARG, "%s: pair %lld: non-finite inv_step", who, (long long)i);
+    }
+    return TDE_OK;
+}
+
+struct PrepPlan {
+    size_t off_qsig, off_csig, off_stats, off_inv, total;
+    std::vector<size_t> off_q, off_gsum;
+};
+
+PrepPlan plan_prepare(const tde_pair* pairs, int64_t np) {
+    PrepPlan P;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        size_t o = off;
+        off += align_bytes(b);
+        return o;
+    };
+    P.off_qsig = take(sizeof(QSig) * 2 * np);
+    P.off_csig = take(sizeof(CnnSig) * 2 * np);
+    P.off_stats = take(sizeof(tde_qstat) * 2 * np);
+    P.off_inv = take(sizeof(float) * 2 * np);
+    P.off_q.resize(2 * np);
+    P.off_gsum.resize(2 * np);
+    for (int64_t i = 0; i < 2 * np; ++i) {
+        const int64_t n = (i & 1) ? pairs[i / 2].ny : pairs[i / 2].nx;
+        P.off_q[i] = take(n);
+        P.off_gsum[i] = take((size_t)quantize_gsum_doubles(n) * 8);
+    }
+    P.total = off;
+    return P;
+}
+
+// Quantizer scales of every signal (and its codes, in the workspace) and the
+// descriptors of their decimation; shared by tde_model_prepare and the
+// learned batch mode. Returns the number of quantize blocks.
+int64_t fill_prepare(const tde_pair* pairs, int64_t np, uint8_t* W, const PrepPlan& P, std::vector<uint8_t>& blob,
+                     bool& need_scale) {
+    blob.assign(P.off_stats, 0);
+    QSig* sigs = reinterpret_cast<QSig*>(blob.data() + P.off_qsig);
+    CnnSig* cs = reinterpret_cast<CnnSig*>(blob.data() + P.off_csig);
+    tde_qstat* stats = reinterpret_cast<tde_qstat*>(W + P.off_stats);
+    float* invs = reinterpret_cast<float*>(W + P.off_inv);
+    int64_t bbase = 0;
+    need_scale = false;
+    for (int64_t i = 0; i < 2 * np; ++i) {
+        const tde_pair& q = pairs[i / 2];
+        const int side = (int)(i & 1);
+        QSig S{};
+        S.x = side ? q.y : q.x;
+        S.n = side ? q.ny : q.nx;
+        S.q = reinterpret_cast<int8_t*>(W + P.off_q[i]);
+        S.stat = stats + i;
+        S.gsum = reinterpret_cast<double*>(W + P.off_gsum[i]);
+        S.inv_out = invs + i;
+        S.blk_base = bbase;
+        const float fixed = side ? q.inv_step_y : q.inv_step_x;
+        S.inv_fixed = fixed > 0.f ? fixed : 0.f;
+        S.bits = q.bits;
+        if (!(fixed > 0.f)) need_scale = true;
+        bbase += ceil_div(S.n, kQuantBlock);
+        sigs[i] = S;
+        cs[i] = CnnSig{S.x, S.inv_out, 6.f / (float)(2 * kmax_of_bits(q.bits) + 1)};
+    }
+    return bbase;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tde_model_prepare_workspace_size(const tde_pair* pairs, int64_t np) {
+    if (check_model_pairs(nullptr, pairs, np, "tde_model_prepare_workspace_size") != TDE_OK) return 0;
+    return plan_prepare(pairs, np).total;
+}
+
+int tde_model_prepare(tde_ctx* ctx, const tde_model* M, const tde_pair* pairs, int64_t np, uint16_t* xdec, void* ws,
+                      size_t ws_bytes, void* stream) {
+    if (!M || !xdec) return set_error(TDE_ERR_ARG, "tde_model_prepare: null model or output");
+    int rc = check_model_pairs(M, pairs, np, "tde_model_prepare");
+    if (rc) return rc;
+    PrepPlan P = plan_prepare(pairs, np);
+    if (!ws || ws_bytes < P.total)
+        return set_error(TDE_ERR_WS, "tde_model_prepare: workspace %zu < %zu bytes", ws_bytes, P.total);
+    if (!ctx) return set_error(TDE_ERR_ARG, "tde_model_prepare: null context");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return set_error(TDE_ERR_HIP, "tde_model_prepare: hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint8_t* W = static_cast<uint8_t*>(ws);
+    std::vector<uint8_t> blob;
+    bool need_scale = false;
+    const int64_t nblk = fill_prepare(pairs, np, W, P, blob, need_scale);
+    drop_graphs_on(ctx, ws, P.total);
+    rc = upload(ctx, W, blob.data(), blob.size(), s);
+    if (rc) return rc;
+    QSig none{};
+    rc = launch_quantize(reinterpret_cast<const QSig*>(W + P.off_qsig), none, (int)(2 * np), nblk, need_scale, false,
+                         nullptr, 0, s);
+    if (rc) return rc;
+    return launch_cnn_decimate(reinterpret_cast<const CnnSig*>(W + P.off_csig), (int)(2 * np), model_net(M).ld, xdec,
+                               s);
+}
+
+}  // extern "C"

@@ -222,4 +222,54 @@ NttGroup ntt_group(const NttPlan& P, uint32_t* tab);
 // All jobs share the group's n and prime count.
 int launch_ntt(const NttGroup& g, const NttJob* jobs_dev, int njobs, hipStream_t s);
 
+// ----------------------------------------------------------------- CNN --
+// Learned lag-window proposer (fixed architecture: 4 conv layers of 32
+// channels, kernel 9, average pooling 2, correlation head).
+constexpr int kCnnC = 32, kCnnK = 9, kCnnLayers = 4, kCnnMaxTop = 16;
+
+struct CnnSig {           // one signal to decimate
+    const float* x;       // 16 ld samples
+    const float* inv;     // quantizer scale (device) or null
+    float scale_mul;      // scale = *inv * scale_mul (or scale_mul alone)
+};
+
+struct CnnNet {
+    int ld;               // decimated input length (multiple of 256)
+    int nb;               // bins (multiple of 64, at most 2 ld / 16)
+    int nparams;
+};
+
+struct CnnActs {          // per layer l: input X_l (x[0] = decimated input), pre-activation Z_l
+    uint16_t* x[kCnnLayers + 1];
+    uint16_t* z[kCnnLayers];   // null for inference
+};
+
+struct CnnGrad {
+    float* dx[kCnnLayers + 1];   // gradient of each layer's output (dx[4] = features)
+    float* part;                 // per-workgroup weight-gradient partials
+    float* grad;                 // flat, parameter layout
+    float* dlog;                 // [B][nb]
+    float* dalpha;               // [B]
+    float* loss;                 // [B]
+};
+
+int cnn_param_count(int layers);
+size_t cnn_param_offset(int layer);
+int launch_cnn_decimate(const CnnSig* sigs, int nsig, int ld, uint16_t* out, hipStream_t s);
+int launch_cnn_forward(const CnnNet& net, const float* wc, const uint16_t* xdec, int B, CnnActs& A, float* raw,
+                       float* logits, hipStream_t s);
+int launch_cnn_topk(const float* logits, int B, int nb, int topk, int32_t* top, float* margin, hipStream_t s);
+int launch_cnn_backward(const CnnNet& net, const float* wc, int B, const int32_t* labels, CnnActs& A,
+                        const float* raw, const float* logits, CnnGrad& G, hipStream_t s);
+int launch_adam(float* p, const float* g, float* m, float* v, float* wc, int n, float lr, int step, hipStream_t s);
+int launch_round_copy(const float* p, float* wc, int n, hipStream_t s);
+// model accessors and the allocation-free inference used by the batch call
+const CnnNet& model_net(const tde_model* M);
+int model_device(const tde_model* M);
+size_t cnn_infer_bytes(const CnnNet& net, int B);
+// Decimates (sigs_dev: 2 B descriptors) or takes xdec, runs the encoder and
+// head with activations carved from ws (cnn_infer_bytes), then top-k.
+int cnn_infer(const tde_model* M, const uint16_t* xdec_or_null, int B, uint8_t* ws, int topk, int32_t* top,
+              float* margin, float* logits_out, hipStream_t s, const CnnSig* sigs_dev);
+
 }  // namespace tde

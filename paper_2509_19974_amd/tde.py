@@ -84,6 +84,18 @@ def load_library(path: str = LIB_PATH):
         "tde_argmax_lag": (i32, [vp, vp, i32, i64, i64, vp, vp, sz, vp]),
         "tde_estimate_workspace_size": (sz, [ctypes.POINTER(tde_pair), i64, ctypes.POINTER(tde_opts)]),
         "tde_estimate_batch": (i32, [vp, ctypes.POINTER(tde_pair), i64, ctypes.POINTER(tde_opts), vp, vp, sz, vp]),
+        "tde_model_create": (i32, [vp, i32, i32, ctypes.c_uint64, ctypes.POINTER(vp)]),
+        "tde_model_destroy": (None, [vp]),
+        "tde_model_num_params": (i64, [vp]),
+        "tde_model_get_params": (i32, [vp, vp, i64]),
+        "tde_model_set_params": (i32, [vp, vp, i64]),
+        "tde_model_gradients": (i32, [vp, vp, i64]),
+        "tde_model_save": (i32, [vp, ctypes.c_char_p]),
+        "tde_model_load": (i32, [vp, ctypes.c_char_p]),
+        "tde_model_prepare_workspace_size": (sz, [ctypes.POINTER(tde_pair), i64]),
+        "tde_model_prepare": (i32, [vp, vp, ctypes.POINTER(tde_pair), i64, vp, vp, sz, vp]),
+        "tde_model_forward": (i32, [vp, vp, vp, i64, vp, i32, vp, vp, vp]),
+        "tde_train_step": (i32, [vp, vp, vp, vp, i64, f32, ctypes.POINTER(f32), vp]),
         "tde_tune": (i32, [vp, i32, vp]),
         "tde_tune_query": (i32, [i64, i64, i32, i32, i64, i64]),
         "tde_tune_save": (i32, [ctypes.c_char_p]),
@@ -185,6 +197,80 @@ def tde_estimate_workspace_size(pairs_arr, npairs, opts: tde_opts) -> int:
 def tde_estimate_batch(ctx, pairs_arr, npairs, opts: tde_opts, out, ws, ws_bytes, stream=None):
     _check(load_library().tde_estimate_batch(ctx, pairs_arr, npairs, ctypes.byref(opts), _ptr(out), _ptr(ws),
                                              ws_bytes, _stream(stream)))
+
+
+class Model:
+    """Learned lag-window proposer (tde_model) on the context's device."""
+
+    def __init__(self, ctx: "Context", ld: int = 16384, nbins: int = 512, seed: int = 1):
+        self.ctx = ctx
+        self.ld, self.nbins = ld, nbins
+        h = ctypes.c_void_p()
+        _check(load_library().tde_model_create(ctx.handle, ld, nbins, seed, ctypes.byref(h)))
+        self.handle = h.value
+
+    def close(self):
+        if self.handle:
+            load_library().tde_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_params(self) -> int:
+        return int(load_library().tde_model_num_params(self.handle))
+
+    def get_params(self) -> np.ndarray:
+        a = np.empty(self.num_params, np.float32)
+        _check(load_library().tde_model_get_params(self.handle, a.ctypes.data, a.size))
+        return a
+
+    def set_params(self, a) -> None:
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        _check(load_library().tde_model_set_params(self.handle, a.ctypes.data, a.size))
+
+    def gradients(self) -> np.ndarray:
+        a = np.empty(self.num_params, np.float32)
+        _check(load_library().tde_model_gradients(self.handle, a.ctypes.data, a.size))
+        return a
+
+    def save(self, path: str) -> None:
+        _check(load_library().tde_model_save(self.handle, path.encode()))
+
+    def load(self, path: str) -> None:
+        _check(load_library().tde_model_load(self.handle, path.encode()))
+
+    def prepare(self, specs, stream=None):
+        """Decimated bf16 inputs (int16 tensor [B][2][ld], bf16 bit patterns)."""
+        torch = self.ctx.torch
+        arr, _, _ = self.ctx.batch_plan(specs)
+        n = len(arr)
+        wsb = int(load_library().tde_model_prepare_workspace_size(arr, n))
+        ws = self.ctx._bytes(wsb)
+        out = torch.empty((n, 2, self.ld), dtype=torch.int16, device=self.ctx.device)
+        _check(load_library().tde_model_prepare(self.ctx.handle, self.handle, arr, n, _ptr(out), _ptr(ws), wsb,
+                                                _stream(stream)))
+        return out
+
+    def forward(self, xdec, topk: int = 0, stream=None):
+        torch = self.ctx.torch
+        B = xdec.shape[0]
+        logits = torch.empty((B, self.nbins), dtype=torch.float32, device=self.ctx.device)
+        top = torch.empty((B, max(topk, 1)), dtype=torch.int32, device=self.ctx.device) if topk else None
+        margin = torch.empty(B, dtype=torch.float32, device=self.ctx.device) if topk else None
+        _check(load_library().tde_model_forward(self.ctx.handle, self.handle, _ptr(xdec), B, _ptr(logits), topk,
+                                                _ptr(top), _ptr(margin), _stream(stream)))
+        return logits, top, margin
+
+    def train_step(self, xdec, labels, lr: float, stream=None) -> float:
+        loss = ctypes.c_float(0.0)
+        _check(load_library().tde_train_step(self.ctx.handle, self.handle, _ptr(xdec), _ptr(labels), xdec.shape[0],
+                                             float(lr), ctypes.byref(loss), _stream(stream)))
+        return float(loss.value)
 
 
 def tde_tune(ctx, max_log_n: int = 22, stream=None) -> None:

@@ -493,3 +493,143 @@ def test_batch_config4_full_size_graph_sampled(T, ctx):
     sizes = np.array([p["x"].size for p in pairs])
     for i in list(np.argsort(sizes)[:4]) + list(np.argsort(sizes)[2048:2052]) + [int(np.argmax(sizes))]:
         _check_pair(pk[i], pairs[i])
+
+
+# --------------------------------------------------- learned proposer (CNN) --
+
+from oracle import cnn  # noqa: E402
+
+MID = cnn.Shape(ld=1024, c=32, layers=4, nbins=64)
+
+
+def _bf16_tensor(T, a):
+    """float array -> int16 tensor of bf16 bit patterns (round to nearest even)."""
+    f = np.ascontiguousarray(cnn.bf16_round(a), dtype=np.float32)
+    return dev(T, (f.view(np.uint32) >> 16).astype(np.uint16).view(np.int16))
+
+
+def _mid_params(seed):
+    rng = np.random.default_rng(seed)
+    p = {}
+    for name, sh in cnn.param_sizes(MID):
+        if not sh:
+            p[name] = 2e-3
+        elif name.startswith("W"):
+            p[name] = rng.standard_normal(sh) * np.sqrt(2.0 / (sh[1] * 9))
+        else:
+            p[name] = rng.standard_normal(sh) * 0.1
+    return p
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-30))
+
+
+def test_cnn_forward_matches_oracle(T, ctx):
+    """Logits of the HIP encoder and head against the float64 oracle run with
+    the same bf16 weights and bf16-stored activations: only float32
+    accumulation differs (tolerance 2e-3 relative, per pair)."""
+    from paper_2509_19974_amd import tde
+    say("cnn forward")
+    p = _mid_params(3)
+    pr = cnn.round_params(MID, p, cnn.bf16_round)
+    m = tde.Model(ctx, MID.ld, MID.nbins)
+    m.set_params(cnn.flatten(MID, p).astype(np.float32))
+    rng = np.random.default_rng(4)
+    B = 3
+    xs = cnn.bf16_round(rng.standard_normal((B, 2, MID.ld)))
+    logits, top, margin = m.forward(_bf16_tensor(T, xs), topk=8)
+    T.cuda.synchronize()
+    lg = logits.cpu().numpy()
+    for b in range(B):
+        ref, _ = cnn.forward(MID, pr, xs[b, 0], xs[b, 1], store=cnn.bf16_round)
+        say(f"   pair {b}: logits relative error {_rel(lg[b], ref):.2e}")
+        assert _rel(lg[b], ref) < 2e-3, (b, _rel(lg[b], ref))
+        t_ref, m_ref = cnn.topk_margin(lg[b].astype(np.float64), 8)        # same float32 logits
+        assert top.cpu().numpy()[b].tolist() == t_ref.tolist()
+        assert abs(float(margin.cpu().numpy()[b]) - m_ref) <= 1e-6 * max(1.0, abs(m_ref))
+    m.close()
+
+
+def test_cnn_gradients_match_oracle(T, ctx):
+    """Mean-loss gradients of every parameter tensor (train step with learning
+    rate 0) against the oracle's hand-derived backward pass with the same
+    bf16 storage: relative L2 error below 5e-3 per tensor, loss within 1e-4."""
+    from paper_2509_19974_amd import tde
+    say("cnn gradients")
+    p = _mid_params(5)
+    pr = cnn.round_params(MID, p, cnn.bf16_round)
+    m = tde.Model(ctx, MID.ld, MID.nbins)
+    m.set_params(cnn.flatten(MID, p).astype(np.float32))
+    rng = np.random.default_rng(6)
+    B = 3
+    xs = cnn.bf16_round(rng.standard_normal((B, 2, MID.ld)))
+    labels = np.array([5, 40, 63], np.int32)
+    loss = m.train_step(_bf16_tensor(T, xs), dev(T, labels), 0.0)
+    g = m.gradients()
+    ref_loss, ref_g, _ = cnn.batch_loss_and_grads(MID, pr, xs[:, 0], xs[:, 1], labels, store=cnn.bf16_round)
+    say(f"   loss gpu {loss:.6f} oracle {ref_loss:.6f}")
+    assert abs(loss - ref_loss) <= 1e-3 * max(1.0, abs(ref_loss))
+    ref_flat = cnn.flatten(MID, ref_g)
+    o = 0
+    for name, sh in cnn.param_sizes(MID):
+        k = int(np.prod(sh)) if sh else 1
+        say(f"   {name}: relative error {_rel(g[o:o + k], ref_flat[o:o + k]):.2e}")
+        assert _rel(g[o:o + k], ref_flat[o:o + k]) < 5e-3, (name, _rel(g[o:o + k], ref_flat[o:o + k]))
+        o += k
+    # the learning rate 0 step leaves the parameters unchanged
+    np.testing.assert_array_equal(m.get_params(), cnn.flatten(MID, p).astype(np.float32))
+    m.close()
+
+
+def test_cnn_adam_step_matches_oracle(T, ctx, tmp_path):
+    """Two Adam steps update the float32 masters as the oracle's Adam does on
+    the device's own gradients; save/load round-trips the parameters."""
+    from paper_2509_19974_amd import tde
+    say("cnn adam")
+    p = _mid_params(7)
+    flat0 = cnn.flatten(MID, p).astype(np.float32)
+    m = tde.Model(ctx, MID.ld, MID.nbins)
+    m.set_params(flat0)
+    rng = np.random.default_rng(8)
+    xs = _bf16_tensor(T, rng.standard_normal((2, 2, MID.ld)))
+    labels = dev(T, np.array([1, 2], np.int32))
+    w = flat0.astype(np.float64)
+    mm, vv = np.zeros_like(w), np.zeros_like(w)
+    for step in (1, 2):
+        m.train_step(xs, labels, 1e-3)
+        g = m.gradients().astype(np.float64)
+        w, mm, vv = cnn.adam_step(w, g, mm, vv, step, 1e-3)
+        np.testing.assert_allclose(m.get_params(), w, rtol=1e-5, atol=1e-7)
+    f = str(tmp_path / "model.bin")
+    m.save(f)
+    m2 = tde.Model(ctx, MID.ld, MID.nbins, seed=99)
+    m2.load(f)
+    np.testing.assert_array_equal(m2.get_params(), m.get_params())
+    m.close()
+    m2.close()
+
+
+def test_cnn_prepare_matches_oracle_decimation(T, ctx):
+    """Decimated inputs: block means of 16 over 1/sigma of the b-bit
+    quantizer's scale (bit-exact inv_step), rounded to bf16: equal to the
+    oracle within one bf16 step (float32 sum order)."""
+    from paper_2509_19974_amd import tde
+    say("cnn prepare")
+    m = tde.Model(ctx, MID.ld, MID.nbins)
+    rng = np.random.default_rng(9)
+    specs, raw = [], []
+    for b, bits in enumerate((2, 4, 8)):
+        x = (rng.standard_normal(16 * MID.ld) * (b + 1)).astype(np.float32)
+        y = (rng.standard_normal(16 * MID.ld) * 0.3).astype(np.float32)
+        raw.append((x, y, bits))
+        specs.append(dict(x=dev(T, x), y=dev(T, y), lag_lo=0, lag_hi=0, bits=bits))
+    xd = m.prepare(specs)
+    T.cuda.synchronize()
+    got = (xd.cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    for b, (x, y, bits) in enumerate(raw):
+        for side, sig in enumerate((x, y)):
+            _, _, inv = oracle.quantize(sig, bits)
+            ref = cnn.bf16_round(cnn.decimate(sig, inv, tde.kmax_of_bits(bits), MID.ld))
+            np.testing.assert_allclose(got[b, side], ref, rtol=2 ** -7, atol=0)
+    m.close()
