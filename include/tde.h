@@ -185,12 +185,26 @@ typedef struct {
 #define TDE_MODE_FULL    0
 #define TDE_MODE_LEARNED 1
 
+typedef struct tde_model tde_model;
+
 typedef struct {
-    int32_t mode;        /* TDE_MODE_FULL */
-    int32_t path;        /* TDE_PATH_* forced for every pair, or AUTO */
-    int32_t use_graph;   /* see below */
+    int32_t mode;            /* TDE_MODE_FULL or TDE_MODE_LEARNED */
+    int32_t path;            /* TDE_PATH_* forced for every pair, or AUTO */
+    int32_t use_graph;       /* see below */
+    int32_t topk;            /* learned mode: windows (bins) per pair, 1..16 */
+    const tde_model* model;  /* learned mode: the proposer */
+    float margin;            /* learned mode: full-range fallback below this logit margin */
     int32_t reserved;
 } tde_opts;
+
+/* TDE_MODE_LEARNED: the model scores the nbins lag bins of every pair (see
+ * the learned model section); if the margin logit_(1) - logit_(topk+1) is at
+ * least opts->margin, the exact correlation runs only on the topk best bins
+ * and out[i] is the argmax (smallest lag, max, count) of r restricted to
+ * their union; otherwise the pair falls back to the full lag range and
+ * out[i].flags carries TDE_FLAG_FALLBACK. Requirements: every pair has
+ * nx = ny = 16 ld, bits in {2,4,8}, lag_lo = -(nbins/2) 256 and lag_hi =
+ * (nbins/2) 256 - 1 (the union of the bins), r_out NULL; path AUTO or MFMA. */
 
 /* use_graph = 1: the first call with a given signature (the bytes of the
  * pairs array, opts, ws, ws_bytes and out) waits for the caller's stream,
@@ -234,8 +248,6 @@ int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs_host, int64_t npairs,
  * These are support calls, not hot calls: they may allocate device memory
  * (model parameters, training buffers sized for the largest batch seen) and
  * synchronize. xdec arrays hold bf16 bit patterns, [B][2][ld] (x then y). */
-typedef struct tde_model tde_model;
-
 /* ld: multiple of 256 in [256, 2^20]; nbins: multiple of 64, at most 2 ld/16
  * and 4096. Weights start He-normal from `seed`, biases 0, alpha 1/(32 F). */
 int tde_model_create(tde_ctx* ctx, int ld, int nbins, uint64_t seed, tde_model** out);

@@ -365,6 +365,7 @@ __global__ void __launch_bounds__(256, MB == 4 ? 2 : 1) k_xcorr_mfma(const XItem
         if (wi >= nwork) break;
         const MWork wk = work[wi];
         const XItem& it = items ? items[wk.pair] : one;
+        if (it.margin && *it.margin >= it.theta) continue;   // learned mode: windows suffice
         mfma_item<MB>(it, wk, lds, tile_parts);     // the list holds only items of this variant
         __syncthreads();
     }
@@ -381,10 +382,20 @@ __global__ void __launch_bounds__(64) k_tiles_final(const XItem* items, XItem on
     const int pi = blockIdx.x;
     const XItem& it = items ? items[pi] : one;
     if (!it.fused) return;
-    Tri64 t{it.out_v, it.out_i, it.out_c};
-    for (int64_t k = threadIdx.x; k < it.ntiles; k += 64) {
-        ArgPart a = tile_parts[it.part_base + k];
-        t = tri_join(t, Tri64{a.vmax, a.idx, a.cnt});
+    // learned mode: the proposed windows, unless the pair fell back
+    const bool windows = it.margin && *it.margin >= it.theta;
+    Tri64 t{INT64_MIN, INT64_MAX, 0};
+    if (windows) {
+        for (int k = threadIdx.x; k < it.nwin; k += 64) {
+            ArgPart a = it.win_parts[k];
+            t = tri_join(t, Tri64{a.vmax, a.idx, a.cnt});
+        }
+    } else {
+        if (threadIdx.x == 0) t = Tri64{it.out_v, it.out_i, it.out_c};
+        for (int64_t k = threadIdx.x; k < it.ntiles; k += 64) {
+            ArgPart a = tile_parts[it.part_base + k];
+            t = tri_join(t, Tri64{a.vmax, a.idx, a.cnt});
+        }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -392,7 +403,8 @@ __global__ void __launch_bounds__(64) k_tiles_final(const XItem* items, XItem on
         t = tri_join(t, u);
     }
     if (threadIdx.x == 0) {
-        const int flags = peak_flags(it.stat_x, it.p.nu, it.stat_y, it.p.nv);
+        const int flags = peak_flags(it.stat_x, it.p.nu, it.stat_y, it.p.nv) |
+                          (it.margin && !windows ? TDE_FLAG_FALLBACK : 0);
         tde_peak pk;
         pk.lag = it.p.lag_lo + t.i;
         pk.rmax = t.v;

@@ -469,8 +469,31 @@ int validate_pairs(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
     if (!pairs || np < 1) return set_error(TDE_ERR_ARG, "tde_estimate_batch: no pairs");
     if (np > 65535) return set_error(TDE_ERR_ARG, "tde_estimate_batch: at most 65535 pairs per call");
     int path = opts ? opts->path : TDE_PATH_AUTO;
-    if (opts && opts->mode != TDE_MODE_FULL)
-        return set_error(TDE_ERR_UNSUPPORTED, "tde_estimate_batch: only TDE_MODE_FULL is available");
+    const bool learned = opts && opts->mode == TDE_MODE_LEARNED;
+    if (opts && opts->mode != TDE_MODE_FULL && !learned)
+        return set_error(TDE_ERR_ARG, "tde_estimate_batch: unknown mode %d", opts->mode);
+    if (learned) {
+        if (!opts->model) return set_error(TDE_ERR_ARG, "tde_estimate_batch: learned mode needs a model");
+        if (opts->topk < 1 || opts->topk > kCnnMaxTop || opts->topk >= model_net(opts->model).nb)
+            return set_error(TDE_ERR_ARG, "tde_estimate_batch: topk must be in [1, %d]", kCnnMaxTop);
+        if (!std::isfinite(opts->margin)) return set_error(TDE_ERR_ARG, "tde_estimate_batch: non-finite margin");
+        if (path != TDE_PATH_AUTO && path != TDE_PATH_MFMA)
+            return set_error(TDE_ERR_ARG, "tde_estimate_batch: learned mode falls back on TDE_PATH_MFMA");
+        const CnnNet& net = model_net(opts->model);
+        const int64_t n = 16 * (int64_t)net.ld, half = (int64_t)(net.nb / 2) * 256;
+        for (int64_t i = 0; i < np; ++i) {
+            const tde_pair& q = pairs[i];
+            if (q.nx != n || q.ny != n || q.lag_lo != -half || q.lag_hi != half - 1 || q.r_out ||
+                (q.bits != 2 && q.bits != 4 && q.bits != 8))
+                return set_error(TDE_ERR_ARG,
+                                 "pair %lld: learned mode needs nx = ny = %lld, lags [%lld, %lld], bits 2/4/8, no r_out",
+                                 (long long)i, (long long)n, (long long)-half, (long long)(half - 1));
+            // each window wave sums a quarter of the m range in int32
+            const int K = kmax_of_bits(q.bits);
+            if ((__int128)(n / 4 + 128) * K * K >= ((__int128)1 << 31))
+                return set_error(TDE_ERR_UNSUPPORTED, "pair %lld: signals too long for int32 window sums", (long long)i);
+        }
+    }
     for (int64_t i = 0; i < np; ++i) {
         const tde_pair& q = pairs[i];
         if (!q.x || !q.y) return set_error(TDE_ERR_ARG, "pair %lld: null signal", (long long)i);
@@ -530,10 +553,10 @@ void outside_triple(int64_t lo, int64_t hi, int64_t c_lo, int64_t c_hi, XItem& i
     }
 }
 
-PairPlan plan_pair(const tde_pair& q, int path) {
+PairPlan plan_pair(const tde_pair& q, int path, bool learned) {
     PairPlan pp{};
     const int K = kmax_of_bits(q.bits);
-    pp.eng = choose_path(path, q.nx, q.ny, K * K, q.lag_lo, q.lag_hi);
+    pp.eng = learned ? TDE_PATH_MFMA : choose_path(path, q.nx, q.ny, K * K, q.lag_lo, q.lag_hi);
     pp.rdt = q.r_out ? q.r_dtype
                      : ((__int128)max_overlap(q.nx, q.ny, q.lag_lo, q.lag_hi) * K * K < ((__int128)1 << 31) ? TDE_I32
                                                                                                           : TDE_I64);
@@ -571,6 +594,12 @@ struct BatchPlan {
     };
     std::vector<NGroup> ngroups;
     std::vector<size_t> off_res;    // per pair (NTT residues)
+    // learned mode
+    bool learned = false;
+    const tde_model* model = nullptr;
+    int topk = 0;
+    float theta = 0.f;
+    size_t off_csig = 0, off_cnn = 0, off_top = 0, off_margin = 0, off_wparts = 0;
     std::vector<PairPlan> pp;
     std::vector<size_t> off_q;      // per signal (2 per pair)
     std::vector<size_t> off_gsum;   // per signal
@@ -587,9 +616,10 @@ BatchPlan plan_batch(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
         return o;
     };
     const int path = opts ? opts->path : TDE_PATH_AUTO;
+    B.learned = opts && opts->mode == TDE_MODE_LEARNED;
     B.pp.resize(np);
     for (int64_t i = 0; i < np; ++i) {
-        B.pp[i] = plan_pair(pairs[i], path);
+        B.pp[i] = plan_pair(pairs[i], path, B.learned);
         const PairPlan& pp = B.pp[i];
         if (pp.eng == TDE_PATH_MFMA) {
             B.nwork += mfma_count_items(pp.probe);
@@ -616,12 +646,22 @@ BatchPlan plan_batch(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
     B.off_items = take(sizeof(XItem) * np);
     B.off_segs = take(sizeof(ArgSeg) * (B.nsegs ? B.nsegs : 1));
     B.off_jobs = take(sizeof(NttJob) * (B.njobs ? B.njobs : 1));
+    if (B.learned) B.off_csig = take(sizeof(CnnSig) * 2 * np);     // uploaded with the descriptors
     B.off_work = take(sizeof(MWork) * (B.nwork ? B.nwork : 1));
     B.off_counters = take(2 * sizeof(int));
     B.off_tparts = take(sizeof(ArgPart) * (B.ntparts ? B.ntparts : 1));
     B.off_stats = take(sizeof(tde_qstat) * 2 * np);
     B.off_inv = take(sizeof(float) * 2 * np);
     B.off_parts = take(sizeof(ArgPart) * (B.total_parts ? B.total_parts : 1));
+    if (B.learned) {
+        B.model = opts->model;
+        B.topk = opts->topk;
+        B.theta = opts->margin;
+        B.off_cnn = take(cnn_infer_bytes(model_net(B.model), (int)np));
+        B.off_top = take(sizeof(int32_t) * np * B.topk);
+        B.off_margin = take(sizeof(float) * np);
+        B.off_wparts = take(sizeof(ArgPart) * np * B.topk);
+    }
     B.off_q.resize(2 * np);
     B.off_gsum.resize(2 * np);
     B.off_r.assign(np, 0);
@@ -714,6 +754,12 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
         it.stat_y = stats + 2 * i + 1;
         it.peak = out + i;
         it.fused = pp.fused ? 1 : 0;
+        if (B.learned) {
+            it.margin = reinterpret_cast<const float*>(W + B.off_margin) + i;
+            it.theta = B.theta;
+            it.nwin = B.topk;
+            it.win_parts = reinterpret_cast<const ArgPart*>(W + B.off_wparts) + i * B.topk;
+        }
         if (it.p.r) {
             L.any_r = true;
             L.max_rbytes = std::max<int64_t>(L.max_rbytes, (q.lag_hi - q.lag_lo + 1) * (pp.rdt == TDE_I32 ? 4 : 8));
@@ -796,6 +842,13 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
     if (!segs.empty()) memcpy(L.blob.data() + B.off_segs, segs.data(), sizeof(ArgSeg) * segs.size());
     if (!work.empty()) memcpy(L.blob.data() + B.off_work, work.data(), work.size() * sizeof(MWork));
     if (!jobs.empty()) memcpy(L.blob.data() + B.off_jobs, jobs.data(), jobs.size() * sizeof(NttJob));
+    if (B.learned) {
+        CnnSig* cs = reinterpret_cast<CnnSig*>(L.blob.data() + B.off_csig);
+        for (int64_t k = 0; k < 2 * np; ++k) {
+            const QSig& S = sigs[k];
+            cs[k] = CnnSig{S.x, S.inv_out, 6.f / (float)(2 * kmax_of_bits(S.bits) + 1)};
+        }
+    }
 }
 
 // Queues the kernels of a prepared batch on s (the descriptors are already in
@@ -820,6 +873,17 @@ int batch_enqueue(tde_ctx* ctx, uint8_t* W, const BatchPlan& B, const BatchLaunc
         if (rc) return rc;
     }
     hipEvent_t t_e0 = mk();
+    if (B.learned) {
+        // proposer: decimate + encoder + head + top-k, then the windows
+        int32_t* top = reinterpret_cast<int32_t*>(W + B.off_top);
+        float* margin = reinterpret_cast<float*>(W + B.off_margin);
+        rc = cnn_infer(B.model, nullptr, (int)L.np, W + B.off_cnn, B.topk, top, margin, nullptr, s,
+                       reinterpret_cast<const CnnSig*>(W + B.off_csig));
+        if (rc) return rc;
+        rc = launch_xcorr_win(items_dev, (int)L.np, top, margin, B.theta, B.topk, model_net(B.model).nb,
+                              reinterpret_cast<ArgPart*>(W + B.off_wparts), s);
+        if (rc) return rc;
+    }
     if (L.any_popc) {
         // zero the plane buffers (padding must read as 0), then pack
         for (const auto& z : L.plane_zero) {

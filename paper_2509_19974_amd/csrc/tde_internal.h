@@ -134,6 +134,12 @@ struct XItem {
     const uint32_t* vnz;
     int64_t nuw;          // u words
     int64_t nvw;          // v words
+    // learned mode: the pair's proposal margin; at or above theta the result
+    // comes from the nwin window triples, below it from the full range
+    const float* margin;  // null outside learned mode
+    float theta;
+    int32_t nwin;
+    const ArgPart* win_parts;
 };
 
 // zero the r arrays of a batch
@@ -175,6 +181,10 @@ int launch_xcorr_popc(const XItem* items_dev, const XItem& one, int nitems, int6
 
 // int8 copy helper
 int launch_copy_bytes(void* dst, const void* src, size_t n, hipStream_t s);
+
+// windowed exact engine (learned mode): grid npairs x topk windows of 256 lags
+int launch_xcorr_win(const XItem* items_dev, int npairs, const int32_t* top, const float* margin, float theta,
+                     int topk, int nb, ArgPart* parts, hipStream_t s);
 
 // ---------------------------------------------------------- auto engine --
 // HIP device of a context.

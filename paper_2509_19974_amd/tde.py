@@ -50,6 +50,7 @@ class tde_pair(ctypes.Structure):
 
 class tde_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("path", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("topk", ctypes.c_int32), ("model", ctypes.c_void_p), ("margin", ctypes.c_float),
                 ("reserved", ctypes.c_int32)]
 
 
@@ -377,7 +378,8 @@ class Context:
         tde_argmax_lag(self.handle, r, r_dtype, lag_lo, lag_hi, out, ws, wsb, stream)
         return out
 
-    def batch_plan(self, specs, path=TDE_PATH_AUTO, mode=TDE_MODE_FULL, use_graph=0):
+    def batch_plan(self, specs, path=TDE_PATH_AUTO, mode=TDE_MODE_FULL, use_graph=0, model=None, topk=8,
+                   margin=0.0):
         """specs: list of dicts with x, y (device float32 tensors), lag_lo, lag_hi,
         bits, optional inv_step_x/y, r_out, r_dtype. Returns (pairs array, opts,
         workspace bytes)."""
@@ -395,7 +397,8 @@ class Context:
             p.r_dtype = int(s.get("r_dtype", TDE_I64))
             pairs.append(p)
         arr = make_pairs(pairs)
-        opts = tde_opts(mode, path, int(use_graph), 0)
+        opts = tde_opts(mode, path, int(use_graph), int(topk), model.handle if model is not None else None,
+                        float(margin), 0)
         wsb = tde_estimate_workspace_size(arr, len(pairs), opts)
         if wsb == 0:
             raise TDEError(TDE_ERR_ARG, tde_last_error())

@@ -158,16 +158,17 @@ def config5_reverb(npairs: int = 1024, n: int = 1 << 18, max_lag: int = 1 << 16,
                    t60_range=(2000, 12000)):
     """Reverberant pairs: x = white noise through a random response with a
     60 dB decay over T ~ U[2000, 12000] samples; y = x delayed by
-    d ~ U{-max_lag..max_lag} plus noise at SNR ~ U[0,30] dB; b = 4."""
+    d ~ U{-max_lag..max_lag-1} plus noise at SNR ~ U[0,30] dB; b = 4; lags
+    [-max_lag, max_lag - 1] (the union of the proposer's 256-lag bins)."""
     out = []
     for rng in pair_rngs(5, npairs, salt):
         t60 = int(rng.integers(t60_range[0], t60_range[1] + 1))
         h = reverb_response(rng, t60)
         x = filtered_noise(rng, n, h)
-        d = int(rng.integers(-max_lag, max_lag + 1))
+        d = int(rng.integers(-max_lag, max_lag))
         snr = float(rng.uniform(0.0, 30.0))
         xf, yf = make_pair(rng, x, d, snr)
-        out.append(dict(x=xf, y=yf, d=d, bits=4, lag_lo=-max_lag, lag_hi=max_lag, snr_db=snr, t60=t60))
+        out.append(dict(x=xf, y=yf, d=d, bits=4, lag_lo=-max_lag, lag_hi=max_lag - 1, snr_db=snr, t60=t60))
     return out
 
 

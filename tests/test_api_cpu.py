@@ -36,11 +36,41 @@ def test_status_strings():
     assert tde.tde_status_string(-99) == "unknown status"
 
 
-def test_struct_sizes_match_header():
-    assert tde.PEAK_DTYPE.itemsize == 24
-    assert tde.QSTAT_DTYPE.itemsize == 40
-    assert ctypes.sizeof(tde.tde_pair) == 8 * 6 + 4 * 4 + 8
-    assert ctypes.sizeof(tde.tde_opts) == 16
+def test_struct_sizes_match_header(tmp_path):
+    """The binding's struct layouts equal what a C compiler makes of
+    include/tde.h (sizes and every field offset)."""
+    structs = {"tde_peak": ["lag", "rmax", "n_ties", "flags"],
+               "tde_qstat": ["inv_step", "flags", "n_nonfinite", "n_zero", "sum_q", "sum_q2"],
+               "tde_pair": ["x", "y", "nx", "ny", "lag_lo", "lag_hi", "bits", "inv_step_x", "inv_step_y",
+                            "r_dtype", "r_out"],
+               "tde_opts": ["mode", "path", "use_graph", "topk", "model", "margin", "reserved"]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{os.path.join(ROOT, "include", "tde.h")}"',
+             "int main(void) {"]
+    for st, fields in structs.items():
+        lines.append(f'printf("{st} size %zu\\n", sizeof({st}));')
+        for f in fields:
+            lines.append(f'printf("{st} {f} %zu\\n", offsetof({st}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n"):
+        if line:
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    ctypes_of = {"tde_pair": tde.tde_pair, "tde_opts": tde.tde_opts}
+    for st, cls in ctypes_of.items():
+        assert got[(st, "size")] == ctypes.sizeof(cls), st
+        for f in structs[st]:
+            assert got[(st, f)] == getattr(cls, f).offset, (st, f)
+    np_of = {"tde_peak": tde.PEAK_DTYPE, "tde_qstat": tde.QSTAT_DTYPE}
+    for st, dt in np_of.items():
+        assert got[(st, "size")] == dt.itemsize, st
+        for f in structs[st]:
+            assert got[(st, f)] == dt.fields[f][1], (st, f)
 
 
 def test_workspace_sizes():
@@ -120,7 +150,7 @@ def test_batch_argument_validation():
         p.r_dtype = k.get("dt", tde.TDE_I64)
         p.r_out = k.get("r", None)
         return p
-    opts = tde.tde_opts(tde.TDE_MODE_FULL, tde.TDE_PATH_AUTO, 0, 0)
+    opts = tde.tde_opts(tde.TDE_MODE_FULL, tde.TDE_PATH_AUTO, 0, 0, None, 0.0, 0)
     good = tde.make_pairs([pair(), pair(nx=7, ny=300, bits=1)])
     assert tde.tde_estimate_workspace_size(good, 2, opts) > 0
     for bad in (pair(bits=5), pair(lo=3, hi=2), pair(nx=0), pair(sx=float("nan"))):

@@ -633,3 +633,114 @@ def test_cnn_prepare_matches_oracle_decimation(T, ctx):
             ref = cnn.bf16_round(cnn.decimate(sig, inv, tde.kmax_of_bits(bits), MID.ld))
             np.testing.assert_allclose(got[b, side], ref, rtol=2 ** -7, atol=0)
     m.close()
+
+
+def test_batch_maximum_is_zero_outside_the_tiles(T, ctx):
+    """x a single pulse and y = -x: r is -K^2 at lag 0 and 0 everywhere else,
+    so the maximum 0 is shared by every other lag, including the lags no tile
+    covers (the requested range reaches far past the support)."""
+    from paper_2509_19974_amd import tde
+    say("batch zero maximum outside the tiles")
+    pairs = []
+    for n, lo, hi in ((3000, -20000, 20000), (5000, -4999, 30000), (700, 900, 5000)):
+        x = np.zeros(n, np.float32)
+        x[n // 3] = 1.0
+        pairs.append(dict(x=x, y=(-x).copy(), lag_lo=lo, lag_hi=hi, bits=4))
+    for path in (0, tde.TDE_PATH_NTT):
+        pk, specs = _batch(T, ctx, pairs, path, want_r=False)
+        for i, p in enumerate(pairs):
+            res = _check_pair(pk[i], p)
+            assert res["rmax"] == 0
+
+
+# -------------------------------------------------------- learned windows --
+
+def _learned_case(T, ctx, model, pairs, topk, theta):
+    """Runs the learned batch and the proposer alone on the same pairs; the
+    oracle then applies the documented semantics to the GPU's proposals."""
+    from paper_2509_19974_amd import tde
+    specs = [dict(x=dev(T, p["x"]), y=dev(T, p["y"]), lag_lo=p["lag_lo"], lag_hi=p["lag_hi"], bits=p["bits"])
+             for p in pairs]
+    plan = ctx.batch_plan(specs, mode=tde.TDE_MODE_LEARNED, model=model, topk=topk, margin=theta)
+    out = ctx.estimate_batch(specs, plan=plan)
+    xd = model.prepare(specs)
+    _, top, margin = model.forward(xd, topk=topk)
+    T.cuda.synchronize()
+    return tde.decode_peaks(out), top.cpu().numpy(), margin.cpu().numpy()
+
+
+def _check_learned(pk, top, margin, pairs, theta, nbins):
+    from paper_2509_19974_amd import tde
+    nfall = 0
+    for i, p in enumerate(pairs):
+        u, _, _ = oracle.quantize(p["x"], p["bits"])
+        v, _, _ = oracle.quantize(p["y"], p["bits"])
+        if margin[i] >= theta:
+            assert not pk[i]["flags"] & tde.TDE_FLAG_FALLBACK
+            lag, rmax, nt = cnn.windowed_argmax(u, v, top[i].tolist(), 256, nbins)
+        else:
+            nfall += 1
+            assert pk[i]["flags"] & tde.TDE_FLAG_FALLBACK
+            lag, rmax, nt = oracle.argmax(oracle.xcorr(u, v, p["lag_lo"], p["lag_hi"]), p["lag_lo"])
+        assert (pk[i]["lag"], pk[i]["rmax"], pk[i]["n_ties"]) == (lag, rmax, nt), i
+    return nfall
+
+
+def test_learned_batch_matches_window_semantics(T, ctx):
+    """Learned mode with an untrained proposer (ld 1024, 64 bins, N = 16384):
+    with the margin threshold at the median, some pairs use their 8 proposed
+    windows and the rest fall back; every result must equal the oracle's
+    argmax over the union of the GPU's proposed bins, or over the full range
+    for the pairs whose margin is below the threshold."""
+    from paper_2509_19974_amd import tde
+    say("learned batch semantics")
+    model = tde.Model(ctx, 1024, 64, seed=3)
+    pairs = synth.config5_reverb(npairs=24, n=16384, max_lag=64 * 128, t60_range=(200, 1200))
+    pk, top, margin = _learned_case(T, ctx, model, pairs, 8, 0.0)
+    theta = float(np.median(margin))
+    pk, top, margin = _learned_case(T, ctx, model, pairs, 8, theta)
+    nfall = _check_learned(pk, top, margin, pairs, theta, 64)
+    assert 0 < nfall < len(pairs)
+    # all windows / all fallback
+    for th in (-1e30, 1e30):
+        pk, top, margin = _learned_case(T, ctx, model, pairs[:6], 5, th)
+        _check_learned(pk, top, margin, pairs[:6], th, 64)
+    model.close()
+
+
+def test_learned_batch_full_size_windows(T, ctx):
+    """The full-size proposer shape (ld 16384, 512 bins of 256 lags over
+    [-65536, 65535], N = 2^18, b = 4) on 8 pairs, every pair on its 8 windows
+    (threshold -inf); also captured in a HIP graph."""
+    from paper_2509_19974_amd import tde
+    say("learned batch full size")
+    model = tde.Model(ctx, 16384, 512, seed=4)
+    pairs = synth.config5_reverb(npairs=8, n=1 << 18, max_lag=1 << 16, salt=9)
+    pk, top, margin = _learned_case(T, ctx, model, pairs, 8, -1e30)
+    _check_learned(pk, top, margin, pairs, -1e30, 512)
+    specs = [dict(x=dev(T, p["x"]), y=dev(T, p["y"]), lag_lo=p["lag_lo"], lag_hi=p["lag_hi"], bits=p["bits"])
+             for p in pairs]
+    plan = ctx.batch_plan(specs, mode=tde.TDE_MODE_LEARNED, model=model, topk=8, margin=-1e30, use_graph=1)
+    ws = T.empty(plan[2], dtype=T.uint8, device="cuda")
+    out = T.empty(len(specs) * 24, dtype=T.uint8, device="cuda")
+    for _ in range(3):
+        ctx.estimate_batch(specs, ws=ws, out=out, plan=plan)
+    T.cuda.synchronize()
+    assert tde.decode_peaks(out).tobytes() == pk.tobytes()
+    model.close()
+
+
+def test_learned_training_reduces_loss(T, ctx):
+    """A few Adam steps on a fixed batch of labelled pairs lower the loss."""
+    from paper_2509_19974_amd import tde
+    say("learned training smoke")
+    model = tde.Model(ctx, 1024, 64, seed=5)
+    pairs = synth.config5_reverb(npairs=32, n=16384, max_lag=64 * 128, t60_range=(200, 1200), salt=2)
+    specs = [dict(x=dev(T, p["x"]), y=dev(T, p["y"]), lag_lo=p["lag_lo"], lag_hi=p["lag_hi"], bits=p["bits"])
+             for p in pairs]
+    xd = model.prepare(specs)
+    labels = dev(T, np.array([cnn.label_of_lag(p["d"], 64, 256) for p in pairs], np.int32))
+    losses = [model.train_step(xd, labels, 3e-3) for _ in range(30)]
+    say(f"   loss {losses[0]:.3f} -> {losses[-1]:.3f}")
+    assert losses[-1] < 0.7 * losses[0]
+    model.close()
