@@ -178,6 +178,120 @@ def cpu_baseline(pairs, budget_s: float = 12.0):
             "int_mac_per_s": macs / el}
 
 
+def _gen_c5(args_):
+    n, npairs, salt = args_
+    import synth
+    return synth.config5_reverb(npairs=npairs, n=n, max_lag=n // 4, salt=salt)
+
+
+def run_c5(args):
+    """Learned lag-window proposal on reverberant pairs (N = 2^18, b = 4, lags
+    [-2^16, 2^16 - 1]): train the proposer on pairs labelled by the exact
+    plain estimator, tune the fallback margin on a validation set, then time
+    the plain and the learned paths (HIP-graph replays) on 1024 held-out
+    pairs and count the lags that differ from the full search."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    n = 1 << 18
+    chunk = 128
+    ntrain, nval, neval = args.c5_train, 512, 1024
+    pool = cf.ProcessPoolExecutor(max_workers=args.c5_workers, mp_context=mp.get_context("spawn"))
+    jobs = {"train": [pool.submit(_gen_c5, (n, chunk, 1000 + k)) for k in range(ntrain // chunk)],
+            "val": [pool.submit(_gen_c5, (n, chunk, 500 + k)) for k in range(nval // chunk)],
+            "eval": [pool.submit(_gen_c5, (n, chunk, k)) for k in range(neval // chunk)]}
+    import numpy as np
+    import torch
+    from paper_2509_19974_amd import tde, learned
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ctx = tde.Context(0)
+    model = tde.Model(ctx, n // 16, 512, seed=1)
+    t0 = time.perf_counter()
+
+    def chunks(name):
+        for f in jobs[name]:
+            yield f.result()
+
+    xtr, ltr = learned.make_dataset(ctx, model, chunks("train"))
+    log(f"[bench] c5 training set ready: {xtr.shape[0]} pairs, {time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = learned.train(ctx, model, xtr, ltr, args.c5_epochs, 64, args.c5_lr, log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    del xtr, ltr
+    val = [p for c in chunks("val") for p in c]
+    vspecs = learned.specs_of(torch, val)
+    vtruth = learned.plain_peaks(ctx, vspecs)
+    vtop, vmargin = learned.proposals(model, model.prepare(vspecs), 8)
+    theta = learned.tune_threshold(vtop, vmargin, vtruth["lag"], 512, 0.0, args.c5_safety)
+    del vspecs
+    log(f"[bench] c5 threshold {theta:.4f}")
+    ev = [p for c in chunks("eval") for p in c]
+    pool.shutdown()
+    specs = learned.specs_of(torch, ev)
+    d = np.array([p["d"] for p in ev])
+
+    def timed(plan):
+        ws = torch.empty(plan[2], dtype=torch.uint8, device="cuda")
+        out = torch.empty(len(specs) * 24, dtype=torch.uint8, device="cuda")
+        for _ in range(max(args.warmup, 1)):
+            ctx.estimate_batch(specs, ws=ws, out=out, plan=plan)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            ctx.estimate_batch(specs, ws=ws, out=out, plan=plan)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps, tde.decode_peaks(out)
+
+    plain_ms, plain = timed(ctx.batch_plan(specs, use_graph=1))
+    learn_ms, lrn = timed(ctx.batch_plan(specs, mode=tde.TDE_MODE_LEARNED, model=model, topk=8, margin=theta,
+                                         use_graph=1))
+    _, lrn0 = timed(ctx.batch_plan(specs, mode=tde.TDE_MODE_LEARNED, model=model, topk=8, margin=-3.0e38,
+                                   use_graph=1))
+
+    def differ(a, b):
+        return float(np.mean((a["lag"] != b["lag"]) | (a["rmax"] != b["rmax"]) | (a["n_ties"] != b["n_ties"])))
+
+    fallback = float(np.mean((lrn["flags"] & tde.TDE_FLAG_FALLBACK) != 0))
+    # stage timing of one eager learned call: CNN + windows (+ fallback) is the engine stage
+    tde.tde_timing_read(ctx.handle)
+    tde.tde_timing_enable(ctx.handle, True)
+    lplan = ctx.batch_plan(specs, mode=tde.TDE_MODE_LEARNED, model=model, topk=8, margin=theta)
+    for _ in range(3):
+        ctx.estimate_batch(specs, plan=lplan)
+    torch.cuda.synchronize()
+    stage_ms, stage_n = tde.tde_timing_read(ctx.handle)
+    tde.tde_timing_enable(ctx.handle, False)
+    engine_ms = stage_ms[1] / max(stage_n[1], 1)
+    cnn_macs = 2 * (16384 * 32 * 9 + (8192 + 4096 + 2048) * 32 * 32 * 9) + 512 * 1024 * 32
+    win_macs = 8 * 256 * n
+    result = {
+        "metric": "pairs/s and int-MAC/s vs FP32-FFT xcorr on MI355X at oracle-exact lags",
+        "value": len(ev) * 1e3 / learn_ms, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": learn_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "i8+bf16", "data": "synthetic",
+        "config": {"workload": "1024 reverberant pairs, N=2^18, b=4, lags [-2^16, 2^16-1], learned windows (top-8 of "
+                               "512 bins, fallback below the tuned margin)", "pairs": len(ev), "n": n},
+        "plain": {"pairs_per_s": len(ev) * 1e3 / plain_ms, "ms_per_step": plain_ms},
+        "speedup_learned_over_plain": plain_ms / learn_ms,
+        "differ_from_full_search": {"before_fallback": differ(lrn0, plain), "after_fallback": differ(lrn, plain)},
+        "fallback_fraction": fallback, "threshold": theta,
+        "lag_accuracy": {"plain": float(np.mean(plain["lag"] == d)), "learned": float(np.mean(lrn["lag"] == d))},
+        "training": {"pairs": ntrain, "epochs": args.c5_epochs, "pairs_per_s": ntrain * args.c5_epochs / train_s,
+                     "loss": hist},
+        "stage_ms": {"quantize": stage_ms[0] / max(stage_n[0], 1), "engine": engine_ms,
+                     "argmax": stage_ms[2] / max(stage_n[2], 1)},
+        "roofline": {"bound": "alu", "achieved": 2.0 * cnn_macs * len(ev) / (engine_ms * 1e-3) / 1e12,
+                     "peak": 157.3, "unit": "TFLOP/s", "frac": 2.0 * cnn_macs * len(ev) / (engine_ms * 1e-3) / 1e12 / 157.3,
+                     "traffic": None, "kernel": "engine stage (CNN forward + windows + fallback), CNN FLOPs only",
+                     "alg_cnn_macs_per_pair": cnn_macs, "alg_window_macs_per_pair": win_macs},
+    }
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +303,12 @@ def main():
                     help="time eager calls instead of HIP-graph replays of the whole call")
     ap.add_argument("--tune", action="store_true", help="run the engine autotuner before planning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--c5-train", type=int, default=8192, help="learned workload: training pairs")
+    ap.add_argument("--c5-epochs", type=int, default=4)
+    ap.add_argument("--c5-lr", type=float, default=1e-3)
+    ap.add_argument("--c5-workers", type=int, default=16)
+    ap.add_argument("--c5-safety", type=float, default=0.02,
+                    help="learned workload: share of validation margins below the fallback threshold")
     ap.add_argument("--no-fft", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain device copy of this many bytes (scales HBM counters)")
@@ -207,6 +327,9 @@ def main():
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
               "the pairs of a batch are independent, see the sharding note in DESIGN.md", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "c5":
+        run_c5(args)
+        return
 
     import numpy as np
     import torch

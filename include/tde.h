@@ -193,7 +193,8 @@ typedef struct {
     int32_t use_graph;       /* see below */
     int32_t topk;            /* learned mode: windows (bins) per pair, 1..16 */
     const tde_model* model;  /* learned mode: the proposer */
-    float margin;            /* learned mode: full-range fallback below this logit margin */
+    float margin;            /* learned mode: full-range fallback below this logit margin
+                                (-inf: never, +inf: always; NaN is rejected) */
     int32_t reserved;
 } tde_opts;
 

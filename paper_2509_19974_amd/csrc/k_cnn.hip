@@ -100,67 +100,99 @@ __global__ void __launch_bounds__(256) k_conv1_fwd(const uint16_t* X, const floa
     for (int q = 0; q < 4; ++q) pd[q] = reinterpret_cast<const uint4*>(po)[q];
 }
 
-// -------------------------------------------------------- conv layers 1+ --
-// 32 -> 32 channels. grid (L / 128, nsig); a workgroup makes 128 conv
-// positions (64 pooled) x 32 channels; thread -> pooled position tp (0..63)
-// and channel group cg (0..3, 8 channels).
-constexpr int kTile = 128;
+constexpr int kTile = 128;           // backward-data tile (positions)
 constexpr int kXs = kTile + 8;       // input rows with halo
 
+// ------------------------------------------------ conv layers 1+ (MFMA) --
+// Implicit GEMM on the bf16 matrix cores (v_mfma_f32_32x32x16_bf16):
+//   C[o][t] = sum_kk A[o][kk] B[kk][t],  kk = 32 tap + i,
+//   A[o][kk] = W[o][i][tap],  B[kk][t] = X[t + tap - 4][i]
+// One matrix instruction per block of 16 kk (fixed tap, 16 channels): 18 per
+// 32 x 32 output tile. The weights of a layer sit in registers as 18
+// per-lane fragments (packed once per weight update); the B fragment of a
+// lane is 8 consecutive channels of one input position, one 16-byte LDS
+// read. A workgroup stages 512 + 8 input rows; each wave makes 4 tiles.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int kMPos = 512;                 // positions per workgroup
+constexpr int kMRow = 80;                  // LDS bytes per staged row (64 + pad)
+
+// frag[b][lane] (8 bf16): row o = lane % 32, kk = 16 b + 8 (lane / 32) + j
+__global__ void k_pack_wfrag(const float* W, uint4* frag) {
+    const int b = blockIdx.x, lane = threadIdx.x;
+    const int o = lane & 31, tap = b >> 1, i0 = 16 * (b & 1) + 8 * (lane >> 5);
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t lo = f2bf(W[(o * kCnnC + i0 + 2 * q) * kCnnK + tap]);
+        const uint32_t hi = f2bf(W[(o * kCnnC + i0 + 2 * q + 1) * kCnnK + tap]);
+        w[q] = lo | (hi << 16);
+    }
+    frag[b * 64 + lane] = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 template <bool SAVE>
-__global__ void __launch_bounds__(256) k_conv32_fwd(const uint16_t* X, const float* W, const float* bias,
-                                                    uint16_t* Z, uint16_t* P, int L) {
-    __shared__ float xs[kCnnC][kXs + 1];
-    __shared__ float ws[kCnnK][kCnnC][kCnnC];   // [k][ci][co]
+__global__ void __launch_bounds__(256) k_conv32_fwd_mfma(const uint16_t* X, const uint4* frag, const float* bias,
+                                                         uint16_t* Z, uint16_t* P, int L) {
+    __shared__ __attribute__((aligned(16))) uint8_t xs[(kMPos + 8) * kMRow];
     const int g = blockIdx.y;
-    const int t0 = blockIdx.x * kTile;
+    const int t0 = blockIdx.x * kMPos;
     const uint16_t* x = X + (int64_t)g * L * kCnnC;
-    for (int e = threadIdx.x; e < kXs * kCnnC; e += 256) {
-        const int r = e / kCnnC, c = e % kCnnC;
+    for (int e = threadIdx.x; e < (kMPos + 8) * 4; e += 256) {
+        const int r = e >> 2, q = e & 3;
         const int t = t0 - 4 + r;
-        xs[c][r] = (t >= 0 && t < L) ? bf2f(x[(int64_t)t * kCnnC + c]) : 0.f;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (t >= 0 && t < L) v = reinterpret_cast<const uint4*>(x + (int64_t)t * kCnnC)[q];
+        *reinterpret_cast<uint4*>(xs + r * kMRow + 16 * q) = v;
     }
-    for (int e = threadIdx.x; e < kCnnC * kCnnC * kCnnK; e += 256) {
-        const int co = e / (kCnnC * kCnnK), rem = e % (kCnnC * kCnnK);
-        const int ci = rem / kCnnK, k = rem % kCnnK;
-        ws[k][ci][co] = W[e];
-    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint4 a[18];
+#pragma unroll
+    for (int b = 0; b < 18; ++b) a[b] = frag[b * 64 + lane];
+    const int col = lane & 31, hg = lane >> 5;
+    float bia[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) bia[e] = bias[8 * (e >> 2) + 4 * hg + (e & 3)];
     __syncthreads();
-    const int tp = threadIdx.x & 63, cg = threadIdx.x >> 6;
-    float acc[2][8];
+    for (int tt = 0; tt < 4; ++tt) {
+        const int p0 = (w * 4 + tt) * 32;          // tile start inside the workgroup
+        if (t0 + p0 >= L) break;
+        f32x16 acc;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) acc[0][c] = acc[1][c] = bias[cg * 8 + c];
-    for (int ci = 0; ci < kCnnC; ++ci) {
-        float xv[10];
+        for (int e = 0; e < 16; ++e) acc[e] = 0.f;
 #pragma unroll
-        for (int j = 0; j < 10; ++j) xv[j] = xs[ci][2 * tp + j];
+        for (int b = 0; b < 18; ++b) {
+            const int tap = b >> 1;
+            const uint4 bv = *reinterpret_cast<const uint4*>(xs + (p0 + col + tap) * kMRow + 32 * (b & 1) + 16 * hg);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[b]),
+                                                          __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
+        }
+        // epilogue: lane holds position t = t0 + p0 + col, channels
+        // o = 8 (e / 4) + 4 hg + e % 4
+        const int t = t0 + p0 + col;
+        uint16_t zb[16], pb[16];
 #pragma unroll
-        for (int k = 0; k < kCnnK; ++k) {
-            const float4 wa = *reinterpret_cast<const float4*>(&ws[k][ci][cg * 8]);
-            const float4 wb = *reinterpret_cast<const float4*>(&ws[k][ci][cg * 8 + 4]);
-            const float w8[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+        for (int e = 0; e < 16; ++e) {
+            const float z = acc[e] + bia[e];
+            const float zn = __shfl_xor(z, 1, 64);
+            zb[e] = f2bf(z);
+            pb[e] = f2bf(0.5f * (fmaxf(z, 0.f) + fmaxf(zn, 0.f)));
+        }
+        if (t < L) {
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                acc[0][c] += w8[c] * xv[k];
-                acc[1][c] += w8[c] * xv[k + 1];
+            for (int q = 0; q < 4; ++q) {
+                const int o = 8 * q + 4 * hg;
+                if (SAVE)
+                    *reinterpret_cast<uint2*>(Z + ((int64_t)g * L + t) * kCnnC + o) =
+                        make_uint2((uint32_t)zb[4 * q] | ((uint32_t)zb[4 * q + 1] << 16),
+                                   (uint32_t)zb[4 * q + 2] | ((uint32_t)zb[4 * q + 3] << 16));
+                if ((t & 1) == 0)
+                    *reinterpret_cast<uint2*>(P + ((int64_t)g * (L / 2) + t / 2) * kCnnC + o) =
+                        make_uint2((uint32_t)pb[4 * q] | ((uint32_t)pb[4 * q + 1] << 16),
+                                   (uint32_t)pb[4 * q + 2] | ((uint32_t)pb[4 * q + 3] << 16));
             }
         }
     }
-    const int tc = t0 + 2 * tp;
-    if (tc >= L) return;
-    uint16_t zo[2][8], po[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        zo[0][c] = f2bf(acc[0][c]);
-        zo[1][c] = f2bf(acc[1][c]);
-        po[c] = f2bf(0.5f * (fmaxf(acc[0][c], 0.f) + fmaxf(acc[1][c], 0.f)));
-    }
-    if (SAVE) {
-        *reinterpret_cast<uint4*>(Z + ((int64_t)g * L + tc) * kCnnC + cg * 8) = *reinterpret_cast<const uint4*>(zo[0]);
-        *reinterpret_cast<uint4*>(Z + ((int64_t)g * L + tc + 1) * kCnnC + cg * 8) =
-            *reinterpret_cast<const uint4*>(zo[1]);
-    }
-    *reinterpret_cast<uint4*>(P + ((int64_t)g * (L / 2) + tc / 2) * kCnnC + cg * 8) = *reinterpret_cast<const uint4*>(po);
 }
 
 // ----------------------------------------------------------------- head --
@@ -552,8 +584,13 @@ int launch_cnn_forward(const CnnNet& net, const float* wc, const uint16_t* xdec,
             if (Z) hipLaunchKernelGGL(k_conv1_fwd<true>, dim3(ceil_div(L / 2, 256), nsig), dim3(256), 0, s, X, W, bias, Z, P, L);
             else hipLaunchKernelGGL(k_conv1_fwd<false>, dim3(ceil_div(L / 2, 256), nsig), dim3(256), 0, s, X, W, bias, Z, P, L);
         } else {
-            if (Z) hipLaunchKernelGGL(k_conv32_fwd<true>, dim3(ceil_div(L, kTile), nsig), dim3(256), 0, s, X, W, bias, Z, P, L);
-            else hipLaunchKernelGGL(k_conv32_fwd<false>, dim3(ceil_div(L, kTile), nsig), dim3(256), 0, s, X, W, bias, Z, P, L);
+            const uint4* fr = reinterpret_cast<const uint4*>(net.frag) + (size_t)(l - 1) * 18 * 64;
+            if (Z)
+                hipLaunchKernelGGL(k_conv32_fwd_mfma<true>, dim3(ceil_div(L, kMPos), nsig), dim3(256), 0, s, X, fr,
+                                   bias, Z, P, L);
+            else
+                hipLaunchKernelGGL(k_conv32_fwd_mfma<false>, dim3(ceil_div(L, kMPos), nsig), dim3(256), 0, s, X, fr,
+                                   bias, Z, P, L);
         }
         TDE_HIP_CHECK(hipGetLastError());
         X = P;
@@ -631,6 +668,16 @@ int launch_adam(float* p, const float* g, float* m, float* v, float* wc, int n, 
 int launch_round_copy(const float* p, float* wc, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_round_copy, dim3(ceil_div(n, 256)), dim3(256), 0, s, p, wc, n);
     TDE_HIP_CHECK(hipGetLastError());
+    return TDE_OK;
+}
+
+// Per-lane matrix-core fragments of the 32 -> 32 layers' bf16 weights.
+int launch_pack_frags(const float* wc, void* frag, hipStream_t s) {
+    for (int l = 1; l < kCnnLayers; ++l) {
+        hipLaunchKernelGGL(k_pack_wfrag, dim3(18), dim3(64), 0, s, wc + cnn_param_offset(l),
+                           reinterpret_cast<uint4*>(frag) + (size_t)(l - 1) * 18 * 64);
+        TDE_HIP_CHECK(hipGetLastError());
+    }
     return TDE_OK;
 }
 

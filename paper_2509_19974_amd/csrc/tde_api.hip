@@ -476,7 +476,7 @@ int validate_pairs(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
         if (!opts->model) return set_error(TDE_ERR_ARG, "tde_estimate_batch: learned mode needs a model");
         if (opts->topk < 1 || opts->topk > kCnnMaxTop || opts->topk >= model_net(opts->model).nb)
             return set_error(TDE_ERR_ARG, "tde_estimate_batch: topk must be in [1, %d]", kCnnMaxTop);
-        if (!std::isfinite(opts->margin)) return set_error(TDE_ERR_ARG, "tde_estimate_batch: non-finite margin");
+        if (std::isnan(opts->margin)) return set_error(TDE_ERR_ARG, "tde_estimate_batch: NaN margin");
         if (path != TDE_PATH_AUTO && path != TDE_PATH_MFMA)
             return set_error(TDE_ERR_ARG, "tde_estimate_batch: learned mode falls back on TDE_PATH_MFMA");
         const CnnNet& net = model_net(opts->model);

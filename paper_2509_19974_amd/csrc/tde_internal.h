@@ -247,7 +247,9 @@ struct CnnNet {
     int ld;               // decimated input length (multiple of 256)
     int nb;               // bins (multiple of 64, at most 2 ld / 16)
     int nparams;
+    const void* frag;     // packed matrix-core weight fragments (device), 3 x 18 x 64 x 16 bytes
 };
+constexpr size_t kCnnFragBytes = 3 * 18 * 64 * 16;
 
 struct CnnActs {          // per layer l: input X_l (x[0] = decimated input), pre-activation Z_l
     uint16_t* x[kCnnLayers + 1];
@@ -273,6 +275,7 @@ int launch_cnn_backward(const CnnNet& net, const float* wc, int B, const int32_t
                         const float* raw, const float* logits, CnnGrad& G, hipStream_t s);
 int launch_adam(float* p, const float* g, float* m, float* v, float* wc, int n, float lr, int step, hipStream_t s);
 int launch_round_copy(const float* p, float* wc, int n, hipStream_t s);
+int launch_pack_frags(const float* wc, void* frag, hipStream_t s);
 // model accessors and the allocation-free inference used by the batch call
 const CnnNet& model_net(const tde_model* M);
 int model_device(const tde_model* M);

@@ -17,6 +17,7 @@ struct tde_model {
     float* m = nullptr;
     float* v = nullptr;
     float* grad = nullptr;
+    void* frag = nullptr;      // packed bf16 fragments of the matrix-core layers
     int step = 0;
     // training buffers, sized for up to cap pairs
     int cap = 0;
@@ -200,10 +201,12 @@ int tde_model_create(tde_ctx* ctx, int ld, int nbins, uint64_t seed, tde_model**
     M->net.ld = ld;
     M->net.nb = nbins;
     M->net.nparams = cnn_param_count(kCnnLayers);
+    M->net.frag = nullptr;
     Guard gd(M->device);
     const size_t n = (size_t)M->net.nparams * 4;
     if (hipMalloc(&M->p, n) != hipSuccess || hipMalloc(&M->wc, n) != hipSuccess || hipMalloc(&M->m, n) != hipSuccess ||
-        hipMalloc(&M->v, n) != hipSuccess || hipMalloc(&M->grad, n) != hipSuccess) {
+        hipMalloc(&M->v, n) != hipSuccess || hipMalloc(&M->grad, n) != hipSuccess ||
+        hipMalloc(&M->frag, kCnnFragBytes) != hipSuccess) {
         tde_model_destroy(M);
         return set_error(TDE_ERR_HIP, "tde_model_create: allocation failed");
     }
@@ -222,7 +225,7 @@ void tde_model_destroy(tde_model* M) {
     if (!M) return;
     Guard gd(M->device);
     (void)hipDeviceSynchronize();
-    for (void* q : {(void*)M->p, (void*)M->wc, (void*)M->m, (void*)M->v, (void*)M->grad, M->buf})
+    for (void* q : {(void*)M->p, (void*)M->wc, (void*)M->m, (void*)M->v, (void*)M->grad, M->buf, M->frag})
         if (q) (void)hipFree(q);
     delete M;
 }
@@ -252,6 +255,9 @@ int tde_model_set_params(tde_model* M, const float* host, int64_t n) {
     TDE_HIP_CHECK(hipMemset(M->v, 0, (size_t)n * 4));
     M->step = 0;
     int rc = launch_round_copy(M->p, M->wc, (int)n, nullptr);
+    if (rc) return rc;
+    M->net.frag = M->frag;
+    rc = launch_pack_frags(M->wc, M->frag, nullptr);
     if (rc) return rc;
     TDE_HIP_CHECK(hipDeviceSynchronize());
     return TDE_OK;
@@ -320,6 +326,8 @@ int tde_train_step(tde_ctx* ctx, tde_model* M, const uint16_t* xdec, const int32
     if (rc) return rc;
     M->step += 1;
     rc = launch_adam(M->p, M->grad, M->m, M->v, M->wc, M->net.nparams, lr, M->step, s);
+    if (rc) return rc;
+    rc = launch_pack_frags(M->wc, M->frag, s);
     if (rc) return rc;
     if (loss_out) {
         std::vector<float> l(B);
