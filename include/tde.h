@@ -250,7 +250,7 @@ int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs_host, int64_t npairs,
  * (model parameters, training buffers sized for the largest batch seen) and
  * synchronize. xdec arrays hold bf16 bit patterns, [B][2][ld] (x then y). */
 /* ld: multiple of 256 in [256, 2^20]; nbins: multiple of 64, at most 2 ld/16
- * and 4096. Weights start He-normal from `seed`, biases 0, alpha 1/(32 F). */
+ * and 1024. Weights start He-normal from `seed`, biases 0, alpha 1/(32 F). */
 int tde_model_create(tde_ctx* ctx, int ld, int nbins, uint64_t seed, tde_model** out);
 void tde_model_destroy(tde_model* model);
 int64_t tde_model_num_params(const tde_model* model);
@@ -317,11 +317,15 @@ int tde_tune_reset(void);
 
 /* Stage timing of tde_estimate_batch, for benchmarks. While enabled, each
  * call records HIP events on the caller's stream around its stages:
- *   0 quantize (scale + codes), 1 correlation engine, 2 argmax, 3 whole call.
+ *   0 quantize (scale + codes), 1 correlation engine (in learned mode also
+ *   the proposer), 2 argmax, 3 whole call, 4 proposer (learned mode: CNN
+ *   forward and top-k, a part of stage 1).
  * tde_timing_read waits for the recorded events, writes the summed
- * milliseconds and the number of timed calls per stage to ms[4] and
- * count[4] (host arrays), and clears the record. Enabling allocates events;
- * the estimate call itself still allocates no device memory. */
+ * milliseconds and the number of timed calls per stage to ms[TDE_STAGES]
+ * and count[TDE_STAGES] (host arrays), and clears the record. Enabling
+ * allocates events; the estimate call itself still allocates no device
+ * memory. */
+#define TDE_STAGES 5
 int tde_timing_enable(tde_ctx* ctx, int on);
 int tde_timing_read(tde_ctx* ctx, double* ms, int64_t* count);
 

@@ -40,17 +40,12 @@ __global__ void __launch_bounds__(256) k_cnn_decimate(const CnnSig* sigs, int ld
     if (t >= ld) return;
     const CnnSig s = sigs[g];
     const float* x = s.x + (int64_t)16 * t;
-    float acc = 0.f;
-    if ((((uintptr_t)x) & 15) == 0) {
+    // ((x0+x1)+(x2+x3)) per quad, then (q0+q1)+(q2+q3): the order of the
+    // decimation fused into the quantize kernel
+    float q[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const float4 v = reinterpret_cast<const float4*>(x)[k];
-            acc += (v.x + v.y) + (v.z + v.w);
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < 16; ++k) acc += x[k];
-    }
+    for (int k = 0; k < 4; ++k) q[k] = (x[4 * k] + x[4 * k + 1]) + (x[4 * k + 2] + x[4 * k + 3]);
+    const float acc = (q[0] + q[1]) + (q[2] + q[3]);
     const float scale = s.inv ? (*s.inv) * s.scale_mul : s.scale_mul;
     out[(int64_t)g * ld + t] = f2bf(acc * (1.f / 16.f) * scale);
 }
@@ -196,55 +191,58 @@ __global__ void __launch_bounds__(256) k_conv32_fwd_mfma(const uint16_t* X, cons
 }
 
 // ----------------------------------------------------------------- head --
-// raw[b][k] = sum_t sum_c Fx[t][c] Fy[t + k - nb/2][c]; grid (nb / 64, B).
-// Thread -> lag kk (0..63) of the block and quarter q of the t range.
+// raw[b][k] = sum_t sum_c Fx[t][c] Fy[t + s][c], s = k - nb/2, on the bf16
+// matrix cores. For a fixed block offset D, the 32 x 32 products
+// C_I[i][j] = <Fx[32 I + i], Fy[32 (I + D) + j]> all belong to the shifts
+// s = j - i + 32 D, so one accumulator per D sums them over every row block
+// I (two instructions of 16 channels each). The diagonals of the D tiles are
+// then added in a fixed order (deterministic). One workgroup per pair; wave
+// w takes D = Dmin + w, w + 4, ...
 __global__ void __launch_bounds__(256) k_head_fwd(const uint16_t* Fe, const float* params_alpha, float* raw,
                                                   float* logits, int F, int nb) {
-    extern __shared__ uint16_t hs[];
-    const int b = blockIdx.y;
-    const int k0 = blockIdx.x * 64;
+    extern __shared__ float tiles[];                 // [nD][32][32]
+    const int b = blockIdx.x;
     const int h = nb / 2;
-    const uint16_t* fx = Fe + (int64_t)(2 * b) * F * kCnnC;
-    const uint16_t* fy = Fe + (int64_t)(2 * b + 1) * F * kCnnC;
-    uint16_t* sx = hs;                          // [F][32]
-    uint16_t* sy = hs + F * kCnnC;              // window rows w = t + s, s = k0 - h + j
-    const int wlo = k0 - h;                     // fy row of window row 0
-    const int nw = F + 64;
-    for (int e = threadIdx.x; e < F * kCnnC / 8; e += 256)
-        reinterpret_cast<uint4*>(sx)[e] = reinterpret_cast<const uint4*>(fx)[e];
-    for (int e = threadIdx.x; e < nw * 4; e += 256) {
-        const int r = e >> 2, q = e & 3;
-        const int t = wlo + r;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (t >= 0 && t < F) v = reinterpret_cast<const uint4*>(fy + (int64_t)t * kCnnC)[q];
-        reinterpret_cast<uint4*>(sy)[e] = v;
-    }
-    __syncthreads();
-    const int kk = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int tq = F / 4;
-    float acc = 0.f;
-    for (int t = q * tq; t < (q + 1) * tq; ++t) {
-        const uint4* ax = reinterpret_cast<const uint4*>(sx + t * kCnnC);
-        const uint4* ay = reinterpret_cast<const uint4*>(sy + (t + kk) * kCnnC);
+    const int dmin = -(h / 32), nD = nb / 32 + 1;
+    const int nblk = F / 32;
+    const uint8_t* fx = reinterpret_cast<const uint8_t*>(Fe + (int64_t)(2 * b) * F * kCnnC);
+    const uint8_t* fy = reinterpret_cast<const uint8_t*>(Fe + (int64_t)(2 * b + 1) * F * kCnnC);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 31, g = lane >> 5;
+    for (int di = w; di < nD; di += 4) {
+        const int D = dmin + di;
+        f32x16 acc;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const uint4 a = ax[v], c = ay[v];
-            const uint32_t aw[4] = {a.x, a.y, a.z, a.w}, cw[4] = {c.x, c.y, c.z, c.w};
+        for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+        const int ilo = D < 0 ? -D : 0, ihi = D > 0 ? nblk - D : nblk;
+        for (int I = ilo; I < ihi; ++I) {
+            const uint8_t* ax = fx + (int64_t)(32 * I + r) * 64 + 16 * g;
+            const uint8_t* by = fy + (int64_t)(32 * (I + D) + r) * 64 + 16 * g;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                acc += __uint_as_float(aw[e] << 16) * __uint_as_float(cw[e] << 16);
-                acc += __uint_as_float(aw[e] & 0xFFFF0000u) * __uint_as_float(cw[e] & 0xFFFF0000u);
+            for (int kb = 0; kb < 2; ++kb) {
+                const uint4 av = *reinterpret_cast<const uint4*>(ax + 32 * kb);
+                const uint4 bv = *reinterpret_cast<const uint4*>(by + 32 * kb);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
+                                                              __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
             }
         }
+        // lane holds column j = r, rows i = 8 (e / 4) + 4 g + e % 4
+#pragma unroll
+        for (int e = 0; e < 16; ++e) tiles[(di * 32 + 8 * (e >> 2) + 4 * g + (e & 3)) * 32 + r] = acc[e];
     }
-    __shared__ float red[4][64];
-    red[q][kk] = acc;
     __syncthreads();
-    if (threadIdx.x < 64) {
-        const float r = (red[0][kk] + red[1][kk]) + (red[2][kk] + red[3][kk]);
-        const int k = k0 + kk;
-        raw[(int64_t)b * nb + k] = r;
-        logits[(int64_t)b * nb + k] = (*params_alpha) * r;
+    const float a = *params_alpha;
+    for (int k = threadIdx.x; k < nb; k += 256) {
+        const int sft = k - h;
+        float sum = 0.f;
+        for (int di = 0; di < nD; ++di) {
+            const int dlt = sft - 32 * (dmin + di);        // j - i
+            if (dlt < -31 || dlt > 31) continue;
+            const int i0 = dlt < 0 ? -dlt : 0, i1 = dlt < 0 ? 32 : 32 - dlt;
+            for (int i = i0; i < i1; ++i) sum += tiles[(di * 32 + i) * 32 + i + dlt];
+        }
+        raw[(int64_t)b * nb + k] = sum;
+        logits[(int64_t)b * nb + k] = a * sum;
     }
 }
 
@@ -597,15 +595,14 @@ int launch_cnn_forward(const CnnNet& net, const float* wc, const uint16_t* xdec,
         L /= 2;
     }
     const int F = L;
-    const size_t hl = (size_t)(F + F + 64) * kCnnC * 2;
+    const size_t hl = (size_t)(net.nb / 32 + 1) * 32 * 32 * 4;
     static bool attr = false;
     if (!attr) {
         TDE_HIP_CHECK(hipFuncSetAttribute((const void*)k_head_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
         TDE_HIP_CHECK(hipFuncSetAttribute((const void*)k_head_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
         attr = true;
     }
-    hipLaunchKernelGGL(k_head_fwd, dim3(net.nb / 64, B), dim3(256), hl, s, X, wc + net.nparams - 1, raw, logits, F,
-                       net.nb);
+    hipLaunchKernelGGL(k_head_fwd, dim3(B), dim3(256), hl, s, X, wc + net.nparams - 1, raw, logits, F, net.nb);
     TDE_HIP_CHECK(hipGetLastError());
     return TDE_OK;
 }

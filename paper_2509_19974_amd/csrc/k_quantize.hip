@@ -47,6 +47,11 @@ __device__ __forceinline__ const QSig& pick_sig(const QSig* sigs, int nsig, cons
     return sigs[lo];
 }
 
+__device__ __forceinline__ uint16_t f2bf_rne(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
 __device__ __forceinline__ double sq_or_zero(float f) {
     double a = f;
     return __builtin_isfinite(a) ? a * a : 0.0;
@@ -215,6 +220,20 @@ __global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QS
 #pragma unroll
             for (int e = 0; e < 4; ++e) t4[e] = (m + e < s.n) ? s.x[m + e] : 0.f;
             xv[k] = make_float4(t4[0], t4[1], t4[2], t4[3]);
+        }
+    }
+    if (s.dec) {
+        // fused decimation: means of 16 samples = 4 neighbouring threads,
+        // summed ((x0+x1)+(x2+x3)) per thread, then lanes t^1, t^2 (the
+        // same order as the stand-alone decimation kernel)
+        const float scale = inv * s.dec_mul;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            float a = (xv[k].x + xv[k].y) + (xv[k].z + xv[k].w);
+            a += __shfl_xor(a, 1, 64);
+            a += __shfl_xor(a, 2, 64);
+            const int64_t m = base + 1024 * k + 4 * (int64_t)threadIdx.x;
+            if ((threadIdx.x & 3) == 0 && m + 16 <= s.n) s.dec[m >> 4] = f2bf_rne(a * (1.f / 16.f) * scale);
         }
     }
 #pragma unroll

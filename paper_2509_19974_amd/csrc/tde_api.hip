@@ -222,7 +222,7 @@ int tde_timing_read(tde_ctx* c, double* ms, int64_t* count) {
     if (!c || !ms || !count) return set_error(TDE_ERR_ARG, "tde_timing_read: null pointer");
     std::lock_guard<std::mutex> lock(c->mu);
     DeviceGuard g(c->device);
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < TDE_STAGES; ++k) {
         ms[k] = 0.0;
         count[k] = 0;
     }
@@ -599,7 +599,7 @@ struct BatchPlan {
     const tde_model* model = nullptr;
     int topk = 0;
     float theta = 0.f;
-    size_t off_csig = 0, off_cnn = 0, off_top = 0, off_margin = 0, off_wparts = 0;
+    size_t off_cnn = 0, off_top = 0, off_margin = 0, off_wparts = 0;
     std::vector<PairPlan> pp;
     std::vector<size_t> off_q;      // per signal (2 per pair)
     std::vector<size_t> off_gsum;   // per signal
@@ -646,7 +646,6 @@ BatchPlan plan_batch(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
     B.off_items = take(sizeof(XItem) * np);
     B.off_segs = take(sizeof(ArgSeg) * (B.nsegs ? B.nsegs : 1));
     B.off_jobs = take(sizeof(NttJob) * (B.njobs ? B.njobs : 1));
-    if (B.learned) B.off_csig = take(sizeof(CnnSig) * 2 * np);     // uploaded with the descriptors
     B.off_work = take(sizeof(MWork) * (B.nwork ? B.nwork : 1));
     B.off_counters = take(2 * sizeof(int));
     B.off_tparts = take(sizeof(ArgPart) * (B.ntparts ? B.ntparts : 1));
@@ -740,6 +739,11 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
             const float fixed = side ? q.inv_step_y : q.inv_step_x;
             S.inv_fixed = (q.bits != 1 && fixed > 0.f) ? fixed : 0.f;
             S.bits = q.bits;
+            if (B.learned) {
+                // decimated CNN input, written by the quantize kernel
+                S.dec = reinterpret_cast<uint16_t*>(W + B.off_cnn) + (2 * i + side) * (int64_t)model_net(B.model).ld;
+                S.dec_mul = 6.f / (float)(2 * kmax_of_bits(q.bits) + 1);
+            }
             if (q.bits != 1 && !(fixed > 0.f)) L.need_scale = true;
             bbase += ceil_div(S.n, kQuantBlock);
         }
@@ -842,13 +846,6 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
     if (!segs.empty()) memcpy(L.blob.data() + B.off_segs, segs.data(), sizeof(ArgSeg) * segs.size());
     if (!work.empty()) memcpy(L.blob.data() + B.off_work, work.data(), work.size() * sizeof(MWork));
     if (!jobs.empty()) memcpy(L.blob.data() + B.off_jobs, jobs.data(), jobs.size() * sizeof(NttJob));
-    if (B.learned) {
-        CnnSig* cs = reinterpret_cast<CnnSig*>(L.blob.data() + B.off_csig);
-        for (int64_t k = 0; k < 2 * np; ++k) {
-            const QSig& S = sigs[k];
-            cs[k] = CnnSig{S.x, S.inv_out, 6.f / (float)(2 * kmax_of_bits(S.bits) + 1)};
-        }
-    }
 }
 
 // Queues the kernels of a prepared batch on s (the descriptors are already in
@@ -877,9 +874,12 @@ int batch_enqueue(tde_ctx* ctx, uint8_t* W, const BatchPlan& B, const BatchLaunc
         // proposer: decimate + encoder + head + top-k, then the windows
         int32_t* top = reinterpret_cast<int32_t*>(W + B.off_top);
         float* margin = reinterpret_cast<float*>(W + B.off_margin);
-        rc = cnn_infer(B.model, nullptr, (int)L.np, W + B.off_cnn, B.topk, top, margin, nullptr, s,
-                       reinterpret_cast<const CnnSig*>(W + B.off_csig));
+        hipEvent_t t_p0 = mk();
+        rc = cnn_infer(B.model, reinterpret_cast<const uint16_t*>(W + B.off_cnn), (int)L.np, W + B.off_cnn, B.topk,
+                       top, margin, nullptr, s, nullptr);
         if (rc) return rc;
+        hipEvent_t t_p1 = mk();
+        if (timed) mark_stage(ctx, 4, t_p0, t_p1);
         rc = launch_xcorr_win(items_dev, (int)L.np, top, margin, B.theta, B.topk, model_net(B.model).nb,
                               reinterpret_cast<ArgPart*>(W + B.off_wparts), s);
         if (rc) return rc;

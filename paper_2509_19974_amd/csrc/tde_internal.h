@@ -43,6 +43,8 @@ struct QSig {
     int64_t blk_base;     // prefix of ceil(n/kQuantBlock) over the signals before it
     float inv_fixed;      // > 0: caller-supplied scale
     int32_t bits;
+    uint16_t* dec;        // optional: n/16 bf16 block means times scale * dec_mul (n a multiple of 16)
+    float dec_mul;
 };
 
 constexpr int kQuantBlock = 4096;   // samples per quantize workgroup (256 threads x 16)

@@ -193,8 +193,8 @@ int tde_model_create(tde_ctx* ctx, int ld, int nbins, uint64_t seed, tde_model**
     if (ld < 256 || ld % 256 != 0 || ld > (1 << 20))
         return set_error(TDE_ERR_ARG, "tde_model_create: ld must be a multiple of 256 in [256, 2^20]");
     const int F = ld >> kCnnLayers;
-    if (nbins < 64 || nbins % 64 != 0 || nbins > 2 * F || nbins > 4096)
-        return set_error(TDE_ERR_ARG, "tde_model_create: nbins must be a multiple of 64, at most 2 ld / 16");
+    if (nbins < 64 || nbins % 64 != 0 || nbins > 2 * F || nbins > 1024)
+        return set_error(TDE_ERR_ARG, "tde_model_create: nbins must be a multiple of 64, at most 2 ld / 16 and 1024");
     if (!ctx) return set_error(TDE_ERR_ARG, "tde_model_create: null context");
     tde_model* M = new tde_model();
     M->device = ctx_device(ctx);

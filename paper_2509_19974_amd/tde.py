@@ -301,10 +301,14 @@ def tde_timing_enable(ctx, on: bool) -> None:
     _check(load_library().tde_timing_enable(ctx, 1 if on else 0))
 
 
+TDE_STAGES = 5
+
+
 def tde_timing_read(ctx):
-    """Returns (ms[4], count[4]) for stages quantize, engine, argmax, whole call."""
-    ms = (ctypes.c_double * 4)()
-    cnt = (ctypes.c_int64 * 4)()
+    """Returns (ms, count) lists for the stages quantize, engine, argmax,
+    whole call, proposer."""
+    ms = (ctypes.c_double * TDE_STAGES)()
+    cnt = (ctypes.c_int64 * TDE_STAGES)()
     _check(load_library().tde_timing_read(ctx, ms, cnt))
     return list(ms), list(cnt)
 
