@@ -188,6 +188,34 @@ def xcorr_f64_at(x, y, lags) -> np.ndarray:
     return r
 
 
+def xcorr_f64_at_pairwise(x, y, lags) -> np.ndarray:
+    """Eq. (1) on the float signals in float64 with a fixed summation order:
+    the products x[m] y[m + tau] (exact in float64) over the overlap, in
+    ascending m, zero-padded to a power-of-two length and added as a binary
+    tree (adjacent pairs, level by level). Used for the tie refinement of
+    Algorithm 1 (lines 5-6), so that the choice between tied lags is made in
+    the same arithmetic on every implementation."""
+    x = np.asarray(_f32(x), dtype=np.float64)
+    y = np.asarray(_f32(y), dtype=np.float64)
+    out = []
+    for tau in np.asarray(lags, dtype=np.int64).tolist():
+        lo = max(0, -tau)
+        hi = min(x.size, y.size - tau)
+        if hi <= lo:
+            out.append(0.0)
+            continue
+        p = x[lo:hi] * y[lo + tau:hi + tau]
+        n = 1
+        while n < p.size:
+            n *= 2
+        a = np.zeros(n)
+        a[:p.size] = p
+        while a.size > 1:
+            a = a[0::2] + a[1::2]
+        out.append(float(a[0]))
+    return np.array(out)
+
+
 def overlap_count(nu: int, nv: int, tau: int) -> int:
     """#{m : 0 <= m < nu, 0 <= m + tau < nv}."""
     return max(0, min(nu, nv - tau) - max(0, -tau))
@@ -209,13 +237,14 @@ def estimate(x, y, bits: int, lag_lo: int, lag_hi: int,
 def estimate_refined(x, y, bits: int, lag_lo: int, lag_hi: int,
                      inv_step_x: float | None = None, inv_step_y: float | None = None):
     """Algorithm 1, lines 1-6: ties of the integer correlation are resolved by
-    the float64 correlation of the unquantized signals, evaluated only at the
-    tied lags. Returns the refined argmax set (sorted) and the line-4 result."""
+    the float64 correlation of the unquantized signals (fixed pairwise
+    summation order), evaluated only at the tied lags. Returns the refined
+    argmax set (sorted) and the line-4 result."""
     res = estimate(x, y, bits, lag_lo, lag_hi, inv_step_x, inv_step_y)
     r = res["r"]
     tied = np.nonzero(r == res["rmax"])[0].astype(np.int64) + lag_lo
     if tied.size > 1:
-        rf = xcorr_f64_at(x, y, tied)
+        rf = xcorr_f64_at_pairwise(x, y, tied)
         best = rf.max()
         tied = tied[rf == best]
     res["lag_set"] = [int(t) for t in tied]

@@ -479,3 +479,30 @@ def test_cnn_bins_and_bf16_rounding():
     assert cnn.bf16_round(vals).tolist() == [1.0, 1.0, 1.0 + 2 ** -6, 1.0 + 2 ** -7, -2.5]
     top, margin = cnn.topk_margin(np.array([0.5, 2.0, 2.0, -1.0, 1.0]), 2)
     assert top.tolist() == [1, 2] and margin == 1.0          # logit_(1) - logit_(3)
+
+
+def test_pairwise_float_correlation_pins():
+    """The fixed-order float64 correlation used for tie refinement: exact on
+    small-integer data (every partial sum is an integer below 2^53), within
+    the pairwise error bound of the exactly rounded sum (math.fsum) on
+    random data, and summed in the stated tree (a hand-made case whose value
+    depends on the order)."""
+    import math
+    rng = np.random.default_rng(21)
+    x = rng.integers(-1000, 1000, 3000).astype(np.float32)
+    y = rng.integers(-1000, 1000, 2500).astype(np.float32)
+    lags = np.array([-2999, -7, 0, 5, 2499])
+    np.testing.assert_array_equal(oracle.xcorr_f64_at_pairwise(x, y, lags), oracle.xcorr_f64_at(x, y, lags))
+    xf = rng.standard_normal(5000).astype(np.float32)
+    yf = rng.standard_normal(5000).astype(np.float32)
+    for tau in (-3000, 0, 17, 4000):
+        lo, hi = max(0, -tau), min(5000, 5000 - tau)
+        prods = [float(a) * float(b) for a, b in zip(xf[lo:hi], yf[lo + tau:hi + tau])]
+        exact = math.fsum(prods)
+        bound = math.ceil(math.log2(len(prods))) * np.finfo(np.float64).eps * math.fsum(abs(p) for p in prods)
+        assert abs(oracle.xcorr_f64_at_pairwise(xf, yf, [tau])[0] - exact) <= bound
+    # [2^53, 1, 1, -2^53] pairwise: (2^53 + 1) + (1 - 2^53) = 2^53 + (1 - 2^53) = 1
+    # (ascending order would give ((2^53 + 1) + 1) - 2^53 = 0 after two roundings)
+    xs = np.array([2.0 ** 26, 1.0, 1.0, -(2.0 ** 26)], np.float32)
+    ys = np.array([2.0 ** 27, 1.0, 1.0, 2.0 ** 27], np.float32)
+    assert oracle.xcorr_f64_at_pairwise(xs, ys, [0])[0] == 1.0
