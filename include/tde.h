@@ -72,6 +72,8 @@ extern "C" {
 #define TDE_FLAG_ZERO_X      4   /* every code of x is 0 (so r is 0 everywhere) */
 #define TDE_FLAG_ZERO_Y      8
 #define TDE_FLAG_FALLBACK   16   /* learned mode: proposal margin too low, full search used */
+#define TDE_FLAG_REFINED    32   /* tde_refine_ties chose among several maximisers */
+#define TDE_FLAG_REFINE_PARTIAL 64  /* more maximisers than max_ties: the smallest max_ties were refined */
 
 typedef struct tde_ctx tde_ctx;
 
@@ -164,6 +166,23 @@ int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, in
 size_t tde_argmax_workspace_size(int64_t nlags);
 int tde_argmax_lag(tde_ctx* ctx, const void* r, int r_dtype, int64_t lag_lo, int64_t lag_hi,
                    tde_peak* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Algorithm 1, lines 5-6: if *peak (device, from tde_argmax_lag or a batch
+ * call with r_out) has n_ties > 1, the real correlation (Eq. (1) on the float
+ * signals x, y (device)) is evaluated at the tied lags of r (device, the
+ * lags [lag_lo, lag_hi] in r_dtype) and *peak becomes {smallest lag of the
+ * refined set, the same integer rmax, size of the refined set, flags |
+ * TDE_FLAG_REFINED}. The real correlation is summed in float64 over a fixed
+ * binary tree (products exact, ascending m zero-padded to a power of two,
+ * adjacent pairs level by level), so the choice is reproducible. At most
+ * max_ties tied lags (the smallest ones, 2 <= max_ties <= 65536) are
+ * considered; more set TDE_FLAG_REFINE_PARTIAL. A peak with n_ties <= 1 is
+ * left unchanged. Errors: TDE_ERR_ARG, TDE_ERR_WS, TDE_ERR_UNSUPPORTED when
+ * min(nx, ny) > 2^22. ws: tde_refine_workspace_size(max_ties) bytes. */
+size_t tde_refine_workspace_size(int max_ties);
+int tde_refine_ties(tde_ctx* ctx, const float* x, int64_t nx, const float* y, int64_t ny, const void* r,
+                    int r_dtype, int64_t lag_lo, int64_t lag_hi, tde_peak* peak, int max_ties, void* ws,
+                    size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------ batch -- */
 

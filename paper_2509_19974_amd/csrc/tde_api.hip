@@ -459,6 +459,40 @@ int tde_argmax_lag(tde_ctx* ctx, const void* r, int r_dtype, int64_t lag_lo, int
     return launch_argmax(nullptr, one, 1, one.nparts, static_cast<ArgPart*>(ws), static_cast<hipStream_t>(stream));
 }
 
+// ------------------------------------------------------ tie refinement --
+
+size_t tde_refine_workspace_size(int max_ties) {
+    if (max_ties < 2 || max_ties > 65536) return 0;
+    return align_bytes((size_t)max_ties * 8) * 2 + align_bytes(sizeof(int));
+}
+
+int tde_refine_ties(tde_ctx* ctx, const float* x, int64_t nx, const float* y, int64_t ny, const void* r,
+                    int r_dtype, int64_t lag_lo, int64_t lag_hi, tde_peak* peak, int max_ties, void* ws,
+                    size_t ws_bytes, void* stream) {
+    if (!x || !y || !r || !peak) return set_error(TDE_ERR_ARG, "tde_refine_ties: null pointer");
+    if (nx < 1 || ny < 1) return set_error(TDE_ERR_ARG, "tde_refine_ties: empty signal");
+    if (lag_lo > lag_hi) return set_error(TDE_ERR_ARG, "tde_refine_ties: lag_lo > lag_hi");
+    if (r_dtype != TDE_I32 && r_dtype != TDE_I64) return set_error(TDE_ERR_ARG, "tde_refine_ties: bad r_dtype");
+    if (max_ties < 2 || max_ties > 65536) return set_error(TDE_ERR_ARG, "tde_refine_ties: max_ties in [2, 65536]");
+    if (std::min(nx, ny) > ((int64_t)1 << 22))
+        return set_error(TDE_ERR_UNSUPPORTED, "tde_refine_ties: overlaps longer than 2^22 samples");
+    const size_t need = tde_refine_workspace_size(max_ties);
+    if (!ws || ws_bytes < need) return set_error(TDE_ERR_WS, "tde_refine_ties: workspace %zu < %zu", ws_bytes, need);
+    if (!ctx) return set_error(TDE_ERR_ARG, "tde_refine_ties: null context");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return set_error(TDE_ERR_HIP, "tde_refine_ties: hipSetDevice failed");
+    {
+        std::lock_guard<std::mutex> lock(ctx->mu);
+        drop_graphs_on(ctx, ws, ws_bytes);
+    }
+    Carve cv(ws);
+    int64_t* lags = static_cast<int64_t*>(cv.take((size_t)max_ties * 8));
+    double* vals = static_cast<double*>(cv.take((size_t)max_ties * 8));
+    int* count = static_cast<int*>(cv.take(sizeof(int)));
+    return launch_refine(x, nx, y, ny, r, r_dtype, lag_lo, lag_hi - lag_lo + 1, peak, max_ties, lags, vals, count,
+                         static_cast<hipStream_t>(stream));
+}
+
 // --------------------------------------------------------------- batch --
 
 }  // extern "C"

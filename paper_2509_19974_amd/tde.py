@@ -35,6 +35,8 @@ TDE_FLAG_NONFINITE_Y = 2
 TDE_FLAG_ZERO_X = 4
 TDE_FLAG_ZERO_Y = 8
 TDE_FLAG_FALLBACK = 16
+TDE_FLAG_REFINED = 32
+TDE_FLAG_REFINE_PARTIAL = 64
 
 PEAK_DTYPE = np.dtype([("lag", "<i8"), ("rmax", "<i8"), ("n_ties", "<i4"), ("flags", "<i4")])
 QSTAT_DTYPE = np.dtype([("inv_step", "<f4"), ("flags", "<i4"), ("n_nonfinite", "<i8"), ("n_zero", "<i8"),
@@ -97,6 +99,8 @@ def load_library(path: str = LIB_PATH):
         "tde_model_prepare": (i32, [vp, vp, ctypes.POINTER(tde_pair), i64, vp, vp, sz, vp]),
         "tde_model_forward": (i32, [vp, vp, vp, i64, vp, i32, vp, vp, vp]),
         "tde_train_step": (i32, [vp, vp, vp, vp, i64, f32, ctypes.POINTER(f32), vp]),
+        "tde_refine_workspace_size": (sz, [i32]),
+        "tde_refine_ties": (i32, [vp, vp, i64, vp, i64, vp, i32, i64, i64, vp, i32, vp, sz, vp]),
         "tde_tune": (i32, [vp, i32, vp]),
         "tde_tune_query": (i32, [i64, i64, i32, i32, i64, i64]),
         "tde_tune_save": (i32, [ctypes.c_char_p]),
@@ -381,6 +385,16 @@ class Context:
         ws = self._bytes(wsb)
         tde_argmax_lag(self.handle, r, r_dtype, lag_lo, lag_hi, out, ws, wsb, stream)
         return out
+
+    def refine(self, x, y, r, lag_lo, lag_hi, peak, max_ties=4096, stream=None):
+        """Algorithm 1, lines 5-6 on a peak record (uint8 tensor of 24 bytes,
+        updated in place); r is the pair's full correlation (int32/int64)."""
+        r_dtype = TDE_I32 if r.dtype == self.torch.int32 else TDE_I64
+        wsb = int(load_library().tde_refine_workspace_size(max_ties))
+        ws = self._bytes(wsb)
+        _check(load_library().tde_refine_ties(self.handle, _ptr(x), x.numel(), _ptr(y), y.numel(), _ptr(r), r_dtype,
+                                              lag_lo, lag_hi, _ptr(peak), max_ties, _ptr(ws), wsb, _stream(stream)))
+        return peak
 
     def batch_plan(self, specs, path=TDE_PATH_AUTO, mode=TDE_MODE_FULL, use_graph=0, model=None, topk=8,
                    margin=0.0):

@@ -744,3 +744,69 @@ def test_learned_training_reduces_loss(T, ctx):
     say(f"   loss {losses[0]:.3f} -> {losses[-1]:.3f}")
     assert losses[-1] < 0.7 * losses[0]
     model.close()
+
+
+# ------------------------------------------------- tie refinement (f1) --
+
+def _refine_case(T, ctx, x, y, bits, lo, hi, max_ties=4096):
+    from paper_2509_19974_amd import tde
+    xd, yd = dev(T, x), dev(T, y)
+    spec = dict(x=xd, y=yd, lag_lo=lo, lag_hi=hi, bits=bits,
+                r_out=T.empty(hi - lo + 1, dtype=T.int64, device="cuda"), r_dtype=tde.TDE_I64)
+    out = ctx.estimate_batch([spec], tde.TDE_PATH_MFMA)
+    before = tde.decode_peaks(out)[0].copy()
+    ctx.refine(xd, yd, spec["r_out"], lo, hi, out, max_ties=max_ties)
+    T.cuda.synchronize()
+    return before, tde.decode_peaks(out)[0]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_refine_ties_matches_algorithm1_lines5_6(T, ctx, seed):
+    """Sign quantization of short signals gives many integer ties; the
+    refinement must return the oracle's refined set (Algorithm 1, lines 5-6,
+    float64 in the fixed pairwise order): its smallest lag and its size."""
+    from paper_2509_19974_amd import tde
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(20, 400))
+    x = rng.standard_normal(n).astype(np.float32)
+    y = rng.standard_normal(n + int(rng.integers(0, 50))).astype(np.float32)
+    lo, hi = -(n - 1), y.size - 1
+    say(f"refine seed={seed} n={n}")
+    before, after = _refine_case(T, ctx, x, y, 1, lo, hi)
+    ref = oracle.estimate_refined(x, y, 1, lo, hi)
+    assert (before["lag"], before["rmax"], before["n_ties"]) == (ref["lag"], ref["rmax"], ref["n_ties"])
+    if ref["n_ties"] > 1:
+        assert after["flags"] & tde.TDE_FLAG_REFINED
+        assert (after["lag"], after["n_ties"]) == (min(ref["lag_set"]), len(ref["lag_set"]))
+        assert after["rmax"] == before["rmax"]
+    else:
+        assert after.tobytes() == before.tobytes()
+
+
+def test_refine_partial_and_exact_shift(T, ctx):
+    """More ties than max_ties: only the smallest max_ties tied lags are
+    refined (flag set). On an untruncated exact shift (Theorem 1), the
+    refined lag is the true delay."""
+    from paper_2509_19974_amd import tde
+    rng = np.random.default_rng(7)
+    x = np.zeros(70, np.float32)
+    x[::7] = 1.0                       # a short pulse train inside a long one:
+    y = np.zeros(3000, np.float32)     # every lag 7k in [0, 2930] ties
+    y[::7] = 1.0
+    before, after = _refine_case(T, ctx, x, y, 1, -69, 2999, max_ties=4)
+    assert before["n_ties"] > 4
+    assert after["flags"] & tde.TDE_FLAG_REFINE_PARTIAL
+    r = oracle.xcorr(oracle.quantize(x, 1)[0], oracle.quantize(y, 1)[0], -69, 2999)
+    tied = (np.nonzero(r == r.max())[0] - 69)[:4]
+    vals = oracle.xcorr_f64_at_pairwise(x, y, tied)
+    best = tied[vals == vals.max()]
+    assert (after["lag"], after["n_ties"]) == (best.min(), best.size)
+    # exact shift with a positive gain: the real correlation has a strict maximum at nu
+    s = rng.standard_normal(2000)
+    nu = 137
+    xx = np.zeros(2000 + nu, np.float32)
+    xx[:2000] = s
+    yy = np.zeros(2000 + nu, np.float32)
+    yy[nu:] = (0.7 * s).astype(np.float32)
+    before, after = _refine_case(T, ctx, xx, yy, 1, -500, 500)
+    assert after["lag"] == nu and (before["n_ties"] == 1 or after["n_ties"] == 1)
