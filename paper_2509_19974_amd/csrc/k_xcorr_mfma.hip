@@ -27,9 +27,10 @@
 // offsets and are assembled from 5 dwords with v_alignbyte. Out-of-range
 // samples are staged as 0: the finite-length convention of Section 2.2.
 //
-// At the end of an item the four partial sums meet in LDS (ds_add). The tile
-// then writes r with plain coalesced stores when r is requested, and its
-// (max, smallest lag, count) triple, so no r array is needed for the argmax.
+// At the end of an item the four partial sums meet in LDS (ds_add, 32- or
+// 64-bit). The tile then writes r with plain coalesced stores when r is
+// requested, and its (max, smallest lag, count) triple (kept in 32-bit for
+// int32 tiles), so no r array is needed for the argmax.
 // Each wave's partial covers at most floor((2^31-1)/(Ku Kv)) values of m, so
 // no int32 accumulator overflows (coefficient bound of Section 3.2); tiles
 // whose total may exceed int32 are summed in int64. Segmented tiles add into
@@ -85,14 +86,12 @@ __device__ __forceinline__ int vphys(int p) {
 
 __device__ __forceinline__ uint4 load16_guarded(const int8_t* base, int64_t n, int64_t gi) {
     const int8_t* p = base + gi;
-    if (gi >= 0 && gi + 16 <= n && ((((uintptr_t)p) & 15) == 0)) {
-        return *reinterpret_cast<const uint4*>(p);
-    }
+    if (gi >= 0 && gi + 16 <= n && ((((uintptr_t)p) & 15) == 0)) return gload16(p);
     uint32_t w[4] = {0u, 0u, 0u, 0u};
     if (gi + 16 > 0 && gi < n) {
         for (int e = 0; e < 16; ++e) {
             int64_t idx = gi + e;
-            uint32_t byte = (idx >= 0 && idx < n) ? (uint32_t)(uint8_t)base[idx] : 0u;
+            uint32_t byte = (idx >= 0 && idx < n) ? gload_u8(base + idx) : 0u;
             w[e >> 2] |= byte << (8 * (e & 3));
         }
     }
@@ -275,9 +274,91 @@ __device__ __forceinline__ void mfma_item(const XItem& it, const MWork& wk, uint
         for (int e = 0; e < 16; ++e) acc[b][e] = 0;
     if (qw_a < qw_b) wave_loop<MB>(p, T0, qw_a, qw_b, lds + w * C::WAVE_LDS, lane, acc);
 
-    // ---- the four partial sums meet in LDS (index = lag - T0)
     __syncthreads();
     const bool wide = it.wide != 0;
+    if (!wide) {
+        // ---- int32 tile: the four partials meet by LDS atomics, then every
+        // thread takes 16 lags; the argmax triple is kept in 32-bit (tile-
+        // local lag k, value, count) and widened once per tile.
+        uint32_t* red = reinterpret_cast<uint32_t*>(lds);
+        for (int k = threadIdx.x; k < C::TLW; k += 256) red[k] = 0u;
+        __syncthreads();
+        {
+            const int lc = lane & 31, g = lane >> 5;
+#pragma unroll
+            for (int b = 0; b < MB; ++b) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    // accumulator layout: lane (j = lc, g), register e -> row 8(e/4) + 4g + e%4
+                    const int i = 8 * (e >> 2) + 4 * g + (e & 3);
+                    const int val = acc[b][e];
+                    if (val != 0) atomicAdd(red + lc + 32 * b + C::S * i, (unsigned int)val);
+                }
+            }
+        }
+        __syncthreads();
+        // lags of the tile inside [lag_lo, lag_hi]: k in [klo, khi]
+        const int64_t klo64 = p.lag_lo - T0, khi64 = p.lag_hi - T0;
+        const int klo = klo64 < 0 ? 0 : (int)klo64;
+        const int khi = khi64 >= C::TLW ? C::TLW - 1 : (int)khi64;
+        int bv = INT32_MIN, bk = INT32_MAX, bc = 0;
+        for (int k = threadIdx.x; k < C::TLW; k += 256) {
+            if (k < klo || k > khi) continue;
+            const int v = (int)red[k];
+            if (p.r) {
+                const int64_t idx = T0 + k - p.lag_lo;
+                if (wk.segmented) {
+                    if (v != 0) {
+                        if (p.r_dtype == TDE_I32)
+                            atomicAdd(static_cast<int*>(p.r) + idx, v);
+                        else
+                            atomicAdd(static_cast<unsigned long long*>(p.r) + idx, (unsigned long long)(long long)v);
+                    }
+                } else if (p.r_dtype == TDE_I32) {
+                    static_cast<int32_t*>(p.r)[idx] = v;
+                } else {
+                    static_cast<int64_t*>(p.r)[idx] = v;
+                }
+            }
+            // k increases along the loop: a new maximum resets, an equal one counts
+            if (v > bv) {
+                bv = v;
+                bk = k;
+                bc = 1;
+            } else if (v == bv) {
+                bc += 1;
+            }
+        }
+        if (tile_parts && !wk.segmented) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const int ov = __shfl_xor(bv, o, 64), ok = __shfl_xor(bk, o, 64), oc = __shfl_xor(bc, o, 64);
+                if (ov > bv) {
+                    bv = ov;
+                    bk = ok;
+                    bc = oc;
+                } else if (ov == bv) {
+                    bk = ok < bk ? ok : bk;
+                    bc += oc;
+                }
+            }
+            __shared__ int sh32[4][3];
+            if (lane == 0) {
+                sh32[w][0] = bv;
+                sh32[w][1] = bk;
+                sh32[w][2] = bc;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                Tri64 a{INT64_MIN, INT64_MAX, 0};
+                for (int q = 0; q < 4; ++q)
+                    if (sh32[q][2] > 0) a = tri_join(a, Tri64{sh32[q][0], T0 + sh32[q][1] - p.lag_lo, sh32[q][2]});
+                tile_parts[it.part_base + wk.tile] = ArgPart{a.v, a.i, a.c};
+            }
+        }
+        return;
+    }
+    // ---- int64 tile (sums may exceed int32): partials meet by LDS atomics
     if (wide) {
         unsigned long long* red = reinterpret_cast<unsigned long long*>(lds);
         for (int k = threadIdx.x; k < C::TLW; k += 256) red[k] = 0ull;

@@ -32,12 +32,12 @@ constexpr int kWinWave = kWinV + kWinU;
 
 __device__ __forceinline__ uint4 ld16(const int8_t* base, int64_t n, int64_t gi) {
     const int8_t* p = base + gi;
-    if (gi >= 0 && gi + 16 <= n && ((((uintptr_t)p) & 15) == 0)) return *reinterpret_cast<const uint4*>(p);
+    if (gi >= 0 && gi + 16 <= n && ((((uintptr_t)p) & 15) == 0)) return gload16(p);
     uint32_t w[4] = {0u, 0u, 0u, 0u};
     if (gi + 16 > 0 && gi < n) {
         for (int e = 0; e < 16; ++e) {
             const int64_t idx = gi + e;
-            const uint32_t byte = (idx >= 0 && idx < n) ? (uint32_t)(uint8_t)base[idx] : 0u;
+            const uint32_t byte = (idx >= 0 && idx < n) ? gload_u8(base + idx) : 0u;
             w[e >> 2] |= byte << (8 * (e & 3));
         }
     }

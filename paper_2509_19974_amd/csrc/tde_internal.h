@@ -28,6 +28,19 @@ __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_
 __host__ __device__ inline int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 inline size_t align_bytes(size_t a) { return (a + 255) & ~size_t(255); }
 
+// Loads through the global address space. Pointers fetched from descriptors
+// are generic, and generic (flat) loads also count in the LDS wait counter,
+// so a prefetch issued that way would stall every later LDS wait until it
+// lands; these keep them on the vector-memory counter only.
+typedef unsigned int tde_u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 gload16(const void* p) {
+    const tde_u32x4 v = *(const __attribute__((address_space(1))) tde_u32x4*)p;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint32_t gload_u8(const int8_t* p) {
+    return (uint32_t)(*(const __attribute__((address_space(1))) uint8_t*)p);
+}
+
 // Largest code magnitude of a b-bit quantizer (sign: ternary, K = 1).
 inline int kmax_of_bits(int bits) { return bits == 1 ? 1 : (1 << (bits - 1)) - 1; }
 

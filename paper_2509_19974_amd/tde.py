@@ -70,6 +70,12 @@ def load_library(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    try:
+        # torch carries its own HIP runtime; loading it first makes libtde
+        # bind to that one instead of bringing a second copy into the process
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise RuntimeError(f"libtde.so not built: {path} missing (run python -m paper_2509_19974_amd.build)")
     lib = ctypes.CDLL(path)
