@@ -21,7 +21,7 @@
 // The 4 waves of a workgroup take one quarter of the m range each and run
 // independently: each wave stages its own v and u windows in a private LDS
 // region, so the main loop has no workgroup barrier. The v window of a
-// 64-step chunk (TLW + 2048 bytes) moves by 2048 bytes per chunk and lives in
+// 128-step chunk (TLW + 4096 bytes) moves by 4096 bytes per chunk and lives in
 // a power-of-two ring; every S bytes carry 16 bytes of padding so the 32 rows
 // of an A fragment fall into distinct banks. B rows start at arbitrary byte
 // offsets and are assembled from 5 dwords with v_alignbyte. Out-of-range
@@ -55,13 +55,16 @@ struct MCfg {
     static constexpr int S = 32 * MB;          // coarse lag stride, A row stride
     static constexpr int LS = MB == 4 ? 7 : 8; // log2(S)
     static constexpr int TLW = 32 * S;         // lags per tile
-    static constexpr int CQ = 64;              // k steps per staged chunk
+    static constexpr int CQ = 128;             // k steps per staged chunk
     static constexpr int CM = 32 * CQ;         // m per chunk
     // per-wave v window of a chunk: [0, VW); the last A read (one step ahead)
     // ends at TLW + CM - S + 32 <= VW
     static constexpr int VW = TLW + CM;
-    static constexpr int R = MB == 4 ? 8192 : 16384;   // ring, >= VW + CM, power of two
-    static_assert(R >= VW + CM, "ring too small");
+    // ring (power of two) >= VW: the new bytes of chunk c+1 are stored only
+    // after every read of chunk c (a wave's LDS operations complete in order),
+    // and they land on the bytes chunk c + 1 no longer needs
+    static constexpr int R = MB == 4 ? 8192 : 16384;
+    static_assert(R >= VW, "ring too small");
     static constexpr int VPH = R + 16 * (R / S);       // padded ring bytes
     static constexpr int UOFF = 32 * MB;               // u window starts UOFF before the chunk
     // u window; the last B read (one step ahead) ends at UOFF + CM + 36 <= UW.
@@ -281,19 +284,30 @@ __device__ __forceinline__ void mfma_item(const XItem& it, const MWork& wk, uint
         // thread takes 16 lags; the argmax triple is kept in 32-bit (tile-
         // local lag k, value, count) and widened once per tile.
         uint32_t* red = reinterpret_cast<uint32_t*>(lds);
-        for (int k = threadIdx.x; k < C::TLW; k += 256) red[k] = 0u;
-        __syncthreads();
         {
+            // wave 0 stores its partial (every lag of the tile once), the
+            // other waves then add theirs
             const int lc = lane & 31, g = lane >> 5;
+            if (w == 0) {
 #pragma unroll
-            for (int b = 0; b < MB; ++b) {
+                for (int b = 0; b < MB; ++b)
 #pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    // accumulator layout: lane (j = lc, g), register e -> row 8(e/4) + 4g + e%4
-                    const int i = 8 * (e >> 2) + 4 * g + (e & 3);
-                    const int val = acc[b][e];
-                    if (val != 0) atomicAdd(red + lc + 32 * b + C::S * i, (unsigned int)val);
-                }
+                    for (int e = 0; e < 16; ++e) {
+                        // accumulator layout: lane (j = lc, g), register e -> row 8(e/4) + 4g + e%4
+                        const int i = 8 * (e >> 2) + 4 * g + (e & 3);
+                        red[lc + 32 * b + C::S * i] = (uint32_t)acc[b][e];
+                    }
+            }
+            __syncthreads();
+            if (w != 0) {
+#pragma unroll
+                for (int b = 0; b < MB; ++b)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const int i = 8 * (e >> 2) + 4 * g + (e & 3);
+                        const int val = acc[b][e];
+                        if (val != 0) atomicAdd(red + lc + 32 * b + C::S * i, (unsigned int)val);
+                    }
             }
         }
         __syncthreads();
