@@ -62,9 +62,11 @@ extern "C" {
 
 /* correlation engines (the autotuner picks one for TDE_PATH_AUTO) */
 #define TDE_PATH_AUTO 0
-#define TDE_PATH_MFMA 1          /* direct sums, int8 matrix cores */
+#define TDE_PATH_MFMA 1          /* direct sums on the matrix cores: codes up to 3 as FP4
+                                    (E2M1), up to 7 as FP6 (E2M3), else int8; all exact */
 #define TDE_PATH_POPC 2          /* direct sums, bit planes (ternary codes only) */
 #define TDE_PATH_NTT  3          /* number-theoretic transform, CRT to int64 */
+#define TDE_PATH_MFMA_I8 4       /* TDE_PATH_MFMA with int8 operands for every code range */
 
 /* result flags */
 #define TDE_FLAG_NONFINITE_X 1   /* x held NaN or Inf samples */
@@ -224,7 +226,8 @@ typedef struct {
  * their union; otherwise the pair falls back to the full lag range and
  * out[i].flags carries TDE_FLAG_FALLBACK. Requirements: every pair has
  * nx = ny = 16 ld, bits in {2,4,8}, lag_lo = -(nbins/2) 256 and lag_hi =
- * (nbins/2) 256 - 1 (the union of the bins), r_out NULL; path AUTO or MFMA. */
+ * (nbins/2) 256 - 1 (the union of the bins), r_out NULL; path AUTO, MFMA or
+ * MFMA_I8 (the engine of the fallback). */
 
 /* use_graph = 1: the first call with a given signature (the bytes of the
  * pairs array, opts, ws, ws_bytes and out) waits for the caller's stream,

@@ -257,6 +257,291 @@ __device__ __forceinline__ void wave_loop(const XPair& p, int64_t T0, int64_t qw
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP4 / FP6 operands: v_mfma_scale_f32_32x32x64_f8f6f4 (scale 1), fp32
+// accumulation, twice the int8 rate. Small integer codes are exact in these
+// formats (E2M1 holds 0..3, E2M3 holds 0..7); every product and partial sum
+// is an integer, exact in fp32 while below 2^24 in magnitude, which bounds
+// each wave's m range (the host cuts items accordingly). The tile is the
+// int8 one (S = 128, 4096 lags, 4 column blocks of 32 lags), so the epilogue
+// is shared; a matrix step takes 64 values of m:
+//     A[i][k]   = v[q + T0 + 128 i + k]          k in [0, 64)
+//     B_b[k][j] = u[q + k - j - 32 b]
+// With q stepping by 64, B_2(q) = B_0(q - 64) and B_3(q) = B_1(q - 64): a
+// step reads one A fragment and the 64-code u window B_1(q) | B_0(q)
+// (2W + 1 dwords, split with v_alignbit) and reuses the previous step's
+// pair for blocks 2 and 3. Codes are packed W bits each, in the operand
+// layout of the instruction (lane (row or column, g) holds k = 32 g ..
+// 32 g + 31, code t at bits W t); the staging converts the int8 codes on
+// their way into LDS.
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+template <int W>
+struct FCfg {
+    static constexpr int FMT = W == 4 ? kFmtF4 : kFmtF6;
+    static constexpr int S = 128;                  // coarse lag stride (samples)
+    static constexpr int LS = 7;
+    static constexpr int TLW = 32 * S;             // lags per tile, as MCfg<4>
+    static constexpr int KS = 64;                  // m per matrix step
+    static constexpr int CQ = 32;                  // steps per staged chunk
+    static constexpr int CM = KS * CQ;             // m per chunk
+    static constexpr int VW = TLW + CM;            // v window of a chunk (samples)
+    // ring >= VW: as in the int8 engine, the new samples of chunk c+1 are
+    // stored after every read of chunk c and replace samples below (c+1) CM
+    static constexpr int R = 8192;
+    static_assert(R >= VW, "ring too small");
+    static constexpr int SB = S * W / 8;           // packed bytes of S samples
+    static constexpr int PAD = W == 4 ? 16 : 8;    // bytes after every S samples (bank spread)
+    static constexpr int BLK = SB + PAD;
+    static constexpr int VPH = (R / S) * BLK;
+    static constexpr int UOFF = 128;               // u window starts UOFF samples before the chunk
+    static constexpr int UW = CM + UOFF + 128;     // u window (samples)
+    static constexpr int UB = UW * W / 8;
+    static constexpr int WAVE_LDS = VPH + UB;
+    static_assert(4 * WAVE_LDS <= MCfg<4>::LDS, "fits the int8 engine's LDS");
+    static constexpr int FILL_V = VW / 16;         // 16-sample units
+    static constexpr int NEW_V = CM / 16;
+    static constexpr int U_UNITS = UW / 16;
+    static constexpr int FILL_PER_LANE = (FILL_V + U_UNITS + 63) / 64;
+    static constexpr int NEXT_PER_LANE = (NEW_V + U_UNITS + 63) / 64;
+    static constexpr int BD = 2 * W + 1;           // dwords of a B_1 | B_0 window
+    // the window of step -1 (history) starts at sample UOFF - 127 >= 0; the
+    // last one read (one step past a full chunk) ends inside the u window
+    static_assert(UOFF >= 127, "history window before the u window");
+    static_assert(((W * (UOFF + CM)) >> 5) + BD <= UB / 4, "u window too small");
+};
+
+// Four int8 codes (|q| <= 7, resp. 3) -> four bytes holding W-bit codes:
+// sign bit W-1, magnitude code from a byte table (v_perm_b32 as an 8-entry
+// lookup), no carries between bytes.
+template <int W>
+__device__ __forceinline__ uint32_t fp_bytes(uint32_t x) {
+    const uint32_t s = (x >> 7) & 0x01010101u;
+    const uint32_t a = (x ^ (s * 0xffu)) + s;      // |q| per byte
+    // E2M3: 0 1 2 3 4 5 6 7 -> 000000 001000 010000 010100 011000 011010 011100 011110
+    // E2M1: 0 1 2 3 (4 . 6 .) -> 0000 0010 0100 0101 (0110 . 0111 .)
+    const uint32_t m = W == 6 ? __builtin_amdgcn_perm(0x1e1c1a18u, 0x14100800u, a)
+                              : __builtin_amdgcn_perm(0x00070006u, 0x05040200u, a);
+    return m | (s << (W - 1));
+}
+
+template <int W>
+struct Packed16 {
+    uint32_t d[W / 2];   // 16 codes
+};
+
+template <int W>
+__device__ __forceinline__ Packed16<W> fp_pack16(uint4 x) {
+    const uint32_t c[4] = {fp_bytes<W>(x.x), fp_bytes<W>(x.y), fp_bytes<W>(x.z), fp_bytes<W>(x.w)};
+    Packed16<W> o;
+    if constexpr (W == 4) {
+        uint32_t h[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            uint32_t t = c[k];
+            t = (t | (t >> 4)) & 0x00ff00ffu;
+            h[k] = (t | (t >> 8)) & 0x0000ffffu;
+        }
+        o.d[0] = h[0] | (h[1] << 16);
+        o.d[1] = h[2] | (h[3] << 16);
+    } else {
+        uint32_t z[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            uint32_t t = c[k];
+            t = (t & 0x003f003fu) | ((t >> 2) & 0x0fc00fc0u);
+            z[k] = (t & 0xfffu) | ((t >> 4) & 0xfff000u);
+        }
+        o.d[0] = z[0] | (z[1] << 24);
+        o.d[1] = (z[1] >> 8) | (z[2] << 16);
+        o.d[2] = (z[2] >> 16) | (z[3] << 8);
+    }
+    return o;
+}
+
+// Per-wave staging of packed codes; the same windows as WaveStager, in
+// samples, with S samples per padded block of the v ring.
+template <int W>
+struct FpStager {
+    using C = FCfg<W>;
+    uint4 reg[C::NEXT_PER_LANE];
+
+    __device__ __forceinline__ static int vphys(int p) { return (p >> C::LS) * C::BLK + ((p & (C::S - 1)) * W) / 8; }
+    __device__ __forceinline__ static void put(uint8_t* dst, uint4 x) {
+        const Packed16<W> c = fp_pack16<W>(x);
+        uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+#pragma unroll
+        for (int k = 0; k < W / 2; ++k) d[k] = c.d[k];
+    }
+
+    __device__ __forceinline__ void fill(const XPair& p, int64_t T0, int64_t qw, uint8_t* vb, uint8_t* ub,
+                                         int lane) {
+        const int64_t gv0 = qw + T0;
+        const int64_t gu0 = qw - C::UOFF;
+        uint4 x[C::FILL_PER_LANE];
+#pragma unroll
+        for (int k = 0; k < C::FILL_PER_LANE; ++k) {
+            const int unit = lane + 64 * k;
+            if (unit < C::FILL_V)
+                x[k] = load16_guarded(p.v, p.nv, gv0 + 16 * (int64_t)unit);
+            else if (unit < C::FILL_V + C::U_UNITS)
+                x[k] = load16_guarded(p.u, p.nu, gu0 + 16 * (int64_t)(unit - C::FILL_V));
+        }
+#pragma unroll
+        for (int k = 0; k < C::FILL_PER_LANE; ++k) {
+            const int unit = lane + 64 * k;
+            if (unit < C::FILL_V)
+                put(vb + vphys(16 * unit), x[k]);
+            else if (unit < C::FILL_V + C::U_UNITS)
+                put(ub + 2 * W * (unit - C::FILL_V), x[k]);
+        }
+    }
+    __device__ __forceinline__ void load_next(const XPair& p, int64_t T0, int64_t qw, int c, int lane) {
+        const int64_t rel0 = (int64_t)(c - 1) * C::CM + C::VW;    // first new window sample
+        const int64_t gv0 = qw + T0 + rel0;
+        const int64_t gu0 = qw + (int64_t)c * C::CM - C::UOFF;
+#pragma unroll
+        for (int k = 0; k < C::NEXT_PER_LANE; ++k) {
+            const int unit = lane + 64 * k;
+            if (unit < C::NEW_V)
+                reg[k] = load16_guarded(p.v, p.nv, gv0 + 16 * (int64_t)unit);
+            else if (unit < C::NEW_V + C::U_UNITS)
+                reg[k] = load16_guarded(p.u, p.nu, gu0 + 16 * (int64_t)(unit - C::NEW_V));
+        }
+    }
+    __device__ __forceinline__ void store_next(int c, uint8_t* vb, uint8_t* ub, int lane) {
+        const int rel0 = (int)(((int64_t)(c - 1) * C::CM + C::VW) & (C::R - 1));
+#pragma unroll
+        for (int k = 0; k < C::NEXT_PER_LANE; ++k) {
+            const int unit = lane + 64 * k;
+            if (unit < C::NEW_V)
+                put(vb + vphys((rel0 + 16 * unit) & (C::R - 1)), reg[k]);
+            else if (unit < C::NEW_V + C::U_UNITS)
+                put(ub + 2 * W * (unit - C::NEW_V), reg[k]);
+        }
+    }
+};
+
+// A fragment: 32 codes of one row (16 or 24 bytes, 16- resp. 8-byte aligned).
+template <int W>
+__device__ __forceinline__ v8i read_a_fp(const uint8_t* p) {
+    v8i r = {0, 0, 0, 0, 0, 0, 0, 0};
+    if constexpr (W == 4) {
+        const uint4 x = *reinterpret_cast<const uint4*>(p);
+        r[0] = (int)x.x; r[1] = (int)x.y; r[2] = (int)x.z; r[3] = (int)x.w;
+    } else {
+        const uint2* q = reinterpret_cast<const uint2*>(p);
+        const uint2 x = q[0], y = q[1], z = q[2];
+        r[0] = (int)x.x; r[1] = (int)x.y; r[2] = (int)y.x; r[3] = (int)y.y; r[4] = (int)z.x; r[5] = (int)z.y;
+    }
+    return r;
+}
+
+template <int W>
+struct BWin {
+    uint32_t d[2 * W + 1];
+};
+
+template <int W>
+__device__ __forceinline__ BWin<W> read_bwin(const uint32_t* dw) {
+    BWin<W> r;
+#pragma unroll
+    for (int k = 0; k < 2 * W + 1; ++k) r.d[k] = dw[k];
+    return r;
+}
+
+// window bits [32 r + sh, ...): B_1 = dwords 0 .. W-1, B_0 = dwords W .. 2W-1
+template <int W>
+__device__ __forceinline__ void split_bwin(const BWin<W>& r, uint32_t sh, v8i& b1, v8i& b0) {
+    b1 = v8i{0, 0, 0, 0, 0, 0, 0, 0};
+    b0 = v8i{0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        b1[k] = (int)__builtin_amdgcn_alignbit(r.d[k + 1], r.d[k], sh);
+        b0[k] = (int)__builtin_amdgcn_alignbit(r.d[W + k + 1], r.d[W + k], sh);
+    }
+}
+
+template <int W>
+__device__ __forceinline__ v16f mfma_fp(const v8i& a, const v8i& b, const v16f& c) {
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, FCfg<W>::FMT, FCfg<W>::FMT, 0, 127, 0, 127);
+}
+
+// The m loop of one wave over [qw_a, qw_b) (a multiple of 128) for the tile
+// at T0, FP operands; the partial sums come back as int32.
+template <int W>
+__device__ __forceinline__ void wave_loop_fp(const XPair& p, int64_t T0, int64_t qw_a, int64_t qw_b, uint8_t* wl,
+                                             int lane, v16i* acc_out) {
+    using C = FCfg<W>;
+    const int lc = lane & 31;
+    const int g = lane >> 5;
+    uint8_t* vb = wl;
+    uint8_t* ub = wl + C::VPH;
+    FpStager<W> st;
+    const int nch = (int)((qw_b - qw_a + C::CM - 1) / C::CM);
+    st.fill(p, T0, qw_a, vb, ub, lane);
+
+    const int brel = C::UOFF + 32 * g - lc - 32;   // first code of the step-0 window (>= 1)
+    const uint32_t* ubw = reinterpret_cast<const uint32_t*>(ub) + ((W * brel) >> 5);
+    const uint32_t bsh = (uint32_t)((W * brel) & 31);
+    const int a_in = (32 * g * W) / 8;             // the lane's k half inside a row
+    constexpr int ASTEP = C::KS * W / 8;           // bytes per step along a row
+
+    v16f acc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[b][e] = 0.f;
+
+    for (int c = 0; c < nch; ++c) {
+        if (c + 1 < nch) st.load_next(p, T0, qw_a, c + 1, lane);
+        const int base = (int)(((int64_t)c * C::CM) & (C::R - 1));
+        const int64_t rem = (qw_b - qw_a - (int64_t)c * C::CM) / C::KS;
+        const int nsteps = rem < C::CQ ? (int)rem : C::CQ;
+
+        v8i h0, h1;                                   // B_0, B_1 of the previous step
+        split_bwin<W>(read_bwin<W>(ubw - 2 * W), bsh, h1, h0);
+        // Software pipeline as in the int8 loop: fragments of step s+1 are
+        // read while the matrix instructions of step s run (reading one step
+        // past the chunk stays inside the staged windows). Two steps share
+        // one padded row block of the ring, so their offsets are constants.
+        int blk = ((base + C::S * lc) & (C::R - 1)) >> C::LS;
+        const uint8_t* arow = vb + blk * C::BLK + a_in;
+        v8i a_cur = read_a_fp<W>(arow);
+        v8i b0, b1;
+        split_bwin<W>(read_bwin<W>(ubw), bsh, b1, b0);
+        for (int s0 = 0; s0 < nsteps; s0 += 2) {
+            const int nb = (blk + 1) & (C::R / C::S - 1);
+            const uint8_t* arow_next = vb + nb * C::BLK + a_in;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int s = s0 + t;
+                const v8i a_nxt = read_a_fp<W>(t == 0 ? arow + ASTEP : arow_next);
+                const BWin<W> raw = read_bwin<W>(ubw + 2 * W * (s + 1));
+                __builtin_amdgcn_sched_barrier(0);
+                acc[0] = mfma_fp<W>(a_cur, b0, acc[0]);
+                acc[1] = mfma_fp<W>(a_cur, b1, acc[1]);
+                acc[2] = mfma_fp<W>(a_cur, h0, acc[2]);
+                acc[3] = mfma_fp<W>(a_cur, h1, acc[3]);
+                __builtin_amdgcn_sched_barrier(0);
+                h0 = b0;
+                h1 = b1;
+                a_cur = a_nxt;
+                split_bwin<W>(raw, bsh, b1, b0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            blk = nb;
+            arow = arow_next;
+        }
+        if (c + 1 < nch) st.store_next(c + 1, vb, ub, lane);
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc_out[b][e] = (int)acc[b][e];
+}
+
 template <int MB>
 __device__ __forceinline__ void mfma_item(const XItem& it, const MWork& wk, uint8_t* lds, ArgPart* tile_parts) {
     using C = MCfg<MB>;
@@ -275,7 +560,14 @@ __device__ __forceinline__ void mfma_item(const XItem& it, const MWork& wk, uint
     for (int b = 0; b < MB; ++b)
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[b][e] = 0;
-    if (qw_a < qw_b) wave_loop<MB>(p, T0, qw_a, qw_b, lds + w * C::WAVE_LDS, lane, acc);
+    if (qw_a < qw_b) {
+        if (MB == 4 && it.fmt == kFmtF6)
+            wave_loop_fp<6>(p, T0, qw_a, qw_b, lds + w * FCfg<6>::WAVE_LDS, lane, acc);
+        else if (MB == 4 && it.fmt == kFmtF4)
+            wave_loop_fp<4>(p, T0, qw_a, qw_b, lds + w * FCfg<4>::WAVE_LDS, lane, acc);
+        else
+            wave_loop<MB>(p, T0, qw_a, qw_b, lds + w * C::WAVE_LDS, lane, acc);
+    }
 
     __syncthreads();
     const bool wide = it.wide != 0;
@@ -448,18 +740,20 @@ __device__ __forceinline__ void mfma_item(const XItem& it, const MWork& wk, uint
 // Persistent: each workgroup takes items until the list is exhausted; every
 // wave of the grid reaches the exit once the counter passes nwork.
 template <int MB>
-__global__ void __launch_bounds__(256, MB == 4 ? 2 : 1) k_xcorr_mfma(const XItem* items, XItem one, const MWork* work,
-                                                       int nwork, int* counter, ArgPart* tile_parts) {
+__global__ void __launch_bounds__(256, MB == 4 ? 2 : 1) k_xcorr_mfma(const XItem* __restrict__ items,
+                                                                      const MWork* __restrict__ work, int nwork,
+                                                                      int* counter, ArgPart* tile_parts) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     __shared__ int s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
         __syncthreads();
-        const int wi = s_item;
+        // uniform: descriptors come through scalar loads, not VGPRs
+        const int wi = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (wi >= nwork) break;
         const MWork wk = work[wi];
-        const XItem& it = items ? items[wk.pair] : one;
+        const XItem& it = items[wk.pair];
         if (it.margin && *it.margin >= it.theta) continue;   // learned mode: windows suffice
         mfma_item<MB>(it, wk, lds, tile_parts);     // the list holds only items of this variant
         __syncthreads();
@@ -538,11 +832,26 @@ static void tile_range_mb(const XItem& it, int64_t t, int64_t& Q_lo, int64_t& le
     else tile_range<4>(it.p, it.T_start + t * MCfg<4>::TLW, Q_lo, len);
 }
 
-// Longest m range one item may cover: each wave's quarter stays int32-safe.
+// Longest m range one item may cover: each wave's quarter stays exact in its
+// accumulators (int32, or fp32 integers below 2^24 for FP operands).
 static int64_t seg_cap(const XItem& it) {
     const int64_t unit = 32 * (int64_t)it.mb;
-    const int64_t per_wave = ((int64_t)0x7fffffff / it.p.kuv) / unit * unit;
+    const int64_t lim = it.fmt == kFmtI8 ? (int64_t)0x7fffffff : ((int64_t)1 << 24) - 1;
+    const int64_t per_wave = (lim / it.p.kuv) / unit * unit;
     return 4 * per_wave;
+}
+
+// FP4 for codes up to 3, FP6 up to 7 (both exact); TDE_MFMA_FP=0 in the
+// environment keeps int8 everywhere.
+static int choose_fmt(const XPair& p, bool allow_fp) {
+    static const bool fp_on = [] {
+        const char* e = getenv("TDE_MFMA_FP");
+        return !(e && atoi(e) == 0);
+    }();
+    if (!allow_fp || !fp_on || p.kmax < 1) return kFmtI8;
+    if (p.kmax <= 3) return kFmtF4;
+    if (p.kmax <= 7) return kFmtF6;
+    return kFmtI8;
 }
 
 // 8 accumulator tiles per wave halve the LDS bytes per matrix instruction but
@@ -559,8 +868,9 @@ int choose_mb(const XPair& p) {
     return 4;
 }
 
-void mfma_plan_pair(XItem& it) {
-    it.mb = choose_mb(it.p);
+void mfma_plan_pair(XItem& it, bool allow_fp) {
+    it.fmt = choose_fmt(it.p, allow_fp);
+    it.mb = it.fmt == kFmtI8 ? choose_mb(it.p) : 4;
     const int64_t TLW = it.mb == 8 ? MCfg<8>::TLW : MCfg<4>::TLW;
     int64_t lo, hi;
     clamp_support(it.p, lo, hi);
@@ -629,26 +939,30 @@ void mfma_items(const XItem& it, int pair, std::vector<MWork>& out) {
         tile_range_mb(it, t, Q_lo, len);
         if (len == 0) {
             // no overlap anywhere in the tile: an empty item writes its zeros
-            out.push_back(MWork{pair, (int32_t)t, 0, 0, it.segmented, it.mb});
+            out.push_back(MWork{pair, (int32_t)t, 0, 0, it.segmented, it.mb, it.fmt, 0});
             continue;
         }
         for (int64_t o = 0; o < len; o += cap)
             out.push_back(MWork{pair, (int32_t)t, Q_lo + o, Q_lo + (o + cap < len ? o + cap : len), it.segmented,
-                                it.mb});
+                                it.mb, it.fmt, 0});
     }
 }
 
-// Longest first, the 4-tile items ahead of the 8-tile ones (two launches).
+// Most expensive first (an FP step covers twice the m of an int8 step for
+// the same matrix work), the 4-tile items ahead of the 8-tile ones (two
+// launches).
+static int64_t item_cost(const MWork& a) { return (a.qb - a.qa) * (a.fmt == kFmtI8 ? 2 : 1); }
+
 void mfma_sort_items(std::vector<MWork>& w) {
     std::stable_sort(w.begin(), w.end(), [](const MWork& a, const MWork& b) {
         if (a.mb != b.mb) return a.mb < b.mb;
-        return (a.qb - a.qa) > (b.qb - b.qa);
+        return item_cost(a) > item_cost(b);
     });
 }
 
 template <int MB>
-static int launch_mb(const XItem* items_dev, const XItem& one, const MWork* work, int nwork, int* counter,
-                     ArgPart* tile_parts, int num_cu, hipStream_t s) {
+static int launch_mb(const XItem* items_dev, const MWork* work, int nwork, int* counter, ArgPart* tile_parts,
+                     int num_cu, hipStream_t s) {
     using C = MCfg<MB>;
     if (nwork == 0) return TDE_OK;
     static int per_cu = 0;
@@ -661,22 +975,21 @@ static int launch_mb(const XItem* items_dev, const XItem& one, const MWork* work
     }
     int grid = per_cu * num_cu;
     if (grid > nwork) grid = nwork;
-    hipLaunchKernelGGL(k_xcorr_mfma<MB>, dim3(grid), dim3(256), C::LDS, s, items_dev, one, work, nwork, counter,
+    hipLaunchKernelGGL(k_xcorr_mfma<MB>, dim3(grid), dim3(256), C::LDS, s, items_dev, work, nwork, counter,
                        tile_parts);
     TDE_HIP_CHECK(hipGetLastError());
     return TDE_OK;
 }
 
-int launch_xcorr_mfma(const XItem* items_dev, const XItem& one, const MWork* work_dev, int nwork,
-                      int* counters_dev, bool counters_zeroed, ArgPart* tile_parts, int num_cu, hipStream_t s,
-                      int n4) {
+int launch_xcorr_mfma(const XItem* items_dev, const MWork* work_dev, int nwork, int* counters_dev,
+                      bool counters_zeroed, ArgPart* tile_parts, int num_cu, hipStream_t s, int n4) {
     if (!counters_zeroed) {
         hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, counters_dev, 2);
         TDE_HIP_CHECK(hipGetLastError());
     }
-    int rc = launch_mb<4>(items_dev, one, work_dev, n4, counters_dev, tile_parts, num_cu, s);
+    int rc = launch_mb<4>(items_dev, work_dev, n4, counters_dev, tile_parts, num_cu, s);
     if (rc) return rc;
-    return launch_mb<8>(items_dev, one, work_dev + n4, nwork - n4, counters_dev + 1, tile_parts, num_cu, s);
+    return launch_mb<8>(items_dev, work_dev + n4, nwork - n4, counters_dev + 1, tile_parts, num_cu, s);
 }
 
 int launch_tiles_final(const XItem* items_dev, const XItem& one, int npairs, const ArgPart* tile_parts,

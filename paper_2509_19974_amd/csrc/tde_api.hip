@@ -158,6 +158,7 @@ void drop_graphs_on(tde_ctx* c, const void* ws, size_t bytes) {
 // Engine choice for one correlation: the caller's, or the tuning table's
 // (every engine is exact; they differ in speed).
 int choose_path(int path, int64_t nu, int64_t nv, int kuv, int64_t lo, int64_t hi) {
+    if (path == TDE_PATH_MFMA_I8) return TDE_PATH_MFMA;
     if (path != TDE_PATH_AUTO) return path;
     return auto_engine(nu, nv, kuv, lo, hi);
 }
@@ -306,7 +307,7 @@ static int check_xcorr(const int8_t* u, int64_t nu, const int8_t* v, int64_t nv,
     if (r_dtype != TDE_I32 && r_dtype != TDE_I64) return set_error(TDE_ERR_ARG, "%s: bad r_dtype", who);
     if (((uintptr_t)r) & (r_dtype == TDE_I32 ? 3 : 7))
         return set_error(TDE_ERR_ARG, "%s: r is not aligned to its element size", who);
-    if (path < TDE_PATH_AUTO || path > TDE_PATH_NTT) return set_error(TDE_ERR_ARG, "%s: bad path", who);
+    if (path < TDE_PATH_AUTO || path > TDE_PATH_MFMA_I8) return set_error(TDE_ERR_ARG, "%s: bad path", who);
     if (path == TDE_PATH_POPC && (kmax_u != 1 || kmax_v != 1))
         return set_error(TDE_ERR_ARG, "%s: the bit-plane engine needs ternary codes (kmax 1)", who);
     if (path == TDE_PATH_NTT) {
@@ -332,6 +333,7 @@ size_t tde_xcorr_workspace_size(int64_t nu, int64_t nv, int kmax_u, int kmax_v, 
     it.p.lag_lo = lag_lo;
     it.p.lag_hi = lag_hi;
     it.p.kuv = kmax_u * kmax_v;
+    it.p.kmax = kmax_u > kmax_v ? kmax_u : kmax_v;
     int eng = choose_path(path, nu, nv, it.p.kuv, lag_lo, lag_hi);
     if (eng == TDE_PATH_POPC) return popc_ws_bytes(it.p);
     if (eng == TDE_PATH_NTT) {
@@ -339,8 +341,9 @@ size_t tde_xcorr_workspace_size(int64_t nu, int64_t nv, int kmax_u, int kmax_v, 
         if (!ntt_plan(nu, nv, it.p.kuv, lag_lo, lag_hi, P)) return 0;
         return align_bytes(sizeof(NttJob)) + align_bytes(ntt_tab_words(P) * 4) + align_bytes(ntt_res_bytes(P));
     }
-    mfma_plan_pair(it);
-    return align_bytes((size_t)mfma_count_items(it) * sizeof(MWork)) + align_bytes(2 * sizeof(int));
+    mfma_plan_pair(it, path != TDE_PATH_MFMA_I8);
+    return align_bytes(sizeof(XItem)) + align_bytes((size_t)mfma_count_items(it) * sizeof(MWork)) +
+           align_bytes(2 * sizeof(int));
 }
 
 int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, int64_t nv, int kmax_u, int kmax_v,
@@ -359,9 +362,11 @@ int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, in
     it.p.r = r;
     it.p.r_dtype = r_dtype;
     it.p.kuv = kmax_u * kmax_v;
+    it.p.kmax = kmax_u > kmax_v ? kmax_u : kmax_v;
     const int eng = choose_path(path, nu, nv, it.p.kuv, lag_lo, lag_hi);
     it.engine = eng;
-    size_t need = tde_xcorr_workspace_size(nu, nv, kmax_u, kmax_v, lag_lo, lag_hi, eng);
+    const int wpath = path == TDE_PATH_MFMA_I8 ? path : eng;
+    size_t need = tde_xcorr_workspace_size(nu, nv, kmax_u, kmax_v, lag_lo, lag_hi, wpath);
     if (need && (!ws || ws_bytes < need))
         return set_error(TDE_ERR_WS, "tde_xcorr_int: workspace %zu < %zu bytes", ws_bytes, need);
     DeviceGuard g(ctx->device);
@@ -409,20 +414,25 @@ int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, in
         if (P.jlo > P.jhi) return TDE_OK;          // every requested lag is outside the support
         return launch_ntt(ntt_group(P, tab), job_dev, 1, s);
     }
-    mfma_plan_pair(it);
+    mfma_plan_pair(it, path != TDE_PATH_MFMA_I8);
     std::vector<MWork> work;
     mfma_items(it, 0, work);
     mfma_sort_items(work);
-    MWork* work_dev = static_cast<MWork*>(ws);
-    int* counters = reinterpret_cast<int*>(static_cast<uint8_t*>(ws) +
-                                           align_bytes((size_t)mfma_count_items(it) * sizeof(MWork)));
+    // workspace: the item, the work list, two counters (one upload)
+    const size_t off_w = align_bytes(sizeof(XItem));
+    std::vector<uint8_t> blob(off_w + work.size() * sizeof(MWork));
+    memcpy(blob.data(), &it, sizeof(XItem));
+    memcpy(blob.data() + off_w, work.data(), work.size() * sizeof(MWork));
+    uint8_t* W = static_cast<uint8_t*>(ws);
+    int* counters = reinterpret_cast<int*>(W + off_w + align_bytes(work.size() * sizeof(MWork)));
     {
         std::lock_guard<std::mutex> lock(ctx->mu);
         drop_graphs_on(ctx, ws, ws_bytes);
-        rc = upload(ctx, work_dev, work.data(), work.size() * sizeof(MWork), s);
+        rc = upload(ctx, W, blob.data(), blob.size(), s);
     }
     if (rc) return rc;
-    return launch_xcorr_mfma(nullptr, it, work_dev, (int)work.size(), counters, false, nullptr, ctx->num_cu, s,
+    return launch_xcorr_mfma(reinterpret_cast<const XItem*>(W), reinterpret_cast<const MWork*>(W + off_w),
+                             (int)work.size(), counters, false, nullptr, ctx->num_cu, s,
                              it.mb == 4 ? (int)work.size() : 0);
 }
 
@@ -506,12 +516,14 @@ int validate_pairs(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
     const bool learned = opts && opts->mode == TDE_MODE_LEARNED;
     if (opts && opts->mode != TDE_MODE_FULL && !learned)
         return set_error(TDE_ERR_ARG, "tde_estimate_batch: unknown mode %d", opts->mode);
+    if (path < TDE_PATH_AUTO || path > TDE_PATH_MFMA_I8)
+        return set_error(TDE_ERR_ARG, "tde_estimate_batch: bad path %d", path);
     if (learned) {
         if (!opts->model) return set_error(TDE_ERR_ARG, "tde_estimate_batch: learned mode needs a model");
         if (opts->topk < 1 || opts->topk > kCnnMaxTop || opts->topk >= model_net(opts->model).nb)
             return set_error(TDE_ERR_ARG, "tde_estimate_batch: topk must be in [1, %d]", kCnnMaxTop);
         if (std::isnan(opts->margin)) return set_error(TDE_ERR_ARG, "tde_estimate_batch: NaN margin");
-        if (path != TDE_PATH_AUTO && path != TDE_PATH_MFMA)
+        if (path != TDE_PATH_AUTO && path != TDE_PATH_MFMA && path != TDE_PATH_MFMA_I8)
             return set_error(TDE_ERR_ARG, "tde_estimate_batch: learned mode falls back on TDE_PATH_MFMA");
         const CnnNet& net = model_net(opts->model);
         const int64_t n = 16 * (int64_t)net.ld, half = (int64_t)(net.nb / 2) * 256;
@@ -599,8 +611,9 @@ PairPlan plan_pair(const tde_pair& q, int path, bool learned) {
     pp.probe.p.lag_lo = q.lag_lo;
     pp.probe.p.lag_hi = q.lag_hi;
     pp.probe.p.kuv = K * K;
+    pp.probe.p.kmax = K;
     if (pp.eng == TDE_PATH_MFMA) {
-        mfma_plan_pair(pp.probe);
+        mfma_plan_pair(pp.probe, path != TDE_PATH_MFMA_I8);
         pp.fused = !pp.probe.segmented;
     } else if (pp.eng == TDE_PATH_NTT) {
         ntt_plan(q.nx, q.ny, K * K, q.lag_lo, q.lag_hi, pp.ntt);
@@ -935,7 +948,7 @@ int batch_enqueue(tde_ctx* ctx, uint8_t* W, const BatchPlan& B, const BatchLaunc
         if (rc) return rc;
     }
     if (L.any_mfma) {
-        rc = launch_xcorr_mfma(items_dev, none, reinterpret_cast<const MWork*>(W + B.off_work), L.nwork,
+        rc = launch_xcorr_mfma(items_dev, reinterpret_cast<const MWork*>(W + B.off_work), L.nwork,
                                reinterpret_cast<int*>(W + B.off_counters), true, tparts, ctx->num_cu, s, L.n4);
         if (rc) return rc;
     }

@@ -118,6 +118,8 @@ struct XPair {
     void* r;              // lag_hi - lag_lo + 1 elements
     int32_t r_dtype;
     int32_t kuv;          // kmax_u * kmax_v
+    int32_t kmax;         // max(kmax_u, kmax_v): selects the operand format of the MFMA engine
+    int32_t pad0;
 };
 
 // fill r with zeros (a kernel, never a memset node)
@@ -136,7 +138,7 @@ struct XItem {
     int32_t wide;         // tile sums may exceed int32: reduce in int64
     int32_t segmented;    // tiles cut into several items: r by atomics, no triples
     int32_t fused;        // argmax from tile triples (no r array needed)
-    int32_t pad0;
+    int32_t fmt;          // MFMA operand format (kFmtI8, kFmtF6, kFmtF4)
     int64_t part_base;    // first tile-triple slot of this pair
     int64_t out_v, out_i, out_c;   // triple of the lags no tile covers (r = 0)
     const tde_qstat* stat_x;
@@ -169,8 +171,18 @@ struct MWork {
     int64_t qa, qb;       // m range [qa, qb), multiples of 32
     int32_t segmented;
     int32_t mb;           // accumulator tiles per wave of the pair's plan
+    int32_t fmt;          // operand format of the pair's plan
+    int32_t pad0;
 };
-void mfma_plan_pair(XItem& it);                 // sets mb, T_start, ntiles, wide, segmented, outside triple
+// Operand formats of the matrix-core engine. Codes with |q| <= 3 are exact in
+// FP4 (E2M1), |q| <= 7 in FP6 (E2M3); both run the f8f6f4 matrix instruction
+// at twice the int8 rate. The values double as the instruction's format codes.
+constexpr int kFmtI8 = 0;      // (the instruction would read 0 as FP8; int8 items never use it)
+constexpr int kFmtF6 = 2;
+constexpr int kFmtF4 = 4;
+// sets fmt, mb, T_start, ntiles, wide, segmented, outside triple; allow_fp =
+// false keeps int8 operands whatever the code range
+void mfma_plan_pair(XItem& it, bool allow_fp = true);
 int64_t mfma_total_q(const XItem& it);          // summed m range of its tiles
 int64_t mfma_count_items(const XItem& it);
 void mfma_items(const XItem& it, int pair, std::vector<MWork>& out);
@@ -179,9 +191,8 @@ void mfma_sort_items(std::vector<MWork>& w);
 // mb = 4. tile_parts may be null (no triples written); counters_dev: 2 ints
 // of scratch, reset here unless an earlier kernel of the call already did.
 int choose_mb(const XPair& p);
-int launch_xcorr_mfma(const XItem* items_dev, const XItem& one, const MWork* work_dev, int nwork,
-                      int* counters_dev, bool counters_zeroed, ArgPart* tile_parts, int num_cu, hipStream_t s,
-                      int n4);
+int launch_xcorr_mfma(const XItem* items_dev, const MWork* work_dev, int nwork, int* counters_dev,
+                      bool counters_zeroed, ArgPart* tile_parts, int num_cu, hipStream_t s, int n4);
 // peaks of the fused pairs from their tile triples
 int launch_tiles_final(const XItem* items_dev, const XItem& one, int npairs, const ArgPart* tile_parts,
                        hipStream_t s);

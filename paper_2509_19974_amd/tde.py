@@ -27,7 +27,7 @@ TDE_ERR_UNSUPPORTED = -5
 TDE_ERR_IO = -6
 
 TDE_I32, TDE_I64 = 0, 1
-TDE_PATH_AUTO, TDE_PATH_MFMA, TDE_PATH_POPC, TDE_PATH_NTT = 0, 1, 2, 3
+TDE_PATH_AUTO, TDE_PATH_MFMA, TDE_PATH_POPC, TDE_PATH_NTT, TDE_PATH_MFMA_I8 = 0, 1, 2, 3, 4
 TDE_MODE_FULL, TDE_MODE_LEARNED = 0, 1
 
 TDE_FLAG_NONFINITE_X = 1

@@ -111,6 +111,9 @@ def test_xcorr_argument_validation():
     assert _xcorr_status(dt=7) == tde.TDE_ERR_ARG
     assert _xcorr_status(r=FAKE + 2, dt=tde.TDE_I32) == tde.TDE_ERR_ARG
     assert _xcorr_status(path=tde.TDE_PATH_POPC, ku=2) == tde.TDE_ERR_ARG
+    assert _xcorr_status(path=tde.TDE_PATH_MFMA_I8 + 1) == tde.TDE_ERR_ARG
+    assert _xcorr_status(path=-1) == tde.TDE_ERR_ARG
+    assert _xcorr_status(path=tde.TDE_PATH_MFMA_I8) == tde.TDE_ERR_ARG and "null context" in tde.tde_last_error()
     # the transform engine stops at n = 2^23: nu + nv - 1 = 2^23 fits, 2^23 + 1 does not
     n22 = 1 << 22
     assert _xcorr_status(path=tde.TDE_PATH_NTT, nu=n22, nv=n22, lo=-(n22 - 1), hi=n22 - 1) == tde.TDE_ERR_ARG
@@ -157,6 +160,12 @@ def test_batch_argument_validation():
         arr = tde.make_pairs([pair(), bad])
         assert tde.tde_estimate_workspace_size(arr, 2, opts) == 0
         assert "pair 1" in tde.tde_last_error()
+    for path in (-1, tde.TDE_PATH_MFMA_I8 + 1):
+        bad_opts = tde.tde_opts(tde.TDE_MODE_FULL, path, 0, 0, None, 0.0, 0)
+        assert tde.tde_estimate_workspace_size(good, 2, bad_opts) == 0
+        assert "bad path" in tde.tde_last_error()
+    i8_opts = tde.tde_opts(tde.TDE_MODE_FULL, tde.TDE_PATH_MFMA_I8, 0, 0, None, 0.0, 0)
+    assert tde.tde_estimate_workspace_size(good, 2, i8_opts) > 0
     arr = tde.make_pairs([pair(nx=300000, ny=300000, bits=8, lo=-10, hi=10, dt=tde.TDE_I32, r=FAKE)])
     lib = tde.load_library()
     st = lib.tde_estimate_batch(None, arr, 1, ctypes.byref(opts), FAKE, FAKE, 1 << 30, None)

@@ -150,6 +150,44 @@ def test_xcorr_mfma_parity_i32(T, ctx, case):
     _run_xcorr(T, ctx, tde.TDE_PATH_MFMA, nu, nv, lo, hi, k, tde.TDE_I32)
 
 
+# codes up to 3 run the matrix cores with FP4 operands, up to 7 with FP6;
+# TDE_PATH_MFMA_I8 keeps int8 operands for the same requests
+FPCASES = [c for c in XCASES if c[4] <= 7] + [
+    # nu, nv, lag_lo, lag_hi, k
+    (8191, 8192, -8191, 8191, 3),
+    (12289, 4097, -4096, 12288, 2),
+    (65536, 65536, -65535, 65535, 5),
+    (130000, 129000, -700, 900, 6),
+    (2049, 70000, 60000, 67999, 7),
+]
+
+
+@pytest.mark.parametrize("case", FPCASES)
+def test_xcorr_mfma_fp_operands_parity(T, ctx, case):
+    from paper_2509_19974_amd import tde
+    nu, nv, lo, hi, k = case
+    r, ro = _run_xcorr(T, ctx, tde.TDE_PATH_MFMA, nu, nv, lo, hi, k, tde.TDE_I64)
+    r8, _ = _run_xcorr(T, ctx, tde.TDE_PATH_MFMA_I8, nu, nv, lo, hi, k, tde.TDE_I64)
+    np.testing.assert_array_equal(r.cpu().numpy(), r8.cpu().numpy())
+
+
+def test_xcorr_fp_segmented_near_fp32_bound(T, ctx):
+    """FP6 codes whose m range exceeds four fp32-exact quarters (each below
+    2^24 / 49 values of m): the tile is cut into segments that add into r."""
+    from paper_2509_19974_amd import tde
+    n = 1500000
+    rng = np.random.default_rng(1500)
+    u = (7 * rng.choice(np.array([-1, 1], np.int8), n)).astype(np.int8)
+    u[rng.integers(0, n, n // 50)] = 3
+    v = u.copy()
+    v[::7] = -v[::7]
+    say("xcorr fp6 segmented")
+    r = ctx.xcorr(dev(T, u), dev(T, v), 7, 7, -3, 3, tde.TDE_I64, tde.TDE_PATH_MFMA)
+    ro = oracle.xcorr(u, v, -3, 3)
+    assert np.abs(ro).max() > 2 ** 24
+    np.testing.assert_array_equal(r.cpu().numpy(), ro)
+
+
 @pytest.mark.parametrize("case", [c[:4] + (1,) for c in XCASES])
 def test_xcorr_popc_parity(T, ctx, case):
     from paper_2509_19974_amd import tde
@@ -297,6 +335,31 @@ def test_batch_ntt_config2_small(T, ctx, bits):
     pk, specs = _batch(T, ctx, pairs, 3, want_r=True)
     for i, p in enumerate(pairs):
         _check_pair(pk[i], p, specs[i]["r_out"].cpu().numpy())
+
+
+def test_batch_fp_and_int8_operands_agree(T, ctx):
+    """Mixed code ranges (FP4, FP6 and int8 operands in one launch) give the
+    same peaks as int8 operands everywhere, and the oracle's."""
+    from paper_2509_19974_amd import tde
+    say("batch fp vs int8 operands")
+    rng = np.random.default_rng(4242)
+    pairs = []
+    for i, b in enumerate([1, 2, 4, 8, 2, 4, 1, 4, 8, 2, 1, 8]):
+        n = int(rng.integers(900, 40000))
+        x = rng.standard_normal(n).astype(np.float32)
+        d = int(rng.integers(-n // 3, n // 3))
+        y = np.zeros(n + 111, np.float32)
+        lo_, hi_ = max(0, d), min(n + 111, n + d)
+        y[lo_:hi_] = x[lo_ - d:hi_ - d]
+        y += (0.3 * rng.standard_normal(n + 111)).astype(np.float32)
+        pairs.append(dict(x=x, y=y, lag_lo=-(n - 1), lag_hi=n + 110, bits=b))
+    pk, sp = _batch(T, ctx, pairs, tde.TDE_PATH_MFMA, want_r=True)
+    pk8, sp8 = _batch(T, ctx, pairs, tde.TDE_PATH_MFMA_I8, want_r=True)
+    assert pk.tobytes() == pk8.tobytes()
+    for i, p in enumerate(pairs):
+        r, r8 = sp[i]["r_out"].cpu().numpy(), sp8[i]["r_out"].cpu().numpy()
+        np.testing.assert_array_equal(r, r8)
+        _check_pair(pk[i], p, r)
 
 
 def test_batch_deterministic(T, ctx):
