@@ -33,6 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 matrix peak, 5.0 POP/s
+FP6_FP4_PEAK_TFLOPS = 10100.0  # MI355X dense FP6 / FP4 matrix peak, 10.1 PFLOP/s
 BF16_PEAK_TFLOPS = 2500.0    # MI355X dense bf16 matrix peak, 2.5 PFLOP/s
 HBM_PEAK_GBS = 8000.0
 # 256 CUs x 16 lanes/clock of 32-bit integer multiply (a quarter of the 64
@@ -278,7 +279,7 @@ def run_c5(args):
         "metric": "pairs/s and int-MAC/s vs FP32-FFT xcorr on MI355X at oracle-exact lags",
         "value": len(ev) * 1e3 / learn_ms, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": learn_ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "i8+bf16", "data": "synthetic",
+        "vs_baseline": None, "dtype": "i8+fp6+bf16", "data": "synthetic",
         "config": {"workload": "1024 reverberant pairs, N=2^18, b=4, lags [-2^16, 2^16-1], learned windows (top-8 of "
                                "512 bins, fallback below the tuned margin)", "pairs": len(ev), "n": n},
         "plain": {"pairs_per_s": len(ev) * 1e3 / plain_ms, "ms_per_step": plain_ms},
@@ -307,7 +308,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2")
-    ap.add_argument("--path", default="auto", choices=["auto", "mfma", "popc", "ntt"])
+    ap.add_argument("--path", default="auto", choices=["auto", "mfma", "mfma_i8", "popc", "ntt"])
     ap.add_argument("--eager", action="store_true",
                     help="time eager calls instead of HIP-graph replays of the whole call")
     ap.add_argument("--tune", action="store_true", help="run the engine autotuner before planning")
@@ -350,8 +351,8 @@ def main():
     ctx = tde.Context(0)
     specs = [dict(x=torch.from_numpy(p["x"]).cuda(), y=torch.from_numpy(p["y"]).cuda(), lag_lo=p["lag_lo"],
                   lag_hi=p["lag_hi"], bits=p["bits"]) for p in pairs]
-    path = {"auto": tde.TDE_PATH_AUTO, "mfma": tde.TDE_PATH_MFMA, "popc": tde.TDE_PATH_POPC,
-            "ntt": tde.TDE_PATH_NTT}[args.path]
+    path = {"auto": tde.TDE_PATH_AUTO, "mfma": tde.TDE_PATH_MFMA, "mfma_i8": tde.TDE_PATH_MFMA_I8,
+            "popc": tde.TDE_PATH_POPC, "ntt": tde.TDE_PATH_NTT}[args.path]
     if args.tune:
         log("[bench] autotuning engines")
         tde.tde_tune(ctx.handle, 20)
@@ -403,12 +404,29 @@ def main():
     log(f"[bench] {ms_step:.3f} ms/step, engine {engine_ms:.3f} ms, stages {stage_ms} {stage_n}")
 
     n_ntt = sum(1 for e in engines if e == tde.TDE_PATH_NTT)
+    # operand format of every matrix-core pair (codes up to 3: FP4, up to 7:
+    # FP6, else int8) and the peak of the mix: MACs over the time each format
+    # would take at its own dense peak
+    fmt_bits = [tde.tde_mfma_operand_bits(tde.kmax_of_bits(p["bits"]), tde.kmax_of_bits(p["bits"]),
+                                          path if path in (tde.TDE_PATH_MFMA, tde.TDE_PATH_MFMA_I8)
+                                          else tde.TDE_PATH_MFMA) if e == tde.TDE_PATH_MFMA else 0
+                for p, e in zip(pairs, engines)]
+    pair_macs = [alg_macs(p["x"].size, p["y"].size, p["lag_lo"], p["lag_hi"]) for p in pairs]
+    fmt_names = {4: "fp4", 6: "fp6", 8: "i8"}
+    fmt_macs = {fmt_names[f]: sum(m for m, g in zip(pair_macs, fmt_bits) if g == f) for f in (4, 6, 8)}
+    dtype = "+".join(k for k in ("fp4", "fp6", "i8") if fmt_macs[k]) or "i8"
     if n_ntt * 2 < len(engines):
         achieved = 2.0 * macs / (engine_ms * 1e-3) / 1e12
+        t_at_peak = sum(m / (INT8_PEAK_TOPS if k == "i8" else FP6_FP4_PEAK_TFLOPS) for k, m in fmt_macs.items())
+        peak = sum(fmt_macs.values()) / t_at_peak if t_at_peak > 0 else INT8_PEAK_TOPS
         src = os.path.join(ROOT, "paper_2509_19974_amd", "csrc", "k_xcorr_mfma.hip")
-        roof = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / INT8_PEAK_TOPS, "traffic": traffic_from_profile(src),
-                "kernel": "k_xcorr_mfma (int8 MFMA 32x32x32, int32 accumulation)",
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TOP/s",
+                "frac": achieved / peak, "traffic": traffic_from_profile(src),
+                "kernel": "k_xcorr_mfma (32x32 matrix tiles: FP4/FP6 operands with fp32 accumulation for codes "
+                          "up to 7, int8 with int32 accumulation beyond)",
+                "peak_mix": {k: {"mac_share": m / max(sum(fmt_macs.values()), 1),
+                                 "peak": INT8_PEAK_TOPS if k == "i8" else FP6_FP4_PEAK_TFLOPS}
+                             for k, m in fmt_macs.items() if m},
                 "kernel_ms": engine_ms, "alg_macs_per_launch": macs}
     else:
         # transform engine: modular butterflies (one Montgomery product each)
@@ -441,7 +459,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "i8",
+        "dtype": dtype if n_ntt * 2 < len(engines) else "u32",
         "data": "synthetic",
         "config": desc,
         "int_mac_per_s": macs * 1e3 / ms_step,

@@ -148,6 +148,10 @@ int tde_quantize(tde_ctx* ctx, const float* x, int64_t n, int bits, float inv_st
  *  r_dtype = TDE_I32 requires max_tau overlap(tau) * kmax_u * kmax_v < 2^31
  *  (the coefficient bound of Section 3.2), else TDE_ERR_RANGE; TDE_I64 is
  *  always exact.
+ *  path = TDE_PATH_MFMA multiplies codes up to 3 as FP4 (E2M1) and up to 7
+ *  as FP6 (E2M3) with fp32 accumulation (integers, exact: every wave's
+ *  partial sum stays below 2^24), larger ones as int8 with int32
+ *  accumulation; TDE_PATH_MFMA_I8 takes int8 for every code range.
  *  path = TDE_PATH_POPC needs kmax_u = kmax_v = 1. TDE_PATH_NTT takes
  *  transforms up to 2^23 points (TDE_ERR_UNSUPPORTED beyond): the smallest
  *  power of two n with no alias on the requested lags inside the support,
@@ -158,6 +162,11 @@ int tde_quantize(tde_ctx* ctx, const float* x, int64_t n, int bits, float inv_st
  * of range), TDE_ERR_RANGE, TDE_ERR_WS. */
 size_t tde_xcorr_workspace_size(int64_t nu, int64_t nv, int kmax_u, int kmax_v,
                                 int64_t lag_lo, int64_t lag_hi, int path);
+/* Operand width (4, 6 or 8 bits) the matrix-core engine multiplies codes of
+ * these ranges in, for path TDE_PATH_AUTO, _MFMA or _MFMA_I8 (the choice
+ * above; the environment variable TDE_MFMA_FP=0 keeps int8 everywhere).
+ * Errors: TDE_ERR_ARG (kmax out of [1, 127], another path). */
+int tde_mfma_operand_bits(int kmax_u, int kmax_v, int path);
 int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, int64_t nv,
                   int kmax_u, int kmax_v, int64_t lag_lo, int64_t lag_hi,
                   void* r, int r_dtype, int path, void* ws, size_t ws_bytes, void* stream);

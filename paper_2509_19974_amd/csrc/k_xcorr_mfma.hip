@@ -843,14 +843,14 @@ static int64_t seg_cap(const XItem& it) {
 
 // FP4 for codes up to 3, FP6 up to 7 (both exact); TDE_MFMA_FP=0 in the
 // environment keeps int8 everywhere.
-static int choose_fmt(const XPair& p, bool allow_fp) {
+int mfma_choose_fmt(int kmax, bool allow_fp) {
     static const bool fp_on = [] {
         const char* e = getenv("TDE_MFMA_FP");
         return !(e && atoi(e) == 0);
     }();
-    if (!allow_fp || !fp_on || p.kmax < 1) return kFmtI8;
-    if (p.kmax <= 3) return kFmtF4;
-    if (p.kmax <= 7) return kFmtF6;
+    if (!allow_fp || !fp_on || kmax < 1) return kFmtI8;
+    if (kmax <= 3) return kFmtF4;
+    if (kmax <= 7) return kFmtF6;
     return kFmtI8;
 }
 
@@ -869,7 +869,7 @@ int choose_mb(const XPair& p) {
 }
 
 void mfma_plan_pair(XItem& it, bool allow_fp) {
-    it.fmt = choose_fmt(it.p, allow_fp);
+    it.fmt = mfma_choose_fmt(it.p.kmax, allow_fp);
     it.mb = it.fmt == kFmtI8 ? choose_mb(it.p) : 4;
     const int64_t TLW = it.mb == 8 ? MCfg<8>::TLW : MCfg<4>::TLW;
     int64_t lo, hi;

@@ -324,6 +324,15 @@ static int check_xcorr(const int8_t* u, int64_t nu, const int8_t* v, int64_t nv,
     return TDE_OK;
 }
 
+int tde_mfma_operand_bits(int kmax_u, int kmax_v, int path) {
+    if (kmax_u < 1 || kmax_u > 127 || kmax_v < 1 || kmax_v > 127)
+        return set_error(TDE_ERR_ARG, "tde_mfma_operand_bits: kmax must be in [1, 127]");
+    if (path != TDE_PATH_AUTO && path != TDE_PATH_MFMA && path != TDE_PATH_MFMA_I8)
+        return set_error(TDE_ERR_ARG, "tde_mfma_operand_bits: not a matrix-core path");
+    const int f = mfma_choose_fmt(kmax_u > kmax_v ? kmax_u : kmax_v, path != TDE_PATH_MFMA_I8);
+    return f == kFmtF4 ? 4 : (f == kFmtF6 ? 6 : 8);
+}
+
 size_t tde_xcorr_workspace_size(int64_t nu, int64_t nv, int kmax_u, int kmax_v, int64_t lag_lo, int64_t lag_hi,
                                 int path) {
     if (nu < 1 || nv < 1 || lag_lo > lag_hi || kmax_u < 1 || kmax_v < 1) return 0;

@@ -183,6 +183,7 @@ constexpr int kFmtF4 = 4;
 // sets fmt, mb, T_start, ntiles, wide, segmented, outside triple; allow_fp =
 // false keeps int8 operands whatever the code range
 void mfma_plan_pair(XItem& it, bool allow_fp = true);
+int mfma_choose_fmt(int kmax, bool allow_fp);   // kFmt* for codes up to kmax
 int64_t mfma_total_q(const XItem& it);          // summed m range of its tiles
 int64_t mfma_count_items(const XItem& it);
 void mfma_items(const XItem& it, int pair, std::vector<MWork>& out);

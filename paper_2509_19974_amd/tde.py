@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH):
         "tde_quantize_workspace_size": (sz, [i64]),
         "tde_quantize": (i32, [vp, vp, i64, i32, f32, vp, vp, vp, sz, vp]),
         "tde_xcorr_workspace_size": (sz, [i64, i64, i32, i32, i64, i64, i32]),
+        "tde_mfma_operand_bits": (i32, [i32, i32, i32]),
         "tde_xcorr_int": (i32, [vp, vp, i64, vp, i64, i32, i32, i64, i64, vp, i32, i32, vp, sz, vp]),
         "tde_argmax_workspace_size": (sz, [i64]),
         "tde_argmax_lag": (i32, [vp, vp, i32, i64, i64, vp, vp, sz, vp]),
@@ -177,6 +178,13 @@ def tde_quantize(ctx, x, n, bits, inv_step, q, stat=None, ws=None, ws_bytes=0, s
 
 def tde_xcorr_workspace_size(nu, nv, kmax_u, kmax_v, lag_lo, lag_hi, path=TDE_PATH_AUTO) -> int:
     return int(load_library().tde_xcorr_workspace_size(nu, nv, kmax_u, kmax_v, lag_lo, lag_hi, path))
+
+
+def tde_mfma_operand_bits(kmax_u, kmax_v, path=TDE_PATH_MFMA) -> int:
+    st = int(load_library().tde_mfma_operand_bits(kmax_u, kmax_v, path))
+    if st < 0:
+        _check(st)
+    return st
 
 
 def tde_xcorr_int(ctx, u, nu, v, nv, kmax_u, kmax_v, lag_lo, lag_hi, r, r_dtype, path=TDE_PATH_AUTO, ws=None,

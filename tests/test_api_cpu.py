@@ -129,6 +129,17 @@ def test_xcorr_argument_validation():
         == tde.TDE_ERR_ARG and "null context" in tde.tde_last_error()
 
 
+def test_mfma_operand_formats():
+    # exact FP4 (E2M1) for codes up to 3, FP6 (E2M3) up to 7, int8 beyond
+    assert [tde.tde_mfma_operand_bits(k, k) for k in (1, 2, 3, 4, 7, 8, 127)] == [4, 4, 4, 6, 6, 8, 8]
+    assert tde.tde_mfma_operand_bits(1, 7) == 6 and tde.tde_mfma_operand_bits(7, 8) == 8
+    assert tde.tde_mfma_operand_bits(1, 1, tde.TDE_PATH_AUTO) == 4
+    assert tde.tde_mfma_operand_bits(1, 1, tde.TDE_PATH_MFMA_I8) == 8
+    for bad in ((0, 1, tde.TDE_PATH_MFMA), (1, 128, tde.TDE_PATH_MFMA), (1, 1, tde.TDE_PATH_NTT)):
+        with pytest.raises(tde.TDEError):
+            tde.tde_mfma_operand_bits(*bad)
+
+
 def test_quantize_argument_validation():
     lib = tde.load_library()
     q = lambda **k: lib.tde_quantize(None, k.get("x", FAKE), k.get("n", 10), k.get("bits", 4),
