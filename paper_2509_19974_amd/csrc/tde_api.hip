@@ -157,10 +157,10 @@ void drop_graphs_on(tde_ctx* c, const void* ws, size_t bytes) {
 
 // Engine choice for one correlation: the caller's, or the tuning table's
 // (every engine is exact; they differ in speed).
-int choose_path(int path, int64_t nu, int64_t nv, int kuv, int64_t lo, int64_t hi) {
+int choose_path(int path, int64_t nu, int64_t nv, int kuv, int kmax, int64_t lo, int64_t hi) {
     if (path == TDE_PATH_MFMA_I8) return TDE_PATH_MFMA;
     if (path != TDE_PATH_AUTO) return path;
-    return auto_engine(nu, nv, kuv, lo, hi);
+    return auto_engine(nu, nv, kuv, kmax, lo, hi);
 }
 
 }  // namespace
@@ -343,7 +343,7 @@ size_t tde_xcorr_workspace_size(int64_t nu, int64_t nv, int kmax_u, int kmax_v, 
     it.p.lag_hi = lag_hi;
     it.p.kuv = kmax_u * kmax_v;
     it.p.kmax = kmax_u > kmax_v ? kmax_u : kmax_v;
-    int eng = choose_path(path, nu, nv, it.p.kuv, lag_lo, lag_hi);
+    int eng = choose_path(path, nu, nv, it.p.kuv, it.p.kmax, lag_lo, lag_hi);
     if (eng == TDE_PATH_POPC) return popc_ws_bytes(it.p);
     if (eng == TDE_PATH_NTT) {
         NttPlan P;
@@ -372,7 +372,7 @@ int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, in
     it.p.r_dtype = r_dtype;
     it.p.kuv = kmax_u * kmax_v;
     it.p.kmax = kmax_u > kmax_v ? kmax_u : kmax_v;
-    const int eng = choose_path(path, nu, nv, it.p.kuv, lag_lo, lag_hi);
+    const int eng = choose_path(path, nu, nv, it.p.kuv, it.p.kmax, lag_lo, lag_hi);
     it.engine = eng;
     const int wpath = path == TDE_PATH_MFMA_I8 ? path : eng;
     size_t need = tde_xcorr_workspace_size(nu, nv, kmax_u, kmax_v, lag_lo, lag_hi, wpath);
@@ -611,7 +611,7 @@ void outside_triple(int64_t lo, int64_t hi, int64_t c_lo, int64_t c_hi, XItem& i
 PairPlan plan_pair(const tde_pair& q, int path, bool learned) {
     PairPlan pp{};
     const int K = kmax_of_bits(q.bits);
-    pp.eng = learned ? TDE_PATH_MFMA : choose_path(path, q.nx, q.ny, K * K, q.lag_lo, q.lag_hi);
+    pp.eng = learned ? TDE_PATH_MFMA : choose_path(path, q.nx, q.ny, K * K, K, q.lag_lo, q.lag_hi);
     pp.rdt = q.r_out ? q.r_dtype
                      : ((__int128)max_overlap(q.nx, q.ny, q.lag_lo, q.lag_hi) * K * K < ((__int128)1 << 31) ? TDE_I32
                                                                                                           : TDE_I64);

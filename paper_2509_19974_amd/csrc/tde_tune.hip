@@ -63,12 +63,13 @@ double overlap_sum(int64_t nu, int64_t nv, int64_t lo, int64_t hi) {
 }
 
 // Default when no table is installed: seconds from rates measured on MI355X
-// (int8 matrix-core engine ~1.17e15 MAC/s on the 64 x 65536 batch; bit-plane
-// engine ~1.5e14 MAC/s; transform engine ~4e-11 s per residue and prime of
-// the transform length).
-int model_choice(int64_t nu, int64_t nv, int kuv, int64_t lo, int64_t hi) {
+// (matrix-core engine ~1.17e15 MAC/s with int8 operands and ~1.9e15 with
+// FP4/FP6 operands on 64 x 65536 batches; bit-plane engine ~1.5e14 MAC/s;
+// transform engine ~4e-11 s per residue and prime of the transform length).
+int model_choice(int64_t nu, int64_t nv, int kuv, int kmax, int64_t lo, int64_t hi) {
     const double macs = overlap_sum(nu, nv, lo, hi);
-    double best = macs / 1.17e15 + 4e-6;
+    const double rate = mfma_choose_fmt(kmax, true) == kFmtI8 ? 1.17e15 : 1.9e15;
+    double best = macs / rate + 4e-6;
     int eng = TDE_PATH_MFMA;
     NttPlan P;
     if (ntt_plan(nu, nv, kuv, lo, hi, P)) {
@@ -98,7 +99,7 @@ uint32_t lcg(uint64_t& s) {
 
 }  // namespace
 
-int auto_engine(int64_t nu, int64_t nv, int kuv, int64_t lag_lo, int64_t lag_hi) {
+int auto_engine(int64_t nu, int64_t nv, int kuv, int kmax, int64_t lag_lo, int64_t lag_hi) {
     {
         std::lock_guard<std::mutex> lock(g_mu);
         if (g_tab.valid) {
@@ -106,7 +107,7 @@ int auto_engine(int64_t nu, int64_t nv, int kuv, int64_t lag_lo, int64_t lag_hi)
             if (e && applicable(e, nu, nv, kuv, lag_lo, lag_hi)) return e;
         }
     }
-    return model_choice(nu, nv, kuv, lag_lo, lag_hi);
+    return model_choice(nu, nv, kuv, kmax, lag_lo, lag_hi);
 }
 
 }  // namespace tde
@@ -118,7 +119,7 @@ extern "C" {
 int tde_tune_query(int64_t nu, int64_t nv, int kmax_u, int kmax_v, int64_t lag_lo, int64_t lag_hi) {
     if (nu < 1 || nv < 1 || lag_lo > lag_hi || kmax_u < 1 || kmax_u > 127 || kmax_v < 1 || kmax_v > 127)
         return set_error(TDE_ERR_ARG, "tde_tune_query: invalid request");
-    return auto_engine(nu, nv, kmax_u * kmax_v, lag_lo, lag_hi);
+    return auto_engine(nu, nv, kmax_u * kmax_v, kmax_u > kmax_v ? kmax_u : kmax_v, lag_lo, lag_hi);
 }
 
 int tde_tune_reset(void) {
