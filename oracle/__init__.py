@@ -19,6 +19,10 @@ What it computes is the plain definition of each step, written out:
   number of maximisers (Remark 1).
 * ``xcorr_f64_at`` -- Eq. (1) on the unquantized signals in float64.
 * ``estimate`` / ``estimate_refined`` -- Algorithm 1 lines 1-4, and 1-6.
+* ``stream`` -- correlation of a stream against a template, block by block
+  (the streaming extension named as future work in Section 5): the plain
+  correlation of Eq. (1) over the concatenated stream, cut into the lags each
+  push makes final, with per-block and running argmaxes.
 * ``xcorr_long_certified`` -- for signals too long for the direct sum over all
   lags: a float64 FFT correlation of the integer sequences, rounded to the
   nearest integer, accepted only under an a-priori rounding-error bound below
@@ -249,6 +253,49 @@ def estimate_refined(x, y, bits: int, lag_lo: int, lag_hi: int,
         tied = tied[rf == best]
     res["lag_set"] = [int(t) for t in tied]
     return res
+
+
+# ------------------------------------------------------------ streaming ---
+
+def stream(x, blocks, bits: int, inv_step_y: float, inv_step_x: float | None = None):
+    """Correlation of a stream against a template x (nx samples), the stream
+    arriving as the float blocks in ``blocks`` (the streaming extension the
+    paper names as future work, Section 5).
+
+    The template is quantized once (its own scale, or inv_step_x); the stream
+    with one fixed scale inv_step_y for every block, so the quantized stream
+    is the quantization of the concatenation (Algorithm 1, line 2, one
+    monotone map). Lags follow Eq. (1) with u = template codes and v = stream
+    codes: r[tau] = sum_m u[m] v[m + tau], v zero outside the stream. After a
+    push that brings the stream to T samples, the lags tau <= T - nx are
+    final (they read v only on [tau, tau + nx), inside [0, T)); a push of B
+    samples makes B new lags final, and the finishing step the last nx - 1
+    lags [T - nx + 1, T - 1] (zero beyond the end). Returns one record per
+    push and one for the finish: the lags, their r, the argmax of those lags
+    and the running argmax over every final lag so far (Algorithm 1, line 4,
+    smallest lag on ties)."""
+    x = _f32(x)
+    nx = x.size
+    ys = [_f32(b) for b in blocks]
+    if not ys or min(b.size for b in ys) < 1:
+        raise ValueError("every block needs at least one sample")
+    u, _, sx = quantize(x, bits, inv_step_x)
+    v, _, _ = quantize(np.concatenate(ys), bits, inv_step_y)
+    T = v.size
+    lo_all = -(nx - 1)
+    r_all = xcorr(u, v, lo_all, T - 1)            # every lag of the finished stream
+    spans, t = [], 0
+    for b in ys:
+        spans.append((t - nx + 1, t + b.size - nx))
+        t += b.size
+    spans.append((T - nx + 1, T - 1))
+    records = []
+    for a, b in spans:
+        rec = {"lag_lo": a, "lag_hi": b, "r": r_all[a - lo_all:b - lo_all + 1]}
+        rec["block"] = argmax(rec["r"], a) if b >= a else None
+        rec["running"] = argmax(r_all[:b - lo_all + 1], lo_all)
+        records.append(rec)
+    return {"u": u, "v": v, "inv_step_x": sx, "records": records, "r_all": r_all}
 
 
 # ------------------------------------------------- long-signal route ------

@@ -506,3 +506,78 @@ def test_pairwise_float_correlation_pins():
     xs = np.array([2.0 ** 26, 1.0, 1.0, -(2.0 ** 26)], np.float32)
     ys = np.array([2.0 ** 27, 1.0, 1.0, 2.0 ** 27], np.float32)
     assert oracle.xcorr_f64_at_pairwise(xs, ys, [0])[0] == 1.0
+
+
+# ---------------------------------------------------------- streaming -------
+# oracle.stream cuts the correlation of the whole stream into the lags each
+# push makes final. Pinned against an overlap-save computation written out
+# in plain Python loops (history of nx - 1 codes, zeros before the stream and
+# after its end), with its own running argmax.
+
+def _overlap_save_loops(u, blocks_codes):
+    nx = len(u)
+    hist = [0] * (nx - 1)
+    t, recs = 0, []
+    best = None          # (value, lag, count)
+    for codes in list(blocks_codes) + [None]:
+        new = [0] * (nx - 1) if codes is None else [int(c) for c in codes]
+        buf = hist + new
+        base = t - (nx - 1)
+        r = []
+        for tp in range(len(new)):
+            r.append(sum(int(u[m]) * buf[m + tp] for m in range(nx)))
+        blk = None
+        for i, val in enumerate(r):
+            lag = base + i
+            if blk is None or val > blk[0]:
+                blk = [val, lag, 1]
+            elif val == blk[0]:
+                blk[2] += 1
+            if best is None or val > best[0]:
+                best = [val, lag, 1]
+            elif val == best[0]:
+                best[2] += 1
+        recs.append((base, base + len(new) - 1, r, None if blk is None else (blk[1], blk[0], blk[2]),
+                     (best[1], best[0], best[2])))
+        hist = buf[len(buf) - (nx - 1):] if nx > 1 else []
+        if codes is not None:
+            t += len(codes)
+    return recs
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_stream_equals_overlap_save_loops(seed):
+    rng = np.random.default_rng(seed)
+    nx = int(rng.integers(1, 12))
+    bits = [1, 2, 4, 8][seed % 4]
+    x = rng.standard_normal(nx).astype(np.float32)
+    sizes = [int(s) for s in rng.integers(1, 15, int(rng.integers(1, 6)))]
+    blocks = [rng.standard_normal(n).astype(np.float32) for n in sizes]
+    o = oracle.stream(x, blocks, bits, inv_step_y=1.7)
+    v = o["v"]
+    cuts = np.cumsum([0] + sizes)
+    ref = _overlap_save_loops(o["u"], [v[cuts[i]:cuts[i + 1]] for i in range(len(sizes))])
+    assert len(ref) == len(o["records"]) == len(sizes) + 1
+    for rec, (a, b, r, blk, run) in zip(o["records"], ref):
+        assert (rec["lag_lo"], rec["lag_hi"]) == (a, b)
+        assert rec["r"].tolist() == r
+        assert rec["block"] == blk
+        assert rec["running"] == run
+    # the quantized stream is the quantization of the concatenation (one map)
+    q, _, _ = oracle.quantize(np.concatenate(blocks), bits, 1.7)
+    assert np.array_equal(q, v)
+
+
+def test_stream_running_argmax_ties_across_blocks():
+    """A one-sample template makes r the stream codes themselves: equal maxima
+    in the first and third blocks give one running maximiser set of size 2
+    that starts at the earlier lag."""
+    x = np.array([1.0], np.float32)
+    blocks = [np.array([0.5, 3.0, -1.0], np.float32), np.array([1.0], np.float32),
+              np.array([-2.0, 3.0, 0.0, 3.0], np.float32)]
+    o = oracle.stream(x, blocks, 8, inv_step_y=10.0)
+    recs = o["records"]
+    assert recs[0]["running"][0] == 1 and recs[0]["running"][2] == 1
+    assert recs[2]["block"] == (5, recs[0]["running"][1], 2)
+    assert recs[2]["running"] == (1, recs[0]["running"][1], 3)
+    assert recs[3]["r"].size == 0 and recs[3]["block"] is None
