@@ -195,6 +195,53 @@ int tde_refine_ties(tde_ctx* ctx, const float* x, int64_t nx, const float* y, in
                     int r_dtype, int64_t lag_lo, int64_t lag_hi, tde_peak* peak, int max_ties, void* ws,
                     size_t ws_bytes, void* stream);
 
+/* --------------------------------------------------------- streaming -- */
+
+/* Correlation of a stream against a template, block by block (overlap-save):
+ * the extension to long and streaming signals that Section 5 names as future
+ * work, built from Algorithm 1 lines 2-4. The template x (device float32, nx
+ * samples) is quantized once with bits in {1,2,4,8} at inv_step_x (0: its own
+ * scale, Algorithm 1 line 2 as in tde_quantize); every stream block is
+ * quantized at the one fixed scale inv_step_y (> 0; ignored for bits = 1), so
+ * the stream's codes are those of the concatenation. With u the template's
+ * codes and v the stream's, zero outside [0, T) for T samples pushed,
+ *   r[tau] = sum_m u[m] v[m + tau]          (Eq. (1))
+ * is final for tau <= T - nx. A push of n samples makes the n lags
+ * [T - nx + 1, T + n - nx] final (T before the push); tde_stream_finish makes
+ * the last nx - 1 lags [T - nx + 1, T - 1] final, with zeros after the end,
+ * and ends the stream. Each call computes its lags exactly on the engine
+ * `path` selects (as tde_xcorr_int: the template against the last nx - 1 + n
+ * codes of the stream) and
+ *   r_out (device, may be NULL): its lags' r, r_dtype (TDE_I32 requires
+ *     nx * K^2 < 2^31, K the bits' largest code);
+ *   block_peak (device, may be NULL): the argmax of its lags (smallest lag,
+ *     max, count; flags 0);
+ *   running_peak (device, may be NULL): the argmax over every final lag so
+ *     far (ties across calls add up; the smallest lag wins).
+ * Work is queued on `stream`; a stream object is used by one host thread at
+ * a time and its calls must follow each other on one HIP stream.
+ * tde_stream_create allocates device memory (template codes, two history
+ * buffers of nx - 1 + max(max_block, nx - 1) codes, r and engine workspace)
+ * and returns TDE_ERR_ARG for null pointers, nx < 1, bad bits, a non-finite
+ * or negative scale, inv_step_y = 0 with bits > 1, max_block < 1, a path
+ * that is not AUTO/MFMA/MFMA_I8/POPC/NTT or does not fit the codes (POPC
+ * needs bits = 1), TDE_ERR_UNSUPPORTED when the NTT engine cannot take the
+ * largest call. tde_stream_push returns TDE_ERR_ARG for n < 1,
+ * n > max_block, a null y, a bad r_dtype or a finished stream, TDE_ERR_RANGE
+ * for TDE_I32 beyond the bound. The finishing call of a template of one
+ * sample has no lags: it writes no r and leaves block_peak unchanged. */
+typedef struct tde_stream tde_stream;
+int tde_stream_create(tde_ctx* ctx, const float* x, int64_t nx, int bits, float inv_step_x, float inv_step_y,
+                      int64_t max_block, int path, tde_stream** out, void* stream);
+int tde_stream_push(tde_stream* st, const float* y, int64_t n, void* r_out, int r_dtype, tde_peak* block_peak,
+                    tde_peak* running_peak, void* stream);
+int tde_stream_finish(tde_stream* st, void* r_out, int r_dtype, tde_peak* block_peak, tde_peak* running_peak,
+                      void* stream);
+/* samples pushed so far (-1 for a null stream) */
+int64_t tde_stream_position(const tde_stream* st);
+/* waits for the device, then frees the stream (NULL is ignored) */
+void tde_stream_destroy(tde_stream* st);
+
 /* ------------------------------------------------------------ batch -- */
 
 /* One pair of the batch. x, y: device float32 signals of nx, ny samples.

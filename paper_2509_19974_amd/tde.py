@@ -107,6 +107,11 @@ def load_library(path: str = LIB_PATH):
         "tde_model_forward": (i32, [vp, vp, vp, i64, vp, i32, vp, vp, vp]),
         "tde_train_step": (i32, [vp, vp, vp, vp, i64, f32, ctypes.POINTER(f32), vp]),
         "tde_refine_workspace_size": (sz, [i32]),
+        "tde_stream_create": (i32, [vp, vp, i64, i32, f32, f32, i64, i32, ctypes.POINTER(vp), vp]),
+        "tde_stream_push": (i32, [vp, vp, i64, vp, i32, vp, vp, vp]),
+        "tde_stream_finish": (i32, [vp, vp, i32, vp, vp, vp]),
+        "tde_stream_position": (i64, [vp]),
+        "tde_stream_destroy": (None, [vp]),
         "tde_refine_ties": (i32, [vp, vp, i64, vp, i64, vp, i32, i64, i64, vp, i32, vp, sz, vp]),
         "tde_tune": (i32, [vp, i32, vp]),
         "tde_tune_query": (i32, [i64, i64, i32, i32, i64, i64]),
@@ -216,6 +221,57 @@ def tde_estimate_workspace_size(pairs_arr, npairs, opts: tde_opts) -> int:
 def tde_estimate_batch(ctx, pairs_arr, npairs, opts: tde_opts, out, ws, ws_bytes, stream=None):
     _check(load_library().tde_estimate_batch(ctx, pairs_arr, npairs, ctypes.byref(opts), _ptr(out), _ptr(ws),
                                              ws_bytes, _stream(stream)))
+
+
+class Stream:
+    """Correlation of a stream against a template, block by block
+    (tde_stream): push float32 device blocks, then finish."""
+
+    def __init__(self, ctx: "Context", x, bits: int, inv_step_y: float, max_block: int, inv_step_x: float = 0.0,
+                 path: int = TDE_PATH_AUTO, stream=None):
+        self.ctx = ctx
+        self.nx = x.numel()
+        h = ctypes.c_void_p()
+        _check(load_library().tde_stream_create(ctx.handle, _ptr(x), x.numel(), bits, float(inv_step_x),
+                                                float(inv_step_y), max_block, path, ctypes.byref(h),
+                                                _stream(stream)))
+        self.handle = h.value
+
+    def close(self):
+        if self.handle:
+            load_library().tde_stream_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def position(self) -> int:
+        return int(load_library().tde_stream_position(self.handle))
+
+    def push(self, y, want_r=False, r_dtype=TDE_I64, stream=None):
+        """Returns (r or None, block peak bytes, running peak bytes) on the device."""
+        torch = self.ctx.torch
+        r = (torch.empty(y.numel(), dtype=torch.int32 if r_dtype == TDE_I32 else torch.int64, device=self.ctx.device)
+             if want_r else None)
+        pk = self.ctx._bytes(2 * PEAK_DTYPE.itemsize)
+        _check(load_library().tde_stream_push(self.handle, _ptr(y), y.numel(), _ptr(r), r_dtype, _ptr(pk),
+                                              _ptr(pk) + PEAK_DTYPE.itemsize, _stream(stream)))
+        return r, pk[:PEAK_DTYPE.itemsize], pk[PEAK_DTYPE.itemsize:]
+
+    def finish(self, want_r=False, r_dtype=TDE_I64, stream=None):
+        torch = self.ctx.torch
+        n = self.nx - 1
+        r = (torch.empty(max(n, 1), dtype=torch.int32 if r_dtype == TDE_I32 else torch.int64, device=self.ctx.device)
+             if want_r else None)
+        pk = self.ctx._bytes(2 * PEAK_DTYPE.itemsize)
+        pk.zero_()
+        _check(load_library().tde_stream_finish(self.handle, _ptr(r), r_dtype, _ptr(pk),
+                                                _ptr(pk) + PEAK_DTYPE.itemsize, _stream(stream)))
+        return (r[:n] if r is not None else None), pk[:PEAK_DTYPE.itemsize], pk[PEAK_DTYPE.itemsize:]
 
 
 class Model:

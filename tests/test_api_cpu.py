@@ -140,6 +140,27 @@ def test_mfma_operand_formats():
             tde.tde_mfma_operand_bits(*bad)
 
 
+def test_stream_argument_validation():
+    lib = tde.load_library()
+    h = ctypes.c_void_p()
+
+    def create(**k):
+        return lib.tde_stream_create(None, k.get("x", FAKE), k.get("nx", 100), k.get("bits", 4),
+                                     k.get("sx", 0.0), k.get("sy", 2.5), k.get("mb", 64), k.get("path", 0),
+                                     ctypes.byref(h) if k.get("out", True) else None, None)
+    assert lib.tde_stream_create(None, FAKE, 100, 4, 0.0, 2.5, 64, 0, None, None) == tde.TDE_ERR_ARG
+    for bad in (dict(x=None), dict(nx=0), dict(bits=3), dict(sy=0.0), dict(sy=float("nan")), dict(sx=-1.0),
+                dict(mb=0), dict(path=tde.TDE_PATH_POPC), dict(path=9), dict(path=-1)):
+        assert create(**bad) == tde.TDE_ERR_ARG, bad
+    assert create(bits=1, sy=0.0, path=tde.TDE_PATH_POPC) == tde.TDE_ERR_ARG
+    assert "null context" in tde.tde_last_error()
+    assert create() == tde.TDE_ERR_ARG and "null context" in tde.tde_last_error()
+    assert lib.tde_stream_push(None, FAKE, 10, None, 0, None, None, None) == tde.TDE_ERR_ARG
+    assert lib.tde_stream_finish(None, None, 0, None, None, None) == tde.TDE_ERR_ARG
+    assert lib.tde_stream_position(None) == -1
+    lib.tde_stream_destroy(None)
+
+
 def test_quantize_argument_validation():
     lib = tde.load_library()
     q = lambda **k: lib.tde_quantize(None, k.get("x", FAKE), k.get("n", 10), k.get("bits", 4),

@@ -873,3 +873,67 @@ def test_refine_partial_and_exact_shift(T, ctx):
     yy[nu:] = (0.7 * s).astype(np.float32)
     before, after = _refine_case(T, ctx, xx, yy, 1, -500, 500)
     assert after["lag"] == nu and (before["n_ties"] == 1 or after["n_ties"] == 1)
+
+
+# ------------------------------------------------------------- streaming --
+
+STREAM_CASES = [
+    # nx, bits, block sizes, path
+    (3000, 4, [1, 4096, 333, 8000, 17], 0),
+    (1, 8, [5, 1, 300], 1),
+    (5000, 1, [2048, 2048, 7], 2),
+    (700, 8, [10000, 1, 2], 3),
+    (4097, 2, [4097, 1, 4096], 4),
+    (20000, 4, [3000, 3000], 0),
+]
+
+
+@pytest.mark.parametrize("case", STREAM_CASES)
+def test_stream_matches_oracle(T, ctx, case):
+    """Every push and the finishing call: the lags' r, the call's argmax and
+    the running argmax equal the oracle's cut of the whole stream's
+    correlation."""
+    from paper_2509_19974_amd import tde
+    nx, bits, sizes, path = case
+    say(f"stream nx={nx} bits={bits} sizes={sizes} path={path}")
+    rng = np.random.default_rng(nx + bits + len(sizes))
+    x = rng.standard_normal(nx).astype(np.float32)
+    blocks = [rng.standard_normal(n).astype(np.float32) for n in sizes]
+    sy = 2.5
+    o = oracle.stream(x, blocks, bits, inv_step_y=sy)
+    st = tde.Stream(ctx, dev(T, x), bits, sy, max(sizes), path=path)
+    for k, (b, rec) in enumerate(zip(blocks + [None], o["records"])):
+        if b is None:
+            r, pb, pr = st.finish(want_r=True)
+        else:
+            r, pb, pr = st.push(dev(T, b), want_r=True)
+        T.cuda.synchronize()
+        np.testing.assert_array_equal(r.cpu().numpy(), rec["r"])
+        if rec["block"] is not None:
+            p = tde.decode_peaks(pb)[0]
+            assert (p["lag"], p["rmax"], p["n_ties"]) == rec["block"], k
+        p = tde.decode_peaks(pr)[0]
+        assert (p["lag"], p["rmax"], p["n_ties"]) == rec["running"], k
+    assert st.position == sum(sizes)
+    st.close()
+
+
+def test_stream_finds_embedded_template(T, ctx):
+    """A template buried in a noisy stream at sample 12345, pushed in blocks
+    of 4096 with int32 r: the running peak lands on 12345."""
+    from paper_2509_19974_amd import tde
+    say("stream embedded template")
+    rng = np.random.default_rng(12345)
+    x = rng.standard_normal(2048).astype(np.float32)
+    y = (0.5 * rng.standard_normal(40000)).astype(np.float32)
+    y[12345:12345 + 2048] += x
+    st = tde.Stream(ctx, dev(T, x), 4, 2.5, 4096)
+    for a in range(0, y.size, 4096):
+        _, _, pr = st.push(dev(T, y[a:a + 4096]), want_r=True, r_dtype=tde.TDE_I32)
+    _, _, pr = st.finish()
+    T.cuda.synchronize()
+    p = tde.decode_peaks(pr)[0]
+    o = oracle.stream(x, [y[a:a + 4096] for a in range(0, y.size, 4096)], 4, inv_step_y=2.5)
+    assert p["lag"] == 12345
+    assert (p["lag"], p["rmax"], p["n_ties"]) == o["records"][-1]["running"]
+    st.close()
