@@ -13,6 +13,11 @@ What it computes is the plain definition of each step, written out:
   agree bit for bit).
 * ``quantize`` -- Algorithm 1, line 2: monotone integer maps with phi(0) = 0;
   sign with sign(0) = 0 (Section 4.2) for bits = 1.
+* ``quantize_nonuniform``, ``mulaw_thresholds``, ``lloyd_max_gauss`` --
+  non-uniform maps for b in {2, 4} (Section 3.2 allows any quantizer with
+  integer range; Section 5 names better quantizers as future work): the
+  cell boundaries of mu-law companding and of the Lloyd-Max quantizer of a
+  unit Gaussian, the code being the cell index.
 * ``xcorr`` / ``xcorr_at`` -- Algorithm 1, line 3: Eq. (1) on the integer
   sequences, int64 direct sums.
 * ``argmax`` -- Algorithm 1, line 4: maximum, smallest maximising lag and the
@@ -149,6 +154,95 @@ def quantize(x, bits: int, inv_step_value: float | None = None):
     q = np.empty(x.size, dtype=np.int8)
     nf = _load().oracle_quantize(_ptr(x), x.size, bits, s, _ptr(q))
     return q, int(nf), s
+
+
+# ------------------------------------------------ non-uniform quantizers ----
+# Quantizer kinds: 0 uniform (above), 1 mu-law (mu = 255), 2 Lloyd-Max for a
+# unit Gaussian. Every kind uses the uniform quantizer's scale
+# inv_step = fl32((2K+1)/(6 sigma)) and the scaled sample z = fl32(x inv_step)
+# (z = +-(K + 1/2) at +-3 sigma); the code is sign(z) times the number of cell
+# boundaries T_1 < ... < T_K (in units of z) strictly below |z|. NaN gives 0,
+# +-Inf gives +-K, inv_step = 0 gives 0. Monotone with phi(0) = 0 (Theorem 1).
+
+MU = 255.0
+
+
+def mulaw_thresholds(K: int, mu: float = MU) -> np.ndarray:
+    """Cell boundaries (units of sigma) of mu-law companding on [-3 sigma,
+    3 sigma]: the compressor c(a) = ln(1 + mu a / 3) / ln(1 + mu) maps a
+    magnitude a (in sigma) to [0, 1], cut uniformly into K + 1/2 cells, so the
+    k-th boundary solves c(a) = (k - 1/2) / (K + 1/2)."""
+    return np.array([3.0 * ((1.0 + mu) ** ((k - 0.5) / (K + 0.5)) - 1.0) / mu for k in range(1, K + 1)])
+
+
+def _phi(t: float) -> float:
+    return math.exp(-0.5 * t * t) / math.sqrt(2.0 * math.pi)
+
+
+def _Phi(t: float) -> float:
+    return 0.5 * math.erfc(-t / math.sqrt(2.0))
+
+
+def lloyd_max_gauss(K: int, tol: float = 1e-15, max_iter: int = 100000):
+    """Lloyd-Max quantizer of a unit Gaussian with 2K+1 levels (0 and +-y_k):
+    each boundary t_k is the midpoint of its two levels, each level the
+    centroid E[X | t_k <= X < t_(k+1)] = (phi(t_k) - phi(t_(k+1))) /
+    (Phi(t_(k+1)) - Phi(t_k)) with t_(K+1) = inf. Lloyd's iteration from the
+    uniform levels k 6/(2K+1), until no level moves by more than tol.
+    Returns (boundaries t_1..t_K, levels y_1..y_K), in units of sigma."""
+    y = [0.0] + [k * 6.0 / (2 * K + 1) for k in range(1, K + 1)]
+    for _ in range(max_iter):
+        t = [0.0] + [(y[k - 1] + y[k]) / 2.0 for k in range(1, K + 1)]
+        ny = [0.0]
+        for k in range(1, K + 1):
+            a = t[k]
+            if k < K:
+                b = t[k + 1]
+                ny.append((_phi(a) - _phi(b)) / (_Phi(b) - _Phi(a)))
+            else:
+                ny.append(_phi(a) / (1.0 - _Phi(a)))
+        moved = max(abs(p - q) for p, q in zip(y, ny))
+        y = ny
+        if moved <= tol:
+            break
+    t = [(y[k - 1] + y[k]) / 2.0 for k in range(1, K + 1)]
+    return np.array(t), np.array(y[1:])
+
+
+def nonuniform_table(kind: int, bits: int) -> np.ndarray:
+    """float32 cell boundaries T_k in units of z = x inv_step (sigma units
+    times (2K+1)/6) for kind 1 (mu-law) or 2 (Lloyd-Max Gaussian), bits 2 or 4."""
+    if bits not in (2, 4):
+        raise ValueError("non-uniform quantizers are defined for bits 2 and 4")
+    K = kmax(bits)
+    t = mulaw_thresholds(K) if kind == 1 else lloyd_max_gauss(K)[0]
+    return np.array([np.float32(v * (2 * K + 1) / 6.0) for v in t], dtype=np.float32)
+
+
+def quantize_nonuniform(x, bits: int, kind: int, inv_step_value: float | None = None):
+    """Algorithm 1, line 2 with a non-uniform monotone map (kind 1 or 2; bits
+    1 is sign for every kind). Returns (q int8, n_nonfinite, inv_step used)."""
+    x = _f32(x)
+    if bits == 1 or kind == 0:
+        return quantize(x, bits, inv_step_value)
+    T = nonuniform_table(kind, bits)
+    if inv_step_value is None or inv_step_value <= 0:
+        s = inv_step(x, bits)
+    else:
+        s = float(np.float32(inv_step_value))
+    nonfinite = int(np.count_nonzero(~np.isfinite(x)))
+    q = np.zeros(x.size, dtype=np.int8)
+    if s == 0.0:
+        return q, nonfinite, s
+    with np.errstate(invalid="ignore", over="ignore"):
+        z = x * np.float32(s)                       # float32 product, rounded to nearest even
+    ok = ~np.isnan(z)
+    a = np.abs(z[ok])
+    code = np.zeros(a.size, dtype=np.int64)
+    for t in T:
+        code += (a > t).astype(np.int64)
+    q[ok] = (np.sign(z[ok]).astype(np.int64) * code).astype(np.int8)
+    return q, nonfinite, s
 
 
 # ---------------------------------------------------------- correlation ----

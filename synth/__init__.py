@@ -172,6 +172,18 @@ def config5_reverb(npairs: int = 1024, n: int = 1 << 18, max_lag: int = 1 << 16,
     return out
 
 
+def stream_embedded(nx: int = 8192, block: int = 65536, nblocks: int = 64, noise: float = 0.7, salt: int = 0):
+    """Streaming workload: a white template of nx samples added once, at a
+    uniform position, to white noise of standard deviation `noise` that is
+    pushed in nblocks blocks of `block` samples. Returns (x, y, position)."""
+    rng = np.random.default_rng(np.random.SeedSequence(BASE_SEED + 6 + 1000 * salt))
+    x = rng.standard_normal(nx)
+    where = int(rng.integers(0, nblocks * block - nx))
+    y = noise * rng.standard_normal(nblocks * block)
+    y[where:where + nx] += x
+    return x.astype(np.float32), y.astype(np.float32), where
+
+
 def random_int_seq(rng, n: int, k: int, p_zero: float = 0.0) -> np.ndarray:
     """Uniform integers in [-k, k] with an optional extra share of zeros."""
     q = rng.integers(-k, k + 1, size=n)

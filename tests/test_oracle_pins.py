@@ -581,3 +581,72 @@ def test_stream_running_argmax_ties_across_blocks():
     assert recs[2]["block"] == (5, recs[0]["running"][1], 2)
     assert recs[2]["running"] == (1, recs[0]["running"][1], 3)
     assert recs[3]["r"].size == 0 and recs[3]["block"] is None
+
+
+# ------------------------------------------------ non-uniform quantizers ----
+
+def test_lloyd_max_gauss_matches_max_1960_tables():
+    """Lloyd-Max quantizers of a unit Gaussian as tabulated by J. Max,
+    'Quantizing for minimum distortion' (1960): 3 levels, boundary 0.6120 and
+    level 1.2240; 7 levels, boundaries 0.2803, 0.8744, 1.611 and levels 0.5606,
+    1.188, 2.033."""
+    t, y = oracle.lloyd_max_gauss(1)
+    assert abs(t[0] - 0.6120) < 5e-5 and abs(y[0] - 1.2240) < 5e-5
+    t, y = oracle.lloyd_max_gauss(3)
+    np.testing.assert_allclose(t, [0.2803, 0.8744, 1.611], atol=6e-4)
+    np.testing.assert_allclose(y, [0.5606, 1.188, 2.033], atol=6e-4)
+
+
+@pytest.mark.parametrize("K", [1, 3, 7])
+def test_lloyd_max_gauss_is_a_fixed_point(K):
+    """Boundaries are midpoints of neighbouring levels and levels are the
+    conditional means of their cells (Gaussian pdf/cdf from math.erf)."""
+    t, y = oracle.lloyd_max_gauss(K)
+    lv = np.concatenate([[0.0], y])
+    np.testing.assert_allclose(t, (lv[:-1] + lv[1:]) / 2, rtol=0, atol=1e-14)
+    pdf = lambda a: math.exp(-a * a / 2) / math.sqrt(2 * math.pi)
+    cdf = lambda a: 0.5 * (1 + math.erf(a / math.sqrt(2)))
+    for k in range(K):
+        a = t[k]
+        b = t[k + 1] if k + 1 < K else math.inf
+        num = pdf(a) - (pdf(b) if b != math.inf else 0.0)
+        den = (cdf(b) if b != math.inf else 1.0) - cdf(a)
+        assert abs(y[k] - num / den) < 1e-12
+    assert np.all(np.diff(t) > 0) and t[0] > 0
+
+
+@pytest.mark.parametrize("K", [1, 7])
+def test_mulaw_boundaries_closed_form_and_uniform_limit(K):
+    t = oracle.mulaw_thresholds(K)
+    comp = np.log1p(255.0 * t / 3.0) / np.log1p(255.0)
+    np.testing.assert_allclose(comp, (np.arange(1, K + 1) - 0.5) / (K + 0.5), atol=1e-14)
+    # mu -> 0: the compressor is the identity, the cells those of the uniform quantizer
+    tu = oracle.mulaw_thresholds(K, mu=1e-9) * (2 * K + 1) / 6.0
+    np.testing.assert_allclose(tu, np.arange(1, K + 1) - 0.5, atol=1e-6)
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("bits", [2, 4])
+def test_nonuniform_quantize_counts_boundaries(kind, bits):
+    """Codes equal the number of float32 boundaries strictly below |z|, signed,
+    with z the float32 product x * inv_step (checked sample by sample); the map
+    is odd, monotone and fixes 0; NaN -> 0, +-Inf -> +-K."""
+    rng = np.random.default_rng(kind * 10 + bits)
+    x = (rng.standard_normal(400) * 1.3).astype(np.float32)
+    x[:4] = [0.0, -0.0, np.nan, np.inf]
+    x[4] = -np.inf
+    q, nf, s = oracle.quantize_nonuniform(x, bits, kind)
+    T = oracle.nonuniform_table(kind, bits)
+    K = oracle.kmax(bits)
+    assert nf == 3 and q[0] == 0 and q[1] == 0 and q[2] == 0 and q[3] == K and q[4] == -K
+    for i in range(5, x.size):
+        z = np.float32(x[i]) * np.float32(s)
+        c = sum(1 for t in T if abs(float(z)) > float(t))
+        assert q[i] == (c if z > 0 else -c)
+    srt = np.sort(x[5:])
+    qs, _, _ = oracle.quantize_nonuniform(srt, bits, kind, s)
+    assert np.all(np.diff(qs.astype(int)) >= 0)
+    qn, _, _ = oracle.quantize_nonuniform(-x[5:], bits, kind, s)
+    np.testing.assert_array_equal(qn, -q[5:])
+    assert np.all(np.abs(q) <= K)
+    np.testing.assert_array_equal(oracle.quantize_nonuniform(x, bits, 0)[0], oracle.quantize(x, bits)[0])
