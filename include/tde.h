@@ -136,6 +136,31 @@ size_t tde_quantize_workspace_size(int64_t n);
 int tde_quantize(tde_ctx* ctx, const float* x, int64_t n, int bits, float inv_step,
                  int8_t* q, tde_qstat* stat, void* ws, size_t ws_bytes, void* stream);
 
+/* Quantizer kinds. Section 3.2 admits any monotone map with integer range
+ * (non-uniform ones included) and Section 5 names better quantizers as future
+ * work. Every kind keeps the uniform quantizer's scale inv_step (above) and
+ * z = fl32(x * inv_step), so |z| = K + 1/2 at 3 sigma; bits = 1 is the sign
+ * map for every kind. The non-uniform kinds, for bits 2 and 4, send x to
+ * sign(z) times the number of cell boundaries T_1 < ... < T_K strictly below
+ * |z| (NaN to 0, +-Inf to +-K), codes in [-K, K], phi(0) = 0:
+ *   TDE_QUANT_MULAW  mu-law companding, mu = 255, on [-3 sigma, 3 sigma]:
+ *                    T_k = 3 ((1+mu)^((k-1/2)/(K+1/2)) - 1) / mu  (sigma units)
+ *   TDE_QUANT_GAUSS  Lloyd-Max quantizer of a unit Gaussian with 2K+1 levels
+ *                    (boundaries midway between levels, levels the
+ *                    conditional means of their cells)
+ * with sigma units turned into z units by (2K+1)/6 and rounded to float32. */
+#define TDE_QUANT_UNIFORM 0
+#define TDE_QUANT_MULAW   1
+#define TDE_QUANT_GAUSS   2
+/* tde_quantize with a quantizer kind; TDE_ERR_UNSUPPORTED for a non-uniform
+ * kind with bits = 8, TDE_ERR_ARG for an unknown kind. */
+int tde_quantize_ex(tde_ctx* ctx, const float* x, int64_t n, int bits, int quantizer, float inv_step,
+                    int8_t* q, tde_qstat* stat, void* ws, size_t ws_bytes, void* stream);
+/* Writes the K boundaries T_k (z units, float32, ascending) of a non-uniform
+ * kind at bits 2 or 4 into out (host, room for 7) and returns K; TDE_ERR_ARG
+ * for another kind or a null out, TDE_ERR_UNSUPPORTED for other bits. */
+int tde_quantizer_thresholds(int quantizer, int bits, float* out);
+
 /* ------------------------------------------------------ correlation -- */
 
 /* Algorithm 1, line 3 (Eq. (1) on integer sequences), exact:
@@ -272,7 +297,8 @@ typedef struct {
     const tde_model* model;  /* learned mode: the proposer */
     float margin;            /* learned mode: full-range fallback below this logit margin
                                 (-inf: never, +inf: always; NaN is rejected) */
-    int32_t reserved;
+    int32_t quantizer;       /* TDE_QUANT_* for every pair (non-uniform kinds: bits 1, 2, 4
+                                only, else TDE_ERR_UNSUPPORTED) */
 } tde_opts;
 
 /* TDE_MODE_LEARNED: the model scores the nbins lag bins of every pair (see

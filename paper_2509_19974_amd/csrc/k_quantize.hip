@@ -12,9 +12,16 @@
 // Quantizer: bits = 1 is sign with sign(0) = 0 (Section 4.2), taken from the
 // IEEE bits; bits in {2,4,8} is clamp(round_half_even(fl32(x * inv_step)),
 // -K, K). Both are monotone non-decreasing with phi(0) = 0 (Theorem 1).
+// Non-uniform maps (any monotone integer-valued map qualifies, Section 3.2)
+// keep the scale and z = fl32(x * inv_step) and count the cell boundaries
+// strictly below |z|: mu-law companding (mu = 255) on [-3 sigma, 3 sigma], or
+// the Lloyd-Max quantizer of a unit Gaussian with 2K+1 levels, for b in {2, 4}.
 //
 // The three kernels are HBM-bound: 4 bytes of x are read once for the scale
 // and once for the codes, 1 byte of q is written.
+#include <algorithm>
+#include <cmath>
+
 #include "tde_internal.h"
 
 namespace tde {
@@ -173,7 +180,7 @@ __global__ void __launch_bounds__(256) k_scale_finalize(const QSig* sigs, int ns
     }
 }
 
-__device__ __forceinline__ int quant1(float xf, int bits, float inv, int K, int& nonfinite) {
+__device__ __forceinline__ int quant1(float xf, int bits, float inv, int K, int& nonfinite, const QSig& s) {
     uint32_t b = __float_as_uint(xf);
     uint32_t mag = b & 0x7fffffffu;
     bool is_nan = mag > 0x7f800000u;
@@ -183,6 +190,14 @@ __device__ __forceinline__ int quant1(float xf, int bits, float inv, int K, int&
         return (b >> 31) ? -1 : 1;
     }
     if (is_nan || inv == 0.f) return 0;
+    if (s.nthr > 0) {
+        const float z = __fmul_rn(xf, inv);
+        const float a = __builtin_fabsf(z);
+        int c = 0;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) c += (k < s.nthr && a > s.thr[k]) ? 1 : 0;
+        return z < 0.f ? -c : c;
+    }
     float t = __fmul_rn(xf, inv);
     float r = __builtin_rintf(t);
     r = r > (float)K ? (float)K : r;
@@ -244,7 +259,7 @@ __global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QS
         uint32_t w = 0u;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            int c = quant1(xs[e], s.bits, inv, K, nonfinite);
+            int c = quant1(xs[e], s.bits, inv, K, nonfinite, s);
             if (m + e < s.n) {
                 nzero += c == 0;
                 sq += c;
@@ -291,6 +306,49 @@ __global__ void k_quantize_flags(const QSig* sigs, int nsig, QSig one) {
     if (s.stat->n_nonfinite) f |= TDE_FLAG_NONFINITE_X;
     if (s.stat->n_zero == s.n) f |= TDE_FLAG_ZERO_X;
     s.stat->flags = f;
+}
+
+// Cell boundaries of the non-uniform maps, in units of sigma, then of z
+// (times (2K+1)/6, the uniform quantizer's scale), rounded to float32.
+//   mu-law: the compressor ln(1 + mu a/3) / ln(1 + mu) of a magnitude a (in
+//     sigma) cut into K + 1/2 equal cells: a_k = 3 ((1+mu)^((k-1/2)/(K+1/2)) - 1) / mu.
+//   Lloyd-Max, unit Gaussian, levels 0 and +-y_k: boundaries are midpoints of
+//     neighbouring levels, levels are conditional means of their cells,
+//     (phi(t_k) - phi(t_k+1)) / (Phi(t_k+1) - Phi(t_k)) with t_K+1 = inf;
+//     Lloyd's iteration from the uniform levels k 6/(2K+1) until no level
+//     moves by more than 1e-15.
+int quant_table(int kind, int bits, float* out) {
+    if (bits != 2 && bits != 4) return 0;
+    const int K = kmax_of_bits(bits);
+    double t[8];
+    if (kind == TDE_QUANT_MULAW) {
+        const double mu = 255.0;
+        for (int k = 1; k <= K; ++k) t[k - 1] = 3.0 * (std::pow(1.0 + mu, (k - 0.5) / (K + 0.5)) - 1.0) / mu;
+    } else if (kind == TDE_QUANT_GAUSS) {
+        auto pdf = [](double a) { return std::exp(-0.5 * a * a) / std::sqrt(2.0 * M_PI); };
+        auto cdf = [](double a) { return 0.5 * std::erfc(-a / std::sqrt(2.0)); };
+        double y[8];
+        y[0] = 0.0;
+        for (int k = 1; k <= K; ++k) y[k] = k * 6.0 / (2 * K + 1);
+        for (int it = 0; it < 100000; ++it) {
+            double b[8], ny[8];
+            for (int k = 1; k <= K; ++k) b[k] = (y[k - 1] + y[k]) / 2.0;
+            ny[0] = 0.0;
+            double moved = 0.0;
+            for (int k = 1; k <= K; ++k) {
+                ny[k] = k < K ? (pdf(b[k]) - pdf(b[k + 1])) / (cdf(b[k + 1]) - cdf(b[k]))
+                              : pdf(b[k]) / (1.0 - cdf(b[k]));
+                moved = std::max(moved, std::fabs(ny[k] - y[k]));
+            }
+            for (int k = 1; k <= K; ++k) y[k] = ny[k];
+            if (moved <= 1e-15) break;
+        }
+        for (int k = 1; k <= K; ++k) t[k - 1] = (y[k - 1] + y[k]) / 2.0;
+    } else {
+        return 0;
+    }
+    for (int k = 0; k < K; ++k) out[k] = (float)(t[k] * (2 * K + 1) / 6.0);
+    return K;
 }
 
 // Doubles of scratch for the sum tree of an n-sample signal (block sums and

@@ -263,10 +263,28 @@ size_t tde_quantize_workspace_size(int64_t n) {
 
 int tde_quantize(tde_ctx* ctx, const float* x, int64_t n, int bits, float inv_step, int8_t* q,
                  tde_qstat* stat, void* ws, size_t ws_bytes, void* stream) {
+    return tde_quantize_ex(ctx, x, n, bits, TDE_QUANT_UNIFORM, inv_step, q, stat, ws, ws_bytes, stream);
+}
+
+int tde_quantizer_thresholds(int quantizer, int bits, float* out) {
+    if (!out) return set_error(TDE_ERR_ARG, "tde_quantizer_thresholds: null out");
+    if (quantizer != TDE_QUANT_MULAW && quantizer != TDE_QUANT_GAUSS)
+        return set_error(TDE_ERR_ARG, "tde_quantizer_thresholds: not a non-uniform quantizer");
+    const int K = quant_table(quantizer, bits, out);
+    if (K == 0) return set_error(TDE_ERR_UNSUPPORTED, "tde_quantizer_thresholds: bits %d (2 or 4 only)", bits);
+    return K;
+}
+
+int tde_quantize_ex(tde_ctx* ctx, const float* x, int64_t n, int bits, int quantizer, float inv_step, int8_t* q,
+                    tde_qstat* stat, void* ws, size_t ws_bytes, void* stream) {
     if (!x || !q) return set_error(TDE_ERR_ARG, "tde_quantize: null x or q");
     if (n < 1) return set_error(TDE_ERR_ARG, "tde_quantize: n = %lld < 1", (long long)n);
     if (!valid_bits(bits)) return set_error(TDE_ERR_ARG, "tde_quantize: bits = %d not in {1,2,4,8}", bits);
     if (!std::isfinite(inv_step)) return set_error(TDE_ERR_ARG, "tde_quantize: inv_step is not finite");
+    if (quantizer < TDE_QUANT_UNIFORM || quantizer > TDE_QUANT_GAUSS)
+        return set_error(TDE_ERR_ARG, "tde_quantize: quantizer %d", quantizer);
+    if (quantizer != TDE_QUANT_UNIFORM && bits == 8)
+        return set_error(TDE_ERR_UNSUPPORTED, "tde_quantize: non-uniform quantizers take bits 1, 2 or 4");
     if (!ctx) return set_error(TDE_ERR_ARG, "tde_quantize: null context");
     const bool need_scale = bits != 1 && !(inv_step > 0.f);
     QSig one{};
@@ -276,6 +294,7 @@ int tde_quantize(tde_ctx* ctx, const float* x, int64_t n, int bits, float inv_st
     one.stat = stat;
     one.bits = bits;
     one.inv_fixed = (bits != 1 && inv_step > 0.f) ? inv_step : 0.f;
+    if (quantizer != TDE_QUANT_UNIFORM && bits != 1) one.nthr = quant_table(quantizer, bits, one.thr);
     if (need_scale) {
         size_t need = tde_quantize_workspace_size(n);
         if (!ws || ws_bytes < need)
@@ -527,6 +546,9 @@ int validate_pairs(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
         return set_error(TDE_ERR_ARG, "tde_estimate_batch: unknown mode %d", opts->mode);
     if (path < TDE_PATH_AUTO || path > TDE_PATH_MFMA_I8)
         return set_error(TDE_ERR_ARG, "tde_estimate_batch: bad path %d", path);
+    const int quantizer = opts ? opts->quantizer : TDE_QUANT_UNIFORM;
+    if (quantizer < TDE_QUANT_UNIFORM || quantizer > TDE_QUANT_GAUSS)
+        return set_error(TDE_ERR_ARG, "tde_estimate_batch: quantizer %d", quantizer);
     if (learned) {
         if (!opts->model) return set_error(TDE_ERR_ARG, "tde_estimate_batch: learned mode needs a model");
         if (opts->topk < 1 || opts->topk > kCnnMaxTop || opts->topk >= model_net(opts->model).nb)
@@ -557,6 +579,9 @@ int validate_pairs(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
         if (q.lag_hi - q.lag_lo + 1 > ((int64_t)1 << 31))
             return set_error(TDE_ERR_ARG, "pair %lld: lag range too large", (long long)i);
         if (!valid_bits(q.bits)) return set_error(TDE_ERR_ARG, "pair %lld: bits %d", (long long)i, q.bits);
+        if (quantizer != TDE_QUANT_UNIFORM && q.bits == 8)
+            return set_error(TDE_ERR_UNSUPPORTED, "pair %lld: non-uniform quantizers take bits 1, 2 or 4",
+                             (long long)i);
         if (!std::isfinite(q.inv_step_x) || !std::isfinite(q.inv_step_y))
             return set_error(TDE_ERR_ARG, "pair %lld: non-finite inv_step", (long long)i);
         if (q.r_out) {
@@ -650,6 +675,7 @@ struct BatchPlan {
     };
     std::vector<NGroup> ngroups;
     std::vector<size_t> off_res;    // per pair (NTT residues)
+    int quantizer = TDE_QUANT_UNIFORM;
     // learned mode
     bool learned = false;
     const tde_model* model = nullptr;
@@ -672,6 +698,7 @@ BatchPlan plan_batch(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
         return o;
     };
     const int path = opts ? opts->path : TDE_PATH_AUTO;
+    B.quantizer = opts ? opts->quantizer : TDE_QUANT_UNIFORM;
     B.learned = opts && opts->mode == TDE_MODE_LEARNED;
     B.pp.resize(np);
     for (int64_t i = 0; i < np; ++i) {
@@ -795,6 +822,7 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
             const float fixed = side ? q.inv_step_y : q.inv_step_x;
             S.inv_fixed = (q.bits != 1 && fixed > 0.f) ? fixed : 0.f;
             S.bits = q.bits;
+            if (B.quantizer != TDE_QUANT_UNIFORM && q.bits != 1) S.nthr = quant_table(B.quantizer, q.bits, S.thr);
             if (B.learned) {
                 // decimated CNN input, written by the quantize kernel
                 S.dec = reinterpret_cast<uint16_t*>(W + B.off_cnn) + (2 * i + side) * (int64_t)model_net(B.model).ld;

@@ -58,7 +58,15 @@ struct QSig {
     int32_t bits;
     uint16_t* dec;        // optional: n/16 bf16 block means times scale * dec_mul (n a multiple of 16)
     float dec_mul;
+    // non-uniform map: code = sign(z) #{k < nthr : |z| > thr[k]}, z = fl32(x inv);
+    // nthr = 0 is the uniform map clamp(rint(z), -K, K)
+    int32_t nthr;
+    float thr[7];
 };
+// z-unit cell boundaries (ascending, K of them) of the non-uniform quantizer
+// `kind` (TDE_QUANT_MULAW, TDE_QUANT_GAUSS) for bits 2 or 4; returns K, or 0
+// for other arguments
+int quant_table(int kind, int bits, float* out);
 
 constexpr int kQuantBlock = 4096;   // samples per quantize workgroup (256 threads x 16)
 int64_t quantize_gsum_doubles(int64_t n);

@@ -29,6 +29,7 @@ TDE_ERR_IO = -6
 TDE_I32, TDE_I64 = 0, 1
 TDE_PATH_AUTO, TDE_PATH_MFMA, TDE_PATH_POPC, TDE_PATH_NTT, TDE_PATH_MFMA_I8 = 0, 1, 2, 3, 4
 TDE_MODE_FULL, TDE_MODE_LEARNED = 0, 1
+TDE_QUANT_UNIFORM, TDE_QUANT_MULAW, TDE_QUANT_GAUSS = 0, 1, 2
 
 TDE_FLAG_NONFINITE_X = 1
 TDE_FLAG_NONFINITE_Y = 2
@@ -53,7 +54,7 @@ class tde_pair(ctypes.Structure):
 class tde_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("path", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("topk", ctypes.c_int32), ("model", ctypes.c_void_p), ("margin", ctypes.c_float),
-                ("reserved", ctypes.c_int32)]
+                ("quantizer", ctypes.c_int32)]
 
 
 class TDEError(RuntimeError):
@@ -87,6 +88,8 @@ def load_library(path: str = LIB_PATH):
         "tde_last_error": (ctypes.c_char_p, []),
         "tde_quantize_workspace_size": (sz, [i64]),
         "tde_quantize": (i32, [vp, vp, i64, i32, f32, vp, vp, vp, sz, vp]),
+        "tde_quantize_ex": (i32, [vp, vp, i64, i32, i32, f32, vp, vp, vp, sz, vp]),
+        "tde_quantizer_thresholds": (i32, [i32, i32, vp]),
         "tde_xcorr_workspace_size": (sz, [i64, i64, i32, i32, i64, i64, i32]),
         "tde_mfma_operand_bits": (i32, [i32, i32, i32]),
         "tde_xcorr_int": (i32, [vp, vp, i64, vp, i64, i32, i32, i64, i64, vp, i32, i32, vp, sz, vp]),
@@ -176,9 +179,17 @@ def tde_quantize_workspace_size(n: int) -> int:
     return int(load_library().tde_quantize_workspace_size(n))
 
 
-def tde_quantize(ctx, x, n, bits, inv_step, q, stat=None, ws=None, ws_bytes=0, stream=None):
-    _check(load_library().tde_quantize(ctx, _ptr(x), n, bits, float(inv_step), _ptr(q), _ptr(stat), _ptr(ws),
-                                       ws_bytes, _stream(stream)))
+def tde_quantize(ctx, x, n, bits, inv_step, q, stat=None, ws=None, ws_bytes=0, stream=None, quantizer=0):
+    _check(load_library().tde_quantize_ex(ctx, _ptr(x), n, bits, quantizer, float(inv_step), _ptr(q), _ptr(stat),
+                                          _ptr(ws), ws_bytes, _stream(stream)))
+
+
+def tde_quantizer_thresholds(quantizer: int, bits: int) -> np.ndarray:
+    out = np.zeros(7, np.float32)
+    k = int(load_library().tde_quantizer_thresholds(quantizer, bits, out.ctypes.data))
+    if k < 0:
+        _check(k)
+    return out[:k]
 
 
 def tde_xcorr_workspace_size(nu, nv, kmax_u, kmax_v, lag_lo, lag_hi, path=TDE_PATH_AUTO) -> int:
@@ -427,7 +438,7 @@ class Context:
     def _bytes(self, n):
         return self.torch.empty(max(int(n), 1), dtype=self.torch.uint8, device=self.device)
 
-    def quantize(self, x, bits: int, inv_step: float = 0.0, stream=None):
+    def quantize(self, x, bits: int, inv_step: float = 0.0, stream=None, quantizer: int = 0):
         """Returns (q int8 tensor, qstat record)."""
         torch = self.torch
         n = x.numel()
@@ -435,7 +446,7 @@ class Context:
         stat = self._bytes(QSTAT_DTYPE.itemsize)
         wsb = tde_quantize_workspace_size(n)
         ws = self._bytes(wsb)
-        tde_quantize(self.handle, x, n, bits, inv_step, q, stat, ws, wsb, stream)
+        tde_quantize(self.handle, x, n, bits, inv_step, q, stat, ws, wsb, stream, quantizer)
         return q, stat
 
     def xcorr(self, u, v, kmax_u, kmax_v, lag_lo, lag_hi, r_dtype=TDE_I64, path=TDE_PATH_AUTO, stream=None):
@@ -467,7 +478,7 @@ class Context:
         return peak
 
     def batch_plan(self, specs, path=TDE_PATH_AUTO, mode=TDE_MODE_FULL, use_graph=0, model=None, topk=8,
-                   margin=0.0):
+                   margin=0.0, quantizer=TDE_QUANT_UNIFORM):
         """specs: list of dicts with x, y (device float32 tensors), lag_lo, lag_hi,
         bits, optional inv_step_x/y, r_out, r_dtype. Returns (pairs array, opts,
         workspace bytes)."""
@@ -486,7 +497,7 @@ class Context:
             pairs.append(p)
         arr = make_pairs(pairs)
         opts = tde_opts(mode, path, int(use_graph), int(topk), model.handle if model is not None else None,
-                        float(margin), 0)
+                        float(margin), int(quantizer))
         wsb = tde_estimate_workspace_size(arr, len(pairs), opts)
         if wsb == 0:
             raise TDEError(TDE_ERR_ARG, tde_last_error())

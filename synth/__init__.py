@@ -184,6 +184,54 @@ def stream_embedded(nx: int = 8192, block: int = 65536, nblocks: int = 64, noise
     return x.astype(np.float32), y.astype(np.float32), where
 
 
+def frac_delay(x: np.ndarray, frac: float, taps: int = 32) -> np.ndarray:
+    """x delayed by a fraction of a sample (0 <= frac < 1): Hann-windowed sinc
+    interpolation with `taps` taps, same length (zero outside)."""
+    k = np.arange(-taps // 2 + 1, taps // 2 + 1)
+    h = np.sinc(k - frac) * (0.5 + 0.5 * np.cos(np.pi * (k - frac) / (taps // 2 + 1)))
+    y = np.convolve(x, h, mode="full")          # y[n] = sum_k x[n - k] h(k), k from -taps/2 + 1
+    return y[taps // 2 - 1:taps // 2 - 1 + x.size]
+
+
+def speech_like_mixtures(npairs: int, snr_db: float, n_target: int = 16000, n_mix: int = 80000,
+                         max_delay: int = 64000, salt: int = 0):
+    """Stand-in for the accuracy experiment of Section 4.2 (its speech and
+    environmental-sound corpora are not available): a one-second 16 kHz
+    'utterance' (AR(2) noise under a random syllable envelope of 2-5 raised-
+    cosine bumps) and a five-second background (AR(1), coefficient 0.95); the
+    target is delayed by nu ~ U[0, max_delay) samples (integer part by
+    placement, fraction by windowed-sinc interpolation) and mixed into the
+    background at the given SNR, measured as power per unit time of the
+    target over its own support against the background's. Returns (targets,
+    mixtures, nu) with float32 signals and float64 delays."""
+    rngs = pair_rngs(7, npairs, salt)
+    xs, ys, nus = [], [], []
+    for rng in rngs:
+        s = ar2(rng, n_target, 0.9, 0.5)
+        env = np.zeros(n_target)
+        t = np.arange(n_target)
+        for _ in range(int(rng.integers(2, 6))):
+            c = rng.uniform(0.1, 0.9) * n_target
+            w = rng.uniform(0.04, 0.15) * n_target
+            env += np.where(np.abs(t - c) < w, 0.5 + 0.5 * np.cos(np.pi * (t - c) / w), 0.0)
+        target = s * env
+        target /= np.sqrt(np.mean(target ** 2))
+        bg = ar1(rng, n_mix, 0.95)
+        nu = rng.uniform(0, max_delay)
+        d = int(np.floor(nu))
+        shifted = frac_delay(target, nu - d)
+        p_t = np.mean(shifted ** 2)
+        p_b = np.mean(bg ** 2)
+        bg *= np.sqrt(p_t / p_b / 10.0 ** (snr_db / 10.0))
+        mix = bg.copy()
+        hi = min(n_mix, d + n_target)
+        mix[d:hi] += shifted[:hi - d]
+        xs.append(target.astype(np.float32))
+        ys.append(mix.astype(np.float32))
+        nus.append(nu)
+    return xs, ys, np.array(nus)
+
+
 def random_int_seq(rng, n: int, k: int, p_zero: float = 0.0) -> np.ndarray:
     """Uniform integers in [-k, k] with an optional extra share of zeros."""
     q = rng.integers(-k, k + 1, size=n)

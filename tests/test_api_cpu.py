@@ -2,6 +2,8 @@
 every entry point declared in include/tde.h, sizes workspaces, and rejects
 invalid arguments before queueing any work."""
 import ctypes
+
+import numpy as np
 import os
 import re
 
@@ -43,7 +45,7 @@ def test_struct_sizes_match_header(tmp_path):
                "tde_qstat": ["inv_step", "flags", "n_nonfinite", "n_zero", "sum_q", "sum_q2"],
                "tde_pair": ["x", "y", "nx", "ny", "lag_lo", "lag_hi", "bits", "inv_step_x", "inv_step_y",
                             "r_dtype", "r_out"],
-               "tde_opts": ["mode", "path", "use_graph", "topk", "model", "margin", "reserved"]}
+               "tde_opts": ["mode", "path", "use_graph", "topk", "model", "margin", "quantizer"]}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{os.path.join(ROOT, "include", "tde.h")}"',
              "int main(void) {"]
     for st, fields in structs.items():
@@ -161,6 +163,24 @@ def test_stream_argument_validation():
     lib.tde_stream_destroy(None)
 
 
+def test_quantizer_tables_match_oracle():
+    import oracle
+    for kind in (tde.TDE_QUANT_MULAW, tde.TDE_QUANT_GAUSS):
+        for bits in (2, 4):
+            np.testing.assert_array_equal(tde.tde_quantizer_thresholds(kind, bits), oracle.nonuniform_table(kind, bits))
+    lib = tde.load_library()
+    out = np.zeros(7, np.float32)
+    assert lib.tde_quantizer_thresholds(tde.TDE_QUANT_UNIFORM, 2, out.ctypes.data) == tde.TDE_ERR_ARG
+    assert lib.tde_quantizer_thresholds(tde.TDE_QUANT_MULAW, 8, out.ctypes.data) == tde.TDE_ERR_UNSUPPORTED
+    assert lib.tde_quantizer_thresholds(tde.TDE_QUANT_GAUSS, 2, None) == tde.TDE_ERR_ARG
+    qx = lambda **k: lib.tde_quantize_ex(None, FAKE, 10, k.get("bits", 4), k.get("kind", 1), 1.0, FAKE, None, None,
+                                         0, None)
+    assert qx(kind=3) == tde.TDE_ERR_ARG
+    assert qx(kind=-1) == tde.TDE_ERR_ARG
+    assert qx(kind=2, bits=8) == tde.TDE_ERR_UNSUPPORTED
+    assert qx(kind=2, bits=4) == tde.TDE_ERR_ARG and "null context" in tde.tde_last_error()
+
+
 def test_quantize_argument_validation():
     lib = tde.load_library()
     q = lambda **k: lib.tde_quantize(None, k.get("x", FAKE), k.get("n", 10), k.get("bits", 4),
@@ -196,6 +216,12 @@ def test_batch_argument_validation():
         bad_opts = tde.tde_opts(tde.TDE_MODE_FULL, path, 0, 0, None, 0.0, 0)
         assert tde.tde_estimate_workspace_size(good, 2, bad_opts) == 0
         assert "bad path" in tde.tde_last_error()
+    bad_q = tde.tde_opts(tde.TDE_MODE_FULL, tde.TDE_PATH_AUTO, 0, 0, None, 0.0, 3)
+    assert tde.tde_estimate_workspace_size(good, 2, bad_q) == 0 and "quantizer" in tde.tde_last_error()
+    mu_opts = tde.tde_opts(tde.TDE_MODE_FULL, tde.TDE_PATH_AUTO, 0, 0, None, 0.0, tde.TDE_QUANT_MULAW)
+    assert tde.tde_estimate_workspace_size(good, 2, mu_opts) > 0
+    assert tde.tde_estimate_workspace_size(tde.make_pairs([pair(bits=8)]), 1, mu_opts) == 0
+    assert "non-uniform" in tde.tde_last_error()
     i8_opts = tde.tde_opts(tde.TDE_MODE_FULL, tde.TDE_PATH_MFMA_I8, 0, 0, None, 0.0, 0)
     assert tde.tde_estimate_workspace_size(good, 2, i8_opts) > 0
     arr = tde.make_pairs([pair(nx=300000, ny=300000, bits=8, lo=-10, hi=10, dt=tde.TDE_I32, r=FAKE)])

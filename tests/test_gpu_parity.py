@@ -81,6 +81,28 @@ def test_quantize_fixed_scale_and_specials(T, ctx, bits):
         assert st["flags"] & tde.TDE_FLAG_NONFINITE_X
 
 
+@pytest.mark.parametrize("n", [1, 1025, 65543])
+@pytest.mark.parametrize("bits", [1, 2, 4])
+@pytest.mark.parametrize("kind", [1, 2])
+def test_quantize_nonuniform_parity(T, ctx, n, bits, kind):
+    """mu-law and Lloyd-Max Gaussian maps: codes and statistics bit-exact,
+    automatic and fixed scale, special values."""
+    from paper_2509_19974_amd import tde
+    say(f"quantize nonuniform kind={kind} n={n} bits={bits}")
+    rng = np.random.default_rng(n * 7 + bits + 100 * kind)
+    x = (rng.standard_normal(n) * rng.uniform(0.1, 10)).astype(np.float32)
+    if n > 20:
+        x[3], x[7], x[11], x[13] = 0.0, -0.0, np.inf, -np.inf
+    for fixed in (0.0, 0.75):
+        q, stat = ctx.quantize(dev(T, x), bits, fixed, quantizer=kind)
+        T.cuda.synchronize()
+        qo, nf, so = oracle.quantize_nonuniform(x, bits, kind, fixed if fixed > 0 else None)
+        np.testing.assert_array_equal(q.cpu().numpy(), qo)
+        st = tde.decode_qstat(stat)[0]
+        assert st["inv_step"] == np.float32(so)
+        assert st["n_nonfinite"] == nf and st["n_zero"] == int(np.count_nonzero(qo == 0))
+
+
 def test_quantize_all_zero_and_sign_specials(T, ctx):
     from paper_2509_19974_amd import tde
     q, stat = ctx.quantize(dev(T, np.zeros(777, np.float32)), 8, 0.0)
@@ -360,6 +382,35 @@ def test_batch_fp_and_int8_operands_agree(T, ctx):
         r, r8 = sp[i]["r_out"].cpu().numpy(), sp8[i]["r_out"].cpu().numpy()
         np.testing.assert_array_equal(r, r8)
         _check_pair(pk[i], p, r)
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_batch_nonuniform_quantizers(T, ctx, kind):
+    """A batch with a non-uniform map on every pair (bits 1, 2, 4): peaks and
+    r equal the oracle's Algorithm 1 with the same map."""
+    from paper_2509_19974_amd import tde
+    say(f"batch nonuniform kind={kind}")
+    rng = np.random.default_rng(77 + kind)
+    pairs = []
+    for b in (1, 2, 4, 4, 2, 1):
+        n = int(rng.integers(2000, 30000))
+        x = rng.standard_normal(n).astype(np.float32)
+        d = int(rng.integers(-n // 4, n // 4))
+        y = synth.delay_zero_fill(x, d) + (0.5 * rng.standard_normal(n)).astype(np.float32)
+        pairs.append(dict(x=x, y=y.astype(np.float32), lag_lo=-(n // 2), lag_hi=n // 2, bits=b))
+    specs = [dict(x=dev(T, p["x"]), y=dev(T, p["y"]), lag_lo=p["lag_lo"], lag_hi=p["lag_hi"], bits=p["bits"],
+                  r_out=T.empty(p["lag_hi"] - p["lag_lo"] + 1, dtype=T.int64, device="cuda"), r_dtype=tde.TDE_I64)
+             for p in pairs]
+    plan = ctx.batch_plan(specs, quantizer=kind)
+    out = ctx.estimate_batch(specs, plan=plan)
+    T.cuda.synchronize()
+    pk = tde.decode_peaks(out)
+    for i, p in enumerate(pairs):
+        u, _, _ = oracle.quantize_nonuniform(p["x"], p["bits"], kind)
+        v, _, _ = oracle.quantize_nonuniform(p["y"], p["bits"], kind)
+        r = oracle.xcorr(u, v, p["lag_lo"], p["lag_hi"])
+        np.testing.assert_array_equal(specs[i]["r_out"].cpu().numpy(), r)
+        assert (pk[i]["lag"], pk[i]["rmax"], pk[i]["n_ties"]) == oracle.argmax(r, p["lag_lo"])
 
 
 def test_batch_deterministic(T, ctx):
