@@ -519,17 +519,19 @@ __device__ __forceinline__ void wave_loop_fp(const XPair& p, int64_t T0, int64_t
                 const int s = s0 + t;
                 const v8i a_nxt = read_a_fp<W>(t == 0 ? arow + ASTEP : arow_next);
                 const BWin<W> raw = read_bwin<W>(ubw + 2 * W * (s + 1));
-                __builtin_amdgcn_sched_barrier(0);
+                // FP4 keeps the pinned order; FP6 (its wider windows) runs about
+                // 5% faster when the compiler interleaves freely
+                if (W == 4) __builtin_amdgcn_sched_barrier(0);
                 acc[0] = mfma_fp<W>(a_cur, b0, acc[0]);
                 acc[1] = mfma_fp<W>(a_cur, b1, acc[1]);
                 acc[2] = mfma_fp<W>(a_cur, h0, acc[2]);
                 acc[3] = mfma_fp<W>(a_cur, h1, acc[3]);
-                __builtin_amdgcn_sched_barrier(0);
+                if (W == 4) __builtin_amdgcn_sched_barrier(0);
                 h0 = b0;
                 h1 = b1;
                 a_cur = a_nxt;
                 split_bwin<W>(raw, bsh, b1, b0);
-                __builtin_amdgcn_sched_barrier(0);
+                if (W == 4) __builtin_amdgcn_sched_barrier(0);
             }
             blk = nb;
             arow = arow_next;
