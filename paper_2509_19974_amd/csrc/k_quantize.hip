@@ -254,25 +254,47 @@ __global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QS
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int64_t m = base + 1024 * k + 4 * (int64_t)threadIdx.x;
-        if (m >= s.n) continue;
-        const float xs[4] = {xv[k].x, xv[k].y, xv[k].z, xv[k].w};
         uint32_t w = 0u;
+        if (m < s.n) {
+            const float xs[4] = {xv[k].x, xv[k].y, xv[k].z, xv[k].w};
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            int c = quant1(xs[e], s.bits, inv, K, nonfinite, s);
-            if (m + e < s.n) {
-                nzero += c == 0;
-                sq += c;
-                sq2 += c * c;
+            for (int e = 0; e < 4; ++e) {
+                int c = quant1(xs[e], s.bits, inv, K, nonfinite, s);
+                if (m + e < s.n) {
+                    nzero += c == 0;
+                    sq += c;
+                    sq2 += c * c;
+                } else {
+                    c = 0;
+                }
+                w |= (uint32_t)(uint8_t)c << (8 * e);
             }
-            w |= (uint32_t)(uint8_t)c << (8 * e);
-        }
-        if (m + 4 <= s.n && ((((uintptr_t)(s.q + m)) & 3) == 0)) {
-            *reinterpret_cast<uint32_t*>(s.q + m) = w;
-        } else {
+            if (m + 4 <= s.n && ((((uintptr_t)(s.q + m)) & 3) == 0)) {
+                *reinterpret_cast<uint32_t*>(s.q + m) = w;
+            } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (m + e < s.n) s.q[m + e] = (int8_t)(w >> (8 * e));
+                for (int e = 0; e < 4; ++e)
+                    if (m + e < s.n) s.q[m + e] = (int8_t)(w >> (8 * e));
+            }
+        }
+        if (s.pk) {
+            // packed FP4/FP6 codes: lanes 4j .. 4j+3 hold the 16 samples of
+            // one unit (4 each); a lane joins its bits with its right
+            // neighbour's to form the unit's dwords
+            const int W = s.pk_bits;
+            const uint32_t z = W == 6 ? fp_bits4<6>(fp_bytes<6>(w)) : fp_bits4<4>(fp_bytes<4>(w));
+            const uint32_t nb = __shfl_down(z, 1, 64);
+            const int j = threadIdx.x & 3;
+            const int64_t unit = (m - 4 * j) / 16;
+            if (16 * unit < s.n) {
+                if (W == 6) {
+                    if (j == 0) s.pk[3 * unit] = z | (nb << 24);
+                    else if (j == 1) s.pk[3 * unit + 1] = (z >> 8) | (nb << 16);
+                    else if (j == 2) s.pk[3 * unit + 2] = (z >> 16) | (nb << 8);
+                } else if (j == 0 || j == 2) {
+                    s.pk[2 * unit + (j >> 1)] = z | (nb << 16);
+                }
+            }
         }
     }
     if (s.stat) {

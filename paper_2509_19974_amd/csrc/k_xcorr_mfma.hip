@@ -312,64 +312,32 @@ struct FCfg {
     static_assert(((W * (UOFF + CM)) >> 5) + BD <= UB / 4, "u window too small");
 };
 
-// Four int8 codes (|q| <= 7, resp. 3) -> four bytes holding W-bit codes:
-// sign bit W-1, magnitude code from a byte table (v_perm_b32 as an 8-entry
-// lookup), no carries between bytes.
+// Per-wave staging of packed codes; the same windows as WaveStager, in
+// samples, with S samples per padded block of the v ring. Window starts are
+// multiples of 16 samples, so every 16-sample unit of a window is one unit of
+// the signal's packed array (or lies outside the signal: zeros).
 template <int W>
-__device__ __forceinline__ uint32_t fp_bytes(uint32_t x) {
-    const uint32_t s = (x >> 7) & 0x01010101u;
-    const uint32_t a = (x ^ (s * 0xffu)) + s;      // |q| per byte
-    // E2M3: 0 1 2 3 4 5 6 7 -> 000000 001000 010000 010100 011000 011010 011100 011110
-    // E2M1: 0 1 2 3 (4 . 6 .) -> 0000 0010 0100 0101 (0110 . 0111 .)
-    const uint32_t m = W == 6 ? __builtin_amdgcn_perm(0x1e1c1a18u, 0x14100800u, a)
-                              : __builtin_amdgcn_perm(0x00070006u, 0x05040200u, a);
-    return m | (s << (W - 1));
-}
-
-template <int W>
-struct Packed16 {
-    uint32_t d[W / 2];   // 16 codes
-};
-
-template <int W>
-__device__ __forceinline__ Packed16<W> fp_pack16(uint4 x) {
-    const uint32_t c[4] = {fp_bytes<W>(x.x), fp_bytes<W>(x.y), fp_bytes<W>(x.z), fp_bytes<W>(x.w)};
+__device__ __forceinline__ Packed16<W> load_unit(const uint32_t* pk, int64_t n, int64_t g) {
     Packed16<W> o;
-    if constexpr (W == 4) {
-        uint32_t h[4];
+    if (g >= 0 && 16 * g < n) {
+        const __attribute__((address_space(1))) uint32_t* p =
+            (const __attribute__((address_space(1))) uint32_t*)(pk + (W / 2) * g);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            uint32_t t = c[k];
-            t = (t | (t >> 4)) & 0x00ff00ffu;
-            h[k] = (t | (t >> 8)) & 0x0000ffffu;
-        }
-        o.d[0] = h[0] | (h[1] << 16);
-        o.d[1] = h[2] | (h[3] << 16);
+        for (int k = 0; k < W / 2; ++k) o.d[k] = p[k];
     } else {
-        uint32_t z[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            uint32_t t = c[k];
-            t = (t & 0x003f003fu) | ((t >> 2) & 0x0fc00fc0u);
-            z[k] = (t & 0xfffu) | ((t >> 4) & 0xfff000u);
-        }
-        o.d[0] = z[0] | (z[1] << 24);
-        o.d[1] = (z[1] >> 8) | (z[2] << 16);
-        o.d[2] = (z[2] >> 16) | (z[3] << 8);
+        for (int k = 0; k < W / 2; ++k) o.d[k] = 0u;
     }
     return o;
 }
 
-// Per-wave staging of packed codes; the same windows as WaveStager, in
-// samples, with S samples per padded block of the v ring.
 template <int W>
 struct FpStager {
     using C = FCfg<W>;
-    uint4 reg[C::NEXT_PER_LANE];
+    Packed16<W> reg[C::NEXT_PER_LANE];
 
     __device__ __forceinline__ static int vphys(int p) { return (p >> C::LS) * C::BLK + ((p & (C::S - 1)) * W) / 8; }
-    __device__ __forceinline__ static void put(uint8_t* dst, uint4 x) {
-        const Packed16<W> c = fp_pack16<W>(x);
+    __device__ __forceinline__ static void put(uint8_t* dst, const Packed16<W>& c) {
         uint32_t* d = reinterpret_cast<uint32_t*>(dst);
 #pragma unroll
         for (int k = 0; k < W / 2; ++k) d[k] = c.d[k];
@@ -377,16 +345,16 @@ struct FpStager {
 
     __device__ __forceinline__ void fill(const XPair& p, int64_t T0, int64_t qw, uint8_t* vb, uint8_t* ub,
                                          int lane) {
-        const int64_t gv0 = qw + T0;
-        const int64_t gu0 = qw - C::UOFF;
-        uint4 x[C::FILL_PER_LANE];
+        const int64_t gv0 = (qw + T0) / 16;            // exact: multiples of 16 (see the host planner)
+        const int64_t gu0 = (qw - C::UOFF) / 16;
+        Packed16<W> x[C::FILL_PER_LANE];
 #pragma unroll
         for (int k = 0; k < C::FILL_PER_LANE; ++k) {
             const int unit = lane + 64 * k;
             if (unit < C::FILL_V)
-                x[k] = load16_guarded(p.v, p.nv, gv0 + 16 * (int64_t)unit);
+                x[k] = load_unit<W>(p.vpk, p.nv, gv0 + unit);
             else if (unit < C::FILL_V + C::U_UNITS)
-                x[k] = load16_guarded(p.u, p.nu, gu0 + 16 * (int64_t)(unit - C::FILL_V));
+                x[k] = load_unit<W>(p.upk, p.nu, gu0 + (unit - C::FILL_V));
         }
 #pragma unroll
         for (int k = 0; k < C::FILL_PER_LANE; ++k) {
@@ -399,15 +367,15 @@ struct FpStager {
     }
     __device__ __forceinline__ void load_next(const XPair& p, int64_t T0, int64_t qw, int c, int lane) {
         const int64_t rel0 = (int64_t)(c - 1) * C::CM + C::VW;    // first new window sample
-        const int64_t gv0 = qw + T0 + rel0;
-        const int64_t gu0 = qw + (int64_t)c * C::CM - C::UOFF;
+        const int64_t gv0 = (qw + T0 + rel0) / 16;
+        const int64_t gu0 = (qw + (int64_t)c * C::CM - C::UOFF) / 16;
 #pragma unroll
         for (int k = 0; k < C::NEXT_PER_LANE; ++k) {
             const int unit = lane + 64 * k;
             if (unit < C::NEW_V)
-                reg[k] = load16_guarded(p.v, p.nv, gv0 + 16 * (int64_t)unit);
+                reg[k] = load_unit<W>(p.vpk, p.nv, gv0 + unit);
             else if (unit < C::NEW_V + C::U_UNITS)
-                reg[k] = load16_guarded(p.u, p.nu, gu0 + 16 * (int64_t)(unit - C::NEW_V));
+                reg[k] = load_unit<W>(p.upk, p.nu, gu0 + (unit - C::NEW_V));
         }
     }
     __device__ __forceinline__ void store_next(int c, uint8_t* vb, uint8_t* ub, int lane) {
@@ -422,6 +390,16 @@ struct FpStager {
         }
     }
 };
+
+// int8 codes -> packed units, one thread per unit.
+template <int W>
+__global__ void __launch_bounds__(256) k_pack_fp(const int8_t* q, int64_t n, uint32_t* pk) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (16 * g >= n) return;
+    const Packed16<W> c = fp_pack16<W>(load16_guarded(q, n, 16 * g));
+#pragma unroll
+    for (int k = 0; k < W / 2; ++k) pk[(W / 2) * g + k] = c.d[k];
+}
 
 // A fragment: 32 codes of one row (16 or 24 bytes, 16- resp. 8-byte aligned).
 template <int W>
@@ -992,6 +970,18 @@ int launch_xcorr_mfma(const XItem* items_dev, const MWork* work_dev, int nwork, 
     int rc = launch_mb<4>(items_dev, work_dev, n4, counters_dev, tile_parts, num_cu, s);
     if (rc) return rc;
     return launch_mb<8>(items_dev, work_dev + n4, nwork - n4, counters_dev + 1, tile_parts, num_cu, s);
+}
+
+int launch_pack_fp(const int8_t* q, int64_t n, uint32_t* pk, int W, hipStream_t s) {
+    const int64_t units = (n + 15) / 16;
+    if (units == 0) return TDE_OK;
+    const unsigned blocks = (unsigned)((units + 255) / 256);
+    if (W == 6)
+        hipLaunchKernelGGL(k_pack_fp<6>, dim3(blocks), dim3(256), 0, s, q, n, pk);
+    else
+        hipLaunchKernelGGL(k_pack_fp<4>, dim3(blocks), dim3(256), 0, s, q, n, pk);
+    TDE_HIP_CHECK(hipGetLastError());
+    return TDE_OK;
 }
 
 int launch_tiles_final(const XItem* items_dev, const XItem& one, int npairs, const ArgPart* tile_parts,

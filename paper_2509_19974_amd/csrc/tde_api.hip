@@ -370,8 +370,13 @@ size_t tde_xcorr_workspace_size(int64_t nu, int64_t nv, int kmax_u, int kmax_v, 
         return align_bytes(sizeof(NttJob)) + align_bytes(ntt_tab_words(P) * 4) + align_bytes(ntt_res_bytes(P));
     }
     mfma_plan_pair(it, path != TDE_PATH_MFMA_I8);
+    size_t pk = 0;
+    if (it.fmt != kFmtI8) {
+        const int wb = it.fmt == kFmtF6 ? 6 : 4;
+        pk = align_bytes(packed_bytes(nu, wb)) + align_bytes(packed_bytes(nv, wb));
+    }
     return align_bytes(sizeof(XItem)) + align_bytes((size_t)mfma_count_items(it) * sizeof(MWork)) +
-           align_bytes(2 * sizeof(int));
+           align_bytes(2 * sizeof(int)) + pk;
 }
 
 int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, int64_t nv, int kmax_u, int kmax_v,
@@ -446,13 +451,25 @@ int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, in
     std::vector<MWork> work;
     mfma_items(it, 0, work);
     mfma_sort_items(work);
-    // workspace: the item, the work list, two counters (one upload)
+    // workspace: the item, the work list, two counters (one upload), then
+    // the packed codes of FP operands
     const size_t off_w = align_bytes(sizeof(XItem));
+    uint8_t* W = static_cast<uint8_t*>(ws);
+    const size_t off_c = off_w + align_bytes(work.size() * sizeof(MWork));
+    int* counters = reinterpret_cast<int*>(W + off_c);
+    if (it.fmt != kFmtI8) {
+        const int wb = it.fmt == kFmtF6 ? 6 : 4;
+        uint32_t* upk = reinterpret_cast<uint32_t*>(W + off_c + align_bytes(2 * sizeof(int)));
+        uint32_t* vpk = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(upk) + align_bytes(packed_bytes(nu, wb)));
+        rc = launch_pack_fp(u, nu, upk, wb, s);
+        if (!rc) rc = launch_pack_fp(v, nv, vpk, wb, s);
+        if (rc) return rc;
+        it.p.upk = upk;
+        it.p.vpk = vpk;
+    }
     std::vector<uint8_t> blob(off_w + work.size() * sizeof(MWork));
     memcpy(blob.data(), &it, sizeof(XItem));
     memcpy(blob.data() + off_w, work.data(), work.size() * sizeof(MWork));
-    uint8_t* W = static_cast<uint8_t*>(ws);
-    int* counters = reinterpret_cast<int*>(W + off_w + align_bytes(work.size() * sizeof(MWork)));
     {
         std::lock_guard<std::mutex> lock(ctx->mu);
         drop_graphs_on(ctx, ws, ws_bytes);
@@ -687,6 +704,7 @@ struct BatchPlan {
     std::vector<size_t> off_gsum;   // per signal
     std::vector<size_t> off_r;      // per pair (r materialized in the workspace)
     std::vector<size_t> off_planes; // per pair (bit-plane engine)
+    std::vector<size_t> off_pk;     // per signal: packed FP4/FP6 codes (0: none)
 };
 
 BatchPlan plan_batch(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
@@ -749,6 +767,7 @@ BatchPlan plan_batch(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
     B.off_r.assign(np, 0);
     B.off_planes.assign(np, 0);
     B.off_res.assign(np, 0);
+    B.off_pk.assign(2 * np, 0);
     for (auto& g : B.ngroups) {
         NttPlan P{};
         P.log_n = g.log_n;
@@ -765,6 +784,11 @@ BatchPlan plan_batch(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
         const int64_t L = q.lag_hi - q.lag_lo + 1;
         if (pp.need_r && !q.r_out) B.off_r[i] = take((size_t)L * (pp.rdt == TDE_I32 ? 4 : 8));
         if (pp.eng == TDE_PATH_POPC) B.off_planes[i] = take(popc_ws_bytes(pp.probe.p));
+        if (pp.eng == TDE_PATH_MFMA && pp.probe.fmt != kFmtI8) {
+            const int wb = pp.probe.fmt == kFmtF6 ? 6 : 4;
+            B.off_pk[2 * i] = take(packed_bytes(q.nx, wb));
+            B.off_pk[2 * i + 1] = take(packed_bytes(q.ny, wb));
+        }
         if (pp.eng == TDE_PATH_NTT && pp.probe.ntiles > 0) B.off_res[i] = take(ntt_res_bytes(pp.ntt));
     }
     B.total = off;
@@ -823,6 +847,10 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
             S.inv_fixed = (q.bits != 1 && fixed > 0.f) ? fixed : 0.f;
             S.bits = q.bits;
             if (B.quantizer != TDE_QUANT_UNIFORM && q.bits != 1) S.nthr = quant_table(B.quantizer, q.bits, S.thr);
+            if (B.off_pk[2 * i + side]) {
+                S.pk = reinterpret_cast<uint32_t*>(W + B.off_pk[2 * i + side]);
+                S.pk_bits = pp.probe.fmt == kFmtF6 ? 6 : 4;
+            }
             if (B.learned) {
                 // decimated CNN input, written by the quantize kernel
                 S.dec = reinterpret_cast<uint16_t*>(W + B.off_cnn) + (2 * i + side) * (int64_t)model_net(B.model).ld;
@@ -836,6 +864,8 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
         it.engine = pp.eng;
         it.p.u = sigs[2 * i].q;
         it.p.v = sigs[2 * i + 1].q;
+        it.p.upk = sigs[2 * i].pk;
+        it.p.vpk = sigs[2 * i + 1].pk;
         it.p.r = pp.need_r ? (q.r_out ? q.r_out : (void*)(W + B.off_r[i])) : nullptr;
         it.p.r_dtype = pp.rdt;
         it.stat_x = stats + 2 * i;

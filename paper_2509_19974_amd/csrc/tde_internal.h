@@ -41,6 +41,59 @@ __device__ __forceinline__ uint32_t gload_u8(const int8_t* p) {
     return (uint32_t)(*(const __attribute__((address_space(1))) uint8_t*)p);
 }
 
+// ------------------------------------------------ FP4 / FP6 code packing --
+// Packed codes for the matrix-core engine's FP4 (E2M1) and FP6 (E2M3)
+// operands: W bits per code, code t of a 16-code unit at bits W t of its
+// W/2 dwords (the instruction's operand layout). A signal's packed array
+// holds ceil(n/16) units, the last one zero-padded.
+// Four int8 codes (|q| <= 7, resp. 3) -> four bytes holding W-bit codes:
+// sign bit W-1, magnitude code from a byte table (v_perm_b32 as an 8-entry
+// lookup), no carries between bytes.
+template <int W>
+__device__ __forceinline__ uint32_t fp_bytes(uint32_t x) {
+    const uint32_t s = (x >> 7) & 0x01010101u;
+    const uint32_t a = (x ^ (s * 0xffu)) + s;      // |q| per byte
+    // E2M3: 0 1 2 3 4 5 6 7 -> 000000 001000 010000 010100 011000 011010 011100 011110
+    // E2M1: 0 1 2 3 (4 . 6 .) -> 0000 0010 0100 0101 (0110 . 0111 .)
+    const uint32_t m = W == 6 ? __builtin_amdgcn_perm(0x1e1c1a18u, 0x14100800u, a)
+                              : __builtin_amdgcn_perm(0x00070006u, 0x05040200u, a);
+    return m | (s << (W - 1));
+}
+
+template <int W>
+struct Packed16 {
+    uint32_t d[W / 2];   // 16 codes
+};
+
+// Four bytes of W-bit codes -> their 4W bits, code e at bits W e.
+template <int W>
+__device__ __forceinline__ uint32_t fp_bits4(uint32_t t) {
+    if constexpr (W == 4) {
+        t = (t | (t >> 4)) & 0x00ff00ffu;
+        return (t | (t >> 8)) & 0x0000ffffu;
+    } else {
+        t = (t & 0x003f003fu) | ((t >> 2) & 0x0fc00fc0u);
+        return (t & 0xfffu) | ((t >> 4) & 0xfff000u);
+    }
+}
+
+// 16 int8 codes (a uint4, sample order) -> one packed unit.
+template <int W>
+__device__ __forceinline__ Packed16<W> fp_pack16(uint4 x) {
+    const uint32_t z0 = fp_bits4<W>(fp_bytes<W>(x.x)), z1 = fp_bits4<W>(fp_bytes<W>(x.y));
+    const uint32_t z2 = fp_bits4<W>(fp_bytes<W>(x.z)), z3 = fp_bits4<W>(fp_bytes<W>(x.w));
+    Packed16<W> o;
+    if constexpr (W == 4) {
+        o.d[0] = z0 | (z1 << 16);
+        o.d[1] = z2 | (z3 << 16);
+    } else {
+        o.d[0] = z0 | (z1 << 24);
+        o.d[1] = (z1 >> 8) | (z2 << 16);
+        o.d[2] = (z2 >> 16) | (z3 << 8);
+    }
+    return o;
+}
+
 // Largest code magnitude of a b-bit quantizer (sign: ternary, K = 1).
 inline int kmax_of_bits(int bits) { return bits == 1 ? 1 : (1 << (bits - 1)) - 1; }
 
@@ -62,6 +115,11 @@ struct QSig {
     // nthr = 0 is the uniform map clamp(rint(z), -K, K)
     int32_t nthr;
     float thr[7];
+    // optional: the codes packed for the FP4/FP6 matrix-core operands (pk_bits
+    // 4 or 6; ceil(n/16) units, the last zero-padded)
+    uint32_t* pk;
+    int32_t pk_bits;
+    int32_t pad1;
 };
 // z-unit cell boundaries (ascending, K of them) of the non-uniform quantizer
 // `kind` (TDE_QUANT_MULAW, TDE_QUANT_GAUSS) for bits 2 or 4; returns K, or 0
@@ -128,7 +186,14 @@ struct XPair {
     int32_t kuv;          // kmax_u * kmax_v
     int32_t kmax;         // max(kmax_u, kmax_v): selects the operand format of the MFMA engine
     int32_t pad0;
+    // FP4/FP6 operands: u and v packed (ceil(n/16) units each), required by
+    // items of those formats
+    const uint32_t* upk;
+    const uint32_t* vpk;
 };
+// int8 codes -> packed W-bit codes (W = 4 or 6) for the FP operand formats
+int launch_pack_fp(const int8_t* q, int64_t n, uint32_t* pk, int W, hipStream_t s);
+inline size_t packed_bytes(int64_t n, int W) { return (size_t)((n + 15) / 16) * 2 * W; }
 
 // fill r with zeros (a kernel, never a memset node)
 int launch_zero(void* p, size_t bytes, hipStream_t s);
