@@ -217,7 +217,9 @@ __global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QS
                                                   int64_t total_blocks) {
     const int64_t blk = blockIdx.x;
     int64_t lb;
-    const QSig& s = pick_sig(sigs, nsig, one, blk, lb);
+    // a copy: the stores below could alias the descriptor array, which
+    // would make the compiler reload its fields after every store
+    const QSig s = pick_sig(sigs, nsig, one, blk, lb);
     const float inv = (s.bits == 1) ? 0.f : (s.inv_fixed > 0.f ? s.inv_fixed : *s.inv_out);
     const int K = s.bits == 1 ? 1 : (1 << (s.bits - 1)) - 1;
     const int64_t base = lb * kQuantBlock;
