@@ -244,7 +244,9 @@ int tde_refine_ties(tde_ctx* ctx, const float* x, int64_t nx, const float* y, in
  *   running_peak (device, may be NULL): the argmax over every final lag so
  *     far (ties across calls add up; the smallest lag wins).
  * Work is queued on `stream`; a stream object is used by one host thread at
- * a time and its calls must follow each other on one HIP stream.
+ * a time and its calls must follow each other on one HIP stream. Pushes of
+ * max_block samples with r_out NULL replay a plan made at creation when the
+ * matrix-core engine takes such calls whole (no host work, no wait).
  * tde_stream_create allocates device memory (template codes, two history
  * buffers of nx - 1 + max(max_block, nx - 1) codes, r and engine workspace)
  * and returns TDE_ERR_ARG for null pointers, nx < 1, bad bits, a non-finite

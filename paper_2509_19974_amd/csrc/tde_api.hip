@@ -44,6 +44,7 @@ struct tde_ctx {
 namespace tde {
 
 int ctx_device(const tde_ctx* ctx) { return ctx->device; }
+int ctx_num_cu(const tde_ctx* ctx) { return ctx->num_cu; }
 
 static thread_local char g_err[512] = "";
 

@@ -293,6 +293,7 @@ int launch_refine(const float* x, int64_t nx, const float* y, int64_t ny, const 
 // ---------------------------------------------------------- auto engine --
 // HIP device of a context.
 int ctx_device(const tde_ctx* ctx);
+int ctx_num_cu(const tde_ctx* ctx);
 // Engine for TDE_PATH_AUTO (tuning table, else the built-in cost model).
 int auto_engine(int64_t nu, int64_t nv, int kuv, int kmax, int64_t lag_lo, int64_t lag_hi);
 

@@ -12,7 +12,19 @@
 // engines of tde_xcorr_int compute it exactly; tde_argmax_lag takes the
 // call's peak, and k_peak_merge folds it into the running peak (later calls
 // hold larger lags, so an equal maximum only adds to the count).
+//
+// Steady state: when the matrix-core engine takes calls of max_block samples
+// without cutting tiles into segments, the stream plans that call once per
+// buffer (item descriptors, sorted work list, packed template codes) and a
+// push that asks for no r only launches kernels: quantize, pack the buffer's
+// codes (FP4/FP6 operands), the engine with its fused per-tile argmax,
+// the per-pair peak, the merge and the history copy; no host planning, no
+// upload, no wait on the device.
+#include <string.h>
+
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "tde_internal.h"
 
@@ -35,6 +47,17 @@ struct tde_stream {
     tde_peak* run = nullptr;          // running peak
     int64_t pos = 0;
     bool finished = false;
+    // cached plan of a max_block call (matrix-core engine, no segments)
+    bool fast = false;
+    int fmt = 0;
+    uint8_t* fdev = nullptr;          // [2 items][work list][2 counters][tile triples]
+    XItem* fitems = nullptr;
+    MWork* fwork = nullptr;
+    int nwork = 0, n4 = 0;
+    int* fcount = nullptr;
+    ArgPart* ftparts = nullptr;
+    uint32_t* upk = nullptr;          // packed template codes
+    uint32_t* vpk[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -50,9 +73,15 @@ struct Dev {
     }
 };
 
-__global__ void k_peak_merge(const tde_peak* blk, tde_peak* run, int first, tde_peak* blk_out, tde_peak* run_out) {
+// blk's lag is shifted by lag_add (buffer to stream lags; 0 when it already
+// holds stream lags)
+__global__ void k_peak_merge(tde_peak* blk, tde_peak* run, int first, tde_peak* blk_out, tde_peak* run_out,
+                             int64_t lag_add) {
     if (threadIdx.x != 0) return;
-    const tde_peak b = *blk;
+    tde_peak b = *blk;
+    b.lag += lag_add;
+    b.flags = 0;
+    *blk = b;
     tde_peak r = *run;
     if (first || b.rmax > r.rmax) {
         r = b;
@@ -89,13 +118,109 @@ int stream_step(tde_stream* st, int64_t n, void* r_out, int r_dtype, tde_peak* b
     rc = tde_argmax_lag(st->ctx, r, rdt, lo, lo + n - 1, st->blk, st->ws + st->ws_x, st->ws_a, s);
     if (rc) return rc;
     hipLaunchKernelGGL(k_peak_merge, dim3(1), dim3(64), 0, s, st->blk, st->run, st->pos == 0 ? 1 : 0, block_peak,
-                       running_peak);
+                       running_peak, (int64_t)0);
     TDE_HIP_CHECK(hipGetLastError());
     // the last nx - 1 codes become the next call's history
     const int nxt = 1 - st->cur;
     rc = launch_copy_bytes(st->buf[nxt], b + n, (size_t)(nx - 1), s);
     if (rc) return rc;
     st->cur = nxt;
+    return TDE_OK;
+}
+
+// A max_block call on the cached plan (no r): the codes are in buf[cur].
+int stream_step_fast(tde_stream* st, tde_peak* block_peak, tde_peak* running_peak, hipStream_t s) {
+    const int64_t nx = st->nx, n = st->max_block;
+    int8_t* b = st->buf[st->cur];
+    int rc = TDE_OK;
+    if (st->fmt != kFmtI8) rc = launch_pack_fp(b, nx - 1 + n, st->vpk[st->cur], st->fmt == kFmtF6 ? 6 : 4, s);
+    if (rc) return rc;
+    const XItem* it = st->fitems + st->cur;
+    rc = launch_xcorr_mfma(it, st->fwork, st->nwork, st->fcount, false, st->ftparts, ctx_num_cu(st->ctx), s, st->n4);
+    if (rc) return rc;
+    XItem none{};
+    rc = launch_tiles_final(it, none, 1, st->ftparts, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_peak_merge, dim3(1), dim3(64), 0, s, st->blk, st->run, st->pos == 0 ? 1 : 0, block_peak,
+                       running_peak, st->pos - nx + 1);
+    TDE_HIP_CHECK(hipGetLastError());
+    const int nxt = 1 - st->cur;
+    rc = launch_copy_bytes(st->buf[nxt], b + n, (size_t)(nx - 1), s);
+    if (rc) return rc;
+    st->cur = nxt;
+    return TDE_OK;
+}
+
+// Plans a max_block call once per buffer when the matrix-core engine takes it
+// whole (no segments); otherwise calls take the general path.
+int stream_plan_fast(tde_stream* st, hipStream_t s) {
+    const int64_t nx = st->nx, n = st->max_block;
+    const int K = st->kmax;
+    int eng = st->path;
+    if (eng == TDE_PATH_AUTO) eng = tde_tune_query(nx, nx - 1 + n, K, K, 0, n - 1);
+    if (eng != TDE_PATH_MFMA && eng != TDE_PATH_MFMA_I8) return TDE_OK;
+    XItem it{};
+    it.p.u = st->u;
+    it.p.nu = nx;
+    it.p.nv = nx - 1 + n;
+    it.p.lag_lo = 0;
+    it.p.lag_hi = n - 1;
+    it.p.r = nullptr;
+    it.p.r_dtype = TDE_I64;
+    it.p.kuv = K * K;
+    it.p.kmax = K;
+    mfma_plan_pair(it, st->path != TDE_PATH_MFMA_I8);
+    if (it.segmented) return TDE_OK;
+    it.engine = TDE_PATH_MFMA;
+    it.fused = 1;
+    it.part_base = 0;
+    it.peak = st->blk;
+    std::vector<MWork> work;
+    mfma_items(it, 0, work);
+    mfma_sort_items(work);
+    const int wb = it.fmt == kFmtF6 ? 6 : 4;
+    const size_t o_items = 0, o_work = align_bytes(2 * sizeof(XItem));
+    const size_t o_cnt = o_work + align_bytes(work.size() * sizeof(MWork));
+    const size_t o_tp = o_cnt + align_bytes(2 * sizeof(int));
+    size_t o_pk = o_tp + align_bytes((size_t)(it.ntiles > 0 ? it.ntiles : 1) * sizeof(ArgPart));
+    size_t total = o_pk;
+    size_t o_upk = 0, o_vpk0 = 0, o_vpk1 = 0;
+    if (it.fmt != kFmtI8) {
+        o_upk = total;
+        total += align_bytes(packed_bytes(nx, wb));
+        o_vpk0 = total;
+        total += align_bytes(packed_bytes(nx - 1 + n, wb));
+        o_vpk1 = total;
+        total += align_bytes(packed_bytes(nx - 1 + n, wb));
+    }
+    if (hipMalloc(&st->fdev, total) != hipSuccess) return set_error(TDE_ERR_HIP, "tde_stream_create: allocation failed");
+    uint8_t* D = st->fdev;
+    if (it.fmt != kFmtI8) {
+        st->upk = reinterpret_cast<uint32_t*>(D + o_upk);
+        st->vpk[0] = reinterpret_cast<uint32_t*>(D + o_vpk0);
+        st->vpk[1] = reinterpret_cast<uint32_t*>(D + o_vpk1);
+        int rc = launch_pack_fp(st->u, nx, st->upk, wb, s);
+        if (rc) return rc;
+        it.p.upk = st->upk;
+    }
+    XItem two[2] = {it, it};
+    for (int p = 0; p < 2; ++p) {
+        two[p].p.v = st->buf[p];
+        two[p].p.vpk = st->vpk[p];
+    }
+    std::vector<uint8_t> blob(o_cnt, 0);
+    memcpy(blob.data() + o_items, two, sizeof(two));
+    if (!work.empty()) memcpy(blob.data() + o_work, work.data(), work.size() * sizeof(MWork));
+    TDE_HIP_CHECK(hipStreamSynchronize(s));
+    TDE_HIP_CHECK(hipMemcpy(D, blob.data(), blob.size(), hipMemcpyHostToDevice));
+    st->fitems = reinterpret_cast<XItem*>(D + o_items);
+    st->fwork = reinterpret_cast<MWork*>(D + o_work);
+    st->nwork = (int)work.size();
+    st->n4 = it.mb == 4 ? (int)work.size() : 0;
+    st->fcount = reinterpret_cast<int*>(D + o_cnt);
+    st->ftparts = reinterpret_cast<ArgPart*>(D + o_tp);
+    st->fmt = it.fmt;
+    st->fast = true;
     return TDE_OK;
 }
 
@@ -161,6 +286,7 @@ int tde_stream_create(tde_ctx* ctx, const float* x, int64_t nx, int bits, float 
     int rc = tde_quantize(ctx, x, nx, bits, inv_step_x, st->u, nullptr, qtmp, qws, s);
     if (!rc) rc = launch_zero(st->buf[0], (size_t)(nx - 1), s);      // nothing before the stream's start
     if (!rc) rc = launch_zero(st->blk, 2 * sizeof(tde_peak), s);
+    if (!rc) rc = stream_plan_fast(st, s);
     if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = set_error(TDE_ERR_HIP, "tde_stream_create: sync failed");
     (void)hipFree(qtmp);
     if (rc) {
@@ -191,7 +317,8 @@ int tde_stream_push(tde_stream* st, const float* y, int64_t n, void* r_out, int 
     int rc = tde_quantize(st->ctx, y, n, st->bits, st->inv_y, st->buf[st->cur] + (st->nx - 1), nullptr, nullptr, 0,
                           s);
     if (rc) return rc;
-    rc = stream_step(st, n, r_out, r_dtype, block_peak, running_peak, s);
+    rc = (st->fast && n == st->max_block && !r_out) ? stream_step_fast(st, block_peak, running_peak, s)
+                                                    : stream_step(st, n, r_out, r_dtype, block_peak, running_peak, s);
     if (rc) return rc;
     st->pos += n;
     return TDE_OK;
@@ -231,7 +358,8 @@ void tde_stream_destroy(tde_stream* st) {
     if (!st) return;
     Dev dv(st->device);
     (void)hipDeviceSynchronize();
-    for (void* q : {(void*)st->u, (void*)st->buf[0], (void*)st->buf[1], (void*)st->r, (void*)st->ws, (void*)st->blk})
+    for (void* q : {(void*)st->u, (void*)st->buf[0], (void*)st->buf[1], (void*)st->r, (void*)st->ws, (void*)st->blk,
+                    (void*)st->fdev})
         if (q) (void)hipFree(q);
     delete st;
 }

@@ -969,6 +969,31 @@ def test_stream_matches_oracle(T, ctx, case):
     st.close()
 
 
+@pytest.mark.parametrize("nx,bits,path", [(3000, 4, 0), (700, 8, 0), (5000, 1, 1), (4097, 2, 4), (1, 4, 0)])
+def test_stream_cached_plan_peaks(T, ctx, nx, bits, path):
+    """Full-size pushes without r take the cached plan (fused per-tile argmax);
+    a short push and the finish take the general path. Peaks equal the
+    oracle's at every call."""
+    from paper_2509_19974_amd import tde
+    say(f"stream cached nx={nx} bits={bits} path={path}")
+    rng = np.random.default_rng(nx * 3 + bits)
+    mb = 6000
+    sizes = [mb, mb, 123, mb, mb]
+    x = rng.standard_normal(nx).astype(np.float32)
+    blocks = [rng.standard_normal(n).astype(np.float32) for n in sizes]
+    o = oracle.stream(x, blocks, bits, inv_step_y=2.5)
+    st = tde.Stream(ctx, dev(T, x), bits, 2.5, mb, path=path)
+    for k, (b, rec) in enumerate(zip(blocks + [None], o["records"])):
+        _, pb, pr = st.finish() if b is None else st.push(dev(T, b))
+        T.cuda.synchronize()
+        if rec["block"] is not None:
+            p = tde.decode_peaks(pb)[0]
+            assert (p["lag"], p["rmax"], p["n_ties"]) == rec["block"], k
+        p = tde.decode_peaks(pr)[0]
+        assert (p["lag"], p["rmax"], p["n_ties"]) == rec["running"], k
+    st.close()
+
+
 def test_stream_finds_embedded_template(T, ctx):
     """A template buried in a noisy stream at sample 12345, pushed in blocks
     of 4096 with int32 r: the running peak lands on 12345."""
