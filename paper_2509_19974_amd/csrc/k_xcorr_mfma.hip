@@ -101,6 +101,14 @@ __device__ __forceinline__ uint4 load16_guarded(const int8_t* base, int64_t n, i
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// The value itself, hidden from the optimiser: per-lane constants derived
+// from it are recomputed where they are used instead of being hoisted out of
+// the persistent loop, where they would hold registers for the whole kernel.
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // Per-wave staging. Chunk c of a wave covers m steps [qw + c CM, qw + (c+1) CM);
 // its v window starts at global v index qw + c CM + T0, at ring byte
 // (c CM) mod R. Only the wave itself touches its region.
@@ -108,9 +116,16 @@ template <int MB>
 struct WaveStager {
     using C = MCfg<MB>;
     uint4 reg[C::NEXT_PER_LANE];
+    // the descriptor fields, read once: LDS stores go through generic
+    // pointers, after which fields read through the descriptor would be
+    // reloaded from memory
+    const int8_t* u;
+    const int8_t* v;
+    int64_t nu, nv;
+    __device__ __forceinline__ explicit WaveStager(const XPair& p) : u(p.u), v(p.v), nu(p.nu), nv(p.nv) {}
 
-    __device__ __forceinline__ void fill(const XPair& p, int64_t T0, int64_t qw, uint8_t* vb, uint8_t* ub,
-                                         int lane) {
+    __device__ __forceinline__ void fill(int64_t T0, int64_t qw, uint8_t* vb, uint8_t* ub, int lane) {
+        lane = opaque(lane);
         const int64_t gv0 = qw + T0;
         const int64_t gu0 = qw - C::UOFF;
         uint4 x[C::FILL_PER_LANE];
@@ -118,9 +133,9 @@ struct WaveStager {
         for (int k = 0; k < C::FILL_PER_LANE; ++k) {
             const int unit = lane + 64 * k;
             if (unit < C::FILL_V)
-                x[k] = load16_guarded(p.v, p.nv, gv0 + 16 * (int64_t)unit);
+                x[k] = load16_guarded(v, nv, gv0 + 16 * (int64_t)unit);
             else if (unit < C::FILL_V + C::U_UNITS)
-                x[k] = load16_guarded(p.u, p.nu, gu0 + 16 * (int64_t)(unit - C::FILL_V));
+                x[k] = load16_guarded(u, nu, gu0 + 16 * (int64_t)(unit - C::FILL_V));
         }
 #pragma unroll
         for (int k = 0; k < C::FILL_PER_LANE; ++k) {
@@ -131,7 +146,8 @@ struct WaveStager {
                 *reinterpret_cast<uint4*>(ub + 16 * (unit - C::FILL_V)) = x[k];
         }
     }
-    __device__ __forceinline__ void load_next(const XPair& p, int64_t T0, int64_t qw, int c, int lane) {
+    __device__ __forceinline__ void load_next(int64_t T0, int64_t qw, int c, int lane) {
+        lane = opaque(lane);
         const int64_t rel0 = (int64_t)(c - 1) * C::CM + C::VW;    // first new window byte
         const int64_t gv0 = qw + T0 + rel0;
         const int64_t gu0 = qw + (int64_t)c * C::CM - C::UOFF;
@@ -139,12 +155,13 @@ struct WaveStager {
         for (int k = 0; k < C::NEXT_PER_LANE; ++k) {
             const int unit = lane + 64 * k;
             if (unit < C::NEW_V)
-                reg[k] = load16_guarded(p.v, p.nv, gv0 + 16 * (int64_t)unit);
+                reg[k] = load16_guarded(v, nv, gv0 + 16 * (int64_t)unit);
             else if (unit < C::NEW_V + C::U_UNITS)
-                reg[k] = load16_guarded(p.u, p.nu, gu0 + 16 * (int64_t)(unit - C::NEW_V));
+                reg[k] = load16_guarded(u, nu, gu0 + 16 * (int64_t)(unit - C::NEW_V));
         }
     }
     __device__ __forceinline__ void store_next(int c, uint8_t* vb, uint8_t* ub, int lane) {
+        lane = opaque(lane);
         const int rel0 = (int)(((int64_t)(c - 1) * C::CM + C::VW) & (C::R - 1));
 #pragma unroll
         for (int k = 0; k < C::NEXT_PER_LANE; ++k) {
@@ -200,20 +217,21 @@ template <int MB>
 __device__ __forceinline__ void wave_loop(const XPair& p, int64_t T0, int64_t qw_a, int64_t qw_b, uint8_t* wl,
                                           int lane, v16i* acc) {
     using C = MCfg<MB>;
+    lane = opaque(lane);
     const int lc = lane & 31;
     const int g = lane >> 5;
     uint8_t* vb = wl;
     uint8_t* ubufs = wl + C::VPH;
-    WaveStager<MB> st;
+    WaveStager<MB> st(p);
     const int nch = (int)((qw_b - qw_a + C::CM - 1) / C::CM);
-    st.fill(p, T0, qw_a, vb, ubufs, lane);
+    st.fill(T0, qw_a, vb, ubufs, lane);
 
     const int a_off = C::S * lc + 16 * g;             // A read offset at step 0
     const int b_off = C::UOFF + 16 * g - lc;          // B_0 read offset at step 0 (> 0)
     const uint32_t bsh = (uint32_t)(b_off & 3);
 
     for (int c = 0; c < nch; ++c) {
-        if (c + 1 < nch) st.load_next(p, T0, qw_a, c + 1, lane);
+        if (c + 1 < nch) st.load_next(T0, qw_a, c + 1, lane);
         const int base = (int)(((int64_t)c * C::CM) & (C::R - 1));
         const uint32_t* ubw = reinterpret_cast<const uint32_t*>(ubufs) + (b_off >> 2);
         const int64_t rem = (qw_b - qw_a - (int64_t)c * C::CM) / 32;
@@ -262,53 +280,53 @@ __device__ __forceinline__ void wave_loop(const XPair& p, int64_t T0, int64_t qw
 // accumulation, twice the int8 rate. Small integer codes are exact in these
 // formats (E2M1 holds 0..3, E2M3 holds 0..7); every product and partial sum
 // is an integer, exact in fp32 while below 2^24 in magnitude, which bounds
-// each wave's m range (the host cuts items accordingly). The tile is the
-// int8 one (S = 128, 4096 lags, 4 column blocks of 32 lags), so the epilogue
-// is shared; a matrix step takes 64 values of m:
-//     A[i][k]   = v[q + T0 + 128 i + k]          k in [0, 64)
+// each wave's m range (the host cuts items accordingly). A tile has NB column
+// blocks of 32 lags (S = 32 NB, 1024 NB lags; the epilogue is the int8
+// engine's for the same NB); a matrix step takes 64 values of m:
+//     A[i][k]   = v[q + T0 + S i + k]            k in [0, 64)
 //     B_b[k][j] = u[q + k - j - 32 b]
-// With q stepping by 64, B_2(q) = B_0(q - 64) and B_3(q) = B_1(q - 64): a
-// step reads one A fragment and the 64-code u window B_1(q) | B_0(q)
-// (2W + 1 dwords, split with v_alignbit) and reuses the previous step's
-// pair for blocks 2 and 3. Codes are packed W bits each, in the operand
-// layout of the instruction (lane (row or column, g) holds k = 32 g ..
-// 32 g + 31, code t at bits W t); the staging converts the int8 codes on
-// their way into LDS.
+// With q stepping by 64, B_{b+2}(q) = B_b(q - 64): a step reads one A
+// fragment and the 64-code u window B_1(q) | B_0(q) (2W + 1 dwords, split
+// with v_alignbit) and reuses the pairs of the NB/2 - 1 previous steps for
+// the other blocks. NB = 8 halves the LDS bytes per matrix instruction
+// against NB = 4 (wide lag ranges); narrow ranges keep NB = 4. Codes are
+// packed W bits each, in the operand layout of the instruction (lane (row or
+// column, g) holds k = 32 g .. 32 g + 31, code t at bits W t).
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-template <int W>
+template <int W, int NB>
 struct FCfg {
     static constexpr int FMT = W == 4 ? kFmtF4 : kFmtF6;
-    static constexpr int S = 128;                  // coarse lag stride (samples)
-    static constexpr int LS = 7;
-    static constexpr int TLW = 32 * S;             // lags per tile, as MCfg<4>
+    static constexpr int S = 32 * NB;              // coarse lag stride (samples)
+    static constexpr int LS = NB == 4 ? 7 : 8;
+    static constexpr int TLW = 32 * S;             // lags per tile, as MCfg<NB>
     static constexpr int KS = 64;                  // m per matrix step
+    static constexpr int NP = S / KS;              // B pairs in use = steps per ring block
     static constexpr int CQ = 32;                  // steps per staged chunk
     static constexpr int CM = KS * CQ;             // m per chunk
     static constexpr int VW = TLW + CM;            // v window of a chunk (samples)
     // ring >= VW: as in the int8 engine, the new samples of chunk c+1 are
     // stored after every read of chunk c and replace samples below (c+1) CM
-    static constexpr int R = 8192;
+    static constexpr int R = NB == 4 ? 8192 : 16384;
     static_assert(R >= VW, "ring too small");
     static constexpr int SB = S * W / 8;           // packed bytes of S samples
     static constexpr int PAD = W == 4 ? 16 : 8;    // bytes after every S samples (bank spread)
     static constexpr int BLK = SB + PAD;
     static constexpr int VPH = (R / S) * BLK;
-    static constexpr int UOFF = 128;               // u window starts UOFF samples before the chunk
+    static constexpr int UOFF = 32 * NB;           // u window starts UOFF samples before the chunk
     static constexpr int UW = CM + UOFF + 128;     // u window (samples)
     static constexpr int UB = UW * W / 8;
     static constexpr int WAVE_LDS = VPH + UB;
-    static_assert(4 * WAVE_LDS <= MCfg<4>::LDS, "fits the int8 engine's LDS");
     static constexpr int FILL_V = VW / 16;         // 16-sample units
     static constexpr int NEW_V = CM / 16;
     static constexpr int U_UNITS = UW / 16;
     static constexpr int FILL_PER_LANE = (FILL_V + U_UNITS + 63) / 64;
     static constexpr int NEXT_PER_LANE = (NEW_V + U_UNITS + 63) / 64;
     static constexpr int BD = 2 * W + 1;           // dwords of a B_1 | B_0 window
-    // the window of step -1 (history) starts at sample UOFF - 127 >= 0; the
-    // last one read (one step past a full chunk) ends inside the u window
-    static_assert(UOFF >= 127, "history window before the u window");
+    // the windows of the NP - 1 history steps start at sample UOFF - 63 - 64 (NP - 1)
+    // >= 0; the last one read (one step past a full chunk) ends inside the u window
+    static_assert(UOFF - 63 - KS * (NP - 1) >= 0, "history windows before the u window");
     static_assert(((W * (UOFF + CM)) >> 5) + BD <= UB / 4, "u window too small");
 };
 
@@ -331,10 +349,14 @@ __device__ __forceinline__ Packed16<W> load_unit(const uint32_t* pk, int64_t n, 
     return o;
 }
 
-template <int W>
+template <int W, int NB>
 struct FpStager {
-    using C = FCfg<W>;
+    using C = FCfg<W, NB>;
     Packed16<W> reg[C::NEXT_PER_LANE];
+    const uint32_t* upk;     // the descriptor fields, read once (as in WaveStager)
+    const uint32_t* vpk;
+    int64_t nu, nv;
+    __device__ __forceinline__ explicit FpStager(const XPair& p) : upk(p.upk), vpk(p.vpk), nu(p.nu), nv(p.nv) {}
 
     __device__ __forceinline__ static int vphys(int p) { return (p >> C::LS) * C::BLK + ((p & (C::S - 1)) * W) / 8; }
     __device__ __forceinline__ static void put(uint8_t* dst, const Packed16<W>& c) {
@@ -343,8 +365,8 @@ struct FpStager {
         for (int k = 0; k < W / 2; ++k) d[k] = c.d[k];
     }
 
-    __device__ __forceinline__ void fill(const XPair& p, int64_t T0, int64_t qw, uint8_t* vb, uint8_t* ub,
-                                         int lane) {
+    __device__ __forceinline__ void fill(int64_t T0, int64_t qw, uint8_t* vb, uint8_t* ub, int lane) {
+        lane = opaque(lane);
         const int64_t gv0 = (qw + T0) / 16;            // exact: multiples of 16 (see the host planner)
         const int64_t gu0 = (qw - C::UOFF) / 16;
         Packed16<W> x[C::FILL_PER_LANE];
@@ -352,9 +374,9 @@ struct FpStager {
         for (int k = 0; k < C::FILL_PER_LANE; ++k) {
             const int unit = lane + 64 * k;
             if (unit < C::FILL_V)
-                x[k] = load_unit<W>(p.vpk, p.nv, gv0 + unit);
+                x[k] = load_unit<W>(vpk, nv, gv0 + unit);
             else if (unit < C::FILL_V + C::U_UNITS)
-                x[k] = load_unit<W>(p.upk, p.nu, gu0 + (unit - C::FILL_V));
+                x[k] = load_unit<W>(upk, nu, gu0 + (unit - C::FILL_V));
         }
 #pragma unroll
         for (int k = 0; k < C::FILL_PER_LANE; ++k) {
@@ -365,7 +387,8 @@ struct FpStager {
                 put(ub + 2 * W * (unit - C::FILL_V), x[k]);
         }
     }
-    __device__ __forceinline__ void load_next(const XPair& p, int64_t T0, int64_t qw, int c, int lane) {
+    __device__ __forceinline__ void load_next(int64_t T0, int64_t qw, int c, int lane) {
+        lane = opaque(lane);
         const int64_t rel0 = (int64_t)(c - 1) * C::CM + C::VW;    // first new window sample
         const int64_t gv0 = (qw + T0 + rel0) / 16;
         const int64_t gu0 = (qw + (int64_t)c * C::CM - C::UOFF) / 16;
@@ -373,12 +396,13 @@ struct FpStager {
         for (int k = 0; k < C::NEXT_PER_LANE; ++k) {
             const int unit = lane + 64 * k;
             if (unit < C::NEW_V)
-                reg[k] = load_unit<W>(p.vpk, p.nv, gv0 + unit);
+                reg[k] = load_unit<W>(vpk, nv, gv0 + unit);
             else if (unit < C::NEW_V + C::U_UNITS)
-                reg[k] = load_unit<W>(p.upk, p.nu, gu0 + (unit - C::NEW_V));
+                reg[k] = load_unit<W>(upk, nu, gu0 + (unit - C::NEW_V));
         }
     }
     __device__ __forceinline__ void store_next(int c, uint8_t* vb, uint8_t* ub, int lane) {
+        lane = opaque(lane);
         const int rel0 = (int)(((int64_t)(c - 1) * C::CM + C::VW) & (C::R - 1));
 #pragma unroll
         for (int k = 0; k < C::NEXT_PER_LANE; ++k) {
@@ -443,73 +467,81 @@ __device__ __forceinline__ void split_bwin(const BWin<W>& r, uint32_t sh, v8i& b
 
 template <int W>
 __device__ __forceinline__ v16f mfma_fp(const v8i& a, const v8i& b, const v16f& c) {
-    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, FCfg<W>::FMT, FCfg<W>::FMT, 0, 127, 0, 127);
+    constexpr int F = W == 4 ? kFmtF4 : kFmtF6;
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, F, F, 0, 127, 0, 127);
 }
 
-// The m loop of one wave over [qw_a, qw_b) (a multiple of 128) for the tile
+// The m loop of one wave over [qw_a, qw_b) (a multiple of 64 NP) for the tile
 // at T0, FP operands; the partial sums come back as int32.
-template <int W>
+template <int W, int NB>
 __device__ __forceinline__ void wave_loop_fp(const XPair& p, int64_t T0, int64_t qw_a, int64_t qw_b, uint8_t* wl,
                                              int lane, v16i* acc_out) {
-    using C = FCfg<W>;
+    using C = FCfg<W, NB>;
+    constexpr int NP = C::NP;
+    lane = opaque(lane);
     const int lc = lane & 31;
     const int g = lane >> 5;
     uint8_t* vb = wl;
     uint8_t* ub = wl + C::VPH;
-    FpStager<W> st;
+    FpStager<W, NB> st(p);
     const int nch = (int)((qw_b - qw_a + C::CM - 1) / C::CM);
-    st.fill(p, T0, qw_a, vb, ub, lane);
+    st.fill(T0, qw_a, vb, ub, lane);
 
-    const int brel = C::UOFF + 32 * g - lc - 32;   // first code of the step-0 window (>= 1)
+    const int brel = C::UOFF + 32 * g - lc - 32;   // first code of the step-0 window
     const uint32_t* ubw = reinterpret_cast<const uint32_t*>(ub) + ((W * brel) >> 5);
     const uint32_t bsh = (uint32_t)((W * brel) & 31);
     const int a_in = (32 * g * W) / 8;             // the lane's k half inside a row
     constexpr int ASTEP = C::KS * W / 8;           // bytes per step along a row
 
-    v16f acc[4];
+    v16f acc[NB];
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[b][e] = 0.f;
 
     for (int c = 0; c < nch; ++c) {
-        if (c + 1 < nch) st.load_next(p, T0, qw_a, c + 1, lane);
+        if (c + 1 < nch) st.load_next(T0, qw_a, c + 1, lane);
         const int base = (int)(((int64_t)c * C::CM) & (C::R - 1));
         const int64_t rem = (qw_b - qw_a - (int64_t)c * C::CM) / C::KS;
         const int nsteps = rem < C::CQ ? (int)rem : C::CQ;
 
-        v8i h0, h1;                                   // B_0, B_1 of the previous step
-        split_bwin<W>(read_bwin<W>(ubw - 2 * W), bsh, h1, h0);
+        // The B_1 | B_0 pair of step s sits in slot s mod NP; blocks 2 k and
+        // 2 k + 1 take the pair of step s - k. Slots of the steps before the
+        // chunk's first are read from the history windows.
+        v8i hb0[NP], hb1[NP];
+#pragma unroll
+        for (int k = 1; k < NP; ++k) split_bwin<W>(read_bwin<W>(ubw - 2 * W * k), bsh, hb1[NP - k], hb0[NP - k]);
         // Software pipeline as in the int8 loop: fragments of step s+1 are
         // read while the matrix instructions of step s run (reading one step
-        // past the chunk stays inside the staged windows). Two steps share
-        // one padded row block of the ring, so their offsets are constants.
+        // past the chunk stays inside the staged windows). The NP steps of a
+        // group share one padded row block of the ring, so their offsets are
+        // constants.
         int blk = ((base + C::S * lc) & (C::R - 1)) >> C::LS;
         const uint8_t* arow = vb + blk * C::BLK + a_in;
         v8i a_cur = read_a_fp<W>(arow);
-        v8i b0, b1;
-        split_bwin<W>(read_bwin<W>(ubw), bsh, b1, b0);
-        for (int s0 = 0; s0 < nsteps; s0 += 2) {
+        split_bwin<W>(read_bwin<W>(ubw), bsh, hb1[0], hb0[0]);
+        for (int s0 = 0; s0 < nsteps; s0 += NP) {
             const int nb = (blk + 1) & (C::R / C::S - 1);
             const uint8_t* arow_next = vb + nb * C::BLK + a_in;
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
+            for (int t = 0; t < NP; ++t) {
                 const int s = s0 + t;
-                const v8i a_nxt = read_a_fp<W>(t == 0 ? arow + ASTEP : arow_next);
+                const v8i a_nxt = read_a_fp<W>(t + 1 < NP ? arow + ASTEP * (t + 1) : arow_next);
                 const BWin<W> raw = read_bwin<W>(ubw + 2 * W * (s + 1));
                 // FP4 keeps the pinned order; FP6 (its wider windows) runs about
                 // 5% faster when the compiler interleaves freely
-                if (W == 4) __builtin_amdgcn_sched_barrier(0);
-                acc[0] = mfma_fp<W>(a_cur, b0, acc[0]);
-                acc[1] = mfma_fp<W>(a_cur, b1, acc[1]);
-                acc[2] = mfma_fp<W>(a_cur, h0, acc[2]);
-                acc[3] = mfma_fp<W>(a_cur, h1, acc[3]);
-                if (W == 4) __builtin_amdgcn_sched_barrier(0);
-                h0 = b0;
-                h1 = b1;
+                if (W == 4 || NB == 8) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int k = 0; k < NP; ++k) {
+                    const int slot = (t - k + NP) % NP;
+                    acc[2 * k] = mfma_fp<W>(a_cur, hb0[slot], acc[2 * k]);
+                    acc[2 * k + 1] = mfma_fp<W>(a_cur, hb1[slot], acc[2 * k + 1]);
+                }
+                if (W == 4 || NB == 8) __builtin_amdgcn_sched_barrier(0);
                 a_cur = a_nxt;
-                split_bwin<W>(raw, bsh, b1, b0);
-                if (W == 4) __builtin_amdgcn_sched_barrier(0);
+                // step s + 1 replaces step s + 1 - NP, whose last use was above
+                split_bwin<W>(raw, bsh, hb1[(t + 1) % NP], hb0[(t + 1) % NP]);
+                if (W == 4 || NB == 8) __builtin_amdgcn_sched_barrier(0);
             }
             blk = nb;
             arow = arow_next;
@@ -517,13 +549,15 @@ __device__ __forceinline__ void wave_loop_fp(const XPair& p, int64_t T0, int64_t
         if (c + 1 < nch) st.store_next(c + 1, vb, ub, lane);
     }
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc_out[b][e] = (int)acc[b][e];
 }
 
-template <int MB>
-__device__ __forceinline__ void mfma_item(const XItem& it, const MWork& wk, uint8_t* lds, ArgPart* tile_parts) {
+// One work item: the wave loops (int8 or FP operands) and the tile's epilogue
+// for a tile of MB column blocks.
+template <int MB, bool FP>
+__device__ __forceinline__ void mfma_tile(const XItem& it, const MWork& wk, uint8_t* lds, ArgPart* tile_parts) {
     using C = MCfg<MB>;
     const XPair& p = it.p;
     const int64_t T0 = it.T_start + (int64_t)wk.tile * C::TLW;
@@ -541,16 +575,20 @@ __device__ __forceinline__ void mfma_item(const XItem& it, const MWork& wk, uint
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[b][e] = 0;
     if (qw_a < qw_b) {
-        if (MB == 4 && it.fmt == kFmtF6)
-            wave_loop_fp<6>(p, T0, qw_a, qw_b, lds + w * FCfg<6>::WAVE_LDS, lane, acc);
-        else if (MB == 4 && it.fmt == kFmtF4)
-            wave_loop_fp<4>(p, T0, qw_a, qw_b, lds + w * FCfg<4>::WAVE_LDS, lane, acc);
-        else
+        if constexpr (FP) {
+            if (it.fmt == kFmtF6)
+                wave_loop_fp<6, MB>(p, T0, qw_a, qw_b, lds + w * FCfg<6, MB>::WAVE_LDS, lane, acc);
+            else
+                wave_loop_fp<4, MB>(p, T0, qw_a, qw_b, lds + w * FCfg<4, MB>::WAVE_LDS, lane, acc);
+        } else {
             wave_loop<MB>(p, T0, qw_a, qw_b, lds + w * C::WAVE_LDS, lane, acc);
+        }
     }
 
     __syncthreads();
-    const bool wide = it.wide != 0;
+    // an FP item's sum is below 4 (2^24 - 1) in magnitude (each wave's cap),
+    // so its tile always meets in int32, also inside a wide segmented pair
+    const bool wide = !FP && it.wide != 0;
     if (!wide) {
         // ---- int32 tile: the four partials meet by LDS atomics, then every
         // thread takes 16 lags; the argmax triple is kept in 32-bit (tile-
@@ -735,7 +773,16 @@ __global__ void __launch_bounds__(256, MB == 4 ? 2 : 1) k_xcorr_mfma(const XItem
         const MWork wk = work[wi];
         const XItem& it = items[wk.pair];
         if (it.margin && *it.margin >= it.theta) continue;   // learned mode: windows suffice
-        mfma_item<MB>(it, wk, lds, tile_parts);     // the list holds only items of this variant
+        // the list holds only items of this variant: FP items (4 or 8 blocks)
+        // run in the 4-block launch
+        if (MB == 4 && wk.fmt != kFmtI8) {
+            if (wk.mb == 8)
+                mfma_tile<8, true>(it, wk, lds, tile_parts);
+            else
+                mfma_tile<4, true>(it, wk, lds, tile_parts);
+        } else {
+            mfma_tile<MB, false>(it, wk, lds, tile_parts);
+        }
         __syncthreads();
     }
 }
@@ -848,9 +895,27 @@ int choose_mb(const XPair& p) {
     return 4;
 }
 
+// FP tiles: 8 blocks (8192 lags) unless that computes more than 1/8 more
+// lags than 4-block tiles would; TDE_MFMA_FPNB=4 or 8 in the environment
+// forces one.
+static int choose_fp_nb(const XPair& p) {
+    static const int forced = [] {
+        const char* e = getenv("TDE_MFMA_FPNB");
+        return e ? atoi(e) : 0;
+    }();
+    if (forced == 4 || forced == 8) return forced;
+    int64_t lo, hi;
+    clamp_support(p, lo, hi);
+    if (lo > hi) return 4;
+    const int64_t L = hi - floor_div(lo, 16) * 16 + 1;
+    const int64_t w8 = ceil_div(L, (int64_t)MCfg<8>::TLW) * MCfg<8>::TLW;
+    const int64_t w4 = ceil_div(L, (int64_t)MCfg<4>::TLW) * MCfg<4>::TLW;
+    return 8 * w8 <= 9 * w4 ? 8 : 4;
+}
+
 void mfma_plan_pair(XItem& it, bool allow_fp) {
     it.fmt = mfma_choose_fmt(it.p.kmax, allow_fp);
-    it.mb = it.fmt == kFmtI8 ? choose_mb(it.p) : 4;
+    it.mb = it.fmt == kFmtI8 ? choose_mb(it.p) : choose_fp_nb(it.p);
     const int64_t TLW = it.mb == 8 ? MCfg<8>::TLW : MCfg<4>::TLW;
     int64_t lo, hi;
     clamp_support(it.p, lo, hi);
@@ -928,17 +993,31 @@ void mfma_items(const XItem& it, int pair, std::vector<MWork>& out) {
     }
 }
 
-// Most expensive first (an FP step covers twice the m of an int8 step for
-// the same matrix work), the 4-tile items ahead of the 8-tile ones (two
-// launches).
-static int64_t item_cost(const MWork& a) { return (a.qb - a.qa) * (a.fmt == kFmtI8 ? 2 : 1); }
+// Most expensive first (matrix work grows with the m range and the tile's
+// blocks; an FP instruction covers twice the m of an int8 one), the items of
+// the 4-block launch ahead of the 8-block int8 ones (two launches).
+static int64_t item_cost(const MWork& a) { return (a.qb - a.qa) * a.mb * (a.fmt == kFmtI8 ? 2 : 1); }
 
 void mfma_sort_items(std::vector<MWork>& w) {
     std::stable_sort(w.begin(), w.end(), [](const MWork& a, const MWork& b) {
-        if (a.mb != b.mb) return a.mb < b.mb;
+        const int ka = mfma_launch_of(a.fmt, a.mb), kb = mfma_launch_of(b.fmt, b.mb);
+        if (ka != kb) return ka < kb;
         return item_cost(a) > item_cost(b);
     });
 }
+
+// Dynamic LDS of a launch: the 4-block launch also runs the FP items.
+template <int MB>
+constexpr int kernel_lds() {
+    if (MB == 8) return MCfg<8>::LDS;
+    int l = MCfg<4>::LDS;
+    const int f[4] = {4 * FCfg<6, 4>::WAVE_LDS, 4 * FCfg<4, 4>::WAVE_LDS, 4 * FCfg<6, 8>::WAVE_LDS,
+                      4 * FCfg<4, 8>::WAVE_LDS};
+    for (int k = 0; k < 4; ++k) l = f[k] > l ? f[k] : l;
+    return l;
+}
+// the int32 epilogue of an 8-block FP tile meets in the 4-block launch's LDS
+static_assert(kernel_lds<4>() >= MCfg<8>::TLW * 4, "FP 8-block reduction area");
 
 template <int MB>
 static int launch_mb(const XItem* items_dev, const MWork* work, int nwork, int* counter, ArgPart* tile_parts,
@@ -948,14 +1027,14 @@ static int launch_mb(const XItem* items_dev, const MWork* work, int nwork, int* 
     static int per_cu = 0;
     if (per_cu == 0) {
         TDE_HIP_CHECK(hipFuncSetAttribute((const void*)k_xcorr_mfma<MB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                          C::LDS));
+                                          kernel_lds<MB>()));
         int nb = 0;
-        TDE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_xcorr_mfma<MB>, 256, C::LDS));
+        TDE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_xcorr_mfma<MB>, 256, kernel_lds<MB>()));
         per_cu = nb > 0 ? nb : 1;
     }
     int grid = per_cu * num_cu;
     if (grid > nwork) grid = nwork;
-    hipLaunchKernelGGL(k_xcorr_mfma<MB>, dim3(grid), dim3(256), C::LDS, s, items_dev, work, nwork, counter,
+    hipLaunchKernelGGL(k_xcorr_mfma<MB>, dim3(grid), dim3(256), kernel_lds<MB>(), s, items_dev, work, nwork, counter,
                        tile_parts);
     TDE_HIP_CHECK(hipGetLastError());
     return TDE_OK;

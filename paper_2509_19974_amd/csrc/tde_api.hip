@@ -479,7 +479,7 @@ int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, in
     if (rc) return rc;
     return launch_xcorr_mfma(reinterpret_cast<const XItem*>(W), reinterpret_cast<const MWork*>(W + off_w),
                              (int)work.size(), counters, false, nullptr, ctx->num_cu, s,
-                             it.mb == 4 ? (int)work.size() : 0);
+                             mfma_launch_of(it.fmt, it.mb) == 4 ? (int)work.size() : 0);
 }
 
 // -------------------------------------------------------------- argmax --
@@ -953,7 +953,7 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
     L.pbase = pbase;
     L.nwork = (int)work.size();
     L.n4 = 0;
-    for (const MWork& w : work) L.n4 += w.mb == 4 ? 1 : 0;
+    for (const MWork& w : work) L.n4 += mfma_launch_of(w.fmt, w.mb) == 4 ? 1 : 0;
     L.nsegs = (int)segs.size();
     L.blob.assign(B.off_work + work.size() * sizeof(MWork), 0);
     memcpy(L.blob.data() + B.off_qsig, sigs.data(), sizeof(QSig) * 2 * np);

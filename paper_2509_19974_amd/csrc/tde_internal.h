@@ -260,6 +260,9 @@ int mfma_choose_fmt(int kmax, bool allow_fp);   // kFmt* for codes up to kmax
 int64_t mfma_total_q(const XItem& it);          // summed m range of its tiles
 int64_t mfma_count_items(const XItem& it);
 void mfma_items(const XItem& it, int pair, std::vector<MWork>& out);
+// Launch that runs an item: the 4-block one for int8 4-block items and every
+// FP item, the 8-block one for int8 8-block items.
+inline int mfma_launch_of(int fmt, int mb) { return fmt == kFmtI8 && mb == 8 ? 8 : 4; }
 void mfma_sort_items(std::vector<MWork>& w);
 // work_dev: nwork items sorted by mfma_sort_items, the first n4 of them with
 // mb = 4. tile_parts may be null (no triples written); counters_dev: 2 ints

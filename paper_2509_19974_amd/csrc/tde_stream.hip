@@ -216,7 +216,7 @@ int stream_plan_fast(tde_stream* st, hipStream_t s) {
     st->fitems = reinterpret_cast<XItem*>(D + o_items);
     st->fwork = reinterpret_cast<MWork*>(D + o_work);
     st->nwork = (int)work.size();
-    st->n4 = it.mb == 4 ? (int)work.size() : 0;
+    st->n4 = mfma_launch_of(it.fmt, it.mb) == 4 ? (int)work.size() : 0;
     st->fcount = reinterpret_cast<int*>(D + o_cnt);
     st->ftparts = reinterpret_cast<ArgPart*>(D + o_tp);
     st->fmt = it.fmt;
