@@ -66,10 +66,24 @@ __device__ __forceinline__ double sq_or_zero(float f) {
 
 // One block per 4096 samples of a signal: four level-10 nodes of the tree
 // (1024 samples each), thread t holding samples 1024 k + 4t .. 4t+3 of node k.
-__global__ void __launch_bounds__(256) k_sumsq_blocks(const QSig* sigs, int nsig, QSig one) {
+// With the scale fused into the quantize kernel, this kernel also zeroes the
+// statistics that kernel accumulates (first block of each signal) and the
+// scratch counters of a later kernel (first block).
+__global__ void __launch_bounds__(256) k_sumsq_blocks(const QSig* sigs, int nsig, QSig one, int fused,
+                                                      int* zero_me, int nzero) {
     const int64_t blk = blockIdx.x;
     int64_t lb;
     const QSig& s = pick_sig(sigs, nsig, one, blk, lb);
+    if (fused) {
+        if (blk == 0 && zero_me && (int)threadIdx.x < nzero) zero_me[threadIdx.x] = 0;
+        if (lb == 0 && threadIdx.x == 0 && s.stat) {
+            s.stat->flags = 0;
+            s.stat->n_nonfinite = 0;
+            s.stat->n_zero = 0;
+            s.stat->sum_q = 0;
+            s.stat->sum_q2 = 0;
+        }
+    }
     if (s.inv_fixed > 0.f || s.bits == 1) return;
     const int64_t base = lb * kQuantBlock;
     float4 xv[4];
@@ -102,6 +116,34 @@ __global__ void __launch_bounds__(256) k_sumsq_blocks(const QSig* sigs, int nsig
         const int64_t node = lb * 4 + k;
         if (node * kSumBlock < s.n) s.gsum[node] = (ws[k][0] + ws[k][1]) + (ws[k][2] + ws[k][3]);
     }
+}
+
+// inv_step of a signal from its sum of squares S: fl32((2K+1) / (6 sigma)),
+// sigma = sqrt(S / n); 0 when S = 0.
+__device__ __forceinline__ float scale_of_sum(double S, int64_t n, int bits) {
+    if (!(S > 0.0)) return 0.f;
+    const int K = (1 << (bits - 1)) - 1;
+    const double var = S / (double)n;
+    const double sigma = __builtin_sqrt(var);
+    const double v = (double)(2 * K + 1) / (6.0 * sigma);
+    return (float)v;
+}
+
+// The whole sum tree of a signal of at most kFuseMaxN samples (at most 256
+// block sums) in one wave: lane l adds block sums 4l .. 4l+3 pairwise, then
+// wave shuffles take the levels above. Zeros beyond the last block sum extend
+// the power-of-two tree of the finalize kernel without changing its value.
+constexpr int64_t kFuseMaxN = 256 * kSumBlock;
+__device__ __forceinline__ double wave_tree_sum(const double* gsum, int64_t n) {
+    const int64_t len = (n + kSumBlock - 1) / kSumBlock;
+    const int l = threadIdx.x & 63;
+    double v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = 4 * l + e < len ? gsum[4 * l + e] : 0.0;
+    double a = (v[0] + v[1]) + (v[2] + v[3]);
+#pragma unroll
+    for (int h = 1; h < 64; h <<= 1) a = a + __shfl_xor(a, h, 64);
+    return a;
 }
 
 // One block per signal: remaining levels of the sum tree, then the scale.
@@ -156,16 +198,7 @@ __global__ void __launch_bounds__(256) k_scale_finalize(const QSig* sigs, int ns
             out = a + nn;
             len = nn;
         }
-        double S = a[0];
-        if (S > 0.0) {
-            int K = (1 << (s.bits - 1)) - 1;
-            double var = S / (double)s.n;
-            double sigma = __builtin_sqrt(var);
-            double v = (double)(2 * K + 1) / (6.0 * sigma);
-            inv = (float)v;
-        } else {
-            inv = 0.f;
-        }
+        inv = scale_of_sum(a[0], s.n, s.bits);
     }
     if (t == 0) {
         if (s.inv_out) *s.inv_out = inv;
@@ -213,14 +246,30 @@ __device__ __forceinline__ T wave_sum(T v) {
 }
 
 // 256 threads x 16 samples per block; one set of statistic atomics per block.
+// fused != 0: every block takes its signal's scale from the block sums itself
+// (signals of 1 .. kFuseMaxN samples), and the first block of each signal
+// publishes it.
 __global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QSig one,
-                                                  int64_t total_blocks) {
+                                                  int64_t total_blocks, int fused) {
     const int64_t blk = blockIdx.x;
     int64_t lb;
     // a copy: the stores below could alias the descriptor array, which
     // would make the compiler reload its fields after every store
     const QSig s = pick_sig(sigs, nsig, one, blk, lb);
-    const float inv = (s.bits == 1) ? 0.f : (s.inv_fixed > 0.f ? s.inv_fixed : *s.inv_out);
+    float inv;
+    if (s.bits == 1) {
+        inv = 0.f;
+    } else if (s.inv_fixed > 0.f) {
+        inv = s.inv_fixed;
+    } else if (fused) {
+        inv = scale_of_sum(wave_tree_sum(s.gsum, s.n), s.n, s.bits);
+    } else {
+        inv = *s.inv_out;
+    }
+    if (fused && lb == 0 && threadIdx.x == 0) {
+        if (s.inv_out) *s.inv_out = inv;
+        if (s.stat) s.stat->inv_step = inv;
+    }
     const int K = s.bits == 1 ? 1 : (1 << (s.bits - 1)) - 1;
     const int64_t base = lb * kQuantBlock;
     int nonfinite = 0, nzero = 0;
@@ -387,14 +436,19 @@ int64_t quantize_gsum_doubles(int64_t n) {
 }
 
 int launch_quantize(const QSig* sigs_dev, const QSig& one, int nsig, int64_t total_blocks, bool need_scale,
-                    bool write_flags, int* zero_me, int nzero, hipStream_t s) {
+                    bool write_flags, int* zero_me, int nzero, hipStream_t s, int64_t min_n, int64_t max_n) {
+    // short signals: the quantize blocks finish the sum tree themselves, and
+    // the finalize kernel (one small launch) is left out
+    const int fused = need_scale && min_n >= 1 && max_n <= kFuseMaxN ? 1 : 0;
     if (need_scale) {
-        hipLaunchKernelGGL(k_sumsq_blocks, dim3((unsigned)total_blocks), dim3(256), 0, s, sigs_dev, nsig, one);
+        hipLaunchKernelGGL(k_sumsq_blocks, dim3((unsigned)total_blocks), dim3(256), 0, s, sigs_dev, nsig, one, fused,
+                           zero_me, nzero);
     }
-    if (need_scale || sigs_dev != nullptr || one.stat != nullptr || one.inv_out != nullptr || zero_me != nullptr)
+    if (!fused &&
+        (need_scale || sigs_dev != nullptr || one.stat != nullptr || one.inv_out != nullptr || zero_me != nullptr))
         hipLaunchKernelGGL(k_scale_finalize, dim3(nsig), dim3(256), 0, s, sigs_dev, nsig, one, zero_me, nzero);
     hipLaunchKernelGGL(k_quantize, dim3((unsigned)total_blocks), dim3(256), 0, s, sigs_dev, nsig, one,
-                       total_blocks);
+                       total_blocks, fused);
     if (write_flags)
         hipLaunchKernelGGL(k_quantize_flags, dim3((unsigned)ceil_div(nsig, 256)), dim3(256), 0, s, sigs_dev, nsig,
                            one);

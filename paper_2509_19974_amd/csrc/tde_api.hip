@@ -311,7 +311,7 @@ int tde_quantize_ex(tde_ctx* ctx, const float* x, int64_t n, int bits, int quant
         drop_graphs_on(ctx, ws, ws_bytes);
     }
     return launch_quantize(nullptr, one, 1, ceil_div(n, kQuantBlock), need_scale, stat != nullptr, nullptr, 0,
-                           static_cast<hipStream_t>(stream));
+                           static_cast<hipStream_t>(stream), n, n);
 }
 
 // --------------------------------------------------------- correlation --
@@ -813,6 +813,7 @@ namespace {
 struct BatchLaunch {
     std::vector<uint8_t> blob;       // descriptors for [0, blob.size()) of the workspace
     int64_t np = 0, bbase = 0, pbase = 0;
+    int64_t min_n = INT64_MAX, max_n = 0;   // signal lengths
     bool need_scale = false, any_popc = false, any_mfma = false, any_fused = false, any_r = false;
     int64_t max_rbytes = 0, p_split = 0, p_tiles = 0, p_words = 0;
     int nwork = 0, nsegs = 0, n4 = 0;
@@ -858,6 +859,8 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
                 S.dec_mul = 6.f / (float)(2 * kmax_of_bits(q.bits) + 1);
             }
             if (q.bits != 1 && !(fixed > 0.f)) L.need_scale = true;
+            L.min_n = S.n < L.min_n ? S.n : L.min_n;
+            L.max_n = S.n > L.max_n ? S.n : L.max_n;
             bbase += ceil_div(S.n, kQuantBlock);
         }
         XItem& it = items[i];
@@ -976,7 +979,7 @@ int batch_enqueue(tde_ctx* ctx, uint8_t* W, const BatchPlan& B, const BatchLaunc
     auto mk = [&](void) { return timed ? mark(ctx, s) : nullptr; };
     hipEvent_t t_q0 = mk();
     int rc = launch_quantize(sigs_dev, nosig, (int)(2 * L.np), L.bbase, L.need_scale, false,
-                             L.any_mfma ? reinterpret_cast<int*>(W + B.off_counters) : nullptr, 2, s);
+                             L.any_mfma ? reinterpret_cast<int*>(W + B.off_counters) : nullptr, 2, s, L.min_n, L.max_n);
     if (rc) return rc;
     hipEvent_t t_q1 = mk();
     if (timed) mark_stage(ctx, 0, t_q0, t_q1);

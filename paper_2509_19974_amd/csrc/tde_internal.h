@@ -133,8 +133,11 @@ int64_t quantize_gsum_doubles(int64_t n);
 // write_flags: also fill tde_qstat::flags (a separate small launch; the batch
 // path derives the flags from the counts where it needs them).
 // zero_me (may be null): nzero ints that later kernels of the call expect at 0.
+// min_n, max_n: bounds of the signal lengths (0, 0 when unknown); when every
+// signal has 1 .. 262144 samples the scale is finished inside the quantize
+// kernel instead of a separate launch.
 int launch_quantize(const QSig* sigs_dev, const QSig& one, int nsig, int64_t total_blocks, bool need_scale,
-                    bool write_flags, int* zero_me, int nzero, hipStream_t s);
+                    bool write_flags, int* zero_me, int nzero, hipStream_t s, int64_t min_n = 0, int64_t max_n = 0);
 
 // Result flags of a pair from the statistics of its two signals.
 __device__ inline int peak_flags(const tde_qstat* sx, int64_t nx, const tde_qstat* sy, int64_t ny) {
