@@ -109,6 +109,25 @@ __device__ __forceinline__ int opaque(int x) {
     return x;
 }
 
+// The next work item of the persistent loop, taken from the counter while the
+// last chunk of the current item runs (one lane of the workgroup asks), so
+// the atomic's round trip overlaps the matrix work. Taking it this late keeps
+// the longest-first order of the dynamic schedule.
+struct NextItem {
+    int* counter;
+    bool ask;       // the asking lane, until it has asked
+    int v;
+    __device__ __forceinline__ void fetch() {
+        if (ask) {
+            // a lane-varying address as far as the compiler knows: an atomic
+            // on a uniform address is rewritten into a form that waits for
+            // its result right away
+            v = atomicAdd(counter + opaque(0), 1);
+            ask = false;
+        }
+    }
+};
+
 // Per-wave staging. Chunk c of a wave covers m steps [qw + c CM, qw + (c+1) CM);
 // its v window starts at global v index qw + c CM + T0, at ring byte
 // (c CM) mod R. Only the wave itself touches its region.
@@ -215,7 +234,7 @@ __device__ __forceinline__ Tri64 tri_join(Tri64 a, Tri64 b) {
 // The m loop of one wave over [qw_a, qw_b) for the tile at T0.
 template <int MB>
 __device__ __forceinline__ void wave_loop(const XPair& p, int64_t T0, int64_t qw_a, int64_t qw_b, uint8_t* wl,
-                                          int lane, v16i* acc) {
+                                          int lane, v16i* acc, NextItem& nx) {
     using C = MCfg<MB>;
     lane = opaque(lane);
     const int lc = lane & 31;
@@ -232,6 +251,7 @@ __device__ __forceinline__ void wave_loop(const XPair& p, int64_t T0, int64_t qw
 
     for (int c = 0; c < nch; ++c) {
         if (c + 1 < nch) st.load_next(T0, qw_a, c + 1, lane);
+        else nx.fetch();
         const int base = (int)(((int64_t)c * C::CM) & (C::R - 1));
         const uint32_t* ubw = reinterpret_cast<const uint32_t*>(ubufs) + (b_off >> 2);
         const int64_t rem = (qw_b - qw_a - (int64_t)c * C::CM) / 32;
@@ -475,7 +495,7 @@ __device__ __forceinline__ v16f mfma_fp(const v8i& a, const v8i& b, const v16f& 
 // at T0, FP operands; the partial sums come back as int32.
 template <int W, int NB>
 __device__ __forceinline__ void wave_loop_fp(const XPair& p, int64_t T0, int64_t qw_a, int64_t qw_b, uint8_t* wl,
-                                             int lane, v16i* acc_out) {
+                                             int lane, v16i* acc_out, NextItem& nx) {
     using C = FCfg<W, NB>;
     constexpr int NP = C::NP;
     lane = opaque(lane);
@@ -501,6 +521,7 @@ __device__ __forceinline__ void wave_loop_fp(const XPair& p, int64_t T0, int64_t
 
     for (int c = 0; c < nch; ++c) {
         if (c + 1 < nch) st.load_next(T0, qw_a, c + 1, lane);
+        else nx.fetch();
         const int base = (int)(((int64_t)c * C::CM) & (C::R - 1));
         const int64_t rem = (qw_b - qw_a - (int64_t)c * C::CM) / C::KS;
         const int nsteps = rem < C::CQ ? (int)rem : C::CQ;
@@ -557,7 +578,8 @@ __device__ __forceinline__ void wave_loop_fp(const XPair& p, int64_t T0, int64_t
 // One work item: the wave loops (int8 or FP operands) and the tile's epilogue
 // for a tile of MB column blocks.
 template <int MB, bool FP>
-__device__ __forceinline__ void mfma_tile(const XItem& it, const MWork& wk, uint8_t* lds, ArgPart* tile_parts) {
+__device__ __forceinline__ void mfma_tile(const XItem& it, const MWork& wk, uint8_t* lds, ArgPart* tile_parts,
+                                          int* counter, int* s_next) {
     using C = MCfg<MB>;
     const XPair& p = it.p;
     const int64_t T0 = it.T_start + (int64_t)wk.tile * C::TLW;
@@ -574,16 +596,19 @@ __device__ __forceinline__ void mfma_tile(const XItem& it, const MWork& wk, uint
     for (int b = 0; b < MB; ++b)
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[b][e] = 0;
+    NextItem nx{counter, threadIdx.x == 0, 0};
     if (qw_a < qw_b) {
         if constexpr (FP) {
             if (it.fmt == kFmtF6)
-                wave_loop_fp<6, MB>(p, T0, qw_a, qw_b, lds + w * FCfg<6, MB>::WAVE_LDS, lane, acc);
+                wave_loop_fp<6, MB>(p, T0, qw_a, qw_b, lds + w * FCfg<6, MB>::WAVE_LDS, lane, acc, nx);
             else
-                wave_loop_fp<4, MB>(p, T0, qw_a, qw_b, lds + w * FCfg<4, MB>::WAVE_LDS, lane, acc);
+                wave_loop_fp<4, MB>(p, T0, qw_a, qw_b, lds + w * FCfg<4, MB>::WAVE_LDS, lane, acc, nx);
         } else {
-            wave_loop<MB>(p, T0, qw_a, qw_b, lds + w * C::WAVE_LDS, lane, acc);
+            wave_loop<MB>(p, T0, qw_a, qw_b, lds + w * C::WAVE_LDS, lane, acc, nx);
         }
     }
+    nx.fetch();                          // the asking lane had no chunk
+    if (threadIdx.x == 0) *s_next = nx.v;
 
     __syncthreads();
     // an FP item's sum is below 4 (2^24 - 1) in magnitude (each wave's cap),
@@ -621,36 +646,54 @@ __device__ __forceinline__ void mfma_tile(const XItem& it, const MWork& wk, uint
             }
         }
         __syncthreads();
+        // the pair's fields, read once: the r stores below go through generic
+        // pointers and would make the compiler re-read them per lag
+        void* const r = p.r;
+        const int r_dtype = p.r_dtype;
+        const bool segmented = wk.segmented != 0;
+        const int64_t lag_lo = p.lag_lo;
         // lags of the tile inside [lag_lo, lag_hi]: k in [klo, khi]
-        const int64_t klo64 = p.lag_lo - T0, khi64 = p.lag_hi - T0;
+        const int64_t klo64 = lag_lo - T0, khi64 = p.lag_hi - T0;
         const int klo = klo64 < 0 ? 0 : (int)klo64;
         const int khi = khi64 >= C::TLW ? C::TLW - 1 : (int)khi64;
+        // thread t takes lags 1024 j + 4 t + e, four per LDS read, the read of
+        // the next four issued before the current ones are used
+        constexpr int NJ = C::TLW / 1024;
+        uint4 cur = *reinterpret_cast<const uint4*>(red + 4 * threadIdx.x);
         int bv = INT32_MIN, bk = INT32_MAX, bc = 0;
-        for (int k = threadIdx.x; k < C::TLW; k += 256) {
-            if (k < klo || k > khi) continue;
-            const int v = (int)red[k];
-            if (p.r) {
-                const int64_t idx = T0 + k - p.lag_lo;
-                if (wk.segmented) {
-                    if (v != 0) {
-                        if (p.r_dtype == TDE_I32)
-                            atomicAdd(static_cast<int*>(p.r) + idx, v);
-                        else
-                            atomicAdd(static_cast<unsigned long long*>(p.r) + idx, (unsigned long long)(long long)v);
+#pragma unroll 1
+        for (int j = 0; j < NJ; ++j) {
+            const uint4 nxt = *reinterpret_cast<const uint4*>(red + 1024 * ((j + 1) % NJ) + 4 * threadIdx.x);
+            const uint32_t q4[4] = {cur.x, cur.y, cur.z, cur.w};
+            cur = nxt;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = 1024 * j + 4 * (int)threadIdx.x + e;
+                if (k < klo || k > khi) continue;
+                const int v = (int)q4[e];
+                if (r) {
+                    const int64_t idx = T0 + k - lag_lo;
+                    if (segmented) {
+                        if (v != 0) {
+                            if (r_dtype == TDE_I32)
+                                atomicAdd(static_cast<int*>(r) + idx, v);
+                            else
+                                atomicAdd(static_cast<unsigned long long*>(r) + idx, (unsigned long long)(long long)v);
+                        }
+                    } else if (r_dtype == TDE_I32) {
+                        static_cast<int32_t*>(r)[idx] = v;
+                    } else {
+                        static_cast<int64_t*>(r)[idx] = v;
                     }
-                } else if (p.r_dtype == TDE_I32) {
-                    static_cast<int32_t*>(p.r)[idx] = v;
-                } else {
-                    static_cast<int64_t*>(p.r)[idx] = v;
                 }
-            }
-            // k increases along the loop: a new maximum resets, an equal one counts
-            if (v > bv) {
-                bv = v;
-                bk = k;
-                bc = 1;
-            } else if (v == bv) {
-                bc += 1;
+                // k increases along the thread's lags: a new maximum resets, an equal one counts
+                if (v > bv) {
+                    bv = v;
+                    bk = k;
+                    bc = 1;
+                } else if (v == bv) {
+                    bc += 1;
+                }
             }
         }
         if (tile_parts && !wk.segmented) {
@@ -714,26 +757,30 @@ __device__ __forceinline__ void mfma_tile(const XItem& it, const MWork& wk, uint
     __syncthreads();
 
     // ---- outputs: r (plain stores or, for segments, atomics) and the triple
-    const int64_t L = p.lag_hi - p.lag_lo + 1;
+    void* const r = p.r;                 // read once (as in the int32 path)
+    const int r_dtype = p.r_dtype;
+    const bool segmented = wk.segmented != 0;
+    const int64_t lag_lo = p.lag_lo;
+    const int64_t L = p.lag_hi - lag_lo + 1;
     Tri64 t{INT64_MIN, INT64_MAX, 0};
     for (int k = threadIdx.x; k < C::TLW; k += 256) {
         const int64_t tau = T0 + k;
-        const int64_t idx = tau - p.lag_lo;
+        const int64_t idx = tau - lag_lo;
         if (idx < 0 || idx >= L) continue;
         const int64_t val = wide ? (int64_t)reinterpret_cast<const unsigned long long*>(lds)[k]
                                  : (int64_t)(int32_t)reinterpret_cast<const uint32_t*>(lds)[k];
-        if (p.r) {
-            if (wk.segmented) {
+        if (r) {
+            if (segmented) {
                 if (val != 0) {
-                    if (p.r_dtype == TDE_I32)
-                        atomicAdd(static_cast<int*>(p.r) + idx, (int)val);
+                    if (r_dtype == TDE_I32)
+                        atomicAdd(static_cast<int*>(r) + idx, (int)val);
                     else
-                        atomicAdd(static_cast<unsigned long long*>(p.r) + idx, (unsigned long long)val);
+                        atomicAdd(static_cast<unsigned long long*>(r) + idx, (unsigned long long)val);
                 }
-            } else if (p.r_dtype == TDE_I32) {
-                static_cast<int32_t*>(p.r)[idx] = (int32_t)val;
+            } else if (r_dtype == TDE_I32) {
+                static_cast<int32_t*>(r)[idx] = (int32_t)val;
             } else {
-                static_cast<int64_t*>(p.r)[idx] = val;
+                static_cast<int64_t*>(r)[idx] = val;
             }
         }
         t = tri_join(t, Tri64{val, idx, 1});
@@ -763,25 +810,29 @@ __global__ void __launch_bounds__(256, MB == 4 ? 2 : 1) k_xcorr_mfma(const XItem
                                                                       int* counter, ArgPart* tile_parts) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     __shared__ int s_item;
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
-        __syncthreads();
         // uniform: descriptors come through scalar loads, not VGPRs
         const int wi = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
+        __syncthreads();                  // every wave has read s_item
         if (wi >= nwork) break;
         const MWork wk = work[wi];
         const XItem& it = items[wk.pair];
-        if (it.margin && *it.margin >= it.theta) continue;   // learned mode: windows suffice
+        if (it.margin && *it.margin >= it.theta) {   // learned mode: windows suffice
+            if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+            __syncthreads();
+            continue;
+        }
         // the list holds only items of this variant: FP items (4 or 8 blocks)
-        // run in the 4-block launch
+        // run in the 4-block launch. Each item leaves the next one in s_item.
         if (MB == 4 && wk.fmt != kFmtI8) {
             if (wk.mb == 8)
-                mfma_tile<8, true>(it, wk, lds, tile_parts);
+                mfma_tile<8, true>(it, wk, lds, tile_parts, counter, &s_item);
             else
-                mfma_tile<4, true>(it, wk, lds, tile_parts);
+                mfma_tile<4, true>(it, wk, lds, tile_parts, counter, &s_item);
         } else {
-            mfma_tile<MB, false>(it, wk, lds, tile_parts);
+            mfma_tile<MB, false>(it, wk, lds, tile_parts, counter, &s_item);
         }
         __syncthreads();
     }
