@@ -264,7 +264,9 @@ __device__ __forceinline__ void wave_loop(const XPair& p, int64_t T0, int64_t qw
         // instructions of step s run; reading one step past the chunk stays
         // inside the staged windows. Inside a group of MB steps the A rows
         // stay in one padded S-byte block (the ring end is S-aligned), so
-        // their LDS offsets are constants.
+        // their LDS offsets are constants. (Unlike the FP loop, each chunk
+        // re-reads its history and step 0: carrying them over measured 3%
+        // slower here.)
         int p0 = (base + a_off) & (C::R - 1);
         const uint8_t* arow = vb + vphys<MB>(p0);
         v4i a_cur = read_a(arow);
@@ -519,28 +521,29 @@ __device__ __forceinline__ void wave_loop_fp(const XPair& p, int64_t T0, int64_t
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[b][e] = 0.f;
 
+    // The B_1 | B_0 pair of step s sits in slot s mod NP; blocks 2 k and
+    // 2 k + 1 take the pair of step s - k. The slots of the steps before the
+    // first are read from the history windows. Chunks are whole groups of NP
+    // steps, so at a chunk boundary the registers already hold the next
+    // chunk's history and its step 0 (read, one step past the old chunk, from
+    // staged data that is still valid): only the first chunk reads them.
+    v8i hb0[NP], hb1[NP];
+#pragma unroll
+    for (int k = 1; k < NP; ++k) split_bwin<W>(read_bwin<W>(ubw - 2 * W * k), bsh, hb1[NP - k], hb0[NP - k]);
+    // Software pipeline as in the int8 loop: fragments of step s+1 are read
+    // while the matrix instructions of step s run (reading one step past the
+    // chunk stays inside the staged windows). The NP steps of a group share
+    // one padded row block of the ring, so their offsets are constants.
+    int blk = ((C::S * lc) & (C::R - 1)) >> C::LS;
+    const uint8_t* arow = vb + blk * C::BLK + a_in;
+    v8i a_cur = read_a_fp<W>(arow);
+    split_bwin<W>(read_bwin<W>(ubw), bsh, hb1[0], hb0[0]);
+
     for (int c = 0; c < nch; ++c) {
         if (c + 1 < nch) st.load_next(T0, qw_a, c + 1, lane);
         else nx.fetch();
-        const int base = (int)(((int64_t)c * C::CM) & (C::R - 1));
         const int64_t rem = (qw_b - qw_a - (int64_t)c * C::CM) / C::KS;
         const int nsteps = rem < C::CQ ? (int)rem : C::CQ;
-
-        // The B_1 | B_0 pair of step s sits in slot s mod NP; blocks 2 k and
-        // 2 k + 1 take the pair of step s - k. Slots of the steps before the
-        // chunk's first are read from the history windows.
-        v8i hb0[NP], hb1[NP];
-#pragma unroll
-        for (int k = 1; k < NP; ++k) split_bwin<W>(read_bwin<W>(ubw - 2 * W * k), bsh, hb1[NP - k], hb0[NP - k]);
-        // Software pipeline as in the int8 loop: fragments of step s+1 are
-        // read while the matrix instructions of step s run (reading one step
-        // past the chunk stays inside the staged windows). The NP steps of a
-        // group share one padded row block of the ring, so their offsets are
-        // constants.
-        int blk = ((base + C::S * lc) & (C::R - 1)) >> C::LS;
-        const uint8_t* arow = vb + blk * C::BLK + a_in;
-        v8i a_cur = read_a_fp<W>(arow);
-        split_bwin<W>(read_bwin<W>(ubw), bsh, hb1[0], hb0[0]);
         for (int s0 = 0; s0 < nsteps; s0 += NP) {
             const int nb = (blk + 1) & (C::R / C::S - 1);
             const uint8_t* arow_next = vb + nb * C::BLK + a_in;
@@ -549,8 +552,9 @@ __device__ __forceinline__ void wave_loop_fp(const XPair& p, int64_t T0, int64_t
                 const int s = s0 + t;
                 const v8i a_nxt = read_a_fp<W>(t + 1 < NP ? arow + ASTEP * (t + 1) : arow_next);
                 const BWin<W> raw = read_bwin<W>(ubw + 2 * W * (s + 1));
-                // FP4 keeps the pinned order; FP6 (its wider windows) runs about
-                // 5% faster when the compiler interleaves freely
+                // FP4 and the 8-block tiles keep the pinned order; the 4-block
+                // FP6 loop (wider windows) runs about 5% faster when the
+                // compiler interleaves freely
                 if (W == 4 || NB == 8) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int k = 0; k < NP; ++k) {
@@ -932,18 +936,22 @@ int mfma_choose_fmt(int kmax, bool allow_fp) {
     return kFmtI8;
 }
 
-// 8 accumulator tiles per wave halve the LDS bytes per matrix instruction but
-// make tiles of 8192 lags; narrow lag ranges keep 4 (4096-lag tiles).
+// Lags of [lo, hi] (the clamped range) covered by tiles of tlw lags.
+static int64_t tiled_lags(int64_t lo, int64_t hi, int64_t tlw) {
+    const int64_t L = hi - floor_div(lo, 16) * 16 + 1;
+    return ceil_div(L, tlw) * tlw;
+}
+
+// int8 items keep 4 accumulator blocks (4096-lag tiles): 8 blocks need more
+// registers than two waves per SIMD allow, and the separate 8-block launch
+// (TDE_MFMA_MB=8 in the environment) runs one wave per SIMD.
 int choose_mb(const XPair& p) {
     static const int forced = [] {
         const char* e = getenv("TDE_MFMA_MB");
         return e ? atoi(e) : 0;
     }();
-    if (forced == 4 || forced == 8) return forced;
-    int64_t lo, hi;
-    clamp_support(p, lo, hi);
     (void)p;
-    return 4;
+    return forced == 8 ? 8 : 4;
 }
 
 // FP tiles: 8 blocks (8192 lags) unless that computes more than 1/8 more
@@ -958,10 +966,7 @@ static int choose_fp_nb(const XPair& p) {
     int64_t lo, hi;
     clamp_support(p, lo, hi);
     if (lo > hi) return 4;
-    const int64_t L = hi - floor_div(lo, 16) * 16 + 1;
-    const int64_t w8 = ceil_div(L, (int64_t)MCfg<8>::TLW) * MCfg<8>::TLW;
-    const int64_t w4 = ceil_div(L, (int64_t)MCfg<4>::TLW) * MCfg<4>::TLW;
-    return 8 * w8 <= 9 * w4 ? 8 : 4;
+    return 8 * tiled_lags(lo, hi, MCfg<8>::TLW) <= 9 * tiled_lags(lo, hi, MCfg<4>::TLW) ? 8 : 4;
 }
 
 void mfma_plan_pair(XItem& it, bool allow_fp) {
