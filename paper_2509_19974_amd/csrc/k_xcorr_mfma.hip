@@ -955,14 +955,17 @@ int choose_mb(const XPair& p) {
 }
 
 // FP tiles: 8 blocks (8192 lags) unless that computes more than 1/8 more
-// lags than 4-block tiles would; TDE_MFMA_FPNB=4 or 8 in the environment
-// forces one.
+// lags than 4-block tiles would, or the shorter signal has fewer than 32768
+// samples: then each wave's share of a tile is a few chunks, fixed per-item
+// costs dominate, and twice as many 4-block items spread over more
+// workgroups. TDE_MFMA_FPNB=4 or 8 in the environment forces one.
 static int choose_fp_nb(const XPair& p) {
     static const int forced = [] {
         const char* e = getenv("TDE_MFMA_FPNB");
         return e ? atoi(e) : 0;
     }();
     if (forced == 4 || forced == 8) return forced;
+    if ((p.nu < p.nv ? p.nu : p.nv) < 32768) return 4;
     int64_t lo, hi;
     clamp_support(p, lo, hi);
     if (lo > hi) return 4;
