@@ -210,6 +210,28 @@ def test_xcorr_fp_segmented_near_fp32_bound(T, ctx):
     np.testing.assert_array_equal(r.cpu().numpy(), ro)
 
 
+def test_xcorr_fp_8block_segmented(T, ctx):
+    """FP6 codes over 16384 lags (8-block tiles of 8192 lags) whose m range
+    exceeds four fp32-exact quarters: the 8-block tiles are cut into segments.
+    r equals the int8 engine's on every lag and the oracle's direct sums on
+    sampled lags (tile edges, the peak, random)."""
+    from paper_2509_19974_amd import tde
+    n = 1500000
+    rng = np.random.default_rng(1501)
+    u = (7 * rng.choice(np.array([-1, 1], np.int8), n)).astype(np.int8)
+    u[rng.integers(0, n, n // 50)] = 3
+    v = np.roll(u, 5000)
+    v[::7] = -v[::7]
+    lo, hi = -8192, 8191                  # exactly two 8192-lag tiles
+    say("xcorr fp6 8-block segmented")
+    r = ctx.xcorr(dev(T, u), dev(T, v), 7, 7, lo, hi, tde.TDE_I64, tde.TDE_PATH_MFMA).cpu().numpy()
+    r8 = ctx.xcorr(dev(T, u), dev(T, v), 7, 7, lo, hi, tde.TDE_I64, tde.TDE_PATH_MFMA_I8).cpu().numpy()
+    np.testing.assert_array_equal(r, r8)
+    taus = np.array([lo, -1, 0, hi, 5000, 31, 32, 255, 256] + [int(t) for t in rng.integers(lo, hi + 1, 12)])
+    np.testing.assert_array_equal(r[taus - lo], oracle.xcorr_at(u, v, taus))
+    assert abs(int(r[5000 - lo])) > 2 ** 24
+
+
 @pytest.mark.parametrize("case", [c[:4] + (1,) for c in XCASES])
 def test_xcorr_popc_parity(T, ctx, case):
     from paper_2509_19974_amd import tde
