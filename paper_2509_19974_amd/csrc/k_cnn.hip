@@ -52,15 +52,13 @@ __global__ void __launch_bounds__(256) k_cnn_decimate(const CnnSig* sigs, int ld
 
 // ---------------------------------------------------------- conv layer 0 --
 // One input channel. grid (ceil(L / 512), nsig); thread -> one pooled
-// position (two conv positions), all 32 channels.
+// position (two conv positions), all 32 channels. The weights are the same
+// for every thread: they come through scalar loads as instruction operands
+// (W[c K + k], bias[c]), not through LDS.
 template <bool SAVE>
-__global__ void __launch_bounds__(256) k_conv1_fwd(const uint16_t* X, const float* W, const float* bias,
-                                                   uint16_t* Z, uint16_t* P, int L) {
-    __shared__ float ws[kCnnK][kCnnC];
-    __shared__ float bs[kCnnC];
-    for (int e = threadIdx.x; e < kCnnK * kCnnC; e += 256) ws[e % kCnnK][e / kCnnK] = W[e];
-    if (threadIdx.x < kCnnC) bs[threadIdx.x] = bias[threadIdx.x];
-    __syncthreads();
+__global__ void __launch_bounds__(256) k_conv1_fwd(const uint16_t* __restrict__ X, const float* __restrict__ W,
+                                                   const float* __restrict__ bias, uint16_t* __restrict__ Z,
+                                                   uint16_t* __restrict__ P, int L) {
     const int g = blockIdx.y;
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (2 * p >= L) return;
@@ -75,11 +73,11 @@ __global__ void __launch_bounds__(256) k_conv1_fwd(const uint16_t* X, const floa
     uint16_t po[kCnnC];
 #pragma unroll
     for (int c = 0; c < kCnnC; ++c) {
-        float z0 = bs[c], z1 = bs[c];
+        float z0 = bias[c], z1 = bias[c];
 #pragma unroll
         for (int k = 0; k < kCnnK; ++k) {
-            z0 += ws[k][c] * xv[k];
-            z1 += ws[k][c] * xv[k + 1];
+            z0 += W[c * kCnnK + k] * xv[k];
+            z1 += W[c * kCnnK + k] * xv[k + 1];
         }
         zo[0][c] = f2bf(z0);
         zo[1][c] = f2bf(z1);
