@@ -188,6 +188,99 @@ __global__ void __launch_bounds__(256) k_conv32_fwd_mfma(const uint16_t* X, cons
     }
 }
 
+// Inference: layers 0 and 1 in one kernel. A workgroup of layer 1 (512
+// positions t0 ..) needs layer-0 rows t0 - 4 .. t0 + 515 (pooled, 32
+// channels); it computes them from the one-channel input (samples
+// 2 t0 - 12 .. 2 t0 + 1035) straight into the LDS rows that
+// k_conv32_fwd_mfma would have loaded, with the arithmetic of k_conv1_fwd
+// (same operations, same order), so layer 0's output never goes to memory.
+// Rows outside [0, L1) are zero, as in the unfused layer's staging.
+__global__ void __launch_bounds__(256) k_conv01_fwd_mfma(const uint16_t* __restrict__ X0,
+                                                         const float* __restrict__ W0,
+                                                         const float* __restrict__ b0, const uint4* frag,
+                                                         const float* bias, uint16_t* P, int L0) {
+    constexpr int kX0 = 2 * (kMPos + 8) + 8;   // input samples of a workgroup
+    __shared__ __attribute__((aligned(16))) uint8_t xs[(kMPos + 8) * kMRow];
+    __shared__ float x0s[kX0];
+    const int L = L0 / 2;                      // layer-1 length
+    const int g = blockIdx.y;
+    const int t0 = blockIdx.x * kMPos;
+    const uint16_t* x0 = X0 + (int64_t)g * L0;
+    for (int e = threadIdx.x; e < kX0; e += 256) {
+        const int t = 2 * t0 - 12 + e;
+        x0s[e] = (t >= 0 && t < L0) ? bf2f(x0[t]) : 0.f;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint4 a[18];
+#pragma unroll
+    for (int b = 0; b < 18; ++b) a[b] = frag[b * 64 + lane];
+    const int col = lane & 31, hg = lane >> 5;
+    float bia[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) bia[e] = bias[8 * (e >> 2) + 4 * hg + (e & 3)];
+    __syncthreads();
+    // layer 0: row r is pooled position t = t0 - 4 + r; its conv positions
+    // 2t, 2t+1 read samples 2t - 4 .. 2t + 5 = x0s[2r .. 2r + 9]
+    for (int r = threadIdx.x; r < kMPos + 8; r += 256) {
+        const int t = t0 - 4 + r;
+        uint16_t po[kCnnC];
+        if (t >= 0 && t < L) {
+            float xv[10];
+#pragma unroll
+            for (int j = 0; j < 10; ++j) xv[j] = x0s[2 * r + j];
+#pragma unroll
+            for (int c = 0; c < kCnnC; ++c) {
+                float z0 = b0[c], z1 = b0[c];
+#pragma unroll
+                for (int k = 0; k < kCnnK; ++k) {
+                    z0 += W0[c * kCnnK + k] * xv[k];
+                    z1 += W0[c * kCnnK + k] * xv[k + 1];
+                }
+                po[c] = f2bf(0.5f * (fmaxf(z0, 0.f) + fmaxf(z1, 0.f)));
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < kCnnC; ++c) po[c] = 0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            *reinterpret_cast<uint4*>(xs + r * kMRow + 16 * q) = reinterpret_cast<const uint4*>(po)[q];
+    }
+    __syncthreads();
+    // layer 1, as k_conv32_fwd_mfma<false>
+    for (int tt = 0; tt < 4; ++tt) {
+        const int p0 = (w * 4 + tt) * 32;
+        if (t0 + p0 >= L) break;
+        f32x16 acc;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+#pragma unroll
+        for (int b = 0; b < 18; ++b) {
+            const int tap = b >> 1;
+            const uint4 bv = *reinterpret_cast<const uint4*>(xs + (p0 + col + tap) * kMRow + 32 * (b & 1) + 16 * hg);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[b]),
+                                                          __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
+        }
+        const int t = t0 + p0 + col;
+        uint16_t pb[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const float z = acc[e] + bia[e];
+            const float zn = __shfl_xor(z, 1, 64);
+            pb[e] = f2bf(0.5f * (fmaxf(z, 0.f) + fmaxf(zn, 0.f)));
+        }
+        if (t < L && (t & 1) == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int o = 8 * q + 4 * hg;
+                *reinterpret_cast<uint2*>(P + ((int64_t)g * (L / 2) + t / 2) * kCnnC + o) =
+                    make_uint2((uint32_t)pb[4 * q] | ((uint32_t)pb[4 * q + 1] << 16),
+                               (uint32_t)pb[4 * q + 2] | ((uint32_t)pb[4 * q + 3] << 16));
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------------- head --
 // raw[b][k] = sum_t sum_c Fx[t][c] Fy[t + s][c], s = k - nb/2, on the bf16
 // matrix cores. For a fixed block offset D, the 32 x 32 products
@@ -576,6 +669,18 @@ int launch_cnn_forward(const CnnNet& net, const float* wc, const uint16_t* xdec,
         const float* bias = W + (l == 0 ? kCnnC * kCnnK : kCnnC * kCnnC * kCnnK);
         uint16_t* Z = A.z[l];
         uint16_t* P = A.x[l + 1];
+        if (l == 0 && !Z && !A.z[1]) {
+            // inference: layers 0 and 1 in one pass (layer 0's output stays in LDS)
+            const float* W1 = wc + cnn_param_offset(1);
+            const uint4* fr = reinterpret_cast<const uint4*>(net.frag);
+            hipLaunchKernelGGL(k_conv01_fwd_mfma, dim3(ceil_div(L / 2, kMPos), nsig), dim3(256), 0, s, X, W, bias,
+                               fr, W1 + kCnnC * kCnnC * kCnnK, A.x[2], L);
+            TDE_HIP_CHECK(hipGetLastError());
+            X = A.x[2];
+            L /= 4;
+            ++l;
+            continue;
+        }
         if (l == 0) {
             if (Z) hipLaunchKernelGGL(k_conv1_fwd<true>, dim3(ceil_div(L / 2, 256), nsig), dim3(256), 0, s, X, W, bias, Z, P, L);
             else hipLaunchKernelGGL(k_conv1_fwd<false>, dim3(ceil_div(L / 2, 256), nsig), dim3(256), 0, s, X, W, bias, Z, P, L);
