@@ -644,8 +644,9 @@ __device__ __forceinline__ void mfma_tile(const XItem& it, const MWork& wk, uint
 #pragma unroll
                     for (int e = 0; e < 16; ++e) {
                         const int i = 8 * (e >> 2) + 4 * g + (e & 3);
-                        const int val = acc[b][e];
-                        if (val != 0) atomicAdd(red + lc + 32 * b + C::S * i, (unsigned int)val);
+                        // unconditional: a test per value costs more in
+                        // branches than the adds it would skip
+                        atomicAdd(red + lc + 32 * b + C::S * i, (unsigned int)acc[b][e]);
                     }
             }
         }
@@ -739,23 +740,22 @@ __device__ __forceinline__ void mfma_tile(const XItem& it, const MWork& wk, uint
     }
     __syncthreads();
     {
+        // accumulator layout: lane (j = lc, g), register e -> row 8(e/4) + 4g + e%4
         const int lc = lane & 31, g = lane >> 5;
+        if (wide) {
 #pragma unroll
-        for (int b = 0; b < MB; ++b) {
+            for (int b = 0; b < MB; ++b)
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                // accumulator layout: lane (j = lc, g), register e -> row 8(e/4) + 4g + e%4
-                const int i = 8 * (e >> 2) + 4 * g + (e & 3);
-                const int idx = lc + 32 * b + C::S * i;
-                const int val = acc[b][e];
-                if (val != 0) {
-                    if (wide)
-                        atomicAdd(reinterpret_cast<unsigned long long*>(lds) + idx,
-                                  (unsigned long long)(long long)val);
-                    else
-                        atomicAdd(reinterpret_cast<unsigned int*>(lds) + idx, (unsigned int)val);
-                }
-            }
+                for (int e = 0; e < 16; ++e)
+                    atomicAdd(reinterpret_cast<unsigned long long*>(lds) + lc + 32 * b + C::S * (8 * (e >> 2) + 4 * g + (e & 3)),
+                              (unsigned long long)(long long)acc[b][e]);
+        } else {
+#pragma unroll
+            for (int b = 0; b < MB; ++b)
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    atomicAdd(reinterpret_cast<unsigned int*>(lds) + lc + 32 * b + C::S * (8 * (e >> 2) + 4 * g + (e & 3)),
+                              (unsigned int)acc[b][e]);
         }
     }
     __syncthreads();
