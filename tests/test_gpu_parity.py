@@ -41,7 +41,7 @@ def dev(T, a):
 
 # ---------------------------------------------------------------- quantize --
 
-@pytest.mark.parametrize("n", [1, 5, 1023, 1024, 1025, 65543, 300000])
+@pytest.mark.parametrize("n", [1, 5, 1023, 1024, 1025, 65543, 262144, 262145, 300000])
 @pytest.mark.parametrize("bits", [1, 2, 4, 8])
 def test_quantize_auto_scale_parity(T, ctx, n, bits):
     from paper_2509_19974_amd import tde
