@@ -258,6 +258,9 @@ __global__ void __launch_bounds__(1024) k_ntt_cols_inv(NttGroup g, const NttJob*
     extern __shared__ uint32_t L[];
     const NttJob& J = jobs[blockIdx.z];
     const int n1 = g.n1, ln1 = g.log_n1, wc = g.wc3;
+    // wc is a power of two: column and row of an index by mask and shift
+    // (an integer division per butterfly would cost more than the butterfly)
+    const int lwc = __builtin_ctz((unsigned)wc);
     const int b0 = blockIdx.x * wc;
     const int tot = wc * n1;
     const uint32_t nmask = ((uint32_t)n1 << 12) - 1u;
@@ -267,7 +270,7 @@ __global__ void __launch_bounds__(1024) k_ntt_cols_inv(NttGroup g, const NttJob*
         const uint32_t* W = J.res + (size_t)pr * ((size_t)n1 << 12);
         uint32_t* Lp = L + pr * tot;
         for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-            const int c = idx % wc, i = idx / wc;
+            const int c = idx & (wc - 1), i = idx >> lwc;
             const uint32_t k1 = brev((uint32_t)i, ln1);
             const uint32_t e = ((uint32_t)(b0 + c) * k1) & nmask;
             const uint32_t w = twiddle_n(T, n1, (0u - e) & nmask, p, pinv);
@@ -277,7 +280,7 @@ __global__ void __launch_bounds__(1024) k_ntt_cols_inv(NttGroup g, const NttJob*
         for (int lh = 0; lh < ln1; ++lh) {
             const int h = 1 << lh;
             for (int bi = threadIdx.x; bi < tot / 2; bi += blockDim.x) {
-                const int c = bi % wc, q = bi / wc;
+                const int c = bi & (wc - 1), q = bi >> lwc;
                 const int pos = q & (h - 1);
                 const int e = ((q >> lh) << (lh + 1)) + pos;
                 const uint32_t w = T[(n1 - (pos << (ln1 - 1 - lh))) & (n1 - 1)];
@@ -291,7 +294,7 @@ __global__ void __launch_bounds__(1024) k_ntt_cols_inv(NttGroup g, const NttJob*
     // scale, CRT, outputs
     Tri tr{INT64_MIN, INT64_MAX, 0};
     for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-        const int c = idx % wc, i = idx / wc;
+        const int c = idx & (wc - 1), i = idx >> lwc;
         const int64_t j = b0 + c + ((int64_t)i << 12);
         if (j < J.jlo || j > J.jhi) continue;
         const uint32_t a1 = mont(L[idx], g.scale_m[0], g.p[0], g.pinv[0]);
