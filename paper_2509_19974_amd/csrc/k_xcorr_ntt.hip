@@ -116,16 +116,40 @@ __global__ void __launch_bounds__(1024) k_ntt_cols_fwd(NttGroup g, const NttJob*
         L[idx] = val;
     }
     __syncthreads();
-    // decimation in frequency over i: half-distance h = n1/2 .. 1
-    for (int lh = ln1 - 1; lh >= 0; --lh) {
-        const int h = 1 << lh;
-        for (int bi = threadIdx.x; bi < tot / 2; bi += blockDim.x) {
+    // decimation in frequency over i: half-distance h = n1/2 .. 1, two
+    // stages per pass through LDS (h and h/2 on the four rows r0 = base +
+    // pos, r0 + h/2, r0 + h, r0 + 3h/2 of a 2h group: the same butterflies,
+    // twiddles and order as one stage at a time), then a last single stage
+    // when log2(n1) is odd
+    int lh = ln1 - 1;
+    for (; lh >= 1; lh -= 2) {
+        const int h = 1 << lh, h2 = h >> 1;
+        const int s1 = ln1 - 1 - lh;             // twiddle index shift of stage h (stage h/2: s1 + 1)
+        for (int bi = threadIdx.x; bi < tot / 4; bi += blockDim.x) {
             const int c = bi % kNttC1, q = bi / kNttC1;
-            const int pos = q & (h - 1);
-            const int e = ((q >> lh) << (lh + 1)) + pos;
-            const uint32_t a = L[e * kNttC1 + c], b = L[(e + h) * kNttC1 + c];
+            const int pos = q & (h2 - 1);
+            const int r0 = ((q >> (lh - 1)) << (lh + 1)) + pos;
+            uint32_t* x0 = &L[r0 * kNttC1 + c];
+            uint32_t* x1 = x0 + h2 * kNttC1;
+            uint32_t* x2 = x0 + h * kNttC1;
+            uint32_t* x3 = x2 + h2 * kNttC1;
+            const uint32_t a0 = *x0, a1 = *x1, a2 = *x2, a3 = *x3;
+            const uint32_t b0 = addm(a0, a2, p), b2 = mont(subm(a0, a2, p), T[pos << s1], p, pinv);
+            const uint32_t b1 = addm(a1, a3, p), b3 = mont(subm(a1, a3, p), T[(pos + h2) << s1], p, pinv);
+            const uint32_t w2 = T[pos << (s1 + 1)];
+            *x0 = addm(b0, b1, p);
+            *x1 = mont(subm(b0, b1, p), w2, p, pinv);
+            *x2 = addm(b2, b3, p);
+            *x3 = mont(subm(b2, b3, p), w2, p, pinv);
+        }
+        __syncthreads();
+    }
+    if (lh == 0) {
+        for (int bi = threadIdx.x; bi < tot / 2; bi += blockDim.x) {
+            const int c = bi % kNttC1, e = 2 * (bi / kNttC1);
+            const uint32_t a = L[e * kNttC1 + c], b = L[(e + 1) * kNttC1 + c];
             L[e * kNttC1 + c] = addm(a, b, p);
-            L[(e + h) * kNttC1 + c] = mont(subm(a, b, p), T[pos << (ln1 - 1 - lh)], p, pinv);
+            L[(e + 1) * kNttC1 + c] = mont(subm(a, b, p), T[0], p, pinv);
         }
         __syncthreads();
     }
@@ -277,16 +301,43 @@ __global__ void __launch_bounds__(1024) k_ntt_cols_inv(NttGroup g, const NttJob*
             Lp[idx] = mont(W[(size_t)b0 + c + ((size_t)i << 12)], w, p, pinv);
         }
         __syncthreads();
-        for (int lh = 0; lh < ln1; ++lh) {
+        // decimation in time, h = 1 .. n1/2, two stages per pass (h and 2h
+        // on the rows r0 = base + pos, r0 + h, r0 + 2h, r0 + 3h of a 4h
+        // group, the butterflies of one stage at a time in the same order),
+        // then a last single stage when log2(n1) is odd
+        int lh = 0;
+        for (; lh + 1 < ln1; lh += 2) {
             const int h = 1 << lh;
-            for (int bi = threadIdx.x; bi < tot / 2; bi += blockDim.x) {
+            const int s1 = ln1 - 1 - lh;         // stage h; stage 2h uses s1 - 1
+            for (int bi = threadIdx.x; bi < tot / 4; bi += blockDim.x) {
                 const int c = bi & (wc - 1), q = bi >> lwc;
                 const int pos = q & (h - 1);
-                const int e = ((q >> lh) << (lh + 1)) + pos;
-                const uint32_t w = T[(n1 - (pos << (ln1 - 1 - lh))) & (n1 - 1)];
-                const uint32_t a = Lp[e * wc + c], b = mont(Lp[(e + h) * wc + c], w, p, pinv);
-                Lp[e * wc + c] = addm(a, b, p);
-                Lp[(e + h) * wc + c] = subm(a, b, p);
+                const int r0 = ((q >> lh) << (lh + 2)) + pos;
+                uint32_t* x0 = &Lp[r0 * wc + c];
+                uint32_t* x1 = x0 + h * wc;
+                uint32_t* x2 = x1 + h * wc;
+                uint32_t* x3 = x2 + h * wc;
+                const uint32_t w1 = T[(n1 - (pos << s1)) & (n1 - 1)];
+                const uint32_t a0 = *x0, a1 = mont(*x1, w1, p, pinv), a2 = *x2, a3 = mont(*x3, w1, p, pinv);
+                const uint32_t b0 = addm(a0, a1, p), b1 = subm(a0, a1, p);
+                const uint32_t b2 = addm(a2, a3, p), b3 = subm(a2, a3, p);
+                const uint32_t t2 = mont(b2, T[(n1 - (pos << (s1 - 1))) & (n1 - 1)], p, pinv);
+                const uint32_t t3 = mont(b3, T[(n1 - ((pos + h) << (s1 - 1))) & (n1 - 1)], p, pinv);
+                *x0 = addm(b0, t2, p);
+                *x2 = subm(b0, t2, p);
+                *x1 = addm(b1, t3, p);
+                *x3 = subm(b1, t3, p);
+            }
+            __syncthreads();
+        }
+        if (lh == ln1 - 1) {
+            const int h = 1 << lh;
+            for (int bi = threadIdx.x; bi < tot / 2; bi += blockDim.x) {
+                const int c = bi & (wc - 1), pos = bi >> lwc;          // one group: e = pos
+                const uint32_t w = T[(n1 - pos) & (n1 - 1)];
+                const uint32_t a = Lp[pos * wc + c], b = mont(Lp[(pos + h) * wc + c], w, p, pinv);
+                Lp[pos * wc + c] = addm(a, b, p);
+                Lp[(pos + h) * wc + c] = subm(a, b, p);
             }
             __syncthreads();
         }
