@@ -16,6 +16,14 @@
 
 namespace tde {
 
+// blockIdx.z: pair; each thread clears one word of the pair's plane region.
+__global__ void __launch_bounds__(256) k_popc_zero(const XItem* items, XItem one) {
+    const XItem& it = items ? items[blockIdx.z] : one;
+    if (it.engine != TDE_PATH_POPC) return;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < it.plane_words) it.planes[k] = 0u;
+}
+
 __global__ void __launch_bounds__(256) k_popc_pack(const XItem* items, XItem one, int64_t max_words) {
     const XItem& it = items ? items[blockIdx.z] : one;
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -125,6 +133,8 @@ void popc_plan(XItem& it, void* ws) {
     uint32_t* usg = reinterpret_cast<uint32_t*>(base);
     uint32_t* vsg = reinterpret_cast<uint32_t*>(base + align_bytes(2 * L.nuw * 4));
     uint32_t* vnz = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(vsg) + align_bytes(L.vwords * 4));
+    it.planes = usg;
+    it.plane_words = (int64_t)(L.bytes / 4);
     it.usg = usg;
     it.unz = usg + L.nuw;
     it.vsg = vsg + L.pad_lo;
@@ -143,6 +153,14 @@ int launch_popc_pack(const XItem* items_dev, const XItem& one, int nitems, int64
     if (max_words == 0) return TDE_OK;
     hipLaunchKernelGGL(k_popc_pack, dim3((unsigned)ceil_div(max_words * 32, 256), 2, (unsigned)nitems), dim3(256),
                        0, s, items_dev, one, max_words);
+    TDE_HIP_CHECK(hipGetLastError());
+    return TDE_OK;
+}
+
+int launch_popc_zero(const XItem* items_dev, const XItem& one, int nitems, int64_t max_words, hipStream_t s) {
+    if (max_words == 0 || nitems == 0) return TDE_OK;
+    hipLaunchKernelGGL(k_popc_zero, dim3((unsigned)ceil_div(max_words, 256), 1, (unsigned)nitems), dim3(256), 0, s,
+                       items_dev, one);
     TDE_HIP_CHECK(hipGetLastError());
     return TDE_OK;
 }

@@ -819,7 +819,7 @@ struct BatchLaunch {
     int nwork = 0, nsegs = 0, n4 = 0;
     std::vector<std::pair<NttGroup, int64_t>> ngroups;   // (group, first job index)
     std::vector<int> ngroup_jobs;
-    std::vector<std::pair<size_t, size_t>> plane_zero;   // (offset, bytes) of bit-plane buffers
+    int64_t p_zero_words = 0;                             // largest bit-plane region (words)
 };
 
 void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* out, uint8_t* W, const BatchPlan& B,
@@ -904,7 +904,7 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
             L.p_tiles = std::max(L.p_tiles, it.ntiles);
             L.p_words = std::max(L.p_words, std::max(it.nuw, it.nvw));
             L.any_popc = true;
-            L.plane_zero.push_back({B.off_planes[i], popc_ws_bytes(it.p)});
+            L.p_zero_words = std::max(L.p_zero_words, it.plane_words);
         }
         if (!pp.fused) {
             ArgSeg sg{};
@@ -1004,10 +1004,8 @@ int batch_enqueue(tde_ctx* ctx, uint8_t* W, const BatchPlan& B, const BatchLaunc
     }
     if (L.any_popc) {
         // zero the plane buffers (padding must read as 0), then pack
-        for (const auto& z : L.plane_zero) {
-            rc = launch_zero(W + z.first, z.second, s);
-            if (rc) return rc;
-        }
+        rc = launch_popc_zero(items_dev, none, (int)L.np, L.p_zero_words, s);
+        if (rc) return rc;
         rc = launch_popc_pack(items_dev, none, (int)L.np, L.p_words, s);
         if (rc) return rc;
         rc = launch_xcorr_popc(items_dev, none, (int)L.np, L.p_split, L.p_tiles, s);

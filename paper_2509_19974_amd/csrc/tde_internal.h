@@ -227,6 +227,8 @@ struct XItem {
     const uint32_t* vnz;
     int64_t nuw;          // u words
     int64_t nvw;          // v words
+    uint32_t* planes;     // the pair's whole plane region (zeroed before packing)
+    int64_t plane_words;  // its size in 32-bit words
     // learned mode: the pair's proposal margin; at or above theta the result
     // comes from the nwin window triples, below it from the full range
     const float* margin;  // null outside learned mode
@@ -234,6 +236,9 @@ struct XItem {
     int32_t nwin;
     const ArgPart* win_parts;
 };
+
+// zero the bit-plane regions of a batch (one launch for every pair)
+int launch_popc_zero(const XItem* items_dev, const XItem& one, int nitems, int64_t max_words, hipStream_t s);
 
 // zero the r arrays of a batch
 int launch_zero_r(const XItem* items_dev, const XItem& one, int nitems, int64_t max_rbytes, hipStream_t s);
