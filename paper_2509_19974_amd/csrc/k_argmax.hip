@@ -98,6 +98,7 @@ __global__ void __launch_bounds__(256) k_argmax_partial(const ArgSeg* segs, int 
 
 __global__ void __launch_bounds__(256) k_argmax_final(const ArgSeg* segs, int nseg, ArgSeg one,
                                                       const ArgPart* parts) {
+    (void)nseg;                      // the grid has one workgroup per segment
     const ArgSeg& s = segs ? segs[blockIdx.x] : one;
     Tri t{kNone, INT64_MAX, 0};
     for (int k = threadIdx.x; k < s.nparts; k += blockDim.x) {

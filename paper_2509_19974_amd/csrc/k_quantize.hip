@@ -150,6 +150,7 @@ __device__ __forceinline__ double wave_tree_sum(const double* gsum, int64_t n) {
 // Also zeroes the statistics that the quantize kernel accumulates.
 __global__ void __launch_bounds__(256) k_scale_finalize(const QSig* sigs, int nsig, QSig one, int* zero_me,
                                                         int nzero) {
+    (void)nsig;                      // the grid has one workgroup per signal
     const QSig& s = sigs ? sigs[blockIdx.x] : one;
     const int t = threadIdx.x;
     // scratch counters of a later kernel of the same call start at zero
@@ -249,8 +250,7 @@ __device__ __forceinline__ T wave_sum(T v) {
 // fused != 0: every block takes its signal's scale from the block sums itself
 // (signals of 1 .. kFuseMaxN samples), and the first block of each signal
 // publishes it.
-__global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QSig one,
-                                                  int64_t total_blocks, int fused) {
+__global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QSig one, int fused) {
     const int64_t blk = blockIdx.x;
     int64_t lb;
     // a copy: the stores below could alias the descriptor array, which
@@ -447,8 +447,7 @@ int launch_quantize(const QSig* sigs_dev, const QSig& one, int nsig, int64_t tot
     if (!fused &&
         (need_scale || sigs_dev != nullptr || one.stat != nullptr || one.inv_out != nullptr || zero_me != nullptr))
         hipLaunchKernelGGL(k_scale_finalize, dim3(nsig), dim3(256), 0, s, sigs_dev, nsig, one, zero_me, nzero);
-    hipLaunchKernelGGL(k_quantize, dim3((unsigned)total_blocks), dim3(256), 0, s, sigs_dev, nsig, one,
-                       total_blocks, fused);
+    hipLaunchKernelGGL(k_quantize, dim3((unsigned)total_blocks), dim3(256), 0, s, sigs_dev, nsig, one, fused);
     if (write_flags)
         hipLaunchKernelGGL(k_quantize_flags, dim3((unsigned)ceil_div(nsig, 256)), dim3(256), 0, s, sigs_dev, nsig,
                            one);

@@ -850,6 +850,7 @@ __global__ void k_zero_counters(int* c, int n) {
 // (their correlation is 0) and write the peak.
 __global__ void __launch_bounds__(64) k_tiles_final(const XItem* items, XItem one, int npairs,
                                                     const ArgPart* tile_parts) {
+    (void)npairs;                    // the grid has one workgroup per pair
     const int pi = blockIdx.x;
     const XItem& it = items ? items[pi] : one;
     if (!it.fused) return;
@@ -1081,7 +1082,6 @@ static_assert(kernel_lds<4>() >= MCfg<8>::TLW * 4, "FP 8-block reduction area");
 template <int MB>
 static int launch_mb(const XItem* items_dev, const MWork* work, int nwork, int* counter, ArgPart* tile_parts,
                      int num_cu, hipStream_t s) {
-    using C = MCfg<MB>;
     if (nwork == 0) return TDE_OK;
     static int per_cu = 0;
     if (per_cu == 0) {

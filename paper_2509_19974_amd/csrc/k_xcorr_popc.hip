@@ -25,6 +25,7 @@ __global__ void __launch_bounds__(256) k_popc_zero(const XItem* items, XItem one
 }
 
 __global__ void __launch_bounds__(256) k_popc_pack(const XItem* items, XItem one, int64_t max_words) {
+    (void)max_words;                 // sizes the grid; each pair stops at its own words
     const XItem& it = items ? items[blockIdx.z] : one;
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (it.engine != TDE_PATH_POPC) return;

@@ -217,7 +217,7 @@ int time_engine(tde_ctx* ctx, TuneBufs& B, int64_t N, int bits, int64_t half, in
         q.lag_hi = half;
         q.bits = bits;
     }
-    tde_opts o{TDE_MODE_FULL, e, 0, 0};
+    tde_opts o{TDE_MODE_FULL, e, 0, 0, nullptr, 0.f, TDE_QUANT_UNIFORM};
     const size_t need = tde_estimate_workspace_size(pairs.data(), P, &o);
     if (need == 0) return set_error(TDE_ERR_ARG, "tde_tune: cannot plan bucket");
     if (need > B.ws_bytes) {
