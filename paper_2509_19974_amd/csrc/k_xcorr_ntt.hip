@@ -122,7 +122,43 @@ __global__ void __launch_bounds__(1024) k_ntt_cols_fwd(NttGroup g, const NttJob*
     // twiddles and order as one stage at a time), then a last single stage
     // when log2(n1) is odd
     int lh = ln1 - 1;
-    for (; lh >= 1; lh -= 2) {
+    // three stages per pass (h, h/2, h/4 on the eight rows base + pos +
+    // k h/4 of a 2h group) while at least three remain
+    for (; lh >= 2; lh -= 3) {
+        const int h4 = 1 << (lh - 2);
+        const int s1 = ln1 - 1 - lh;
+        for (int bi = threadIdx.x; bi < tot / 8; bi += blockDim.x) {
+            const int c = bi % kNttC1, q = bi / kNttC1;
+            const int pos = q & (h4 - 1);
+            uint32_t* x0 = &L[(((q >> (lh - 2)) << (lh + 1)) + pos) * kNttC1 + c];
+            uint32_t x[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) x[k] = x0[k * h4 * kNttC1];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {                  // stage h
+                const uint32_t a = x[k], b = x[k + 4];
+                x[k] = addm(a, b, p);
+                x[k + 4] = mont(subm(a, b, p), T[(pos + k * h4) << s1], p, pinv);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; k += (k & 1) ? 3 : 1) {  // stage h/2: k = 0, 1, 4, 5
+                const uint32_t a = x[k], b = x[k + 2];
+                x[k] = addm(a, b, p);
+                x[k + 2] = mont(subm(a, b, p), T[(pos + (k & 1) * h4) << (s1 + 1)], p, pinv);
+            }
+            const uint32_t w3 = T[pos << (s1 + 2)];
+#pragma unroll
+            for (int k = 0; k < 8; k += 2) {                // stage h/4
+                const uint32_t a = x[k], b = x[k + 1];
+                x[k] = addm(a, b, p);
+                x[k + 1] = mont(subm(a, b, p), w3, p, pinv);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) x0[k * h4 * kNttC1] = x[k];
+        }
+        __syncthreads();
+    }
+    if (lh == 1) {
         const int h = 1 << lh, h2 = h >> 1;
         const int s1 = ln1 - 1 - lh;             // twiddle index shift of stage h (stage h/2: s1 + 1)
         for (int bi = threadIdx.x; bi < tot / 4; bi += blockDim.x) {
@@ -143,6 +179,7 @@ __global__ void __launch_bounds__(1024) k_ntt_cols_fwd(NttGroup g, const NttJob*
             *x3 = mont(subm(b2, b3, p), w2, p, pinv);
         }
         __syncthreads();
+        lh -= 2;
     }
     if (lh == 0) {
         for (int bi = threadIdx.x; bi < tot / 2; bi += blockDim.x) {
@@ -306,7 +343,45 @@ __global__ void __launch_bounds__(1024) k_ntt_cols_inv(NttGroup g, const NttJob*
         // group, the butterflies of one stage at a time in the same order),
         // then a last single stage when log2(n1) is odd
         int lh = 0;
-        for (; lh + 1 < ln1; lh += 2) {
+        // three stages per pass (h, 2h, 4h on the eight rows base + pos +
+        // k h of an 8h group) while at least three remain
+        for (; lh + 2 < ln1; lh += 3) {
+            const int h = 1 << lh;
+            const int s1 = ln1 - 1 - lh;
+            for (int bi = threadIdx.x; bi < tot / 8; bi += blockDim.x) {
+                const int c = bi & (wc - 1), q = bi >> lwc;
+                const int pos = q & (h - 1);
+                uint32_t* x0 = &Lp[(((q >> lh) << (lh + 3)) + pos) * wc + c];
+                uint32_t x[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) x[k] = x0[k * h * wc];
+                const uint32_t w1 = T[(n1 - (pos << s1)) & (n1 - 1)];
+#pragma unroll
+                for (int k = 0; k < 8; k += 2) {            // stage h
+                    const uint32_t a = x[k], b = mont(x[k + 1], w1, p, pinv);
+                    x[k] = addm(a, b, p);
+                    x[k + 1] = subm(a, b, p);
+                }
+#pragma unroll
+                for (int k = 0; k < 8; k += (k & 1) ? 3 : 1) {  // stage 2h: k = 0, 1, 4, 5
+                    const uint32_t w = T[(n1 - ((pos + (k & 1) * h) << (s1 - 1))) & (n1 - 1)];
+                    const uint32_t a = x[k], b = mont(x[k + 2], w, p, pinv);
+                    x[k] = addm(a, b, p);
+                    x[k + 2] = subm(a, b, p);
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {                // stage 4h
+                    const uint32_t w = T[(n1 - ((pos + k * h) << (s1 - 2))) & (n1 - 1)];
+                    const uint32_t a = x[k], b = mont(x[k + 4], w, p, pinv);
+                    x[k] = addm(a, b, p);
+                    x[k + 4] = subm(a, b, p);
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) x0[k * h * wc] = x[k];
+            }
+            __syncthreads();
+        }
+        if (lh + 1 < ln1) {
             const int h = 1 << lh;
             const int s1 = ln1 - 1 - lh;         // stage h; stage 2h uses s1 - 1
             for (int bi = threadIdx.x; bi < tot / 4; bi += blockDim.x) {
@@ -329,6 +404,7 @@ __global__ void __launch_bounds__(1024) k_ntt_cols_inv(NttGroup g, const NttJob*
                 *x3 = subm(b1, t3, p);
             }
             __syncthreads();
+            lh += 2;
         }
         if (lh == ln1 - 1) {
             const int h = 1 << lh;
