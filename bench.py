@@ -460,7 +460,7 @@ def main():
         print(json.dumps({"copy_bytes": n, "launches": 3}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); "
               "the pairs of a batch are independent and would be split across GPUs by predicted cost",
               file=sys.stderr)
         sys.exit(2)

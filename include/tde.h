@@ -53,7 +53,7 @@ extern "C" {
 #define TDE_ERR_RANGE       -2   /* int32 result cannot hold the exact value */
 #define TDE_ERR_WS          -3   /* workspace missing or too small */
 #define TDE_ERR_HIP         -4   /* a HIP runtime call failed */
-#define TDE_ERR_UNSUPPORTED -5   /* valid request this build does not handle */
+#define TDE_ERR_UNSUPPORTED -5   /* valid request the library does not handle */
 #define TDE_ERR_IO          -6   /* file read/write failed (models) */
 
 /* r_dtype values */

@@ -7,7 +7,7 @@ with the HIP library (``paper_2509_19974_amd``) and never imports it.
 What it computes is the plain definition of each step, written out:
 
 * ``sumsq_pairwise`` / ``inv_step`` -- the per-signal scale of the uniform
-  quantizer (the paper leaves the quantizer free, Section 3.2; this build fixes
+  quantizer (the paper leaves the quantizer free, Section 3.2; the library fixes
   a symmetric mid-tread quantizer on [-3 sigma, 3 sigma] and a pairwise
   float64 sum of squares over a fixed binary tree so that two implementations
   agree bit for bit).
