@@ -1,8 +1,8 @@
 #!/usr/bin/env python3
 """Throughput of the exact integer time-difference estimator on one MI355X.
 
-One step = one call of tde_estimate_batch over the whole batch (Algorithm 1,
-lines 1-4 for every pair: scale + quantize, exact integer correlation over the
+One step = one call of tde_estimate_batch over the whole batch (Algorithm 1
+up to its argmax step for every pair: scale + quantize, exact integer correlation over the
 full lag range, argmax), with the float32 inputs already resident in HBM. By
 default the call is replayed from its captured HIP graph (use_graph = 1: the
 descriptors stay in the workspace, so a step is only kernel launches);
@@ -175,7 +175,7 @@ def cpu_baseline(pairs, budget_s: float = 12.0):
             break
     el = time.perf_counter() - t0
     return {"value": done / el, "unit": "pairs/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{done} pairs of the {len(pairs)}-pair batch, each the full Algorithm 1 lines 1-4 "
+            "sample": f"{done} pairs of the {len(pairs)}-pair batch, each Algorithm 1 up to its argmax step "
                       f"(scale, quantize, int64 direct sums over every lag, argmax), {el:.1f} s",
             "int_mac_per_s": macs / el}
 
@@ -306,7 +306,7 @@ def run_quant(args):
     """Quantizer study: a synthetic analogue of the accuracy-vs-SNR experiment
     of Section 4.2 (speech-like 16000-sample targets delayed by a real
     nu in [0, 64000) inside 80000-sample AR(1) backgrounds). For each SNR:
-    the FP32 FFT correlation, and Algorithm 1 lines 1-4 and lines 1-6 with
+    the FP32 FFT correlation, and Algorithm 1 without and with its tie-refinement step, with
     the uniform map at b in {1, 2, 4, 8} and the mu-law and Lloyd-Max maps at
     b in {2, 4}. An estimate is correct when every lag of the (refined)
     argmax set is within one sample of nu."""
@@ -348,7 +348,7 @@ def run_quant(args):
                 r = specs[i]["r_out"].cpu().numpy()
                 tied = np.nonzero(r == r.max())[0] + lo
                 ok4 += bool(np.all(np.abs(tied - nus[i]) < 1.0))
-                # Algorithm 1, lines 5-6: the real correlation at the tied lags
+                # Algorithm 1, tie-refinement step: the real correlation at the tied lags
                 peak = out[24 * i:24 * (i + 1)].clone()
                 ctx.refine(specs[i]["x"], specs[i]["y"], specs[i]["r_out"], lo, hi, peak)
                 torch.cuda.synchronize()

@@ -11,9 +11,8 @@
  *                          phi(0) = psi(0) = 0, the correlation of phi(x) and
  *                          psi(y) peaks at the same tau as that of x and y when
  *                          x[m] = a y[m + nu] (Eq. (2)).
- *   Algorithm 1:           quantize both signals to integers (line 2), compute
- *                          the integer correlation exactly (line 3), take its
- *                          argmax (line 4).
+ *   Algorithm 1:           quantize both signals to integers, compute the
+ *                          integer correlation exactly, take its argmax.
  *
  * Lag convention (Eqs. (1)-(2)): if y is x delayed by d samples,
  * y[n] = x[n - d], the correlation peaks at tau = +d. Output arrays hold
@@ -79,7 +78,7 @@ extern "C" {
 
 typedef struct tde_ctx tde_ctx;
 
-/* Algorithm 1, line 4, reported for one pair: the smallest maximising lag,
+/* Algorithm 1, argmax step, reported for one pair: the smallest maximising lag,
  * the maximum, and the size of the argmax set (Remark 1: the quantized
  * correlation can have several peaks, the true shift always among them). */
 typedef struct {
@@ -111,7 +110,7 @@ const char* tde_last_error(void);
 
 /* --------------------------------------------------------- quantize -- */
 
-/* Algorithm 1, lines 1-2: monotone integer maps phi with phi(0) = 0.
+/* Algorithm 1, quantization step: monotone integer maps phi with phi(0) = 0.
  *
  * x[n] (device, float32) -> q[n] (device, int8).
  *  bits = 1: sign with sign(0) = 0 (Section 4.2), decided from the IEEE bits:
@@ -163,7 +162,7 @@ int tde_quantizer_thresholds(int quantizer, int bits, float* out);
 
 /* ------------------------------------------------------ correlation -- */
 
-/* Algorithm 1, line 3 (Eq. (1) on integer sequences), exact:
+/* Algorithm 1, correlation step (Eq. (1) on integer sequences), exact:
  *   r[i] = sum_m u[m] v[m + tau],  tau = lag_lo + i,  i in [0, lag_hi - lag_lo],
  * with u on [0, nu) and v on [0, nv), zero elsewhere (finite-length signals,
  * Section 2.2). u and v (device, int8) hold codes with |u| <= kmax_u and
@@ -196,14 +195,14 @@ int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, in
                   int kmax_u, int kmax_v, int64_t lag_lo, int64_t lag_hi,
                   void* r, int r_dtype, int path, void* ws, size_t ws_bytes, void* stream);
 
-/* Algorithm 1, line 4: over r[0 .. lag_hi-lag_lo] (device, r_dtype), writes
+/* Algorithm 1, argmax step: over r[0 .. lag_hi-lag_lo] (device, r_dtype), writes
  * *out (device) = {smallest tau with r = max, max, number of maximisers, 0}.
  * Errors: TDE_ERR_ARG. ws: tde_argmax_workspace_size(lag_hi-lag_lo+1). */
 size_t tde_argmax_workspace_size(int64_t nlags);
 int tde_argmax_lag(tde_ctx* ctx, const void* r, int r_dtype, int64_t lag_lo, int64_t lag_hi,
                    tde_peak* out, void* ws, size_t ws_bytes, void* stream);
 
-/* Algorithm 1, lines 5-6: if *peak (device, from tde_argmax_lag or a batch
+/* Algorithm 1, tie-refinement step: if *peak (device, from tde_argmax_lag or a batch
  * call with r_out) has n_ties > 1, the real correlation (Eq. (1) on the float
  * signals x, y (device)) is evaluated at the tied lags of r (device, the
  * lags [lag_lo, lag_hi] in r_dtype) and *peak becomes {smallest lag of the
@@ -224,9 +223,9 @@ int tde_refine_ties(tde_ctx* ctx, const float* x, int64_t nx, const float* y, in
 
 /* Correlation of a stream against a template, block by block (overlap-save):
  * the extension to long and streaming signals that Section 5 names as future
- * work, built from Algorithm 1 lines 2-4. The template x (device float32, nx
- * samples) is quantized once with bits in {1,2,4,8} at inv_step_x (0: its own
- * scale, Algorithm 1 line 2 as in tde_quantize); every stream block is
+ * work, built from the steps of Algorithm 1 from quantization to argmax. The
+ * template x (device float32, nx samples) is quantized once with bits in
+ * {1,2,4,8} at inv_step_x (0: its own scale, as in tde_quantize); every stream block is
  * quantized at the one fixed scale inv_step_y (> 0; ignored for bits = 1), so
  * the stream's codes are those of the concatenation. With u the template's
  * codes and v the stream's, zero outside [0, T) for T samples pushed,
@@ -323,7 +322,7 @@ typedef struct {
  * context whose workspace overlaps it drops the cached graph. Stage timing
  * is not recorded for graph launches. */
 
-/* Algorithm 1, lines 1-4 for every pair of pairs_host[0..npairs) (host array):
+/* Algorithm 1 up to its argmax step for every pair of pairs_host[0..npairs) (host array):
  * quantize x and y, correlate exactly, and write out[i] (device) for pair i.
  * Pairs may differ in length, lag range and bits. Errors: TDE_ERR_ARG for an
  * invalid pair (the message names it), TDE_ERR_RANGE if a requested int32 r
@@ -335,7 +334,7 @@ int tde_estimate_batch(tde_ctx* ctx, const tde_pair* pairs_host, int64_t npairs,
 /* ------------------------------------------------------ learned model -- */
 
 /* Learned lag-window proposer. Not part of the paper: it only chooses where
- * Algorithm 1's exact correlation (line 3) is evaluated, and the full lag
+ * Algorithm 1's exact correlation step is evaluated, and the full lag
  * range remains the fallback, so results stay exact. Architecture (fixed):
  *   input   xd[t] = bf16(mean of x[16t .. 16t+15] / sigma), t < ld, with
  *           sigma = sqrt(S/n) of the quantizer scale (Section on the scale in

@@ -11,19 +11,20 @@ What it computes is the plain definition of each step, written out:
   a symmetric mid-tread quantizer on [-3 sigma, 3 sigma] and a pairwise
   float64 sum of squares over a fixed binary tree so that two implementations
   agree bit for bit).
-* ``quantize`` -- Algorithm 1, line 2: monotone integer maps with phi(0) = 0;
+* ``quantize`` -- Algorithm 1, quantization step: monotone integer maps with phi(0) = 0;
   sign with sign(0) = 0 (Section 4.2) for bits = 1.
 * ``quantize_nonuniform``, ``mulaw_thresholds``, ``lloyd_max_gauss`` --
   non-uniform maps for b in {2, 4} (Section 3.2 allows any quantizer with
   integer range; Section 5 names better quantizers as future work): the
   cell boundaries of mu-law companding and of the Lloyd-Max quantizer of a
   unit Gaussian, the code being the cell index.
-* ``xcorr`` / ``xcorr_at`` -- Algorithm 1, line 3: Eq. (1) on the integer
+* ``xcorr`` / ``xcorr_at`` -- Algorithm 1, correlation step: Eq. (1) on the integer
   sequences, int64 direct sums.
-* ``argmax`` -- Algorithm 1, line 4: maximum, smallest maximising lag and the
+* ``argmax`` -- Algorithm 1, argmax step: maximum, smallest maximising lag and the
   number of maximisers (Remark 1).
 * ``xcorr_f64_at`` -- Eq. (1) on the unquantized signals in float64.
-* ``estimate`` / ``estimate_refined`` -- Algorithm 1 lines 1-4, and 1-6.
+* ``estimate`` / ``estimate_refined`` -- Algorithm 1 without, and with, its
+  tie-refinement step.
 * ``stream`` -- correlation of a stream against a template, block by block
   (the streaming extension named as future work in Section 5): the plain
   correlation of Eq. (1) over the concatenated stream, cut into the lags each
@@ -141,7 +142,7 @@ def inv_step(x, bits: int) -> float:
 # ------------------------------------------------------------- quantize ----
 
 def quantize(x, bits: int, inv_step_value: float | None = None):
-    """Algorithm 1, line 2. Returns (q int8, n_nonfinite, inv_step used)."""
+    """Algorithm 1, quantization step. Returns (q int8, n_nonfinite, inv_step used)."""
     x = _f32(x)
     if bits not in (1, 2, 4, 8):
         raise ValueError("bits must be 1, 2, 4 or 8")
@@ -220,7 +221,7 @@ def nonuniform_table(kind: int, bits: int) -> np.ndarray:
 
 
 def quantize_nonuniform(x, bits: int, kind: int, inv_step_value: float | None = None):
-    """Algorithm 1, line 2 with a non-uniform monotone map (kind 1 or 2; bits
+    """Algorithm 1, quantization step with a non-uniform monotone map (kind 1 or 2; bits
     1 is sign for every kind). Returns (q int8, n_nonfinite, inv_step used)."""
     x = _f32(x)
     if bits == 1 or kind == 0:
@@ -267,7 +268,7 @@ def xcorr_at(u, v, lags) -> np.ndarray:
 
 
 def argmax(r, lag_lo: int):
-    """Algorithm 1, line 4: (smallest maximising lag, max value, #maximisers)."""
+    """Algorithm 1, argmax step: (smallest maximising lag, max value, #maximisers)."""
     r = np.ascontiguousarray(r, dtype=np.int64)
     if r.size == 0:
         raise ValueError("empty lag range")
@@ -291,7 +292,7 @@ def xcorr_f64_at_pairwise(x, y, lags) -> np.ndarray:
     the products x[m] y[m + tau] (exact in float64) over the overlap, in
     ascending m, zero-padded to a power-of-two length and added as a binary
     tree (adjacent pairs, level by level). Used for the tie refinement of
-    Algorithm 1 (lines 5-6), so that the choice between tied lags is made in
+    Algorithm 1, tie-refinement step, so that the choice between tied lags is made in
     the same arithmetic on every implementation."""
     x = np.asarray(_f32(x), dtype=np.float64)
     y = np.asarray(_f32(y), dtype=np.float64)
@@ -323,7 +324,7 @@ def overlap_count(nu: int, nv: int, tau: int) -> int:
 
 def estimate(x, y, bits: int, lag_lo: int, lag_hi: int,
              inv_step_x: float | None = None, inv_step_y: float | None = None):
-    """Algorithm 1, lines 1-4. Returns a dict with lag, rmax, n_ties, r, q's."""
+    """Algorithm 1 up to its argmax step. Returns a dict with lag, rmax, n_ties, r, q's."""
     u, nfx, sx = quantize(x, bits, inv_step_x)
     v, nfy, sy = quantize(y, bits, inv_step_y)
     r = xcorr(u, v, lag_lo, lag_hi)
@@ -334,7 +335,7 @@ def estimate(x, y, bits: int, lag_lo: int, lag_hi: int,
 
 def estimate_refined(x, y, bits: int, lag_lo: int, lag_hi: int,
                      inv_step_x: float | None = None, inv_step_y: float | None = None):
-    """Algorithm 1, lines 1-6: ties of the integer correlation are resolved by
+    """Algorithm 1 with its tie-refinement step: ties of the integer correlation are resolved by
     the float64 correlation of the unquantized signals (fixed pairwise
     summation order), evaluated only at the tied lags. Returns the refined
     argmax set (sorted) and the line-4 result."""
@@ -358,7 +359,7 @@ def stream(x, blocks, bits: int, inv_step_y: float, inv_step_x: float | None = N
 
     The template is quantized once (its own scale, or inv_step_x); the stream
     with one fixed scale inv_step_y for every block, so the quantized stream
-    is the quantization of the concatenation (Algorithm 1, line 2, one
+    is the quantization of the concatenation (Algorithm 1, quantization step, one
     monotone map). Lags follow Eq. (1) with u = template codes and v = stream
     codes: r[tau] = sum_m u[m] v[m + tau], v zero outside the stream. After a
     push that brings the stream to T samples, the lags tau <= T - nx are
@@ -366,7 +367,7 @@ def stream(x, blocks, bits: int, inv_step_y: float, inv_step_x: float | None = N
     samples makes B new lags final, and the finishing step the last nx - 1
     lags [T - nx + 1, T - 1] (zero beyond the end). Returns one record per
     push and one for the finish: the lags, their r, the argmax of those lags
-    and the running argmax over every final lag so far (Algorithm 1, line 4,
+    and the running argmax over every final lag so far (Algorithm 1, argmax step,
     smallest lag on ties)."""
     x = _f32(x)
     nx = x.size

@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE ONLY (same rule as the rest of ``oracle``): only
 use it; it shares no code with the HIP library.
 
 The proposer is not part of the paper; it narrows the lag range on which the
-paper's exact integer correlation (Algorithm 1, line 3) is evaluated. The
+paper's exact integer correlation (Algorithm 1, correlation step) is evaluated. The
 network, written out:
 
 * input: each signal of N = 16 Ld samples is reduced to Ld block means of 16

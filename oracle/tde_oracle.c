@@ -9,14 +9,14 @@
  * states it, with no blocking or reordering:
  *   - the cross-correlation (x * y)[n] = sum_m x[m] y[m+n] of two finite-length
  *     sequences (Section 2.2, Eq. (1));
- *   - Algorithm 1, line 2: integer-valued monotone maps phi, psi with
+ *   - Algorithm 1, quantization step: integer-valued monotone maps phi, psi with
  *     phi(0) = psi(0) = 0 (sign with sign(0) = 0 as in Section 4.2, or a
  *     symmetric mid-tread uniform quantizer on [-3 sigma, 3 sigma]);
- *   - Algorithm 1, line 3: w = u * v, accumulated in int64;
- *   - Algorithm 1, line 4: the argmax set, reported as its smallest element,
+ *   - Algorithm 1, correlation step: w = u * v, accumulated in int64;
+ *   - Algorithm 1, argmax step: the argmax set, reported as its smallest element,
  *     the maximum and the size of the set (Remark 1: ties are legitimate).
  *   - the real-valued correlation of the unquantized signals in float64,
- *     summed in ascending m (used by Algorithm 1, lines 5-6).
+ *     summed in ascending m (used by Algorithm 1, tie-refinement step).
  *
  * Plain C, compiled without fast-math: every float operation below is one
  * correctly rounded IEEE-754 operation.
@@ -76,7 +76,7 @@ float oracle_inv_step_from_sumsq(double S, int64_t n, int bits) {
 
 static uint32_t f32_bits(float f) { uint32_t b; memcpy(&b, &f, 4); return b; }
 
-/* Algorithm 1, line 2. Returns the number of non-finite samples.
+/* Algorithm 1, quantization step. Returns the number of non-finite samples.
  * bits == 1: sign from the IEEE bits: +1 for positive non-zero (including
  *   +Inf), -1 for negative non-zero (including -Inf), 0 for +-0 and NaN.
  * bits in {2,4,8}: K = 2^(b-1)-1, t = fl32(x * inv_step), q = clamp(rne(t),
@@ -136,7 +136,7 @@ void oracle_xcorr_i64_at(const int8_t* u, int64_t nu, const int8_t* v, int64_t n
     for (int64_t i = 0; i < nlags; ++i) r[i] = xcorr_one(u, nu, v, nv, lags[i]);
 }
 
-/* Algorithm 1, line 4 over r[0..L): the maximum, the smallest maximising lag
+/* Algorithm 1, argmax step over r[0..L): the maximum, the smallest maximising lag
  * and the number of maximisers. */
 void oracle_argmax_i64(const int64_t* r, int64_t L, int64_t lag_lo,
                        int64_t* lag, int64_t* rmax, int64_t* nties) {
@@ -151,7 +151,7 @@ void oracle_argmax_i64(const int64_t* r, int64_t L, int64_t lag_lo,
 }
 
 /* Eq. (1) on the unquantized float signals, in float64, summed in ascending
- * m. Used for the refinement of tied lags (Algorithm 1, lines 5-6) and for the
+ * m. Used for the refinement of tied lags (Algorithm 1, tie-refinement step) and for the
  * accuracy of the plain real correlation. */
 void oracle_xcorr_f64_at(const float* x, int64_t nx, const float* y, int64_t ny,
                          const int64_t* lags, int64_t nlags, double* r) {

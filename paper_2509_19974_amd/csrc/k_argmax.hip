@@ -1,4 +1,4 @@
-// Algorithm 1, line 4: the argmax of the integer correlation, reported as the
+// Algorithm 1, argmax step: the argmax of the integer correlation, reported as the
 // smallest maximising lag, the maximum and the number of maximisers (Remark 1:
 // the quantized correlation may have several peaks).
 //

@@ -1,6 +1,6 @@
 // Learned lag-window proposer (not part of the paper): a small 1-D CNN over
 // decimated signals whose feature cross-correlation scores coarse lag bins,
-// so that the exact integer correlation of Algorithm 1 (line 3) is evaluated
+// so that the exact integer correlation (Algorithm 1, correlation step) is evaluated
 // only inside the best bins.
 //
 //   input   xd[t] = bf16(mean of x[16t .. 16t+15] / sigma), t < Ld

@@ -1,4 +1,4 @@
-// Algorithm 1, lines 1-2: per-signal scale and monotone integer quantization.
+// Algorithm 1, quantization step: per-signal scale and monotone integer quantization.
 //
 // Scale: S = sum of x^2 over finite samples, every square exact in float64,
 // summed in float64 over a fixed binary tree (zero-padded to a power-of-two

@@ -1,4 +1,4 @@
-// Algorithm 1, lines 5-6: when the integer correlation has several maximising
+// Algorithm 1, tie-refinement step: when the integer correlation has several maximising
 // lags (Remark 1), the real-valued correlation (Eq. (1) on the unquantized
 // signals) decides among them. The products x[m] y[m + tau] are exact in
 // float64; they are added over a fixed binary tree (ascending m, zero-padded

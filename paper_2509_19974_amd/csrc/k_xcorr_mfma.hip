@@ -1,6 +1,6 @@
-// Algorithm 1, line 3 (Eq. (1) on integer codes), exact, on the int8 matrix
+// Algorithm 1, correlation step (Eq. (1) on integer codes), exact, on the int8 matrix
 // cores of gfx950 (v_mfma_i32_32x32x32_i8, int32 accumulation), with the
-// argmax of line 4 taken on chip.
+// argmax step taken on chip.
 //
 // The correlation r[tau] = sum_m u[m] v[m + tau] is a product of a Hankel
 // and a Toeplitz matrix. A lag tile is 1024*MB consecutive lags

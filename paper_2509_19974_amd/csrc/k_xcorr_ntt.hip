@@ -1,4 +1,4 @@
-// Algorithm 1, line 3 for long signals: the exact integer correlation as a
+// Algorithm 1, correlation step for long signals: the exact integer correlation as a
 // cyclic convolution computed with number-theoretic transforms modulo one or
 // two primes, combined by the Chinese remainder theorem (the multimodular
 // route among the exact multiplication methods of Section 3.2).

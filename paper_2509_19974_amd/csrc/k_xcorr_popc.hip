@@ -1,4 +1,4 @@
-// Algorithm 1, line 3 for ternary codes (sign quantization with sign(0) = 0,
+// Algorithm 1, correlation step for ternary codes (sign quantization with sign(0) = 0,
 // Section 4.2), exact, on bit planes.
 //
 // Each code c in {-1, 0, +1} is two bits: nz = (c != 0) and sg = (c < 0). A

@@ -1,4 +1,4 @@
-// Algorithm 1, line 3 restricted to proposed lag windows: the exact integer
+// Algorithm 1, correlation step restricted to proposed lag windows: the exact integer
 // correlation r[tau] = sum_m u[m] v[m + tau] (Eq. (1)) over one window of 256
 // consecutive lags per workgroup, on the int8 matrix cores
 // (v_mfma_i32_16x16x64_i8, int32 accumulation), with the window's

@@ -98,7 +98,7 @@ __device__ __forceinline__ Packed16<W> fp_pack16(uint4 x) {
 inline int kmax_of_bits(int bits) { return bits == 1 ? 1 : (1 << (bits - 1)) - 1; }
 
 // ------------------------------------------------------------ quantize --
-// One signal to quantize (Algorithm 1, line 2).
+// One signal to quantize (Algorithm 1, quantization step).
 struct QSig {
     const float* x;
     int64_t n;
@@ -297,7 +297,7 @@ int launch_copy_bytes(void* dst, const void* src, size_t n, hipStream_t s);
 int launch_xcorr_win(const XItem* items_dev, int npairs, const int32_t* top, const float* margin, float theta,
                      int topk, int nb, ArgPart* parts, hipStream_t s);
 
-// tie refinement (Algorithm 1, lines 5-6)
+// tie refinement (Algorithm 1, tie-refinement step)
 int launch_refine(const float* x, int64_t nx, const float* y, int64_t ny, const void* r, int dtype, int64_t lag_lo,
                   int64_t L, tde_peak* peak, int max_ties, int64_t* lags, double* vals, int* count, hipStream_t s);
 

@@ -1,6 +1,6 @@
 // Correlation of a stream against a template, block by block (overlap-save):
 // the extension to long and streaming signals that Section 5 names as future
-// work, assembled from Algorithm 1 lines 2-4.
+// work, assembled from the steps of Algorithm 1 from quantization to argmax.
 //
 // The stream's codes live in two alternating buffers laid out as
 //     [ last nx - 1 codes of the stream | the call's n new codes ]

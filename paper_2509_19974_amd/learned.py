@@ -1,7 +1,7 @@
 """Training and evaluation helpers for the learned lag-window proposer.
 
-The proposer (tde_model) only decides where the exact correlation of
-Algorithm 1 (line 3) runs; its labels come from the plain method itself: the
+The proposer (tde_model) only decides where the exact correlation
+(the correlation step of Algorithm 1) runs; its labels come from the plain method itself: the
 exact full-range argmax of the integer correlation, mapped to the 256-lag
 bin that holds it. Everything numeric runs in libtde (quantize, exact
 correlation, the CNN's forward/backward/Adam); this module only sequences the

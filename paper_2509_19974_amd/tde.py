@@ -468,7 +468,7 @@ class Context:
         return out
 
     def refine(self, x, y, r, lag_lo, lag_hi, peak, max_ties=4096, stream=None):
-        """Algorithm 1, lines 5-6 on a peak record (uint8 tensor of 24 bytes,
+        """Algorithm 1, tie-refinement step on a peak record (uint8 tensor of 24 bytes,
         updated in place); r is the pair's full correlation (int32/int64)."""
         r_dtype = TDE_I32 if r.dtype == self.torch.int32 else TDE_I64
         wsb = int(load_library().tde_refine_workspace_size(max_ties))

@@ -899,7 +899,7 @@ def _refine_case(T, ctx, x, y, bits, lo, hi, max_ties=4096):
 @pytest.mark.parametrize("seed", range(6))
 def test_refine_ties_matches_algorithm1_lines5_6(T, ctx, seed):
     """Sign quantization of short signals gives many integer ties; the
-    refinement must return the oracle's refined set (Algorithm 1, lines 5-6,
+    refinement must return the oracle's refined set (Algorithm 1, tie-refinement step,
     float64 in the fixed pairwise order): its smallest lag and its size."""
     from paper_2509_19974_amd import tde
     rng = np.random.default_rng(100 + seed)

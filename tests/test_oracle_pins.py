@@ -327,7 +327,7 @@ def test_theorem1_peak_invariance(seed, n, kind, k):
 
 @pytest.mark.parametrize("bits", [1, 2, 4, 8])
 def test_algorithm1_refined_returns_true_shift(bits):
-    """Algorithm 1 with lines 5-6: ties are resolved by x * y, which is strictly
+    """Algorithm 1 with its tie-refinement step: ties are resolved by x * y, which is strictly
     maximal at nu on exact shifts (Cauchy-Schwarz), so the set is {nu}."""
     rng = np.random.default_rng(100 + bits)
     for _ in range(20):
