@@ -29,14 +29,20 @@ namespace tde {
 constexpr int kSumBlock = 1024;    // samples per block sum (a level-10 subtree)
 constexpr int kSumChunk = 4096;    // block sums reduced per LDS pass in the finalize
 
-// Signal of a global block index: a 64-way search per round (one load per
+// Signal of a global block index. bps > 0: every signal has bps blocks, so
+// the index is a division. Otherwise a 64-way search per round (one load per
 // lane, a ballot), so finding the signal takes ceil(log64(nsig)) rounds
 // instead of a chain of dependent loads. Every wave computes it by itself.
-__device__ __forceinline__ const QSig& pick_sig(const QSig* sigs, int nsig, const QSig& one, int64_t unit,
+__device__ __forceinline__ const QSig& pick_sig(const QSig* sigs, int nsig, const QSig& one, int bps, int64_t unit,
                                                 int64_t& local) {
     if (sigs == nullptr) {
         local = unit;
         return one;
+    }
+    if (bps > 0) {
+        const uint32_t i = (uint32_t)unit / (uint32_t)bps;
+        local = unit - (int64_t)i * bps;
+        return sigs[i];
     }
     const int lane = threadIdx.x & 63;
     int lo = 0, n = nsig;                      // invariant: sigs[lo].blk_base <= unit
@@ -69,11 +75,11 @@ __device__ __forceinline__ double sq_or_zero(float f) {
 // With the scale fused into the quantize kernel, this kernel also zeroes the
 // statistics that kernel accumulates (first block of each signal) and the
 // scratch counters of a later kernel (first block).
-__global__ void __launch_bounds__(256) k_sumsq_blocks(const QSig* sigs, int nsig, QSig one, int fused,
+__global__ void __launch_bounds__(256) k_sumsq_blocks(const QSig* sigs, int nsig, QSig one, int bps, int fused,
                                                       int* zero_me, int nzero) {
     const int64_t blk = blockIdx.x;
     int64_t lb;
-    const QSig& s = pick_sig(sigs, nsig, one, blk, lb);
+    const QSig& s = pick_sig(sigs, nsig, one, bps, blk, lb);
     if (fused) {
         if (blk == 0 && zero_me && (int)threadIdx.x < nzero) zero_me[threadIdx.x] = 0;
         if (lb == 0 && threadIdx.x == 0 && s.stat) {
@@ -250,12 +256,12 @@ __device__ __forceinline__ T wave_sum(T v) {
 // fused != 0: every block takes its signal's scale from the block sums itself
 // (signals of 1 .. kFuseMaxN samples), and the first block of each signal
 // publishes it.
-__global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QSig one, int fused) {
+__global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QSig one, int bps, int fused) {
     const int64_t blk = blockIdx.x;
     int64_t lb;
     // a copy: the stores below could alias the descriptor array, which
     // would make the compiler reload its fields after every store
-    const QSig s = pick_sig(sigs, nsig, one, blk, lb);
+    const QSig s = pick_sig(sigs, nsig, one, bps, blk, lb);
     float inv;
     if (s.bits == 1) {
         inv = 0.f;
@@ -320,7 +326,8 @@ __global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QS
                 }
                 w |= (uint32_t)(uint8_t)c << (8 * e);
             }
-            if (m + 4 <= s.n && ((((uintptr_t)(s.q + m)) & 3) == 0)) {
+            if (s.skip_q) {
+            } else if (m + 4 <= s.n && ((((uintptr_t)(s.q + m)) & 3) == 0)) {
                 *reinterpret_cast<uint32_t*>(s.q + m) = w;
             } else {
 #pragma unroll
@@ -440,14 +447,19 @@ int launch_quantize(const QSig* sigs_dev, const QSig& one, int nsig, int64_t tot
     // short signals: the quantize blocks finish the sum tree themselves, and
     // the finalize kernel (one small launch) is left out
     const int fused = need_scale && min_n >= 1 && max_n <= kFuseMaxN ? 1 : 0;
+    // equal lengths: the block -> signal map is a division (checked against
+    // the grid, which is the sum of every signal's blocks)
+    int bps = 0;
+    if (sigs_dev && min_n >= 1 && min_n == max_n && total_blocks == nsig * ceil_div(min_n, kQuantBlock))
+        bps = (int)ceil_div(min_n, kQuantBlock);
     if (need_scale) {
-        hipLaunchKernelGGL(k_sumsq_blocks, dim3((unsigned)total_blocks), dim3(256), 0, s, sigs_dev, nsig, one, fused,
-                           zero_me, nzero);
+        hipLaunchKernelGGL(k_sumsq_blocks, dim3((unsigned)total_blocks), dim3(256), 0, s, sigs_dev, nsig, one, bps,
+                           fused, zero_me, nzero);
     }
     if (!fused &&
         (need_scale || sigs_dev != nullptr || one.stat != nullptr || one.inv_out != nullptr || zero_me != nullptr))
         hipLaunchKernelGGL(k_scale_finalize, dim3(nsig), dim3(256), 0, s, sigs_dev, nsig, one, zero_me, nzero);
-    hipLaunchKernelGGL(k_quantize, dim3((unsigned)total_blocks), dim3(256), 0, s, sigs_dev, nsig, one, fused);
+    hipLaunchKernelGGL(k_quantize, dim3((unsigned)total_blocks), dim3(256), 0, s, sigs_dev, nsig, one, bps, fused);
     if (write_flags)
         hipLaunchKernelGGL(k_quantize_flags, dim3((unsigned)ceil_div(nsig, 256)), dim3(256), 0, s, sigs_dev, nsig,
                            one);

@@ -852,6 +852,9 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
             if (B.off_pk[2 * i + side]) {
                 S.pk = reinterpret_cast<uint32_t*>(W + B.off_pk[2 * i + side]);
                 S.pk_bits = pp.probe.fmt == kFmtF6 ? 6 : 4;
+                // the FP engine reads only the packed codes; the window
+                // kernel of the learned path reads the int8 ones
+                S.skip_q = B.learned ? 0 : 1;
             }
             if (B.learned) {
                 // decimated CNN input, written by the quantize kernel

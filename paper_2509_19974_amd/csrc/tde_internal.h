@@ -119,7 +119,9 @@ struct QSig {
     // 4 or 6; ceil(n/16) units, the last zero-padded)
     uint32_t* pk;
     int32_t pk_bits;
-    int32_t pad1;
+    // 1: only the packed codes are stored (nothing reads the int8 codes; the
+    // statistics still count them)
+    int32_t skip_q;
 };
 // z-unit cell boundaries (ascending, K of them) of the non-uniform quantizer
 // `kind` (TDE_QUANT_MULAW, TDE_QUANT_GAUSS) for bits 2 or 4; returns K, or 0
@@ -135,7 +137,9 @@ int64_t quantize_gsum_doubles(int64_t n);
 // zero_me (may be null): nzero ints that later kernels of the call expect at 0.
 // min_n, max_n: bounds of the signal lengths (0, 0 when unknown); when every
 // signal has 1 .. 262144 samples the scale is finished inside the quantize
-// kernel instead of a separate launch.
+// kernel instead of a separate launch. When min_n == max_n >= 1 and the
+// descriptors are consecutive (blk_base = i ceil(n/kQuantBlock)), a block finds
+// its signal by a division instead of a search.
 int launch_quantize(const QSig* sigs_dev, const QSig& one, int nsig, int64_t total_blocks, bool need_scale,
                     bool write_flags, int* zero_me, int nzero, hipStream_t s, int64_t min_n = 0, int64_t max_n = 0);
 
