@@ -406,6 +406,29 @@ def test_batch_fp_and_int8_operands_agree(T, ctx):
         _check_pair(pk[i], p, r)
 
 
+def test_batch_equal_lengths_ragged_blocks(T, ctx):
+    """Signals of one length (12289 samples: three full 4096-sample quantize
+    blocks and one of a single sample), so every block finds its signal by a
+    division; mixed code ranges put ternary, FP4, FP6 and int8 pairs in one
+    launch, and the FP pairs keep only their packed codes."""
+    from paper_2509_19974_amd import tde
+    say("batch equal lengths, ragged blocks")
+    rng = np.random.default_rng(12289)
+    n = 12289
+    pairs = []
+    for b in [1, 2, 4, 8, 4, 2, 8, 1]:
+        x = rng.standard_normal(n).astype(np.float32)
+        d = int(rng.integers(-n // 2, n // 2))
+        y = np.roll(x, d) + (0.5 * rng.standard_normal(n)).astype(np.float32)
+        pairs.append(dict(x=x, y=y.astype(np.float32), lag_lo=-(n - 1), lag_hi=n - 1, bits=b))
+    for path in (tde.TDE_PATH_MFMA, tde.TDE_PATH_MFMA_I8):
+        pk, sp = _batch(T, ctx, pairs, path, want_r=True)
+        for i, p in enumerate(pairs):
+            _check_pair(pk[i], p, sp[i]["r_out"].cpu().numpy())
+        pk2, _ = _batch(T, ctx, pairs, path, want_r=False)    # fused argmax, no r array
+        assert pk2.tobytes() == pk.tobytes()
+
+
 @pytest.mark.parametrize("kind", [1, 2])
 def test_batch_nonuniform_quantizers(T, ctx, kind):
     """A batch with a non-uniform map on every pair (bits 1, 2, 4): peaks and
