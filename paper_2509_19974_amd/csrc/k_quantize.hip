@@ -326,13 +326,14 @@ __global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QS
                 }
                 w |= (uint32_t)(uint8_t)c << (8 * e);
             }
-            if (s.skip_q) {
-            } else if (m + 4 <= s.n && ((((uintptr_t)(s.q + m)) & 3) == 0)) {
-                *reinterpret_cast<uint32_t*>(s.q + m) = w;
-            } else {
+            if (!s.skip_q) {
+                if (m + 4 <= s.n && ((((uintptr_t)(s.q + m)) & 3) == 0)) {
+                    *reinterpret_cast<uint32_t*>(s.q + m) = w;
+                } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (m + e < s.n) s.q[m + e] = (int8_t)(w >> (8 * e));
+                    for (int e = 0; e < 4; ++e)
+                        if (m + e < s.n) s.q[m + e] = (int8_t)(w >> (8 * e));
+                }
             }
         }
         if (s.pk) {
