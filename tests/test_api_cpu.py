@@ -276,3 +276,21 @@ def test_auto_engine_cost_model_and_tuning_file(tmp_path):
     assert tde.tde_tune_query(n16, n16, 1, 1, -(n16 - 1), n16 - 1) == tde.TDE_PATH_POPC
     tde.tde_tune_reset()
     assert tde.tde_tune_query(n16, n16, 1, 1, -(n16 - 1), n16 - 1) == tde.TDE_PATH_MFMA
+
+
+def test_missing_library_raises(tmp_path, monkeypatch):
+    """No fallback path: without the built library the binding refuses to load."""
+    monkeypatch.setattr(tde, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        tde.load_library(str(tmp_path / "libtde.so"))
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU; asked for more it exits with status 2 and says
+    why, before any device work."""
+    import subprocess
+    import sys
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=ROOT)
+    assert p.returncode == 2
+    assert "one GPU only" in p.stderr
