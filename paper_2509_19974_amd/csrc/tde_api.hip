@@ -519,7 +519,8 @@ int tde_argmax_lag(tde_ctx* ctx, const void* r, int r_dtype, int64_t lag_lo, int
 
 size_t tde_refine_workspace_size(int max_ties) {
     if (max_ties < 2 || max_ties > 65536) return 0;
-    return align_bytes((size_t)max_ties * 8) * 2 + align_bytes(sizeof(int));
+    return align_bytes((size_t)max_ties * 8) * 2 + align_bytes(sizeof(int)) +
+           align_bytes((size_t)kRefineMaxChunks * sizeof(int));
 }
 
 int tde_refine_ties(tde_ctx* ctx, const float* x, int64_t nx, const float* y, int64_t ny, const void* r,
@@ -545,8 +546,9 @@ int tde_refine_ties(tde_ctx* ctx, const float* x, int64_t nx, const float* y, in
     int64_t* lags = static_cast<int64_t*>(cv.take((size_t)max_ties * 8));
     double* vals = static_cast<double*>(cv.take((size_t)max_ties * 8));
     int* count = static_cast<int*>(cv.take(sizeof(int)));
+    int* hits = static_cast<int*>(cv.take((size_t)kRefineMaxChunks * sizeof(int)));
     return launch_refine(x, nx, y, ny, r, r_dtype, lag_lo, lag_hi - lag_lo + 1, peak, max_ties, lags, vals, count,
-                         static_cast<hipStream_t>(stream));
+                         hits, static_cast<hipStream_t>(stream));
 }
 
 // --------------------------------------------------------------- batch --

@@ -301,9 +301,12 @@ int launch_copy_bytes(void* dst, const void* src, size_t n, hipStream_t s);
 int launch_xcorr_win(const XItem* items_dev, int npairs, const int32_t* top, const float* margin, float theta,
                      int topk, int nb, ArgPart* parts, hipStream_t s);
 
-// tie refinement (Algorithm 1, tie-refinement step)
+// tie refinement (Algorithm 1, tie-refinement step); hits: kRefineMaxChunks
+// ints of scratch for the per-chunk counts of the collect
+constexpr int kRefineMaxChunks = 4096;
 int launch_refine(const float* x, int64_t nx, const float* y, int64_t ny, const void* r, int dtype, int64_t lag_lo,
-                  int64_t L, tde_peak* peak, int max_ties, int64_t* lags, double* vals, int* count, hipStream_t s);
+                  int64_t L, tde_peak* peak, int max_ties, int64_t* lags, double* vals, int* count, int* hits,
+                  hipStream_t s);
 
 // ---------------------------------------------------------- auto engine --
 // HIP device of a context.

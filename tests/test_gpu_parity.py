@@ -920,7 +920,7 @@ def _refine_case(T, ctx, x, y, bits, lo, hi, max_ties=4096):
 
 
 @pytest.mark.parametrize("seed", range(6))
-def test_refine_ties_matches_algorithm1_lines5_6(T, ctx, seed):
+def test_refine_ties_matches_algorithm1_refinement(T, ctx, seed):
     """Sign quantization of short signals gives many integer ties; the
     refinement must return the oracle's refined set (Algorithm 1, tie-refinement step,
     float64 in the fixed pairwise order): its smallest lag and its size."""
@@ -969,6 +969,65 @@ def test_refine_partial_and_exact_shift(T, ctx):
     yy[nu:] = (0.7 * s).astype(np.float32)
     before, after = _refine_case(T, ctx, xx, yy, 1, -500, 500)
     assert after["lag"] == nu and (before["n_ties"] == 1 or after["n_ties"] == 1)
+
+
+def _planted_peak(T, tde, lags_in_r, lo, rmax):
+    rec = np.zeros(1, tde.PEAK_DTYPE)
+    rec["lag"], rec["rmax"], rec["n_ties"] = lags_in_r[0] + lo, rmax, lags_in_r.size
+    return T.from_numpy(np.frombuffer(rec.tobytes(), np.uint8).copy()).cuda()
+
+
+@pytest.mark.parametrize("n,ntie,max_ties,rdt", [(70000, 5, 4096, np.int64), (65536, 40, 16, np.int32),
+                                                 (20000, 3, 2, np.int64), (9000, 300, 4096, np.int32)])
+def test_refine_planted_ties_long_signals(T, ctx, n, ntie, max_ties, rdt):
+    """Tied maxima planted in r over a long lag range (several chunks of the
+    tie collection; overlaps of up to 70000 samples, so many 1024-product
+    blocks per dot product): the refined set is the oracle's among the first
+    max_ties tied lags, and the partial flag says whether any were left out."""
+    from paper_2509_19974_amd import tde
+    say(f"refine planted n={n} ties={ntie} max_ties={max_ties}")
+    rng = np.random.default_rng(n + ntie)
+    x = rng.standard_normal(n).astype(np.float32)
+    y = rng.standard_normal(n + 77).astype(np.float32)
+    lo, hi = -(n - 1), y.size - 1
+    r = np.zeros(hi - lo + 1, rdt)
+    idx = np.sort(rng.choice(r.size, ntie, replace=False))
+    r[idx] = 99
+    peak = _planted_peak(T, tde, idx, lo, 99)
+    ctx.refine(dev(T, x), dev(T, y), dev(T, r), lo, hi, peak, max_ties=max_ties)
+    T.cuda.synchronize()
+    out = tde.decode_peaks(peak)[0]
+    tied = idx[:max_ties] + lo
+    vals = oracle.xcorr_f64_at_pairwise(x, y, tied)
+    best = tied[vals == vals.max()]
+    assert (out["lag"], out["rmax"], out["n_ties"]) == (best.min(), 99, best.size)
+    assert out["flags"] & tde.TDE_FLAG_REFINED
+    assert bool(out["flags"] & tde.TDE_FLAG_REFINE_PARTIAL) == (ntie > max_ties)
+
+
+def test_refine_exact_real_ties_long(T, ctx):
+    """Pulse trains: every lag 7k with full overlap has the same real
+    correlation (the pulse count of x), over overlaps of 5000 samples; more
+    tied lags than max_ties, so the refined set is the first max_ties."""
+    from paper_2509_19974_amd import tde
+    say("refine exact real ties, long")
+    x = np.zeros(5000, np.float32)
+    x[::7] = 1.0
+    y = np.zeros(60000, np.float32)
+    y[::7] = 1.0
+    lo, hi = -4999, 59999
+    r = oracle.xcorr(oracle.quantize(x, 1)[0], oracle.quantize(y, 1)[0], lo, hi)
+    idx = np.nonzero(r == r.max())[0]
+    assert idx.size > 4096
+    peak = _planted_peak(T, tde, idx, lo, int(r.max()))
+    ctx.refine(dev(T, x), dev(T, y), dev(T, r), lo, hi, peak, max_ties=4096)
+    T.cuda.synchronize()
+    out = tde.decode_peaks(peak)[0]
+    tied = idx[:4096] + lo
+    vals = oracle.xcorr_f64_at_pairwise(x, y, tied)
+    best = tied[vals == vals.max()]
+    assert (out["lag"], out["n_ties"]) == (best.min(), best.size)
+    assert out["flags"] & tde.TDE_FLAG_REFINE_PARTIAL
 
 
 # ------------------------------------------------------------- streaming --
