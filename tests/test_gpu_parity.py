@@ -978,12 +978,15 @@ def _planted_peak(T, tde, lags_in_r, lo, rmax):
 
 
 @pytest.mark.parametrize("n,ntie,max_ties,rdt", [(70000, 5, 4096, np.int64), (65536, 40, 16, np.int32),
-                                                 (20000, 3, 2, np.int64), (9000, 300, 4096, np.int32)])
+                                                 (20000, 3, 2, np.int64), (9000, 300, 4096, np.int32),
+                                                 (2500000, 6, 4096, np.int32)])
 def test_refine_planted_ties_long_signals(T, ctx, n, ntie, max_ties, rdt):
     """Tied maxima planted in r over a long lag range (several chunks of the
-    tie collection; overlaps of up to 70000 samples, so many 1024-product
+    tie collection; overlaps of up to 2.5 M samples, so many 1024-product
     blocks per dot product): the refined set is the oracle's among the first
-    max_ties tied lags, and the partial flag says whether any were left out."""
+    max_ties tied lags, and the partial flag says whether any were left out.
+    2.5 M samples give about 5 M lags, more than 4096 chunks of the smallest
+    size, so the chunks grow."""
     from paper_2509_19974_amd import tde
     say(f"refine planted n={n} ties={ntie} max_ties={max_ties}")
     rng = np.random.default_rng(n + ntie)
