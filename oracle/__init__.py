@@ -6,11 +6,11 @@ with the HIP library (``paper_2509_19974_amd``) and never imports it.
 
 What it computes is the plain definition of each step, written out:
 
-* ``sumsq_pairwise`` / ``inv_step`` -- the per-signal scale of the uniform
-  quantizer (the paper leaves the quantizer free, Section 3.2; the library fixes
-  a symmetric mid-tread quantizer on [-3 sigma, 3 sigma] and a pairwise
-  float64 sum of squares over a fixed binary tree so that two implementations
-  agree bit for bit).
+* ``sumsq`` / ``inv_step`` -- the per-signal scale of the uniform quantizer
+  (the paper leaves the quantizer free, Section 3.2; the library fixes a
+  symmetric mid-tread quantizer on [-3 sigma, 3 sigma]). S = sum of x^2 is
+  the exact real sum rounded once to float64 (``math.fsum`` of the squares,
+  each exact in float64), so it depends on no summation order.
 * ``quantize`` -- Algorithm 1, quantization step: monotone integer maps with phi(0) = 0;
   sign with sign(0) = 0 (Section 4.2) for bits = 1.
 * ``quantize_nonuniform``, ``mulaw_thresholds``, ``lloyd_max_gauss`` --
@@ -24,16 +24,21 @@ What it computes is the plain definition of each step, written out:
   number of maximisers (Remark 1).
 * ``xcorr_f64_at`` -- Eq. (1) on the unquantized signals in float64.
 * ``estimate`` / ``estimate_refined`` -- Algorithm 1 without, and with, its
-  tie-refinement step.
+  tie-refinement step. The refinement compares the exact real values of
+  Eq. (1) at the tied lags: every product x[m] y[m + tau] of float32 samples
+  is exact in float64, and the sign of the exactly rounded sum of the
+  products at one lag minus those at another (``math.fsum``) is the sign of
+  the exact difference.
 * ``stream`` -- correlation of a stream against a template, block by block
   (the streaming extension named as future work in Section 5): the plain
   correlation of Eq. (1) over the concatenated stream, cut into the lags each
   push makes final, with per-block and running argmaxes.
 * ``xcorr_long_certified`` -- for signals too long for the direct sum over all
-  lags: a float64 FFT correlation of the integer sequences, rounded to the
-  nearest integer, accepted only under an a-priori rounding-error bound below
-  one half (so the rounding is provably exact), and cross-checked by direct
-  sums on a lag subset.
+  lags: a float64 radix-2 FFT correlation of the integer sequences (plain C,
+  ``oracle_conv_fft``), rounded to the nearest integer and accepted only when
+  Percival's a-priori bound on the FFT-product error is below one half (so
+  the rounding is provably exact), and cross-checked by direct sums on a lag
+  subset.
 
 Everything heavy runs in ``tde_oracle.c`` (plain loops, int64/float64),
 compiled with gcc and loaded through ctypes.
@@ -72,8 +77,6 @@ def _load():
         build(force=False)
     lib = ctypes.CDLL(_LIB_PATH)
     i64, f32, f64, vp = ctypes.c_int64, ctypes.c_float, ctypes.c_double, ctypes.c_void_p
-    lib.oracle_sumsq_pairwise.argtypes = [vp, i64, vp]
-    lib.oracle_sumsq_pairwise.restype = f64
     lib.oracle_kmax.argtypes = [ctypes.c_int]
     lib.oracle_kmax.restype = ctypes.c_int
     lib.oracle_inv_step_from_sumsq.argtypes = [f64, i64, ctypes.c_int]
@@ -88,6 +91,8 @@ def _load():
     lib.oracle_argmax_i64.restype = None
     lib.oracle_xcorr_f64_at.argtypes = [vp, i64, vp, i64, vp, i64, vp]
     lib.oracle_xcorr_f64_at.restype = None
+    lib.oracle_conv_fft.argtypes = [vp, i64, vp, i64, i64, vp, vp]
+    lib.oracle_conv_fft.restype = None
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = ctypes.c_int
     _lib = lib
@@ -120,23 +125,26 @@ def kmax(bits: int) -> int:
     return int(_load().oracle_kmax(bits))
 
 
-def sumsq_pairwise(x) -> float:
-    """Pairwise (fixed binary tree) float64 sum of the exact squares of the
-    finite samples, zero-padded to a power-of-two length."""
-    x = _f32(x)
-    n = x.size
-    p2 = 1
-    while p2 < n:
-        p2 *= 2
-    scratch = np.zeros(p2, dtype=np.float64)
-    return float(_load().oracle_sumsq_pairwise(_ptr(x), n, _ptr(scratch)))
+def sumsq(x) -> float:
+    """S = sum of x[m]^2 over the finite samples, as the exact real sum
+    rounded once to float64 (round to nearest, ties to even). Each square of
+    a float32 is exact in float64; ``math.fsum`` returns the correctly
+    rounded sum of its float64 inputs, so S depends on no summation order."""
+    x = _f32(x).astype(np.float64)
+    x = x[np.isfinite(x)]
+    return math.fsum((x * x).tolist())
+
+
+def inv_step_from_sumsq(S: float, n: int, bits: int) -> float:
+    """fl32((2K+1) / (6 sigma)), sigma = sqrt(S/n) (float64 operations, each
+    correctly rounded); 0.0 when S == 0."""
+    return float(np.float32(_load().oracle_inv_step_from_sumsq(float(S), int(n), bits)))
 
 
 def inv_step(x, bits: int) -> float:
-    """fl32((2K+1) / (6 sigma)), sigma = sqrt(S/n); 0.0 when S == 0."""
+    """The uniform quantizer's automatic scale of a signal (see ``sumsq``)."""
     x = _f32(x)
-    S = sumsq_pairwise(x)
-    return float(np.float32(_load().oracle_inv_step_from_sumsq(S, x.size, bits)))
+    return inv_step_from_sumsq(sumsq(x), x.size, bits)
 
 
 # ------------------------------------------------------------- quantize ----
@@ -287,32 +295,63 @@ def xcorr_f64_at(x, y, lags) -> np.ndarray:
     return r
 
 
-def xcorr_f64_at_pairwise(x, y, lags) -> np.ndarray:
-    """Eq. (1) on the float signals in float64 with a fixed summation order:
-    the products x[m] y[m + tau] (exact in float64) over the overlap, in
-    ascending m, zero-padded to a power-of-two length and added as a binary
-    tree (adjacent pairs, level by level). Used for the tie refinement of
-    Algorithm 1, tie-refinement step, so that the choice between tied lags is made in
-    the same arithmetic on every implementation."""
-    x = np.asarray(_f32(x), dtype=np.float64)
-    y = np.asarray(_f32(y), dtype=np.float64)
-    out = []
-    for tau in np.asarray(lags, dtype=np.int64).tolist():
-        lo = max(0, -tau)
-        hi = min(x.size, y.size - tau)
-        if hi <= lo:
-            out.append(0.0)
-            continue
-        p = x[lo:hi] * y[lo + tau:hi + tau]
-        n = 1
-        while n < p.size:
-            n *= 2
-        a = np.zeros(n)
-        a[:p.size] = p
-        while a.size > 1:
-            a = a[0::2] + a[1::2]
-        out.append(float(a[0]))
-    return np.array(out)
+def _products(x64, y64, tau: int) -> np.ndarray:
+    """x[m] y[m + tau] over the overlap, ascending m (each exact in float64)."""
+    lo = max(0, -tau)
+    hi = min(x64.size, y64.size - tau)
+    if hi <= lo:
+        return np.zeros(0)
+    return x64[lo:hi] * y64[lo + tau:hi + tau]
+
+
+def compare_real_xcorr(x, y, tau_a: int, tau_b: int) -> int:
+    """Sign (-1, 0, +1) of (x * y)[tau_a] - (x * y)[tau_b], Eq. (1) on the
+    float signals, decided exactly: the products are exact in float64, and
+    ``math.fsum`` of the products at tau_a and the negated products at tau_b
+    is the exact difference rounded once, whose sign is exact (a non-zero
+    difference of multiples of 2^-298 rounds to a non-zero float64). The
+    overlaps must hold finite samples only."""
+    return _compare64(_f32(x).astype(np.float64), _f32(y).astype(np.float64), tau_a, tau_b)
+
+
+def _compare64(x64, y64, tau_a: int, tau_b: int) -> int:
+    d = math.fsum(_products(x64, y64, tau_a).tolist() + (-_products(x64, y64, tau_b)).tolist())
+    return (d > 0) - (d < 0)
+
+
+def real_xcorr_finite(x, y, tau: int) -> bool:
+    """True when every sample of x and y in the overlap at tau is finite."""
+    x, y = _f32(x), _f32(y)
+    lo = max(0, -tau)
+    hi = min(x.size, y.size - tau)
+    if hi <= lo:
+        return True
+    return bool(np.all(np.isfinite(x[lo:hi])) and np.all(np.isfinite(y[lo + tau:hi + tau])))
+
+
+def refine_ties(x, y, tied):
+    """Algorithm 1, tie-refinement step: among the tied lags (ascending), the
+    set whose exact real correlation (Eq. (1) on x, y) is largest, in
+    ascending order. Reading for non-finite samples (not in the paper): if
+    any tied lag's overlap holds a NaN or Inf sample, its real correlation is
+    not a real number and the lags cannot be compared; the tied set is then
+    returned unchanged. Returns (refined set, compared) with compared False
+    in that case."""
+    tied = [int(t) for t in tied]
+    if len(tied) <= 1:
+        return tied, True
+    if not all(real_xcorr_finite(x, y, t) for t in tied):
+        return tied, False
+    x64 = _f32(x).astype(np.float64)
+    y64 = _f32(y).astype(np.float64)
+    best = [tied[0]]
+    for t in tied[1:]:
+        c = _compare64(x64, y64, t, best[0])
+        if c > 0:
+            best = [t]
+        elif c == 0:
+            best.append(t)
+    return best, True
 
 
 def overlap_count(nu: int, nv: int, tau: int) -> int:
@@ -334,19 +373,21 @@ def estimate(x, y, bits: int, lag_lo: int, lag_hi: int,
 
 
 def estimate_refined(x, y, bits: int, lag_lo: int, lag_hi: int,
-                     inv_step_x: float | None = None, inv_step_y: float | None = None):
-    """Algorithm 1 with its tie-refinement step: ties of the integer correlation are resolved by
-    the float64 correlation of the unquantized signals (fixed pairwise
-    summation order), evaluated only at the tied lags. Returns the refined
-    argmax set (sorted) and the line-4 result."""
+                     inv_step_x: float | None = None, inv_step_y: float | None = None,
+                     max_ties: int | None = None):
+    """Algorithm 1 with its tie-refinement step: ties of the integer
+    correlation are resolved by the exact real correlation of the unquantized
+    signals at the tied lags (``refine_ties``). With max_ties, only the
+    smallest max_ties tied lags take part (the library's partial refinement).
+    Returns the argmax-step result plus ``lag_set`` (sorted), ``refined``
+    (False when non-finite samples prevented the comparison) and ``partial``."""
     res = estimate(x, y, bits, lag_lo, lag_hi, inv_step_x, inv_step_y)
     r = res["r"]
-    tied = np.nonzero(r == res["rmax"])[0].astype(np.int64) + lag_lo
-    if tied.size > 1:
-        rf = xcorr_f64_at_pairwise(x, y, tied)
-        best = rf.max()
-        tied = tied[rf == best]
-    res["lag_set"] = [int(t) for t in tied]
+    tied = (np.nonzero(r == res["rmax"])[0].astype(np.int64) + lag_lo).tolist()
+    res["partial"] = max_ties is not None and len(tied) > max_ties
+    if res["partial"]:
+        tied = tied[:max_ties]
+    res["lag_set"], res["refined"] = refine_ties(x, y, tied)
     return res
 
 
@@ -396,22 +437,45 @@ def stream(x, blocks, bits: int, inv_step_y: float, inv_step_x: float | None = N
 # ------------------------------------------------- long-signal route ------
 
 def fft_rounding_bound(u, v, n_fft: int) -> float:
-    """A-priori bound on the max-norm error of a float64 FFT convolution of the
-    integer sequences u and v with transform length n_fft:
-    ||err||_inf <= ||u||_2 ||v||_2 * 3 log2(n) * 8 eps (a generous multiple of
-    the standard forward-error estimate for radix-2 FFT convolution)."""
-    nu2 = math.sqrt(float(np.dot(u.astype(np.float64), u.astype(np.float64))))
-    nv2 = math.sqrt(float(np.dot(v.astype(np.float64), v.astype(np.float64))))
-    eps = np.finfo(np.float64).eps
-    return nu2 * nv2 * 3.0 * math.log2(n_fft) * 8.0 * eps
+    """A-priori bound on the max-norm error of the float64 FFT product in
+    ``oracle_conv_fft`` (radix-2 complex transforms of length N = 2^k, three
+    transforms and one pointwise product): Percival's bound for FFT-based
+    multiplication (C. Percival, Math. Comp. 72 (2003); restated by Brent and
+    Zimmermann, Modern Computer Arithmetic, Section 3.3),
+        ||z' - z||_inf < ||u||_2 ||v||_2 ((1+e)^(3k) (1+e sqrt5)^(3k+1) (1+b)^(3k) - 1),
+    with e = 2^-53 the unit roundoff, sqrt(5) e the error of a complex
+    product computed with four real products, and b the twiddle error (2 e:
+    the twiddles are long-double values rounded once). The norms are exact
+    integers; the bound is evaluated in float64 and inflated by 1% to cover
+    its own rounding."""
+    nu2 = math.sqrt(float(int(np.dot(u.astype(np.int64), u.astype(np.int64)))))
+    nv2 = math.sqrt(float(int(np.dot(v.astype(np.int64), v.astype(np.int64)))))
+    k = int(round(math.log2(n_fft)))
+    if (1 << k) != n_fft:
+        raise ValueError("n_fft must be a power of two")
+    e = 2.0 ** -53
+    b = 2.0 * e
+    growth = math.expm1(3 * k * math.log1p(e) + (3 * k + 1) * math.log1p(e * math.sqrt(5.0))
+                        + 3 * k * math.log1p(b))
+    return 1.01 * nu2 * nv2 * growth
+
+
+def conv_fft_f64(u, v, n_fft: int) -> np.ndarray:
+    """rev(u) conv v (length nu + nv - 1) through the float64 radix-2 FFT,
+    unrounded; entry j approximates r[j - (nu - 1)]."""
+    u, v = _i8(u), _i8(v)
+    out = np.empty(u.size + v.size - 1, dtype=np.float64)
+    scratch = np.empty(5 * n_fft, dtype=np.float64)
+    _load().oracle_conv_fft(_ptr(u), u.size, _ptr(v), v.size, n_fft, _ptr(out), _ptr(scratch))
+    return out
 
 
 def xcorr_long_certified(u, v, lag_lo: int, lag_hi: int, check_lags=None):
     """Exact int64 r over [lag_lo, lag_hi] for long sequences.
 
     The float64 FFT correlation of the integer sequences is rounded to the
-    nearest integer; the result is exact when the rounding-error bound is
-    below 1/2, which is asserted. The lags in ``check_lags`` are additionally
+    nearest integer; the result is exact when Percival's error bound
+    (``fft_rounding_bound``) is below 1/2, which is asserted. The lags in ``check_lags`` are additionally
     recomputed by direct int64 sums and must agree."""
     u, v = _i8(u), _i8(v)
     nu, nv = u.size, v.size
@@ -422,9 +486,7 @@ def xcorr_long_certified(u, v, lag_lo: int, lag_hi: int, check_lags=None):
     if not bound < 0.5:
         raise ArithmeticError(f"FFT rounding bound {bound} not below 1/2")
     # r[tau] = sum_m u[m] v[m+tau]; with ur = reversed u, (ur conv v)[j] = r[j - (nu-1)]
-    ur = u[::-1].astype(np.float64)
-    full = np.fft.irfft(np.fft.rfft(ur, n) * np.fft.rfft(v.astype(np.float64), n), n)
-    full = full[: nu + nv - 1]
+    full = conv_fft_f64(u, v, n)
     rounded = np.rint(full)
     taus = np.arange(lag_lo, lag_hi + 1, dtype=np.int64)
     idx = taus + (nu - 1)

@@ -16,7 +16,11 @@
  *   - Algorithm 1, argmax step: the argmax set, reported as its smallest element,
  *     the maximum and the size of the set (Remark 1: ties are legitimate).
  *   - the real-valued correlation of the unquantized signals in float64,
- *     summed in ascending m (used by Algorithm 1, tie-refinement step).
+ *     summed in ascending m (lag accuracy of the real correlation);
+ *   - a plain radix-2 complex FFT (Cooley-Tukey, decimation in time) used to
+ *     correlate long integer sequences in float64; its rounding error is
+ *     bounded a priori (Percival's bound for FFT-based products), so the
+ *     rounded result is exact whenever that bound is below 1/2.
  *
  * Plain C, compiled without fast-math: every float operation below is one
  * correctly rounded IEEE-754 operation.
@@ -26,33 +30,6 @@
 #include <string.h>
 
 /* ---------------------------------------------------------------- scale -- */
-
-/* Sum of squares used for the per-signal scale sigma. The paper does not fix
- * how sigma is computed; this oracle fixes it so that two implementations can
- * agree bit for bit:
- *   s_m = (double)x_m * (double)x_m for finite x_m (exact in float64), 0 else;
- *   pad the list with zeros to a power-of-two length and repeatedly replace it
- *   by the float64 sums of adjacent pairs (a[2k] + a[2k+1]) until one value
- *   remains (a pairwise sum over a fixed binary tree).
- * scratch must hold the padded length (the next power of two >= n) doubles. */
-double oracle_sumsq_pairwise(const float* x, int64_t n, double* scratch) {
-    if (n <= 0) return 0.0;
-    int64_t len = 1;
-    while (len < n) len *= 2;
-    for (int64_t m = 0; m < len; ++m) {
-        double s = 0.0;
-        if (m < n) {
-            double xm = (double)x[m];
-            if (isfinite(xm)) s = xm * xm;
-        }
-        scratch[m] = s;
-    }
-    while (len > 1) {
-        len /= 2;
-        for (int64_t k = 0; k < len; ++k) scratch[k] = scratch[2 * k] + scratch[2 * k + 1];
-    }
-    return scratch[0];
-}
 
 /* Largest code magnitude K of a b-bit symmetric quantizer; sign (b = 1) is
  * ternary with K = 1 (Section 4.2 uses sign with sign(0) = 0, i.e. K = 1). */
@@ -164,6 +141,83 @@ void oracle_xcorr_f64_at(const float* x, int64_t nx, const float* y, int64_t ny,
         for (int64_t m = m0; m < m1; ++m) acc += (double)x[m] * (double)y[m + tau];
         r[i] = acc;
     }
+}
+
+/* ------------------------------------------------------------ long FFT -- */
+
+/* Twiddles w_j = exp(-2 pi i j / n), j < n/2, evaluated in long double (x86
+ * extended precision, 64-bit significand) and rounded once to double: each
+ * is within about one unit roundoff of double of the exact value (the bound
+ * takes beta = 2 eps). The inverse transform uses their conjugates. */
+static void fft_twiddles(int64_t n, double* twr, double* twi) {
+    for (int64_t j = 0; j < n / 2; ++j) {
+        long double a = -2.0L * 3.141592653589793238462643383279502884L * (long double)j / (long double)n;
+        twr[j] = (double)cosl(a);
+        twi[j] = (double)sinl(a);
+    }
+}
+
+/* In-place radix-2 decimation-in-time complex FFT of length n = 2^k (re, im
+ * separate arrays); inverse = 1 conjugates the twiddles (unscaled inverse).
+ * Every butterfly is t = w b (four real products, two sums, each rounded
+ * once), then a + t and a - t: the arithmetic Percival's error bound
+ * describes. */
+static void fft_r2(double* re, double* im, int64_t n, int inverse, const double* twr, const double* twi) {
+    /* bit-reversal permutation */
+    for (int64_t i = 1, j = 0; i < n; ++i) {
+        int64_t bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) {
+            double t = re[i]; re[i] = re[j]; re[j] = t;
+            t = im[i]; im[i] = im[j]; im[j] = t;
+        }
+    }
+    for (int64_t len = 2; len <= n; len <<= 1) {
+        int64_t half = len / 2, step = n / len;
+#pragma omp parallel for schedule(static) if (n >= 65536)
+        for (int64_t b = 0; b < n; b += len) {
+            for (int64_t k = 0; k < half; ++k) {
+                double wr = twr[k * step], wi = inverse ? -twi[k * step] : twi[k * step];
+                double br = re[b + k + half], bi = im[b + k + half];
+                double tr = wr * br - wi * bi;
+                double ti = wr * bi + wi * br;
+                double ar = re[b + k], ai = im[b + k];
+                re[b + k] = ar + tr;
+                im[b + k] = ai + ti;
+                re[b + k + half] = ar - tr;
+                im[b + k + half] = ai - ti;
+            }
+        }
+    }
+}
+
+/* Linear convolution c = rev(u) conv v of int8 sequences (length nu + nv - 1)
+ * through complex FFTs of length n >= nu + nv - 1 (a power of two), in
+ * float64, unrounded: out[j] approximates r[j - (nu - 1)] of Eq. (1).
+ * scratch: 5 n doubles (two complex arrays and the twiddles). */
+void oracle_conv_fft(const int8_t* u, int64_t nu, const int8_t* v, int64_t nv, int64_t n, double* out,
+                     double* scratch) {
+    double *ar = scratch, *ai = scratch + n, *br = scratch + 2 * n, *bi = scratch + 3 * n;
+    double *twr = scratch + 4 * n, *twi = scratch + 4 * n + n / 2;
+    for (int64_t i = 0; i < n; ++i) {
+        ar[i] = i < nu ? (double)u[nu - 1 - i] : 0.0;
+        br[i] = i < nv ? (double)v[i] : 0.0;
+        ai[i] = 0.0;
+        bi[i] = 0.0;
+    }
+    fft_twiddles(n, twr, twi);
+    fft_r2(ar, ai, n, 0, twr, twi);
+    fft_r2(br, bi, n, 0, twr, twi);
+    for (int64_t i = 0; i < n; ++i) {      /* pointwise complex product */
+        double pr = ar[i] * br[i] - ai[i] * bi[i];
+        double pi = ar[i] * bi[i] + ai[i] * br[i];
+        ar[i] = pr;
+        ai[i] = pi;
+    }
+    fft_r2(ar, ai, n, 1, twr, twi);
+    double inv_n = 1.0 / (double)n;        /* a power of two: exact */
+    for (int64_t j = 0; j < nu + nv - 1; ++j) out[j] = ar[j] * inv_n;
 }
 
 /* Number of OpenMP threads the direct sums use. */

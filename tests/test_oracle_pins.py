@@ -227,31 +227,42 @@ def test_quantize_thresholds_monotone_odd(bits):
 
 # ------------------------------------------------------------------ scale --
 
-def test_sumsq_pairwise_hand_derived_rounding():
-    """Squares [2^54, 1 x 7]: ulp(2^54) = 4. Pairwise: (2^54+1) -> 2^54,
-    1+1 = 2 three times; (2^54+2) is a tie -> 2^54 (even), 2+2 = 4; then
-    2^54 + 4 is exact. A left-to-right sum would lose every +1 (2^54), the
-    exact value is 2^54 + 7."""
-    x = np.array([2.0 ** 27] + [1.0] * 7, dtype=np.float32)
-    assert oracle.sumsq_pairwise(x) == 2.0 ** 54 + 4
-    assert oracle.sumsq_pairwise(np.array([3.0], np.float32)) == 9.0
-    assert oracle.sumsq_pairwise(np.array([1.0, 2.0, 3.0], np.float32)) == 14.0
+def test_sumsq_exactly_rounded_hand_derived():
+    """Squares [2^54, 1 x k]: the exact sum is 2^54 + k, and ulp(2^54) = 4.
+    Rounded once to nearest (ties to even): k = 7 -> 2^54 + 8; k = 6 is a tie
+    between 2^54 + 4 (odd significand) and 2^54 + 8 (even) -> 2^54 + 8; k = 5
+    -> 2^54 + 4. A pairwise tree over [2^54, 1 x 7] would give 2^54 + 4 and a
+    left-to-right sum 2^54."""
+    for k, want in ((7, 2.0 ** 54 + 8), (6, 2.0 ** 54 + 8), (5, 2.0 ** 54 + 4), (1, 2.0 ** 54)):
+        x = np.array([2.0 ** 27] + [1.0] * k, dtype=np.float32)
+        assert oracle.sumsq(x) == want
+        assert oracle.sumsq(x[::-1]) == want
+    assert oracle.sumsq(np.array([3.0], np.float32)) == 9.0
+    assert oracle.sumsq(np.array([1.0, 2.0, 3.0], np.float32)) == 14.0
 
 
-def test_sumsq_pairwise_exact_on_integers_and_fsum_bound():
+def test_sumsq_equals_exact_rational_and_ignores_order():
+    """S equals the exact rational sum of the squares rounded once
+    (Fraction arithmetic, float() rounds correctly), for data spanning many
+    binades, and is unchanged by any permutation of the samples; non-finite
+    samples add nothing."""
     rng = np.random.default_rng(2)
-    for n in (1, 5, 255, 256, 1000, 65536 + 17):
-        xi = rng.integers(-1000, 1001, size=n)
-        x = xi.astype(np.float32)
-        # every partial sum is an integer below 2^53: the tree sum is exact
-        assert oracle.sumsq_pairwise(x) == float(int((xi.astype(np.int64) ** 2).sum()))
-    x = (rng.standard_normal(256 * 37 + 11) * 10).astype(np.float32)
-    exact = math.fsum(x.astype(np.float64) ** 2)
-    depth = math.ceil(math.log2(x.size))
-    assert abs(oracle.sumsq_pairwise(x) - exact) <= depth * np.finfo(np.float64).eps * exact
-    x[5] = np.nan
-    x[6] = np.inf
-    assert math.isfinite(oracle.sumsq_pairwise(x))
+    for n in (1, 5, 255, 1000, 4099):
+        x = (rng.standard_normal(n) * np.exp2(rng.integers(-60, 60, n))).astype(np.float32)
+        exact = sum((Fraction(float(v)) ** 2 for v in x), Fraction(0))
+        assert oracle.sumsq(x) == float(exact)
+        for _ in range(3):
+            assert oracle.sumsq(rng.permutation(x)) == float(exact)
+    xi = rng.integers(-1000, 1001, size=65536 + 17)
+    assert oracle.sumsq(xi.astype(np.float32)) == float(int((xi.astype(np.int64) ** 2).sum()))
+    x = rng.standard_normal(100).astype(np.float32)
+    y = x.copy()
+    y[5], y[6] = np.nan, np.inf
+    x[5], x[6] = 0.0, 0.0
+    assert oracle.sumsq(y) == oracle.sumsq(x)
+    # float32 subnormals square to normal float64 values (>= 2^-298)
+    tiny = np.array([np.float32(2.0 ** -149)] * 3, np.float32)
+    assert oracle.sumsq(tiny) == 3 * 2.0 ** -298
 
 
 @pytest.mark.parametrize("bits", [2, 4, 8])
@@ -371,6 +382,35 @@ def test_certified_fft_route_equals_direct(n, k):
     np.testing.assert_array_equal(got, direct)
 
 
+def test_fft_route_error_within_percival_bound():
+    """The float64 FFT product's error never exceeds the a-priori bound, on
+    full-scale codes (the worst case for the norms) with the exact
+    correlation from int64 direct sums; the bound's growth factor has the
+    first-order value 3k e + (3k+1) sqrt(5) e + 3k (2e) of the theorem; and at
+    the long-signal workload's largest shape (two 2^22-sample b = 8 signals,
+    transform 2^23) the bound stays far below 1/2."""
+    rng = np.random.default_rng(77)
+    for k in (4, 10, 14):
+        n = 1 << k
+        nu = n // 2
+        u = (rng.choice([-1, 1], nu) * 127).astype(np.int8)
+        v = (rng.choice([-1, 1], n - nu) * 127).astype(np.int8)
+        exact = oracle.xcorr(u, v, -(nu - 1), n - nu - 1)
+        got = oracle.conv_fft_f64(u, v, n)
+        err = float(np.max(np.abs(got - exact.astype(np.float64))))
+        bound = oracle.fft_rounding_bound(u, v, n)
+        assert err <= bound
+        assert np.array_equal(np.rint(got).astype(np.int64), exact)
+    e = 2.0 ** -53
+    for k in (1, 10, 23):
+        one = np.ones(1, np.int8)
+        first = (3 * k + (3 * k + 1) * math.sqrt(5.0) + 6 * k) * e
+        assert abs(oracle.fft_rounding_bound(one, one, 1 << k) / 1.01 / first - 1.0) < 1e-9
+    # the long workload: ||u||_2 <= 127 sqrt(2^22) is the worst case
+    worst = np.full(1 << 22, 127, np.int8)
+    assert oracle.fft_rounding_bound(worst, worst, 1 << 23) < 0.05
+
+
 # ------------------------------------------------- learned proposer (CNN) --
 
 from oracle import cnn  # noqa: E402
@@ -481,31 +521,76 @@ def test_cnn_bins_and_bf16_rounding():
     assert top.tolist() == [1, 2] and margin == 1.0          # logit_(1) - logit_(3)
 
 
-def test_pairwise_float_correlation_pins():
-    """The fixed-order float64 correlation used for tie refinement: exact on
-    small-integer data (every partial sum is an integer below 2^53), within
-    the pairwise error bound of the exactly rounded sum (math.fsum) on
-    random data, and summed in the stated tree (a hand-made case whose value
-    depends on the order)."""
-    import math
+def _planted_real_near_tie(n=64, ta=10, tb=20):
+    """x = 2^30 at m = 0 and 1 at m = 5; y = 2^30 at ta and at tb, 1 at
+    ta + 5. Then (x * y)[ta] = 2^60 + 1 and (x * y)[tb] = 2^60 exactly, but
+    2^60 + 1 is not a float64 (ulp(2^60) = 256): any float64 summation of the
+    products gives 2^60 at both lags."""
+    x = np.zeros(n, np.float32)
+    y = np.zeros(n, np.float32)
+    x[0], x[5] = 2.0 ** 30, 1.0
+    y[ta], y[tb], y[ta + 5] = 2.0 ** 30, 2.0 ** 30, 1.0
+    return x, y
+
+
+def test_exact_real_comparison_pins():
+    """compare_real_xcorr is the sign of the exact difference: it separates a
+    planted pair of lags that no float64 summation order separates, agrees
+    with exact Fraction arithmetic on random data, is antisymmetric, and
+    refine_ties keeps exactly the lags with the largest exact value."""
+    x, y = _planted_real_near_tie()
+    assert oracle.xcorr_f64_at(x, y, [10])[0] == oracle.xcorr_f64_at(x, y, [20])[0] == 2.0 ** 60
+    assert oracle.compare_real_xcorr(x, y, 10, 20) == 1
+    assert oracle.compare_real_xcorr(x, y, 20, 10) == -1
+    assert oracle.refine_ties(x, y, [10, 20]) == ([10], True)
+    # a third lag with the same exact value as lag 10: x[0] y[30] + x[5] y[35]
+    y[30], y[35] = 2.0 ** 30, 1.0
+    assert oracle.compare_real_xcorr(x, y, 30, 10) == 0
+    assert oracle.refine_ties(x, y, [10, 20, 30]) == ([10, 30], True)
     rng = np.random.default_rng(21)
-    x = rng.integers(-1000, 1000, 3000).astype(np.float32)
-    y = rng.integers(-1000, 1000, 2500).astype(np.float32)
-    lags = np.array([-2999, -7, 0, 5, 2499])
-    np.testing.assert_array_equal(oracle.xcorr_f64_at_pairwise(x, y, lags), oracle.xcorr_f64_at(x, y, lags))
-    xf = rng.standard_normal(5000).astype(np.float32)
-    yf = rng.standard_normal(5000).astype(np.float32)
-    for tau in (-3000, 0, 17, 4000):
-        lo, hi = max(0, -tau), min(5000, 5000 - tau)
-        prods = [float(a) * float(b) for a, b in zip(xf[lo:hi], yf[lo + tau:hi + tau])]
-        exact = math.fsum(prods)
-        bound = math.ceil(math.log2(len(prods))) * np.finfo(np.float64).eps * math.fsum(abs(p) for p in prods)
-        assert abs(oracle.xcorr_f64_at_pairwise(xf, yf, [tau])[0] - exact) <= bound
-    # [2^53, 1, 1, -2^53] pairwise: (2^53 + 1) + (1 - 2^53) = 2^53 + (1 - 2^53) = 1
-    # (ascending order would give ((2^53 + 1) + 1) - 2^53 = 0 after two roundings)
-    xs = np.array([2.0 ** 26, 1.0, 1.0, -(2.0 ** 26)], np.float32)
-    ys = np.array([2.0 ** 27, 1.0, 1.0, 2.0 ** 27], np.float32)
-    assert oracle.xcorr_f64_at_pairwise(xs, ys, [0])[0] == 1.0
+    xf = (rng.standard_normal(300) * np.exp2(rng.integers(-20, 20, 300))).astype(np.float32)
+    yf = (rng.standard_normal(280) * np.exp2(rng.integers(-20, 20, 280))).astype(np.float32)
+
+    def exact(tau):
+        lo, hi = max(0, -tau), min(300, 280 - tau)
+        return sum((Fraction(float(xf[m])) * Fraction(float(yf[m + tau])) for m in range(lo, hi)), Fraction(0))
+
+    lags = [-299, -150, -3, 0, 1, 17, 200, 279]
+    ex = {t: exact(t) for t in lags}
+    for a in lags:
+        assert oracle.compare_real_xcorr(xf, yf, a, a) == 0
+        for b in lags:
+            want = (ex[a] > ex[b]) - (ex[a] < ex[b])
+            assert oracle.compare_real_xcorr(xf, yf, a, b) == want
+    best = max(ex.values())
+    assert oracle.refine_ties(xf, yf, lags)[0] == [t for t in lags if ex[t] == best]
+    # reading for non-finite samples: a NaN or Inf inside a tied lag's
+    # overlap leaves the tied set unchanged; outside every overlap it does not matter
+    xn = x.copy()
+    xn[7] = np.nan
+    assert oracle.refine_ties(xn, y, [10, 20]) == ([10, 20], False)
+    assert oracle.refine_ties(x, y, [5]) == ([5], True)
+    yi = y.copy()
+    yi[63] = np.inf          # inside the overlap of lag 10 (m = 53)
+    assert oracle.refine_ties(x, yi, [10, 20]) == ([10, 20], False)
+    yj = np.concatenate([y, [np.inf]]).astype(np.float32)   # y[64]: inside lag 10's overlap (m = 54)
+    assert oracle.refine_ties(x, yj, [10, 20])[1] is False
+    assert oracle.refine_ties(x[:40], yj, [10, 20]) == ([10], True)   # m + 20 < 60: y[64] is outside both overlaps
+
+
+def test_estimate_refined_partial_and_planted():
+    """estimate_refined on the planted near-tie plus y[25] = 2^-10: the sign
+    codes' correlation ties at lags 10, 15 and 20 (value 2), the exact real
+    correlation is 2^60 + 1 at lag 10, 2^31 at 15 and 2^60 + 2^-10 at 20, so
+    the refined set is {10}; max_ties cuts the tied list to its smallest lags."""
+    x, y = _planted_real_near_tie()
+    y[25] = 2.0 ** -10
+    res = oracle.estimate_refined(x, y, 1, 0, 40)
+    tied = (np.nonzero(res["r"] == res["rmax"])[0]).tolist()
+    assert 10 in tied and 20 in tied and res["n_ties"] == len(tied) >= 2
+    assert res["lag_set"] == [10] and res["refined"] and not res["partial"]
+    cut = oracle.estimate_refined(x, y, 1, 0, 40, max_ties=1 + tied.index(10))
+    assert cut["partial"] == (len(tied) > 1 + tied.index(10))
 
 
 # ---------------------------------------------------------- streaming -------
