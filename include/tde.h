@@ -75,6 +75,10 @@ extern "C" {
 #define TDE_FLAG_FALLBACK   16   /* learned mode: proposal margin too low, full search used */
 #define TDE_FLAG_REFINED    32   /* tde_refine_ties chose among several maximisers */
 #define TDE_FLAG_REFINE_PARTIAL 64  /* more maximisers than max_ties: the smallest max_ties were refined */
+#define TDE_FLAG_SCALE_EXACT 128  /* an automatic scale needed the exact sum of squares (the float64
+                                     tree sum's error bound straddled a float32 rounding boundary) */
+#define TDE_FLAG_REFINE_EXACT 256 /* tde_refine_ties compared tied lags by exact sums */
+#define TDE_FLAG_REFINE_NONFINITE 512  /* a tied lag's overlap held NaN or Inf: peak left unrefined */
 
 typedef struct tde_ctx tde_ctx;
 
@@ -121,15 +125,18 @@ const char* tde_last_error(void);
  *            The 2K+1 cells tile [-3 sigma, 3 sigma] when
  *            inv_step = (2K+1) / (6 sigma).
  *  inv_step <= 0 selects the automatic scale: sigma = sqrt(S / n) with S the
- *            sum of x^2 over the finite samples, each square exact in float64,
- *            summed in float64 over a fixed binary tree (the list of squares
- *            zero-padded to a power-of-two length, adjacent pairs added level
- *            by level); inv_step = fl32((2K+1) / (6 sigma)), or 0 when S = 0
- *            (then every code is 0). The scale used is written to
- *            stat->inv_step.
+ *            exact sum of x^2 over the finite samples rounded once to
+ *            float64 (nearest, ties to even; it depends on no summation
+ *            order); inv_step = fl32((2K+1) / (6 sigma)) in float64
+ *            operations, or 0 when S = 0 (then every code is 0). The scale
+ *            used is written to stat->inv_step. The library adds the squares
+ *            in float64 and forms the exact sum only when that sum's error
+ *            bound leaves inv_step undecided (stat->flags then carries
+ *            TDE_FLAG_SCALE_EXACT).
  *  stat (device, may be NULL) receives the tde_qstat of the signal.
  * Errors: TDE_ERR_ARG for n < 1, a null x/q, bits not in {1,2,4,8}, or a
- * non-finite inv_step. ws: tde_quantize_workspace_size(n) bytes (may be 0
+ * non-finite inv_step; TDE_ERR_UNSUPPORTED for the automatic scale of
+ * n >= 2^32 samples. ws: tde_quantize_workspace_size(n) bytes (may be 0
  * when inv_step > 0 and stat is NULL). */
 size_t tde_quantize_workspace_size(int64_t n);
 int tde_quantize(tde_ctx* ctx, const float* x, int64_t n, int bits, float inv_step,
@@ -207,13 +214,18 @@ int tde_argmax_lag(tde_ctx* ctx, const void* r, int r_dtype, int64_t lag_lo, int
  * signals x, y (device)) is evaluated at the tied lags of r (device, the
  * lags [lag_lo, lag_hi] in r_dtype) and *peak becomes {smallest lag of the
  * refined set, the same integer rmax, size of the refined set, flags |
- * TDE_FLAG_REFINED}. The real correlation is summed in float64 over a fixed
- * binary tree (products exact, ascending m zero-padded to a power of two,
- * adjacent pairs level by level), so the choice is reproducible. At most
- * max_ties tied lags (the smallest ones, 2 <= max_ties <= 65536) are
+ * TDE_FLAG_REFINED}. The refined set is the tied lags whose EXACT real
+ * correlation is largest (no summation order enters): float64 sums with a
+ * rigorous error bound decide where they can, exact sums of the products
+ * (each product of two float32 values is an integer times 2^-298) decide the
+ * rest (then TDE_FLAG_REFINE_EXACT is also set). If any tied lag's overlap
+ * holds a NaN or Inf sample, the real correlations cannot be compared: the
+ * peak keeps its lag and n_ties and gains TDE_FLAG_REFINE_NONFINITE only. At
+ * most max_ties tied lags (the smallest ones, 2 <= max_ties <= 65536) are
  * considered; more set TDE_FLAG_REFINE_PARTIAL. A peak with n_ties <= 1 is
- * left unchanged. Errors: TDE_ERR_ARG, TDE_ERR_WS, TDE_ERR_UNSUPPORTED when
- * min(nx, ny) > 2^22. ws: tde_refine_workspace_size(max_ties) bytes. */
+ * left unchanged. Errors: TDE_ERR_ARG (also for more than 2^31 - 1 lags),
+ * TDE_ERR_WS, TDE_ERR_UNSUPPORTED when min(nx, ny) > 2^22.
+ * ws: tde_refine_workspace_size(max_ties) bytes. */
 size_t tde_refine_workspace_size(int max_ties);
 int tde_refine_ties(tde_ctx* ctx, const float* x, int64_t nx, const float* y, int64_t ny, const void* r,
                     int r_dtype, int64_t lag_lo, int64_t lag_hi, tde_peak* peak, int max_ties, void* ws,

@@ -1,13 +1,16 @@
 // Algorithm 1, quantization step: per-signal scale and monotone integer quantization.
 //
-// Scale: S = sum of x^2 over finite samples, every square exact in float64,
-// summed in float64 over a fixed binary tree (zero-padded to a power-of-two
-// length, adjacent pairs added level by level). sigma = sqrt(S / n),
-// inv_step = fl32((2K+1) / (6 sigma)). The tree maps onto the GPU directly:
-// pairs inside a lane, then wave shuffles (lane l with l ^ k, lower lane on
-// the left; float64 addition is commutative, so either order gives the same
-// bits), then LDS across waves and blocks; every subtree is aligned to its
-// own power-of-two boundary, so the split into kernels does not change it.
+// Scale: S = sum of x^2 over the finite samples is an exact real (the
+// quantizer on [-3 sigma, 3 sigma] fixes no summation order); the scale is
+// sigma = sqrt(fl64(S) / n), inv_step = fl32((2K+1) / (6 sigma)) with fl64(S)
+// the exact S rounded once. The kernels add the squares (each exact in
+// float64) in float64 over a binary tree: pairs inside a lane, wave
+// shuffles, then LDS across waves and blocks. That sum S' satisfies
+// |S' - S| <= 2^-45 S (exact_sum.h), and inv_step is a non-increasing
+// function of S (every operation is correctly rounded and monotone), so
+// when the ends of [S'(1 - 2^-45), S'(1 + 2^-45)] give the same inv_step,
+// fl64(S) does too. Otherwise the workgroup forms S exactly (integer digits)
+// and rounds it once; the statistics then carry TDE_FLAG_SCALE_EXACT.
 //
 // Quantizer: bits = 1 is sign with sign(0) = 0 (Section 4.2), taken from the
 // IEEE bits; bits in {2,4,8} is clamp(round_half_even(fl32(x * inv_step)),
@@ -135,6 +138,55 @@ __device__ __forceinline__ float scale_of_sum(double S, int64_t n, int bits) {
     return (float)v;
 }
 
+// The scale from a float64 tree sum St of the squares, if St's error bound
+// decides it (St = 0 only when every square is 0, so S = 0 exactly).
+__device__ __forceinline__ bool scale_decided(double St, int64_t n, int bits, float& inv) {
+    if (!(St > 0.0)) {
+        inv = 0.f;
+        return true;
+    }
+    const float a = scale_of_sum(St * (1.0 - kTreeRelErr), n, bits);
+    const float b = scale_of_sum(St * (1.0 + kTreeRelErr), n, bits);
+    inv = a;
+    return a == b;
+}
+
+// The exact sum of squares of the finite samples of x[0 .. n), n < 2^32,
+// rounded once to float64, by the whole workgroup (every thread calls it).
+// Each square is split into base-2^32 digits (exact_sum.h) that are added
+// to one LDS row of limbs with 64-bit atomics; a limb receives at most one
+// digit (< 2^32) per sample, so it stays below 2^64.
+__device__ double exact_sumsq_wg(const float* x, int64_t n) {
+    __shared__ unsigned long long acc[kExactLimbs];
+    __shared__ double res;
+    for (int i = threadIdx.x; i < kExactLimbs; i += blockDim.x) acc[i] = 0ull;
+    __syncthreads();
+    for (int64_t m = threadIdx.x; m < n; m += blockDim.x) {
+        const float f = x[m];
+        if (!__builtin_isfinite(f) || f == 0.f) continue;
+        int li;
+        uint32_t d0, d1, d2;
+        exact_digits(exact_term(f, f), li, d0, d1, d2);
+        atomicAdd(&acc[li], (unsigned long long)d0);
+        if (d1) atomicAdd(&acc[li + 1], (unsigned long long)d1);
+        if (d2) atomicAdd(&acc[li + 2], (unsigned long long)d2);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // unsigned carries first (a limb may exceed 2^63), then the digits
+        int64_t v[kExactLimbs];
+        unsigned long long carry = 0ull;
+        for (int i = 0; i < kExactLimbs; ++i) {
+            const unsigned long long a = acc[i] + carry;   // below 2^64: a limb plus a carry below 2^32
+            v[i] = (int64_t)(a & 0xffffffffull);
+            carry = a >> 32;
+        }
+        res = exact_to_double(v);
+    }
+    __syncthreads();
+    return res;
+}
+
 // The whole sum tree of a signal of at most kFuseMaxN samples (at most 256
 // block sums) in one wave: lane l adds block sums 4l .. 4l+3 pairwise, then
 // wave shuffles take the levels above. Zeros beyond the last block sum extend
@@ -162,6 +214,7 @@ __global__ void __launch_bounds__(256) k_scale_finalize(const QSig* sigs, int ns
     // scratch counters of a later kernel of the same call start at zero
     if (blockIdx.x == 0 && zero_me && t < nzero) zero_me[t] = 0;
     float inv;
+    int exact = 0;
     if (s.bits == 1) {
         inv = 0.f;
     } else if (s.inv_fixed > 0.f) {
@@ -205,13 +258,16 @@ __global__ void __launch_bounds__(256) k_scale_finalize(const QSig* sigs, int ns
             out = a + nn;
             len = nn;
         }
-        inv = scale_of_sum(a[0], s.n, s.bits);
+        if (!scale_decided(a[0], s.n, s.bits, inv)) {
+            inv = scale_of_sum(exact_sumsq_wg(s.x, s.n), s.n, s.bits);
+            exact = TDE_FLAG_SCALE_EXACT;
+        }
     }
     if (t == 0) {
         if (s.inv_out) *s.inv_out = inv;
         if (s.stat) {
             s.stat->inv_step = inv;
-            s.stat->flags = 0;
+            s.stat->flags = exact;
             s.stat->n_nonfinite = 0;
             s.stat->n_zero = 0;
             s.stat->sum_q = 0;
@@ -263,18 +319,26 @@ __global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QS
     // would make the compiler reload its fields after every store
     const QSig s = pick_sig(sigs, nsig, one, bps, blk, lb);
     float inv;
+    int exact = 0;
     if (s.bits == 1) {
         inv = 0.f;
     } else if (s.inv_fixed > 0.f) {
         inv = s.inv_fixed;
     } else if (fused) {
-        inv = scale_of_sum(wave_tree_sum(s.gsum, s.n), s.n, s.bits);
+        // every block of the signal decides alike (same tree, same bound)
+        if (!scale_decided(wave_tree_sum(s.gsum, s.n), s.n, s.bits, inv)) {
+            inv = scale_of_sum(exact_sumsq_wg(s.x, s.n), s.n, s.bits);
+            exact = TDE_FLAG_SCALE_EXACT;
+        }
     } else {
         inv = *s.inv_out;
     }
     if (fused && lb == 0 && threadIdx.x == 0) {
         if (s.inv_out) *s.inv_out = inv;
-        if (s.stat) s.stat->inv_step = inv;
+        if (s.stat) {
+            s.stat->inv_step = inv;
+            s.stat->flags = exact;
+        }
     }
     const int K = s.bits == 1 ? 1 : (1 << (s.bits - 1)) - 1;
     const int64_t base = lb * kQuantBlock;
@@ -383,7 +447,7 @@ __global__ void k_quantize_flags(const QSig* sigs, int nsig, QSig one) {
     if (i >= nsig) return;
     const QSig& s = sigs ? sigs[i] : one;
     if (!s.stat) return;
-    int f = 0;
+    int f = s.stat->flags & TDE_FLAG_SCALE_EXACT;
     if (s.stat->n_nonfinite) f |= TDE_FLAG_NONFINITE_X;
     if (s.stat->n_zero == s.n) f |= TDE_FLAG_ZERO_X;
     s.stat->flags = f;

@@ -165,6 +165,23 @@ int choose_path(int path, int64_t nu, int64_t nv, int kuv, int kmax, int64_t lo,
 }
 
 }  // namespace
+
+// Scratch of tde_refine_ties, carved in this order; with ws = nullptr only
+// the size is computed.
+RefineWs refine_ws_carve(void* ws, int max_ties, size_t* bytes) {
+    Carve cv(ws);
+    RefineWs w;
+    w.lags = static_cast<int64_t*>(cv.take((size_t)max_ties * 8));
+    w.vals = static_cast<double*>(cv.take((size_t)max_ties * 8));
+    w.errs = static_cast<double*>(cv.take((size_t)max_ties * 8));
+    w.cand = static_cast<int*>(cv.take((size_t)max_ties * 4));
+    w.ncand = static_cast<int*>(cv.take(sizeof(int)));
+    w.count = static_cast<int*>(cv.take(sizeof(int)));
+    w.hits = static_cast<int*>(cv.take((size_t)kRefineMaxChunks * sizeof(int)));
+    w.limbs = static_cast<int64_t*>(cv.take((size_t)max_ties * kExactLimbs * 8));
+    if (bytes) *bytes = cv.off;
+    return w;
+}
 }  // namespace tde
 
 using namespace tde;
@@ -286,8 +303,12 @@ int tde_quantize_ex(tde_ctx* ctx, const float* x, int64_t n, int bits, int quant
         return set_error(TDE_ERR_ARG, "tde_quantize: quantizer %d", quantizer);
     if (quantizer != TDE_QUANT_UNIFORM && bits == 8)
         return set_error(TDE_ERR_UNSUPPORTED, "tde_quantize: non-uniform quantizers take bits 1, 2 or 4");
-    if (!ctx) return set_error(TDE_ERR_ARG, "tde_quantize: null context");
     const bool need_scale = bits != 1 && !(inv_step > 0.f);
+    // the exact sum of squares behind an undecided automatic scale counts
+    // at most 2^32 - 1 digits per limb
+    if (need_scale && n >= ((int64_t)1 << 32))
+        return set_error(TDE_ERR_UNSUPPORTED, "tde_quantize: automatic scale of 2^32 or more samples");
+    if (!ctx) return set_error(TDE_ERR_ARG, "tde_quantize: null context");
     QSig one{};
     one.x = x;
     one.n = n;
@@ -519,8 +540,9 @@ int tde_argmax_lag(tde_ctx* ctx, const void* r, int r_dtype, int64_t lag_lo, int
 
 size_t tde_refine_workspace_size(int max_ties) {
     if (max_ties < 2 || max_ties > 65536) return 0;
-    return align_bytes((size_t)max_ties * 8) * 2 + align_bytes(sizeof(int)) +
-           align_bytes((size_t)kRefineMaxChunks * sizeof(int));
+    size_t bytes = 0;
+    refine_ws_carve(nullptr, max_ties, &bytes);
+    return bytes;
 }
 
 int tde_refine_ties(tde_ctx* ctx, const float* x, int64_t nx, const float* y, int64_t ny, const void* r,
@@ -529,6 +551,9 @@ int tde_refine_ties(tde_ctx* ctx, const float* x, int64_t nx, const float* y, in
     if (!x || !y || !r || !peak) return set_error(TDE_ERR_ARG, "tde_refine_ties: null pointer");
     if (nx < 1 || ny < 1) return set_error(TDE_ERR_ARG, "tde_refine_ties: empty signal");
     if (lag_lo > lag_hi) return set_error(TDE_ERR_ARG, "tde_refine_ties: lag_lo > lag_hi");
+    // tie counts and chunk offsets are int
+    if (lag_hi - lag_lo >= ((int64_t)1 << 31) - 1)
+        return set_error(TDE_ERR_ARG, "tde_refine_ties: more than 2^31 - 1 lags");
     if (r_dtype != TDE_I32 && r_dtype != TDE_I64) return set_error(TDE_ERR_ARG, "tde_refine_ties: bad r_dtype");
     if (max_ties < 2 || max_ties > 65536) return set_error(TDE_ERR_ARG, "tde_refine_ties: max_ties in [2, 65536]");
     if (std::min(nx, ny) > ((int64_t)1 << 22))
@@ -542,13 +567,8 @@ int tde_refine_ties(tde_ctx* ctx, const float* x, int64_t nx, const float* y, in
         std::lock_guard<std::mutex> lock(ctx->mu);
         drop_graphs_on(ctx, ws, ws_bytes);
     }
-    Carve cv(ws);
-    int64_t* lags = static_cast<int64_t*>(cv.take((size_t)max_ties * 8));
-    double* vals = static_cast<double*>(cv.take((size_t)max_ties * 8));
-    int* count = static_cast<int*>(cv.take(sizeof(int)));
-    int* hits = static_cast<int*>(cv.take((size_t)kRefineMaxChunks * sizeof(int)));
-    return launch_refine(x, nx, y, ny, r, r_dtype, lag_lo, lag_hi - lag_lo + 1, peak, max_ties, lags, vals, count,
-                         hits, static_cast<hipStream_t>(stream));
+    return launch_refine(x, nx, y, ny, r, r_dtype, lag_lo, lag_hi - lag_lo + 1, peak, max_ties,
+                         refine_ws_carve(ws, max_ties, nullptr), static_cast<hipStream_t>(stream));
 }
 
 // --------------------------------------------------------------- batch --
@@ -604,6 +624,10 @@ int validate_pairs(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
                              (long long)i);
         if (!std::isfinite(q.inv_step_x) || !std::isfinite(q.inv_step_y))
             return set_error(TDE_ERR_ARG, "pair %lld: non-finite inv_step", (long long)i);
+        if (q.bits != 1 && ((!(q.inv_step_x > 0.f) && q.nx >= ((int64_t)1 << 32)) ||
+                            (!(q.inv_step_y > 0.f) && q.ny >= ((int64_t)1 << 32))))
+            return set_error(TDE_ERR_UNSUPPORTED, "pair %lld: automatic scale of 2^32 or more samples",
+                             (long long)i);
         if (q.r_out) {
             if (q.r_dtype != TDE_I32 && q.r_dtype != TDE_I64)
                 return set_error(TDE_ERR_ARG, "pair %lld: bad r_dtype", (long long)i);

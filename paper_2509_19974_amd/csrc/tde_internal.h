@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/tde.h"
+#include "exact_sum.h"
 
 namespace tde {
 
@@ -146,6 +147,8 @@ int launch_quantize(const QSig* sigs_dev, const QSig& one, int nsig, int64_t tot
 // Result flags of a pair from the statistics of its two signals.
 __device__ inline int peak_flags(const tde_qstat* sx, int64_t nx, const tde_qstat* sy, int64_t ny) {
     int f = 0;
+    if ((sx && (sx->flags & TDE_FLAG_SCALE_EXACT)) || (sy && (sy->flags & TDE_FLAG_SCALE_EXACT)))
+        f |= TDE_FLAG_SCALE_EXACT;
     if (sx) {
         if (sx->n_nonfinite) f |= TDE_FLAG_NONFINITE_X;
         if (sx->n_zero == nx) f |= TDE_FLAG_ZERO_X;
@@ -301,12 +304,23 @@ int launch_copy_bytes(void* dst, const void* src, size_t n, hipStream_t s);
 int launch_xcorr_win(const XItem* items_dev, int npairs, const int32_t* top, const float* margin, float theta,
                      int topk, int nb, ArgPart* parts, hipStream_t s);
 
-// tie refinement (Algorithm 1, tie-refinement step); hits: kRefineMaxChunks
-// ints of scratch for the per-chunk counts of the collect
+// tie refinement (Algorithm 1, tie-refinement step): scratch of one call,
+// every array sized for max_ties lags except hits (kRefineMaxChunks per-chunk
+// counts of the collect) and limbs (kExactLimbs int64 per lag)
 constexpr int kRefineMaxChunks = 4096;
+struct RefineWs {
+    int64_t* lags;        // collected tied lags
+    double* vals;         // float64 tree sums of the real correlation
+    double* errs;         // their error bounds
+    int* cand;            // lags (indices into lags) that still need exact sums
+    int* ncand;
+    int* count;           // tied lags in r
+    int* hits;
+    int64_t* limbs;       // exact sums of the candidates
+};
+RefineWs refine_ws_carve(void* ws, int max_ties, size_t* bytes);
 int launch_refine(const float* x, int64_t nx, const float* y, int64_t ny, const void* r, int dtype, int64_t lag_lo,
-                  int64_t L, tde_peak* peak, int max_ties, int64_t* lags, double* vals, int* count, int* hits,
-                  hipStream_t s);
+                  int64_t L, tde_peak* peak, int max_ties, const RefineWs& w, hipStream_t s);
 
 // ---------------------------------------------------------- auto engine --
 // HIP device of a context.

@@ -38,6 +38,9 @@ TDE_FLAG_ZERO_Y = 8
 TDE_FLAG_FALLBACK = 16
 TDE_FLAG_REFINED = 32
 TDE_FLAG_REFINE_PARTIAL = 64
+TDE_FLAG_SCALE_EXACT = 128
+TDE_FLAG_REFINE_EXACT = 256
+TDE_FLAG_REFINE_NONFINITE = 512
 
 PEAK_DTYPE = np.dtype([("lag", "<i8"), ("rmax", "<i8"), ("n_ties", "<i4"), ("flags", "<i4")])
 QSTAT_DTYPE = np.dtype([("inv_step", "<f4"), ("flags", "<i4"), ("n_nonfinite", "<i8"), ("n_zero", "<i8"),

@@ -191,6 +191,30 @@ def test_quantize_argument_validation():
     assert q(inv=float("inf")) == tde.TDE_ERR_ARG
     assert q(x=None) == tde.TDE_ERR_ARG
     assert q() == tde.TDE_ERR_ARG and "null context" in tde.tde_last_error()
+    # the automatic scale's exact fallback counts digits per limb in 64 bits
+    assert q(n=1 << 32, inv=0.0) == tde.TDE_ERR_UNSUPPORTED
+    assert q(n=1 << 32, inv=1.0) == tde.TDE_ERR_ARG and "null context" in tde.tde_last_error()
+    assert q(n=1 << 32, inv=0.0, bits=1) == tde.TDE_ERR_ARG
+
+
+def test_refine_argument_validation():
+    lib = tde.load_library()
+    ws_need = lib.tde_refine_workspace_size(16)
+    assert ws_need > 16 * 160       # exact sums: 20 int64 limbs per tied lag
+    assert lib.tde_refine_workspace_size(1) == 0 and lib.tde_refine_workspace_size(65537) == 0
+
+    def st(**k):
+        return lib.tde_refine_ties(None, FAKE, k.get("nx", 100), FAKE, k.get("ny", 100), FAKE, k.get("dt", 1),
+                                   k.get("lo", -99), k.get("hi", 99), FAKE, k.get("mt", 16), FAKE,
+                                   k.get("ws", ws_need), None)
+    assert st(lo=5, hi=4) == tde.TDE_ERR_ARG
+    assert st(mt=1) == tde.TDE_ERR_ARG
+    assert st(dt=3) == tde.TDE_ERR_ARG
+    # tie counts are int: at most 2^31 - 1 lags
+    assert st(lo=0, hi=(1 << 31) - 2) == tde.TDE_ERR_ARG and "null context" in tde.tde_last_error()
+    assert st(lo=0, hi=(1 << 31) - 1) == tde.TDE_ERR_ARG and "2^31" in tde.tde_last_error()
+    assert st(nx=(1 << 22) + 1, ny=(1 << 22) + 1) == tde.TDE_ERR_UNSUPPORTED
+    assert st(ws=ws_need - 1) == tde.TDE_ERR_WS
 
 
 def test_batch_argument_validation():

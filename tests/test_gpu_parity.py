@@ -1,8 +1,9 @@
 """GPU parity of the HIP path against the CPU oracle, through the C ABI.
 
 Integer results (codes, r, lags, maxima, tie counts) must be bit-exact. The
-scale of the uniform quantizer is a float computation with a fixed order, so
-the automatic scale must also match the oracle's bit for bit."""
+automatic scale of the uniform quantizer is a function of the exact sum of
+squares, and the tie refinement compares exact real correlations, so both
+must also match the oracle's bit for bit."""
 import sys
 
 import numpy as np
@@ -62,6 +63,97 @@ def test_quantize_auto_scale_parity(T, ctx, n, bits):
     assert st["n_zero"] == int(np.count_nonzero(qo == 0))
     assert st["sum_q"] == int(qo.astype(np.int64).sum())
     assert st["sum_q2"] == int((qo.astype(np.int64) ** 2).sum())
+
+
+def _scale_flip(n, bits, rng):
+    """Consecutive float64 values S_lo < S_hi (integers near 2^60) of the sum
+    of squares between which the oracle's inv_step changes: its float32
+    rounding flips there."""
+    import math
+    K = oracle.kmax(bits)
+    S0 = 2.0 ** 60 * rng.uniform(1.0, 2.0)
+    f = np.float32((2 * K + 1) / (6 * math.sqrt(S0 / n)))
+    m = (float(f) + float(np.nextafter(f, np.float32(0)))) / 2       # a float32 midpoint, exact in float64
+    g = lambda S: oracle.inv_step_from_sumsq(S, n, bits)
+    a = n * ((2 * K + 1) / (6 * m)) ** 2
+    step = np.inf if g(a) == float(f) else -np.inf
+    for _ in range(10000):
+        b = np.nextafter(a, step)
+        if g(b) != g(a):
+            break
+        a = b
+    lo, hi = (a, b) if step > 0 else (b, a)
+    assert g(lo) != g(hi)
+    return int(lo), int(hi)
+
+
+def _float32_squares(T):
+    """float32 values whose exact squares sum to the integer T (greedy)."""
+    import math
+    out = []
+    while T > 0:
+        r = math.isqrt(T)
+        a = np.float32(r)
+        if int(a) > r:
+            a = np.nextafter(a, np.float32(0))
+        out.append(int(a))
+        T -= int(a) * int(a)
+    return out
+
+
+def _planted_scale_signal(T_sum, n, rng):
+    vals = _float32_squares(T_sum)
+    x = np.zeros(n, np.float32)
+    pos = rng.choice(n, len(vals), replace=False)
+    x[pos] = np.asarray(vals, np.float64) * rng.choice([-1.0, 1.0], len(vals))
+    assert sum(int(v) ** 2 for v in np.abs(x[pos]).astype(np.int64)) == T_sum
+    return x
+
+
+@pytest.mark.parametrize("n", [5000, 300000])
+@pytest.mark.parametrize("bits", [2, 4, 8])
+def test_quantize_auto_scale_at_rounding_flips(T, ctx, n, bits):
+    """Signals whose exact sum of squares sits at a float32 rounding flip of
+    inv_step: exactly at the float64 values on either side, at their midpoint
+    (ties to even) and one unit off it. No float64 summation order can be
+    trusted here; the library must take the exact sum (flag set) and match
+    the oracle's exactly rounded S bit for bit."""
+    from paper_2509_19974_amd import tde
+    rng = np.random.default_rng(n + bits)
+    lo, hi = _scale_flip(n, bits, rng)
+    mid = (lo + hi) // 2
+    for Tsum in (lo, hi, mid, mid - 1, mid + 1):
+        x = _planted_scale_signal(Tsum, n, rng)
+        say(f"scale flip n={n} bits={bits} S={Tsum}")
+        q, stat = ctx.quantize(dev(T, x), bits, 0.0)
+        T.cuda.synchronize()
+        qo, nf, so = oracle.quantize(x, bits)
+        st = tde.decode_qstat(stat)[0]
+        assert st["inv_step"] == np.float32(so)
+        assert st["flags"] & tde.TDE_FLAG_SCALE_EXACT
+        np.testing.assert_array_equal(q.cpu().numpy(), qo)
+
+
+def test_batch_auto_scale_at_rounding_flip(T, ctx):
+    """The same planted sums through the batch call: every pair's peak equals
+    the oracle's and carries the exact-scale flag."""
+    from paper_2509_19974_amd import tde
+    rng = np.random.default_rng(77)
+    n, pairs = 4096, []
+    for bits in (2, 4, 8):
+        lo, hi = _scale_flip(n, bits, rng)
+        for Tsum in (lo, hi, (lo + hi) // 2):
+            x = _planted_scale_signal(Tsum, n, rng)
+            y = np.roll(x, 37) + (rng.standard_normal(n) * 1e6).astype(np.float32)
+            pairs.append(dict(x=x, y=y.astype(np.float32), bits=bits, lag_lo=-200, lag_hi=200))
+    specs = [dict(x=dev(T, p["x"]), y=dev(T, p["y"]), lag_lo=p["lag_lo"], lag_hi=p["lag_hi"], bits=p["bits"])
+             for p in pairs]
+    pk = tde.decode_peaks(ctx.estimate_batch(specs))
+    T.cuda.synchronize()
+    for i, p in enumerate(pairs):
+        ref = oracle.estimate(p["x"], p["y"], p["bits"], p["lag_lo"], p["lag_hi"])
+        assert (pk[i]["lag"], pk[i]["rmax"], pk[i]["n_ties"]) == (ref["lag"], ref["rmax"], ref["n_ties"]), i
+        assert pk[i]["flags"] & tde.TDE_FLAG_SCALE_EXACT, i
 
 
 @pytest.mark.parametrize("bits", [2, 4, 8])
@@ -922,8 +1014,9 @@ def _refine_case(T, ctx, x, y, bits, lo, hi, max_ties=4096):
 @pytest.mark.parametrize("seed", range(6))
 def test_refine_ties_matches_algorithm1_refinement(T, ctx, seed):
     """Sign quantization of short signals gives many integer ties; the
-    refinement must return the oracle's refined set (Algorithm 1, tie-refinement step,
-    float64 in the fixed pairwise order): its smallest lag and its size."""
+    refinement must return the oracle's refined set (Algorithm 1,
+    tie-refinement step, exact real correlations): its smallest lag and its
+    size."""
     from paper_2509_19974_amd import tde
     rng = np.random.default_rng(100 + seed)
     n = int(rng.integers(20, 400))
@@ -957,9 +1050,9 @@ def test_refine_partial_and_exact_shift(T, ctx):
     assert after["flags"] & tde.TDE_FLAG_REFINE_PARTIAL
     r = oracle.xcorr(oracle.quantize(x, 1)[0], oracle.quantize(y, 1)[0], -69, 2999)
     tied = (np.nonzero(r == r.max())[0] - 69)[:4]
-    vals = oracle.xcorr_f64_at_pairwise(x, y, tied)
-    best = tied[vals == vals.max()]
-    assert (after["lag"], after["n_ties"]) == (best.min(), best.size)
+    best, done = oracle.refine_ties(x, y, tied)
+    assert done
+    assert (after["lag"], after["n_ties"]) == (min(best), len(best))
     # exact shift with a positive gain: the real correlation has a strict maximum at nu
     s = rng.standard_normal(2000)
     nu = 137
@@ -1001,9 +1094,9 @@ def test_refine_planted_ties_long_signals(T, ctx, n, ntie, max_ties, rdt):
     T.cuda.synchronize()
     out = tde.decode_peaks(peak)[0]
     tied = idx[:max_ties] + lo
-    vals = oracle.xcorr_f64_at_pairwise(x, y, tied)
-    best = tied[vals == vals.max()]
-    assert (out["lag"], out["rmax"], out["n_ties"]) == (best.min(), 99, best.size)
+    best, done = oracle.refine_ties(x, y, tied)
+    assert done
+    assert (out["lag"], out["rmax"], out["n_ties"]) == (min(best), 99, len(best))
     assert out["flags"] & tde.TDE_FLAG_REFINED
     assert bool(out["flags"] & tde.TDE_FLAG_REFINE_PARTIAL) == (ntie > max_ties)
 
@@ -1027,10 +1120,108 @@ def test_refine_exact_real_ties_long(T, ctx):
     T.cuda.synchronize()
     out = tde.decode_peaks(peak)[0]
     tied = idx[:4096] + lo
-    vals = oracle.xcorr_f64_at_pairwise(x, y, tied)
-    best = tied[vals == vals.max()]
-    assert (out["lag"], out["n_ties"]) == (best.min(), best.size)
+    best, done = oracle.refine_ties(x, y, tied)
+    assert done
+    assert (out["lag"], out["n_ties"]) == (min(best), len(best))
     assert out["flags"] & tde.TDE_FLAG_REFINE_PARTIAL
+    assert out["flags"] & tde.TDE_FLAG_REFINE_EXACT      # equal reals: only exact sums can say so
+
+
+def _refine_planted(T, ctx, x, y, tied, max_ties=4096):
+    """Peak with the given tied lags planted in r (value 5) over the full
+    lag range; returns the refined peak record."""
+    from paper_2509_19974_amd import tde
+    lo, hi = -(x.size - 1), y.size - 1
+    r = np.zeros(hi - lo + 1, np.int64)
+    idx = np.sort(np.asarray(tied, np.int64)) - lo
+    r[idx] = 5
+    peak = _planted_peak(T, tde, idx, lo, 5)
+    ctx.refine(dev(T, x), dev(T, y), dev(T, r), lo, hi, peak, max_ties=max_ties)
+    T.cuda.synchronize()
+    return tde.decode_peaks(peak)[0]
+
+
+def _two_term_signals(n, ta, tb, ca, cb):
+    """x nonzero at 0 (2^30) and 5 (1); y puts 2^30 at ta and tb, and ca, cb
+    at ta + 5, tb + 5, so the real correlation is 2^60 + ca at lag ta and
+    2^60 + cb at lag tb: a float64 sum of 2^60 and a small term rounds it away."""
+    x = np.zeros(n, np.float32)
+    x[0], x[5] = 2.0 ** 30, 1.0
+    y = np.zeros(n, np.float32)
+    y[ta] = y[tb] = 2.0 ** 30
+    y[ta + 5], y[tb + 5] = ca, cb
+    return x, y
+
+
+@pytest.mark.parametrize("ca,cb,want", [(1.0, 0.0, "a"), (-1.0, 0.0, "b"), (3.0, 3.0, "ab"), (0.5, 0.25, "a"),
+                                        (-0.5, -0.25, "b")])
+def test_refine_planted_near_ties(T, ctx, ca, cb, want):
+    """Tied lags whose real correlations differ by far less than a float64
+    unit of their size (2^60 + 1 against 2^60, and the like): no float64
+    summation separates them, the exact comparison of Algorithm 1's
+    tie-refinement step does. The oracle decides by exact sums too."""
+    from paper_2509_19974_amd import tde
+    ta, tb = 40, 17
+    x, y = _two_term_signals(100, ta, tb, ca, cb)
+    say(f"refine near tie ca={ca} cb={cb}")
+    out = _refine_planted(T, ctx, x, y, [tb, ta])
+    best, done = oracle.refine_ties(x, y, [tb, ta])
+    assert done
+    assert best == {"a": [ta], "b": [tb], "ab": [tb, ta]}[want]
+    assert (out["lag"], out["n_ties"]) == (min(best), len(best))
+    assert out["flags"] & tde.TDE_FLAG_REFINED
+    assert out["flags"] & tde.TDE_FLAG_REFINE_EXACT
+
+
+def test_refine_many_candidates_exact(T, ctx):
+    """Hundreds of tied lags whose real correlations agree to about 2^-45
+    of their size (2^60 plus terms of at most a few 10^4): the float64 error
+    bounds cannot order them, so they go to exact sums, over overlaps long
+    enough that each exact sum spans many threads."""
+    from paper_2509_19974_amd import tde
+    rng = np.random.default_rng(31)
+    n = 30000
+    x = np.zeros(n, np.float32)
+    x[0] = 2.0 ** 30
+    x[1:] = rng.integers(-3, 4, n - 1).astype(np.float32) * np.float32(2.0 ** -20)
+    y = np.zeros(3 * n, np.float32)
+    tied = np.sort(rng.choice(np.arange(10, 2 * n), 300, replace=False))
+    y[tied] = 2.0 ** 30                     # the 2^60 term at every tied lag
+    # small products from a shared pattern, so the exact sums differ slightly
+    y[n:] = rng.integers(-2, 3, 2 * n).astype(np.float32)
+    y[tied] = 2.0 ** 30
+    say("refine many candidates")
+    out = _refine_planted(T, ctx, x, y, tied)
+    best, done = oracle.refine_ties(x, y, tied)
+    assert done
+    assert (out["lag"], out["n_ties"]) == (min(best), len(best))
+    assert out["flags"] & tde.TDE_FLAG_REFINE_EXACT
+
+
+def test_refine_nonfinite_overlap_leaves_peak(T, ctx):
+    """A NaN in the overlap of one tied lag: the real correlations cannot be
+    compared, so the peak keeps its lag and count (the oracle's reading) and
+    says why; a NaN outside every tied overlap changes nothing."""
+    from paper_2509_19974_amd import tde
+    ta, tb = 40, 17
+    x, y = _two_term_signals(100, ta, tb, 1.0, 0.0)
+    y2 = y.copy()
+    y2[ta + 50] = np.nan                    # inside the overlap at ta (m = 50)
+    out = _refine_planted(T, ctx, x, y2, [tb, ta])
+    best, done = oracle.refine_ties(x, y2, [tb, ta])
+    assert not done and best == [tb, ta]
+    assert (out["lag"], out["n_ties"]) == (tb, 2)
+    assert out["flags"] & tde.TDE_FLAG_REFINE_NONFINITE
+    assert not out["flags"] & tde.TDE_FLAG_REFINED
+    x2 = np.zeros(50, np.float32)
+    x2[0], x2[5] = 2.0 ** 30, 1.0
+    y3 = y.copy()
+    y3[95] = np.inf                         # overlaps: y[40 .. 90) at lag 40, y[17 .. 67) at lag 17
+    best3, done3 = oracle.refine_ties(x2, y3, [tb, ta])
+    assert done3 and best3 == [ta]
+    out3 = _refine_planted(T, ctx, x2, y3, [tb, ta])
+    assert (out3["lag"], out3["n_ties"]) == (ta, 1)
+    assert out3["flags"] & tde.TDE_FLAG_REFINED
 
 
 # ------------------------------------------------------------- streaming --
