@@ -377,7 +377,12 @@ int tde_model_get_params(tde_model* model, float* host, int64_t n);
 int tde_model_set_params(tde_model* model, const float* host, int64_t n);
 /* Gradient of the mean loss from the last tde_train_step (host copy). */
 int tde_model_gradients(tde_model* model, float* host, int64_t n);
-/* Binary file: magic, ld, nbins, count, then the float32 parameters. */
+/* Checkpoint file: magic "TDE2", ld, nbins, count, Adam step (int32), then
+ * the float32 parameters and Adam's first and second moments, so a training
+ * run resumed from it continues bit for bit. Load also takes the older
+ * parameters-only files (magic "TDE1"; the Adam state then restarts) and
+ * fails with TDE_ERR_IO for a file of another shape, a short or over-long
+ * file, or invalid moments. */
 int tde_model_save(tde_model* model, const char* path);
 int tde_model_load(tde_model* model, const char* path);
 

@@ -263,14 +263,27 @@ int tde_model_set_params(tde_model* M, const float* host, int64_t n) {
     return TDE_OK;
 }
 
+// Checkpoint: a header {magic "TDE2", ld, nbins, nparams, Adam step}, then
+// the float32 parameters and the Adam moments m and v, so a run resumed from
+// it continues bit for bit. Files with magic "TDE1" (parameters only) load
+// with the Adam state reset.
 int tde_model_save(tde_model* M, const char* path) {
     if (!M || !path) return set_error(TDE_ERR_ARG, "tde_model_save: null pointer");
-    std::vector<float> h(M->net.nparams);
-    int rc = tde_model_get_params(M, h.data(), M->net.nparams);
-    if (rc) return rc;
+    const size_t n = (size_t)M->net.nparams;
+    std::vector<float> h(3 * n);
+    int32_t step;
+    {
+        std::lock_guard<std::mutex> lock(M->mu);
+        Guard gd(M->device);
+        TDE_HIP_CHECK(hipDeviceSynchronize());
+        TDE_HIP_CHECK(hipMemcpy(h.data(), M->p, n * 4, hipMemcpyDeviceToHost));
+        TDE_HIP_CHECK(hipMemcpy(h.data() + n, M->m, n * 4, hipMemcpyDeviceToHost));
+        TDE_HIP_CHECK(hipMemcpy(h.data() + 2 * n, M->v, n * 4, hipMemcpyDeviceToHost));
+        step = M->step;
+    }
     FILE* f = fopen(path, "wb");
     if (!f) return set_error(TDE_ERR_IO, "tde_model_save: cannot open %s", path);
-    const int32_t head[4] = {0x31454454, M->net.ld, M->net.nb, M->net.nparams};   // "TDE1"
+    const int32_t head[5] = {0x32454454, M->net.ld, M->net.nb, M->net.nparams, step};   // "TDE2"
     bool ok = fwrite(head, sizeof(head), 1, f) == 1 && fwrite(h.data(), 4, h.size(), f) == h.size();
     ok = (fclose(f) == 0) && ok;
     return ok ? TDE_OK : set_error(TDE_ERR_IO, "tde_model_save: write to %s failed", path);
@@ -280,13 +293,29 @@ int tde_model_load(tde_model* M, const char* path) {
     if (!M || !path) return set_error(TDE_ERR_ARG, "tde_model_load: null pointer");
     FILE* f = fopen(path, "rb");
     if (!f) return set_error(TDE_ERR_IO, "tde_model_load: cannot open %s", path);
-    int32_t head[4];
-    std::vector<float> h(M->net.nparams);
-    bool ok = fread(head, sizeof(head), 1, f) == 1 && head[0] == 0x31454454 && head[1] == M->net.ld &&
-              head[2] == M->net.nb && head[3] == M->net.nparams && fread(h.data(), 4, h.size(), f) == h.size();
+    const size_t n = (size_t)M->net.nparams;
+    int32_t head[4], step = 0;
+    std::vector<float> h(3 * n);
+    bool ok = fread(head, sizeof(head), 1, f) == 1 && (head[0] == 0x31454454 || head[0] == 0x32454454) &&
+              head[1] == M->net.ld && head[2] == M->net.nb && head[3] == M->net.nparams;
+    const bool full = ok && head[0] == 0x32454454;
+    if (full) ok = fread(&step, 4, 1, f) == 1 && step >= 0;
+    if (ok) ok = fread(h.data(), 4, full ? 3 * n : n, f) == (full ? 3 * n : n);
+    if (ok) ok = fgetc(f) == EOF;        // nothing after the last value
     fclose(f);
     if (!ok) return set_error(TDE_ERR_IO, "tde_model_load: %s is not a model of this shape", path);
-    return tde_model_set_params(M, h.data(), M->net.nparams);
+    if (full)
+        for (size_t i = n; i < 3 * n; ++i)
+            if (!isfinite(h[i]) || (i >= 2 * n && h[i] < 0.f))
+                return set_error(TDE_ERR_IO, "tde_model_load: %s holds an invalid Adam moment", path);
+    int rc = tde_model_set_params(M, h.data(), M->net.nparams);     // resets m, v and the step
+    if (rc || !full) return rc;
+    std::lock_guard<std::mutex> lock(M->mu);
+    Guard gd(M->device);
+    TDE_HIP_CHECK(hipMemcpy(M->m, h.data() + n, n * 4, hipMemcpyHostToDevice));
+    TDE_HIP_CHECK(hipMemcpy(M->v, h.data() + 2 * n, n * 4, hipMemcpyHostToDevice));
+    M->step = step;
+    return TDE_OK;
 }
 
 int tde_model_forward(tde_ctx* ctx, tde_model* M, const uint16_t* xdec, int64_t B, float* logits, int topk,

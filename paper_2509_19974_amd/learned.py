@@ -52,19 +52,55 @@ def make_dataset(ctx, model, pair_chunks, log=None):
     return torch.cat(xs), torch.cat(ls)
 
 
-def train(ctx, model, xdec, labels, epochs: int, batch: int, lr: float, seed: int = 0, log=None):
-    """Adam over shuffled mini-batches; returns the mean loss per epoch."""
+def device_specs(x, y, bits: int, lag_lo: int, lag_hi: int):
+    """Batch specs for the rows of two device tensors [B][n] (one pair per row)."""
+    return [dict(x=x[i], y=y[i], lag_lo=lag_lo, lag_hi=lag_hi, bits=bits) for i in range(x.shape[0])]
+
+
+def make_dataset_device(ctx, model, chunks, npairs: int, bits: int, lag_lo: int, lag_hi: int, log=None):
+    """Training set generated and labelled on the device: `chunks` yields
+    (x, y) device tensors [B][n]; each chunk is labelled by the exact
+    full-range plain estimate and reduced to the proposer's decimated input,
+    so only the bf16 inputs (2 ld values per pair) and the labels are kept."""
+    torch = ctx.torch
+    xdec = torch.empty((npairs, 2, model.ld), dtype=torch.int16, device="cuda")
+    labels = torch.empty(npairs, dtype=torch.int32, device="cuda")
+    at = 0
+    for k, (x, y) in enumerate(chunks):
+        specs = device_specs(x, y, bits, lag_lo, lag_hi)
+        pk = plain_peaks(ctx, specs)
+        b = len(specs)
+        xdec[at:at + b] = model.prepare(specs)
+        labels[at:at + b] = torch.from_numpy(bins_of_lags(pk["lag"], model.nbins)).cuda()
+        at += b
+        if log and (k % 32 == 0 or at == npairs):
+            log(f"[learned] dataset: {at} of {npairs} pairs")
+        if at >= npairs:
+            break
+    return xdec[:at], labels[:at]
+
+
+def train(ctx, model, xdec, labels, epochs: int, batch: int, lr, seed: int = 0, log=None, loss_every: int = 64):
+    """Adam over shuffled mini-batches; lr is a number or one value per
+    epoch. Returns the mean loss per epoch (sampled every loss_every steps)."""
     torch = ctx.torch
     n = xdec.shape[0]
     g = torch.Generator(device="cpu").manual_seed(seed)
+    lrs = list(lr) if isinstance(lr, (list, tuple)) else [lr] * epochs
     hist = []
     for ep in range(epochs):
         perm = torch.randperm(n, generator=g).cuda()
         tot, cnt = 0.0, 0
-        for s in range(0, n - batch + 1, batch):
+        nsteps = n // batch
+        for k, s in enumerate(range(0, n - batch + 1, batch)):
             idx = perm[s:s + batch]
-            tot += model.train_step(xdec[idx].contiguous(), labels[idx].contiguous(), lr)
-            cnt += 1
+            want = k % loss_every == 0
+            loss = model.train_step(xdec[idx].contiguous(), labels[idx].contiguous(), lrs[ep], want_loss=want)
+            if want:
+                tot += loss
+                cnt += 1
+            if log and k and k % max(nsteps // 8, 1) == 0:
+                log(f"[learned] epoch {ep} step {k}/{nsteps}: loss {tot / max(cnt, 1):.4f}")
         hist.append(tot / max(cnt, 1))
         if log:
             log(f"[learned] epoch {ep}: loss {hist[-1]:.4f}")

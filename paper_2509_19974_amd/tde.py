@@ -355,11 +355,13 @@ class Model:
                                                 _ptr(top), _ptr(margin), _stream(stream)))
         return logits, top, margin
 
-    def train_step(self, xdec, labels, lr: float, stream=None) -> float:
+    def train_step(self, xdec, labels, lr: float, stream=None, want_loss: bool = True) -> float:
+        """One Adam step; returns the mean loss (the call then waits for the
+        stream), or nan with want_loss=False (no wait)."""
         loss = ctypes.c_float(0.0)
         _check(load_library().tde_train_step(self.ctx.handle, self.handle, _ptr(xdec), _ptr(labels), xdec.shape[0],
-                                             float(lr), ctypes.byref(loss), _stream(stream)))
-        return float(loss.value)
+                                             float(lr), ctypes.byref(loss) if want_loss else None, _stream(stream)))
+        return float(loss.value) if want_loss else float("nan")
 
 
 def tde_tune(ctx, max_log_n: int = 22, stream=None) -> None:

@@ -172,6 +172,44 @@ def config5_reverb(npairs: int = 1024, n: int = 1 << 18, max_lag: int = 1 << 16,
     return out
 
 
+def config5_reverb_torch(torch, npairs: int, salt: int = 0, n: int = 1 << 18, max_lag: int = 1 << 16,
+                         device="cuda", t60_range=(2000, 12000)):
+    """The reverberant recipe of ``config5_reverb`` drawn with torch's
+    generator on ``device`` (float32), for training-scale sets: the host
+    recipe costs tens of milliseconds per pair. Per pair: T ~ U{t60_range};
+    h[k] = g[k] 10^(-3k/T) for k < T, unit energy; x = steady-state white
+    noise through h (the valid part of a linear convolution, taken by FFT);
+    d ~ U{-max_lag..max_lag-1}; y[n] = x[n - d] (zero fill) plus white noise
+    at SNR ~ U[0, 30] dB (power of the delayed signal over its support).
+    The same salt and device give the same bytes. Returns a dict of tensors
+    x, y [npairs][n] float32 and d, snr_db, t60 [npairs]."""
+    g = torch.Generator(device=device)
+    g.manual_seed(BASE_SEED + 5 + 1000 * salt)
+    tmax = int(t60_range[1])
+    t60 = torch.randint(int(t60_range[0]), tmax + 1, (npairs,), generator=g, device=device)
+    k = torch.arange(tmax, device=device, dtype=torch.float32)
+    env = torch.pow(10.0, -3.0 * k[None, :] / t60[:, None].float()) * (k[None, :] < t60[:, None]).float()
+    h = torch.randn(npairs, tmax, generator=g, device=device) * env
+    h = h / torch.linalg.vector_norm(h, dim=1, keepdim=True)
+    e = torch.randn(npairs, n + tmax - 1, generator=g, device=device)
+    nfft = 1
+    while nfft < n + 2 * tmax - 2:
+        nfft *= 2
+    full = torch.fft.irfft(torch.fft.rfft(e, nfft) * torch.fft.rfft(h, nfft), nfft)
+    del e
+    x = full[:, tmax - 1:tmax - 1 + n].contiguous()
+    del full
+    d = torch.randint(-max_lag, max_lag, (npairs,), generator=g, device=device)
+    src = torch.arange(n, device=device)[None, :] - d[:, None]
+    inside = (src >= 0) & (src < n)
+    y = torch.where(inside, torch.gather(x, 1, src.clamp(0, n - 1)), torch.zeros((), device=device))
+    snr = torch.rand(npairs, generator=g, device=device) * 30.0
+    ps = (y * y).sum(dim=1) / inside.sum(dim=1).clamp(min=1)
+    sd = torch.sqrt(ps / torch.pow(10.0, snr / 10.0))
+    y = y + sd[:, None] * torch.randn(npairs, n, generator=g, device=device)
+    return {"x": x, "y": y.contiguous(), "d": d, "snr_db": snr, "t60": t60}
+
+
 def stream_embedded(nx: int = 8192, block: int = 65536, nblocks: int = 64, noise: float = 0.7, salt: int = 0):
     """Streaming workload: a white template of nx samples added once, at a
     uniform position, to white noise of standard deviation `noise` that is

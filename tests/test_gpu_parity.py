@@ -861,6 +861,51 @@ def test_cnn_adam_step_matches_oracle(T, ctx, tmp_path):
     m2.close()
 
 
+def test_cnn_checkpoint_resume_is_bit_identical(T, ctx, tmp_path):
+    """A checkpoint keeps the parameters, Adam's moments and its step: a
+    model loaded from it and given the same mini-batches ends with exactly
+    the parameters of the run that kept going; a parameters-only file (the
+    older format) restarts Adam, which changes the result."""
+    import struct
+    from paper_2509_19974_amd import tde
+    say("cnn checkpoint resume")
+    rng = np.random.default_rng(12)
+    batches = [(_bf16_tensor(T, rng.standard_normal((4, 2, MID.ld))),
+                dev(T, rng.integers(0, MID.nbins, 4).astype(np.int32))) for _ in range(6)]
+    a = tde.Model(ctx, MID.ld, MID.nbins, seed=5)
+    for xb, lb in batches[:3]:
+        a.train_step(xb, lb, 2e-3)
+    f = str(tmp_path / "ckpt.bin")
+    a.save(f)
+    raw = open(f, "rb").read()
+    magic, ld, nb, n, step = struct.unpack("<5i", raw[:20])
+    assert (magic, ld, nb, n, step) == (0x32454454, MID.ld, MID.nbins, a.num_params, 3)
+    assert len(raw) == 20 + 12 * n
+    for xb, lb in batches[3:]:
+        a.train_step(xb, lb, 2e-3)
+    b = tde.Model(ctx, MID.ld, MID.nbins, seed=77)
+    b.load(f)
+    for xb, lb in batches[3:]:
+        b.train_step(xb, lb, 2e-3)
+    np.testing.assert_array_equal(b.get_params(), a.get_params())
+    # parameters only: Adam restarts from step 0 and zero moments
+    f1 = str(tmp_path / "params_only.bin")
+    with open(f1, "wb") as fh:
+        fh.write(struct.pack("<4i", 0x31454454, MID.ld, MID.nbins, n) + raw[20:20 + 4 * n])
+    c = tde.Model(ctx, MID.ld, MID.nbins, seed=77)
+    c.load(f1)
+    for xb, lb in batches[3:]:
+        c.train_step(xb, lb, 2e-3)
+    assert not np.array_equal(c.get_params(), a.get_params())
+    # a truncated checkpoint is refused
+    with open(f1, "wb") as fh:
+        fh.write(raw[:-4])
+    with pytest.raises(tde.TDEError):
+        c.load(f1)
+    for m in (a, b, c):
+        m.close()
+
+
 def test_cnn_prepare_matches_oracle_decimation(T, ctx):
     """Decimated inputs: block means of 16 over 1/sigma of the b-bit
     quantizer's scale (bit-exact inv_step), rounded to bf16: equal to the
