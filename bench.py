@@ -1,30 +1,39 @@
 #!/usr/bin/env python3
 """Throughput of the exact integer time-difference estimator on one MI355X.
 
-One step = one call of tde_estimate_batch over the whole batch (Algorithm 1
-up to its argmax step for every pair: scale + quantize, exact integer correlation over the
-full lag range, argmax), with the float32 inputs already resident in HBM. By
-default the call is replayed from its captured HIP graph (use_graph = 1: the
-descriptors stay in the workspace, so a step is only kernel launches);
---eager times plain calls (descriptor upload + launches). Stage times (and the
-roofline's kernel time) come from an eager pass with the library's stage
-events, recorded on the stream the kernels run on.
+Default workload, the largest configuration that fits one GPU: 1024
+reverberant pairs of N = 2^18 float32 samples (white noise through a random
+response with a 60 dB decay over T ~ U[2000, 12000] samples, y = x delayed
+by d ~ U{-2^16..2^16-1} plus noise at SNR ~ U[0, 30] dB), the uniform
+quantizer on [-3 sigma, 3 sigma] at b = 4, lags [-2^16, 2^16 - 1]. The pairs
+are drawn on the GPU by the seeded generator. One step is one
+tde_estimate_batch call in learned mode (Algorithm 1 up to its argmax step
+with the exact correlation run only where the proposer points): scale and
+quantize (with the proposer's decimated input), the trained proposer
+(weights committed beside the library), exact correlation inside the top-8
+lag bins, the full lag range for pairs whose logit margin is below the
+committed threshold, argmax. The float32 inputs are resident in HBM; steps
+are replays of the call's captured HIP graph, timed with HIP events on the
+stream the kernels run on.
 
-Default workload: 64 pairs of N = 65536 float32 AR(2) coloured noise (poles
-0.95, 0.6), delays uniform in [-N/4, N/4], SNR uniform in [0, 30] dB, uniform
-quantizer on [-3 sigma, 3 sigma] with b in {2, 4, 8} (pair i takes b =
-(2, 4, 8)[i % 3]), full lag range [-(N-1), N-1].
+Beside it, on the same pairs: the plain full-range path (the method without
+the proposer), an FP32 FFT cross-correlation, the lags that differ from the
+full search (on the timed pairs and on 16384 held-out pairs, with 95%
+intervals), the CPU oracle on a bounded sample (also the parity check of
+the GPU results), stage times from the library's HIP events, and the
+roofline of the longest stage. "workloads" holds the other configurations:
+the 64 x 65536 batch (mixed b and each b alone), 8 long pairs of 2^22
+samples on the transform engine, and 4096 uneven pairs.
 
-Prints ONE JSON line (rank 0) with pairs/s, the algorithmic integer MAC rate,
-the roofline of the dominant kernel (the int8 matrix-core correlation, timed
-with HIP events on the stream it runs on), an FP32 FFT cross-correlation of
-the same pairs on the same GPU, and the CPU oracle timed on a bounded sample.
+Prints ONE JSON line. The exit status is 3 when any GPU result checked
+against the oracle differs (the line then says "parity": {"ok": false}).
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -36,10 +45,8 @@ INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 matrix peak, 5.0 POP/s
 FP6_FP4_PEAK_TFLOPS = 10100.0  # MI355X dense FP6 / FP4 matrix peak, 10.1 PFLOP/s
 BF16_PEAK_TFLOPS = 2500.0    # MI355X dense bf16 matrix peak, 2.5 PFLOP/s
 HBM_PEAK_GBS = 8000.0
-# 256 CUs x 16 lanes/clock of 32-bit integer multiply (a quarter of the 64
-# lanes/clock of simple VALU ops) x 2.4 GHz, 4 multiplies per Montgomery
-# butterfly: 2.46e12 butterflies/s
-MODMUL_PEAK_T = 256 * 16 * 2.4e9 / 4 / 1e12
+METRIC = "pairs/s and int-MAC/s vs FP32-FFT xcorr on MI355X at oracle-exact lags"
+WEIGHTS = os.path.join(ROOT, "paper_2509_19974_amd", "weights", "proposer_n18")
 
 
 def log(*a):
@@ -54,14 +61,34 @@ def alg_macs(nx: int, ny: int, lo: int, hi: int) -> int:
     return int(np.clip(ov, 0, None).sum())
 
 
+def binom_ci(k: int, n: int):
+    """Clopper-Pearson 95% interval of a proportion k/n."""
+    from scipy.stats import beta
+    lo = 0.0 if k == 0 else float(beta.ppf(0.025, k, n - k + 1))
+    hi = 1.0 if k == n else float(beta.ppf(0.975, k + 1, n - k))
+    return [lo, hi]
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def make_workload(name: str):
     import synth
-    if name == "c2":
+    if name.startswith("c2"):
         pairs = synth.config2_batch(8, npairs=64, n=65536)
+        fixed = int(name[4:]) if name.startswith("c2_b") else None
         for i, p in enumerate(pairs):
-            p["bits"] = (2, 4, 8)[i % 3]
-        desc = {"workload": "batch of 64 pairs, N=65536, AR(2) noise, b in {2,4,8}, full lag range",
-                "pairs": 64, "n": 65536, "bits": [2, 4, 8], "lags": "[-(N-1), N-1]"}
+            p["bits"] = fixed if fixed else (2, 4, 8)[i % 3]
+        bits = [fixed] if fixed else [2, 4, 8]
+        desc = {"workload": f"batch of 64 pairs, N=65536, AR(2) noise, b in {bits}, full lag range",
+                "pairs": 64, "n": 65536, "bits": bits, "lags": "[-(N-1), N-1]"}
         return pairs, desc
     if name == "c1":
         pairs = synth.config1_single(npairs=1)
@@ -88,10 +115,10 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def traffic_from_profile(kernel_src: str):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
+def traffic_from_profile(kernel_src: str, name: str):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary, if it
     was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "xcorr_mfma_c2_pmc.json")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     try:
@@ -104,14 +131,15 @@ def traffic_from_profile(kernel_src: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def fft_baseline(torch, pairs, specs, steps, warmup):
+def fft_baseline(torch, pairs, specs, steps, warmup, stream=None):
     """FP32 FFT cross-correlation r = irfft(conj(X) Y) of the float signals,
     argmax over each pair's lags (first maximum = smallest lag). Pairs are
     batched by transform length (a power of two covering the pair's lags
-    without wrap-around), zero-padded to the longest signal of their batch."""
+    without wrap-around), zero-padded to the longest signal of their batch.
+    Eager torch calls, timed with events on `stream`."""
     groups = {}
     for i, p in enumerate(pairs):
-        nx, ny = p["x"].size, p["y"].size
+        nx, ny = p["nx"], p["ny"]
         need = max(p["lag_hi"] + nx, ny - p["lag_lo"])
         nfft = 1
         while nfft < need:
@@ -119,12 +147,12 @@ def fft_baseline(torch, pairs, specs, steps, warmup):
         groups.setdefault(nfft, []).append(i)
     plans = []
     for nfft, idx in groups.items():
-        nmax = max(max(pairs[i]["x"].size, pairs[i]["y"].size) for i in idx)
+        nmax = max(max(pairs[i]["nx"], pairs[i]["ny"]) for i in idx)
         xs = torch.zeros(len(idx), nmax, device="cuda")
         ys = torch.zeros(len(idx), nmax, device="cuda")
         for k, i in enumerate(idx):
-            xs[k, :pairs[i]["x"].size] = specs[i]["x"]
-            ys[k, :pairs[i]["y"].size] = specs[i]["y"]
+            xs[k, :pairs[i]["nx"]] = specs[i]["x"]
+            ys[k, :pairs[i]["ny"]] = specs[i]["y"]
         lo = torch.tensor([pairs[i]["lag_lo"] for i in idx], device="cuda")
         L = max(pairs[i]["lag_hi"] - pairs[i]["lag_lo"] + 1 for i in idx)
         off = torch.arange(L, device="cuda")[None, :]
@@ -142,164 +170,373 @@ def fft_baseline(torch, pairs, specs, steps, warmup):
             outs.append((idx, torch.argmax(g, dim=1) + lo))
         return outs
 
+    stream = stream or torch.cuda.current_stream()
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
+    e0.record(stream)
     for _ in range(steps):
         outs = step()
-    e1.record()
+    e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     lag = [0] * len(pairs)
     for idx, l in outs:
         for k, v in zip(idx, l.cpu().numpy().tolist()):
             lag[k] = v
+    del plans
     return ms, lag
 
 
-def cpu_baseline(pairs, budget_s: float = 12.0):
-    """The oracle, pair after pair of the same batch (wrapping round), until
-    about budget_s seconds of CPU work are done."""
-    import oracle
-    t0 = time.perf_counter()
-    done = 0
-    macs = 0
-    while True:
-        p = pairs[done % len(pairs)]
-        oracle.estimate(p["x"], p["y"], p["bits"], p["lag_lo"], p["lag_hi"])
-        done += 1
-        macs += alg_macs(p["x"].size, p["y"].size, p["lag_lo"], p["lag_hi"])
-        if time.perf_counter() - t0 > budget_s:
-            break
-    el = time.perf_counter() - t0
-    return {"value": done / el, "unit": "pairs/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{done} pairs of the {len(pairs)}-pair batch, each Algorithm 1 up to its argmax step "
-                      f"(scale, quantize, int64 direct sums over every lag, argmax), {el:.1f} s",
-            "int_mac_per_s": macs / el}
+def time_batch(ctx, torch, specs, steps, warmup, stream, **plan_kw):
+    """Eager calls with the library's stage events, then graph replays of
+    the same call. Returns graph and eager ms per step, average stage ms and
+    the peaks of the last replay."""
+    from paper_2509_19974_amd import tde
+    out = torch.empty(len(specs) * tde.PEAK_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    plan = ctx.batch_plan(specs, **plan_kw)
+    ws = torch.empty(plan[2], dtype=torch.uint8, device="cuda")
+    for _ in range(max(warmup, 1)):
+        ctx.estimate_batch(specs, ws=ws, out=out, plan=plan, stream=stream)
+    torch.cuda.synchronize()
+    tde.tde_timing_read(ctx.handle)
+    tde.tde_timing_enable(ctx.handle, True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        ctx.estimate_batch(specs, ws=ws, out=out, plan=plan, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    eager_ms = e0.elapsed_time(e1) / steps
+    sms, sn = tde.tde_timing_read(ctx.handle)
+    tde.tde_timing_enable(ctx.handle, False)
+    del ws
+    names = ["quantize", "engine", "argmax", "call", "proposer", "windows", "mfma_engine"]
+    stage = {names[k]: sms[k] / sn[k] for k in range(len(names)) if sn[k]}
+    gplan = ctx.batch_plan(specs, use_graph=1, **plan_kw)
+    gws = torch.empty(gplan[2], dtype=torch.uint8, device="cuda")
+    for _ in range(max(warmup, 1)):
+        ctx.estimate_batch(specs, ws=gws, out=out, plan=gplan, stream=stream)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        ctx.estimate_batch(specs, ws=gws, out=out, plan=gplan, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / steps
+    pk = tde.decode_peaks(out)
+    del gws
+    return {"graph_ms": graph_ms, "eager_ms": eager_ms, "stage_ms": stage, "peaks": pk}
 
 
-def _gen_c5(args_):
-    n, npairs, salt = args_
-    import synth
-    return synth.config5_reverb(npairs=npairs, n=n, max_lag=n // 4, salt=salt)
+def mfma_roofline(tde, pairs, engines, path, macs, engine_ms):
+    """Roofline of the matrix-core engine: algorithmic ops (2 x sum of
+    overlaps) over its launch time, against the peak of its operand-format
+    mix (each format's dense peak weighted by its share of the MACs)."""
+    fmt_bits = [tde.tde_mfma_operand_bits(tde.kmax_of_bits(p["bits"]), tde.kmax_of_bits(p["bits"]),
+                                          path if path in (tde.TDE_PATH_MFMA, tde.TDE_PATH_MFMA_I8)
+                                          else tde.TDE_PATH_MFMA) if e == tde.TDE_PATH_MFMA else 0
+                for p, e in zip(pairs, engines)]
+    pair_macs = [alg_macs(p["nx"], p["ny"], p["lag_lo"], p["lag_hi"]) for p in pairs]
+    names = {4: "fp4", 6: "fp6", 8: "i8"}
+    fmt_macs = {names[f]: sum(m for m, g in zip(pair_macs, fmt_bits) if g == f) for f in (4, 6, 8)}
+    t_at_peak = sum(m / (INT8_PEAK_TOPS if k == "i8" else FP6_FP4_PEAK_TFLOPS) for k, m in fmt_macs.items())
+    tot = sum(fmt_macs.values())
+    peak = tot / t_at_peak if t_at_peak > 0 else INT8_PEAK_TOPS
+    achieved = 2.0 * tot / (engine_ms * 1e-3) / 1e12
+    src = os.path.join(ROOT, "paper_2509_19974_amd", "csrc", "k_xcorr_mfma.hip")
+    dtype = "+".join(k for k in ("fp4", "fp6", "i8") if fmt_macs[k]) or "i8"
+    return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TOP/s", "frac": achieved / peak,
+            "traffic": traffic_from_profile(src, "xcorr_mfma_c2_pmc.json"),
+            "kernel": "k_xcorr_mfma (32x32 matrix tiles: FP4/FP6 operands with fp32 accumulation for codes "
+                      "up to 7, int8 with int32 accumulation beyond)",
+            "peak_mix": {k: {"mac_share": m / max(tot, 1), "peak": INT8_PEAK_TOPS if k == "i8" else FP6_FP4_PEAK_TFLOPS}
+                         for k, m in fmt_macs.items() if m},
+            "kernel_ms": engine_ms, "alg_macs_per_launch": tot}, dtype
+
+
+def ntt_roofline(tde, pairs, engine_ms):
+    """Roofline of the transform engine against HBM: per pair and prime the
+    three transforms of n points each take two passes over their residues
+    (read and write, 4 bytes each), so 2 primes x 3 transforms x 2 passes x
+    2 x 4 n bytes; one prime when the coefficient bound allows it."""
+    nbytes = 0
+    for p in pairs:
+        nx, ny = p["nx"], p["ny"]
+        lo, hi = max(p["lag_lo"], -(nx - 1)), min(p["lag_hi"], ny - 1)
+        need = max(hi + nx, ny - lo)
+        lg = 13
+        while (1 << lg) < need:
+            lg += 1
+        k = tde.kmax_of_bits(p["bits"])
+        nprimes = 1 if min(nx, ny) * k * k < 2013265921 // 2 else 2
+        nbytes += nprimes * 3 * 2 * 2 * 4 * (1 << lg)
+    achieved = nbytes / (engine_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None, "kernel": "k_ntt_cols_fwd + k_ntt_rows + k_ntt_cols_inv (two-prime NTT)",
+            "kernel_ms": engine_ms, "alg_bytes_per_launch": nbytes}
+
+
+def run_plain(args, name, path_name="auto", fft=True, cpu_parity=False):
+    """One plain (full-search) workload: graph and eager step times, stage
+    times, roofline of the correlation engine, FP32 FFT on the same pairs,
+    and optionally every pair against the oracle."""
+    import numpy as np
+    import torch
+    from paper_2509_19974_amd import tde
+    log(f"[bench] generating workload {name}")
+    pairs, desc = make_workload(name)
+    for p in pairs:
+        p["nx"], p["ny"] = p["x"].size, p["y"].size
+    ctx = tde.Context(0)
+    stream = torch.cuda.current_stream()
+    specs = [dict(x=torch.from_numpy(p["x"]).cuda(), y=torch.from_numpy(p["y"]).cuda(), lag_lo=p["lag_lo"],
+                  lag_hi=p["lag_hi"], bits=p["bits"]) for p in pairs]
+    path = {"auto": tde.TDE_PATH_AUTO, "mfma": tde.TDE_PATH_MFMA, "mfma_i8": tde.TDE_PATH_MFMA_I8,
+            "popc": tde.TDE_PATH_POPC, "ntt": tde.TDE_PATH_NTT}[path_name]
+    if args.tune:
+        log("[bench] autotuning engines")
+        tde.tde_tune(ctx.handle, 20)
+    engines = [tde.tde_tune_query(p["nx"], p["ny"], tde.kmax_of_bits(p["bits"]), tde.kmax_of_bits(p["bits"]),
+                                  p["lag_lo"], p["lag_hi"]) if path == tde.TDE_PATH_AUTO else path for p in pairs]
+    macs = sum(alg_macs(p["nx"], p["ny"], p["lag_lo"], p["lag_hi"]) for p in pairs)
+    log(f"[bench] {name}: timing {args.steps} steps")
+    t = time_batch(ctx, torch, specs, args.steps, args.warmup, stream, path=path)
+    ms_step = t["eager_ms"] if args.eager else t["graph_ms"]
+    pk = t["peaks"]
+    d = np.array([p["d"] for p in pairs])
+    n_ntt = sum(1 for e in engines if e == tde.TDE_PATH_NTT)
+    if n_ntt * 2 < len(engines):
+        roof, dtype = mfma_roofline(tde, pairs, engines, path, macs, t["stage_ms"].get("mfma_engine", t["stage_ms"]["engine"]))
+    else:
+        roof, dtype = ntt_roofline(tde, pairs, t["stage_ms"]["engine"]), "u32"
+    res = {"pairs_per_s": len(pairs) * 1e3 / ms_step, "ms_per_step": ms_step, "timing": "eager calls" if args.eager
+           else "hip graph replay", "eager_ms_per_step": t["eager_ms"], "int_mac_per_s": macs * 1e3 / ms_step,
+           "dtype": dtype, "config": desc,
+           "engines": {nm: sum(1 for e in engines if e == code) for nm, code in
+                       (("mfma", tde.TDE_PATH_MFMA), ("popc", tde.TDE_PATH_POPC), ("ntt", tde.TDE_PATH_NTT))},
+           "stage_ms": t["stage_ms"], "lag_accuracy": {"int": float(np.mean((pk["lag"] == d) & (pk["n_ties"] == 1)))},
+           "roofline": roof}
+    if fft:
+        fms, flag = fft_baseline(torch, pairs, specs, args.steps, args.warmup, stream)
+        res["fft_fp32"] = {"pairs_per_s": len(pairs) * 1e3 / fms, "ms_per_step": fms,
+                           "lag_accuracy": float(np.mean(np.array(flag) == d)),
+                           "speedup_int_graph_over_fft": fms / t["graph_ms"],
+                           "speedup_int_eager_over_fft": fms / t["eager_ms"]}
+    if cpu_parity:
+        import oracle
+        t0 = time.perf_counter()
+        bad = 0
+        for i, p in enumerate(pairs):
+            ref = oracle.estimate(p["x"], p["y"], p["bits"], p["lag_lo"], p["lag_hi"])
+            bad += (int(pk[i]["lag"]), int(pk[i]["rmax"]), int(pk[i]["n_ties"])) != \
+                   (ref["lag"], ref["rmax"], ref["n_ties"])
+        res["parity"] = {"oracle_pairs": len(pairs), "mismatches": bad, "ok": bad == 0,
+                         "oracle_s": time.perf_counter() - t0}
+    ctx.close()
+    del specs
+    torch.cuda.empty_cache()
+    return res
+
+
+def window_macs(top, fallback, n, nbins, bin_lags=256):
+    """Exact MACs the learned step computes: for a pair on its windows, the
+    overlaps of every lag in its top bins; for a fallback pair, the full range."""
+    import numpy as np
+    half = nbins // 2
+    full = alg_macs(n, n, -half * bin_lags, half * bin_lags - 1)
+    tot = 0
+    for k in range(top.shape[0]):
+        if fallback[k]:
+            tot += full
+            continue
+        for b in top[k]:
+            lo = (int(b) - half) * bin_lags
+            t = np.arange(lo, lo + bin_lags)
+            tot += int(np.clip(n - np.abs(t), 0, None).sum())
+    return tot
 
 
 def run_c5(args):
-    """Learned lag-window proposal on reverberant pairs (N = 2^18, b = 4, lags
-    [-2^16, 2^16 - 1]): train the proposer on pairs labelled by the exact
-    plain estimator, tune the fallback margin on a validation set, then time
-    the plain and the learned paths (HIP-graph replays) on 1024 held-out
-    pairs and count the lags that differ from the full search."""
-    import concurrent.futures as cf
-    import multiprocessing as mp
-    n = 1 << 18
-    chunk = 128
-    ntrain, nval, neval = args.c5_train, 512, 1024
-    seeds = {"train": [1000 + k for k in range(ntrain // chunk)], "val": [500 + k for k in range(nval // chunk)],
-             "eval": list(range(neval // chunk))}
-    # generator processes start before anything touches the GPU (or run in
-    # this process with --c5-workers 0, e.g. under a profiler)
-    pool = None
-    if args.c5_workers > 0:
-        pool = cf.ProcessPoolExecutor(max_workers=args.c5_workers, mp_context=mp.get_context("spawn"))
-        jobs = {k: [pool.submit(_gen_c5, (n, chunk, sd)) for sd in v] for k, v in seeds.items()}
+    """The default line (see the module docstring)."""
     import numpy as np
     import torch
-    from paper_2509_19974_amd import tde, learned
+    import synth
+    import oracle
+    from paper_2509_19974_amd import learned, tde
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    n, lag, bits, nbins, npairs = 1 << 18, 1 << 16, 4, 512, 1024
+    meta = json.load(open(WEIGHTS + ".json"))
+    theta, topk = float(meta["threshold"]), int(meta["topk"])
     ctx = tde.Context(0)
-    model = tde.Model(ctx, n // 16, 512, seed=1)
-    t0 = time.perf_counter()
+    stream = torch.cuda.current_stream()
+    model = tde.Model(ctx, n // 16, nbins)
+    model.load(WEIGHTS + ".tdem")
+    log("[bench] generating 1024 reverberant pairs on the GPU")
+    g = [synth.config5_reverb_torch(torch, 512, salt=s, n=n, max_lag=lag) for s in (0, 1)]
+    X = torch.cat([a["x"] for a in g])
+    Y = torch.cat([a["y"] for a in g])
+    d = torch.cat([a["d"] for a in g]).cpu().numpy()
+    del g
+    specs = learned.device_specs(X, Y, bits, -lag, lag - 1)
+    pairs = [dict(nx=n, ny=n, lag_lo=-lag, lag_hi=lag - 1, bits=bits) for _ in range(npairs)]
 
-    def chunks(name):
-        for k, sd in enumerate(seeds[name]):
-            yield jobs[name][k].result() if pool else _gen_c5((n, chunk, sd))
-
-    xtr, ltr = learned.make_dataset(ctx, model, chunks("train"))
-    log(f"[bench] c5 training set ready: {xtr.shape[0]} pairs, {time.perf_counter() - t0:.1f} s")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    hist = learned.train(ctx, model, xtr, ltr, args.c5_epochs, 64, args.c5_lr, log=log)
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t1
-    del xtr, ltr
-    val = [p for c in chunks("val") for p in c]
-    vspecs = learned.specs_of(torch, val)
-    vtruth = learned.plain_peaks(ctx, vspecs)
-    vtop, vmargin = learned.proposals(model, model.prepare(vspecs), 8)
-    theta = learned.tune_threshold(vtop, vmargin, vtruth["lag"], 512, 0.0, args.c5_safety)
-    del vspecs
-    log(f"[bench] c5 threshold {theta:.4f}")
-    ev = [p for c in chunks("eval") for p in c]
-    if pool:
-        pool.shutdown()
-    specs = learned.specs_of(torch, ev)
-    d = np.array([p["d"] for p in ev])
-
-    def timed(plan):
-        ws = torch.empty(plan[2], dtype=torch.uint8, device="cuda")
-        out = torch.empty(len(specs) * 24, dtype=torch.uint8, device="cuda")
-        for _ in range(max(args.warmup, 1)):
-            ctx.estimate_batch(specs, ws=ws, out=out, plan=plan)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(args.steps):
-            ctx.estimate_batch(specs, ws=ws, out=out, plan=plan)
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / args.steps, tde.decode_peaks(out)
-
-    plain_ms, plain = timed(ctx.batch_plan(specs, use_graph=1))
-    learn_ms, lrn = timed(ctx.batch_plan(specs, mode=tde.TDE_MODE_LEARNED, model=model, topk=8, margin=theta,
-                                         use_graph=1))
-    _, lrn0 = timed(ctx.batch_plan(specs, mode=tde.TDE_MODE_LEARNED, model=model, topk=8, margin=-3.0e38,
-                                   use_graph=1))
+    log("[bench] c5: plain full-range path")
+    tp = time_batch(ctx, torch, specs, args.steps, args.warmup, stream)
+    log("[bench] c5: learned path")
+    tl = time_batch(ctx, torch, specs, args.steps, args.warmup, stream, mode=tde.TDE_MODE_LEARNED, model=model,
+                    topk=topk, margin=theta)
+    t0 = time_batch(ctx, torch, specs, 1, 1, stream, mode=tde.TDE_MODE_LEARNED, model=model, topk=topk,
+                    margin=float("-inf"))
+    plain, lrn, lrn0 = tp["peaks"], tl["peaks"], t0["peaks"]
 
     def differ(a, b):
-        return float(np.mean((a["lag"] != b["lag"]) | (a["rmax"] != b["rmax"]) | (a["n_ties"] != b["n_ties"])))
+        return int(np.count_nonzero((a["lag"] != b["lag"]) | (a["rmax"] != b["rmax"]) | (a["n_ties"] != b["n_ties"])))
 
-    fallback = float(np.mean((lrn["flags"] & tde.TDE_FLAG_FALLBACK) != 0))
-    # stage timing of one eager learned call: CNN + windows (+ fallback) is the engine stage
-    tde.tde_timing_read(ctx.handle)
-    tde.tde_timing_enable(ctx.handle, True)
-    lplan = ctx.batch_plan(specs, mode=tde.TDE_MODE_LEARNED, model=model, topk=8, margin=theta)
-    for _ in range(3):
-        ctx.estimate_batch(specs, plan=lplan)
+    fb_mask = (lrn["flags"] & tde.TDE_FLAG_FALLBACK) != 0
+    _, top, _ = model.forward(model.prepare(specs), topk=topk)
+    win_macs = window_macs(top.cpu().numpy(), fb_mask, n, nbins)
+    full_macs = npairs * alg_macs(n, n, -lag, lag - 1)
+
+    log("[bench] c5: held-out pairs for the differ rates")
+    held = {"pairs": 0, "before": 0, "after": 0, "fallback": 0}
+    for s in range(10, 10 + args.c5_heldout // 1024):
+        gg = [synth.config5_reverb_torch(torch, 512, salt=2 * s + h, n=n, max_lag=lag) for h in (0, 1)]
+        hs = learned.device_specs(torch.cat([a["x"] for a in gg]), torch.cat([a["y"] for a in gg]), bits, -lag,
+                                  lag - 1)
+        a = tde.decode_peaks(ctx.estimate_batch(hs))
+        b = tde.decode_peaks(ctx.estimate_batch(hs, plan=ctx.batch_plan(
+            hs, mode=tde.TDE_MODE_LEARNED, model=model, topk=topk, margin=theta)))
+        c = tde.decode_peaks(ctx.estimate_batch(hs, plan=ctx.batch_plan(
+            hs, mode=tde.TDE_MODE_LEARNED, model=model, topk=topk, margin=float("-inf"))))
+        held["pairs"] += len(hs)
+        held["before"] += differ(c, a)
+        held["after"] += differ(b, a)
+        held["fallback"] += int(np.count_nonzero(b["flags"] & tde.TDE_FLAG_FALLBACK))
+        del hs, gg
     torch.cuda.synchronize()
-    stage_ms, stage_n = tde.tde_timing_read(ctx.handle)
-    tde.tde_timing_enable(ctx.handle, False)
-    engine_ms = stage_ms[1] / max(stage_n[1], 1)
-    prop_ms = stage_ms[4] / max(stage_n[4], 1)
-    cnn_macs = 2 * (16384 * 32 * 9 + (8192 + 4096 + 2048) * 32 * 32 * 9) + 512 * 1024 * 32
-    win_macs = 8 * 256 * n
+
+    log("[bench] c5: FP32 FFT baseline")
+    fspecs = [dict(x=X[i], y=Y[i]) for i in range(npairs)]
+    fms, flag = fft_baseline(torch, pairs, fspecs, max(args.steps // 4, 2), 1, stream)
+    torch.cuda.empty_cache()
+
+    st_l, st_p = tl["stage_ms"], tp["stage_ms"]
+    # per-stage rooflines of the learned step
+    samples = 2 * npairs * n
+    cnn_macs = 2 * (16384 * 32 * 9 + (8192 + 4096 + 2048) * 32 * 32 * 9) + nbins * 1024 * 32
+    roofs = {}
+    qb = samples * (4 + 1 + 0.125)        # float in, int8 code out, bf16 decimated value per 16 samples
+    roofs["quantize"] = {"bound": "hbm", "achieved": qb / (st_l["quantize"] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "kernel": "k_sumsq_blocks + k_quantize (scale, codes, decimated input)",
+                         "kernel_ms": st_l["quantize"], "alg_bytes_per_launch": qb}
+    roofs["proposer"] = {"bound": "mfma", "achieved": 2.0 * cnn_macs * npairs / (st_l["proposer"] * 1e-3) / 1e12,
+                         "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "kernel": "CNN forward (bf16 matrix-core convolutions, head) and top-k",
+                         "kernel_ms": st_l["proposer"], "alg_macs_per_launch": cnn_macs * npairs}
+    wm = window_macs(top.cpu().numpy(), np.zeros(npairs, bool), n, nbins)
+    roofs["windows"] = {"bound": "mfma", "achieved": 2.0 * wm / (st_l["windows"] * 1e-3) / 1e12,
+                        "peak": INT8_PEAK_TOPS, "unit": "TOP/s", "kernel": "k_xcorr_win (exact correlation in the "
+                        "top bins, int8 matrix tiles)", "kernel_ms": st_l["windows"], "alg_macs_per_launch": wm}
+    if "mfma_engine" in st_l:
+        fm = int(np.count_nonzero(fb_mask)) * alg_macs(n, n, -lag, lag - 1)
+        roofs["fallback"] = {"bound": "mfma", "achieved": 2.0 * fm / (st_l["mfma_engine"] * 1e-3) / 1e12,
+                             "peak": FP6_FP4_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "kernel": "k_xcorr_mfma over the fallback pairs (FP6 operands)",
+                             "kernel_ms": st_l["mfma_engine"], "alg_macs_per_launch": fm}
+    for r in roofs.values():
+        r["frac"] = r["achieved"] / r["peak"]
+        r["traffic"] = None
+    dom = max(roofs, key=lambda k: roofs[k]["kernel_ms"])
+    roof = dict(roofs[dom], stage=dom)
+
+    log("[bench] c5: CPU oracle (baseline and parity sample)")
+    cpu, parity = None, None
+    if not args.no_cpu_baseline:
+        Xh, Yh = X.cpu().numpy(), Y.cpu().numpy()
+        t_start = time.perf_counter()
+        bad_plain = bad_learned = 0
+        done = 0
+        while done < npairs:
+            ref = oracle.estimate(Xh[done], Yh[done], bits, -lag, lag - 1)
+            got = (ref["lag"], ref["rmax"], ref["n_ties"])
+            bad_plain += (int(plain[done]["lag"]), int(plain[done]["rmax"]), int(plain[done]["n_ties"])) != got
+            bad_learned += (int(lrn[done]["lag"]), int(lrn[done]["rmax"]), int(lrn[done]["n_ties"])) != got
+            done += 1
+            if time.perf_counter() - t_start > args.cpu_budget:
+                break
+        el = time.perf_counter() - t_start
+        threads = oracle.threads()
+        # one thread, on a lag subset of one pair (linear in MACs)
+        oracle.set_threads(1)
+        sub_lo, sub_hi = -2048, 2047
+        t1 = time.perf_counter()
+        oracle.xcorr(oracle.quantize(Xh[0], bits)[0], oracle.quantize(Yh[0], bits)[0], sub_lo, sub_hi)
+        el1 = time.perf_counter() - t1
+        oracle.set_threads(threads)
+        sub_macs = alg_macs(n, n, sub_lo, sub_hi)
+        pair_macs = alg_macs(n, n, -lag, lag - 1)
+        cpu = {"value": done / el, "unit": "pairs/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": f"{done} of the 1024 timed pairs, each Algorithm 1 up to its argmax step (scale, quantize, "
+                         f"int64 direct sums over all 131072 lags, argmax), {el:.1f} s on {threads} threads",
+               "int_mac_per_s": done * pair_macs / el,
+               "single_thread": {"pairs_per_s": sub_macs / el1 / pair_macs, "int_mac_per_s": sub_macs / el1,
+                                 "sample": f"int64 direct sums of one pair over lags [{sub_lo}, {sub_hi}] "
+                                           f"({sub_macs} MACs, {el1:.2f} s), extrapolated linearly in MACs"}}
+        parity = {"oracle_pairs": done, "plain_mismatches": bad_plain, "learned_mismatches": bad_learned,
+                  "ok": bad_plain == 0 and bad_learned == 0,
+                  "check": "(lag, rmax, n_ties) of the plain and the learned GPU results against the oracle"}
+
+    lms = tl["eager_ms"] if args.eager else tl["graph_ms"]
+    pms = tp["eager_ms"] if args.eager else tp["graph_ms"]
+    hp = held["pairs"]
     result = {
-        "metric": "pairs/s and int-MAC/s vs FP32-FFT xcorr on MI355X at oracle-exact lags",
-        "value": len(ev) * 1e3 / learn_ms, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": learn_ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "i8+fp6+bf16", "data": "synthetic",
-        "config": {"workload": "1024 reverberant pairs, N=2^18, b=4, lags [-2^16, 2^16-1], learned windows (top-8 of "
-                               "512 bins, fallback below the tuned margin)", "pairs": len(ev), "n": n},
-        "plain": {"pairs_per_s": len(ev) * 1e3 / plain_ms, "ms_per_step": plain_ms},
-        "speedup_learned_over_plain": plain_ms / learn_ms,
-        "differ_from_full_search": {"before_fallback": differ(lrn0, plain), "after_fallback": differ(lrn, plain)},
-        "fallback_fraction": fallback, "threshold": theta,
-        "lag_accuracy": {"plain": float(np.mean(plain["lag"] == d)), "learned": float(np.mean(lrn["lag"] == d))},
-        "training": {"pairs": ntrain, "epochs": args.c5_epochs, "pairs_per_s": ntrain * args.c5_epochs / train_s,
-                     "loss": hist},
-        "stage_ms": {"quantize": stage_ms[0] / max(stage_n[0], 1), "engine": engine_ms, "proposer": prop_ms,
-                     "argmax": stage_ms[2] / max(stage_n[2], 1)},
-        "roofline": {"bound": "mfma", "achieved": 2.0 * cnn_macs * len(ev) / (prop_ms * 1e-3) / 1e12,
-                     "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": 2.0 * cnn_macs * len(ev) / (prop_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
-                     "traffic": None, "kernel": "proposer stage: decimated-input CNN forward (bf16 matrix-core "
-                                                "convolutions and head, fp32 accumulation) and top-k",
-                     "kernel_ms": prop_ms, "alg_cnn_macs_per_pair": cnn_macs, "alg_window_macs_per_pair": win_macs},
+        "metric": METRIC, "value": npairs * 1e3 / lms, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": lms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "i8+bf16+fp6", "data": "synthetic",
+        "config": {"workload": "1024 reverberant pairs, N=2^18, b=4, lags [-2^16, 2^16-1], learned windows "
+                               "(top-8 of 512 bins, full-range fallback below the margin threshold)",
+                   "pairs": npairs, "n": n, "bits": bits, "topk": topk, "threshold": theta,
+                   "proposer": "paper_2509_19974_amd/weights/proposer_n18.tdem"},
+        "timing": "eager calls" if args.eager else "hip graph replay",
+        "eager_ms_per_step": tl["eager_ms"],
+        "int_mac_per_s": win_macs * 1e3 / lms,
+        "full_range_equivalent_mac_per_s": full_macs * 1e3 / lms,
+        "plain": {"pairs_per_s": npairs * 1e3 / pms, "ms_per_step": pms, "eager_ms_per_step": tp["eager_ms"],
+                  "int_mac_per_s": full_macs * 1e3 / pms, "stage_ms": st_p,
+                  "roofline": mfma_roofline(tde, pairs, [tde.TDE_PATH_MFMA] * npairs, tde.TDE_PATH_AUTO, full_macs,
+                                            st_p.get("mfma_engine", st_p["engine"]))[0]},
+        "speedup_learned_over_plain": pms / lms,
+        "differ_from_full_search": {
+            "timed_pairs": {"pairs": npairs, "before_fallback": differ(lrn0, plain),
+                            "after_fallback": differ(lrn, plain)},
+            "held_out": {"pairs": hp, "before_fallback": held["before"],
+                         "before_fallback_rate": held["before"] / max(hp, 1),
+                         "before_fallback_ci95": binom_ci(held["before"], hp) if hp else None,
+                         "after_fallback": held["after"], "after_fallback_rate": held["after"] / max(hp, 1),
+                         "after_fallback_ci95": binom_ci(held["after"], hp) if hp else None,
+                         "fallback_fraction": held["fallback"] / max(hp, 1)}},
+        "fallback_fraction": float(np.mean(fb_mask)),
+        "lag_accuracy": {"plain": float(np.mean(plain["lag"] == d)), "learned": float(np.mean(lrn["lag"] == d)),
+                         "fft_fp32": float(np.mean(np.array(flag) == d))},
+        "stage_ms": st_l,
+        "fft_fp32": {"pairs_per_s": npairs * 1e3 / fms, "ms_per_step": fms, "timing": "eager torch calls",
+                     "speedup_learned_graph_over_fft": fms / tl["graph_ms"],
+                     "speedup_learned_eager_over_fft": fms / tl["eager_ms"],
+                     "speedup_plain_graph_over_fft": fms / tp["graph_ms"],
+                     "speedup_plain_eager_over_fft": fms / tp["eager_ms"]},
+        "roofline": roof, "roofline_stages": roofs,
+        "training": meta["train"],
     }
+    if cpu:
+        result["cpu_baseline"] = cpu
+        result["parity"] = parity
+    model.close()
     ctx.close()
-    print(json.dumps(result), flush=True)
+    del X, Y, specs
+    torch.cuda.empty_cache()
+    return result
 
 
 def run_quant(args):
@@ -325,7 +562,7 @@ def run_quant(args):
     t_start = time.time()
     for snr in snrs:
         xs, ys, nus = synth.speech_like_mixtures(npairs, float(snr))
-        pairs = [dict(x=x, y=y, lag_lo=lo, lag_hi=hi, bits=1) for x, y in zip(xs, ys)]
+        pairs = [dict(x=x, y=y, nx=x.size, ny=y.size, lag_lo=lo, lag_hi=hi, bits=1) for x, y in zip(xs, ys)]
         base = [dict(x=torch.from_numpy(x).cuda(), y=torch.from_numpy(y).cuda()) for x, y in zip(xs, ys)]
         _, flags = fft_baseline(torch, pairs, base, 1, 0)
         row = {"fft_fp32": float(np.mean(np.abs(np.array(flags) - nus) < 1.0))}
@@ -500,18 +737,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c5")
     ap.add_argument("--path", default="auto", choices=["auto", "mfma", "mfma_i8", "popc", "ntt"])
     ap.add_argument("--eager", action="store_true",
                     help="time eager calls instead of HIP-graph replays of the whole call")
     ap.add_argument("--tune", action="store_true", help="run the engine autotuner before planning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--c5-train", type=int, default=8192, help="learned workload: training pairs")
-    ap.add_argument("--c5-epochs", type=int, default=4)
-    ap.add_argument("--c5-lr", type=float, default=1e-3)
-    ap.add_argument("--c5-workers", type=int, default=16)
-    ap.add_argument("--c5-safety", type=float, default=0.02,
-                    help="learned workload: share of validation margins below the fallback threshold")
+    ap.add_argument("--no-workloads", action="store_true", help="default line only, without the other configs")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of CPU oracle work")
+    ap.add_argument("--c5-heldout", type=int, default=16384, help="held-out pairs for the differ rates")
     ap.add_argument("--no-fft", action="store_true")
     ap.add_argument("--quant-pairs", type=int, default=256, help="quantizer study: pairs per SNR")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -532,161 +766,35 @@ def main():
               "the pairs of a batch are independent and would be split across GPUs by predicted cost",
               file=sys.stderr)
         sys.exit(2)
-    if args.workload == "c5":
-        run_c5(args)
+    special = {"stream": run_stream, "refine": run_refine, "quant": run_quant}
+    if args.workload in special:
+        special[args.workload](args)
         return
-    if args.workload == "stream":
-        run_stream(args)
-        return
-    if args.workload == "refine":
-        run_refine(args)
-        return
-    if args.workload == "quant":
-        run_quant(args)
-        return
-
-    import numpy as np
     import torch
-    from paper_2509_19974_amd import tde
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    log(f"[bench] generating workload {args.workload}")
-    pairs, desc = make_workload(args.workload)
-    ctx = tde.Context(0)
-    specs = [dict(x=torch.from_numpy(p["x"]).cuda(), y=torch.from_numpy(p["y"]).cuda(), lag_lo=p["lag_lo"],
-                  lag_hi=p["lag_hi"], bits=p["bits"]) for p in pairs]
-    path = {"auto": tde.TDE_PATH_AUTO, "mfma": tde.TDE_PATH_MFMA, "mfma_i8": tde.TDE_PATH_MFMA_I8,
-            "popc": tde.TDE_PATH_POPC, "ntt": tde.TDE_PATH_NTT}[args.path]
-    if args.tune:
-        log("[bench] autotuning engines")
-        tde.tde_tune(ctx.handle, 20)
-    engines = [tde.tde_tune_query(p["x"].size, p["y"].size, tde.kmax_of_bits(p["bits"]), tde.kmax_of_bits(p["bits"]),
-                                  p["lag_lo"], p["lag_hi"]) if path == tde.TDE_PATH_AUTO else path for p in pairs]
-    plan = ctx.batch_plan(specs, path=path)
-    ws = torch.empty(plan[2], dtype=torch.uint8, device="cuda")
-    out = torch.empty(len(pairs) * tde.PEAK_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
-    macs = sum(alg_macs(p["x"].size, p["y"].size, p["lag_lo"], p["lag_hi"]) for p in pairs)
-
-    log(f"[bench] warmup {args.warmup}")
-    for _ in range(args.warmup):
-        ctx.estimate_batch(specs, path, ws=ws, out=out, plan=plan)
-    torch.cuda.synchronize()
-    tde.tde_timing_read(ctx.handle)
-    tde.tde_timing_enable(ctx.handle, True)
-    log(f"[bench] timing {args.steps} steps")
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        ctx.estimate_batch(specs, path, ws=ws, out=out, plan=plan, stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = e0.elapsed_time(e1)
-    stage_ms, stage_n = tde.tde_timing_read(ctx.handle)
-    tde.tde_timing_enable(ctx.handle, False)
-    ms_step = total_ms / args.steps
-    eager_ms = ms_step
-    if not args.eager:
-        # the same call replayed from a captured HIP graph (descriptors stay in
-        # the workspace); stage timing is not recorded in this mode
-        gplan = ctx.batch_plan(specs, path=path, use_graph=1)
-        gws = torch.empty(gplan[2], dtype=torch.uint8, device="cuda")
-        for _ in range(max(args.warmup, 1)):
-            ctx.estimate_batch(specs, path, ws=gws, out=out, plan=gplan, stream=stream)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(args.steps):
-            ctx.estimate_batch(specs, path, ws=gws, out=out, plan=gplan, stream=stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms_step = e0.elapsed_time(e1) / args.steps
-    pk = tde.decode_peaks(out)
-    d = np.array([p["d"] for p in pairs])
-    int_correct = float(np.mean((pk["lag"] == d) & (pk["n_ties"] == 1)))
-    engine_ms = stage_ms[1] / max(stage_n[1], 1)
-    log(f"[bench] {ms_step:.3f} ms/step, engine {engine_ms:.3f} ms, stages {stage_ms} {stage_n}")
-
-    n_ntt = sum(1 for e in engines if e == tde.TDE_PATH_NTT)
-    # operand format of every matrix-core pair (codes up to 3: FP4, up to 7:
-    # FP6, else int8) and the peak of the mix: MACs over the time each format
-    # would take at its own dense peak
-    fmt_bits = [tde.tde_mfma_operand_bits(tde.kmax_of_bits(p["bits"]), tde.kmax_of_bits(p["bits"]),
-                                          path if path in (tde.TDE_PATH_MFMA, tde.TDE_PATH_MFMA_I8)
-                                          else tde.TDE_PATH_MFMA) if e == tde.TDE_PATH_MFMA else 0
-                for p, e in zip(pairs, engines)]
-    pair_macs = [alg_macs(p["x"].size, p["y"].size, p["lag_lo"], p["lag_hi"]) for p in pairs]
-    fmt_names = {4: "fp4", 6: "fp6", 8: "i8"}
-    fmt_macs = {fmt_names[f]: sum(m for m, g in zip(pair_macs, fmt_bits) if g == f) for f in (4, 6, 8)}
-    dtype = "+".join(k for k in ("fp4", "fp6", "i8") if fmt_macs[k]) or "i8"
-    if n_ntt * 2 < len(engines):
-        achieved = 2.0 * macs / (engine_ms * 1e-3) / 1e12
-        t_at_peak = sum(m / (INT8_PEAK_TOPS if k == "i8" else FP6_FP4_PEAK_TFLOPS) for k, m in fmt_macs.items())
-        peak = sum(fmt_macs.values()) / t_at_peak if t_at_peak > 0 else INT8_PEAK_TOPS
-        src = os.path.join(ROOT, "paper_2509_19974_amd", "csrc", "k_xcorr_mfma.hip")
-        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TOP/s",
-                "frac": achieved / peak, "traffic": traffic_from_profile(src),
-                "kernel": "k_xcorr_mfma (32x32 matrix tiles: FP4/FP6 operands with fp32 accumulation for codes "
-                          "up to 7, int8 with int32 accumulation beyond)",
-                "peak_mix": {k: {"mac_share": m / max(sum(fmt_macs.values()), 1),
-                                 "peak": INT8_PEAK_TOPS if k == "i8" else FP6_FP4_PEAK_TFLOPS}
-                             for k, m in fmt_macs.items() if m},
-                "kernel_ms": engine_ms, "alg_macs_per_launch": macs}
+    if args.workload == "c5":
+        result = run_c5(args)
+        if not args.no_workloads:
+            wl = {}
+            wl["c2"] = run_plain(args, "c2", cpu_parity=not args.no_cpu_baseline)
+            for b in (2, 4, 8):
+                wl[f"c2_b{b}"] = run_plain(args, f"c2_b{b}", fft=False)
+            wl["c3_22"] = run_plain(args, "c3_22", path_name="ntt")
+            wl["c4"] = run_plain(args, "c4")
+            result["workloads"] = wl
+        ok = all(r.get("parity", {}).get("ok", True) for r in [result] + list(result.get("workloads", {}).values()))
     else:
-        # transform engine: modular butterflies (one Montgomery product each)
-        # of the three transforms per prime, against the 32-bit multiply rate
-        bf = 0
-        for p in pairs:
-            nx, ny = p["x"].size, p["y"].size
-            lo, hi = max(p["lag_lo"], -(nx - 1)), min(p["lag_hi"], ny - 1)
-            need = max(hi + nx, ny - lo)
-            lg = 13
-            while (1 << lg) < need:
-                lg += 1
-            k = tde.kmax_of_bits(p["bits"])
-            nprimes = 1 if min(nx, ny) * k * k < 2013265921 // 2 else 2
-            bf += nprimes * 3 * (1 << (lg - 1)) * lg
-        achieved = bf / (engine_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": MODMUL_PEAK_T, "unit": "Tbutterfly/s",
-                "frac": achieved / MODMUL_PEAK_T, "traffic": None,
-                "kernel": "k_ntt_cols_fwd + k_ntt_rows + k_ntt_cols_inv (two-prime NTT, Montgomery)",
-                "kernel_ms": engine_ms, "alg_butterflies_per_launch": bf}
-
-    result = {
-        "metric": "pairs/s and int-MAC/s vs FP32-FFT xcorr on MI355X at oracle-exact lags",
-        "value": len(pairs) * 1e3 / ms_step,
-        "unit": "pairs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": dtype if n_ntt * 2 < len(engines) else "u32",
-        "data": "synthetic",
-        "config": desc,
-        "int_mac_per_s": macs * 1e3 / ms_step,
-        "engines": {name: sum(1 for e in engines if e == code) for name, code in
-                    (("mfma", tde.TDE_PATH_MFMA), ("popc", tde.TDE_PATH_POPC), ("ntt", tde.TDE_PATH_NTT))},
-        "timing": "eager calls" if args.eager else "hip graph replay",
-        "eager_ms_per_step": eager_ms,
-        "stage_ms": {"quantize": stage_ms[0] / max(stage_n[0], 1), "engine": engine_ms,
-                     "argmax": stage_ms[2] / max(stage_n[2], 1), "call": stage_ms[3] / max(stage_n[3], 1)},
-        "lag_accuracy": {"int": int_correct},
-        "roofline": roof,
-    }
-    if not args.no_fft:
-        log("[bench] FP32 FFT baseline")
-        fms, flag = fft_baseline(torch, pairs, specs, args.steps, args.warmup)
-        result["fft_fp32"] = {"pairs_per_s": len(pairs) * 1e3 / fms, "ms_per_step": fms,
-                              "lag_accuracy": float(np.mean(np.array(flag) == d)),
-                              "speedup_int_over_fft": fms / ms_step}
-    if not args.no_cpu_baseline:
-        log("[bench] CPU oracle baseline")
-        result["cpu_baseline"] = cpu_baseline(pairs)
-    ctx.close()
+        res = run_plain(args, args.workload, args.path, fft=not args.no_fft, cpu_parity=not args.no_cpu_baseline)
+        result = {"metric": METRIC, "value": res.pop("pairs_per_s"), "unit": "pairs/s", "n_gpus": 1,
+                  "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),
+                  "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": res.pop("dtype"),
+                  "data": "synthetic", "config": res.pop("config")}
+        result.update(res)
+        ok = result.get("parity", {}).get("ok", True)
     print(json.dumps(result), flush=True)
+    if not ok:
+        log("[bench] PARITY FAILURE: a GPU result differs from the oracle")
+        sys.exit(3)
 
 
 if __name__ == "__main__":

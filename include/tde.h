@@ -441,13 +441,15 @@ int tde_tune_reset(void);
  * call records HIP events on the caller's stream around its stages:
  *   0 quantize (scale + codes), 1 correlation engine (in learned mode also
  *   the proposer), 2 argmax, 3 whole call, 4 proposer (learned mode: CNN
- *   forward and top-k, a part of stage 1).
+ *   forward and top-k, a part of stage 1), 5 windowed exact correlation
+ *   (learned mode, a part of stage 1), 6 the matrix-core engine's launch
+ *   (a part of stage 1; in learned mode the full-range fallback).
  * tde_timing_read waits for the recorded events, writes the summed
  * milliseconds and the number of timed calls per stage to ms[TDE_STAGES]
  * and count[TDE_STAGES] (host arrays), and clears the record. Enabling
  * allocates events; the estimate call itself still allocates no device
  * memory. */
-#define TDE_STAGES 5
+#define TDE_STAGES 7
 int tde_timing_enable(tde_ctx* ctx, int on);
 int tde_timing_read(tde_ctx* ctx, double* ms, int64_t* count);
 

@@ -95,6 +95,8 @@ def _load():
     lib.oracle_conv_fft.restype = None
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = None
     _lib = lib
     return lib
 
@@ -102,6 +104,11 @@ def _load():
 def threads() -> int:
     """OpenMP threads used by the direct sums."""
     return int(_load().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads for later direct sums (timing only; results do not depend on it)."""
+    _load().oracle_set_threads(int(n))
 
 
 def _ptr(a: np.ndarray):

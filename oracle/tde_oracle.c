@@ -223,3 +223,6 @@ void oracle_conv_fft(const int8_t* u, int64_t nu, const int8_t* v, int64_t nv, i
 /* Number of OpenMP threads the direct sums use. */
 #include <omp.h>
 int oracle_threads(void) { return omp_get_max_threads(); }
+
+/* Threads for the later direct sums (the CPU baseline times one thread too). */
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }

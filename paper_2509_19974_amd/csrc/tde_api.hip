@@ -1030,6 +1030,8 @@ int batch_enqueue(tde_ctx* ctx, uint8_t* W, const BatchPlan& B, const BatchLaunc
         rc = launch_xcorr_win(items_dev, (int)L.np, top, margin, B.theta, B.topk, model_net(B.model).nb,
                               reinterpret_cast<ArgPart*>(W + B.off_wparts), s);
         if (rc) return rc;
+        hipEvent_t t_w1 = mk();
+        if (timed) mark_stage(ctx, 5, t_p1, t_w1);
     }
     if (L.any_popc) {
         // zero the plane buffers (padding must read as 0), then pack
@@ -1046,9 +1048,12 @@ int batch_enqueue(tde_ctx* ctx, uint8_t* W, const BatchPlan& B, const BatchLaunc
         if (rc) return rc;
     }
     if (L.any_mfma) {
+        hipEvent_t t_m0 = mk();
         rc = launch_xcorr_mfma(items_dev, reinterpret_cast<const MWork*>(W + B.off_work), L.nwork,
                                reinterpret_cast<int*>(W + B.off_counters), true, tparts, ctx->num_cu, s, L.n4);
         if (rc) return rc;
+        hipEvent_t t_m1 = mk();
+        if (timed) mark_stage(ctx, 6, t_m0, t_m1);
     }
     hipEvent_t t_e1 = mk();
     if (timed) mark_stage(ctx, 1, t_e0, t_e1);

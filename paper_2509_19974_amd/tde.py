@@ -391,7 +391,7 @@ def tde_timing_enable(ctx, on: bool) -> None:
     _check(load_library().tde_timing_enable(ctx, 1 if on else 0))
 
 
-TDE_STAGES = 5
+TDE_STAGES = 7
 
 
 def tde_timing_read(ctx):
