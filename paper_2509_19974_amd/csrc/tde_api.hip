@@ -12,6 +12,10 @@
 
 #include "tde_internal.h"
 
+// pinned staging of a context, made once at tde_create (descriptor uploads
+// larger than this go through it in chunks)
+constexpr size_t kStagingBytes = (size_t)4 << 20;
+
 struct tde_ctx {
     int device;
     int num_cu;
@@ -98,23 +102,24 @@ struct Carve {
     }
 };
 
+// Host -> device copy through the context's pinned staging buffer (made at
+// tde_create, never reallocated): chunks of at most its size, each staged
+// only after the previous copy out of it has finished, so nothing here
+// allocates.
 int upload(tde_ctx* ctx, void* dst_dev, const void* src_host, size_t bytes, hipStream_t s) {
-    if (bytes == 0) return TDE_OK;
-    if (ctx->upload_pending) {
-        TDE_HIP_CHECK(hipEventSynchronize(ctx->upload_done));
-        ctx->upload_pending = false;
+    size_t done = 0;
+    while (done < bytes) {
+        if (ctx->upload_pending) {
+            TDE_HIP_CHECK(hipEventSynchronize(ctx->upload_done));
+            ctx->upload_pending = false;
+        }
+        const size_t nb = std::min(bytes - done, ctx->pinned_bytes);
+        memcpy(ctx->pinned, static_cast<const uint8_t*>(src_host) + done, nb);
+        TDE_HIP_CHECK(hipMemcpyAsync(static_cast<uint8_t*>(dst_dev) + done, ctx->pinned, nb, hipMemcpyHostToDevice, s));
+        TDE_HIP_CHECK(hipEventRecord(ctx->upload_done, s));
+        ctx->upload_pending = true;
+        done += nb;
     }
-    if (bytes > ctx->pinned_bytes) {
-        if (ctx->pinned) TDE_HIP_CHECK(hipHostFree(ctx->pinned));
-        ctx->pinned = nullptr;
-        size_t nb = std::max<size_t>(bytes, 1 << 20);
-        TDE_HIP_CHECK(hipHostMalloc(&ctx->pinned, nb, hipHostMallocDefault));
-        ctx->pinned_bytes = nb;
-    }
-    memcpy(ctx->pinned, src_host, bytes);
-    TDE_HIP_CHECK(hipMemcpyAsync(dst_dev, ctx->pinned, bytes, hipMemcpyHostToDevice, s));
-    TDE_HIP_CHECK(hipEventRecord(ctx->upload_done, s));
-    ctx->upload_pending = true;
     return TDE_OK;
 }
 
@@ -221,10 +226,12 @@ int tde_create(tde_ctx** out, int device) {
     {
         DeviceGuard g(device);
         if (hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) != hipSuccess ||
-            hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
-            delete c;
-            return set_error(TDE_ERR_HIP, "tde_create: event or stream creation failed");
+            hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+            hipHostMalloc(&c->pinned, kStagingBytes, hipHostMallocDefault) != hipSuccess) {
+            tde_destroy(c);
+            return set_error(TDE_ERR_HIP, "tde_create: event, stream or pinned staging creation failed");
         }
+        c->pinned_bytes = kStagingBytes;
     }
     *out = c;
     return TDE_OK;
@@ -401,12 +408,16 @@ size_t tde_xcorr_workspace_size(int64_t nu, int64_t nv, int kmax_u, int kmax_v, 
            align_bytes(2 * sizeof(int)) + pk;
 }
 
-int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, int64_t nv, int kmax_u, int kmax_v,
-                  int64_t lag_lo, int64_t lag_hi, void* r, int r_dtype, int path, void* ws, size_t ws_bytes,
-                  void* stream) {
-    int rc = check_xcorr(u, nu, v, nv, kmax_u, kmax_v, lag_lo, lag_hi, r, r_dtype, path, "tde_xcorr_int");
-    if (rc) return rc;
-    if (!ctx) return set_error(TDE_ERR_ARG, "tde_xcorr_int: null context");
+}  // extern "C"
+
+namespace {
+
+// Body of tde_xcorr_int, on the scratch ws (the caller's workspace, or the
+// device's static scratch for tde_xcorr_int_noalloc).
+int xcorr_run(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, int64_t nv, int kmax_u, int kmax_v,
+              int64_t lag_lo, int64_t lag_hi, void* r, int r_dtype, int path, void* ws, size_t ws_bytes,
+              void* stream) {
+    int rc;
     XItem it{};
     it.p.u = u;
     it.p.v = v;
@@ -501,6 +512,19 @@ int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, in
     return launch_xcorr_mfma(reinterpret_cast<const XItem*>(W), reinterpret_cast<const MWork*>(W + off_w),
                              (int)work.size(), counters, false, nullptr, ctx->num_cu, s,
                              mfma_launch_of(it.fmt, it.mb) == 4 ? (int)work.size() : 0);
+}
+
+}  // namespace
+
+extern "C" {
+
+int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, int64_t nv, int kmax_u, int kmax_v,
+                  int64_t lag_lo, int64_t lag_hi, void* r, int r_dtype, int path, void* ws, size_t ws_bytes,
+                  void* stream) {
+    int rc = check_xcorr(u, nu, v, nv, kmax_u, kmax_v, lag_lo, lag_hi, r, r_dtype, path, "tde_xcorr_int");
+    if (rc) return rc;
+    if (!ctx) return set_error(TDE_ERR_ARG, "tde_xcorr_int: null context");
+    return xcorr_run(ctx, u, nu, v, nv, kmax_u, kmax_v, lag_lo, lag_hi, r, r_dtype, path, ws, ws_bytes, stream);
 }
 
 // -------------------------------------------------------------- argmax --
