@@ -201,6 +201,20 @@ int tde_mfma_operand_bits(int kmax_u, int kmax_v, int path);
 int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, int64_t nv,
                   int kmax_u, int kmax_v, int64_t lag_lo, int64_t lag_hi,
                   void* r, int r_dtype, int path, void* ws, size_t ws_bytes, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid allocation):
+ * tde_xcorr_int without a workspace argument. Its scratch is a static
+ * device array of 16 MiB per device (one copy per GPU, held until the
+ * process ends), whose address tde_create looks up; the call allocates
+ * nothing, host or device. Same arguments, results and errors as
+ * tde_xcorr_int, plus TDE_ERR_UNSUPPORTED when the correlation needs more
+ * scratch than 16 MiB (tde_xcorr_workspace_size for the engine `path`
+ * selects). Calls on one device share that scratch: calls whose work
+ * overlaps in time on one GPU (different streams, or threads) race and
+ * must be serialised by the caller. */
+int tde_xcorr_int_noalloc(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, int64_t nv,
+                          int kmax_u, int kmax_v, int64_t lag_lo, int64_t lag_hi,
+                          void* r, int r_dtype, int path, void* stream);
 
 /* Algorithm 1, argmax step: over r[0 .. lag_hi-lag_lo] (device, r_dtype), writes
  * *out (device) = {smallest tau with r = max, max, number of maximisers, 0}.

@@ -16,6 +16,16 @@
 // larger than this go through it in chunks)
 constexpr size_t kStagingBytes = (size_t)4 << 20;
 
+// Static device scratch of tde_xcorr_int_noalloc: one copy per device, held
+// from the library's load until the process ends. In host code `scratch` is
+// only a handle: its device address (one per device) comes from
+// hipGetSymbolAddress at tde_create and is kept in g_scratch_ptr.
+constexpr size_t kNoAllocScratchBytes = (size_t)16 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+static void* g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
 struct tde_ctx {
     int device;
     int num_cu;
@@ -232,6 +242,19 @@ int tde_create(tde_ctx** out, int device) {
             return set_error(TDE_ERR_HIP, "tde_create: event, stream or pinned staging creation failed");
         }
         c->pinned_bytes = kStagingBytes;
+        if (device < kMaxDevices) {
+            std::lock_guard<std::mutex> lock(g_scratch_mu);
+            if (!g_scratch_ptr[device]) {
+                void* p = nullptr;
+                const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+                if (e != hipSuccess || !p) {
+                    tde_destroy(c);
+                    return set_error(TDE_ERR_HIP, "tde_create: address of the static scratch on device %d: %s",
+                                     device, hipGetErrorString(e));
+                }
+                g_scratch_ptr[device] = p;
+            }
+        }
     }
     *out = c;
     return TDE_OK;
@@ -525,6 +548,25 @@ int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, in
     if (rc) return rc;
     if (!ctx) return set_error(TDE_ERR_ARG, "tde_xcorr_int: null context");
     return xcorr_run(ctx, u, nu, v, nv, kmax_u, kmax_v, lag_lo, lag_hi, r, r_dtype, path, ws, ws_bytes, stream);
+}
+
+// tde_xcorr_int with the device's static scratch as its workspace.
+int tde_xcorr_int_noalloc(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, int64_t nv, int kmax_u,
+                          int kmax_v, int64_t lag_lo, int64_t lag_hi, void* r, int r_dtype, int path, void* stream) {
+    int rc = check_xcorr(u, nu, v, nv, kmax_u, kmax_v, lag_lo, lag_hi, r, r_dtype, path, "tde_xcorr_int_noalloc");
+    if (rc) return rc;
+    const int wpath = path == TDE_PATH_MFMA_I8 ? path
+                      : choose_path(path, nu, nv, kmax_u * kmax_v, kmax_u > kmax_v ? kmax_u : kmax_v, lag_lo, lag_hi);
+    const size_t need = tde_xcorr_workspace_size(nu, nv, kmax_u, kmax_v, lag_lo, lag_hi, wpath);
+    if (need > kNoAllocScratchBytes)
+        return set_error(TDE_ERR_UNSUPPORTED,
+                         "tde_xcorr_int_noalloc: this correlation needs %zu bytes of scratch; the static scratch "
+                         "holds %zu", need, kNoAllocScratchBytes);
+    if (!ctx) return set_error(TDE_ERR_ARG, "tde_xcorr_int_noalloc: null context");
+    void* ws = g_scratch_ptr[ctx->device];
+    if (!ws) return set_error(TDE_ERR_HIP, "tde_xcorr_int_noalloc: no scratch address for device %d", ctx->device);
+    return xcorr_run(ctx, u, nu, v, nv, kmax_u, kmax_v, lag_lo, lag_hi, r, r_dtype, path, ws, kNoAllocScratchBytes,
+                     stream);
 }
 
 // -------------------------------------------------------------- argmax --

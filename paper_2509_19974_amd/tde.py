@@ -96,6 +96,7 @@ def load_library(path: str = LIB_PATH):
         "tde_xcorr_workspace_size": (sz, [i64, i64, i32, i32, i64, i64, i32]),
         "tde_mfma_operand_bits": (i32, [i32, i32, i32]),
         "tde_xcorr_int": (i32, [vp, vp, i64, vp, i64, i32, i32, i64, i64, vp, i32, i32, vp, sz, vp]),
+        "tde_xcorr_int_noalloc": (i32, [vp, vp, i64, vp, i64, i32, i32, i64, i64, vp, i32, i32, vp]),
         "tde_argmax_workspace_size": (sz, [i64]),
         "tde_argmax_lag": (i32, [vp, vp, i32, i64, i64, vp, vp, sz, vp]),
         "tde_estimate_workspace_size": (sz, [ctypes.POINTER(tde_pair), i64, ctypes.POINTER(tde_opts)]),
