@@ -192,6 +192,7 @@ __device__ double exact_sumsq_wg(const float* x, int64_t n) {
 // wave shuffles take the levels above. Zeros beyond the last block sum extend
 // the power-of-two tree of the finalize kernel without changing its value.
 constexpr int64_t kFuseMaxN = 256 * kSumBlock;
+constexpr int64_t kFuseMaxBlocks = 8192;
 __device__ __forceinline__ double wave_tree_sum(const double* gsum, int64_t n) {
     const int64_t len = (n + kSumBlock - 1) / kSumBlock;
     const int l = threadIdx.x & 63;
@@ -424,8 +425,8 @@ __global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QS
         __shared__ long long red[4][4];
         long long a = wave_sum<long long>(nonfinite);
         long long z = wave_sum<long long>(nzero);
-        long long q1 = wave_sum<long long>(sq);
-        long long q2 = wave_sum<long long>(sq2);
+        long long q1 = s.stat_lite ? 0 : wave_sum<long long>(sq);
+        long long q2 = s.stat_lite ? 0 : wave_sum<long long>(sq2);
         const int wv = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
             red[wv][0] = a; red[wv][1] = z; red[wv][2] = q1; red[wv][3] = q2;
@@ -511,7 +512,9 @@ int launch_quantize(const QSig* sigs_dev, const QSig& one, int nsig, int64_t tot
                     bool write_flags, int* zero_me, int nzero, hipStream_t s, int64_t min_n, int64_t max_n) {
     // short signals: the quantize blocks finish the sum tree themselves, and
     // the finalize kernel (one small launch) is left out
-    const int fused = need_scale && min_n >= 1 && max_n <= kFuseMaxN ? 1 : 0;
+    // (large batches keep the finalize: one small launch costs less than every
+    // block re-deriving its signal's scale)
+    const int fused = need_scale && min_n >= 1 && max_n <= kFuseMaxN && total_blocks <= kFuseMaxBlocks ? 1 : 0;
     // equal lengths: the block -> signal map is a division (checked against
     // the grid, which is the sum of every signal's blocks)
     int bps = 0;

@@ -314,8 +314,6 @@ __device__ __forceinline__ void wave_loop(const XPair& p, int64_t T0, int64_t qw
 // against NB = 4 (wide lag ranges); narrow ranges keep NB = 4. Codes are
 // packed W bits each, in the operand layout of the instruction (lane (row or
 // column, g) holds k = 32 g .. 32 g + 31, code t at bits W t).
-typedef int v8i __attribute__((ext_vector_type(8)));
-typedef float v16f __attribute__((ext_vector_type(16)));
 
 template <int W, int NB>
 struct FCfg {
@@ -356,21 +354,6 @@ struct FCfg {
 // samples, with S samples per padded block of the v ring. Window starts are
 // multiples of 16 samples, so every 16-sample unit of a window is one unit of
 // the signal's packed array (or lies outside the signal: zeros).
-template <int W>
-__device__ __forceinline__ Packed16<W> load_unit(const uint32_t* pk, int64_t n, int64_t g) {
-    Packed16<W> o;
-    if (g >= 0 && 16 * g < n) {
-        const __attribute__((address_space(1))) uint32_t* p =
-            (const __attribute__((address_space(1))) uint32_t*)(pk + (W / 2) * g);
-#pragma unroll
-        for (int k = 0; k < W / 2; ++k) o.d[k] = p[k];
-    } else {
-#pragma unroll
-        for (int k = 0; k < W / 2; ++k) o.d[k] = 0u;
-    }
-    return o;
-}
-
 template <int W, int NB>
 struct FpStager {
     using C = FCfg<W, NB>;
@@ -445,52 +428,6 @@ __global__ void __launch_bounds__(256) k_pack_fp(const int8_t* q, int64_t n, uin
     const Packed16<W> c = fp_pack16<W>(load16_guarded(q, n, 16 * g));
 #pragma unroll
     for (int k = 0; k < W / 2; ++k) pk[(W / 2) * g + k] = c.d[k];
-}
-
-// A fragment: 32 codes of one row (16 or 24 bytes, 16- resp. 8-byte aligned).
-template <int W>
-__device__ __forceinline__ v8i read_a_fp(const uint8_t* p) {
-    v8i r = {0, 0, 0, 0, 0, 0, 0, 0};
-    if constexpr (W == 4) {
-        const uint4 x = *reinterpret_cast<const uint4*>(p);
-        r[0] = (int)x.x; r[1] = (int)x.y; r[2] = (int)x.z; r[3] = (int)x.w;
-    } else {
-        const uint2* q = reinterpret_cast<const uint2*>(p);
-        const uint2 x = q[0], y = q[1], z = q[2];
-        r[0] = (int)x.x; r[1] = (int)x.y; r[2] = (int)y.x; r[3] = (int)y.y; r[4] = (int)z.x; r[5] = (int)z.y;
-    }
-    return r;
-}
-
-template <int W>
-struct BWin {
-    uint32_t d[2 * W + 1];
-};
-
-template <int W>
-__device__ __forceinline__ BWin<W> read_bwin(const uint32_t* dw) {
-    BWin<W> r;
-#pragma unroll
-    for (int k = 0; k < 2 * W + 1; ++k) r.d[k] = dw[k];
-    return r;
-}
-
-// window bits [32 r + sh, ...): B_1 = dwords 0 .. W-1, B_0 = dwords W .. 2W-1
-template <int W>
-__device__ __forceinline__ void split_bwin(const BWin<W>& r, uint32_t sh, v8i& b1, v8i& b0) {
-    b1 = v8i{0, 0, 0, 0, 0, 0, 0, 0};
-    b0 = v8i{0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-        b1[k] = (int)__builtin_amdgcn_alignbit(r.d[k + 1], r.d[k], sh);
-        b0[k] = (int)__builtin_amdgcn_alignbit(r.d[W + k + 1], r.d[W + k], sh);
-    }
-}
-
-template <int W>
-__device__ __forceinline__ v16f mfma_fp(const v8i& a, const v8i& b, const v16f& c) {
-    constexpr int F = W == 4 ? kFmtF4 : kFmtF6;
-    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, F, F, 0, 127, 0, 127);
 }
 
 // The m loop of one wave over [qw_a, qw_b) (a multiple of 64 NP) for the tile

@@ -1,21 +1,35 @@
 // Algorithm 1, correlation step restricted to proposed lag windows: the exact integer
-// correlation r[tau] = sum_m u[m] v[m + tau] (Eq. (1)) over one window of 256
-// consecutive lags per workgroup, on the int8 matrix cores
-// (v_mfma_i32_16x16x64_i8, int32 accumulation), with the window's
-// (max, smallest lag, count) triple as the only output.
+// correlation r[tau] = sum_m u[m] v[m + tau] (Eq. (1)) over windows of 256
+// consecutive lags, with each window's (max, smallest lag, count) triple as
+// the only output. Two kernels:
 //
-// A window tile holds tau = T0 + j + 16 i (i, j < 16). With steps of 64 in m:
+// k_xcorr_win_fp (codes up to 3 / 7: FP4 / FP6 operands of
+// v_mfma_scale_f32_32x32x64_f8f6f4, fp32 accumulation of integers, exact
+// while a wave's partial sum stays below 2^24): one workgroup per pair, all
+// of its windows (at most 8) in one 32-row tile. Row i = 4 w + g is group g
+// (64 lags) of window w, column j, column block b in {0, 1}:
+//     tau = T0_w + 64 g + 32 b + j
+//     A[i][k]   = v[q + T0_w + 64 g + k]       k in [0, 64)
+//     B_b[k][j] = u[q + k - j - 32 b]          the same for every window
+// so C_b[i][j] collects u[m] v[m + tau] for m = q + k - j - 32 b, and one
+// 64-code u window (B_1 | B_0) per step feeds both matrix instructions of
+// all 8 windows.
+//
+// k_xcorr_win (int8 operands, v_mfma_i32_16x16x64_i8, int32 accumulation):
+// one workgroup per window, for int8 codes or more than 8 windows. A window
+// tile holds tau = T0 + j + 16 i (i, j < 16). With steps of 64 in m:
 //     A[i][k] = v[q + T0 + 16 i + k]     (rows 16 bytes apart)
 //     B[k][j] = u[q + k - j]             (Hankel in (k, j))
 //     C[i][j] += sum_k A[i][k] B[k][j]   collects u[m] v[m + tau], m = q + k - j
-// For each j the steps q = Qa, Qa + 64, ... cover m in [Qa - j, Qb - j) once,
-// so Qa <= first m and Qb >= last m + 16 make every sum complete; samples
-// outside the signals are staged as 0 (finite support, Section 2.2).
 //
-// The 4 waves of a workgroup take a quarter of the steps each, staging their
-// own chunk of u and v in LDS; partial tiles meet in LDS in int64. Each
-// wave's int32 sum covers at most a quarter of the m range, which the host
-// keeps below (2^31 - 1) / (Ku Kv) values.
+// In both, for each column the steps q = Qa, Qa + 64, ... cover a contiguous
+// m range, so Qa <= first m and Qb >= last m + 16 (+ 32 for block 1) make
+// every sum complete; samples outside the signals are staged as 0 (finite
+// support, Section 2.2). The 4 waves of a workgroup take a quarter of the
+// steps each, staging their own chunk of u and v in LDS; partial tiles meet
+// in LDS in int64. Each wave's partial covers at most a quarter of the m
+// range, which the host keeps below 2^24 / (Ku Kv) values for the FP kernel
+// and (2^31 - 1) / (Ku Kv) for the int8 one.
 #include "tde_internal.h"
 
 namespace tde {
@@ -66,6 +80,7 @@ __global__ void __launch_bounds__(256) k_xcorr_win(const XItem* items, const int
     const int pair = blockIdx.x / topk, slot = blockIdx.x % topk;
     if (!(margin[pair] >= theta)) return;          // fallback pair (also NaN)
     const XItem& it = items[pair];
+    if (it.win_w != 0) return;                     // windows on the FP kernel
     const XPair& p = it.p;
     const int bin = top[(int64_t)pair * topk + slot];
     const int64_t T0 = (int64_t)(bin - nb / 2) * 256;
@@ -140,11 +155,198 @@ __global__ void __launch_bounds__(256) k_xcorr_win(const XItem* items, const int
     }
 }
 
+// ------------------------------------------------------------ FP operands --
+template <int W>
+struct WinFp {
+    static constexpr int KS = 64;                 // m per matrix step
+    static constexpr int CQ = 16;                 // steps per staged chunk
+    static constexpr int CM = KS * CQ;            // m per chunk
+    static constexpr int VWIN = CM + 192;         // v codes of a window region: rows reach 64 g + k < 256
+    static constexpr int UWIN = CM + 144;         // u codes from q0 - 64: B windows end by q + 64, plus one dword
+    // padded bytes of a window region: A rows are read as 8-byte (FP6) or
+    // 16-byte (FP4) pieces, so regions and wave areas keep 16-byte alignment
+    static constexpr int VB = VWIN * W / 8 + 16;
+    static constexpr int UB = UWIN * W / 8;
+    static constexpr int WAVE_LDS = (8 * VB + UB + 15) / 16 * 16;
+    static constexpr int VUNITS = VWIN / 16, UUNITS = UWIN / 16;
+    static constexpr int UNITS = 8 * VUNITS + UUNITS;
+    static constexpr int PER_LANE = (UNITS + 63) / 64;
+    static_assert(VWIN % 16 == 0 && UWIN % 16 == 0, "regions are whole 16-code units");
+    static_assert(VB % 16 == 0, "16-byte aligned window regions");
+    static_assert(4 * WAVE_LDS >= 8 * 256 * 8, "the reduction area must fit");
+};
+
+// grid npairs: workgroup -> pair. Pairs below the margin threshold (full-range
+// fallback) and pairs whose windows run on the int8 kernel are skipped.
+template <int W>
+__global__ void __launch_bounds__(256) k_xcorr_win_fp(const XItem* items, const int32_t* top, const float* margin,
+                                                      float theta, int topk, int nb, ArgPart* parts) {
+    using C = WinFp<W>;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[4 * C::WAVE_LDS];
+    __shared__ int64_t s_t0[8];
+    const int pair = blockIdx.x;
+    if (!(margin[pair] >= theta)) return;          // fallback pair (also NaN)
+    const XItem& it = items[pair];
+    if (it.win_w != W) return;
+    // descriptor fields in registers (LDS stores below go through generic
+    // pointers, after which fields read through `it` would be reloaded)
+    const uint32_t* upk = it.p.upk;
+    const uint32_t* vpk = it.p.vpk;
+    const int64_t nu = it.p.nu, nv = it.p.nv, lag_lo = it.p.lag_lo, lag_hi = it.p.lag_hi;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform in the wave
+    // the windows' first lags (an LDS table: the staging loop indexes it by
+    // a computed window); the union of their m ranges
+    if (threadIdx.x < 8)
+        s_t0[threadIdx.x] = (int)threadIdx.x < topk ? (int64_t)(top[(int64_t)pair * topk + threadIdx.x] - nb / 2) * 256
+                                                    : 0;
+    __syncthreads();
+    int64_t m_lo = INT64_MAX, m_hi = INT64_MIN;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+        if (w < topk) {
+            const int64_t t0 = s_t0[w];
+            const int64_t lo = t0 + 255 < 0 ? -(t0 + 255) : 0;
+            const int64_t hi = nu < nv - t0 ? nu : nv - t0;
+            if (hi > lo) {
+                m_lo = lo < m_lo ? lo : m_lo;
+                m_hi = hi > m_hi ? hi : m_hi;
+            }
+        }
+    }
+    v16f acc0, acc1;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc0[e] = acc1[e] = 0.f;
+    if (m_hi > m_lo) {
+        const int64_t Qa = floor_div(m_lo, 64) * 64;
+        const int64_t Qb = ceil_div(m_hi + 63, 64) * 64;
+        // whole chunks per wave: steps past Qb meet only zero samples (each
+        // window's m range ends by Qb - 63), so they add nothing
+        const int64_t nsteps = (Qb - Qa) / 64;
+        const int64_t per = round_up(ceil_div(nsteps, 4), C::CQ);
+        const int64_t sa = wv * per, sb = sa + per;
+        uint8_t* vb = lds + wv * C::WAVE_LDS;
+        uint8_t* ub = vb + 8 * C::VB;
+        const int i = lane & 31, kh = lane >> 5;
+        const int w = i >> 2, g = i & 3;
+        const bool live = w < topk;
+        // A row of this lane: window w's region, group g, k half kh
+        const uint8_t* arow = vb + w * C::VB + ((64 * g + 32 * kh) * W) / 8;
+        // B window of this lane (column j = i, k half kh) at step s of a chunk
+        // starts at code 64 s + 32 + 32 kh - j of the u region
+        const int brel = 32 + 32 * kh - i;
+        const uint32_t* ubw = reinterpret_cast<const uint32_t*>(ub) + ((W * brel) >> 5);
+        const uint32_t bsh = (uint32_t)((W * brel) & 31);
+        Packed16<W> reg[C::PER_LANE];
+        auto load = [&](int64_t q0) {
+#pragma unroll
+            for (int k = 0; k < C::PER_LANE; ++k) {
+                const int unit = lane + 64 * k;
+                if (unit < 8 * C::VUNITS) {
+                    const int ww = unit / C::VUNITS, uu = unit - ww * C::VUNITS;
+                    if (ww < topk) reg[k] = load_unit<W>(vpk, nv, (q0 + s_t0[ww]) / 16 + uu);
+                } else if (unit < C::UNITS) {
+                    reg[k] = load_unit<W>(upk, nu, (q0 - 64) / 16 + (unit - 8 * C::VUNITS));
+                }
+            }
+        };
+        auto store = [&]() {
+#pragma unroll
+            for (int k = 0; k < C::PER_LANE; ++k) {
+                const int unit = lane + 64 * k;
+                uint8_t* dst = nullptr;
+                if (unit < 8 * C::VUNITS) {
+                    const int ww = unit / C::VUNITS, uu = unit - ww * C::VUNITS;
+                    if (ww < topk) dst = vb + ww * C::VB + 2 * W * uu;
+                } else if (unit < C::UNITS) {
+                    dst = ub + 2 * W * (unit - 8 * C::VUNITS);
+                }
+                if (dst) {
+                    uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+#pragma unroll
+                    for (int e = 0; e < W / 2; ++e) d[e] = reg[k].d[e];
+                }
+            }
+        };
+        constexpr int ASTEP = C::KS * W / 8;       // bytes per step along a row
+        // a row of a window past topk is zero (its region is never staged)
+        const int live_mask = live ? -1 : 0;
+        load(Qa + 64 * sa);
+        for (int64_t s0 = sa; s0 < sb; s0 += C::CQ) {
+            store();                                // this wave's reads of the last chunk are done (in order)
+            if (s0 + C::CQ < sb) load(Qa + 64 * (s0 + C::CQ));
+            // fragments of step s + 1 are read while the matrix
+            // instructions of step s run
+            v8i a = read_a_fp<W>(arow);
+            BWin<W> raw = read_bwin<W>(ubw);
+#pragma unroll
+            for (int s = 0; s < C::CQ; ++s) {
+                v8i b1, b0;
+                split_bwin<W>(raw, bsh, b1, b0);
+                v8i a_cur;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) a_cur[e] = a[e] & live_mask;
+                if (s + 1 < C::CQ) {
+                    a = read_a_fp<W>(arow + ASTEP * (s + 1));
+                    raw = read_bwin<W>(ubw + 2 * W * (s + 1));
+                }
+                acc0 = mfma_fp<W>(a_cur, b0, acc0);
+                acc1 = mfma_fp<W>(a_cur, b1, acc1);
+            }
+        }
+    }
+    // the waves' partials meet in LDS (int64): red[w][lag offset in the window]
+    __syncthreads();
+    long long* red = reinterpret_cast<long long*>(lds);
+    for (int k = threadIdx.x; k < 8 * 256; k += 256) red[k] = 0;
+    __syncthreads();
+    {
+        const int j = lane & 31, gq = lane >> 5;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int i = 8 * (e >> 2) + 4 * gq + (e & 3);
+            const int w = i >> 2, g = i & 3;
+            const int v0 = (int)acc0[e], v1 = (int)acc1[e];
+            if (v0) atomicAdd((unsigned long long*)&red[w * 256 + 64 * g + j], (unsigned long long)(long long)v0);
+            if (v1) atomicAdd((unsigned long long*)&red[w * 256 + 64 * g + 32 + j], (unsigned long long)(long long)v1);
+        }
+    }
+    __syncthreads();
+    // wave wv: the triples of windows 2 wv and 2 wv + 1
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int w = 2 * wv + h;
+        Tri t{INT64_MIN, INT64_MAX, 0};
+        if (w < topk) {
+            const int64_t base = s_t0[w] - lag_lo;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int k = lane + 64 * r;
+                const int64_t idx = base + k;
+                if (idx >= 0 && idx <= lag_hi - lag_lo) t = tjoin(t, Tri{(int64_t)red[w * 256 + k], idx, 1});
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            Tri u{__shfl_xor(t.v, o, 64), __shfl_xor(t.i, o, 64), __shfl_xor(t.c, o, 64)};
+            t = tjoin(t, u);
+        }
+        if (lane == 0 && w < topk) parts[(int64_t)pair * topk + w] = ArgPart{t.v, t.i, t.c};
+    }
+}
+
 int launch_xcorr_win(const XItem* items_dev, int npairs, const int32_t* top, const float* margin, float theta,
-                     int topk, int nb, ArgPart* parts, hipStream_t s) {
+                     int topk, int nb, ArgPart* parts, hipStream_t s, int formats) {
     if (npairs == 0) return TDE_OK;
-    hipLaunchKernelGGL(k_xcorr_win, dim3(npairs * topk), dim3(256), 0, s, items_dev, top, margin, theta, topk, nb,
-                       parts);
+    if (formats & 1)
+        hipLaunchKernelGGL(k_xcorr_win, dim3(npairs * topk), dim3(256), 0, s, items_dev, top, margin, theta, topk, nb,
+                           parts);
+    if (formats & 2)
+        hipLaunchKernelGGL(k_xcorr_win_fp<6>, dim3(npairs), dim3(256), 0, s, items_dev, top, margin, theta, topk, nb,
+                           parts);
+    if (formats & 4)
+        hipLaunchKernelGGL(k_xcorr_win_fp<4>, dim3(npairs), dim3(256), 0, s, items_dev, top, margin, theta, topk, nb,
+                           parts);
     TDE_HIP_CHECK(hipGetLastError());
     return TDE_OK;
 }

@@ -909,10 +909,24 @@ struct BatchLaunch {
     bool need_scale = false, any_popc = false, any_mfma = false, any_fused = false, any_r = false;
     int64_t max_rbytes = 0, p_split = 0, p_tiles = 0, p_words = 0;
     int nwork = 0, nsegs = 0, n4 = 0;
+    int win_formats = 0;                                  // learned mode: window kernels to launch
     std::vector<std::pair<NttGroup, int64_t>> ngroups;   // (group, first job index)
     std::vector<int> ngroup_jobs;
     int64_t p_zero_words = 0;                             // largest bit-plane region (words)
 };
+
+// Learned mode: the operand width (4 or 6) of the pair's FP window kernel, or
+// 0 for the int8 one. The FP kernel takes codes up to 7 (the pair's
+// matrix-core format is FP4/FP6), at most 8 windows in its one tile, and
+// signals short enough that a wave's fp32 partial (a quarter of the m range
+// in whole chunks, plus the tile's reach) stays below 2^24.
+int win_fp_width(const tde_pair& q, const PairPlan& pp, const BatchPlan& B) {
+    if (!B.learned || B.topk > 8 || pp.probe.fmt == kFmtI8) return 0;
+    const int64_t K = kmax_of_bits(q.bits);
+    // a wave's m range: a quarter of the steps, rounded up to whole 16-step chunks
+    if ((std::max(q.nx, q.ny) / 4 + 2048) * K * K >= ((int64_t)1 << 24)) return 0;
+    return pp.probe.fmt == kFmtF6 ? 6 : 4;
+}
 
 void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* out, uint8_t* W, const BatchPlan& B,
                    BatchLaunch& L) {
@@ -934,6 +948,7 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
             S.n = side ? q.ny : q.nx;
             S.q = reinterpret_cast<int8_t*>(W + B.off_q[2 * i + side]);
             S.stat = stats + 2 * i + side;
+            S.stat_lite = 1;
             S.gsum = reinterpret_cast<double*>(W + B.off_gsum[2 * i + side]);
             S.inv_out = invs + 2 * i + side;
             S.blk_base = bbase;
@@ -944,9 +959,9 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
             if (B.off_pk[2 * i + side]) {
                 S.pk = reinterpret_cast<uint32_t*>(W + B.off_pk[2 * i + side]);
                 S.pk_bits = pp.probe.fmt == kFmtF6 ? 6 : 4;
-                // the FP engine reads only the packed codes; the window
-                // kernel of the learned path reads the int8 ones
-                S.skip_q = B.learned ? 0 : 1;
+                // the FP engine reads only the packed codes; so does the
+                // learned path's FP window kernel (the int8 one reads int8 codes)
+                S.skip_q = B.learned && win_fp_width(q, pp, B) == 0 ? 0 : 1;
             }
             if (B.learned) {
                 // decimated CNN input, written by the quantize kernel
@@ -976,6 +991,8 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
             it.theta = B.theta;
             it.nwin = B.topk;
             it.win_parts = reinterpret_cast<const ArgPart*>(W + B.off_wparts) + i * B.topk;
+            it.win_w = win_fp_width(q, pp, B);
+            L.win_formats |= it.win_w == 6 ? 2 : it.win_w == 4 ? 4 : 1;
         }
         if (it.p.r) {
             L.any_r = true;
@@ -1094,7 +1111,7 @@ int batch_enqueue(tde_ctx* ctx, uint8_t* W, const BatchPlan& B, const BatchLaunc
         hipEvent_t t_p1 = mk();
         if (timed) mark_stage(ctx, 4, t_p0, t_p1);
         rc = launch_xcorr_win(items_dev, (int)L.np, top, margin, B.theta, B.topk, model_net(B.model).nb,
-                              reinterpret_cast<ArgPart*>(W + B.off_wparts), s);
+                              reinterpret_cast<ArgPart*>(W + B.off_wparts), s, L.win_formats);
         if (rc) return rc;
         hipEvent_t t_w1 = mk();
         if (timed) mark_stage(ctx, 5, t_p1, t_w1);

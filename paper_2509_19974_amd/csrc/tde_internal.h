@@ -95,6 +95,81 @@ __device__ __forceinline__ Packed16<W> fp_pack16(uint4 x) {
     return o;
 }
 
+// Fragments of the FP4/FP6 matrix instruction v_mfma_scale_f32_32x32x64_f8f6f4
+// (scale 1): a lane holds row (A) or column (B) l mod 32 and k = 32 (l / 32)
+// .. + 31, code t at bits W t of its W dwords; the 32 x 32 fp32 result
+// has the int8 instruction's layout (lane j + 32 g, register e: row
+// 8 (e / 4) + 4 g + (e mod 4), column j).
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// Operand format codes of the matrix-core engine (the instruction's own).
+constexpr int kFmtI8 = 0;      // (the instruction would read 0 as FP8; int8 items never use it)
+constexpr int kFmtF6 = 2;
+constexpr int kFmtF4 = 4;
+
+// 16-code unit g of a packed array of n codes (zeros outside the signal).
+template <int W>
+__device__ __forceinline__ Packed16<W> load_unit(const uint32_t* pk, int64_t n, int64_t g) {
+    Packed16<W> o;
+    if (g >= 0 && 16 * g < n) {
+        const __attribute__((address_space(1))) uint32_t* p =
+            (const __attribute__((address_space(1))) uint32_t*)(pk + (W / 2) * g);
+#pragma unroll
+        for (int k = 0; k < W / 2; ++k) o.d[k] = p[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < W / 2; ++k) o.d[k] = 0u;
+    }
+    return o;
+}
+
+// A fragment: 32 codes of one row (16 or 24 bytes, 16- resp. 8-byte aligned).
+template <int W>
+__device__ __forceinline__ v8i read_a_fp(const uint8_t* p) {
+    v8i r = {0, 0, 0, 0, 0, 0, 0, 0};
+    if constexpr (W == 4) {
+        const uint4 x = *reinterpret_cast<const uint4*>(p);
+        r[0] = (int)x.x; r[1] = (int)x.y; r[2] = (int)x.z; r[3] = (int)x.w;
+    } else {
+        const uint2* q = reinterpret_cast<const uint2*>(p);
+        const uint2 x = q[0], y = q[1], z = q[2];
+        r[0] = (int)x.x; r[1] = (int)x.y; r[2] = (int)y.x; r[3] = (int)y.y; r[4] = (int)z.x; r[5] = (int)z.y;
+    }
+    return r;
+}
+
+template <int W>
+struct BWin {
+    uint32_t d[2 * W + 1];
+};
+
+template <int W>
+__device__ __forceinline__ BWin<W> read_bwin(const uint32_t* dw) {
+    BWin<W> r;
+#pragma unroll
+    for (int k = 0; k < 2 * W + 1; ++k) r.d[k] = dw[k];
+    return r;
+}
+
+// window bits [32 r + sh, ...): B_1 = dwords 0 .. W-1, B_0 = dwords W .. 2W-1
+template <int W>
+__device__ __forceinline__ void split_bwin(const BWin<W>& r, uint32_t sh, v8i& b1, v8i& b0) {
+    b1 = v8i{0, 0, 0, 0, 0, 0, 0, 0};
+    b0 = v8i{0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        b1[k] = (int)__builtin_amdgcn_alignbit(r.d[k + 1], r.d[k], sh);
+        b0[k] = (int)__builtin_amdgcn_alignbit(r.d[W + k + 1], r.d[W + k], sh);
+    }
+}
+
+template <int W>
+__device__ __forceinline__ v16f mfma_fp(const v8i& a, const v8i& b, const v16f& c) {
+    constexpr int F = W == 4 ? kFmtF4 : kFmtF6;
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, F, F, 0, 127, 0, 127);
+}
+
 // Largest code magnitude of a b-bit quantizer (sign: ternary, K = 1).
 inline int kmax_of_bits(int bits) { return bits == 1 ? 1 : (1 << (bits - 1)) - 1; }
 
@@ -123,6 +198,9 @@ struct QSig {
     // 1: only the packed codes are stored (nothing reads the int8 codes; the
     // statistics still count them)
     int32_t skip_q;
+    // 1: the statistics keep only the non-finite and zero counts (sum_q and
+    // sum_q2 stay 0), all that the batch call's flags need
+    int32_t stat_lite;
 };
 // z-unit cell boundaries (ascending, K of them) of the non-uniform quantizer
 // `kind` (TDE_QUANT_MULAW, TDE_QUANT_GAUSS) for bits 2 or 4; returns K, or 0
@@ -242,6 +320,7 @@ struct XItem {
     float theta;
     int32_t nwin;
     const ArgPart* win_parts;
+    int32_t win_w;        // learned mode: 4 or 6, windows on FP operands of that width; 0, on int8
 };
 
 // zero the bit-plane regions of a batch (one launch for every pair)
@@ -262,12 +341,9 @@ struct MWork {
     int32_t fmt;          // operand format of the pair's plan
     int32_t pad0;
 };
-// Operand formats of the matrix-core engine. Codes with |q| <= 3 are exact in
-// FP4 (E2M1), |q| <= 7 in FP6 (E2M3); both run the f8f6f4 matrix instruction
-// at twice the int8 rate. The values double as the instruction's format codes.
-constexpr int kFmtI8 = 0;      // (the instruction would read 0 as FP8; int8 items never use it)
-constexpr int kFmtF6 = 2;
-constexpr int kFmtF4 = 4;
+// Operand formats of the matrix-core engine (kFmtI8, kFmtF6, kFmtF4 above).
+// Codes with |q| <= 3 are exact in FP4 (E2M1), |q| <= 7 in FP6 (E2M3); both
+// run the f8f6f4 matrix instruction at twice the int8 rate.
 // sets fmt, mb, T_start, ntiles, wide, segmented, outside triple; allow_fp =
 // false keeps int8 operands whatever the code range
 void mfma_plan_pair(XItem& it, bool allow_fp = true);
@@ -300,9 +376,12 @@ int launch_xcorr_popc(const XItem* items_dev, const XItem& one, int nitems, int6
 // int8 copy helper
 int launch_copy_bytes(void* dst, const void* src, size_t n, hipStream_t s);
 
-// windowed exact engine (learned mode): grid npairs x topk windows of 256 lags
+// windowed exact engine (learned mode), windows of 256 lags: formats bit 0
+// launches the int8 kernel (a workgroup per window) for pairs with win_w = 0,
+// bits 1 and 2 the FP6 and FP4 kernels (a workgroup per pair, topk <= 8)
+// for pairs with win_w = 6 and 4
 int launch_xcorr_win(const XItem* items_dev, int npairs, const int32_t* top, const float* margin, float theta,
-                     int topk, int nb, ArgPart* parts, hipStream_t s);
+                     int topk, int nb, ArgPart* parts, hipStream_t s, int formats);
 
 // tie refinement (Algorithm 1, tie-refinement step): scratch of one call,
 // every array sized for max_ties lags except hits (kRefineMaxChunks per-chunk

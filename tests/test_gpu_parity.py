@@ -1071,6 +1071,23 @@ def test_learned_batch_matches_window_semantics(T, ctx):
     model.close()
 
 
+@pytest.mark.parametrize("topk", [8, 12])
+def test_learned_batch_window_formats(T, ctx, topk):
+    """Windows on every operand format in one learned batch: b = 2 (FP4
+    window kernel), b = 4 (FP6), b = 8 (int8 kernel); with 12 windows every
+    pair takes the int8 kernel (the FP kernel holds 8 windows per tile).
+    Results equal the oracle's argmax over the union of the GPU's bins."""
+    from paper_2509_19974_amd import tde
+    say(f"learned window formats topk={topk}")
+    model = tde.Model(ctx, 1024, 64, seed=8)
+    pairs = synth.config5_reverb(npairs=12, n=16384, max_lag=64 * 128, t60_range=(200, 1200), salt=4)
+    for i, p in enumerate(pairs):
+        p["bits"] = (2, 4, 8)[i % 3]
+    pk, top, margin = _learned_case(T, ctx, model, pairs, topk, -1e30)
+    _check_learned(pk, top, margin, pairs, -1e30, 64)
+    model.close()
+
+
 def test_learned_batch_full_size_windows(T, ctx):
     """The full-size proposer shape (ld 16384, 512 bins of 256 lags over
     [-65536, 65535], N = 2^18, b = 4) on 8 pairs, every pair on its 8 windows
