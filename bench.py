@@ -437,8 +437,9 @@ def run_c5(args):
                          "kernel_ms": st_l["proposer"], "alg_macs_per_launch": cnn_macs * npairs}
     wm = window_macs(top.cpu().numpy(), np.zeros(npairs, bool), n, nbins)
     roofs["windows"] = {"bound": "mfma", "achieved": 2.0 * wm / (st_l["windows"] * 1e-3) / 1e12,
-                        "peak": INT8_PEAK_TOPS, "unit": "TOP/s", "kernel": "k_xcorr_win (exact correlation in the "
-                        "top bins, int8 matrix tiles)", "kernel_ms": st_l["windows"], "alg_macs_per_launch": wm}
+                        "peak": FP6_FP4_PEAK_TFLOPS, "unit": "TFLOP/s", "kernel": "k_xcorr_win_fp<6> (exact "
+                        "correlation in the top-8 bins, FP6 matrix operands, one 32-row tile per pair)",
+                        "kernel_ms": st_l["windows"], "alg_macs_per_launch": wm}
     if "mfma_engine" in st_l:
         fm = int(np.count_nonzero(fb_mask)) * alg_macs(n, n, -lag, lag - 1)
         roofs["fallback"] = {"bound": "mfma", "achieved": 2.0 * fm / (st_l["mfma_engine"] * 1e-3) / 1e12,
