@@ -47,6 +47,7 @@ BF16_PEAK_TFLOPS = 2500.0    # MI355X dense bf16 matrix peak, 2.5 PFLOP/s
 HBM_PEAK_GBS = 8000.0
 METRIC = "pairs/s and int-MAC/s vs FP32-FFT xcorr on MI355X at oracle-exact lags"
 WEIGHTS = os.path.join(ROOT, "paper_2509_19974_amd", "weights", "proposer_n18")
+TUNE_TABLE = os.path.join(ROOT, "paper_2509_19974_amd", "weights", "tune_mi355x.txt")
 
 
 def log(*a):
@@ -298,6 +299,9 @@ def run_plain(args, name, path_name="auto", fft=True, cpu_parity=False):
     if args.tune:
         log("[bench] autotuning engines")
         tde.tde_tune(ctx.handle, 20)
+    elif args.tune_table:
+        log(f"[bench] engine table {args.tune_table}")
+        tde.tde_tune_load(args.tune_table)
     engines = [tde.tde_tune_query(p["nx"], p["ny"], tde.kmax_of_bits(p["bits"]), tde.kmax_of_bits(p["bits"]),
                                   p["lag_lo"], p["lag_hi"]) if path == tde.TDE_PATH_AUTO else path for p in pairs]
     macs = sum(alg_macs(p["nx"], p["ny"], p["lag_lo"], p["lag_hi"]) for p in pairs)
@@ -373,6 +377,8 @@ def run_c5(args):
     stream = torch.cuda.current_stream()
     model = tde.Model(ctx, n // 16, nbins)
     model.load(WEIGHTS + ".tdem")
+    if args.tune_table:
+        tde.tde_tune_load(args.tune_table)
     log("[bench] generating 1024 reverberant pairs on the GPU")
     g = [synth.config5_reverb_torch(torch, 512, salt=s, n=n, max_lag=lag) for s in (0, 1)]
     X = torch.cat([a["x"] for a in g])
@@ -743,6 +749,8 @@ def main():
     ap.add_argument("--eager", action="store_true",
                     help="time eager calls instead of HIP-graph replays of the whole call")
     ap.add_argument("--tune", action="store_true", help="run the engine autotuner before planning")
+    ap.add_argument("--tune-table", default=TUNE_TABLE,
+                    help="engine and tile-width table measured on MI355X ('' for the built-in rules)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-workloads", action="store_true", help="default line only, without the other configs")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of CPU oracle work")

@@ -195,9 +195,13 @@ size_t tde_xcorr_workspace_size(int64_t nu, int64_t nv, int kmax_u, int kmax_v,
                                 int64_t lag_lo, int64_t lag_hi, int path);
 /* Operand width (4, 6 or 8 bits) the matrix-core engine multiplies codes of
  * these ranges in, for path TDE_PATH_AUTO, _MFMA or _MFMA_I8 (the choice
- * above; the environment variable TDE_MFMA_FP=0 keeps int8 everywhere).
+ * above).
  * Errors: TDE_ERR_ARG (kmax out of [1, 127], another path). */
 int tde_mfma_operand_bits(int kmax_u, int kmax_v, int path);
+/* Lags per tile (4096 or 8192) the matrix-core engine cuts this correlation
+ * into, for path TDE_PATH_AUTO, _MFMA or _MFMA_I8: the tuning table's tile
+ * width for its bucket, else the built-in rule. Errors: TDE_ERR_ARG. */
+int tde_mfma_tile_lags(int64_t nu, int64_t nv, int kmax_u, int kmax_v, int64_t lag_lo, int64_t lag_hi, int path);
 int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, int64_t nv,
                   int kmax_u, int kmax_v, int64_t lag_lo, int64_t lag_hi,
                   void* r, int r_dtype, int path, void* ws, size_t ws_bytes, void* stream);
@@ -425,14 +429,18 @@ int tde_train_step(tde_ctx* ctx, tde_model* model, const uint16_t* xdec, const i
  * shared by every context of the process, keyed on the size bucket
  * round(log2(max(nu, nv))) in [10, 23], the requested fraction of the full
  * linear lag range (<= 1/16, <= 1/2, more) and the code class (Ku Kv = 1,
- * <= 49, larger). Without a table a built-in cost model decides. All engines
- * give identical results; only speed differs. Workspace sizes computed for
- * TDE_PATH_AUTO assume the table in place at that moment: install or change
- * the table before sizing workspaces (a call with a too-small workspace
- * returns TDE_ERR_WS). */
+ * <= 49, larger). The table also holds, per bucket, the matrix-core
+ * engine's tile width (4 or 8 accumulator blocks of 1024 lags), used by
+ * every matrix-core correlation of the bucket whatever its path. Without a
+ * table a built-in cost model picks the engine and a rule the tile width.
+ * All engines and tiles give identical results; only speed differs.
+ * Workspace sizes assume the table in place at that moment: install or
+ * change the table before sizing workspaces (a call with a too-small
+ * workspace returns TDE_ERR_WS). */
 
-/* Measure every applicable engine for sizes 2^10 .. 2^max_log_n (max_log_n
- * in [10, 22]) and all buckets, and install the fastest per bucket; larger
+/* Measure every applicable engine (the matrix-core engine at both tile
+ * widths) for sizes 2^10 .. 2^max_log_n (max_log_n in [10, 22]) and all
+ * buckets, and install the fastest engine and tile width per bucket; larger
  * sizes take the largest measured bucket. Each bucket is timed as the batch
  * call runs it: a batch of identical synthetic pairs (b = 1, 4 or 8 for the
  * three code classes) large enough to fill the device, scored per pair. Not
@@ -441,10 +449,12 @@ int tde_tune(tde_ctx* ctx, int max_log_n, void* stream);
 /* The engine (TDE_PATH_MFMA, _POPC or _NTT) that TDE_PATH_AUTO takes for this
  * correlation, or TDE_ERR_ARG. */
 int tde_tune_query(int64_t nu, int64_t nv, int kmax_u, int kmax_v, int64_t lag_lo, int64_t lag_hi);
-/* Text file: a line "tde-tune 1", then lines "code_class lag_class log2n
- * engine". Save fails with TDE_ERR_ARG when no table is installed; load
- * replaces the table (TDE_ERR_IO for an unreadable or malformed file, which
- * leaves the table unchanged); reset returns to the cost model. */
+/* Text file: a line "tde-tune 2", then lines "code_class lag_class log2n
+ * engine tile_blocks" (tile_blocks 4, 8, or 0 for the rule); files of
+ * version 1 (no tile column) still load. Save fails with TDE_ERR_ARG when no
+ * table is installed; load replaces the table (TDE_ERR_IO for an unreadable
+ * or malformed file, which leaves the table unchanged); reset returns to the
+ * cost model and the tile rule. */
 int tde_tune_save(const char* path);
 int tde_tune_load(const char* path);
 int tde_tune_reset(void);

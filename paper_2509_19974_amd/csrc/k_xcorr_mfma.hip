@@ -861,14 +861,9 @@ static int64_t seg_cap(const XItem& it) {
     return 4 * per_wave;
 }
 
-// FP4 for codes up to 3, FP6 up to 7 (both exact); TDE_MFMA_FP=0 in the
-// environment keeps int8 everywhere.
+// FP4 for codes up to 3, FP6 up to 7 (both exact), int8 beyond.
 int mfma_choose_fmt(int kmax, bool allow_fp) {
-    static const bool fp_on = [] {
-        const char* e = getenv("TDE_MFMA_FP");
-        return !(e && atoi(e) == 0);
-    }();
-    if (!allow_fp || !fp_on || kmax < 1) return kFmtI8;
+    if (!allow_fp || kmax < 1) return kFmtI8;
     if (kmax <= 3) return kFmtF4;
     if (kmax <= 7) return kFmtF6;
     return kFmtI8;
@@ -880,29 +875,21 @@ static int64_t tiled_lags(int64_t lo, int64_t hi, int64_t tlw) {
     return ceil_div(L, tlw) * tlw;
 }
 
-// int8 items keep 4 accumulator blocks (4096-lag tiles): 8 blocks need more
-// registers than two waves per SIMD allow, and the separate 8-block launch
-// (TDE_MFMA_MB=8 in the environment) runs one wave per SIMD.
+// int8 items: 4 accumulator blocks (4096-lag tiles) unless the tuning table
+// picked 8 for the pair's bucket (the separate 8-block launch, one wave per
+// SIMD).
 int choose_mb(const XPair& p) {
-    static const int forced = [] {
-        const char* e = getenv("TDE_MFMA_MB");
-        return e ? atoi(e) : 0;
-    }();
-    (void)p;
-    return forced == 8 ? 8 : 4;
+    return tuned_tile_blocks(p.nu, p.nv, p.kuv, p.lag_lo, p.lag_hi) == 8 ? 8 : 4;
 }
 
-// FP tiles: 8 blocks (8192 lags) unless that computes more than 1/8 more
-// lags than 4-block tiles would, or the shorter signal has fewer than 32768
-// samples: then each wave's share of a tile is a few chunks, fixed per-item
-// costs dominate, and twice as many 4-block items spread over more
-// workgroups. TDE_MFMA_FPNB=4 or 8 in the environment forces one.
+// FP tiles: the tuning table's choice for the pair's bucket; without one,
+// 8 blocks (8192 lags) unless that computes more than 1/8 more lags than
+// 4-block tiles would, or the shorter signal has fewer than 32768 samples:
+// then each wave's share of a tile is a few chunks, fixed per-item costs
+// dominate, and twice as many 4-block items spread over more workgroups.
 static int choose_fp_nb(const XPair& p) {
-    static const int forced = [] {
-        const char* e = getenv("TDE_MFMA_FPNB");
-        return e ? atoi(e) : 0;
-    }();
-    if (forced == 4 || forced == 8) return forced;
+    const int tuned = tuned_tile_blocks(p.nu, p.nv, p.kuv, p.lag_lo, p.lag_hi);
+    if (tuned == 4 || tuned == 8) return tuned;
     if ((p.nu < p.nv ? p.nu : p.nv) < 32768) return 4;
     int64_t lo, hi;
     clamp_support(p, lo, hi);

@@ -541,6 +541,22 @@ int xcorr_run(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, int64_
 
 extern "C" {
 
+int tde_mfma_tile_lags(int64_t nu, int64_t nv, int kmax_u, int kmax_v, int64_t lag_lo, int64_t lag_hi, int path) {
+    if (nu < 1 || nv < 1 || lag_lo > lag_hi || kmax_u < 1 || kmax_u > 127 || kmax_v < 1 || kmax_v > 127)
+        return set_error(TDE_ERR_ARG, "tde_mfma_tile_lags: invalid request");
+    if (path != TDE_PATH_AUTO && path != TDE_PATH_MFMA && path != TDE_PATH_MFMA_I8)
+        return set_error(TDE_ERR_ARG, "tde_mfma_tile_lags: path %d is not a matrix-core path", path);
+    XItem it{};
+    it.p.nu = nu;
+    it.p.nv = nv;
+    it.p.lag_lo = lag_lo;
+    it.p.lag_hi = lag_hi;
+    it.p.kuv = kmax_u * kmax_v;
+    it.p.kmax = kmax_u > kmax_v ? kmax_u : kmax_v;
+    mfma_plan_pair(it, path != TDE_PATH_MFMA_I8);
+    return 1024 * it.mb;
+}
+
 int tde_xcorr_int(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, int64_t nv, int kmax_u, int kmax_v,
                   int64_t lag_lo, int64_t lag_hi, void* r, int r_dtype, int path, void* ws, size_t ws_bytes,
                   void* stream) {

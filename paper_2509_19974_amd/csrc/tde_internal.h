@@ -407,6 +407,10 @@ int ctx_device(const tde_ctx* ctx);
 int ctx_num_cu(const tde_ctx* ctx);
 // Engine for TDE_PATH_AUTO (tuning table, else the built-in cost model).
 int auto_engine(int64_t nu, int64_t nv, int kuv, int kmax, int64_t lag_lo, int64_t lag_hi);
+// Accumulator blocks per matrix-core tile (4 or 8) for a correlation's
+// bucket: the tuner's forced value while it measures, else the tuning
+// table's entry, else 0 (the built-in rule decides).
+int tuned_tile_blocks(int64_t nu, int64_t nv, int kuv, int64_t lag_lo, int64_t lag_hi);
 
 // ----------------------------------------------------------------- NTT --
 // Number-theoretic-transform engine (two primes + CRT), for long signals.

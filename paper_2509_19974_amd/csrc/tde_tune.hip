@@ -1,11 +1,15 @@
-// Engine selection for TDE_PATH_AUTO: a tuning table measured on the device
-// (tde_tune), saved and loaded as text, with a cost model as the default.
+// Engine and tile selection for TDE_PATH_AUTO: a tuning table measured on the
+// device (tde_tune), saved and loaded as text, with a cost model and a tile
+// rule as the default.
 //
 // Buckets: m = round(log2(max(nu, nv))) clamped to [10, 23]; lag class by the
 // fraction of the full linear range requested (narrow <= 1/16, part <= 1/2,
 // full above); code class by Ku Kv (ternary = 1, small <= 49, large). Each
-// bucket holds the engine that ran fastest on codes of that class, and the
-// choice is only taken where that engine applies to the request.
+// bucket holds the engine that ran fastest on codes of that class, and for
+// the matrix-core engine its tile width (4 or 8 accumulator blocks: 4096 or
+// 8192 lags per tile); the engine is only taken where it applies to the
+// request, and the tile width applies to any matrix-core correlation of the
+// bucket (also one forced by the caller's path).
 #include <stdio.h>
 #include <string.h>
 
@@ -26,10 +30,13 @@ constexpr int kNB = kMaxLog - kMinLog + 1;
 struct Table {
     bool valid = false;
     int eng[3][3][kNB] = {};   // [code class][lag class][size bucket], 0 = unset
+    int tb[3][3][kNB] = {};    // matrix-core tile blocks (4 or 8), 0 = the rule
 };
 
 std::mutex g_mu;
 Table g_tab;
+// while tde_tune measures a tile width (its own thread only)
+thread_local int t_force_tb = 0;
 
 int size_bucket(int64_t nu, int64_t nv) {
     const double m = std::log2((double)std::max(nu, nv));
@@ -99,6 +106,13 @@ uint32_t lcg(uint64_t& s) {
 
 }  // namespace
 
+int tuned_tile_blocks(int64_t nu, int64_t nv, int kuv, int64_t lag_lo, int64_t lag_hi) {
+    if (t_force_tb) return t_force_tb;
+    std::lock_guard<std::mutex> lock(g_mu);
+    if (!g_tab.valid) return 0;
+    return g_tab.tb[code_class(kuv)][lag_class(nu, nv, lag_lo, lag_hi)][size_bucket(nu, nv)];
+}
+
 int auto_engine(int64_t nu, int64_t nv, int kuv, int kmax, int64_t lag_lo, int64_t lag_hi) {
     {
         std::lock_guard<std::mutex> lock(g_mu);
@@ -138,11 +152,12 @@ int tde_tune_save(const char* path) {
     if (!t.valid) return set_error(TDE_ERR_ARG, "tde_tune_save: no tuning table installed");
     FILE* f = fopen(path, "w");
     if (!f) return set_error(TDE_ERR_IO, "tde_tune_save: cannot open %s", path);
-    fprintf(f, "tde-tune 1\n");
+    fprintf(f, "tde-tune 2\n");
     for (int c = 0; c < 3; ++c)
         for (int l = 0; l < 3; ++l)
             for (int b = 0; b < kNB; ++b)
-                if (t.eng[c][l][b]) fprintf(f, "%d %d %d %d\n", c, l, b + kMinLog, t.eng[c][l][b]);
+                if (t.eng[c][l][b])
+                    fprintf(f, "%d %d %d %d %d\n", c, l, b + kMinLog, t.eng[c][l][b], t.tb[c][l][b]);
     const bool ok = fclose(f) == 0;
     return ok ? TDE_OK : set_error(TDE_ERR_IO, "tde_tune_save: write to %s failed", path);
 }
@@ -154,19 +169,23 @@ int tde_tune_load(const char* path) {
     Table t;
     char head[32] = {0};
     int ver = 0;
-    if (fscanf(f, "%31s %d", head, &ver) != 2 || strcmp(head, "tde-tune") != 0 || ver != 1) {
+    if (fscanf(f, "%31s %d", head, &ver) != 2 || strcmp(head, "tde-tune") != 0 || (ver != 1 && ver != 2)) {
         fclose(f);
         return set_error(TDE_ERR_IO, "tde_tune_load: %s is not a tuning file", path);
     }
-    int c, l, m, e, n = 0;
+    // version 1 lines: code lag log2n engine; version 2 adds the tile blocks
+    const int fields = ver == 1 ? 4 : 5;
+    int c, l, m, e, tb = 0, n = 0;
     int got;
-    while ((got = fscanf(f, "%d %d %d %d", &c, &l, &m, &e)) == 4) {
+    while ((got = ver == 1 ? fscanf(f, "%d %d %d %d", &c, &l, &m, &e)
+                           : fscanf(f, "%d %d %d %d %d", &c, &l, &m, &e, &tb)) == fields) {
         if (c < 0 || c > 2 || l < 0 || l > 2 || m < kMinLog || m > kMaxLog || e < TDE_PATH_MFMA ||
-            e > TDE_PATH_NTT) {
+            e > TDE_PATH_NTT || (tb != 0 && tb != 4 && tb != 8)) {
             fclose(f);
-            return set_error(TDE_ERR_IO, "tde_tune_load: bad entry %d %d %d %d in %s", c, l, m, e, path);
+            return set_error(TDE_ERR_IO, "tde_tune_load: bad entry %d %d %d %d %d in %s", c, l, m, e, tb, path);
         }
         t.eng[c][l][m - kMinLog] = e;
+        t.tb[c][l][m - kMinLog] = tb;
         ++n;
     }
     const bool clean_end = got == EOF;
@@ -286,31 +305,60 @@ int tde_tune(tde_ctx* ctx, int max_log_n, void* stream) {
             const int64_t N = (int64_t)1 << m;
             for (int l = 0; l < 3; ++l) {
                 const int64_t half = l == 0 ? std::max<int64_t>(16, N / 64) : (l == 1 ? N / 4 : N - 1);
-                // enough pairs for about 2^36 multiply-adds (a full chip for
-                // milliseconds), at most kTunePairs
+                // enough pairs for about 2^38 multiply-adds (0.1 - 0.3 ms of
+                // the matrix cores) and at least 2048 matrix-core work items
+                // (8 per CU), so that the timing reflects a full device
+                // rather than a few long items; at most kTunePairs
                 const double macs = overlap_sum(N, N, -half, half);
-                const int P = (int)std::clamp(std::ceil(68719476736.0 / std::max(macs, 1.0)), 1.0,
-                                              (double)kTunePairs);
-                double best = 1e30;
-                int best_e = 0;
-                for (int e = TDE_PATH_MFMA; e <= TDE_PATH_NTT; ++e) {
+                XItem probe{};
+                probe.p.nu = N;
+                probe.p.nv = N;
+                probe.p.lag_lo = -half;
+                probe.p.lag_hi = half;
+                probe.p.kuv = K * K;
+                probe.p.kmax = K;
+                t_force_tb = 4;
+                mfma_plan_pair(probe, true);
+                t_force_tb = 0;
+                const double items = (double)std::max<int64_t>(1, mfma_count_items(probe));
+                const double want = std::max(274877906944.0 / std::max(macs, 1.0), 2048.0 / items);
+                const int P = (int)std::clamp(std::ceil(want), 1.0, (double)kTunePairs);
+                double best = 1e30, best_mfma = 1e30;
+                int best_e = 0, best_tb = 0;
+                // the matrix-core engine at both tile widths (int8 codes at 8
+                // blocks take a launch of their own, one wave per SIMD), then
+                // the other engines
+                const int trials[4][2] = {{TDE_PATH_MFMA, 4}, {TDE_PATH_MFMA, 8}, {TDE_PATH_POPC, 0},
+                                          {TDE_PATH_NTT, 0}};
+                for (const auto& tr : trials) {
+                    const int e = tr[0];
                     if (!applicable(e, N, N, K * K, -half, half)) continue;
                     double sec = 0.0;
+                    t_force_tb = tr[1];
                     const int st = time_engine(ctx, B, N, bits, half, P, e, s, &sec);
+                    t_force_tb = 0;
                     if (st != TDE_OK) return st;
+                    if (e == TDE_PATH_MFMA && sec < best_mfma) {
+                        best_mfma = sec;
+                        best_tb = tr[1];
+                    }
                     if (sec < best) {
                         best = sec;
                         best_e = e;
                     }
                 }
                 t.eng[c][l][m - kMinLog] = best_e;
+                t.tb[c][l][m - kMinLog] = best_tb;
             }
         }
     }
     // sizes beyond the measured range take the largest measured bucket
     for (int c = 0; c < 3; ++c)
         for (int l = 0; l < 3; ++l)
-            for (int m = max_log_n + 1; m <= kMaxLog; ++m) t.eng[c][l][m - kMinLog] = t.eng[c][l][max_log_n - kMinLog];
+            for (int m = max_log_n + 1; m <= kMaxLog; ++m) {
+                t.eng[c][l][m - kMinLog] = t.eng[c][l][max_log_n - kMinLog];
+                t.tb[c][l][m - kMinLog] = t.tb[c][l][max_log_n - kMinLog];
+            }
     t.valid = true;
     std::lock_guard<std::mutex> lock(g_mu);
     g_tab = t;

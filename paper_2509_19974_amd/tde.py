@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH):
         "tde_quantizer_thresholds": (i32, [i32, i32, vp]),
         "tde_xcorr_workspace_size": (sz, [i64, i64, i32, i32, i64, i64, i32]),
         "tde_mfma_operand_bits": (i32, [i32, i32, i32]),
+        "tde_mfma_tile_lags": (i32, [i64, i64, i32, i32, i64, i64, i32]),
         "tde_xcorr_int": (i32, [vp, vp, i64, vp, i64, i32, i32, i64, i64, vp, i32, i32, vp, sz, vp]),
         "tde_xcorr_int_noalloc": (i32, [vp, vp, i64, vp, i64, i32, i32, i64, i64, vp, i32, i32, vp]),
         "tde_argmax_workspace_size": (sz, [i64]),
@@ -198,6 +199,14 @@ def tde_quantizer_thresholds(quantizer: int, bits: int) -> np.ndarray:
 
 def tde_xcorr_workspace_size(nu, nv, kmax_u, kmax_v, lag_lo, lag_hi, path=TDE_PATH_AUTO) -> int:
     return int(load_library().tde_xcorr_workspace_size(nu, nv, kmax_u, kmax_v, lag_lo, lag_hi, path))
+
+
+def tde_mfma_tile_lags(nu, nv, kmax_u, kmax_v, lag_lo, lag_hi, path=TDE_PATH_AUTO) -> int:
+    """Lags per matrix-core tile (4096 or 8192) for this correlation."""
+    st = load_library().tde_mfma_tile_lags(nu, nv, kmax_u, kmax_v, lag_lo, lag_hi, path)
+    if st < 0:
+        _check(st)
+    return int(st)
 
 
 def tde_mfma_operand_bits(kmax_u, kmax_v, path=TDE_PATH_MFMA) -> int:

@@ -288,10 +288,27 @@ def test_auto_engine_cost_model_and_tuning_file(tmp_path):
     assert tde.tde_tune_query(n16, n16, 127, 127, -100, 100) == tde.TDE_PATH_MFMA
     g = tmp_path / "back.txt"
     tde.tde_tune_save(str(g))
-    assert g.read_text().split("\n")[0] == "tde-tune 1"
-    assert sorted(g.read_text().split("\n")[1:-1]) == sorted(["0 2 16 2", "2 2 16 3", "2 0 16 2"])
+    assert g.read_text().split("\n")[0] == "tde-tune 2"
+    assert sorted(g.read_text().split("\n")[1:-1]) == sorted(["0 2 16 2 0", "2 2 16 3 0", "2 0 16 2 0"])
+    # version 2: tile widths per bucket; 0 keeps the rule (8192-lag FP tiles
+    # for a wide range of long signals, 4096 for int8 codes)
+    n17 = 1 << 17
+    assert tde.tde_mfma_tile_lags(n17, n17, 7, 7, -(n17 - 1), n17 - 1) == 8192
+    assert tde.tde_mfma_tile_lags(n17, n17, 127, 127, -(n17 - 1), n17 - 1) == 4096
+    f.write_text("tde-tune 2\n1 2 17 1 4\n2 2 17 1 8\n1 0 17 1 0\n")
+    tde.tde_tune_load(str(f))
+    assert tde.tde_mfma_tile_lags(n17, n17, 7, 7, -(n17 - 1), n17 - 1) == 4096
+    assert tde.tde_mfma_tile_lags(n17, n17, 127, 127, -(n17 - 1), n17 - 1) == 8192
+    assert tde.tde_mfma_tile_lags(n17, n17, 127, 127, -(n17 - 1), n17 - 1, tde.TDE_PATH_MFMA_I8) == 8192
+    tde.tde_tune_save(str(g))
+    assert sorted(g.read_text().split("\n")[1:-1]) == sorted(["1 2 17 1 4", "2 2 17 1 8", "1 0 17 1 0"])
+    with pytest.raises(tde.TDEError):
+        tde.tde_mfma_tile_lags(n17, n17, 7, 7, 0, 0, tde.TDE_PATH_NTT)
+    f.write_text("tde-tune 1\n0 2 16 2\n2 2 16 3\n2 0 16 2\n")
+    tde.tde_tune_load(str(f))
     bad = tmp_path / "bad.txt"
-    for text in ("nope 1\n", "tde-tune 1\n0 2 16 9\n", "tde-tune 1\n0 2 16 2 x\n", "tde-tune 1\n5 0 12 1\n"):
+    for text in ("nope 1\n", "tde-tune 1\n0 2 16 9\n", "tde-tune 1\n0 2 16 2 x\n", "tde-tune 1\n5 0 12 1\n",
+                 "tde-tune 2\n0 2 16 2 6\n", "tde-tune 3\n0 2 16 2 4\n"):
         bad.write_text(text)
         with pytest.raises(tde.TDEError) as e:
             tde.tde_tune_load(str(bad))

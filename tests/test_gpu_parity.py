@@ -723,13 +723,18 @@ def test_tune_on_device_and_auto_batch(T, ctx, tmp_path):
     f = str(tmp_path / "tune.txt")
     tde.tde_tune_save(f)
     lines = open(f).read().split("\n")
-    assert lines[0] == "tde-tune 1" and len(lines) > 3 * 3 * 7
+    assert lines[0] == "tde-tune 2" and len(lines) > 3 * 3 * 7
+    assert all(int(l.split()[4]) in (4, 8) for l in lines[1:] if l and l.split()[3] == "1")
     n16 = 1 << 16
-    before = [tde.tde_tune_query(n, n, k, k, -(n // 4), n // 4) for n in (1000, 5000, n16) for k in (1, 7, 127)]
+    probe = [(n, k) for n in (1000, 5000, n16) for k in (1, 7, 127)]
+    before = [(tde.tde_tune_query(n, n, k, k, -(n // 4), n // 4),
+               tde.tde_mfma_tile_lags(n, n, k, k, -(n // 4), n // 4)) for n, k in probe]
     tde.tde_tune_reset()
     tde.tde_tune_load(f)
-    after = [tde.tde_tune_query(n, n, k, k, -(n // 4), n // 4) for n in (1000, 5000, n16) for k in (1, 7, 127)]
+    after = [(tde.tde_tune_query(n, n, k, k, -(n // 4), n // 4),
+              tde.tde_mfma_tile_lags(n, n, k, k, -(n // 4), n // 4)) for n, k in probe]
     assert before == after
+    say(f"  tuned (engine, tile lags): {after}")
     pairs = synth.config4_uneven(npairs=32, nmin_log2=10, nmax_log2=15, salt=3)
     pk, specs = _batch(T, ctx, pairs, tde.TDE_PATH_AUTO, want_r=True)
     for i, p in enumerate(pairs):
