@@ -4,8 +4,8 @@
 // quantizer on [-3 sigma, 3 sigma] fixes no summation order); the scale is
 // sigma = sqrt(fl64(S) / n), inv_step = fl32((2K+1) / (6 sigma)) with fl64(S)
 // the exact S rounded once. The kernels add the squares (each exact in
-// float64) in float64 over a binary tree: pairs inside a lane, wave
-// shuffles, then LDS across waves and blocks. That sum S' satisfies
+// float64) in float64 over a binary tree: pairs inside a lane, then across
+// the wave that holds a 1024-sample node, then across nodes. That sum S' satisfies
 // |S' - S| <= 2^-45 S (exact_sum.h), and inv_step is a non-increasing
 // function of S (every operation is correctly rounded and monotone), so
 // when the ends of [S'(1 - 2^-45), S'(1 + 2^-45)] give the same inv_step,
@@ -20,8 +20,14 @@
 // strictly below |z|: mu-law companding (mu = 255) on [-3 sigma, 3 sigma], or
 // the Lloyd-Max quantizer of a unit Gaussian with 2K+1 levels, for b in {2, 4}.
 //
-// The three kernels are HBM-bound: 4 bytes of x are read once for the scale
-// and once for the codes, 1 byte of q is written.
+// The kernels are HBM-bound: 4 bytes of x are read once for the scale and
+// once for the codes; 1 byte of q, or the packed FP codes (4 or 6 bits) and
+// the decimated input, are written. Whole blocks take a path without
+// per-sample bounds checks. Keeping a block's samples on chip between the
+// scale and the codes (one read) needs every block of a signal to wait for
+// the signal's sum; a persistent one-pass kernel built that way measured
+// slower than the two passes (the waits put several memory round trips on
+// each workgroup's path, and its stash allows 3 to 4 workgroups per CU).
 #include <algorithm>
 #include <cmath>
 
@@ -73,12 +79,108 @@ __device__ __forceinline__ double sq_or_zero(float f) {
     return __builtin_isfinite(a) ? a * a : 0.0;
 }
 
+// Global-memory views of the descriptors' pointers: global loads and stores
+// wait on the vector counter alone, where generic (flat) accesses also hold up
+// every wait for the descriptors' scalar loads.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
+// A workgroup barrier that orders LDS accesses only: it waits for the wave's
+// LDS operations, not for its outstanding global loads and stores, which
+// __syncthreads() would also drain.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// 16 bytes of global memory (p 16-byte aligned) as a float4.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 gload4(const float* p) {
+    const f32x4_t v = *gmem(reinterpret_cast<const f32x4_t*>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+// The samples of block lb held by this thread: base + 1024 w + 256 k + 4 l + e
+// for wave w, lane l and k, e < 4. Wave w holds node w of the block (1024
+// samples) and each of its loads reads 1 KiB of consecutive samples; lanes
+// 4j .. 4j+3 hold 16 consecutive samples.
+__device__ __forceinline__ int64_t sample_of(int64_t lb, int k) {
+    return lb * kQuantBlock + 1024 * (int64_t)(threadIdx.x >> 6) + 256 * k + 4 * (int64_t)(threadIdx.x & 63);
+}
+
+// This thread's 16 samples of block lb (sample_of), zero beyond n.
+__device__ __forceinline__ void load_block(const QSig& s, int64_t lb, float4 (&xv)[4]) {
+    if (lb * kQuantBlock + kQuantBlock <= s.n && ((((uintptr_t)s.x) & 15) == 0)) {
+        // a whole aligned block (the workgroup's branch): four plain loads
+#pragma unroll
+        for (int k = 0; k < 4; ++k) xv[k] = gload4(s.x + sample_of(lb, k));
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t m = sample_of(lb, k);
+        if (m + 4 <= s.n && ((((uintptr_t)(s.x + m)) & 15) == 0)) {
+            xv[k] = gload4(s.x + m);
+        } else {
+            float t4[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) t4[e] = (m + e < s.n) ? *gmem(s.x + m + e) : 0.f;
+            xv[k] = make_float4(t4[0], t4[1], t4[2], t4[3]);
+        }
+    }
+}
+
+// Lane exchanges inside rows of 16 lanes (DPP), for 32- and 64-bit values.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __builtin_bit_cast(float, dpp_u32<CTRL>(__builtin_bit_cast(uint32_t, v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = dpp_u32<CTRL>((uint32_t)b), hi = dpp_u32<CTRL>((uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, (hi << 32) | lo);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]: lane l ^ 1
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]: lane l ^ 2
+constexpr int kDppNext = 0xF9;        // quad_perm [1,2,3,3]: lane l + 1 inside a quad
+constexpr int kDppHalfMirror = 0x141; // lane 7 - i inside each 8 lanes
+constexpr int kDppMirror = 0x140;     // lane 15 - i inside each 16 lanes
+
+// The node sum of this wave's 1024 samples (load_block) in every lane: the
+// squares (exact in float64) added pairwise inside the lane, then across
+// quads, 8- and 16-lane groups (DPP) and the wave's 16- and 32-lane halves.
+// Every level adds two equal-sized disjoint groups, so the whole is a binary
+// tree of height 10 (a partner's sum is the same in both lanes: addition
+// commutes).
+__device__ __forceinline__ double wave_node_sum(const float4 (&xv)[4]) {
+    double p[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        p[k] = (sq_or_zero(xv[k].x) + sq_or_zero(xv[k].y)) + (sq_or_zero(xv[k].z) + sq_or_zero(xv[k].w));
+    double a = (p[0] + p[1]) + (p[2] + p[3]);
+    a = a + dpp_f64<kDppXor1>(a);
+    a = a + dpp_f64<kDppXor2>(a);
+    a = a + dpp_f64<kDppHalfMirror>(a);
+    a = a + dpp_f64<kDppMirror>(a);
+    a = a + __shfl_xor(a, 16, 64);
+    a = a + __shfl_xor(a, 32, 64);
+    return a;
+}
+
 // One block per 4096 samples of a signal: four level-10 nodes of the tree
-// (1024 samples each), thread t holding samples 1024 k + 4t .. 4t+3 of node k.
+// (1024 samples each), wave w summing node w.
 // With the scale fused into the quantize kernel, this kernel also zeroes the
 // statistics that kernel accumulates (first block of each signal) and the
 // scratch counters of a later kernel (first block).
-__global__ void __launch_bounds__(256) k_sumsq_blocks(const QSig* sigs, int nsig, QSig one, int bps, int fused,
+__global__ void __launch_bounds__(256) k_sumsq_blocks(const QSig* __restrict__ sigs, int nsig, QSig one, int bps, int fused,
                                                       int* zero_me, int nzero) {
     const int64_t blk = blockIdx.x;
     int64_t lb;
@@ -94,36 +196,12 @@ __global__ void __launch_bounds__(256) k_sumsq_blocks(const QSig* sigs, int nsig
         }
     }
     if (s.inv_fixed > 0.f || s.bits == 1) return;
-    const int64_t base = lb * kQuantBlock;
     float4 xv[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int64_t m = base + 1024 * k + 4 * (int64_t)threadIdx.x;
-        if (m + 4 <= s.n && ((((uintptr_t)(s.x + m)) & 15) == 0)) {
-            xv[k] = *reinterpret_cast<const float4*>(s.x + m);
-        } else {
-            float t4[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) t4[e] = (m + e < s.n) ? s.x[m + e] : 0.f;
-            xv[k] = make_float4(t4[0], t4[1], t4[2], t4[3]);
-        }
-    }
-    __shared__ double ws[4][4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        double a = (sq_or_zero(xv[k].x) + sq_or_zero(xv[k].y)) + (sq_or_zero(xv[k].z) + sq_or_zero(xv[k].w));
-#pragma unroll
-        for (int h = 1; h < 64; h <<= 1) {
-            double o = __shfl_xor(a, h, 64);
-            a = a + o;     // lanes l and l^h hold the two children; the sum is the same in both
-        }
-        if ((threadIdx.x & 63) == 0) ws[k][threadIdx.x >> 6] = a;
-    }
-    __syncthreads();
-    if (threadIdx.x < 4) {
-        const int k = threadIdx.x;
-        const int64_t node = lb * 4 + k;
-        if (node * kSumBlock < s.n) s.gsum[node] = (ws[k][0] + ws[k][1]) + (ws[k][2] + ws[k][3]);
+    load_block(s, lb, xv);
+    const double a = wave_node_sum(xv);
+    if ((threadIdx.x & 63) == 0) {
+        const int64_t node = lb * 4 + (threadIdx.x >> 6);
+        if (node * kSumBlock < s.n) s.gsum[node] = a;
     }
 }
 
@@ -156,11 +234,11 @@ __device__ __forceinline__ bool scale_decided(double St, int64_t n, int bits, fl
 // Each square is split into base-2^32 digits (exact_sum.h) that are added
 // to one LDS row of limbs with 64-bit atomics; a limb receives at most one
 // digit (< 2^32) per sample, so it stays below 2^64.
-__device__ double exact_sumsq_wg(const float* x, int64_t n) {
+__device__ __attribute__((noinline)) double exact_sumsq_wg(const float* x, int64_t n) {
     __shared__ unsigned long long acc[kExactLimbs];
     __shared__ double res;
     for (int i = threadIdx.x; i < kExactLimbs; i += blockDim.x) acc[i] = 0ull;
-    __syncthreads();
+    lds_barrier();
     for (int64_t m = threadIdx.x; m < n; m += blockDim.x) {
         const float f = x[m];
         if (!__builtin_isfinite(f) || f == 0.f) continue;
@@ -171,7 +249,7 @@ __device__ double exact_sumsq_wg(const float* x, int64_t n) {
         if (d1) atomicAdd(&acc[li + 1], (unsigned long long)d1);
         if (d2) atomicAdd(&acc[li + 2], (unsigned long long)d2);
     }
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x == 0) {
         // unsigned carries first (a limb may exceed 2^63), then the digits
         int64_t v[kExactLimbs];
@@ -183,7 +261,7 @@ __device__ double exact_sumsq_wg(const float* x, int64_t n) {
         }
         res = exact_to_double(v);
     }
-    __syncthreads();
+    lds_barrier();
     return res;
 }
 
@@ -207,7 +285,7 @@ __device__ __forceinline__ double wave_tree_sum(const double* gsum, int64_t n) {
 
 // One block per signal: remaining levels of the sum tree, then the scale.
 // Also zeroes the statistics that the quantize kernel accumulates.
-__global__ void __launch_bounds__(256) k_scale_finalize(const QSig* sigs, int nsig, QSig one, int* zero_me,
+__global__ void __launch_bounds__(256) k_scale_finalize(const QSig* __restrict__ sigs, int nsig, QSig one, int* zero_me,
                                                         int nzero) {
     (void)nsig;                      // the grid has one workgroup per signal
     const QSig& s = sigs ? sigs[blockIdx.x] : one;
@@ -309,73 +387,43 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-// 256 threads x 16 samples per block; one set of statistic atomics per block.
-// fused != 0: every block takes its signal's scale from the block sums itself
-// (signals of 1 .. kFuseMaxN samples), and the first block of each signal
-// publishes it.
-__global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QSig one, int bps, int fused) {
-    const int64_t blk = blockIdx.x;
-    int64_t lb;
-    // a copy: the stores below could alias the descriptor array, which
-    // would make the compiler reload its fields after every store
-    const QSig s = pick_sig(sigs, nsig, one, bps, blk, lb);
-    float inv;
-    int exact = 0;
-    if (s.bits == 1) {
-        inv = 0.f;
-    } else if (s.inv_fixed > 0.f) {
-        inv = s.inv_fixed;
-    } else if (fused) {
-        // every block of the signal decides alike (same tree, same bound)
-        if (!scale_decided(wave_tree_sum(s.gsum, s.n), s.n, s.bits, inv)) {
-            inv = scale_of_sum(exact_sumsq_wg(s.x, s.n), s.n, s.bits);
-            exact = TDE_FLAG_SCALE_EXACT;
-        }
-    } else {
-        inv = *s.inv_out;
+// Packed FP4/FP6 codes of one k: lanes 4j .. 4j+3 hold the 16 samples of one
+// unit (4 each); a lane joins its bits with its right neighbour's to form
+// the unit's dwords. m: the lane's first sample.
+__device__ __forceinline__ void store_packed(const QSig& s, int64_t m, uint32_t w) {
+    const int W = __builtin_amdgcn_readfirstlane(s.pk_bits);     // uniform
+    const uint32_t z = W == 6 ? fp_bits4<6>(fp_bytes<6>(w)) : fp_bits4<4>(fp_bytes<4>(w));
+    const uint32_t nb = dpp_u32<kDppNext>(z);
+    const int j = threadIdx.x & 3;
+    const int64_t unit = (m - 4 * j) / 16;
+    if (16 * unit >= s.n) return;
+    if (W == 6) {
+        if (j == 0) *gmem(s.pk + 3 * unit) = z | (nb << 24);
+        else if (j == 1) *gmem(s.pk + 3 * unit + 1) = (z >> 8) | (nb << 16);
+        else if (j == 2) *gmem(s.pk + 3 * unit + 2) = (z >> 16) | (nb << 8);
+    } else if (j == 0 || j == 2) {
+        *gmem(s.pk + 2 * unit + (j >> 1)) = z | (nb << 16);
     }
-    if (fused && lb == 0 && threadIdx.x == 0) {
-        if (s.inv_out) *s.inv_out = inv;
-        if (s.stat) {
-            s.stat->inv_step = inv;
-            s.stat->flags = exact;
-        }
-    }
-    const int K = s.bits == 1 ? 1 : (1 << (s.bits - 1)) - 1;
-    const int64_t base = lb * kQuantBlock;
+}
+
+// Decimated input of one k: the mean of 16 samples = 4 neighbouring lanes,
+// summed ((x0+x1)+(x2+x3)) per lane, then lanes l^1, l^2 (the order of the
+// stand-alone decimation kernel), times the scale.
+__device__ __forceinline__ void store_dec(const QSig& s, int64_t m, const float4& x, float scale) {
+    float a = (x.x + x.y) + (x.z + x.w);
+    a += dpp_f32<kDppXor1>(a);
+    a += dpp_f32<kDppXor2>(a);
+    if ((threadIdx.x & 3) == 0 && m + 16 <= s.n) *gmem(s.dec + (m >> 4)) = f2bf_rne(a * (1.f / 16.f) * scale);
+}
+
+// quant_block for any block: every sample checked against n, any map.
+__device__ __forceinline__ void quant_block_checked(const QSig& s, int64_t lb, const float4 (&xv)[4], float inv,
+                                                    int K, long long& nonfinite_w, long long& nzero_w, int& sq,
+                                                    int& sq2) {
     int nonfinite = 0, nzero = 0;
-    int sq = 0, sq2 = 0;
-    // four coalesced passes: thread t takes samples base + 1024 k + 4t + e
-    float4 xv[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int64_t m = base + 1024 * k + 4 * (int64_t)threadIdx.x;
-        if (m + 4 <= s.n && ((((uintptr_t)(s.x + m)) & 15) == 0)) {
-            xv[k] = *reinterpret_cast<const float4*>(s.x + m);
-        } else {
-            float t4[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) t4[e] = (m + e < s.n) ? s.x[m + e] : 0.f;
-            xv[k] = make_float4(t4[0], t4[1], t4[2], t4[3]);
-        }
-    }
-    if (s.dec) {
-        // fused decimation: means of 16 samples = 4 neighbouring threads,
-        // summed ((x0+x1)+(x2+x3)) per thread, then lanes t^1, t^2 (the
-        // same order as the stand-alone decimation kernel)
-        const float scale = inv * s.dec_mul;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            float a = (xv[k].x + xv[k].y) + (xv[k].z + xv[k].w);
-            a += __shfl_xor(a, 1, 64);
-            a += __shfl_xor(a, 2, 64);
-            const int64_t m = base + 1024 * k + 4 * (int64_t)threadIdx.x;
-            if ((threadIdx.x & 3) == 0 && m + 16 <= s.n) s.dec[m >> 4] = f2bf_rne(a * (1.f / 16.f) * scale);
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int64_t m = base + 1024 * k + 4 * (int64_t)threadIdx.x;
+        const int64_t m = sample_of(lb, k);
         uint32_t w = 0u;
         if (m < s.n) {
             const float xs[4] = {xv[k].x, xv[k].y, xv[k].z, xv[k].w};
@@ -393,45 +441,92 @@ __global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QS
             }
             if (!s.skip_q) {
                 if (m + 4 <= s.n && ((((uintptr_t)(s.q + m)) & 3) == 0)) {
-                    *reinterpret_cast<uint32_t*>(s.q + m) = w;
+                    *gmem(reinterpret_cast<uint32_t*>(s.q + m)) = w;
                 } else {
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
-                        if (m + e < s.n) s.q[m + e] = (int8_t)(w >> (8 * e));
+                        if (m + e < s.n) *gmem(s.q + m + e) = (int8_t)(w >> (8 * e));
                 }
             }
         }
-        if (s.pk) {
-            // packed FP4/FP6 codes: lanes 4j .. 4j+3 hold the 16 samples of
-            // one unit (4 each); a lane joins its bits with its right
-            // neighbour's to form the unit's dwords
-            const int W = s.pk_bits;
-            const uint32_t z = W == 6 ? fp_bits4<6>(fp_bytes<6>(w)) : fp_bits4<4>(fp_bytes<4>(w));
-            const uint32_t nb = __shfl_down(z, 1, 64);
-            const int j = threadIdx.x & 3;
-            const int64_t unit = (m - 4 * j) / 16;
-            if (16 * unit < s.n) {
-                if (W == 6) {
-                    if (j == 0) s.pk[3 * unit] = z | (nb << 24);
-                    else if (j == 1) s.pk[3 * unit + 1] = (z >> 8) | (nb << 16);
-                    else if (j == 2) s.pk[3 * unit + 2] = (z >> 16) | (nb << 8);
-                } else if (j == 0 || j == 2) {
-                    s.pk[2 * unit + (j >> 1)] = z | (nb << 16);
+        if (s.pk) store_packed(s, m, w);
+    }
+    nonfinite_w = wave_sum<long long>(nonfinite);
+    nzero_w = wave_sum<long long>(nzero);
+}
+
+// Codes of block lb from its samples (load_block) under scale inv: the int8
+// codes, the packed FP codes and the decimated input where the descriptor asks
+// for them, and one set of statistic atomics. Every thread of the workgroup
+// calls it (a barrier inside when the signal has statistics).
+//
+// A whole block with the uniform map (or the sign map) takes a path without
+// per-sample bounds checks: its counts come from wave ballots. Other blocks
+// check every sample against n.
+__device__ __forceinline__ void quant_block(const QSig& s, int64_t lb, const float4 (&xv)[4], float inv) {
+    const int K = s.bits == 1 ? 1 : (1 << (s.bits - 1)) - 1;
+    const bool want_sums = s.stat && !s.stat_lite;
+    long long nonfinite_w, nzero_w;     // the wave's counts
+    int sq = 0, sq2 = 0;                // the lane's sums (want_sums)
+    if (s.dec) {
+        const float scale = inv * s.dec_mul;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) store_dec(s, sample_of(lb, k), xv[k], scale);
+    }
+    // the descriptor is uniform; reading its fields through the first lane
+    // makes the branches below scalar ones
+    const int bits = __builtin_amdgcn_readfirstlane(s.bits);
+    const bool whole = __builtin_amdgcn_readfirstlane(
+        lb * kQuantBlock + kQuantBlock <= s.n && s.nthr == 0 && (bits == 1 || inv > 0.f) &&
+        (s.skip_q || ((((uintptr_t)s.q) & 3) == 0)));
+    if (whole) {
+        const bool store_q = !__builtin_amdgcn_readfirstlane(s.skip_q);
+        const bool store_pk = __builtin_amdgcn_readfirstlane(s.pk != nullptr);
+        const float Kf = (float)K;
+        uint32_t nz = 0, nf = 0;        // wave counts (uniform)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t m = sample_of(lb, k);
+            const float xs[4] = {xv[k].x, xv[k].y, xv[k].z, xv[k].w};
+            int c[4];
+            if (bits == 1) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) c[e] = (xs[e] > 0.f) - (xs[e] < 0.f);   // 0 for +-0 and NaN
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float r = __builtin_amdgcn_fmed3f(__builtin_rintf(__fmul_rn(xs[e], inv)), -Kf, Kf);
+                    c[e] = xs[e] == xs[e] ? (int)r : 0;              // NaN -> 0, +-inf -> +-K
                 }
             }
+            uint32_t w = 0u;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                nf += (uint32_t)__builtin_popcountll(__ballot(!__builtin_isfinite(xs[e])));
+                nz += (uint32_t)__builtin_popcountll(__ballot(c[e] == 0));
+                if (want_sums) {
+                    sq += c[e];
+                    sq2 += c[e] * c[e];
+                }
+                w |= (uint32_t)(c[e] & 0xff) << (8 * e);
+            }
+            if (store_q) *gmem(reinterpret_cast<uint32_t*>(s.q + m)) = w;
+            if (store_pk) store_packed(s, m, w);
         }
+        nonfinite_w = nf;
+        nzero_w = nz;
+    } else {
+        quant_block_checked(s, lb, xv, inv, K, nonfinite_w, nzero_w, sq, sq2);
     }
     if (s.stat) {
         __shared__ long long red[4][4];
-        long long a = wave_sum<long long>(nonfinite);
-        long long z = wave_sum<long long>(nzero);
-        long long q1 = s.stat_lite ? 0 : wave_sum<long long>(sq);
-        long long q2 = s.stat_lite ? 0 : wave_sum<long long>(sq2);
+        long long q1 = want_sums ? wave_sum<long long>(sq) : 0;
+        long long q2 = want_sums ? wave_sum<long long>(sq2) : 0;
         const int wv = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
-            red[wv][0] = a; red[wv][1] = z; red[wv][2] = q1; red[wv][3] = q2;
+            red[wv][0] = nonfinite_w; red[wv][1] = nzero_w; red[wv][2] = q1; red[wv][3] = q2;
         }
-        __syncthreads();
+        lds_barrier();
         if (threadIdx.x < 4) {
             long long v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
             int64_t* dst = threadIdx.x == 0 ? &s.stat->n_nonfinite
@@ -440,6 +535,44 @@ __global__ void __launch_bounds__(256) k_quantize(const QSig* sigs, int nsig, QS
             if (v) atomicAdd((unsigned long long*)dst, (unsigned long long)v);
         }
     }
+}
+
+// 256 threads x 16 samples per block; one set of statistic atomics per block.
+// fused: every block takes its signal's scale from the block sums itself
+// (signals of 1 .. kFuseMaxN samples), and the first block of each signal
+// publishes it.
+template <bool fused>
+__global__ void __launch_bounds__(256) k_quantize(const QSig* __restrict__ sigs, int nsig, QSig one, int bps) {
+    const int64_t blk = blockIdx.x;
+    int64_t lb;
+    // a copy: the stores below could alias the descriptor array, which
+    // would make the compiler reload its fields after every store
+    const QSig s = pick_sig(sigs, nsig, one, bps, blk, lb);
+    float inv;
+    int exact = 0;
+    if (s.bits == 1) {
+        inv = 0.f;
+    } else if (s.inv_fixed > 0.f) {
+        inv = s.inv_fixed;
+    } else if constexpr (fused) {
+        // every block of the signal decides alike (same tree, same bound)
+        if (!scale_decided(wave_tree_sum(s.gsum, s.n), s.n, s.bits, inv)) {
+            inv = scale_of_sum(exact_sumsq_wg(s.x, s.n), s.n, s.bits);
+            exact = TDE_FLAG_SCALE_EXACT;
+        }
+    } else {
+        inv = *s.inv_out;
+    }
+    if (fused && lb == 0 && threadIdx.x == 0) {
+        if (s.inv_out) *s.inv_out = inv;
+        if (s.stat) {
+            s.stat->inv_step = inv;
+            s.stat->flags = exact;
+        }
+    }
+    float4 xv[4];
+    load_block(s, lb, xv);
+    quant_block(s, lb, xv, inv);
 }
 
 // tde_qstat::flags from the finished counts (one thread per signal).
@@ -527,7 +660,10 @@ int launch_quantize(const QSig* sigs_dev, const QSig& one, int nsig, int64_t tot
     if (!fused &&
         (need_scale || sigs_dev != nullptr || one.stat != nullptr || one.inv_out != nullptr || zero_me != nullptr))
         hipLaunchKernelGGL(k_scale_finalize, dim3(nsig), dim3(256), 0, s, sigs_dev, nsig, one, zero_me, nzero);
-    hipLaunchKernelGGL(k_quantize, dim3((unsigned)total_blocks), dim3(256), 0, s, sigs_dev, nsig, one, bps, fused);
+    if (fused)
+        hipLaunchKernelGGL(k_quantize<true>, dim3((unsigned)total_blocks), dim3(256), 0, s, sigs_dev, nsig, one, bps);
+    else
+        hipLaunchKernelGGL(k_quantize<false>, dim3((unsigned)total_blocks), dim3(256), 0, s, sigs_dev, nsig, one, bps);
     if (write_flags)
         hipLaunchKernelGGL(k_quantize_flags, dim3((unsigned)ceil_div(nsig, 256)), dim3(256), 0, s, sigs_dev, nsig,
                            one);
