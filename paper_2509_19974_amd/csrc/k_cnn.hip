@@ -110,15 +110,17 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kMPos = 512;                 // positions per workgroup
 constexpr int kMRow = 80;                  // LDS bytes per staged row (64 + pad)
 
-// frag[b][lane] (8 bf16): row o = lane % 32, kk = 16 b + 8 (lane / 32) + j
-__global__ void k_pack_wfrag(const float* W, uint4* frag) {
+// frag[b][lane] (8 bf16): row o = lane % 32, kk = 16 b + 8 (lane / 32) + j,
+// of scale * W (scale 1, or 1/2 for the fused inference kernel: halving a
+// bf16 weight is exact)
+__global__ void k_pack_wfrag(const float* W, uint4* frag, float scale) {
     const int b = blockIdx.x, lane = threadIdx.x;
     const int o = lane & 31, tap = b >> 1, i0 = 16 * (b & 1) + 8 * (lane >> 5);
     uint32_t w[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const uint32_t lo = f2bf(W[(o * kCnnC + i0 + 2 * q) * kCnnK + tap]);
-        const uint32_t hi = f2bf(W[(o * kCnnC + i0 + 2 * q + 1) * kCnnK + tap]);
+        const uint32_t lo = f2bf(scale * W[(o * kCnnC + i0 + 2 * q) * kCnnK + tap]);
+        const uint32_t hi = f2bf(scale * W[(o * kCnnC + i0 + 2 * q + 1) * kCnnK + tap]);
         w[q] = lo | (hi << 16);
     }
     frag[b * 64 + lane] = make_uint4(w[0], w[1], w[2], w[3]);
@@ -188,95 +190,201 @@ __global__ void __launch_bounds__(256) k_conv32_fwd_mfma(const uint16_t* X, cons
     }
 }
 
-// Inference: layers 0 and 1 in one kernel. A workgroup of layer 1 (512
-// positions t0 ..) needs layer-0 rows t0 - 4 .. t0 + 515 (pooled, 32
-// channels); it computes them from the one-channel input (samples
-// 2 t0 - 12 .. 2 t0 + 1035) straight into the LDS rows that
-// k_conv32_fwd_mfma would have loaded, with the arithmetic of k_conv1_fwd
-// (same operations, same order), so layer 0's output never goes to memory.
-// Rows outside [0, L1) are zero, as in the unfused layer's staging.
-__global__ void __launch_bounds__(256) k_conv01_fwd_mfma(const uint16_t* __restrict__ X0,
-                                                         const float* __restrict__ W0,
-                                                         const float* __restrict__ b0, const uint4* frag,
-                                                         const float* bias, uint16_t* P, int L0) {
-    constexpr int kX0 = 2 * (kMPos + 8) + 8;   // input samples of a workgroup
-    __shared__ __attribute__((aligned(16))) uint8_t xs[(kMPos + 8) * kMRow];
-    __shared__ float x0s[kX0];
-    const int L = L0 / 2;                      // layer-1 length
-    const int g = blockIdx.y;
-    const int t0 = blockIdx.x * kMPos;
-    const uint16_t* x0 = X0 + (int64_t)g * L0;
-    for (int e = threadIdx.x; e < kX0; e += 256) {
-        const int t = 2 * t0 - 12 + e;
-        x0s[e] = (t >= 0 && t < L0) ? bf2f(x0[t]) : 0.f;
+// ------------------------------------------------ inference, all layers --
+// Inference in one kernel: a workgroup computes the features of rows u0 ..
+// u0 + kFM - 1 of one signal from the input samples they depend on, keeping
+// every layer's pooled output in LDS (activations never go to memory).
+// Layer l's input rows are taken relative to a_l, with a_4 = u0 and
+// a_l = 2 a_{l+1} - 4 (a_0 = 16 u0 - 60): row r of layer l's output (row
+// a_{l+1} + r of the next layer's input) pools conv positions cp = 2r and
+// 2r + 1, and conv position cp reads input rows cp .. cp + 8. Rows outside
+// [0, L_l) are zero at every layer, as in the layer-by-layer kernels.
+//
+// Layer 0 (one input channel, 9 taps) runs on the matrix cores as a
+// contraction 16 deep: A = W0 (32 channels x 16 taps, taps 9 .. 15 zero) and
+// B = the input's Toeplitz matrix (taps x 32 positions, taps 9 .. 15 zeroed
+// as well, so no sample outside a position's window enters a product); it
+// rounds differently from the vector-ALU layer 0 of training, within float32
+// accumulation. Layers 1 .. 3 run the 18-instruction tiles of
+// k_conv32_fwd_mfma in the same order, but start the accumulators at the
+// bias and round to bf16 with the hardware conversion (nearest even, as the
+// software rounding for finite values). Weights and biases enter halved
+// (exact), so pooling needs no multiplication; halving commutes with every
+// rounding here unless a value falls below 2^-126.
+//
+// Tiles per workgroup (32 conv positions each) and rows kept (each covers
+// what the next layer's tiles read):
+//   layer 0: 37 tiles -> 592 rows of A1, from 1216 staged samples (< 1200 read)
+//   layer 1: 18 tiles -> 288 rows of A2 (296 kept, rows 288 .. 295 zero)
+//   layer 2:  9 tiles -> 144 rows of A3 (in A1's space)
+//   layer 3:  4 tiles ->  64 feature rows, stored when below F
+// The 64 features need A3 rows < 136, A2 rows < 280, A1 rows < 568 and
+// samples < 1144, all inside what the tiles compute.
+constexpr int kFM = 64;
+constexpr int kF0Tiles = 37, kF1Tiles = 18, kF2Tiles = 9, kF3Tiles = 4;
+constexpr int kA1Rows = 16 * kF0Tiles, kA2Rows = 296, kX0N = 1216;
+constexpr int kFusedLds = 2 * kX0N * 2 + (kA1Rows + kA2Rows) * kMRow + 4 * kCnnC * 4;
+static_assert(16 * kF2Tiles <= kA1Rows, "A3 fits in A1's space");
+static_assert(32 * kF1Tiles + 8 <= kA1Rows && 32 * kF2Tiles + 8 <= kA2Rows && 32 * kF3Tiles + 8 <= 16 * kF2Tiles,
+              "each layer's tiles read kept rows");
+static_assert(32 * kF0Tiles + 16 <= kX0N, "layer 0 reads staged samples");
+
+__device__ __forceinline__ float dpp_xor1(float v) {
+    // quad_perm [1,0,3,2]: lane l ^ 1 (every lane has a source, so bound_ctrl
+    // changes nothing; it lets the move fold into the addition)
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xf, 0xf, true));
+}
+
+// One layer-1..3 tile: conv positions p0 .. p0 + 31 from input rows in LDS,
+// accumulated onto the bias (acc holds the bias values on entry).
+__device__ __forceinline__ f32x16 conv_tile(const uint8_t* in, const uint4 (&a)[18], int p0, int col, int hg,
+                                            f32x16 acc) {
+#pragma unroll
+    for (int b = 0; b < 18; ++b) {
+        const int tap = b >> 1;
+        const uint4 bv = *reinterpret_cast<const uint4*>(in + (p0 + col + tap) * kMRow + 32 * (b & 1) + 16 * hg);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[b]), __builtin_bit_cast(bf16x8, bv),
+                                                      acc, 0, 0, 0);
     }
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint4 a[18];
+    return acc;
+}
+
+// The bias values of a lane's accumulator slots (channels 8 (e / 4) + 4 hg
+// + e % 4).
+__device__ __forceinline__ f32x16 bias_acc(const float* sb, int hg) {
+    f32x16 acc;
 #pragma unroll
-    for (int b = 0; b < 18; ++b) a[b] = frag[b * 64 + lane];
-    const int col = lane & 31, hg = lane >> 5;
-    float bia[16];
+    for (int e = 0; e < 16; ++e) acc[e] = sb[8 * (e >> 2) + 4 * hg + (e & 3)];
+    return acc;
+}
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// ReLU as an integer maximum of the bit pattern with 0: every negative value
+// (-0 included) becomes +0, every other value stays.
+__device__ __forceinline__ float relu_bits(float v) {
+    return __builtin_bit_cast(float, max(__builtin_bit_cast(int, v), 0));
+}
+
+// ReLU and pooling of a tile (lane col: conv position p0 + col, channels
+// 8 (e / 4) + 4 hg + e % 4). The accumulators hold z / 2 (weights and bias
+// halved, exact), so relu(z/2) + relu(z'/2) = (relu(z) + relu(z')) / 2 with
+// z' the neighbouring position's, the same value as halving the sum. Both
+// lanes of a pair get the pooled row (p0 + col) / 2 (the sum is symmetric);
+// this lane's half of it, rounded to bf16 (nearest even): channel groups q =
+// 2 odd and 2 odd + 1 (4 channels each, o = 8 q + 4 hg ..), odd = col & 1.
+struct PoolHalf {
+    uint2 q0, q1;
+};
+__device__ __forceinline__ PoolHalf tile_pool(const f32x16& acc, int odd) {
+    uint32_t pk[8];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) bia[e] = bias[8 * (e >> 2) + 4 * hg + (e & 3)];
-    __syncthreads();
-    // layer 0: row r is pooled position t = t0 - 4 + r; its conv positions
-    // 2t, 2t+1 read samples 2t - 4 .. 2t + 5 = x0s[2r .. 2r + 9]
-    for (int r = threadIdx.x; r < kMPos + 8; r += 256) {
-        const int t = t0 - 4 + r;
-        uint16_t po[kCnnC];
-        if (t >= 0 && t < L) {
-            float xv[10];
-#pragma unroll
-            for (int j = 0; j < 10; ++j) xv[j] = x0s[2 * r + j];
-#pragma unroll
-            for (int c = 0; c < kCnnC; ++c) {
-                float z0 = b0[c], z1 = b0[c];
-#pragma unroll
-                for (int k = 0; k < kCnnK; ++k) {
-                    z0 += W0[c * kCnnK + k] * xv[k];
-                    z1 += W0[c * kCnnK + k] * xv[k + 1];
-                }
-                po[c] = f2bf(0.5f * (fmaxf(z0, 0.f) + fmaxf(z1, 0.f)));
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < kCnnC; ++c) po[c] = 0;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            *reinterpret_cast<uint4*>(xs + r * kMRow + 16 * q) = reinterpret_cast<const uint4*>(po)[q];
+    for (int e = 0; e < 16; e += 2) {
+        const float r0 = relu_bits(acc[e]), r1 = relu_bits(acc[e + 1]);
+        const float p0 = r0 + dpp_xor1(r0), p1 = r1 + dpp_xor1(r1);
+        const f32x2_t p = {p0, p1};
+        pk[e >> 1] = __builtin_bit_cast(uint32_t, __builtin_convertvector(p, bf16x2_t));
     }
+    PoolHalf h;
+    h.q0 = make_uint2(odd ? pk[4] : pk[0], odd ? pk[5] : pk[1]);
+    h.q1 = make_uint2(odd ? pk[6] : pk[2], odd ? pk[7] : pk[3]);
+    return h;
+}
+
+// Pooled rows into LDS: zeros where the row's absolute index a_out + row is
+// outside [0, Lout); the even lane of a pair stores channel groups 0, 1, the
+// odd one 2, 3.
+__device__ __forceinline__ void pool_to_lds(const f32x16& acc, int p0, int col, int hg, uint8_t* out, int a_out,
+                                            int Lout) {
+    const int row = (p0 + col) >> 1, ab = a_out + row, odd = col & 1;
+    const PoolHalf h = tile_pool(acc, odd);
+    const bool ok = ab >= 0 && ab < Lout;
+    uint8_t* dst = out + row * kMRow + 2 * (16 * odd + 4 * hg);
+    *reinterpret_cast<uint2*>(dst) = ok ? h.q0 : make_uint2(0u, 0u);
+    *reinterpret_cast<uint2*>(dst + 16) = ok ? h.q1 : make_uint2(0u, 0u);
+}
+
+constexpr int kFusedWaves = 8;     // waves per workgroup (two workgroups per CU by LDS)
+
+__global__ void __launch_bounds__(64 * kFusedWaves) k_cnn_fwd_fused(
+    const uint16_t* __restrict__ X0, const float* __restrict__ W0, const float* __restrict__ b0,
+    const uint4* __restrict__ frag, const float* __restrict__ bias1, const float* __restrict__ bias2,
+    const float* __restrict__ bias3, uint16_t* __restrict__ Fout, int L0) {
+    constexpr int NT = 64 * kFusedWaves;
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    uint16_t* x0e = reinterpret_cast<uint16_t*>(lds);     // x0e[i] = input sample a_0 + i
+    uint16_t* x0o = x0e + kX0N;                            // x0o[i] = input sample a_0 + i + 1
+    uint8_t* a1 = lds + 2 * kX0N * 2;
+    uint8_t* a2 = a1 + kA1Rows * kMRow;
+    uint8_t* a3 = a1;                                      // layer 2 writes after layer 1 has read A1
+    float* sb = reinterpret_cast<float*>(a2 + kA2Rows * kMRow);   // biases, [layer][32]
+    const int g = blockIdx.y, u0 = blockIdx.x * kFM;
+    const int L1 = L0 / 2, L2 = L0 / 4, L3 = L0 / 8, F = L0 / 16;
+    const int s0 = 16 * u0 - 60, s1 = 8 * u0 - 28, s2 = 4 * u0 - 12, s3 = 2 * u0 - 4;
+    const uint16_t* x = X0 + (int64_t)g * L0;
+    const int tid = threadIdx.x;
+    for (int i = tid; i <= kX0N; i += NT) {
+        const int t = s0 + i;
+        const uint16_t v = (t >= 0 && t < L0) ? x[t] : (uint16_t)0;
+        if (i < kX0N) x0e[i] = v;
+        if (i > 0) x0o[i - 1] = v;
+    }
+    if (tid < 4 * kCnnC) {
+        const int l = tid / kCnnC, o = tid % kCnnC;
+        sb[tid] = 0.5f * (l == 0 ? b0 : l == 1 ? bias1 : l == 2 ? bias2 : bias3)[o];
+    }
+    for (int e = tid; e < (kA2Rows - 16 * kF1Tiles) * 4; e += NT)
+        *reinterpret_cast<uint4*>(a2 + (16 * kF1Tiles + (e >> 2)) * kMRow + 16 * (e & 3)) = make_uint4(0, 0, 0, 0);
+    const int lane = tid & 63, w = tid >> 6, col = lane & 31, hg = lane >> 5;
+    // layer 0's A fragment: channel col, taps 8 hg .. 8 hg + 7 (zero from 9)
+    uint32_t w0p[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int k0 = 8 * hg + 2 * q, k1 = k0 + 1;
+        const uint32_t lo = k0 < kCnnK ? f2bf(0.5f * W0[col * kCnnK + k0]) : 0u;
+        const uint32_t hi = k1 < kCnnK ? f2bf(0.5f * W0[col * kCnnK + k1]) : 0u;
+        w0p[q] = lo | (hi << 16);
+    }
+    const uint4 a0f = make_uint4(w0p[0], w0p[1], w0p[2], w0p[3]);
+    // one layer's fragments at a time: a wave loads the next layer's as soon
+    // as its own tiles of the current layer are done
+    uint4 wf[18];
+    frag += (size_t)(kCnnLayers - 1) * 18 * 64;               // the halved fragments
+#pragma unroll
+    for (int b = 0; b < 18; ++b) wf[b] = frag[b * 64 + lane];
     __syncthreads();
-    // layer 1, as k_conv32_fwd_mfma<false>
-    for (int tt = 0; tt < 4; ++tt) {
-        const int p0 = (w * 4 + tt) * 32;
-        if (t0 + p0 >= L) break;
-        f32x16 acc;
+    // layer 0 -> A1
+    for (int t = w; t < kF0Tiles; t += kFusedWaves) {
+        const int p0 = 32 * t, base = p0 + col + 8 * hg;
+        const uint32_t* src = reinterpret_cast<const uint32_t*>((base & 1) ? x0o + (base - 1) : x0e + base);
+        uint4 bv = make_uint4(src[0], src[1], src[2], src[3]);
+        if (hg) bv = make_uint4(bv.x & 0xffffu, 0u, 0u, 0u);     // tap 8 only
+        const f32x16 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+            __builtin_bit_cast(bf16x8, a0f), __builtin_bit_cast(bf16x8, bv), bias_acc(sb, hg), 0, 0, 0);
+        pool_to_lds(acc, p0, col, hg, a1, s1, L1);
+    }
+    lds_barrier();
+    // layer 1 -> A2
+    for (int t = w; t < kF1Tiles; t += kFusedWaves)
+        pool_to_lds(conv_tile(a1, wf, 32 * t, col, hg, bias_acc(sb + kCnnC, hg)), 32 * t, col, hg, a2, s2, L2);
 #pragma unroll
-        for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+    for (int b = 0; b < 18; ++b) wf[b] = frag[(18 + b) * 64 + lane];
+    lds_barrier();
+    // layer 2 -> A3
+    for (int t = w; t < kF2Tiles; t += kFusedWaves)
+        pool_to_lds(conv_tile(a2, wf, 32 * t, col, hg, bias_acc(sb + 2 * kCnnC, hg)), 32 * t, col, hg, a3, s3, L3);
 #pragma unroll
-        for (int b = 0; b < 18; ++b) {
-            const int tap = b >> 1;
-            const uint4 bv = *reinterpret_cast<const uint4*>(xs + (p0 + col + tap) * kMRow + 32 * (b & 1) + 16 * hg);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[b]),
-                                                          __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
-        }
-        const int t = t0 + p0 + col;
-        uint16_t pb[16];
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const float z = acc[e] + bia[e];
-            const float zn = __shfl_xor(z, 1, 64);
-            pb[e] = f2bf(0.5f * (fmaxf(z, 0.f) + fmaxf(zn, 0.f)));
-        }
-        if (t < L && (t & 1) == 0) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int o = 8 * q + 4 * hg;
-                *reinterpret_cast<uint2*>(P + ((int64_t)g * (L / 2) + t / 2) * kCnnC + o) =
-                    make_uint2((uint32_t)pb[4 * q] | ((uint32_t)pb[4 * q + 1] << 16),
-                               (uint32_t)pb[4 * q + 2] | ((uint32_t)pb[4 * q + 3] << 16));
-            }
+    for (int b = 0; b < 18; ++b) wf[b] = frag[(36 + b) * 64 + lane];
+    lds_barrier();
+    // layer 3 -> features
+    for (int t = w; t < kF3Tiles; t += kFusedWaves) {
+        const int p0 = 32 * t, row = (p0 + col) >> 1, odd = col & 1;
+        const PoolHalf h = tile_pool(conv_tile(a3, wf, p0, col, hg, bias_acc(sb + 3 * kCnnC, hg)), odd);
+        if (u0 + row < F) {
+            uint16_t* dst = Fout + ((int64_t)g * F + u0 + row) * kCnnC + 16 * odd + 4 * hg;
+            *reinterpret_cast<uint2*>(dst) = h.q0;
+            *reinterpret_cast<uint2*>(dst + 8) = h.q1;
         }
     }
 }
@@ -289,7 +397,7 @@ __global__ void __launch_bounds__(256) k_conv01_fwd_mfma(const uint16_t* __restr
 // I (two instructions of 16 channels each). The diagonals of the D tiles are
 // then added in a fixed order (deterministic). One workgroup per pair; wave
 // w takes D = Dmin + w, w + 4, ...
-__global__ void __launch_bounds__(256) k_head_fwd(const uint16_t* Fe, const float* params_alpha, float* raw,
+__global__ void __launch_bounds__(256) k_head_fwd(const uint16_t* __restrict__ Fe, const float* params_alpha, float* raw,
                                                   float* logits, int F, int nb) {
     extern __shared__ float tiles[];                 // [nD][32][32]
     const int b = blockIdx.x;
@@ -306,15 +414,32 @@ __global__ void __launch_bounds__(256) k_head_fwd(const uint16_t* Fe, const floa
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[e] = 0.f;
         const int ilo = D < 0 ? -D : 0, ihi = D > 0 ? nblk - D : nblk;
-        for (int I = ilo; I < ihi; ++I) {
-            const uint8_t* ax = fx + (int64_t)(32 * I + r) * 64 + 16 * g;
-            const uint8_t* by = fy + (int64_t)(32 * (I + D) + r) * 64 + 16 * g;
+        // four row blocks' loads in flight before their matrix instructions
+        // (the same instructions in the same order as one block at a time)
+        constexpr int kU = 4;
+        for (int I0 = ilo; I0 < ihi; I0 += kU) {
+            uint4 av[kU][2], bv[kU][2];
 #pragma unroll
-            for (int kb = 0; kb < 2; ++kb) {
-                const uint4 av = *reinterpret_cast<const uint4*>(ax + 32 * kb);
-                const uint4 bv = *reinterpret_cast<const uint4*>(by + 32 * kb);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
-                                                              __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
+            for (int u = 0; u < kU; ++u) {
+                if (I0 + u < ihi) {
+                    const uint8_t* ax = fx + (int64_t)(32 * (I0 + u) + r) * 64 + 16 * g;
+                    const uint8_t* by = fy + (int64_t)(32 * (I0 + u + D) + r) * 64 + 16 * g;
+#pragma unroll
+                    for (int kb = 0; kb < 2; ++kb) {
+                        av[u][kb] = *reinterpret_cast<const uint4*>(ax + 32 * kb);
+                        bv[u][kb] = *reinterpret_cast<const uint4*>(by + 32 * kb);
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                if (I0 + u < ihi) {
+#pragma unroll
+                    for (int kb = 0; kb < 2; ++kb)
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av[u][kb]),
+                                                                      __builtin_bit_cast(bf16x8, bv[u][kb]), acc, 0,
+                                                                      0, 0);
+                }
             }
         }
         // lane holds column j = r, rows i = 8 (e / 4) + 4 g + e % 4
@@ -669,17 +794,24 @@ int launch_cnn_forward(const CnnNet& net, const float* wc, const uint16_t* xdec,
         const float* bias = W + (l == 0 ? kCnnC * kCnnK : kCnnC * kCnnC * kCnnK);
         uint16_t* Z = A.z[l];
         uint16_t* P = A.x[l + 1];
-        if (l == 0 && !Z && !A.z[1]) {
-            // inference: layers 0 and 1 in one pass (layer 0's output stays in LDS)
-            const float* W1 = wc + cnn_param_offset(1);
+        if (l == 0 && kCnnLayers == 4 && !A.z[0] && !A.z[1] && !A.z[2] && !A.z[3]) {
+            // inference: all four layers in one pass (activations stay in LDS)
+            static bool lds_attr = false;
+            if (!lds_attr) {
+                TDE_HIP_CHECK(hipFuncSetAttribute((const void*)k_cnn_fwd_fused,
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, kFusedLds));
+                lds_attr = true;
+            }
+            const float* bl[4];
+            for (int k = 1; k < 4; ++k) bl[k] = wc + cnn_param_offset(k) + kCnnC * kCnnC * kCnnK;
             const uint4* fr = reinterpret_cast<const uint4*>(net.frag);
-            hipLaunchKernelGGL(k_conv01_fwd_mfma, dim3(ceil_div(L / 2, kMPos), nsig), dim3(256), 0, s, X, W, bias,
-                               fr, W1 + kCnnC * kCnnC * kCnnK, A.x[2], L);
+            hipLaunchKernelGGL(k_cnn_fwd_fused, dim3(ceil_div(L / 16, kFM), nsig), dim3(64 * kFusedWaves), kFusedLds, s,
+                               X, W, bias,
+                               fr, bl[1], bl[2], bl[3], A.x[4], L);
             TDE_HIP_CHECK(hipGetLastError());
-            X = A.x[2];
-            L /= 4;
-            ++l;
-            continue;
+            X = A.x[4];
+            L /= 16;
+            break;
         }
         if (l == 0) {
             if (Z) hipLaunchKernelGGL(k_conv1_fwd<true>, dim3(ceil_div(L / 2, 256), nsig), dim3(256), 0, s, X, W, bias, Z, P, L);
@@ -772,12 +904,16 @@ int launch_round_copy(const float* p, float* wc, int n, hipStream_t s) {
 }
 
 // Per-lane matrix-core fragments of the 32 -> 32 layers' bf16 weights.
+// The second half holds the same fragments of W / 2 (the fused inference
+// kernel's, see there).
 int launch_pack_frags(const float* wc, void* frag, hipStream_t s) {
-    for (int l = 1; l < kCnnLayers; ++l) {
-        hipLaunchKernelGGL(k_pack_wfrag, dim3(18), dim3(64), 0, s, wc + cnn_param_offset(l),
-                           reinterpret_cast<uint4*>(frag) + (size_t)(l - 1) * 18 * 64);
-        TDE_HIP_CHECK(hipGetLastError());
-    }
+    for (int h = 0; h < 2; ++h)
+        for (int l = 1; l < kCnnLayers; ++l) {
+            hipLaunchKernelGGL(k_pack_wfrag, dim3(18), dim3(64), 0, s, wc + cnn_param_offset(l),
+                               reinterpret_cast<uint4*>(frag) + (size_t)(h * (kCnnLayers - 1) + l - 1) * 18 * 64,
+                               h ? 0.5f : 1.f);
+            TDE_HIP_CHECK(hipGetLastError());
+        }
     return TDE_OK;
 }
 

@@ -87,15 +87,6 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
     return (__attribute__((address_space(1))) T*)p;
 }
 
-// A workgroup barrier that orders LDS accesses only: it waits for the wave's
-// LDS operations, not for its outstanding global loads and stores, which
-// __syncthreads() would also drain.
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
 // 16 bytes of global memory (p 16-byte aligned) as a float4.
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ float4 gload4(const float* p) {

@@ -42,6 +42,15 @@ __device__ __forceinline__ uint32_t gload_u8(const int8_t* p) {
     return (uint32_t)(*(const __attribute__((address_space(1))) uint8_t*)p);
 }
 
+// A workgroup barrier that orders LDS accesses only: it waits for the wave's
+// LDS operations, not for its outstanding global loads and stores, which
+// __syncthreads() would also drain.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ------------------------------------------------ FP4 / FP6 code packing --
 // Packed codes for the matrix-core engine's FP4 (E2M1) and FP6 (E2M3)
 // operands: W bits per code, code t of a 16-code unit at bits W t of its
@@ -469,7 +478,7 @@ struct CnnNet {
     int nparams;
     const void* frag;     // packed matrix-core weight fragments (device), 3 x 18 x 64 x 16 bytes
 };
-constexpr size_t kCnnFragBytes = 3 * 18 * 64 * 16;
+constexpr size_t kCnnFragBytes = 2 * 3 * 18 * 64 * 16;   // fragments of W, then of W / 2
 
 struct CnnActs {          // per layer l: input X_l (x[0] = decimated input), pre-activation Z_l
     uint16_t* x[kCnnLayers + 1];
