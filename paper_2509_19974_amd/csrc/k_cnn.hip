@@ -201,16 +201,16 @@ __global__ void __launch_bounds__(256) k_conv32_fwd_mfma(const uint16_t* X, cons
 // [0, L_l) are zero at every layer, as in the layer-by-layer kernels.
 //
 // Layer 0 (one input channel, 9 taps) runs on the matrix cores as a
-// contraction 16 deep: A = W0 (32 channels x 16 taps, taps 9 .. 15 zero) and
-// B = the input's Toeplitz matrix (taps x 32 positions, taps 9 .. 15 zeroed
-// as well, so no sample outside a position's window enters a product); it
-// rounds differently from the vector-ALU layer 0 of training, within float32
-// accumulation. Layers 1 .. 3 run the 18-instruction tiles of
-// k_conv32_fwd_mfma in the same order, but start the accumulators at the
-// bias and round to bf16 with the hardware conversion (nearest even, as the
-// software rounding for finite values). Weights and biases enter halved
-// (exact), so pooling needs no multiplication; halving commutes with every
-// rounding here unless a value falls below 2^-126.
+// contraction 16 deep: the input's Toeplitz matrix (32 positions x 16 taps)
+// times W0 (16 taps x 32 channels); tap 9 is the bias (input 1, weight b0),
+// taps 10 .. 15 are zero on both sides, so no sample outside a position's
+// window enters a product. It rounds differently from the vector-ALU layer 0
+// of training, within float32 accumulation. Layers 1 .. 3 run the 18-instruction tiles of
+// k_conv32_fwd_mfma in the same order, transposed (see conv_tile), start the
+// accumulators at the bias and round to bf16 with the hardware conversion
+// (nearest even, as the software rounding for finite values). Weights and
+// biases enter halved (exact), so pooling needs no multiplication; halving
+// commutes with every rounding here unless a value falls below 2^-126.
 //
 // Tiles per workgroup (32 conv positions each) and rows kept (each covers
 // what the next layer's tiles read):
@@ -235,26 +235,32 @@ __device__ __forceinline__ float dpp_xor1(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xf, 0xf, true));
 }
 
+// The fused kernel computes each tile transposed: C[t][o] = sum_k X[t][k]
+// W[k][o] with the input fragment as the first operand and the weights as
+// the second (the two operands of v_mfma_f32_32x32x16_bf16 have the same
+// lane layout, so the fragments are those of k_conv32_fwd_mfma). Lane l then
+// holds channel o = l % 32 of conv positions p0 + 8 (e / 4) + 4 (l / 32) +
+// e % 4: the two positions of a pooled row sit in one lane (e, e + 1 for
+// even e), and the lane's bias is one value.
+//
 // One layer-1..3 tile: conv positions p0 .. p0 + 31 from input rows in LDS,
-// accumulated onto the bias (acc holds the bias values on entry).
+// accumulated onto the bias (acc holds the lane's bias on entry).
 __device__ __forceinline__ f32x16 conv_tile(const uint8_t* in, const uint4 (&a)[18], int p0, int col, int hg,
                                             f32x16 acc) {
 #pragma unroll
     for (int b = 0; b < 18; ++b) {
         const int tap = b >> 1;
         const uint4 bv = *reinterpret_cast<const uint4*>(in + (p0 + col + tap) * kMRow + 32 * (b & 1) + 16 * hg);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[b]), __builtin_bit_cast(bf16x8, bv),
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, bv), __builtin_bit_cast(bf16x8, a[b]),
                                                       acc, 0, 0, 0);
     }
     return acc;
 }
 
-// The bias values of a lane's accumulator slots (channels 8 (e / 4) + 4 hg
-// + e % 4).
-__device__ __forceinline__ f32x16 bias_acc(const float* sb, int hg) {
+__device__ __forceinline__ f32x16 splat16(float v) {
     f32x16 acc;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[e] = sb[8 * (e >> 2) + 4 * hg + (e & 3)];
+    for (int e = 0; e < 16; ++e) acc[e] = v;
     return acc;
 }
 
@@ -267,42 +273,45 @@ __device__ __forceinline__ float relu_bits(float v) {
     return __builtin_bit_cast(float, max(__builtin_bit_cast(int, v), 0));
 }
 
-// ReLU and pooling of a tile (lane col: conv position p0 + col, channels
-// 8 (e / 4) + 4 hg + e % 4). The accumulators hold z / 2 (weights and bias
-// halved, exact), so relu(z/2) + relu(z'/2) = (relu(z) + relu(z')) / 2 with
-// z' the neighbouring position's, the same value as halving the sum. Both
-// lanes of a pair get the pooled row (p0 + col) / 2 (the sum is symmetric);
-// this lane's half of it, rounded to bf16 (nearest even): channel groups q =
-// 2 odd and 2 odd + 1 (4 channels each, o = 8 q + 4 hg ..), odd = col & 1.
-struct PoolHalf {
-    uint2 q0, q1;
-};
-__device__ __forceinline__ PoolHalf tile_pool(const f32x16& acc, int odd) {
-    uint32_t pk[8];
+// ReLU and pooling of a transposed tile. The accumulators hold z / 2
+// (weights and bias halved, exact), so relu(z/2) + relu(z'/2) = (relu(z) +
+// relu(z')) / 2, the pooled value. Dword q holds pooled rows
+// p0 / 2 + 4 q + 2 hg and the next one (low and high bf16, rounded to
+// nearest even) of the lane's channel.
+__device__ __forceinline__ void tile_pool(const f32x16& acc, uint32_t (&pk)[4]) {
 #pragma unroll
-    for (int e = 0; e < 16; e += 2) {
-        const float r0 = relu_bits(acc[e]), r1 = relu_bits(acc[e + 1]);
-        const float p0 = r0 + dpp_xor1(r0), p1 = r1 + dpp_xor1(r1);
-        const f32x2_t p = {p0, p1};
-        pk[e >> 1] = __builtin_bit_cast(uint32_t, __builtin_convertvector(p, bf16x2_t));
+    for (int q = 0; q < 4; ++q) {
+        const float r0 = relu_bits(acc[4 * q]) + relu_bits(acc[4 * q + 1]);
+        const float r1 = relu_bits(acc[4 * q + 2]) + relu_bits(acc[4 * q + 3]);
+        const f32x2_t p = {r0, r1};
+        pk[q] = __builtin_bit_cast(uint32_t, __builtin_convertvector(p, bf16x2_t));
     }
-    PoolHalf h;
-    h.q0 = make_uint2(odd ? pk[4] : pk[0], odd ? pk[5] : pk[1]);
-    h.q1 = make_uint2(odd ? pk[6] : pk[2], odd ? pk[7] : pk[3]);
-    return h;
 }
 
-// Pooled rows into LDS: zeros where the row's absolute index a_out + row is
-// outside [0, Lout); the even lane of a pair stores channel groups 0, 1, the
-// odd one 2, 3.
+// Pooled rows into LDS: zeros where a row's absolute index a_out + row is
+// outside [0, Lout) (only tiles at the signal's ends have such rows).
 __device__ __forceinline__ void pool_to_lds(const f32x16& acc, int p0, int col, int hg, uint8_t* out, int a_out,
                                             int Lout) {
-    const int row = (p0 + col) >> 1, ab = a_out + row, odd = col & 1;
-    const PoolHalf h = tile_pool(acc, odd);
-    const bool ok = ab >= 0 && ab < Lout;
-    uint8_t* dst = out + row * kMRow + 2 * (16 * odd + 4 * hg);
-    *reinterpret_cast<uint2*>(dst) = ok ? h.q0 : make_uint2(0u, 0u);
-    *reinterpret_cast<uint2*>(dst + 16) = ok ? h.q1 : make_uint2(0u, 0u);
+    uint32_t pk[4];
+    tile_pool(acc, pk);
+    const int r0 = p0 / 2 + 2 * hg;
+    uint8_t* dst = out + r0 * kMRow + 2 * col;
+    const int first = a_out + p0 / 2;
+    if (first >= 0 && first + 16 <= Lout) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            *reinterpret_cast<uint16_t*>(dst + 4 * q * kMRow) = (uint16_t)pk[q];
+            *reinterpret_cast<uint16_t*>(dst + (4 * q + 1) * kMRow) = (uint16_t)(pk[q] >> 16);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int ab = a_out + r0 + 4 * q;
+            const bool ok0 = ab >= 0 && ab < Lout, ok1 = ab + 1 >= 0 && ab + 1 < Lout;
+            *reinterpret_cast<uint16_t*>(dst + 4 * q * kMRow) = ok0 ? (uint16_t)pk[q] : (uint16_t)0;
+            *reinterpret_cast<uint16_t*>(dst + (4 * q + 1) * kMRow) = ok1 ? (uint16_t)(pk[q] >> 16) : (uint16_t)0;
+        }
+    }
 }
 
 constexpr int kFusedWaves = 8;     // waves per workgroup (two workgroups per CU by LDS)
@@ -337,14 +346,16 @@ __global__ void __launch_bounds__(64 * kFusedWaves) k_cnn_fwd_fused(
     for (int e = tid; e < (kA2Rows - 16 * kF1Tiles) * 4; e += NT)
         *reinterpret_cast<uint4*>(a2 + (16 * kF1Tiles + (e >> 2)) * kMRow + 16 * (e & 3)) = make_uint4(0, 0, 0, 0);
     const int lane = tid & 63, w = tid >> 6, col = lane & 31, hg = lane >> 5;
-    // layer 0's A fragment: channel col, taps 8 hg .. 8 hg + 7 (zero from 9)
+    // layer 0's weight fragment: channel col, taps 8 hg .. 8 hg + 7; tap 9
+    // carries the bias (its input is 1), taps 10 .. 15 are zero
     uint32_t w0p[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int k0 = 8 * hg + 2 * q, k1 = k0 + 1;
-        const uint32_t lo = k0 < kCnnK ? f2bf(0.5f * W0[col * kCnnK + k0]) : 0u;
-        const uint32_t hi = k1 < kCnnK ? f2bf(0.5f * W0[col * kCnnK + k1]) : 0u;
-        w0p[q] = lo | (hi << 16);
+        auto wk = [&](int k) -> uint32_t {
+            return k < kCnnK ? f2bf(0.5f * W0[col * kCnnK + k]) : k == kCnnK ? f2bf(0.5f * b0[col]) : 0u;
+        };
+        w0p[q] = wk(k0) | (wk(k1) << 16);
     }
     const uint4 a0f = make_uint4(w0p[0], w0p[1], w0p[2], w0p[3]);
     // one layer's fragments at a time: a wave loads the next layer's as soon
@@ -359,33 +370,38 @@ __global__ void __launch_bounds__(64 * kFusedWaves) k_cnn_fwd_fused(
         const int p0 = 32 * t, base = p0 + col + 8 * hg;
         const uint32_t* src = reinterpret_cast<const uint32_t*>((base & 1) ? x0o + (base - 1) : x0e + base);
         uint4 bv = make_uint4(src[0], src[1], src[2], src[3]);
-        if (hg) bv = make_uint4(bv.x & 0xffffu, 0u, 0u, 0u);     // tap 8 only
+        if (hg) bv = make_uint4((bv.x & 0xffffu) | 0x3f800000u, 0u, 0u, 0u);   // tap 8, then 1.0 for the bias
         const f32x16 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-            __builtin_bit_cast(bf16x8, a0f), __builtin_bit_cast(bf16x8, bv), bias_acc(sb, hg), 0, 0, 0);
+            __builtin_bit_cast(bf16x8, bv), __builtin_bit_cast(bf16x8, a0f), splat16(0.f), 0, 0, 0);
         pool_to_lds(acc, p0, col, hg, a1, s1, L1);
     }
     lds_barrier();
     // layer 1 -> A2
     for (int t = w; t < kF1Tiles; t += kFusedWaves)
-        pool_to_lds(conv_tile(a1, wf, 32 * t, col, hg, bias_acc(sb + kCnnC, hg)), 32 * t, col, hg, a2, s2, L2);
+        pool_to_lds(conv_tile(a1, wf, 32 * t, col, hg, splat16(sb[kCnnC + col])), 32 * t, col, hg, a2, s2, L2);
 #pragma unroll
     for (int b = 0; b < 18; ++b) wf[b] = frag[(18 + b) * 64 + lane];
     lds_barrier();
     // layer 2 -> A3
     for (int t = w; t < kF2Tiles; t += kFusedWaves)
-        pool_to_lds(conv_tile(a2, wf, 32 * t, col, hg, bias_acc(sb + 2 * kCnnC, hg)), 32 * t, col, hg, a3, s3, L3);
+        pool_to_lds(conv_tile(a2, wf, 32 * t, col, hg, splat16(sb[2 * kCnnC + col])), 32 * t, col, hg, a3, s3,
+                    L3);
 #pragma unroll
     for (int b = 0; b < 18; ++b) wf[b] = frag[(36 + b) * 64 + lane];
     lds_barrier();
     // layer 3 -> features
     for (int t = w; t < kF3Tiles; t += kFusedWaves) {
-        const int p0 = 32 * t, row = (p0 + col) >> 1, odd = col & 1;
-        const PoolHalf h = tile_pool(conv_tile(a3, wf, p0, col, hg, bias_acc(sb + 3 * kCnnC, hg)), odd);
-        if (u0 + row < F) {
-            uint16_t* dst = Fout + ((int64_t)g * F + u0 + row) * kCnnC + 16 * odd + 4 * hg;
-            *reinterpret_cast<uint2*>(dst) = h.q0;
-            *reinterpret_cast<uint2*>(dst + 8) = h.q1;
-        }
+        const int p0 = 32 * t;
+        uint32_t pk[4];
+        tile_pool(conv_tile(a3, wf, p0, col, hg, splat16(sb[3 * kCnnC + col])), pk);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int row = p0 / 2 + 2 * hg + 4 * q + h;
+                if (u0 + row < F)
+                    Fout[((int64_t)g * F + u0 + row) * kCnnC + col] = (uint16_t)(h ? pk[q] >> 16 : pk[q]);
+            }
     }
 }
 
