@@ -520,7 +520,7 @@ __device__ __forceinline__ void wave_loop_fp(const XPair& p, int64_t T0, int64_t
 // for a tile of MB column blocks.
 template <int MB, bool FP>
 __device__ __forceinline__ void mfma_tile(const XItem& it, const MWork& wk, uint8_t* lds, ArgPart* tile_parts,
-                                          int* counter, int* s_next) {
+                                          int* counter, int* s_next, void* rbuf) {
     using C = MCfg<MB>;
     const XPair& p = it.p;
     const int64_t T0 = it.T_start + (int64_t)wk.tile * C::TLW;
@@ -590,7 +590,7 @@ __device__ __forceinline__ void mfma_tile(const XItem& it, const MWork& wk, uint
         __syncthreads();
         // the pair's fields, read once: the r stores below go through generic
         // pointers and would make the compiler re-read them per lag
-        void* const r = p.r;
+        void* const r = rbuf;
         const int r_dtype = p.r_dtype;
         const bool segmented = wk.segmented != 0;
         const int64_t lag_lo = p.lag_lo;
@@ -698,7 +698,7 @@ __device__ __forceinline__ void mfma_tile(const XItem& it, const MWork& wk, uint
     __syncthreads();
 
     // ---- outputs: r (plain stores or, for segments, atomics) and the triple
-    void* const r = p.r;                 // read once (as in the int32 path)
+    void* const r = rbuf;                // read once (as in the int32 path)
     const int r_dtype = p.r_dtype;
     const bool segmented = wk.segmented != 0;
     const int64_t lag_lo = p.lag_lo;
@@ -745,12 +745,38 @@ __device__ __forceinline__ void mfma_tile(const XItem& it, const MWork& wk, uint
 
 // Persistent: each workgroup takes items until the list is exhausted; every
 // wave of the grid reaches the exit once the counter passes nwork.
+// A value written by an earlier kernel of the same call, read with a
+// device-scope load (not through the scalar cache).
+__device__ __forceinline__ uint64_t fresh_u64(const void* p) {
+    return __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int fresh_int(const int* p) {
+    return __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ MWork fresh_work(const MWork* p) {
+    constexpr int N = sizeof(MWork) / 8;
+    static_assert(sizeof(MWork) % 8 == 0, "whole 8-byte words");
+    uint64_t w[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const uint64_t v = fresh_u64(reinterpret_cast<const uint64_t*>(p) + k);
+        w[k] = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
+               __builtin_amdgcn_readfirstlane((uint32_t)v);
+    }
+    return __builtin_bit_cast(MWork, w);
+}
+
 template <int MB>
 __global__ void __launch_bounds__(256, MB == 4 ? 2 : 1) k_xcorr_mfma(const XItem* __restrict__ items,
                                                                       const MWork* __restrict__ work, int nwork,
-                                                                      int* counter, ArgPart* tile_parts) {
+                                                                      int* counter, ArgPart* tile_parts,
+                                                                      const int* nwork_dev, uint8_t* rpool,
+                                                                      int64_t slot_bytes) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     __shared__ int s_item;
+    // a list planned on the device (nwork was its capacity): its length and
+    // items come through device-scope loads
+    if (nwork_dev) nwork = fresh_int(nwork_dev);
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
     for (;;) {
@@ -758,8 +784,9 @@ __global__ void __launch_bounds__(256, MB == 4 ? 2 : 1) k_xcorr_mfma(const XItem
         const int wi = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();                  // every wave has read s_item
         if (wi >= nwork) break;
-        const MWork wk = work[wi];
+        const MWork wk = nwork_dev ? fresh_work(work + wi) : work[wi];
         const XItem& it = items[wk.pair];
+        void* const rbuf = wk.rslot ? rpool + (int64_t)(wk.rslot - 1) * slot_bytes : it.p.r;
         if (it.margin && *it.margin >= it.theta) {   // learned mode: windows suffice
             if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
             __syncthreads();
@@ -769,11 +796,11 @@ __global__ void __launch_bounds__(256, MB == 4 ? 2 : 1) k_xcorr_mfma(const XItem
         // run in the 4-block launch. Each item leaves the next one in s_item.
         if (MB == 4 && wk.fmt != kFmtI8) {
             if (wk.mb == 8)
-                mfma_tile<8, true>(it, wk, lds, tile_parts, counter, &s_item);
+                mfma_tile<8, true>(it, wk, lds, tile_parts, counter, &s_item, rbuf);
             else
-                mfma_tile<4, true>(it, wk, lds, tile_parts, counter, &s_item);
+                mfma_tile<4, true>(it, wk, lds, tile_parts, counter, &s_item, rbuf);
         } else {
-            mfma_tile<MB, false>(it, wk, lds, tile_parts, counter, &s_item);
+            mfma_tile<MB, false>(it, wk, lds, tile_parts, counter, &s_item, rbuf);
         }
         __syncthreads();
     }
@@ -1005,7 +1032,7 @@ static_assert(kernel_lds<4>() >= MCfg<8>::TLW * 4, "FP 8-block reduction area");
 
 template <int MB>
 static int launch_mb(const XItem* items_dev, const MWork* work, int nwork, int* counter, ArgPart* tile_parts,
-                     int num_cu, hipStream_t s) {
+                     int num_cu, hipStream_t s, const int* nwork_dev, uint8_t* rpool, int64_t slot_bytes) {
     if (nwork == 0) return TDE_OK;
     static int per_cu = 0;
     if (per_cu == 0) {
@@ -1018,20 +1045,24 @@ static int launch_mb(const XItem* items_dev, const MWork* work, int nwork, int* 
     int grid = per_cu * num_cu;
     if (grid > nwork) grid = nwork;
     hipLaunchKernelGGL(k_xcorr_mfma<MB>, dim3(grid), dim3(256), kernel_lds<MB>(), s, items_dev, work, nwork, counter,
-                       tile_parts);
+                       tile_parts, nwork_dev, rpool, slot_bytes);
     TDE_HIP_CHECK(hipGetLastError());
     return TDE_OK;
 }
 
 int launch_xcorr_mfma(const XItem* items_dev, const MWork* work_dev, int nwork, int* counters_dev,
-                      bool counters_zeroed, ArgPart* tile_parts, int num_cu, hipStream_t s, int n4) {
+                      bool counters_zeroed, ArgPart* tile_parts, int num_cu, hipStream_t s, int n4,
+                      const int* nwork_dev, uint8_t* rpool, int64_t slot_bytes) {
     if (!counters_zeroed) {
         hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, counters_dev, 2);
         TDE_HIP_CHECK(hipGetLastError());
     }
-    int rc = launch_mb<4>(items_dev, work_dev, n4, counters_dev, tile_parts, num_cu, s);
+    // a device-planned list holds 4-block-launch items only
+    int rc = launch_mb<4>(items_dev, work_dev, n4, counters_dev, tile_parts, num_cu, s, nwork_dev, rpool, slot_bytes);
     if (rc) return rc;
-    return launch_mb<8>(items_dev, work_dev + n4, nwork - n4, counters_dev + 1, tile_parts, num_cu, s);
+    if (nwork_dev) return TDE_OK;
+    return launch_mb<8>(items_dev, work_dev + n4, nwork - n4, counters_dev + 1, tile_parts, num_cu, s, nullptr,
+                        nullptr, 0);
 }
 
 int launch_pack_fp(const int8_t* q, int64_t n, uint32_t* pk, int W, hipStream_t s) {
@@ -1049,6 +1080,219 @@ int launch_pack_fp(const int8_t* q, int64_t n, uint32_t* pk, int W, hipStream_t 
 int launch_tiles_final(const XItem* items_dev, const XItem& one, int npairs, const ArgPart* tile_parts,
                        hipStream_t s) {
     hipLaunchKernelGGL(k_tiles_final, dim3(npairs), dim3(64), 0, s, items_dev, one, npairs, tile_parts);
+    TDE_HIP_CHECK(hipGetLastError());
+    return TDE_OK;
+}
+
+// ------------------------------------------- learned fallback, on device --
+// One workgroup: the pairs below the margin threshold (in pair order), their
+// items, and the split factor S that makes about `target` items; then the
+// work list, and for S > 1 the pairs' r slots. ctl[0]: pairs with a slot
+// (0 when S <= 1), ctl[1]: items in the list.
+__global__ void __launch_bounds__(1024) k_fb_plan(const XItem* items, int npairs, const MWork* __restrict__ swork,
+                                                  MWork* dwork, int* ctl, int* slots, int target) {
+    __shared__ int s_sum[2][32];
+    __shared__ int s_tot[2];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    auto falls = [&](int i) { return !(*items[i].margin >= items[i].theta); };
+    // pass 1: how many pairs fall back, and their items
+    int nf = 0, ni = 0;
+    for (int i = tid; i < npairs; i += 1024)
+        if (falls(i)) {
+            nf += 1;
+            ni += items[i].work_count;
+        }
+    for (int o = 32; o > 0; o >>= 1) {
+        nf += __shfl_xor(nf, o, 64);
+        ni += __shfl_xor(ni, o, 64);
+    }
+    if (lane == 0) {
+        s_sum[0][wv] = nf;
+        s_sum[1][wv] = ni;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int a = 0, b = 0;
+        for (int k = 0; k < 16; ++k) {
+            a += s_sum[0][k];
+            b += s_sum[1][k];
+        }
+        s_tot[0] = a;
+        s_tot[1] = b;
+    }
+    __syncthreads();
+    const int NF = s_tot[0], NI = s_tot[1];
+    int S = 1;
+    if (NF > 0 && NF <= kFbSlots && NI < target) {
+        S = (target + NI - 1) / NI;
+        S = S > kFbMaxSplit ? kFbMaxSplit : S;
+    }
+    // pass 2: the list, chunk by chunk of 1024 pairs (exclusive scans of the
+    // item counts and of the fallback flags)
+    int base_items = 0, base_slot = 0;
+    for (int c0 = 0; c0 < npairs; c0 += 1024) {
+        __syncthreads();
+        const int i = c0 + tid;
+        const bool fb = i < npairs && falls(i);
+        const int cnt = fb ? items[i].work_count * S : 0, one = fb ? 1 : 0;
+        int pc = cnt, po = one;                       // inclusive scans inside the wave
+        for (int o = 1; o < 64; o <<= 1) {
+            const int a = __shfl_up(pc, o, 64), b = __shfl_up(po, o, 64);
+            if (lane >= o) {
+                pc += a;
+                po += b;
+            }
+        }
+        if (lane == 63) {
+            s_sum[0][wv] = pc;
+            s_sum[1][wv] = po;
+        }
+        __syncthreads();
+        int wc = 0, wo = 0, tc = 0, to = 0;
+        for (int k = 0; k < 16; ++k) {
+            if (k < wv) {
+                wc += s_sum[0][k];
+                wo += s_sum[1][k];
+            }
+            tc += s_sum[0][k];
+            to += s_sum[1][k];
+        }
+        if (fb) {
+            const XItem& it = items[i];
+            const int pos = base_items + wc + pc - cnt, slot = base_slot + wo + po - one;
+            if (S > 1) slots[slot] = i;
+            int o = pos;
+            for (int j = 0; j < it.work_count; ++j) {
+                const MWork w = swork[it.work_first + j];
+                if (S == 1) {
+                    dwork[o++] = w;
+                    continue;
+                }
+                // segments of whole 4 x 32 mb steps (the cut of a long tile)
+                const int64_t unit = 128 * (int64_t)w.mb, len = w.qb - w.qa;
+                const int64_t seg = (len + S - 1) / S;
+                const int64_t step = (seg + unit - 1) / unit * unit;
+                for (int k = 0; k < S; ++k) {
+                    MWork x = w;
+                    const int64_t a = w.qa + k * step;
+                    x.qa = a < w.qb ? a : w.qb;
+                    x.qb = a + step < w.qb ? a + step : w.qb;
+                    x.segmented = 1;
+                    x.rslot = slot + 1;
+                    dwork[o++] = x;
+                }
+            }
+        }
+        base_items += tc;
+        base_slot += to;
+    }
+    if (tid == 0) {
+        ctl[0] = S > 1 ? NF : 0;
+        ctl[1] = NI * S;
+    }
+}
+
+// grid (kFbSlots, 64): the r slots of the split pairs to zero.
+__global__ void __launch_bounds__(256) k_fb_zero(const XItem* items, const int* ctl, const int* slots,
+                                                 uint8_t* rpool, int64_t slot_bytes) {
+    const int k = blockIdx.x;
+    if (k >= fresh_int(ctl)) return;
+    const XPair& p = items[fresh_int(slots + k)].p;
+    const int64_t bytes = (p.lag_hi - p.lag_lo + 1) * (p.r_dtype == TDE_I32 ? 4 : 8);
+    uint8_t* r = rpool + (int64_t)k * slot_bytes;     // 16-byte aligned slot, whole 16-byte pieces
+    for (int64_t e = 16 * ((int64_t)blockIdx.y * 256 + threadIdx.x); e < bytes; e += 16 * 256 * 64)
+        *reinterpret_cast<uint4*>(r + e) = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// grid (kFbSlots, kFbChunks): (max, first lag, count) of a split pair's r
+// over one of kFbChunks consecutive parts of its lags (lags no tile covers
+// kept their zero), four values per load.
+constexpr int kFbChunks = 64;
+__global__ void __launch_bounds__(256) k_fb_argmax_parts(const XItem* items, const int* ctl, const int* slots,
+                                                         const uint8_t* rpool, int64_t slot_bytes, ArgPart* parts) {
+    const int k = blockIdx.x, c = blockIdx.y;
+    if (k >= fresh_int(ctl)) return;
+    const XItem& it = items[fresh_int(slots + k)];
+    const int64_t L = it.p.lag_hi - it.p.lag_lo + 1;
+    const int64_t per = ((L + kFbChunks - 1) / kFbChunks + 3) / 4 * 4;     // keeps 16-byte loads aligned
+    const int64_t lo = c * per, hi = lo + per < L ? lo + per : L;
+    const bool i32 = it.p.r_dtype == TDE_I32;
+    const uint8_t* r = rpool + (int64_t)k * slot_bytes;
+    Tri64 t{INT64_MIN, INT64_MAX, 0};
+    for (int64_t e0 = lo + 4 * (int64_t)threadIdx.x; e0 < hi; e0 += 4 * 256) {
+        int64_t v[4];
+        if (i32 && e0 + 4 <= hi && (e0 & 3) == 0) {
+            const int4 q = *reinterpret_cast<const int4*>(r + 4 * e0);
+            v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                v[e] = e0 + e >= hi ? INT64_MIN
+                       : i32        ? (int64_t) reinterpret_cast<const int32_t*>(r)[e0 + e]
+                                    : reinterpret_cast<const int64_t*>(r)[e0 + e];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (e0 + e < hi) t = tri_join(t, Tri64{v[e], e0 + e, 1});
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        Tri64 u{__shfl_xor(t.v, o, 64), __shfl_xor(t.i, o, 64), __shfl_xor(t.c, o, 64)};
+        t = tri_join(t, u);
+    }
+    __shared__ Tri64 sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        t = tri_join(tri_join(sh[0], sh[1]), tri_join(sh[2], sh[3]));
+        parts[k * kFbChunks + c] = ArgPart{t.v, t.i, t.c};
+    }
+}
+
+// grid kFbSlots: the peaks of the split pairs from their parts.
+__global__ void __launch_bounds__(64) k_fb_argmax(const XItem* items, const int* ctl, const int* slots,
+                                                  const ArgPart* parts) {
+    const int k = blockIdx.x;
+    if (k >= fresh_int(ctl)) return;
+    const XItem& it = items[fresh_int(slots + k)];
+    const ArgPart a = parts[k * kFbChunks + threadIdx.x];
+    Tri64 t{a.vmax, a.idx, a.cnt};
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        Tri64 u{__shfl_xor(t.v, o, 64), __shfl_xor(t.i, o, 64), __shfl_xor(t.c, o, 64)};
+        t = tri_join(t, u);
+    }
+    if (threadIdx.x == 0) {
+        tde_peak pk;
+        pk.lag = it.p.lag_lo + t.i;
+        pk.rmax = t.v;
+        pk.n_ties = (int32_t)t.c;
+        pk.flags = peak_flags(it.stat_x, it.p.nu, it.stat_y, it.p.nv) | TDE_FLAG_FALLBACK;
+        *it.peak = pk;
+    }
+}
+static_assert(kFbChunks == 64, "one part per lane of the final wave");
+
+int launch_fb_plan(const XItem* items_dev, int npairs, const MWork* swork, MWork* dwork, int* ctl, int* slots,
+                   int target, hipStream_t s) {
+    hipLaunchKernelGGL(k_fb_plan, dim3(1), dim3(1024), 0, s, items_dev, npairs, swork, dwork, ctl, slots, target);
+    TDE_HIP_CHECK(hipGetLastError());
+    return TDE_OK;
+}
+
+int launch_fb_zero(const XItem* items_dev, const int* ctl, const int* slots, uint8_t* rpool, int64_t slot_bytes,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_fb_zero, dim3(kFbSlots, 64), dim3(256), 0, s, items_dev, ctl, slots, rpool, slot_bytes);
+    TDE_HIP_CHECK(hipGetLastError());
+    return TDE_OK;
+}
+
+int launch_fb_argmax(const XItem* items_dev, const int* ctl, const int* slots, const uint8_t* rpool,
+                     int64_t slot_bytes, ArgPart* parts, hipStream_t s) {
+    hipLaunchKernelGGL(k_fb_argmax_parts, dim3(kFbSlots, kFbChunks), dim3(256), 0, s, items_dev, ctl, slots, rpool,
+                       slot_bytes, parts);
+    TDE_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_fb_argmax, dim3(kFbSlots), dim3(64), 0, s, items_dev, ctl, slots, parts);
     TDE_HIP_CHECK(hipGetLastError());
     return TDE_OK;
 }

@@ -814,6 +814,11 @@ struct BatchPlan {
     std::vector<size_t> off_r;      // per pair (r materialized in the workspace)
     std::vector<size_t> off_planes; // per pair (bit-plane engine)
     std::vector<size_t> off_pk;     // per signal: packed FP4/FP6 codes (0: none)
+    // learned mode: the fallback's work list planned on the device (every pair
+    // on 4-block matrix-core items with tile triples, no caller r)
+    bool fb_dyn = false;
+    int64_t fb_cap = 0, fb_slot_bytes = 0;
+    size_t off_fbctl = 0, off_fbslots = 0, off_dwork = 0, off_rpool = 0, off_fbparts = 0;
 };
 
 BatchPlan plan_batch(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
@@ -870,6 +875,28 @@ BatchPlan plan_batch(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
         B.off_top = take(sizeof(int32_t) * np * B.topk);
         B.off_margin = take(sizeof(float) * np);
         B.off_wparts = take(sizeof(ArgPart) * np * B.topk);
+        bool dyn = true;
+        int64_t max_items = 0, slot = 0;
+        for (int64_t i = 0; i < np; ++i) {
+            const PairPlan& pp = B.pp[i];
+            if (pp.eng != TDE_PATH_MFMA || !pp.fused || pairs[i].r_out ||
+                mfma_launch_of(pp.probe.fmt, pp.probe.mb) != 4) {
+                dyn = false;
+                break;
+            }
+            max_items = std::max<int64_t>(max_items, mfma_count_items(pp.probe));
+            slot = std::max<int64_t>(slot, (pairs[i].lag_hi - pairs[i].lag_lo + 1) * (pp.rdt == TDE_I32 ? 4 : 8));
+        }
+        if (dyn && np > 0) {
+            B.fb_dyn = true;
+            B.fb_cap = std::max<int64_t>(B.nwork, (int64_t)kFbSlots * max_items * kFbMaxSplit);
+            B.fb_slot_bytes = (int64_t)align_bytes((size_t)slot);
+            B.off_fbctl = take(4 * sizeof(int));
+            B.off_fbslots = take(kFbSlots * sizeof(int));
+            B.off_dwork = take(sizeof(MWork) * B.fb_cap);
+            B.off_rpool = take((size_t)(kFbSlots * B.fb_slot_bytes));
+            B.off_fbparts = take(sizeof(ArgPart) * kFbSlots * 64);
+        }
     }
     B.off_q.resize(2 * np);
     B.off_gsum.resize(2 * np);
@@ -1021,7 +1048,9 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
                 tbase += it.ntiles;
                 L.any_fused = true;
             }
+            it.work_first = (int32_t)work.size();
             mfma_items(it, (int)i, work);
+            it.work_count = (int32_t)(work.size() - it.work_first);
         } else if (pp.eng == TDE_PATH_NTT) {
             it.part_base = tbase;
             tbase += it.ntiles;
@@ -1079,7 +1108,9 @@ void batch_prepare(tde_ctx* ctx, const tde_pair* pairs, int64_t np, tde_peak* ou
             jobs.push_back(J);
         }
     }
-    mfma_sort_items(work);
+    // longest first; a list the device plans from keeps pair order (each
+    // pair's items at work_first .. work_first + work_count - 1)
+    if (!B.fb_dyn) mfma_sort_items(work);
     L.bbase = bbase;
     L.pbase = pbase;
     L.nwork = (int)work.size();
@@ -1146,10 +1177,25 @@ int batch_enqueue(tde_ctx* ctx, uint8_t* W, const BatchPlan& B, const BatchLaunc
                         L.ngroup_jobs[k], s);
         if (rc) return rc;
     }
+    int* fb_ctl = reinterpret_cast<int*>(W + B.off_fbctl);
+    int* fb_slots = reinterpret_cast<int*>(W + B.off_fbslots);
     if (L.any_mfma) {
         hipEvent_t t_m0 = mk();
-        rc = launch_xcorr_mfma(items_dev, reinterpret_cast<const MWork*>(W + B.off_work), L.nwork,
-                               reinterpret_cast<int*>(W + B.off_counters), true, tparts, ctx->num_cu, s, L.n4);
+        if (B.fb_dyn) {
+            // the fallback pairs' items, cut so that they fill the device
+            // (about two items per resident workgroup of the engine)
+            MWork* dwork = reinterpret_cast<MWork*>(W + B.off_dwork);
+            rc = launch_fb_plan(items_dev, (int)L.np, reinterpret_cast<const MWork*>(W + B.off_work), dwork, fb_ctl,
+                                fb_slots, 4 * ctx->num_cu, s);
+            if (rc) return rc;
+            rc = launch_fb_zero(items_dev, fb_ctl, fb_slots, W + B.off_rpool, B.fb_slot_bytes, s);
+            if (rc) return rc;
+            rc = launch_xcorr_mfma(items_dev, dwork, (int)B.fb_cap, reinterpret_cast<int*>(W + B.off_counters), true,
+                                   tparts, ctx->num_cu, s, (int)B.fb_cap, fb_ctl + 1, W + B.off_rpool, B.fb_slot_bytes);
+        } else {
+            rc = launch_xcorr_mfma(items_dev, reinterpret_cast<const MWork*>(W + B.off_work), L.nwork,
+                                   reinterpret_cast<int*>(W + B.off_counters), true, tparts, ctx->num_cu, s, L.n4);
+        }
         if (rc) return rc;
         hipEvent_t t_m1 = mk();
         if (timed) mark_stage(ctx, 6, t_m0, t_m1);
@@ -1158,6 +1204,11 @@ int batch_enqueue(tde_ctx* ctx, uint8_t* W, const BatchPlan& B, const BatchLaunc
     if (timed) mark_stage(ctx, 1, t_e0, t_e1);
     if (L.any_fused) {
         rc = launch_tiles_final(items_dev, none, (int)L.np, tparts, s);
+        if (rc) return rc;
+    }
+    if (B.fb_dyn && L.any_mfma) {
+        rc = launch_fb_argmax(items_dev, fb_ctl, fb_slots, W + B.off_rpool, B.fb_slot_bytes,
+                              reinterpret_cast<ArgPart*>(W + B.off_fbparts), s);
         if (rc) return rc;
     }
     if (L.nsegs) {

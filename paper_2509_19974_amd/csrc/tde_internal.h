@@ -330,6 +330,9 @@ struct XItem {
     int32_t nwin;
     const ArgPart* win_parts;
     int32_t win_w;        // learned mode: 4 or 6, windows on FP operands of that width; 0, on int8
+    // learned mode with the fallback planned on the device: the pair's
+    // unsegmented matrix-core items in the static list
+    int32_t work_first, work_count;
 };
 
 // zero the bit-plane regions of a batch (one launch for every pair)
@@ -348,7 +351,7 @@ struct MWork {
     int32_t segmented;
     int32_t mb;           // accumulator tiles per wave of the pair's plan
     int32_t fmt;          // operand format of the pair's plan
-    int32_t pad0;
+    int32_t rslot;        // 0, or k + 1: r is slot k of the learned fallback's pool (not the pair's r)
 };
 // Operand formats of the matrix-core engine (kFmtI8, kFmtF6, kFmtF4 above).
 // Codes with |q| <= 3 are exact in FP4 (E2M1), |q| <= 7 in FP6 (E2M3); both
@@ -369,10 +372,31 @@ void mfma_sort_items(std::vector<MWork>& w);
 // of scratch, reset here unless an earlier kernel of the call already did.
 int choose_mb(const XPair& p);
 int launch_xcorr_mfma(const XItem* items_dev, const MWork* work_dev, int nwork, int* counters_dev,
-                      bool counters_zeroed, ArgPart* tile_parts, int num_cu, hipStream_t s, int n4);
+                      bool counters_zeroed, ArgPart* tile_parts, int num_cu, hipStream_t s, int n4,
+                      const int* nwork_dev = nullptr, uint8_t* rpool = nullptr, int64_t slot_bytes = 0);
 // peaks of the fused pairs from their tile triples
 int launch_tiles_final(const XItem* items_dev, const XItem& one, int npairs, const ArgPart* tile_parts,
                        hipStream_t s);
+// Learned mode, fallback planned on the device (graph-safe, no host
+// decision): the pairs whose margin is below the threshold get their
+// matrix-core items in a work list whose length the engine reads from
+// ctl[1]. When few pairs fall back (at most kFbSlots, fewer items than
+// `target`), each item is cut into up to kFbMaxSplit segments along m that
+// add into slot k of rpool (ctl[0] pairs, slots[k] = pair, the item's
+// rslot = k + 1), so that the segments fill the device; launch_fb_zero
+// clears those slots first and launch_fb_argmax writes their peaks after
+// the engine (over the peaks launch_tiles_final wrote from unused tile
+// triples). The descriptors are never written during a call: what the
+// planner writes is read back with device-scope loads, never through the
+// scalar cache that earlier kernels of the call may have filled.
+constexpr int kFbSlots = 64, kFbMaxSplit = 16;
+int launch_fb_plan(const XItem* items_dev, int npairs, const MWork* swork, MWork* dwork, int* ctl, int* slots,
+                   int target, hipStream_t s);
+int launch_fb_zero(const XItem* items_dev, const int* ctl, const int* slots, uint8_t* rpool, int64_t slot_bytes,
+                   hipStream_t s);
+// parts: kFbSlots * 64 ArgPart of scratch
+int launch_fb_argmax(const XItem* items_dev, const int* ctl, const int* slots, const uint8_t* rpool,
+                     int64_t slot_bytes, ArgPart* parts, hipStream_t s);
 
 // bit-plane engine for ternary codes
 size_t popc_ws_bytes(const XPair& p);

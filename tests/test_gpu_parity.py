@@ -1076,6 +1076,37 @@ def test_learned_batch_matches_window_semantics(T, ctx):
     model.close()
 
 
+def test_learned_fallback_split_and_unsplit(T, ctx):
+    """The fallback's work list is planned on the device: with at most 64
+    fallback pairs their items are cut along m into segments that add into r
+    slots, beyond that they run whole. Both must give the plain full search's
+    peaks, with the fallback flag: 80 of 80 pairs falling back (whole items)
+    and a threshold between the margins that leaves a few (cut items)."""
+    from paper_2509_19974_amd import tde
+    say("learned fallback, split and unsplit")
+    model = tde.Model(ctx, 1024, 64, seed=5)
+    pairs = synth.config5_reverb(npairs=80, n=16384, max_lag=64 * 128, t60_range=(200, 1200))
+    specs = [dict(x=dev(T, p["x"]), y=dev(T, p["y"]), lag_lo=p["lag_lo"], lag_hi=p["lag_hi"], bits=p["bits"])
+             for p in pairs]
+    full = tde.decode_peaks(ctx.estimate_batch(specs))
+    _, _, margin = model.forward(model.prepare(specs), topk=8)
+    m = np.sort(margin.cpu().numpy())
+    for theta, want in ((1e30, 80), (float(m[5]) if m[5] > m[4] else float(np.nextafter(m[4], np.inf)), None)):
+        plan = ctx.batch_plan(specs, mode=tde.TDE_MODE_LEARNED, model=model, topk=8, margin=theta, use_graph=1)
+        for rep in range(2):
+            pk = tde.decode_peaks(ctx.estimate_batch(specs, plan=plan))
+            fb = (pk["flags"] & tde.TDE_FLAG_FALLBACK) != 0
+            nf = int(fb.sum())
+            say(f"  theta {theta:.4g}, replay {rep}: {nf} fallback pairs")
+            if want is not None:
+                assert nf == want
+            else:
+                assert 0 < nf <= 64
+            for key in ("lag", "rmax", "n_ties"):
+                assert (pk[key][fb] == full[key][fb]).all(), key
+    model.close()
+
+
 @pytest.mark.parametrize("topk", [8, 12])
 def test_learned_batch_window_formats(T, ctx, topk):
     """Windows on every operand format in one learned batch: b = 2 (FP4
