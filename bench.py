@@ -116,6 +116,21 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def stage_traffic(stage: str):
+    """HBM bytes per launch of a stage of the learned line, from the committed
+    rocprofv3 --pmc summary profiles/learned_c5_pmc.json, if it was taken on
+    the stage's current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "learned_c5_pmc.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))["stages"][stage]
+    except Exception:
+        return None
+    h = hashlib.sha256(open(os.path.join(ROOT, rec["source"]), "rb").read()).hexdigest()
+    return rec["hbm_bytes_per_launch"] if rec.get("source_sha256") == h else None
+
+
 def traffic_from_profile(kernel_src: str, name: str):
     """HBM bytes per launch from a committed rocprofv3 --pmc summary, if it
     was taken on the current kernel source; else None."""
@@ -452,9 +467,9 @@ def run_c5(args):
                              "peak": FP6_FP4_PEAK_TFLOPS, "unit": "TFLOP/s",
                              "kernel": "k_xcorr_mfma over the fallback pairs (FP6 operands)",
                              "kernel_ms": st_l["mfma_engine"], "alg_macs_per_launch": fm}
-    for r in roofs.values():
+    for st, r in roofs.items():
         r["frac"] = r["achieved"] / r["peak"]
-        r["traffic"] = None
+        r["traffic"] = stage_traffic(st)
     dom = max(roofs, key=lambda k: roofs[k]["kernel_ms"])
     roof = dict(roofs[dom], stage=dom)
 
