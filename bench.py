@@ -286,7 +286,7 @@ def ntt_roofline(tde, pairs, engine_ms):
         while (1 << lg) < need:
             lg += 1
         k = tde.kmax_of_bits(p["bits"])
-        nprimes = 1 if min(nx, ny) * k * k < 2013265921 // 2 else 2
+        nprimes = 1 if min(nx, ny) * k * k < 998244353 // 2 else 2
         nbytes += nprimes * 3 * 2 * 2 * 4 * (1 << lg)
     achieved = nbytes / (engine_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -343,6 +343,8 @@ def run_plain(args, name, path_name="auto", fft=True, cpu_parity=False):
                            "lag_accuracy": float(np.mean(np.array(flag) == d)),
                            "speedup_int_graph_over_fft": fms / t["graph_ms"],
                            "speedup_int_eager_over_fft": fms / t["eager_ms"]}
+    if n_ntt * 2 >= len(engines) and name.startswith("c3_"):
+        res["direct_mfma_1_64"] = direct_mfma_slice(tde, ctx, torch, specs, pairs, args, t)
     if cpu_parity:
         import oracle
         t0 = time.perf_counter()
@@ -357,6 +359,40 @@ def run_plain(args, name, path_name="auto", fft=True, cpu_parity=False):
     del specs
     torch.cuda.empty_cache()
     return res
+
+
+def direct_mfma_slice(tde, ctx, torch, specs, pairs, args, t_ntt):
+    """The long-signal pairs on the direct matrix-core engine over the central
+    1/64 of their lags, beside the transform engine over all of them: both
+    engines' r over that slice compared bit for bit, the direct engine's
+    time on the slice, and that time scaled to the full range by MACs."""
+    sl, full_macs, part_macs = [], 0, 0
+    for s, p in zip(specs, pairs):
+        L = (p["lag_hi"] - p["lag_lo"] + 1 + 63) // 64
+        lo = -(L // 2)
+        sl.append(dict(s, lag_lo=lo, lag_hi=lo + L - 1))
+        full_macs += alg_macs(p["nx"], p["ny"], p["lag_lo"], p["lag_hi"])
+        part_macs += alg_macs(p["nx"], p["ny"], lo, lo + L - 1)
+    t = time_batch(ctx, torch, sl, args.steps, args.warmup, torch.cuda.current_stream(), path=tde.TDE_PATH_MFMA)
+    # r over the slice from both engines (one eager call each, outside the timing)
+    same = True
+    for s in sl:
+        n = s["lag_hi"] - s["lag_lo"] + 1
+        rs = []
+        for path in (tde.TDE_PATH_NTT, tde.TDE_PATH_MFMA):
+            r = torch.empty(n, dtype=torch.int64, device="cuda")
+            ctx.estimate_batch([dict(s, r_out=r, r_dtype=tde.TDE_I64)], path=path)
+            rs.append(r)
+        torch.cuda.synchronize()
+        same = same and bool(torch.equal(rs[0], rs[1]))
+        del rs
+    ms = t["graph_ms"]
+    return {"lags": "central 1/64 of each pair's range", "ms_per_step": ms, "pairs_per_s": len(sl) * 1e3 / ms,
+            "int_mac_per_s": part_macs * 1e3 / ms, "mac_share_of_full_range": part_macs / full_macs,
+            "full_range_ms_scaled_by_macs": ms * full_macs / part_macs,
+            "transform_engine_full_range_ms": t_ntt["graph_ms"],
+            "transform_speedup_over_direct_scaled": ms * full_macs / part_macs / t_ntt["graph_ms"],
+            "r_equal_to_transform_engine": same}
 
 
 def window_macs(top, fallback, n, nbins, bin_lags=256):

@@ -1127,8 +1127,12 @@ __global__ void __launch_bounds__(1024) k_fb_plan(const XItem* items, int npairs
         S = (target + NI - 1) / NI;
         S = S > kFbMaxSplit ? kFbMaxSplit : S;
     }
-    // pass 2: the list, chunk by chunk of 1024 pairs (exclusive scans of the
-    // item counts and of the fallback flags)
+    // pass 2: the list, chunk by chunk of 1024 pairs. Exclusive scans of the
+    // item counts and of the fallback flags give each fallback pair of the
+    // chunk its first list position and its slot; then every thread writes
+    // list entries, finding an entry's pair by binary search over the
+    // chunk's first positions.
+    __shared__ int s_fpair[1024], s_fstart[1024];
     int base_items = 0, base_slot = 0;
     for (int c0 = 0; c0 < npairs; c0 += 1024) {
         __syncthreads();
@@ -1158,30 +1162,38 @@ __global__ void __launch_bounds__(1024) k_fb_plan(const XItem* items, int npairs
             to += s_sum[1][k];
         }
         if (fb) {
-            const XItem& it = items[i];
-            const int pos = base_items + wc + pc - cnt, slot = base_slot + wo + po - one;
-            if (S > 1) slots[slot] = i;
-            int o = pos;
-            for (int j = 0; j < it.work_count; ++j) {
-                const MWork w = swork[it.work_first + j];
-                if (S == 1) {
-                    dwork[o++] = w;
-                    continue;
-                }
-                // segments of whole 4 x 32 mb steps (the cut of a long tile)
-                const int64_t unit = 128 * (int64_t)w.mb, len = w.qb - w.qa;
-                const int64_t seg = (len + S - 1) / S;
-                const int64_t step = (seg + unit - 1) / unit * unit;
-                for (int k = 0; k < S; ++k) {
-                    MWork x = w;
-                    const int64_t a = w.qa + k * step;
-                    x.qa = a < w.qb ? a : w.qb;
-                    x.qb = a + step < w.qb ? a + step : w.qb;
-                    x.segmented = 1;
-                    x.rslot = slot + 1;
-                    dwork[o++] = x;
-                }
+            const int ci = wo + po - one;
+            s_fpair[ci] = i;
+            s_fstart[ci] = wc + pc - cnt;
+            if (S > 1) slots[base_slot + ci] = i;
+        }
+        __syncthreads();
+        for (int o = tid; o < tc; o += 1024) {
+            // the last fallback pair of the chunk whose first position is <= o
+            // (pairs without items share their successor's first position)
+            int lo = 0, hi = to - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_fstart[mid] <= o) lo = mid;
+                else hi = mid - 1;
             }
+            const int rel = o - s_fstart[lo], j = rel / S, k = rel - j * S;
+            const MWork w = swork[items[s_fpair[lo]].work_first + j];
+            if (S == 1) {
+                dwork[base_items + o] = w;
+                continue;
+            }
+            // segments of whole 4 x 32 mb steps (the cut of a long tile)
+            const int64_t unit = 128 * (int64_t)w.mb, len = w.qb - w.qa;
+            const int64_t seg = (len + S - 1) / S;
+            const int64_t step = (seg + unit - 1) / unit * unit;
+            MWork x = w;
+            const int64_t a = w.qa + k * step;
+            x.qa = a < w.qb ? a : w.qb;
+            x.qb = a + step < w.qb ? a + step : w.qb;
+            x.segmented = 1;
+            x.rslot = base_slot + lo + 1;
+            dwork[base_items + o] = x;
         }
         base_items += tc;
         base_slot += to;

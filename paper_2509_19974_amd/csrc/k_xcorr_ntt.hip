@@ -20,8 +20,15 @@
 //   K3 columns:  the factor w_n^(-b k1), the inverse length-n1 transform,
 //                scaling by 1/n, CRT to a signed 64-bit value, the output r
 //                and the (max, smallest index, count) triple of the tile.
-// Arithmetic: Montgomery multiplication with R = 2^32 on residues in [0, p);
-// twiddle tables hold w^k R mod p.
+// Arithmetic: primes below 2^30, so that residues may be kept lazily in
+// [0, 2p) or [0, 4p) inside 32 bits. Butterflies multiply by a twiddle w
+// with Shoup's method (the table holds w and floor(w 2^32 / p); the product
+// lands in [0, 2p) with two low and one high 32-bit multiply). The forward
+// (decimation-in-frequency) butterfly keeps its values in [0, 2p), the
+// inverse (decimation-in-time) one in [0, 4p), as in Harvey's lazy
+// butterflies. The pointwise product and the final scaling use Montgomery
+// multiplication with R = 2^32 (a b < p 2^32 holds for a, b < 4p).
+// Twiddle tables hold plain residues with their Shoup quotients.
 #include <algorithm>
 #include <vector>
 
@@ -31,8 +38,11 @@ namespace tde {
 
 namespace {
 
-constexpr uint32_t kP[2] = {2013265921u, 1811939329u};   // 15*2^27+1, 27*2^26+1
-constexpr uint32_t kG[2] = {31u, 13u};                    // primitive roots
+// 119 2^23 + 1 and 45 2^24 + 1: both below 2^30 (4p < 2^32), 2^23 divides
+// p - 1 (transforms up to 2^23 points), and p1 < 2 p2 (one conditional
+// subtraction reduces a residue mod p1 to one mod p2 in the CRT)
+constexpr uint32_t kP[2] = {998244353u, 754974721u};
+constexpr uint32_t kG[2] = {3u, 11u};                     // primitive roots
 
 __device__ __forceinline__ uint32_t mont(uint32_t a, uint32_t b, uint32_t p, uint32_t pinv) {
     const uint64_t t = (uint64_t)a * b;
@@ -43,11 +53,6 @@ __device__ __forceinline__ uint32_t mont(uint32_t a, uint32_t b, uint32_t p, uin
     return thi < mh ? r + p : r;
 }
 
-__device__ __forceinline__ uint32_t addm(uint32_t a, uint32_t b, uint32_t p) {
-    const uint32_t s = a + b;
-    return s >= p ? s - p : s;
-}
-
 __device__ __forceinline__ uint32_t subm(uint32_t a, uint32_t b, uint32_t p) {
     return a >= b ? a - b : a + p - b;
 }
@@ -56,18 +61,53 @@ __device__ __forceinline__ uint32_t residue(int8_t x, uint32_t p) {
     return x < 0 ? (uint32_t)((int32_t)p + x) : (uint32_t)x;
 }
 
+// a w mod p in [0, 2p) for any 32-bit a, from t = (w, floor(w 2^32 / p)), w < p
+__device__ __forceinline__ uint32_t shoup(uint32_t a, uint2 t, uint32_t p) {
+    const uint32_t q = __umulhi(a, t.y);
+    return a * t.x - q * p;
+}
+
+// [0, 4p) -> [0, 2p): a - 2p wraps above a unless a >= 2p
+__device__ __forceinline__ uint32_t red2(uint32_t a, uint32_t p2) {
+    const uint32_t b = a - p2;
+    return b < a ? b : a;
+}
+
+// forward butterfly, x, y in [0, 2p): (x + y, (x - y) w), both in [0, 2p)
+__device__ __forceinline__ void dif(uint32_t& x, uint32_t& y, uint2 t, uint32_t p, uint32_t p2) {
+    const uint32_t s = x + y, d = x + p2 - y;
+    x = red2(s, p2);
+    y = shoup(d, t, p);
+}
+
+// inverse butterfly, x, y in [0, 4p): (x + y w, x - y w), both in [0, 4p)
+__device__ __forceinline__ void dit(uint32_t& x, uint32_t& y, uint2 t, uint32_t p, uint32_t p2) {
+    const uint32_t a = red2(x, p2), b = shoup(y, t, p);
+    x = a + b;
+    y = a + p2 - b;
+}
+
 __device__ __forceinline__ uint32_t brev(uint32_t x, int bits) {
     return bits ? __builtin_bitreverse32(x) >> (32 - bits) : 0u;
 }
 
-// table layout per prime: TC[n1] (w_n1^k), TL[4096] (w_n^k), TR[4096] (w_4096^k)
-__device__ __forceinline__ const uint32_t* tab_of(const NttGroup& g, int pr) {
-    return g.tab + (size_t)pr * (g.n1 + 2 * kNttRow);
+// Column block of workgroup x of nb: workgroups are dealt to the 8 XCDs in
+// turn, so x = 8 q + r takes block r (nb / 8) + q, and the blocks that one
+// XCD works on at a time are neighbours (their short row segments share L2
+// lines).
+__device__ __forceinline__ int xcd_block(int x, int nb) {
+    return (nb & 7) ? x : (x & 7) * (nb >> 3) + (x >> 3);
 }
 
-// w_n^e R for e in [0, n), from the two small tables: w_n^(4096 eh) = w_n1^eh.
-__device__ __forceinline__ uint32_t twiddle_n(const uint32_t* T, int n1, uint32_t e, uint32_t p, uint32_t pinv) {
-    return mont(T[e >> 12], T[n1 + (e & 4095u)], p, pinv);
+// table layout per prime, (w, Shoup quotient) pairs: TC[n1] (w_n1^k),
+// TL[4096] (w_n^k), TR[4096] (w_4096^k)
+__device__ __forceinline__ const uint2* tab_of(const NttGroup& g, int pr) {
+    return reinterpret_cast<const uint2*>(g.tab) + (size_t)pr * (g.n1 + 2 * kNttRow);
+}
+
+// x w_n^e in [0, 2p) for e in [0, n): w_n^e = w_n1^(e >> 12) w_n^(e & 4095)
+__device__ __forceinline__ uint32_t twist(uint32_t x, const uint2* T, int n1, uint32_t e, uint32_t p) {
+    return shoup(shoup(x, T[n1 + (e & 4095u)], p), T[e >> 12], p);
 }
 
 // ------------------------------------------------------------- tables --
@@ -89,115 +129,156 @@ __global__ void k_ntt_tables(NttGroup g) {
         base = mont(base, base, p, pinv);
         e >>= 1;
     }
-    g.tab[k] = acc;
+    const uint32_t w = mont(acc, 1u, p, pinv);   // out of Montgomery form
+    reinterpret_cast<uint2*>(g.tab)[k] = make_uint2(w, (uint32_t)(((uint64_t)w << 32) / p));
 }
 
 // ------------------------------------------------- K1: forward columns --
-// grid (4096 / kNttC1, 2 * nprimes, njobs); LDS: kNttC1 x n1 residues,
+// grid (4096 / kNttC1, 2 sides, njobs), every prime in turn; LDS: kNttC1 x n1 residues,
 // row-major (16 consecutive columns of a row side by side).
 
 __global__ void __launch_bounds__(1024) k_ntt_cols_fwd(NttGroup g, const NttJob* jobs) {
     extern __shared__ uint32_t L[];
     const NttJob& J = jobs[blockIdx.z];
-    const int side = blockIdx.y / g.nprimes;       // 0: reversed u, 1: v
-    const int pr = blockIdx.y % g.nprimes;
-    const uint32_t p = g.p[pr], pinv = g.pinv[pr];
-    const uint32_t* T = tab_of(g, pr);
+    const int side = blockIdx.y;                   // 0: reversed u, 1: v
     const int n1 = g.n1, ln1 = g.log_n1;
-    const int b0 = blockIdx.x * kNttC1;
+    const int b0 = xcd_block(blockIdx.x, gridDim.x) * kNttC1;
     const int tot = kNttC1 * n1;
     const int8_t* src = side ? J.v : J.u;
     const int64_t nsrc = side ? J.nv : J.nu;
-    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-        const int c = idx % kNttC1, i = idx / kNttC1;
-        const int64_t j = b0 + c + ((int64_t)i << 12);
-        uint32_t val = 0;
-        if (j < nsrc) val = residue(side ? src[j] : src[nsrc - 1 - j], p);
-        L[idx] = val;
-    }
-    __syncthreads();
-    // decimation in frequency over i: half-distance h = n1/2 .. 1, two
-    // stages per pass through LDS (h and h/2 on the four rows r0 = base +
-    // pos, r0 + h/2, r0 + h, r0 + 3h/2 of a 2h group: the same butterflies,
-    // twiddles and order as one stage at a time), then a last single stage
-    // when log2(n1) is odd
-    int lh = ln1 - 1;
-    // three stages per pass (h, h/2, h/4 on the eight rows base + pos +
-    // k h/4 of a 2h group) while at least three remain
-    for (; lh >= 2; lh -= 3) {
-        const int h4 = 1 << (lh - 2);
-        const int s1 = ln1 - 1 - lh;
-        for (int bi = threadIdx.x; bi < tot / 8; bi += blockDim.x) {
-            const int c = bi % kNttC1, q = bi / kNttC1;
-            const int pos = q & (h4 - 1);
-            uint32_t* x0 = &L[(((q >> (lh - 2)) << (lh + 1)) + pos) * kNttC1 + c];
-            uint32_t x[8];
+    // the thread's codes (elements threadIdx.x + 1024 m of the block), all
+    // loads in flight together, kept for every prime
+    int32_t code[kNttK1Per];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) x[k] = x0[k * h4 * kNttC1];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {                  // stage h
-                const uint32_t a = x[k], b = x[k + 4];
-                x[k] = addm(a, b, p);
-                x[k + 4] = mont(subm(a, b, p), T[(pos + k * h4) << s1], p, pinv);
-            }
-#pragma unroll
-            for (int k = 0; k < 8; k += (k & 1) ? 3 : 1) {  // stage h/2: k = 0, 1, 4, 5
-                const uint32_t a = x[k], b = x[k + 2];
-                x[k] = addm(a, b, p);
-                x[k + 2] = mont(subm(a, b, p), T[(pos + (k & 1) * h4) << (s1 + 1)], p, pinv);
-            }
-            const uint32_t w3 = T[pos << (s1 + 2)];
-#pragma unroll
-            for (int k = 0; k < 8; k += 2) {                // stage h/4
-                const uint32_t a = x[k], b = x[k + 1];
-                x[k] = addm(a, b, p);
-                x[k + 1] = mont(subm(a, b, p), w3, p, pinv);
-            }
-#pragma unroll
-            for (int k = 0; k < 8; ++k) x0[k * h4 * kNttC1] = x[k];
+    for (int m = 0; m < kNttK1Per; ++m) {
+        const int idx = threadIdx.x + m * 1024;
+        int32_t v = 0;
+        if (idx < tot) {
+            const int c = idx % kNttC1, i = idx / kNttC1;
+            const int64_t j = b0 + c + ((int64_t)i << 12);
+            if (j < nsrc) v = side ? src[j] : src[nsrc - 1 - j];
         }
-        __syncthreads();
+        code[m] = v;
     }
-    if (lh == 1) {
-        const int h = 1 << lh, h2 = h >> 1;
-        const int s1 = ln1 - 1 - lh;             // twiddle index shift of stage h (stage h/2: s1 + 1)
-        for (int bi = threadIdx.x; bi < tot / 4; bi += blockDim.x) {
-            const int c = bi % kNttC1, q = bi / kNttC1;
-            const int pos = q & (h2 - 1);
-            const int r0 = ((q >> (lh - 1)) << (lh + 1)) + pos;
-            uint32_t* x0 = &L[r0 * kNttC1 + c];
-            uint32_t* x1 = x0 + h2 * kNttC1;
-            uint32_t* x2 = x0 + h * kNttC1;
-            uint32_t* x3 = x2 + h2 * kNttC1;
-            const uint32_t a0 = *x0, a1 = *x1, a2 = *x2, a3 = *x3;
-            const uint32_t b0 = addm(a0, a2, p), b2 = mont(subm(a0, a2, p), T[pos << s1], p, pinv);
-            const uint32_t b1 = addm(a1, a3, p), b3 = mont(subm(a1, a3, p), T[(pos + h2) << s1], p, pinv);
-            const uint32_t w2 = T[pos << (s1 + 1)];
-            *x0 = addm(b0, b1, p);
-            *x1 = mont(subm(b0, b1, p), w2, p, pinv);
-            *x2 = addm(b2, b3, p);
-            *x3 = mont(subm(b2, b3, p), w2, p, pinv);
+    for (int pr = 0; pr < g.nprimes; ++pr) {
+        const uint32_t p = g.p[pr], p2 = 2 * p;
+        const uint2* T = tab_of(g, pr);
+        if (pr) lds_barrier();                         // the previous prime's residues are read
+#pragma unroll
+        for (int m = 0; m < kNttK1Per; ++m) {
+            const int idx = threadIdx.x + m * 1024;
+            if (idx < tot) L[idx] = residue((int8_t)code[m], p);
         }
-        __syncthreads();
-        lh -= 2;
-    }
-    if (lh == 0) {
-        for (int bi = threadIdx.x; bi < tot / 2; bi += blockDim.x) {
-            const int c = bi % kNttC1, e = 2 * (bi / kNttC1);
-            const uint32_t a = L[e * kNttC1 + c], b = L[(e + 1) * kNttC1 + c];
-            L[e * kNttC1 + c] = addm(a, b, p);
-            L[(e + 1) * kNttC1 + c] = mont(subm(a, b, p), T[0], p, pinv);
+        lds_barrier();
+        // decimation in frequency over i: half-distance h = n1/2 .. 1, two
+        // stages per pass through LDS (h and h/2 on the four rows r0 = base +
+        // pos, r0 + h/2, r0 + h, r0 + 3h/2 of a 2h group: the same butterflies,
+        // twiddles and order as one stage at a time), then a last single stage
+        // when log2(n1) is odd
+        int lh = ln1 - 1;
+        // three stages per pass (h, h/2, h/4 on the eight rows base + pos +
+        // k h/4 of a 2h group) while at least three remain
+        for (; lh >= 2; lh -= 3) {
+            const int h4 = 1 << (lh - 2);
+            const int s1 = ln1 - 1 - lh;
+            // the seven twiddles of a group at position pos: stage h (4), h/2 (2), h/4 (1)
+            auto twiddles = [&](int pos, uint2(&w)[7]) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) w[k] = T[(pos + k * h4) << s1];
+                w[4] = T[pos << (s1 + 1)];
+                w[5] = T[(pos + h4) << (s1 + 1)];
+                w[6] = T[pos << (s1 + 2)];
+            };
+            auto group = [&](int bi, const uint2(&w)[7]) {
+                const int c = bi % kNttC1, q = bi / kNttC1;
+                const int pos = q & (h4 - 1);
+                uint32_t* x0 = &L[(((q >> (lh - 2)) << (lh + 1)) + pos) * kNttC1 + c];
+                uint32_t x[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) x[k] = x0[k * h4 * kNttC1];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) dif(x[k], x[k + 4], w[k], p, p2);              // stage h
+#pragma unroll
+                for (int k = 0; k < 8; k += (k & 1) ? 3 : 1)                               // stage h/2: k = 0, 1, 4, 5
+                    dif(x[k], x[k + 2], w[4 + (k & 1)], p, p2);
+#pragma unroll
+                for (int k = 0; k < 8; k += 2) dif(x[k], x[k + 1], w[6], p, p2);           // stage h/4
+#pragma unroll
+                for (int k = 0; k < 8; ++k) x0[k * h4 * kNttC1] = x[k];
+            };
+            if (((int)blockDim.x / kNttC1) % h4 == 0) {
+                // every group of this thread has the same position: twiddles once
+                uint2 w[7];
+                twiddles((int)(threadIdx.x / kNttC1) & (h4 - 1), w);
+                for (int bi = threadIdx.x; bi < tot / 8; bi += blockDim.x) group(bi, w);
+            } else {
+                for (int bi = threadIdx.x; bi < tot / 8; bi += blockDim.x) {
+                    uint2 w[7];
+                    twiddles((bi / kNttC1) & (h4 - 1), w);
+                    group(bi, w);
+                }
+            }
+            lds_barrier();
         }
-        __syncthreads();
-    }
-    // factor w_n^(b k1), k1 = bit-reversed row index; store the residues
-    uint32_t* out = J.res + ((size_t)side * g.nprimes + pr) * ((size_t)n1 << 12);
-    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-        const int c = idx % kNttC1, i = idx / kNttC1;
-        const uint32_t k1 = brev((uint32_t)i, ln1);
-        const uint32_t e = (uint32_t)(b0 + c) * k1;          // < 4096 n1 = n <= 2^23
-        const uint32_t w = twiddle_n(T, n1, e, p, pinv);
-        out[(size_t)b0 + c + ((size_t)i << 12)] = mont(L[idx], w, p, pinv);
+        if (lh == 1) {
+            const int h = 1 << lh, h2 = h >> 1;
+            const int s1 = ln1 - 1 - lh;             // twiddle index shift of stage h (stage h/2: s1 + 1)
+            for (int bi = threadIdx.x; bi < tot / 4; bi += blockDim.x) {
+                const int c = bi % kNttC1, q = bi / kNttC1;
+                const int pos = q & (h2 - 1);
+                const int r0 = ((q >> (lh - 1)) << (lh + 1)) + pos;
+                uint32_t* x0 = &L[r0 * kNttC1 + c];
+                uint32_t* x1 = x0 + h2 * kNttC1;
+                uint32_t* x2 = x0 + h * kNttC1;
+                uint32_t* x3 = x2 + h2 * kNttC1;
+                uint32_t a0 = *x0, a1 = *x1, a2 = *x2, a3 = *x3;
+                dif(a0, a2, T[pos << s1], p, p2);
+                dif(a1, a3, T[(pos + h2) << s1], p, p2);
+                const uint2 w2 = T[pos << (s1 + 1)];
+                dif(a0, a1, w2, p, p2);
+                dif(a2, a3, w2, p, p2);
+                *x0 = a0;
+                *x1 = a1;
+                *x2 = a2;
+                *x3 = a3;
+            }
+            lds_barrier();
+            lh -= 2;
+        }
+        if (lh == 0) {
+            for (int bi = threadIdx.x; bi < tot / 2; bi += blockDim.x) {
+                const int c = bi % kNttC1, e = 2 * (bi / kNttC1);
+                uint32_t a = L[e * kNttC1 + c], b = L[(e + 1) * kNttC1 + c];
+                dif(a, b, T[0], p, p2);
+                L[e * kNttC1 + c] = a;
+                L[(e + 1) * kNttC1 + c] = b;
+            }
+            lds_barrier();
+        }
+        // factor w_n^(b k1), k1 = bit-reversed row index; store the residues
+        uint32_t* out = J.res + ((size_t)side * g.nprimes + pr) * ((size_t)n1 << 12);
+        if (ln1 >= 6) {
+            // thread: column c, rows i = i0 + 64 m with k1 = K + brev(m), K =
+            // brev6(i0) << (ln1 - 6); taking m in the order of brev(m) the
+            // factor is f = w^(b K) times w^b per step, carried with one R
+            // (Montgomery form) so that one Montgomery product applies it
+            const int c = threadIdx.x & (kNttC1 - 1), i0 = threadIdx.x >> 4, lm = ln1 - 6;
+            const uint32_t b = b0 + c;
+            uint32_t f = twist(g.one_m[pr], T, n1, b * (brev((uint32_t)i0, 6) << lm), p);   // R w^(b K), [0, 2p)
+            const uint2 step = T[n1 + b];                                                    // w_n^b
+            for (int mr = 0; mr < (1 << lm); ++mr) {
+                const int i = i0 + (int)(brev((uint32_t)mr, lm) << 6);
+                out[(size_t)b + ((size_t)i << 12)] = mont(L[c + i * kNttC1], f, p, g.pinv[pr]);
+                f = shoup(f, step, p);
+            }
+        } else {
+            for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+                const int c = idx % kNttC1, i = idx / kNttC1;
+                const uint32_t k1 = brev((uint32_t)i, ln1);
+                const uint32_t e = (uint32_t)(b0 + c) * k1;          // < 4096 n1 = n <= 2^23
+                out[(size_t)b0 + c + ((size_t)i << 12)] = twist(L[idx], T, n1, e, p);
+            }
+        }
     }
 }
 
@@ -217,42 +298,63 @@ __device__ __forceinline__ int rpos(int round, int t, int k) {
 
 __device__ __forceinline__ int lds_ix(int b) { return b + (b >> 4); }
 
-// forward DIF stages of one round; the stage's register distance is d and
-// its half-distance in the row is h = d * stride(round)
-__device__ __forceinline__ void dif_round(uint32_t* x, int round, int t, const uint32_t* TR, uint32_t p,
-                                          uint32_t pinv) {
+// Twiddles of a round. At the stage with register distance d = 2^ld (row
+// half-distance 2^lh, lh = ld + 8, 4, 0 in rounds A, B, C) element k of
+// thread t takes w_4096^e, e = (rpos mod 2^(lh+1)) << (11 - lh); for the
+// upper element's partner k (bit ld clear) e splits into a lane part
+// lane(round, t) << (11 - lh) and (k mod d) << (11 - ld), which is the same
+// in every lane. The lane part's twiddle is one load per stage; the other
+// comes from a lane-uniform load, and the butterfly multiplies by both
+// (once when either is 1).
+__device__ __forceinline__ int lane_part(int round, int t) { return round == 0 ? t : (round == 1 ? (t & 15) : 0); }
+
+__device__ __forceinline__ void dif2(uint32_t& x, uint32_t& y, uint2 a, uint2 b, uint32_t p, uint32_t p2) {
+    const uint32_t s = x + y, d = x + p2 - y;
+    x = red2(s, p2);
+    y = shoup(shoup(d, a, p), b, p);
+}
+
+__device__ __forceinline__ void dit2(uint32_t& x, uint32_t& y, uint2 a, uint2 b, uint32_t p, uint32_t p2) {
+    const uint32_t u = red2(x, p2), v = shoup(shoup(y, a, p), b, p);
+    x = u + v;
+    y = u + p2 - v;
+}
+
+// forward DIF stages of one round (h decreasing)
+__device__ __forceinline__ void dif_round(uint32_t* x, int round, int t, const uint2* TR, uint32_t p) {
     const int lstride = round == 0 ? 8 : (round == 1 ? 4 : 0);
 #pragma unroll
     for (int ld = 3; ld >= 0; --ld) {
         const int d = 1 << ld;
         const int lh = ld + lstride;
+        const uint2 A = TR[lane_part(round, t) << (11 - lh)];
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             if (k & d) continue;
-            const int pos = rpos(round, t, k) & ((2 << lh) - 1);
-            const uint32_t a = x[k], b = x[k + d];
-            x[k] = addm(a, b, p);
-            x[k + d] = mont(subm(a, b, p), TR[pos << (11 - lh)], p, pinv);
+            const int ku = k & (d - 1);
+            if (round == 2) dif(x[k], x[k + d], TR[ku << (11 - ld)], p, 2 * p);
+            else if (ku == 0) dif(x[k], x[k + d], A, p, 2 * p);
+            else dif2(x[k], x[k + d], A, TR[ku << (11 - ld)], p, 2 * p);
         }
     }
 }
 
-// inverse DIT stages of one round (h increasing), twiddles w^-pos
-__device__ __forceinline__ void dit_round(uint32_t* x, int round, int t, const uint32_t* TR, uint32_t p,
-                                          uint32_t pinv) {
+// inverse DIT stages of one round (h increasing), twiddles w^-e
+__device__ __forceinline__ void dit_round(uint32_t* x, int round, int t, const uint2* TR, uint32_t p) {
     const int lstride = round == 0 ? 8 : (round == 1 ? 4 : 0);
 #pragma unroll
     for (int ld = 0; ld <= 3; ++ld) {
         const int d = 1 << ld;
         const int lh = ld + lstride;
+        const uint2 A = TR[(kNttRow - (lane_part(round, t) << (11 - lh))) & (kNttRow - 1)];
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             if (k & d) continue;
-            const int pos = rpos(round, t, k) & ((2 << lh) - 1);
-            const uint32_t w = TR[(kNttRow - (pos << (11 - lh))) & (kNttRow - 1)];
-            const uint32_t a = x[k], b = mont(x[k + d], w, p, pinv);
-            x[k] = addm(a, b, p);
-            x[k + d] = subm(a, b, p);
+            const int ku = k & (d - 1);
+            const uint2 B = TR[(kNttRow - (ku << (11 - ld))) & (kNttRow - 1)];
+            if (round == 2) dit(x[k], x[k + d], B, p, 2 * p);
+            else if (ku == 0) dit(x[k], x[k + d], A, p, 2 * p);
+            else dit2(x[k], x[k + d], A, B, p, 2 * p);
         }
     }
 }
@@ -271,7 +373,7 @@ __global__ void __launch_bounds__(256) k_ntt_rows(NttGroup g, const NttJob* jobs
     const NttJob& J = jobs[blockIdx.z];
     const int pr = blockIdx.y;
     const uint32_t p = g.p[pr], pinv = g.pinv[pr];
-    const uint32_t* TR = tab_of(g, pr) + g.n1 + kNttRow;
+    const uint2* __restrict__ TR = tab_of(g, pr) + g.n1 + kNttRow;
     const size_t n = (size_t)g.n1 << 12;
     uint32_t* U = J.res + (size_t)pr * n + ((size_t)blockIdx.x << 12);
     const uint32_t* V = J.res + ((size_t)g.nprimes + pr) * n + ((size_t)blockIdx.x << 12);
@@ -281,29 +383,29 @@ __global__ void __launch_bounds__(256) k_ntt_rows(NttGroup g, const NttJob* jobs
     for (int k = 0; k < 16; ++k) xu[k] = U[t + 256 * k];
 #pragma unroll
     for (int k = 0; k < 16; ++k) xv[k] = V[t + 256 * k];
-    dif_round(xu, 0, t, TR, p, pinv);
+    dif_round(xu, 0, t, TR, p);
     exchange(xu, S, 0, 1, t);
-    dif_round(xu, 1, t, TR, p, pinv);
+    dif_round(xu, 1, t, TR, p);
     exchange(xu, S, 1, 2, t);
-    dif_round(xu, 2, t, TR, p, pinv);
-    dif_round(xv, 0, t, TR, p, pinv);
+    dif_round(xu, 2, t, TR, p);
+    dif_round(xv, 0, t, TR, p);
     exchange(xv, S, 0, 1, t);
-    dif_round(xv, 1, t, TR, p, pinv);
+    dif_round(xv, 1, t, TR, p);
     exchange(xv, S, 1, 2, t);
-    dif_round(xv, 2, t, TR, p, pinv);
+    dif_round(xv, 2, t, TR, p);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) xu[k] = mont(xu[k], xv[k], p, pinv);   // carries R^-1, removed in K3
-    dit_round(xu, 2, t, TR, p, pinv);
+    for (int k = 0; k < 16; ++k) xu[k] = mont(xu[k], xv[k], p, pinv);   // in [0, p), carries R^-1, removed in K3
+    dit_round(xu, 2, t, TR, p);
     exchange(xu, S, 2, 1, t);
-    dit_round(xu, 1, t, TR, p, pinv);
+    dit_round(xu, 1, t, TR, p);
     exchange(xu, S, 1, 0, t);
-    dit_round(xu, 0, t, TR, p, pinv);
+    dit_round(xu, 0, t, TR, p);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) U[t + 256 * k] = xu[k];
+    for (int k = 0; k < 16; ++k) U[t + 256 * k] = xu[k];                 // in [0, 4p)
 }
 
 // ------------------------------------------------- K3: inverse columns --
-// grid (4096 / wc3, 1, njobs); LDS: nprimes x wc3 x n1 residues.
+// grid (4096 / wc3, 1, njobs); LDS: wc3 x n1 residues of one prime at a time.
 
 struct Tri {
     int64_t v, i, c;
@@ -322,22 +424,52 @@ __global__ void __launch_bounds__(1024) k_ntt_cols_inv(NttGroup g, const NttJob*
     // wc is a power of two: column and row of an index by mask and shift
     // (an integer division per butterfly would cost more than the butterfly)
     const int lwc = __builtin_ctz((unsigned)wc);
-    const int b0 = blockIdx.x * wc;
+    const int b0 = xcd_block(blockIdx.x, gridDim.x) * wc;
     const int tot = wc * n1;
     const uint32_t nmask = ((uint32_t)n1 << 12) - 1u;
+    // the primes one after the other in the same LDS; the first prime's
+    // scaled residues wait in registers (at most kNttK3Per per thread)
+    uint32_t A0[kNttK3Per];
     for (int pr = 0; pr < g.nprimes; ++pr) {
-        const uint32_t p = g.p[pr], pinv = g.pinv[pr];
-        const uint32_t* T = tab_of(g, pr);
+        const uint32_t p = g.p[pr], p2 = 2 * p;
+        const uint2* T = tab_of(g, pr);
         const uint32_t* W = J.res + (size_t)pr * ((size_t)n1 << 12);
-        uint32_t* Lp = L + pr * tot;
-        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-            const int c = idx & (wc - 1), i = idx >> lwc;
-            const uint32_t k1 = brev((uint32_t)i, ln1);
-            const uint32_t e = ((uint32_t)(b0 + c) * k1) & nmask;
-            const uint32_t w = twiddle_n(T, n1, (0u - e) & nmask, p, pinv);
-            Lp[idx] = mont(W[(size_t)b0 + c + ((size_t)i << 12)], w, p, pinv);
+        uint32_t* Lp = L;
+        if (pr) lds_barrier();            // the previous prime's residues are read
+        if (tot >= 1024) {
+            // as in the forward columns: thread = column c, rows i = i0 +
+            // 2^li m, k1 = K + brev(m); f = R w^-(b K), times w^-b per step
+            const int c = threadIdx.x & (wc - 1), i0 = threadIdx.x >> lwc, li = 10 - lwc, lm = ln1 - li;
+            const uint32_t b = b0 + c, pinv = g.pinv[pr];
+            uint32_t f = twist(g.one_m[pr], T, n1, (0u - b * (brev((uint32_t)i0, li) << lm)) & nmask, p);
+            f = f >= p ? f - p : f;                                                    // [0, p): W f < 4p^2
+            const uint32_t step = twist(g.one_m[pr], T, n1, (0u - b) & nmask, p);      // R w^-b, [0, 2p)
+            // the residues of each 16 steps are loaded together
+#pragma unroll 1
+            for (int m0 = 0; m0 < (1 << lm); m0 += 16) {
+                uint32_t wv[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k)
+                    if (m0 + k < (1 << lm))
+                        wv[k] = W[(size_t)b + ((size_t)(i0 + (int)(brev((uint32_t)(m0 + k), lm) << li)) << 12)];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    if (m0 + k < (1 << lm)) {
+                        const int i = i0 + (int)(brev((uint32_t)(m0 + k), lm) << li);
+                        Lp[c + (i << lwc)] = mont(wv[k], f, p, pinv);
+                        f = mont(f, step, p, pinv);
+                    }
+                }
+            }
+        } else {
+            for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+                const int c = idx & (wc - 1), i = idx >> lwc;
+                const uint32_t k1 = brev((uint32_t)i, ln1);
+                const uint32_t e = ((uint32_t)(b0 + c) * k1) & nmask;
+                Lp[idx] = twist(W[(size_t)b0 + c + ((size_t)i << 12)], T, n1, (0u - e) & nmask, p);
+            }
         }
-        __syncthreads();
+        lds_barrier();
         // decimation in time, h = 1 .. n1/2, two stages per pass (h and 2h
         // on the rows r0 = base + pos, r0 + h, r0 + 2h, r0 + 3h of a 4h
         // group, the butterflies of one stage at a time in the same order),
@@ -348,38 +480,44 @@ __global__ void __launch_bounds__(1024) k_ntt_cols_inv(NttGroup g, const NttJob*
         for (; lh + 2 < ln1; lh += 3) {
             const int h = 1 << lh;
             const int s1 = ln1 - 1 - lh;
-            for (int bi = threadIdx.x; bi < tot / 8; bi += blockDim.x) {
+            // the seven twiddles of a group at position pos: stage h (1), 2h (2), 4h (4)
+            auto twiddles = [&](int pos, uint2(&w)[7]) {
+                w[0] = T[(n1 - (pos << s1)) & (n1 - 1)];
+                w[1] = T[(n1 - (pos << (s1 - 1))) & (n1 - 1)];
+                w[2] = T[(n1 - ((pos + h) << (s1 - 1))) & (n1 - 1)];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) w[3 + k] = T[(n1 - ((pos + k * h) << (s1 - 2))) & (n1 - 1)];
+            };
+            auto group = [&](int bi, const uint2(&w)[7]) {
                 const int c = bi & (wc - 1), q = bi >> lwc;
                 const int pos = q & (h - 1);
                 uint32_t* x0 = &Lp[(((q >> lh) << (lh + 3)) + pos) * wc + c];
                 uint32_t x[8];
 #pragma unroll
                 for (int k = 0; k < 8; ++k) x[k] = x0[k * h * wc];
-                const uint32_t w1 = T[(n1 - (pos << s1)) & (n1 - 1)];
 #pragma unroll
-                for (int k = 0; k < 8; k += 2) {            // stage h
-                    const uint32_t a = x[k], b = mont(x[k + 1], w1, p, pinv);
-                    x[k] = addm(a, b, p);
-                    x[k + 1] = subm(a, b, p);
-                }
+                for (int k = 0; k < 8; k += 2) dit(x[k], x[k + 1], w[0], p, p2);           // stage h
 #pragma unroll
-                for (int k = 0; k < 8; k += (k & 1) ? 3 : 1) {  // stage 2h: k = 0, 1, 4, 5
-                    const uint32_t w = T[(n1 - ((pos + (k & 1) * h) << (s1 - 1))) & (n1 - 1)];
-                    const uint32_t a = x[k], b = mont(x[k + 2], w, p, pinv);
-                    x[k] = addm(a, b, p);
-                    x[k + 2] = subm(a, b, p);
-                }
+                for (int k = 0; k < 8; k += (k & 1) ? 3 : 1)                               // stage 2h: k = 0, 1, 4, 5
+                    dit(x[k], x[k + 2], w[1 + (k & 1)], p, p2);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {                // stage 4h
-                    const uint32_t w = T[(n1 - ((pos + k * h) << (s1 - 2))) & (n1 - 1)];
-                    const uint32_t a = x[k], b = mont(x[k + 4], w, p, pinv);
-                    x[k] = addm(a, b, p);
-                    x[k + 4] = subm(a, b, p);
-                }
+                for (int k = 0; k < 4; ++k) dit(x[k], x[k + 4], w[3 + k], p, p2);          // stage 4h
 #pragma unroll
                 for (int k = 0; k < 8; ++k) x0[k * h * wc] = x[k];
+            };
+            if (((int)blockDim.x >> lwc) % h == 0) {
+                // every group of this thread has the same position: twiddles once
+                uint2 w[7];
+                twiddles((int)(threadIdx.x >> lwc) & (h - 1), w);
+                for (int bi = threadIdx.x; bi < tot / 8; bi += blockDim.x) group(bi, w);
+            } else {
+                for (int bi = threadIdx.x; bi < tot / 8; bi += blockDim.x) {
+                    uint2 w[7];
+                    twiddles((bi >> lwc) & (h - 1), w);
+                    group(bi, w);
+                }
             }
-            __syncthreads();
+            lds_barrier();
         }
         if (lh + 1 < ln1) {
             const int h = 1 << lh;
@@ -392,44 +530,54 @@ __global__ void __launch_bounds__(1024) k_ntt_cols_inv(NttGroup g, const NttJob*
                 uint32_t* x1 = x0 + h * wc;
                 uint32_t* x2 = x1 + h * wc;
                 uint32_t* x3 = x2 + h * wc;
-                const uint32_t w1 = T[(n1 - (pos << s1)) & (n1 - 1)];
-                const uint32_t a0 = *x0, a1 = mont(*x1, w1, p, pinv), a2 = *x2, a3 = mont(*x3, w1, p, pinv);
-                const uint32_t b0 = addm(a0, a1, p), b1 = subm(a0, a1, p);
-                const uint32_t b2 = addm(a2, a3, p), b3 = subm(a2, a3, p);
-                const uint32_t t2 = mont(b2, T[(n1 - (pos << (s1 - 1))) & (n1 - 1)], p, pinv);
-                const uint32_t t3 = mont(b3, T[(n1 - ((pos + h) << (s1 - 1))) & (n1 - 1)], p, pinv);
-                *x0 = addm(b0, t2, p);
-                *x2 = subm(b0, t2, p);
-                *x1 = addm(b1, t3, p);
-                *x3 = subm(b1, t3, p);
+                const uint2 w1 = T[(n1 - (pos << s1)) & (n1 - 1)];
+                uint32_t a0 = *x0, a1 = *x1, a2 = *x2, a3 = *x3;
+                dit(a0, a1, w1, p, p2);                                      // stage h
+                dit(a2, a3, w1, p, p2);
+                dit(a0, a2, T[(n1 - (pos << (s1 - 1))) & (n1 - 1)], p, p2);  // stage 2h
+                dit(a1, a3, T[(n1 - ((pos + h) << (s1 - 1))) & (n1 - 1)], p, p2);
+                *x0 = a0;
+                *x1 = a1;
+                *x2 = a2;
+                *x3 = a3;
             }
-            __syncthreads();
+            lds_barrier();
             lh += 2;
         }
         if (lh == ln1 - 1) {
             const int h = 1 << lh;
             for (int bi = threadIdx.x; bi < tot / 2; bi += blockDim.x) {
                 const int c = bi & (wc - 1), pos = bi >> lwc;          // one group: e = pos
-                const uint32_t w = T[(n1 - pos) & (n1 - 1)];
-                const uint32_t a = Lp[pos * wc + c], b = mont(Lp[(pos + h) * wc + c], w, p, pinv);
-                Lp[pos * wc + c] = addm(a, b, p);
-                Lp[(pos + h) * wc + c] = subm(a, b, p);
+                uint32_t a = Lp[pos * wc + c], b = Lp[(pos + h) * wc + c];
+                dit(a, b, T[(n1 - pos) & (n1 - 1)], p, p2);
+                Lp[pos * wc + c] = a;
+                Lp[(pos + h) * wc + c] = b;
             }
-            __syncthreads();
+            lds_barrier();
+        }
+        if (pr == 0 && g.nprimes == 2) {
+#pragma unroll
+            for (int m = 0; m < kNttK3Per; ++m) {
+                const int idx = threadIdx.x + m * 1024;
+                if (idx < tot) A0[m] = mont(L[idx], g.scale_m[0], p, g.pinv[0]);   // L < 4p: [0, p1)
+            }
         }
     }
     // scale, CRT, outputs
     Tri tr{INT64_MIN, INT64_MAX, 0};
-    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+#pragma unroll
+    for (int m = 0; m < kNttK3Per; ++m) {
+        const int idx = threadIdx.x + m * 1024;
         const int c = idx & (wc - 1), i = idx >> lwc;
         const int64_t j = b0 + c + ((int64_t)i << 12);
-        if (j < J.jlo || j > J.jhi) continue;
-        const uint32_t a1 = mont(L[idx], g.scale_m[0], g.p[0], g.pinv[0]);
+        if (idx >= tot || j < J.jlo || j > J.jhi) continue;
         int64_t val;
         if (g.nprimes == 1) {
+            const uint32_t a1 = mont(L[idx], g.scale_m[0], g.p[0], g.pinv[0]);     // L < 4p: a1 in [0, p1)
             val = a1 > (g.p[0] - 1) / 2 ? (int64_t)a1 - (int64_t)g.p[0] : (int64_t)a1;
         } else {
-            const uint32_t a2 = mont(L[tot + idx], g.scale_m[1], g.p[1], g.pinv[1]);
+            const uint32_t a1 = A0[m];
+            const uint32_t a2 = mont(L[idx], g.scale_m[1], g.p[1], g.pinv[1]);
             const uint32_t a1r = a1 >= g.p[1] ? a1 - g.p[1] : a1;
             const uint32_t d = subm(a2, a1r, g.p[1]);
             const uint32_t tq = mont(d, g.crt_m, g.p[1], g.pinv[1]);       // (a2 - a1) p1^-1 mod p2
@@ -494,12 +642,13 @@ bool ntt_plan(int64_t nu, int64_t nv, int kuv, int64_t lag_lo, int64_t lag_hi, N
     const int64_t ov = std::min(nu, nv);
     P.nprimes = ((__int128)ov * kuv < (__int128)(kP[0] / 2)) ? 1 : 2;
     const int n1 = 1 << (L - 12);
-    P.wc3 = std::min(kNttC1, (int)(32768 / (P.nprimes * n1)));
+    P.wc3 = std::min(kNttC1, (int)(32768 / n1));      // one prime at a time in LDS
     P.ntiles = kNttRow / P.wc3;
     return true;
 }
 
-size_t ntt_tab_words(const NttPlan& P) { return (size_t)P.nprimes * ((1u << (P.log_n - 12)) + 2 * kNttRow); }
+// (w, quotient) pairs: two words per entry
+size_t ntt_tab_words(const NttPlan& P) { return (size_t)P.nprimes * 2 * ((1u << (P.log_n - 12)) + 2 * kNttRow); }
 
 size_t ntt_res_bytes(const NttPlan& P) { return (size_t)2 * P.nprimes * ((size_t)4 << P.log_n); }
 
@@ -541,13 +690,13 @@ int launch_ntt(const NttGroup& g, const NttJob* jobs_dev, int njobs, hipStream_t
                                           32768 * 4));
         attr = true;
     }
-    hipLaunchKernelGGL(k_ntt_cols_fwd, dim3(kNttRow / kNttC1, 2 * g.nprimes, njobs), dim3(1024),
+    hipLaunchKernelGGL(k_ntt_cols_fwd, dim3(kNttRow / kNttC1, 2, njobs), dim3(1024),
                        kNttC1 * g.n1 * 4, s, g, jobs_dev);
     TDE_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_ntt_rows, dim3(g.n1, g.nprimes, njobs), dim3(256), 0, s, g, jobs_dev);
     TDE_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(k_ntt_cols_inv, dim3(kNttRow / g.wc3, 1, njobs), dim3(1024), g.nprimes * g.wc3 * g.n1 * 4, s,
-                       g, jobs_dev);
+    hipLaunchKernelGGL(k_ntt_cols_inv, dim3(kNttRow / g.wc3, 1, njobs), dim3(1024), g.wc3 * g.n1 * 4, s, g,
+                       jobs_dev);
     TDE_HIP_CHECK(hipGetLastError());
     return TDE_OK;
 }

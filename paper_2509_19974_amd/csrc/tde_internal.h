@@ -450,6 +450,8 @@ int tuned_tile_blocks(int64_t nu, int64_t nv, int kuv, int64_t lag_lo, int64_t l
 constexpr int kNttRow = 4096;      // row length of the four-step split
 constexpr int kNttC1 = 16;         // columns per forward-column workgroup
 constexpr int kNttMinLog = 13, kNttMaxLog = 23;
+constexpr int kNttK1Per = 16 * 2048 / 1024;  // forward-column codes per thread, at most
+constexpr int kNttK3Per = 32768 / 1024;   // inverse-column residues per thread, at most
 
 struct NttPlan {
     int log_n;            // transform length n = 2^log_n
@@ -460,7 +462,7 @@ struct NttPlan {
 };
 
 struct NttGroup {         // passed by value: everything shared by a launch
-    uint32_t* tab;        // twiddle tables (device), nprimes x (n1 + 8192) words
+    uint32_t* tab;        // twiddle tables (device), nprimes x (n1 + 8192) (w, Shoup quotient) word pairs
     int log_n, log_n1, n1, nprimes, wc3;
     uint32_t p[2], pinv[2], one_m[2], root_m[2], scale_m[2], crt_m;
 };
