@@ -272,12 +272,19 @@ def mfma_roofline(tde, pairs, engines, path, macs, engine_ms):
             "kernel_ms": engine_ms, "alg_macs_per_launch": tot}, dtype
 
 
-def ntt_roofline(tde, pairs, engine_ms):
-    """Roofline of the transform engine against HBM: per pair and prime the
-    three transforms of n points each take two passes over their residues
-    (read and write, 4 bytes each), so 2 primes x 3 transforms x 2 passes x
-    2 x 4 n bytes; one prime when the coefficient bound allows it."""
-    nbytes = 0
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9      # 32-bit vector ALU lane operations per second (CUs x SIMDs x lanes x clock)
+NTT_BFLY_OPS = 9                            # one lazy Shoup butterfly: mul_hi, 2 mul_lo, sub; add, sub, min; add, sub
+
+
+def ntt_roofline(tde, pairs, engine_ms, name=""):
+    """Roofline of the transform engine. Its kernels are bound by the vector
+    ALU: per pair and prime three transforms of n points, (n/2) log2 n
+    butterflies each, against the lane-operation rate of the chip divided by
+    the nine operations of a lazy butterfly. HBM beside it: per pair and
+    prime the three transforms take two passes over their residues (read and
+    write, 4 bytes each), 2 x 3 x 2 x 2 x 4 n bytes; one prime when the
+    coefficient bound allows it."""
+    nbytes, nbfly = 0, 0
     for p in pairs:
         nx, ny = p["nx"], p["ny"]
         lo, hi = max(p["lag_lo"], -(nx - 1)), min(p["lag_hi"], ny - 1)
@@ -288,10 +295,16 @@ def ntt_roofline(tde, pairs, engine_ms):
         k = tde.kmax_of_bits(p["bits"])
         nprimes = 1 if min(nx, ny) * k * k < 998244353 // 2 else 2
         nbytes += nprimes * 3 * 2 * 2 * 4 * (1 << lg)
-    achieved = nbytes / (engine_ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None, "kernel": "k_ntt_cols_fwd + k_ntt_rows + k_ntt_cols_inv (two-prime NTT)",
-            "kernel_ms": engine_ms, "alg_bytes_per_launch": nbytes}
+        nbfly += nprimes * 3 * (1 << (lg - 1)) * lg
+    achieved = nbfly / (engine_ms * 1e-3) / 1e9
+    peak = VALU_LANE_OPS / NTT_BFLY_OPS / 1e9
+    src = os.path.join(ROOT, "paper_2509_19974_amd", "csrc", "k_xcorr_ntt.hip")
+    traffic = traffic_from_profile(src, "xcorr_ntt_c3_n22_pmc.json") if name == "c3_22" else None
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "G butterflies/s", "frac": achieved / peak,
+            "traffic": traffic, "kernel": "k_ntt_cols_fwd + k_ntt_rows + k_ntt_cols_inv (two-prime NTT)",
+            "kernel_ms": engine_ms, "alg_butterflies_per_launch": nbfly,
+            "hbm": {"alg_bytes_per_launch": nbytes, "achieved_GBps": nbytes / (engine_ms * 1e-3) / 1e9,
+                    "frac": nbytes / (engine_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
 
 def run_plain(args, name, path_name="auto", fft=True, cpu_parity=False):
@@ -329,7 +342,7 @@ def run_plain(args, name, path_name="auto", fft=True, cpu_parity=False):
     if n_ntt * 2 < len(engines):
         roof, dtype = mfma_roofline(tde, pairs, engines, path, macs, t["stage_ms"].get("mfma_engine", t["stage_ms"]["engine"]))
     else:
-        roof, dtype = ntt_roofline(tde, pairs, t["stage_ms"]["engine"]), "u32"
+        roof, dtype = ntt_roofline(tde, pairs, t["stage_ms"]["engine"], name), "u32"
     res = {"pairs_per_s": len(pairs) * 1e3 / ms_step, "ms_per_step": ms_step, "timing": "eager calls" if args.eager
            else "hip graph replay", "eager_ms_per_step": t["eager_ms"], "int_mac_per_s": macs * 1e3 / ms_step,
            "dtype": dtype, "config": desc,

@@ -335,3 +335,54 @@ def test_bench_refuses_several_gpus():
                        text=True, timeout=300, cwd=ROOT)
     assert p.returncode == 2
     assert "one GPU only" in p.stderr
+
+
+def _is_prime(n: int) -> bool:
+    """Deterministic Miller-Rabin for n < 3.3e24 (bases up to 41)."""
+    if n < 2:
+        return False
+    for q in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41):
+        if n % q == 0:
+            return n == q
+    d, r = n - 1, 0
+    while d % 2 == 0:
+        d, r = d // 2, r + 1
+    for a in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41):
+        x = pow(a, d, n)
+        if x in (1, n - 1):
+            continue
+        for _ in range(r - 1):
+            x = x * x % n
+            if x == n - 1:
+                break
+        else:
+            return False
+    return True
+
+
+def test_ntt_primes():
+    """The transform engine's primes and roots, read from its source: prime,
+    2^23 divides p - 1 (transforms up to 2^23 points), 4p < 2^32 (lazy
+    residues in [0, 4p) fit 32 bits), p1 < 2 p2 (one subtraction maps a
+    residue mod p1 into [0, p2) in the CRT), each root generates the whole
+    multiplicative group, and p1 p2 / 2 exceeds the largest |r| of int8 codes
+    over 2^23 overlapping samples."""
+    import re
+    src = open(os.path.join(ROOT, "paper_2509_19974_amd", "csrc", "k_xcorr_ntt.hip")).read()
+    P = [int(x) for x in re.search(r"kP\[2\]\s*=\s*\{(\d+)u,\s*(\d+)u\}", src).groups()]
+    G = [int(x) for x in re.search(r"kG\[2\]\s*=\s*\{(\d+)u,\s*(\d+)u\}", src).groups()]
+    for p, g in zip(P, G):
+        assert _is_prime(p)
+        assert (p - 1) % (1 << 23) == 0
+        assert 4 * p < 1 << 32
+        m, fac, f = p - 1, set(), 2
+        while f * f <= m:
+            while m % f == 0:
+                fac.add(f)
+                m //= f
+            f += 1
+        if m > 1:
+            fac.add(m)
+        assert all(pow(g, (p - 1) // q, p) != 1 for q in fac)
+    assert P[0] < 2 * P[1]
+    assert P[0] * P[1] // 2 > (1 << 23) * 127 * 127
