@@ -190,7 +190,10 @@ int tde_quantizer_thresholds(int quantizer, int bits, float* out);
  *  nu + nv - 1 <= 2^23 for the full range. TDE_PATH_AUTO lets the tuning
  *  table choose.
  * Errors: TDE_ERR_ARG (nu, nv < 1, lag_lo > lag_hi, null pointers, kmax out
- * of range), TDE_ERR_RANGE, TDE_ERR_WS. */
+ * of range), TDE_ERR_RANGE, TDE_ERR_WS.
+ * tde_xcorr_workspace_size returns 0 (and sets the last error) for a request
+ * that tde_xcorr_int refuses for its sizes, code ranges, lag range (more
+ * than 2^40 lags) or engine. */
 size_t tde_xcorr_workspace_size(int64_t nu, int64_t nv, int kmax_u, int kmax_v,
                                 int64_t lag_lo, int64_t lag_hi, int path);
 /* Operand width (4, 6 or 8 bits) the matrix-core engine multiplies codes of

@@ -367,17 +367,15 @@ int tde_quantize_ex(tde_ctx* ctx, const float* x, int64_t n, int bits, int quant
 
 // --------------------------------------------------------- correlation --
 
-static int check_xcorr(const int8_t* u, int64_t nu, const int8_t* v, int64_t nv, int kmax_u, int kmax_v,
-                       int64_t lag_lo, int64_t lag_hi, const void* r, int r_dtype, int path, const char* who) {
-    if (!u || !v || !r) return set_error(TDE_ERR_ARG, "%s: null pointer", who);
+// The request itself (sizes, code ranges, lag range, engine), without its
+// buffers: what tde_xcorr_int and the workspace query both refuse.
+static int check_xcorr_request(int64_t nu, int64_t nv, int kmax_u, int kmax_v, int64_t lag_lo, int64_t lag_hi,
+                               int path, const char* who) {
     if (nu < 1 || nv < 1) return set_error(TDE_ERR_ARG, "%s: empty signal", who);
     if (lag_lo > lag_hi) return set_error(TDE_ERR_ARG, "%s: lag_lo > lag_hi", who);
     if (lag_hi - lag_lo + 1 > ((int64_t)1 << 40)) return set_error(TDE_ERR_ARG, "%s: lag range too large", who);
     if (kmax_u < 1 || kmax_u > 127 || kmax_v < 1 || kmax_v > 127)
         return set_error(TDE_ERR_ARG, "%s: kmax must be in [1, 127]", who);
-    if (r_dtype != TDE_I32 && r_dtype != TDE_I64) return set_error(TDE_ERR_ARG, "%s: bad r_dtype", who);
-    if (((uintptr_t)r) & (r_dtype == TDE_I32 ? 3 : 7))
-        return set_error(TDE_ERR_ARG, "%s: r is not aligned to its element size", who);
     if (path < TDE_PATH_AUTO || path > TDE_PATH_MFMA_I8) return set_error(TDE_ERR_ARG, "%s: bad path", who);
     if (path == TDE_PATH_POPC && (kmax_u != 1 || kmax_v != 1))
         return set_error(TDE_ERR_ARG, "%s: the bit-plane engine needs ternary codes (kmax 1)", who);
@@ -386,6 +384,17 @@ static int check_xcorr(const int8_t* u, int64_t nu, const int8_t* v, int64_t nv,
         if (!ntt_plan(nu, nv, kmax_u * kmax_v, lag_lo, lag_hi, P))
             return set_error(TDE_ERR_UNSUPPORTED, "%s: transform longer than 2^%d", who, kNttMaxLog);
     }
+    return TDE_OK;
+}
+
+static int check_xcorr(const int8_t* u, int64_t nu, const int8_t* v, int64_t nv, int kmax_u, int kmax_v,
+                       int64_t lag_lo, int64_t lag_hi, const void* r, int r_dtype, int path, const char* who) {
+    if (!u || !v || !r) return set_error(TDE_ERR_ARG, "%s: null pointer", who);
+    const int rc = check_xcorr_request(nu, nv, kmax_u, kmax_v, lag_lo, lag_hi, path, who);
+    if (rc) return rc;
+    if (r_dtype != TDE_I32 && r_dtype != TDE_I64) return set_error(TDE_ERR_ARG, "%s: bad r_dtype", who);
+    if (((uintptr_t)r) & (r_dtype == TDE_I32 ? 3 : 7))
+        return set_error(TDE_ERR_ARG, "%s: r is not aligned to its element size", who);
     if (r_dtype == TDE_I32) {
         const int64_t ov = max_overlap(nu, nv, lag_lo, lag_hi);
         if ((__int128)ov * kmax_u * kmax_v >= ((__int128)1 << 31))
@@ -406,7 +415,7 @@ int tde_mfma_operand_bits(int kmax_u, int kmax_v, int path) {
 
 size_t tde_xcorr_workspace_size(int64_t nu, int64_t nv, int kmax_u, int kmax_v, int64_t lag_lo, int64_t lag_hi,
                                 int path) {
-    if (nu < 1 || nv < 1 || lag_lo > lag_hi || kmax_u < 1 || kmax_v < 1) return 0;
+    if (check_xcorr_request(nu, nv, kmax_u, kmax_v, lag_lo, lag_hi, path, "tde_xcorr_workspace_size")) return 0;
     XItem it{};
     it.p.nu = nu;
     it.p.nv = nv;
@@ -542,10 +551,10 @@ int xcorr_run(tde_ctx* ctx, const int8_t* u, int64_t nu, const int8_t* v, int64_
 extern "C" {
 
 int tde_mfma_tile_lags(int64_t nu, int64_t nv, int kmax_u, int kmax_v, int64_t lag_lo, int64_t lag_hi, int path) {
-    if (nu < 1 || nv < 1 || lag_lo > lag_hi || kmax_u < 1 || kmax_u > 127 || kmax_v < 1 || kmax_v > 127)
-        return set_error(TDE_ERR_ARG, "tde_mfma_tile_lags: invalid request");
     if (path != TDE_PATH_AUTO && path != TDE_PATH_MFMA && path != TDE_PATH_MFMA_I8)
         return set_error(TDE_ERR_ARG, "tde_mfma_tile_lags: path %d is not a matrix-core path", path);
+    const int rc = check_xcorr_request(nu, nv, kmax_u, kmax_v, lag_lo, lag_hi, path, "tde_mfma_tile_lags");
+    if (rc) return rc;
     XItem it{};
     it.p.nu = nu;
     it.p.nv = nv;
