@@ -411,8 +411,7 @@ __global__ void __launch_bounds__(64 * kFusedWaves) k_cnn_fwd_fused(
 // C_I[i][j] = <Fx[32 I + i], Fy[32 (I + D) + j]> all belong to the shifts
 // s = j - i + 32 D, so one accumulator per D sums them over every row block
 // I (two instructions of 16 channels each). The diagonals of the D tiles are
-// then added in a fixed order (deterministic). One workgroup per pair; wave
-// w takes D = Dmin + w, w + 4, ...
+// then added in a fixed order (deterministic). One workgroup per pair.
 __global__ void __launch_bounds__(256) k_head_fwd(const uint16_t* __restrict__ Fe, const float* params_alpha, float* raw,
                                                   float* logits, int F, int nb) {
     extern __shared__ float tiles[];                 // [nD][32][32]
@@ -424,43 +423,55 @@ __global__ void __launch_bounds__(256) k_head_fwd(const uint16_t* __restrict__ F
     const uint8_t* fy = reinterpret_cast<const uint8_t*>(Fe + (int64_t)(2 * b + 1) * F * kCnnC);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r = lane & 31, g = lane >> 5;
-    for (int di = w; di < nD; di += 4) {
-        const int D = dmin + di;
-        f32x16 acc;
+    // wave w takes a contiguous range of offsets, kHD at a time: the Fx row
+    // block I is loaded once for all of them, and the Fy blocks I + D of
+    // neighbouring offsets are neighbours (cache hits). Each accumulator
+    // still sums I in increasing order, two instructions per block.
+    constexpr int kHD = 5;
+    const int per = (nD + 3) / 4;
+    const int d_end = min(nD, (w + 1) * per);
+    for (int c0 = w * per; c0 < d_end; c0 += kHD) {
+        const int cnt = min(kHD, d_end - c0), D0 = dmin + c0;
+        f32x16 acc[kHD];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) acc[e] = 0.f;
-        const int ilo = D < 0 ? -D : 0, ihi = D > 0 ? nblk - D : nblk;
-        // four row blocks' loads in flight before their matrix instructions
-        // (the same instructions in the same order as one block at a time)
-        constexpr int kU = 4;
-        for (int I0 = ilo; I0 < ihi; I0 += kU) {
-            uint4 av[kU][2], bv[kU][2];
+        for (int k = 0; k < kHD; ++k)
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                if (I0 + u < ihi) {
-                    const uint8_t* ax = fx + (int64_t)(32 * (I0 + u) + r) * 64 + 16 * g;
-                    const uint8_t* by = fy + (int64_t)(32 * (I0 + u + D) + r) * 64 + 16 * g;
+            for (int e = 0; e < 16; ++e) acc[k][e] = 0.f;
+        const int ilo = max(0, -(D0 + cnt - 1)), ihi = min(nblk, nblk - D0);
+        for (int I = ilo; I < ihi; ++I) {
+            uint4 av[2], bv[kHD][2];
+            const uint8_t* ax = fx + (int64_t)(32 * I + r) * 64 + 16 * g;
 #pragma unroll
-                    for (int kb = 0; kb < 2; ++kb) {
-                        av[u][kb] = *reinterpret_cast<const uint4*>(ax + 32 * kb);
-                        bv[u][kb] = *reinterpret_cast<const uint4*>(by + 32 * kb);
-                    }
+            for (int kb = 0; kb < 2; ++kb) av[kb] = *reinterpret_cast<const uint4*>(ax + 32 * kb);
+#pragma unroll
+            for (int k = 0; k < kHD; ++k) {
+                const int J = I + D0 + k;
+                if (k < cnt && J >= 0 && J < nblk) {
+                    const uint8_t* by = fy + (int64_t)(32 * J + r) * 64 + 16 * g;
+#pragma unroll
+                    for (int kb = 0; kb < 2; ++kb) bv[k][kb] = *reinterpret_cast<const uint4*>(by + 32 * kb);
                 }
             }
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                if (I0 + u < ihi) {
+            for (int k = 0; k < kHD; ++k) {
+                const int J = I + D0 + k;
+                if (k < cnt && J >= 0 && J < nblk) {
 #pragma unroll
                     for (int kb = 0; kb < 2; ++kb)
-                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av[u][kb]),
-                                                                      __builtin_bit_cast(bf16x8, bv[u][kb]), acc, 0,
-                                                                      0, 0);
+                        acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av[kb]),
+                                                                         __builtin_bit_cast(bf16x8, bv[k][kb]), acc[k],
+                                                                         0, 0, 0);
                 }
             }
         }
         // lane holds column j = r, rows i = 8 (e / 4) + 4 g + e % 4
 #pragma unroll
-        for (int e = 0; e < 16; ++e) tiles[(di * 32 + 8 * (e >> 2) + 4 * g + (e & 3)) * 32 + r] = acc[e];
+        for (int k = 0; k < kHD; ++k)
+            if (k < cnt) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    tiles[((c0 + k) * 32 + 8 * (e >> 2) + 4 * g + (e & 3)) * 32 + r] = acc[k][e];
+            }
     }
     __syncthreads();
     const float a = *params_alpha;
