@@ -1107,6 +1107,41 @@ def test_learned_fallback_split_and_unsplit(T, ctx):
     model.close()
 
 
+def test_learned_fallback_across_pair_chunks(T, ctx):
+    """The device planner of the fallback takes the pairs in chunks of 1024:
+    1100 pairs, every one falling back (whole items over two chunks), then a
+    threshold whose few fallback pairs include one of the second chunk (cut
+    items, r slots numbered across chunks). Peaks equal the plain full
+    search's on every replay."""
+    from paper_2509_19974_amd import tde
+    say("learned fallback across pair chunks")
+    model = tde.Model(ctx, 512, 64, seed=6)
+    pairs = synth.config5_reverb(npairs=1100, n=8192, max_lag=32 * 256, t60_range=(100, 600), salt=11)
+    specs = [dict(x=dev(T, p["x"]), y=dev(T, p["y"]), lag_lo=p["lag_lo"], lag_hi=p["lag_hi"], bits=p["bits"])
+             for p in pairs]
+    full = tde.decode_peaks(ctx.estimate_batch(specs))
+    _, _, margin = model.forward(model.prepare(specs), topk=8)
+    mg = margin.cpu().numpy()
+    order = np.argsort(mg, kind="stable")
+    r = int(np.nonzero(order >= 1024)[0][0])          # rank of the second chunk's smallest margin
+    assert r < 64, r
+    theta = float(np.nextafter(mg[order[r]], np.inf))
+    for theta, want in ((1e30, 1100), (theta, None)):
+        plan = ctx.batch_plan(specs, mode=tde.TDE_MODE_LEARNED, model=model, topk=8, margin=theta, use_graph=1)
+        for rep in range(2):
+            pk = tde.decode_peaks(ctx.estimate_batch(specs, plan=plan))
+            fb = (pk["flags"] & tde.TDE_FLAG_FALLBACK) != 0
+            nf = int(fb.sum())
+            say(f"  theta {theta:.4g}, replay {rep}: {nf} fallback pairs, {int(fb[1024:].sum())} in the second chunk")
+            if want is not None:
+                assert nf == want
+            else:
+                assert 0 < nf <= 64 and fb[1024:].any()
+            for key in ("lag", "rmax", "n_ties"):
+                assert (pk[key][fb] == full[key][fb]).all(), key
+    model.close()
+
+
 @pytest.mark.parametrize("topk", [8, 12])
 def test_learned_batch_window_formats(T, ctx, topk):
     """Windows on every operand format in one learned batch: b = 2 (FP4
