@@ -228,6 +228,15 @@ static_assert(16 * kF2Tiles <= kA1Rows, "A3 fits in A1's space");
 static_assert(32 * kF1Tiles + 8 <= kA1Rows && 32 * kF2Tiles + 8 <= kA2Rows && 32 * kF3Tiles + 8 <= 16 * kF2Tiles,
               "each layer's tiles read kept rows");
 static_assert(32 * kF0Tiles + 16 <= kX0N, "layer 0 reads staged samples");
+// A1 rows from which layer 2's weight fragments (18 KB) are kept: past the
+// rows layer 2 writes (A3), inside A1; A2 holds layer 1's and layer 3's,
+// clear of its zeroed tail rows
+constexpr int kFragRowA1 = 152;
+static_assert(16 * kF2Tiles + 8 <= kFragRowA1 && kFragRowA1 * kMRow + 18 * 64 * 16 <= kA1Rows * kMRow,
+              "layer 2's fragments sit in A1 past A3");
+static_assert(18 * 64 * 16 <= 16 * kF1Tiles * kMRow, "layer 1's and 3's fragments sit in A2 before its zeroed rows");
+static_assert((2 * kX0N * 2) % 16 == 0 && (kFragRowA1 * kMRow) % 16 == 0 && (kA1Rows * kMRow) % 16 == 0,
+              "fragment areas are 16-byte aligned");
 
 __device__ __forceinline__ float dpp_xor1(float v) {
     // quad_perm [1,0,3,2]: lane l ^ 1 (every lane has a source, so bound_ctrl
@@ -358,12 +367,24 @@ __global__ void __launch_bounds__(64 * kFusedWaves) k_cnn_fwd_fused(
         w0p[q] = wk(k0) | (wk(k1) << 16);
     }
     const uint4 a0f = make_uint4(w0p[0], w0p[1], w0p[2], w0p[3]);
-    // one layer's fragments at a time: a wave loads the next layer's as soon
-    // as its own tiles of the current layer are done
+    // A layer's 18 weight fragments (18 KB) are copied once per workgroup
+    // into LDS the layer does not touch, and every wave takes its registers'
+    // copy from there: loaded by each wave from memory they cost the
+    // vector-memory data path eight times their size. Layer 1's go into A2
+    // (written only by layer 1), layer 2's into A1 past the rows of A3,
+    // layer 3's into A2 again.
     uint4 wf[18];
     frag += (size_t)(kCnnLayers - 1) * 18 * 64;               // the halved fragments
+    uint4* fl_a2 = reinterpret_cast<uint4*>(a2);
+    uint4* fl_a1 = reinterpret_cast<uint4*>(a1 + kFragRowA1 * kMRow);
+    auto stage_frags = [&](const uint4* src, uint4* dst) {
+        for (int e = tid; e < 18 * 64; e += NT) dst[e] = src[e];
+    };
+    auto take_frags = [&](const uint4* src) {
 #pragma unroll
-    for (int b = 0; b < 18; ++b) wf[b] = frag[b * 64 + lane];
+        for (int b = 0; b < 18; ++b) wf[b] = src[b * 64 + lane];
+    };
+    stage_frags(frag, fl_a2);
     __syncthreads();
     // layer 0 -> A1
     for (int t = w; t < kF0Tiles; t += kFusedWaves) {
@@ -375,20 +396,23 @@ __global__ void __launch_bounds__(64 * kFusedWaves) k_cnn_fwd_fused(
             __builtin_bit_cast(bf16x8, bv), __builtin_bit_cast(bf16x8, a0f), splat16(0.f), 0, 0, 0);
         pool_to_lds(acc, p0, col, hg, a1, s1, L1);
     }
-    lds_barrier();
+    take_frags(fl_a2);
+    lds_barrier();                                  // A1 complete, layer 1's fragments taken from A2
     // layer 1 -> A2
     for (int t = w; t < kF1Tiles; t += kFusedWaves)
         pool_to_lds(conv_tile(a1, wf, 32 * t, col, hg, splat16(sb[kCnnC + col])), 32 * t, col, hg, a2, s2, L2);
-#pragma unroll
-    for (int b = 0; b < 18; ++b) wf[b] = frag[(18 + b) * 64 + lane];
+    lds_barrier();                                  // A1 read, A2 complete
+    stage_frags(frag + 18 * 64, fl_a1);
     lds_barrier();
-    // layer 2 -> A3
+    take_frags(fl_a1);
+    // layer 2 -> A3 (A1's first rows, below layer 2's fragments)
     for (int t = w; t < kF2Tiles; t += kFusedWaves)
         pool_to_lds(conv_tile(a2, wf, 32 * t, col, hg, splat16(sb[2 * kCnnC + col])), 32 * t, col, hg, a3, s3,
                     L3);
-#pragma unroll
-    for (int b = 0; b < 18; ++b) wf[b] = frag[(36 + b) * 64 + lane];
+    lds_barrier();                                  // A2 read, A3 complete
+    stage_frags(frag + 36 * 64, fl_a2);
     lds_barrier();
+    take_frags(fl_a2);
     // layer 3 -> features
     for (int t = w; t < kF3Tiles; t += kFusedWaves) {
         const int p0 = 32 * t;
