@@ -665,11 +665,13 @@ def test_batch_segmented_pair(T, ctx):
 
 # ---------------------------------------------------------- long signals --
 
-@pytest.mark.parametrize("log_n,npairs", [(20, 8), (21, 8), (22, 8)])
-def test_batch_ntt_long_signals(T, ctx, log_n, npairs):
+@pytest.mark.parametrize("log_n,npairs,bits", [(20, 8, 8), (21, 8, 8), (22, 8, 8), (22, 2, 4)])
+def test_batch_ntt_long_signals(T, ctx, log_n, npairs, bits):
     """Long-signal workload (8 pairs of N = 2^20, 2^21 and 2^22, b = 8, full lag range of
     2N - 1 lags, the two-prime transform with CRT to int64) in the batch
-    call's launch configuration. The oracle cannot sum 2^44 products per
+    call's launch configuration; also 2 pairs of 2^22 with b = 4, where one
+    prime suffices (its inverse columns hold 32 residues per thread, loaded in
+    two batches, with one chain of factors). The oracle cannot sum 2^44 products per
     pair directly, so r is checked over every lag against the certified
     float64 FFT route (exact after rounding, its error bound asserted below
     1/2), and at sampled lags (every 4099th, the ends, and +-64 around both
@@ -678,7 +680,9 @@ def test_batch_ntt_long_signals(T, ctx, log_n, npairs):
     from paper_2509_19974_amd import tde
     n = 1 << log_n
     pairs = synth.config3_long(n, npairs=npairs)
-    say(f"batch ntt long N=2^{log_n} pairs={npairs}")
+    for p in pairs:
+        p["bits"] = bits
+    say(f"batch ntt long N=2^{log_n} pairs={npairs} b={bits}")
     import concurrent.futures as cf
     pk, specs = _batch(T, ctx, pairs, tde.TDE_PATH_NTT, want_r=True)
     r_host = [sp["r_out"].cpu().numpy() for sp in specs]
@@ -687,8 +691,8 @@ def test_batch_ntt_long_signals(T, ctx, log_n, npairs):
     def check(i):
         p = pairs[i]
         r_gpu = r_host[i]
-        u, _, _ = oracle.quantize(p["x"], 8)
-        v, _, _ = oracle.quantize(p["y"], 8)
+        u, _, _ = oracle.quantize(p["x"], bits)
+        v, _, _ = oracle.quantize(p["y"], bits)
         lo, hi = p["lag_lo"], p["lag_hi"]
         lag = int(pk[i]["lag"])
         sample = np.unique(np.concatenate([
