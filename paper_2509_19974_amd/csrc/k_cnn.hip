@@ -430,13 +430,14 @@ __global__ void __launch_bounds__(64 * kFusedWaves) k_cnn_fwd_fused(
 }
 
 // ----------------------------------------------------------------- head --
+constexpr int kHeadWaves = 8;     // waves per workgroup (one workgroup per pair)
 // raw[b][k] = sum_t sum_c Fx[t][c] Fy[t + s][c], s = k - nb/2, on the bf16
 // matrix cores. For a fixed block offset D, the 32 x 32 products
 // C_I[i][j] = <Fx[32 I + i], Fy[32 (I + D) + j]> all belong to the shifts
 // s = j - i + 32 D, so one accumulator per D sums them over every row block
 // I (two instructions of 16 channels each). The diagonals of the D tiles are
 // then added in a fixed order (deterministic). One workgroup per pair.
-__global__ void __launch_bounds__(256) k_head_fwd(const uint16_t* __restrict__ Fe, const float* params_alpha, float* raw,
+__global__ void __launch_bounds__(64 * kHeadWaves) k_head_fwd(const uint16_t* __restrict__ Fe, const float* params_alpha, float* raw,
                                                   float* logits, int F, int nb) {
     extern __shared__ float tiles[];                 // [nD][32][32]
     const int b = blockIdx.x;
@@ -451,8 +452,8 @@ __global__ void __launch_bounds__(256) k_head_fwd(const uint16_t* __restrict__ F
     // block I is loaded once for all of them, and the Fy blocks I + D of
     // neighbouring offsets are neighbours (cache hits). Each accumulator
     // still sums I in increasing order, two instructions per block.
-    constexpr int kHD = 5;
-    const int per = (nD + 3) / 4;
+    constexpr int kHD = 3;
+    const int per = (nD + kHeadWaves - 1) / kHeadWaves;
     const int d_end = min(nD, (w + 1) * per);
     for (int c0 = w * per; c0 < d_end; c0 += kHD) {
         const int cnt = min(kHD, d_end - c0), D0 = dmin + c0;
@@ -499,7 +500,7 @@ __global__ void __launch_bounds__(256) k_head_fwd(const uint16_t* __restrict__ F
     }
     __syncthreads();
     const float a = *params_alpha;
-    for (int k = threadIdx.x; k < nb; k += 256) {
+    for (int k = threadIdx.x; k < nb; k += 64 * kHeadWaves) {
         const int sft = k - h;
         float sum = 0.f;
         for (int di = 0; di < nD; ++di) {
@@ -888,7 +889,7 @@ int launch_cnn_forward(const CnnNet& net, const float* wc, const uint16_t* xdec,
         TDE_HIP_CHECK(hipFuncSetAttribute((const void*)k_head_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
         attr = true;
     }
-    hipLaunchKernelGGL(k_head_fwd, dim3(B), dim3(256), hl, s, X, wc + net.nparams - 1, raw, logits, F, net.nb);
+    hipLaunchKernelGGL(k_head_fwd, dim3(B), dim3(64 * kHeadWaves), hl, s, X, wc + net.nparams - 1, raw, logits, F, net.nb);
     TDE_HIP_CHECK(hipGetLastError());
     return TDE_OK;
 }
