@@ -613,6 +613,54 @@ __global__ void __launch_bounds__(256) k_softmax_topk(const float* logits, const
     }
 }
 
+// Proposal only: one wave per pair holds the pair's logits in registers
+// (bin lane + 64 j in v[j]) and takes k + 1 rounds of (max, smallest bin)
+// over the bins not yet taken, by shuffles; the same choices and margin as
+// the proposal path of k_softmax_topk.
+constexpr int kTopPerLane = 16;             // bins per lane: nb <= 1024
+__global__ void __launch_bounds__(256) k_topk_wave(const float* __restrict__ logits, int B, int nb, int topk,
+                                                   int32_t* __restrict__ top, float* __restrict__ margin) {
+    const int lane = threadIdx.x & 63;
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= B) return;                     // the whole wave
+    const float* z = logits + (int64_t)b * nb;
+    float v[kTopPerLane];
+#pragma unroll
+    for (int j = 0; j < kTopPerLane; ++j) {
+        const int k = lane + 64 * j;
+        v[j] = k < nb ? z[k] : 0.f;
+    }
+    uint32_t taken = 0;                     // bit j: bin lane + 64 j is taken
+    float first = 0.f;
+    for (int r = 0; r <= topk; ++r) {
+        float bv = -INFINITY;
+        int bi = INT32_MAX;
+#pragma unroll
+        for (int j = 0; j < kTopPerLane; ++j) {
+            const int k = lane + 64 * j;
+            if (k < nb && !((taken >> j) & 1u) && (v[j] > bv || (v[j] == bv && k < bi))) {
+                bv = v[j];
+                bi = k;
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const float v2 = __shfl_xor(bv, o, 64);
+            const int i2 = __shfl_xor(bi, o, 64);
+            if (v2 > bv || (v2 == bv && i2 < bi)) {
+                bv = v2;
+                bi = i2;
+            }
+        }
+        if (bi != INT32_MAX && (bi & 63) == lane) taken |= 1u << (bi >> 6);
+        if (r == 0) first = bv;
+        if (lane == 0) {
+            if (r < topk) top[(int64_t)b * topk + r] = bi;
+            else margin[b] = bi == INT32_MAX ? INFINITY : first - bv;
+        }
+    }
+}
+
 // ------------------------------------------------------------ head bwd --
 // dFx[t][c] = alpha sum_k dlog[k] Fy[t + k - h][c]
 // dFy[t][c] = alpha sum_k dlog[k] Fx[t - k + h][c]
@@ -895,8 +943,8 @@ int launch_cnn_forward(const CnnNet& net, const float* wc, const uint16_t* xdec,
 }
 
 int launch_cnn_topk(const float* logits, int B, int nb, int topk, int32_t* top, float* margin, hipStream_t s) {
-    hipLaunchKernelGGL(k_softmax_topk, dim3(B), dim3(256), 0, s, logits, nullptr, nullptr, nb, 0.f, nullptr, nullptr,
-                       nullptr, topk, top, margin);
+    if (nb > 64 * kTopPerLane) return set_error(TDE_ERR_ARG, "cnn top-k: more than %d bins", 64 * kTopPerLane);
+    hipLaunchKernelGGL(k_topk_wave, dim3(ceil_div(B, 4)), dim3(256), 0, s, logits, B, nb, topk, top, margin);
     TDE_HIP_CHECK(hipGetLastError());
     return TDE_OK;
 }

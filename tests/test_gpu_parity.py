@@ -849,6 +849,27 @@ def test_cnn_forward_matches_oracle(T, ctx):
     m.close()
 
 
+def test_cnn_topk_all_ties(T, ctx):
+    """Zero weights make every logit equal: the top-k picks take the
+    smallest bins (ties go to the smaller bin) and the margin is 0, as the
+    oracle's top-k gives for the same logits."""
+    from paper_2509_19974_amd import tde
+    say("cnn top-k ties")
+    m = tde.Model(ctx, MID.ld, MID.nbins)
+    m.set_params(np.zeros(m.num_params, np.float32))
+    rng = np.random.default_rng(5)
+    xs = cnn.bf16_round(rng.standard_normal((3, 2, MID.ld)))
+    logits, top, margin = m.forward(_bf16_tensor(T, xs), topk=8)
+    T.cuda.synchronize()
+    lg = logits.cpu().numpy()
+    assert (lg == 0).all()
+    for b in range(3):
+        t_ref, m_ref = cnn.topk_margin(lg[b].astype(np.float64), 8)
+        assert top.cpu().numpy()[b].tolist() == t_ref.tolist() == list(range(8))
+        assert float(margin.cpu().numpy()[b]) == m_ref == 0.0
+    m.close()
+
+
 def test_cnn_forward_full_size_matches_oracle(T, ctx):
     """The full-size proposer (ld 16384, 512 bins) with the committed
     weights on one pair: logits element by element against the float64
