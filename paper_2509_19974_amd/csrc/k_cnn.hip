@@ -412,7 +412,7 @@ __global__ void __launch_bounds__(64 * kFusedWaves) k_cnn_fwd_fused(
     lds_barrier();                                  // A2 read, A3 complete
     stage_frags(frag + 36 * 64, fl_a2);
     lds_barrier();
-    take_frags(fl_a2);
+    if (w < kF3Tiles) take_frags(fl_a2);            // waves without a layer-3 tile need none
     // layer 3 -> features
     for (int t = w; t < kF3Tiles; t += kFusedWaves) {
         const int p0 = 32 * t;
