@@ -8,7 +8,8 @@
 // j in [jlo, jhi] when no other position aliases onto it; the host picks
 // n > max(jhi, nu + nv - 2 - jlo). |r| <= overlap * Ku * Kv (the coefficient
 // bound of Section 3.2): one prime suffices below p1 / 2, two primes
-// (product ~ 2^61.7) cover every int8 case this library accepts.
+// (product ~ 2^59.4) cover every int8 case this library accepts (|r| <=
+// 2^23 x 127^2 < 2^37).
 //
 // Transform (four-step, n = n1 x 4096, element j = b + 4096 i):
 //   K1 columns:  for each column b, a length-n1 decimation-in-frequency
@@ -26,8 +27,10 @@
 // lands in [0, 2p) with two low and one high 32-bit multiply). The forward
 // (decimation-in-frequency) butterfly keeps its values in [0, 2p), the
 // inverse (decimation-in-time) one in [0, 4p), as in Harvey's lazy
-// butterflies. The pointwise product and the final scaling use Montgomery
-// multiplication with R = 2^32 (a b < p 2^32 holds for a, b < 4p).
+// butterflies. The pointwise product, the chained column factors and the
+// final scaling use Montgomery multiplication with R = 2^32, which needs
+// a b < p 2^32: every use has both factors below 2p, or one below p and
+// the other below 4p, so a b < 4 p^2 < p 2^32.
 // Twiddle tables hold plain residues with their Shoup quotients.
 #include <algorithm>
 #include <vector>
