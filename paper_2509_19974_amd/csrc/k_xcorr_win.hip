@@ -7,13 +7,16 @@
 // v_mfma_scale_f32_32x32x64_f8f6f4, fp32 accumulation of integers, exact
 // while a wave's partial sum stays below 2^24): one workgroup per pair, all
 // of its windows (at most 8) in one 32-row tile. Row i = 4 w + g is group g
-// (64 lags) of window w, column j, column block b in {0, 1}:
-//     tau = T0_w + 64 g + 32 b + j
-//     A[i][k]   = v[q + T0_w + 64 g + k]       k in [0, 64)
-//     B_b[k][j] = u[q + k - j - 32 b]          the same for every window
-// so C_b[i][j] collects u[m] v[m + tau] for m = q + k - j - 32 b, and one
-// 64-code u window (B_1 | B_0) per step feeds both matrix instructions of
-// all 8 windows.
+// of window w, with lag offset f(g) = 32 (g mod 2) + 128 floor(g / 2), i.e.
+// 0, 32, 128, 160; column j, column block b in {0, 1}:
+//     tau = T0_w + f(g) + 64 b + j
+//     A[i][k]   = v[q + T0_w + f(g) + k]       k in [0, 64)
+//     B_b[k][j] = u[q + k - j - 64 b]          the same for every window
+// so C_b[i][j] collects u[m] v[m + tau] for m = q + k - j - 64 b, and the
+// offsets {f(g) + 64 b + j} cover the window's 256 lags once. B_0 feeds both
+// matrix instructions of all 8 windows, and B_1 of a step is B_0 of the step
+// before (q - 64) in the same lane: each step reads one 32-code u piece per
+// lane.
 //
 // k_xcorr_win (int8 operands, v_mfma_i32_16x16x64_i8, int32 accumulation):
 // one workgroup per window, for int8 codes or more than 8 windows. A window
@@ -161,8 +164,8 @@ struct WinFp {
     static constexpr int KS = 64;                 // m per matrix step
     static constexpr int CQ = 16;                 // steps per staged chunk
     static constexpr int CM = KS * CQ;            // m per chunk
-    static constexpr int VWIN = CM + 192;         // v codes of a window region: rows reach 64 g + k < 256
-    static constexpr int UWIN = CM + 144;         // u codes from q0 - 64: B windows end by q + 64, plus one dword
+    static constexpr int VWIN = CM + 192;         // v codes of a window region: rows reach f(g) + k < 224
+    static constexpr int UWIN = CM + 144;         // u codes from q0 - 128: B_0 pieces end by q + 64, plus one dword
     // padded bytes of a window region: A rows are read as 8-byte (FP6) or
     // 16-byte (FP4) pieces, so regions and wave areas keep 16-byte alignment
     static constexpr int VB = VWIN * W / 8 + 16;
@@ -218,10 +221,12 @@ __global__ void __launch_bounds__(256) k_xcorr_win_fp(const XItem* items, const 
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc0[e] = acc1[e] = 0.f;
     if (m_hi > m_lo) {
+        // block b covers m in [Qa - j - 64 b, Qb - j - 64 b): Qa <= m_lo and
+        // Qb >= m_hi + 31 + 64 include every nonzero term once
         const int64_t Qa = floor_div(m_lo, 64) * 64;
-        const int64_t Qb = ceil_div(m_hi + 63, 64) * 64;
+        const int64_t Qb = ceil_div(m_hi + 95, 64) * 64;
         // whole chunks per wave: steps past Qb meet only zero samples (each
-        // window's m range ends by Qb - 63), so they add nothing
+        // window's m range ends by Qb - 95), so they add nothing
         const int64_t nsteps = (Qb - Qa) / 64;
         const int64_t per = round_up(ceil_div(nsteps, 4), C::CQ);
         const int64_t sa = wv * per, sb = sa + per;
@@ -229,12 +234,12 @@ __global__ void __launch_bounds__(256) k_xcorr_win_fp(const XItem* items, const 
         uint8_t* ub = vb + 8 * C::VB;
         const int i = lane & 31, kh = lane >> 5;
         const int w = i >> 2, g = i & 3;
-        const bool live = w < topk;
         // A row of this lane: window w's region, group g, k half kh
-        const uint8_t* arow = vb + w * C::VB + ((64 * g + 32 * kh) * W) / 8;
-        // B window of this lane (column j = i, k half kh) at step s of a chunk
-        // starts at code 64 s + 32 + 32 kh - j of the u region
-        const int brel = 32 + 32 * kh - i;
+        const int fg = 32 * (g & 1) + 128 * (g >> 1);
+        const uint8_t* arow = vb + w * C::VB + ((fg + 32 * kh) * W) / 8;
+        // B_0 piece of this lane (column j = i, k half kh) at step s of a
+        // chunk: 32 codes from code 64 s + 128 + 32 kh - j of the u region
+        const int brel = 128 + 32 * kh - i;
         const uint32_t* ubw = reinterpret_cast<const uint32_t*>(ub) + ((W * brel) >> 5);
         const uint32_t bsh = (uint32_t)((W * brel) & 31);
         Packed16<W> reg[C::PER_LANE];
@@ -246,7 +251,7 @@ __global__ void __launch_bounds__(256) k_xcorr_win_fp(const XItem* items, const 
                     const int ww = unit / C::VUNITS, uu = unit - ww * C::VUNITS;
                     if (ww < topk) reg[k] = load_unit<W>(vpk, nv, (q0 + s_t0[ww]) / 16 + uu);
                 } else if (unit < C::UNITS) {
-                    reg[k] = load_unit<W>(upk, nu, (q0 - 64) / 16 + (unit - 8 * C::VUNITS));
+                    reg[k] = load_unit<W>(upk, nu, (q0 - 128) / 16 + (unit - 8 * C::VUNITS));
                 }
             }
         };
@@ -269,29 +274,32 @@ __global__ void __launch_bounds__(256) k_xcorr_win_fp(const XItem* items, const 
             }
         };
         constexpr int ASTEP = C::KS * W / 8;       // bytes per step along a row
-        // a row of a window past topk is zero (its region is never staged)
-        const int live_mask = live ? -1 : 0;
+        // rows of windows past topk read zeros: their regions are cleared
+        // once here and never staged (the wave's own area; its LDS accesses
+        // take effect in order)
+        for (int ww = topk; ww < 8; ++ww)
+            for (int o = 4 * lane; o < C::VB; o += 256) *reinterpret_cast<uint32_t*>(vb + ww * C::VB + o) = 0u;
         load(Qa + 64 * sa);
+        v8i b1;                                     // B_0 of the previous step
         for (int64_t s0 = sa; s0 < sb; s0 += C::CQ) {
             store();                                // this wave's reads of the last chunk are done (in order)
             if (s0 + C::CQ < sb) load(Qa + 64 * (s0 + C::CQ));
+            if (s0 == sa) b1 = split_piece<W>(read_piece<W>(ubw - 2 * W), bsh);   // step sa - 1
             // fragments of step s + 1 are read while the matrix
             // instructions of step s run
             v8i a = read_a_fp<W>(arow);
-            BWin<W> raw = read_bwin<W>(ubw);
+            BPiece<W> raw = read_piece<W>(ubw);
 #pragma unroll
             for (int s = 0; s < C::CQ; ++s) {
-                v8i b1, b0;
-                split_bwin<W>(raw, bsh, b1, b0);
-                v8i a_cur;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) a_cur[e] = a[e] & live_mask;
+                const v8i b0 = split_piece<W>(raw, bsh);
+                const v8i a_cur = a;
                 if (s + 1 < C::CQ) {
                     a = read_a_fp<W>(arow + ASTEP * (s + 1));
-                    raw = read_bwin<W>(ubw + 2 * W * (s + 1));
+                    raw = read_piece<W>(ubw + 2 * W * (s + 1));
                 }
                 acc0 = mfma_fp<W>(a_cur, b0, acc0);
                 acc1 = mfma_fp<W>(a_cur, b1, acc1);
+                b1 = b0;
             }
         }
     }
@@ -306,9 +314,10 @@ __global__ void __launch_bounds__(256) k_xcorr_win_fp(const XItem* items, const 
         for (int e = 0; e < 16; ++e) {
             const int i = 8 * (e >> 2) + 4 * gq + (e & 3);
             const int w = i >> 2, g = i & 3;
+            const int o = w * 256 + 32 * (g & 1) + 128 * (g >> 1) + j;
             const int v0 = (int)acc0[e], v1 = (int)acc1[e];
-            if (v0) atomicAdd((unsigned long long*)&red[w * 256 + 64 * g + j], (unsigned long long)(long long)v0);
-            if (v1) atomicAdd((unsigned long long*)&red[w * 256 + 64 * g + 32 + j], (unsigned long long)(long long)v1);
+            if (v0) atomicAdd((unsigned long long*)&red[o], (unsigned long long)(long long)v0);
+            if (v1) atomicAdd((unsigned long long*)&red[o + 64], (unsigned long long)(long long)v1);
         }
     }
     __syncthreads();

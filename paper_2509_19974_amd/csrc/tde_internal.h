@@ -173,6 +173,28 @@ __device__ __forceinline__ void split_bwin(const BWin<W>& r, uint32_t sh, v8i& b
     }
 }
 
+// One B fragment (32 codes) per lane: W + 1 dwords from dw, shifted by sh bits.
+template <int W>
+struct BPiece {
+    uint32_t d[W + 1];
+};
+
+template <int W>
+__device__ __forceinline__ BPiece<W> read_piece(const uint32_t* dw) {
+    BPiece<W> r;
+#pragma unroll
+    for (int k = 0; k < W + 1; ++k) r.d[k] = dw[k];
+    return r;
+}
+
+template <int W>
+__device__ __forceinline__ v8i split_piece(const BPiece<W>& r, uint32_t sh) {
+    v8i b = v8i{0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < W; ++k) b[k] = (int)__builtin_amdgcn_alignbit(r.d[k + 1], r.d[k], sh);
+    return b;
+}
+
 template <int W>
 __device__ __forceinline__ v16f mfma_fp(const v8i& a, const v8i& b, const v16f& c) {
     constexpr int F = W == 4 ? kFmtF4 : kFmtF6;

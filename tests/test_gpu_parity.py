@@ -1172,7 +1172,8 @@ def test_learned_batch_window_formats(T, ctx, topk):
     """Windows on every operand format in one learned batch: b = 2 (FP4
     window kernel), b = 4 (FP6), b = 8 (int8 kernel); with 12 windows every
     pair takes the int8 kernel (the FP kernel holds 8 windows per tile);
-    with 3 the FP kernel's rows of the 5 unused windows are masked to zero.
+    with 3 the FP kernel's rows of the 5 unused windows read their cleared
+    (never staged) LDS regions.
     Results equal the oracle's argmax over the union of the GPU's bins."""
     from paper_2509_19974_amd import tde
     say(f"learned window formats topk={topk}")
