@@ -285,20 +285,24 @@ __global__ void __launch_bounds__(256) k_xcorr_win_fp(const XItem* items, const 
             store();                                // this wave's reads of the last chunk are done (in order)
             if (s0 + C::CQ < sb) load(Qa + 64 * (s0 + C::CQ));
             if (s0 == sa) b1 = split_piece<W>(read_piece<W>(ubw - 2 * W), bsh);   // step sa - 1
-            // fragments of step s + 1 are read while the matrix
+            // fragments of step s + 2 are read while the matrix
             // instructions of step s run
-            v8i a = read_a_fp<W>(arow);
-            BPiece<W> raw = read_piece<W>(ubw);
+            v8i a = read_a_fp<W>(arow), a_nx = read_a_fp<W>(arow + ASTEP);
+            BPiece<W> raw = read_piece<W>(ubw), raw_nx = read_piece<W>(ubw + 2 * W);
 #pragma unroll
             for (int s = 0; s < C::CQ; ++s) {
                 const v8i b0 = split_piece<W>(raw, bsh);
                 const v8i a_cur = a;
-                if (s + 1 < C::CQ) {
-                    a = read_a_fp<W>(arow + ASTEP * (s + 1));
-                    raw = read_piece<W>(ubw + 2 * W * (s + 1));
+                a = a_nx;
+                raw = raw_nx;
+                if (s + 2 < C::CQ) {
+                    a_nx = read_a_fp<W>(arow + ASTEP * (s + 2));
+                    raw_nx = read_piece<W>(ubw + 2 * W * (s + 2));
                 }
-                acc0 = mfma_fp<W>(a_cur, b0, acc0);
+                __builtin_amdgcn_sched_barrier(0);
                 acc1 = mfma_fp<W>(a_cur, b1, acc1);
+                acc0 = mfma_fp<W>(a_cur, b0, acc0);
+                __builtin_amdgcn_sched_barrier(0);
                 b1 = b0;
             }
         }
