@@ -6,7 +6,7 @@
 // k_xcorr_win_fp (codes up to 3 / 7: FP4 / FP6 operands of
 // v_mfma_scale_f32_32x32x64_f8f6f4, fp32 accumulation of integers, exact
 // while a wave's partial sum stays below 2^24): one workgroup per pair, all
-// of its windows (at most 8) in one 32-row tile. Row i = 4 w + g is group g
+// of its windows (at most 8) in one 32-row tile. Row i = 8 g + w is group g
 // of window w, with lag offset f(g) = 32 (g mod 2) + 128 floor(g / 2), i.e.
 // 0, 32, 128, 160; column j, column block b in {0, 1}:
 //     tau = T0_w + f(g) + 64 b + j
@@ -167,8 +167,11 @@ struct WinFp {
     static constexpr int VWIN = CM + 192;         // v codes of a window region: rows reach f(g) + k < 224
     static constexpr int UWIN = CM + 144;         // u codes from q0 - 128: B_0 pieces end by q + 64, plus one dword
     // padded bytes of a window region: A rows are read as 8-byte (FP6) or
-    // 16-byte (FP4) pieces, so regions and wave areas keep 16-byte alignment
-    static constexpr int VB = VWIN * W / 8 + 16;
+    // 16-byte (FP4) pieces, so regions and wave areas keep 16-byte alignment;
+    // with rows i = 8 g + w, 32 (FP6) or 16 (FP4) bytes of padding put the
+    // pieces that 16 lanes read together (8 or 4 bytes each) on distinct
+    // banks of a 32-bank LDS
+    static constexpr int VB = VWIN * W / 8 + (W == 6 ? 32 : 16);
     static constexpr int UB = UWIN * W / 8;
     static constexpr int WAVE_LDS = (8 * VB + UB + 15) / 16 * 16;
     static constexpr int VUNITS = VWIN / 16, UUNITS = UWIN / 16;
@@ -233,7 +236,7 @@ __global__ void __launch_bounds__(256) k_xcorr_win_fp(const XItem* items, const 
         uint8_t* vb = lds + wv * C::WAVE_LDS;
         uint8_t* ub = vb + 8 * C::VB;
         const int i = lane & 31, kh = lane >> 5;
-        const int w = i >> 2, g = i & 3;
+        const int w = i & 7, g = i >> 3;
         // A row of this lane: window w's region, group g, k half kh
         const int fg = 32 * (g & 1) + 128 * (g >> 1);
         const uint8_t* arow = vb + w * C::VB + ((fg + 32 * kh) * W) / 8;
@@ -317,7 +320,7 @@ __global__ void __launch_bounds__(256) k_xcorr_win_fp(const XItem* items, const 
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const int i = 8 * (e >> 2) + 4 * gq + (e & 3);
-            const int w = i >> 2, g = i & 3;
+            const int w = i & 7, g = i >> 3;
             const int o = w * 256 + 32 * (g & 1) + 128 * (g >> 1) + j;
             const int v0 = (int)acc0[e], v1 = (int)acc1[e];
             if (v0) atomicAdd((unsigned long long*)&red[o], (unsigned long long)(long long)v0);

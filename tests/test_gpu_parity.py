@@ -1186,6 +1186,33 @@ def test_learned_batch_window_formats(T, ctx, topk):
     model.close()
 
 
+def test_learned_windows_at_lag_range_ends(T, ctx):
+    """Windows at both ends of the lag range, where the two signals overlap
+    in a few samples or none: a 64-bin model on 8192-sample pairs covers
+    lags [-8192, 8191]. Zero kernels, biases 1 and alpha = -1 make every
+    feature 1, so logit k is -32 (32 - |k - 32|) exactly and the top 8 are
+    bins 0..4 and 61..63 (ties to the smaller bin). b = 2, 4, 8 (FP4, FP6,
+    int8 window kernels). Results equal the oracle's argmax over the union
+    of the GPU's bins."""
+    from paper_2509_19974_amd import tde
+    say("learned windows at the lag-range ends")
+    shape = cnn.Shape(ld=512, nbins=64)
+    model = tde.Model(ctx, shape.ld, shape.nbins, seed=3)
+    p = {name: (np.zeros(sh) if sh else 0.0) for name, sh in cnn.param_sizes(shape)}
+    for l in range(shape.layers):
+        p[f"b{l}"] = np.ones(shape.c)
+    p["alpha"] = -1.0
+    model.set_params(cnn.flatten(shape, p).astype(np.float32))
+    pairs = synth.config5_reverb(npairs=12, n=8192, max_lag=64 * 128, t60_range=(200, 1200), salt=7)
+    for i, q in enumerate(pairs):
+        q["bits"] = (2, 4, 8)[i % 3]
+    pk, top, margin = _learned_case(T, ctx, model, pairs, 8, -1e30)
+    for i in range(len(pairs)):
+        assert sorted(top[i].tolist()) == [0, 1, 2, 3, 4, 61, 62, 63]
+    _check_learned(pk, top, margin, pairs, -1e30, 64)
+    model.close()
+
+
 def test_learned_batch_full_size_windows(T, ctx):
     """The full-size proposer shape (ld 16384, 512 bins of 256 lags over
     [-65536, 65535], N = 2^18, b = 4) on 8 pairs, every pair on its 8 windows
