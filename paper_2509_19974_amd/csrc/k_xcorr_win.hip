@@ -19,15 +19,19 @@
 // lane.
 //
 // k_xcorr_win (int8 operands, v_mfma_i32_16x16x64_i8, int32 accumulation):
-// one workgroup per window, for int8 codes or more than 8 windows. A window
-// tile holds tau = T0 + j + 16 i (i, j < 16). With steps of 64 in m:
-//     A[i][k] = v[q + T0 + 16 i + k]     (rows 16 bytes apart)
-//     B[k][j] = u[q + k - j]             (Hankel in (k, j))
-//     C[i][j] += sum_k A[i][k] B[k][j]   collects u[m] v[m + tau], m = q + k - j
+// one workgroup per 4 windows, for int8 codes or more than 8 windows. Row
+// i = 4 w + r is lag offset 16 r of window w, column j, column block b < 4:
+//     tau = T0_w + 16 r + 64 b + j
+//     A[i][k]   = v[q + T0_w + 16 r + k]   (16-byte row pieces)
+//     B_b[k][j] = u[q + k - j - 64 b]      (Hankel in (k, j), the same for every window)
+//     C_b[i][j] += sum_k A[i][k] B_b[k][j] collects u[m] v[m + tau], m = q + k - j - 64 b
+// so the offsets 16 r + 64 b + j cover a window's 256 lags once, and B_b at
+// step q is B_0 at step q - 64 b in the same lane: a step reads one A piece
+// and one B_0 piece per lane for 4 matrix instructions.
 //
 // In both, for each column the steps q = Qa, Qa + 64, ... cover a contiguous
-// m range, so Qa <= first m and Qb >= last m + 16 (+ 32 for block 1) make
-// every sum complete; samples outside the signals are staged as 0 (finite
+// m range, so Qa <= first m and Qb >= last m + j + 64 b make every sum
+// complete; samples outside the signals are staged as 0 (finite
 // support, Section 2.2). The 4 waves of a workgroup take a quarter of the
 // steps each, staging their own chunk of u and v in LDS; partial tiles meet
 // in LDS in int64. Each wave's partial covers at most a quarter of the m
@@ -41,11 +45,17 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-constexpr int kWinSteps = 32;                   // steps of 64 m per staged chunk
-constexpr int kWinCM = 64 * kWinSteps;          // m per chunk
-constexpr int kWinV = kWinCM + 256 + 64;        // v bytes of a chunk (+ one step ahead)
-constexpr int kWinU = kWinCM + 64 + 32;         // u bytes: [q0 - 16, q0 + CM + 80)
-constexpr int kWinWave = kWinV + kWinU;
+constexpr int kW8Steps = 32;                    // steps of 64 m per staged chunk
+constexpr int kW8CM = 64 * kW8Steps;            // m per chunk
+// v bytes of a window region: rows reach 16 r + k < 112 past the chunk's last
+// step; the 64 bytes of padding (a region is 64 mod 128 bytes) put the
+// 16-byte row pieces that one LDS pass serves (8 lanes: 2 windows x 4 rows)
+// on distinct banks
+constexpr int kW8V = kW8CM + 128 + 64;
+constexpr int kW8U = kW8CM + 288;               // u bytes from q0 - 208: B_0 pieces end by q + 64, plus one dword
+constexpr int kW8Wave = 4 * kW8V + kW8U;
+static_assert(kW8V % 128 == 64 && kW8U % 16 == 0, "region layout");
+static_assert(4 * kW8Wave >= 4 * 256 * 8, "the reduction area must fit");
 
 __device__ __forceinline__ uint4 ld16(const int8_t* base, int64_t n, int64_t gi) {
     const int8_t* p = base + gi;
@@ -73,88 +83,150 @@ __device__ __forceinline__ Tri tjoin(Tri a, Tri b) {
 
 }  // namespace
 
-// grid (npairs * topk): workgroup -> (pair, slot). Pairs whose margin is
-// below theta (full-range fallback) are skipped.
+// grid (npairs * ceil(topk / 4)): workgroup -> (pair, group of 4 windows).
+// Pairs whose margin is below theta (full-range fallback) are skipped.
 __global__ void __launch_bounds__(256) k_xcorr_win(const XItem* items, const int32_t* top, const float* margin,
                                                    float theta, int topk, int nb, ArgPart* parts) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[4 * kWinWave];
-    __shared__ unsigned long long red[256];
-    __shared__ Tri sh[4];
-    const int pair = blockIdx.x / topk, slot = blockIdx.x % topk;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[4 * kW8Wave];
+    __shared__ int64_t s_t0[4];
+    const int ngrp = (topk + 3) / 4;
+    const int pair = blockIdx.x / ngrp, grp = blockIdx.x % ngrp;
     if (!(margin[pair] >= theta)) return;          // fallback pair (also NaN)
     const XItem& it = items[pair];
     if (it.win_w != 0) return;                     // windows on the FP kernel
-    const XPair& p = it.p;
-    const int bin = top[(int64_t)pair * topk + slot];
-    const int64_t T0 = (int64_t)(bin - nb / 2) * 256;
-    // m range of the tile (zero outside the signals)
-    const int64_t m_lo = T0 + 255 < 0 ? -(T0 + 255) : 0;
-    int64_t m_hi = p.nu < p.nv - T0 ? p.nu : p.nv - T0;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    v4i acc = {0, 0, 0, 0};
-    if (m_hi > m_lo) {
-        const int64_t Qa = floor_div(m_lo, 64) * 64;
-        const int64_t Qb = ceil_div(m_hi + 15, 64) * 64;
-        const int64_t nsteps = (Qb - Qa) / 64;
-        const int64_t per = ceil_div(nsteps, 4);
-        const int64_t sa = w * per, sb = sa + per < nsteps ? sa + per : nsteps;
-        uint8_t* vb = lds + w * kWinWave;
-        uint8_t* ub = vb + kWinV;
-        const int r = lane & 15, g = lane >> 4;
-        const int a_off = 16 * r + 16 * g;                 // A row r, k bytes 16 g .. 16 g + 15
-        const int b_off = 16 + 16 * g - r;                 // u[q + 16 g - r ...] relative to q0 - 16
-        for (int64_t s0 = sa; s0 < sb; s0 += kWinSteps) {
-            const int64_t q0 = Qa + 64 * s0;
-            const int ns = (int)(sb - s0 < kWinSteps ? sb - s0 : kWinSteps);
-            // stage v[q0 + T0, + kWinV) and u[q0 - 16, + kWinU)
-            for (int e = lane; e < kWinV / 16; e += 64)
-                *reinterpret_cast<uint4*>(vb + 16 * e) = ld16(p.v, p.nv, q0 + T0 + 16 * e);
-            for (int e = lane; e < kWinU / 16; e += 64)
-                *reinterpret_cast<uint4*>(ub + 16 * e) = ld16(p.u, p.nu, q0 - 16 + 16 * e);
-            for (int s = 0; s < ns; ++s) {
-                const uint4 av = *reinterpret_cast<const uint4*>(vb + 64 * s + a_off);
-                const int bo = 64 * s + b_off;
-                const uint32_t* bw = reinterpret_cast<const uint32_t*>(ub + (bo & ~3));
-                uint32_t d[5];
+    // descriptor fields in registers (the LDS stores below go through
+    // generic pointers, after which fields read through `it` are reloaded)
+    const int8_t* up = it.p.u;
+    const int8_t* vp = it.p.v;
+    const int64_t nu = it.p.nu, nv = it.p.nv, lag_lo = it.p.lag_lo, lag_hi = it.p.lag_hi;
+    const int nw = topk - 4 * grp < 4 ? topk - 4 * grp : 4;     // live windows of the group
+    if (threadIdx.x < 4)
+        s_t0[threadIdx.x] =
+            (int)threadIdx.x < nw ? (int64_t)(top[(int64_t)pair * topk + 4 * grp + threadIdx.x] - nb / 2) * 256 : 0;
+    __syncthreads();
+    // the union of the live windows' m ranges (zero outside the signals)
+    int64_t m_lo = INT64_MAX, m_hi = INT64_MIN;
 #pragma unroll
-                for (int k = 0; k < 5; ++k) d[k] = bw[k];
-                const uint32_t sh8 = (uint32_t)(bo & 3);
-                v4i a, b;
-                a[0] = (int)av.x;
-                a[1] = (int)av.y;
-                a[2] = (int)av.z;
-                a[3] = (int)av.w;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) b[k] = (int)__builtin_amdgcn_alignbyte(d[k + 1], d[k], sh8);
-                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc, 0, 0, 0);
+    for (int w = 0; w < 4; ++w) {
+        if (w < nw) {
+            const int64_t t0 = s_t0[w];
+            const int64_t lo = t0 + 255 < 0 ? -(t0 + 255) : 0;
+            const int64_t hi = nu < nv - t0 ? nu : nv - t0;
+            if (hi > lo) {
+                m_lo = lo < m_lo ? lo : m_lo;
+                m_hi = hi > m_hi ? hi : m_hi;
             }
         }
     }
-    // partial tiles meet in LDS; output layout: lane -> column j = lane % 16,
-    // rows 4 (lane / 16) + e
-    red[threadIdx.x] = 0ull;
-    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform in the wave
+    v4i acc[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int i = 4 * (lane >> 4) + e, j = lane & 15;
-        if (acc[e]) atomicAdd(&red[16 * i + j], (unsigned long long)(long long)acc[e]);
+    for (int b = 0; b < 4; ++b) acc[b] = v4i{0, 0, 0, 0};
+    if (m_hi > m_lo) {
+        // block b covers m in [Qa - j - 64 b, Qb - j - 64 b): Qa <= m_lo and
+        // Qb >= m_hi + 15 + 192 include every nonzero term once
+        const int64_t Qa = floor_div(m_lo, 64) * 64;
+        const int64_t Qb = ceil_div(m_hi + 207, 64) * 64;
+        // whole groups of 4 steps per wave (the history slots rotate by 4);
+        // steps past Qb meet only zero samples
+        const int64_t nsteps = (Qb - Qa) / 64;
+        const int64_t per = round_up(ceil_div(nsteps, 4), 4);
+        const int64_t sa = wv * per, sb = sa + per;
+        uint8_t* vb = lds + wv * kW8Wave;
+        uint8_t* ub = vb + 4 * kW8V;
+        const int i = lane & 15, kq = lane >> 4;
+        const int w = i >> 2, r = i & 3;
+        // regions of windows past the live ones read zeros: cleared once
+        // here and never staged (the wave's own area; its LDS accesses take
+        // effect in order)
+        for (int ww = nw; ww < 4; ++ww)
+            for (int o = 16 * lane; o < kW8V; o += 1024)
+                *reinterpret_cast<uint4*>(vb + ww * kW8V + o) = make_uint4(0u, 0u, 0u, 0u);
+        // A row i = 4 w + r: window w's region, lag offset 16 r, k bytes 16 kq ..
+        const uint8_t* arow = vb + w * kW8V + 16 * r + 16 * kq;
+        // B_0 piece of this lane (column j = i, k bytes 16 kq ..) at step s of
+        // a chunk: u[q + 16 kq - j ..], at byte 64 s + 208 + 16 kq - j of the
+        // u region (which starts at q0 - 208)
+        const int b_off = 208 + 16 * kq - i;
+        const uint32_t* bw0 = reinterpret_cast<const uint32_t*>(ub + (b_off & ~3));
+        const uint32_t sh8 = (uint32_t)(b_off & 3);
+        auto piece = [&](int s) {                   // B_0 of step s (s >= -3)
+            const uint32_t* bw = bw0 + 16 * s;
+            uint32_t d[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) d[k] = bw[k];
+            v4i b;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) b[k] = (int)__builtin_amdgcn_alignbyte(d[k + 1], d[k], sh8);
+            return b;
+        };
+        // slot t holds B_0 of the step = t (mod 4); block b at step s takes
+        // slot (s - b) mod 4, B_0 of step s - b
+        v4i hb[4];
+        for (int64_t s0 = sa; s0 < sb; s0 += kW8Steps) {
+            const int64_t q0 = Qa + 64 * s0;
+            const int ns = (int)(sb - s0 < kW8Steps ? sb - s0 : kW8Steps);     // a multiple of 4
+            // stage v[q0 + T0_w, + kW8V) of the live windows and u[q0 - 208, + kW8U)
+            for (int ww = 0; ww < nw; ++ww) {
+                const int64_t g0 = q0 + s_t0[ww];
+                for (int e = lane; e < kW8V / 16; e += 64)
+                    *reinterpret_cast<uint4*>(vb + ww * kW8V + 16 * e) = ld16(vp, nv, g0 + 16 * e);
+            }
+            for (int e = lane; e < kW8U / 16; e += 64)
+                *reinterpret_cast<uint4*>(ub + 16 * e) = ld16(up, nu, q0 - 208 + 16 * e);
+            if (s0 == sa) {
+                hb[3] = piece(-1);
+                hb[2] = piece(-2);
+                hb[1] = piece(-3);
+            }
+            for (int s = 0; s < ns; s += 4) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const uint4 av = *reinterpret_cast<const uint4*>(arow + 64 * (s + t));
+                    const v4i a = {(int)av.x, (int)av.y, (int)av.z, (int)av.w};
+                    hb[t] = piece(s + t);
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        acc[b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, hb[(t - b) & 3], acc[b], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // the waves' partials meet in LDS (int64): red[w][lag offset in the window];
+    // output layout: lane -> column j = lane % 16, rows 4 (lane / 16) + e, so
+    // a lane's rows all belong to window lane / 16
+    __syncthreads();
+    long long* red = reinterpret_cast<long long*>(lds);
+    for (int k = threadIdx.x; k < 4 * 256; k += 256) red[k] = 0;
+    __syncthreads();
+    {
+        const int j = lane & 15, gq = lane >> 4;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (acc[b][e])
+                    atomicAdd((unsigned long long*)&red[gq * 256 + 16 * e + 64 * b + j],
+                              (unsigned long long)(long long)acc[b][e]);
     }
     __syncthreads();
-    // lag index of red[16 i + j] is T0 + j + 16 i - lag_lo
-    const int k = threadIdx.x;
-    const int64_t idx = T0 + k - p.lag_lo;
-    Tri t{INT64_MIN, INT64_MAX, 0};
-    if (idx >= 0 && idx <= p.lag_hi - p.lag_lo) t = Tri{(int64_t)red[k], idx, 1};
+    // wave wv: the triple of window wv of the group
+    if (wv < nw) {
+        Tri t{INT64_MIN, INT64_MAX, 0};
+        const int64_t base = s_t0[wv] - lag_lo;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        Tri u{__shfl_xor(t.v, o, 64), __shfl_xor(t.i, o, 64), __shfl_xor(t.c, o, 64)};
-        t = tjoin(t, u);
-    }
-    if (lane == 0) sh[w] = t;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const Tri a = tjoin(tjoin(sh[0], sh[1]), tjoin(sh[2], sh[3]));
-        parts[blockIdx.x] = ArgPart{a.v, a.i, a.c};
+        for (int rr = 0; rr < 4; ++rr) {
+            const int k = lane + 64 * rr;
+            const int64_t idx = base + k;
+            if (idx >= 0 && idx <= lag_hi - lag_lo) t = tjoin(t, Tri{(int64_t)red[wv * 256 + k], idx, 1});
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            Tri u{__shfl_xor(t.v, o, 64), __shfl_xor(t.i, o, 64), __shfl_xor(t.c, o, 64)};
+            t = tjoin(t, u);
+        }
+        if (lane == 0) parts[(int64_t)pair * topk + 4 * grp + wv] = ArgPart{t.v, t.i, t.c};
     }
 }
 
@@ -355,8 +427,8 @@ int launch_xcorr_win(const XItem* items_dev, int npairs, const int32_t* top, con
                      int topk, int nb, ArgPart* parts, hipStream_t s, int formats) {
     if (npairs == 0) return TDE_OK;
     if (formats & 1)
-        hipLaunchKernelGGL(k_xcorr_win, dim3(npairs * topk), dim3(256), 0, s, items_dev, top, margin, theta, topk, nb,
-                           parts);
+        hipLaunchKernelGGL(k_xcorr_win, dim3(npairs * ((topk + 3) / 4)), dim3(256), 0, s, items_dev, top, margin, theta,
+                           topk, nb, parts);
     if (formats & 2)
         hipLaunchKernelGGL(k_xcorr_win_fp<6>, dim3(npairs), dim3(256), 0, s, items_dev, top, margin, theta, topk, nb,
                            parts);

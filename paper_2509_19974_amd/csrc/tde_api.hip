@@ -696,9 +696,10 @@ int validate_pairs(const tde_pair* pairs, int64_t np, const tde_opts* opts) {
                 return set_error(TDE_ERR_ARG,
                                  "pair %lld: learned mode needs nx = ny = %lld, lags [%lld, %lld], bits 2/4/8, no r_out",
                                  (long long)i, (long long)n, (long long)-half, (long long)(half - 1));
-            // each window wave sums a quarter of the m range in int32
+            // each window wave sums a quarter of the m range (plus the
+            // tile's reach and whole groups of 4 steps) in int32
             const int K = kmax_of_bits(q.bits);
-            if ((__int128)(n / 4 + 128) * K * K >= ((__int128)1 << 31))
+            if ((__int128)(n / 4 + 512) * K * K >= ((__int128)1 << 31))
                 return set_error(TDE_ERR_UNSUPPORTED, "pair %lld: signals too long for int32 window sums", (long long)i);
         }
     }
