@@ -164,17 +164,41 @@ __global__ void __launch_bounds__(256) k_xcorr_win(const XItem* items, const int
         // slot t holds B_0 of the step = t (mod 4); block b at step s takes
         // slot (s - b) mod 4, B_0 of step s - b
         v4i hb[4];
-        for (int64_t s0 = sa; s0 < sb; s0 += kW8Steps) {
-            const int64_t q0 = Qa + 64 * s0;
-            const int ns = (int)(sb - s0 < kW8Steps ? sb - s0 : kW8Steps);     // a multiple of 4
-            // stage v[q0 + T0_w, + kW8V) of the live windows and u[q0 - 208, + kW8U)
-            for (int ww = 0; ww < nw; ++ww) {
-                const int64_t g0 = q0 + s_t0[ww];
-                for (int e = lane; e < kW8V / 16; e += 64)
-                    *reinterpret_cast<uint4*>(vb + ww * kW8V + 16 * e) = ld16(vp, nv, g0 + 16 * e);
+        // staging of a chunk: v[q0 + T0_w, + kW8V) of the live windows and
+        // u[q0 - 208, + kW8U), 16-byte units; the next chunk's units are
+        // loaded into registers while the current chunk runs
+        constexpr int VU = kW8V / 16, UU = kW8U / 16;
+        constexpr int PER_LANE = (4 * VU + UU + 63) / 64;
+        uint4 reg[PER_LANE];
+        auto load = [&](int64_t q0) {
+#pragma unroll
+            for (int k = 0; k < PER_LANE; ++k) {
+                const int unit = lane + 64 * k;
+                if (unit < 4 * VU) {
+                    const int ww = unit / VU, uu = unit - ww * VU;
+                    if (ww < nw) reg[k] = ld16(vp, nv, q0 + s_t0[ww] + 16 * uu);
+                } else if (unit < 4 * VU + UU) {
+                    reg[k] = ld16(up, nu, q0 - 208 + 16 * (unit - 4 * VU));
+                }
             }
-            for (int e = lane; e < kW8U / 16; e += 64)
-                *reinterpret_cast<uint4*>(ub + 16 * e) = ld16(up, nu, q0 - 208 + 16 * e);
+        };
+        auto store = [&]() {
+#pragma unroll
+            for (int k = 0; k < PER_LANE; ++k) {
+                const int unit = lane + 64 * k;
+                if (unit < 4 * VU) {
+                    const int ww = unit / VU, uu = unit - ww * VU;
+                    if (ww < nw) *reinterpret_cast<uint4*>(vb + ww * kW8V + 16 * uu) = reg[k];
+                } else if (unit < 4 * VU + UU) {
+                    *reinterpret_cast<uint4*>(ub + 16 * (unit - 4 * VU)) = reg[k];
+                }
+            }
+        };
+        load(Qa + 64 * sa);
+        for (int64_t s0 = sa; s0 < sb; s0 += kW8Steps) {
+            const int ns = (int)(sb - s0 < kW8Steps ? sb - s0 : kW8Steps);     // a multiple of 4
+            store();                                // this wave's reads of the last chunk are done (in order)
+            if (s0 + kW8Steps < sb) load(Qa + 64 * (s0 + kW8Steps));
             if (s0 == sa) {
                 hb[3] = piece(-1);
                 hb[2] = piece(-2);
