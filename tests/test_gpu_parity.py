@@ -1213,14 +1213,18 @@ def test_learned_windows_at_lag_range_ends(T, ctx):
     model.close()
 
 
-def test_learned_batch_full_size_windows(T, ctx):
+@pytest.mark.parametrize("bits", [4, 8])
+def test_learned_batch_full_size_windows(T, ctx, bits):
     """The full-size proposer shape (ld 16384, 512 bins of 256 lags over
-    [-65536, 65535], N = 2^18, b = 4) on 8 pairs, every pair on its 8 windows
-    (threshold -inf); also captured in a HIP graph."""
+    [-65536, 65535], N = 2^18) on 8 pairs, every pair on its 8 windows
+    (threshold -inf): b = 4 on the FP6 window kernel, b = 8 on the int8 one
+    (two groups of 4 windows per pair); also captured in a HIP graph."""
     from paper_2509_19974_amd import tde
-    say("learned batch full size")
+    say(f"learned batch full size b={bits}")
     model = tde.Model(ctx, 16384, 512, seed=4)
     pairs = synth.config5_reverb(npairs=8, n=1 << 18, max_lag=1 << 16, salt=9)
+    for p in pairs:
+        p["bits"] = bits
     pk, top, margin = _learned_case(T, ctx, model, pairs, 8, -1e30)
     _check_learned(pk, top, margin, pairs, -1e30, 512)
     specs = [dict(x=dev(T, p["x"]), y=dev(T, p["y"]), lag_lo=p["lag_lo"], lag_hi=p["lag_hi"], bits=p["bits"])
